@@ -1,0 +1,254 @@
+"""ctypes wrapper of the CPU oracle (picard_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the benchmark's
+CPU-baseline leg, never by the GPU path.  Every function takes an `Instance` from
+paper_2406_01939_amd.instances (numpy arrays) and a trajectory index.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "picard_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+LOST = -1
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain -O2, IEEE semantics kept)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-Wall",
+                               "-Wno-unused-variable", SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class _Problem(C.Structure):
+    _fields_ = [("N", C.c_int32), ("K", C.c_int32), ("R", C.c_int32), ("T", C.c_int64),
+                ("sku", C.c_void_p), ("region", C.c_void_p), ("qty", C.c_void_p),
+                ("x0", C.c_void_p), ("cost", C.c_void_p), ("params", C.c_void_p),
+                ("hidden", C.c_int32), ("n_hidden_layers", C.c_int32),
+                ("rng_seed", C.c_uint64), ("traj", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build(force=False)
+        L = C.CDLL(LIB)
+        P = C.POINTER(_Problem)
+        vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+        L.orc_serial.argtypes = [P, vp, vp, vp, vp, vp]
+        L.orc_eval_at.argtypes = [P, vp, vp, vp, vp, vp]
+        L.orc_alg1.argtypes = [P, vp, i64, vp, i32, vp, vp, vp]
+        L.orc_picard_runs.argtypes = [P, vp, vp, i32, vp, vp, vp, vp]
+        L.orc_reinforce.argtypes = [P, vp, vp, vp, vp, vp]
+        L.orc_mlp_scores.argtypes = [P, i32, vp, vp]
+        L.orc_philox4x32_10.argtypes = [vp, vp, vp]
+        L.orc_philox4x32_10.restype = None
+        L.orc_uniform.argtypes = [C.c_uint64, i32, i64, i32]
+        L.orc_uniform.restype = C.c_double
+        L.orc_gumbel.argtypes = [C.c_uint64, i32, i64, i32]
+        L.orc_gumbel.restype = C.c_double
+        L.orc_param_count.argtypes = [i32, i32, i32]
+        L.orc_param_count.restype = C.c_int64
+        _lib = L
+    return _lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data
+
+
+class _Bound:
+    """Keeps the numpy arrays behind a _Problem alive while it is in use."""
+
+    def __init__(self, inst, b: int):
+        lo, hi = int(inst.traj_offsets[b]), int(inst.traj_offsets[b + 1])
+        self.sku = np.ascontiguousarray(inst.sku[lo:hi], dtype=np.int32)
+        self.region = np.ascontiguousarray(inst.region[lo:hi], dtype=np.int32)
+        self.qty = np.ascontiguousarray(inst.qty[lo:hi], dtype=np.int32)
+        self.x0 = np.ascontiguousarray(inst.x0[b], dtype=np.int32)
+        self.cost = np.ascontiguousarray(inst.cost[b], dtype=np.int32)
+        self.params = (None if inst.params is None
+                       else np.ascontiguousarray(inst.params, dtype=np.float32))
+        self.T = hi - lo
+        self.p = _Problem(inst.N, inst.K, inst.R, self.T, _ptr(self.sku), _ptr(self.region),
+                          _ptr(self.qty), _ptr(self.x0), _ptr(self.cost), _ptr(self.params),
+                          inst.hidden, inst.n_hidden_layers, inst.rng_seed & (2**64 - 1), b)
+
+
+def _check(rc: int, what: str):
+    if rc < 0:
+        raise ValueError(f"oracle {what} failed with code {rc}")
+
+
+def serial(inst, b: int = 0, greedy: bool = False) -> dict:
+    """Serial rollout of trajectory b (greedy=True forces the greedy policy)."""
+    B = _Bound(inst, b)
+    if greedy:
+        B.p.params = None
+    T = B.T
+    act = np.empty(T, np.int32)
+    sh = np.empty(T, np.int32)
+    fin = np.empty((inst.K, inst.N), np.int32)
+    z1 = np.empty(T, np.float64)
+    z2 = np.empty(T, np.float64)
+    _check(lib().orc_serial(C.byref(B.p), _ptr(act), _ptr(sh), _ptr(fin), _ptr(z1), _ptr(z2)),
+           "serial")
+    return dict(actions=act, shipped=sh, final_inv=fin, z1=z1, z2=z2)
+
+
+def eval_at(inst, actions: np.ndarray, b: int = 0) -> dict:
+    """Policy choice and top-two perturbed scores at the states a given sequence induces."""
+    B = _Bound(inst, b)
+    T = B.T
+    actions = np.ascontiguousarray(actions, dtype=np.int32)
+    ch = np.empty(T, np.int32)
+    z1 = np.empty(T, np.float64)
+    z2 = np.empty(T, np.float64)
+    nf = np.empty(T, np.int32)
+    rc = lib().orc_eval_at(C.byref(B.p), _ptr(actions), _ptr(ch), _ptr(z1), _ptr(z2), _ptr(nf))
+    _check(rc, "eval_at")
+    if rc == -2:
+        raise ValueError("action sequence is infeasible")
+    return dict(choice=ch, z1=z1, z2=z2, n_feasible=nf)
+
+
+def alg1(inst, worker: np.ndarray, n_workers: int, b: int = 0, init_cache=None,
+         max_passes: Optional[int] = None, record: bool = True) -> dict:
+    """Algorithm 1 taken literally (tiny instances only)."""
+    B = _Bound(inst, b)
+    T = B.T
+    if max_passes is None:
+        max_passes = T + 1
+    worker = np.ascontiguousarray(worker, dtype=np.int64)
+    init = None if init_cache is None else np.ascontiguousarray(init_cache, dtype=np.int32)
+    fin = np.empty(T, np.int32)
+    passes = np.zeros(1, np.int32)
+    caches = np.empty((max_passes, T), np.int32) if record else None
+    rc = lib().orc_alg1(C.byref(B.p), _ptr(worker), n_workers, _ptr(init), max_passes,
+                        _ptr(fin), _ptr(passes), _ptr(caches))
+    _check(rc, "alg1")
+    k = int(passes[0])
+    return dict(actions=fin, passes=k, converged=rc == 0,
+                caches=None if caches is None else caches[:k])
+
+
+def picard_runs(inst, worker: np.ndarray, b: int = 0, init_cache=None,
+                max_passes: Optional[int] = None, record: bool = False) -> dict:
+    """Run-form Picard (same passes as Algorithm 1 for one-run-per-segment partitions)."""
+    B = _Bound(inst, b)
+    T = B.T
+    if max_passes is None:
+        max_passes = T + 1
+    worker = np.ascontiguousarray(worker, dtype=np.int64)
+    init = None if init_cache is None else np.ascontiguousarray(init_cache, dtype=np.int32)
+    fin = np.empty(T, np.int32)
+    passes = np.zeros(1, np.int32)
+    changed = np.zeros(max_passes, np.int64)
+    caches = np.empty((max_passes, T), np.int32) if record else None
+    rc = lib().orc_picard_runs(C.byref(B.p), _ptr(worker), _ptr(init), max_passes, _ptr(fin),
+                               _ptr(passes), _ptr(changed), _ptr(caches))
+    if rc == -2:
+        raise ValueError("partition gives some process two runs of one SKU")
+    _check(rc, "picard_runs")
+    k = int(passes[0])
+    return dict(actions=fin, passes=k, converged=rc == 0, changed=changed[:k],
+                caches=None if caches is None else caches[:k])
+
+
+def reinforce(inst, actions: np.ndarray, adv: np.ndarray, b: int = 0,
+              want_grad: bool = True) -> dict:
+    """FP64 surrogate L = sum_t A_t log pi(a_t|s_t), per-step log pi and dL/dtheta."""
+    B = _Bound(inst, b)
+    T = B.T
+    actions = np.ascontiguousarray(actions, dtype=np.int32)
+    adv = np.ascontiguousarray(adv, dtype=np.float64)
+    n = int(lib().orc_param_count(inst.R, inst.hidden, inst.n_hidden_layers))
+    logp = np.empty(T, np.float64)
+    grad = np.empty(n, np.float64) if want_grad else None
+    L = np.zeros(1, np.float64)
+    rc = lib().orc_reinforce(C.byref(B.p), _ptr(actions), _ptr(adv), _ptr(logp), _ptr(grad),
+                             _ptr(L))
+    if rc == -2:
+        raise ValueError("an action is outside the feasible set of its state")
+    _check(rc, "reinforce")
+    return dict(objective=float(L[0]), logp=logp, grad=grad)
+
+
+def mlp_scores(inst, r: int, x_row: np.ndarray, b: int = 0) -> np.ndarray:
+    B = _Bound(inst, b)
+    x_row = np.ascontiguousarray(x_row, dtype=np.int32)
+    s = np.empty(inst.N, np.float64)
+    _check(lib().orc_mlp_scores(C.byref(B.p), r, _ptr(x_row), _ptr(s)), "mlp_scores")
+    return s
+
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.empty(4, np.uint32)
+    lib().orc_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def uniform(seed: int, traj: int, t: int, w: int) -> float:
+    return float(lib().orc_uniform(seed & (2**64 - 1), traj, t, w))
+
+
+def gumbel(seed: int, traj: int, t: int, w: int) -> float:
+    return float(lib().orc_gumbel(seed & (2**64 - 1), traj, t, w))
+
+
+def param_count(R: int, hidden: int = 64, n_hidden_layers: int = 2) -> int:
+    return int(lib().orc_param_count(R, hidden, n_hidden_layers))
+
+
+# --------------------------------------------------------------------------------------
+# Partitions (Section 2: each process m owns a disjoint set of steps T_m).
+# --------------------------------------------------------------------------------------
+def sorted_positions(inst) -> np.ndarray:
+    """Position of every order in the batch's (trajectory, SKU)-sorted list, ties kept in
+    time order."""
+    traj = np.repeat(np.arange(inst.n_traj, dtype=np.int64), np.diff(inst.traj_offsets))
+    key = traj * inst.K + inst.sku.astype(np.int64)
+    order = np.argsort(key, kind="stable")
+    pos = np.empty_like(order)
+    pos[order] = np.arange(order.size, dtype=np.int64)
+    return pos
+
+
+def block_workers(inst, block_len: int) -> np.ndarray:
+    """Process of every order when blocks of `block_len` consecutive positions of the
+    (trajectory, SKU)-sorted list form the processes.  block_len=1 gives every step its
+    own process; a block at least as long as every segment gives a product partition."""
+    return sorted_positions(inst) // int(block_len)
+
+
+def product_workers(inst, b: int = 0) -> np.ndarray:
+    """Product partition of Section 3: all orders of one SKU go to one process."""
+    lo, hi = int(inst.traj_offsets[b]), int(inst.traj_offsets[b + 1])
+    return inst.sku[lo:hi].astype(np.int64)
+
+
+def n_runs_per_segment(inst, worker: np.ndarray, b: int = 0) -> np.ndarray:
+    """Number of runs (maximal same-process stretches) of each SKU segment."""
+    lo, hi = int(inst.traj_offsets[b]), int(inst.traj_offsets[b + 1])
+    sku = inst.sku[lo:hi]
+    w = worker[lo:hi] if worker.size == inst.total_orders else worker
+    order = np.argsort(sku, kind="stable")
+    s, ww = sku[order], w[order]
+    new = np.ones(s.size, bool)
+    new[1:] = (s[1:] != s[:-1]) | (ww[1:] != ww[:-1])
+    return np.bincount(s[new], minlength=inst.K)

@@ -1,0 +1,577 @@
+/*
+ * CPU oracle for Picard policy simulation on the fulfillment problem.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the benchmark's
+ * CPU-baseline leg may load this library.  It shares no code with the GPU path.
+ *
+ * Everything here is written to be read against the paper, not to be fast:
+ *
+ *   orc_serial        the serial rollout that defines the answer (Section 2, problem
+ *                     statement: a_t = pi(s_t, w_t), s_{t+1} = f(s_t, a_t, w_t)), with the
+ *                     FO transition of Section 3 (no node capacity).
+ *   orc_alg1          Algorithm 1 (the Picard iteration) taken literally: every virtual
+ *                     process keeps its own full state and walks t = 1..T; cached actions
+ *                     that are infeasible locally are replaced by the always-feasible
+ *                     action (lost sale).  O(P*T*N) per pass: tiny instances only.
+ *   orc_picard_runs   The same passes, computed per SKU: by inventory independence
+ *                     (Assumption 1) and with no capacity, SKUs never interact, and for
+ *                     a partition where each process owns one contiguous run of a SKU's
+ *                     orders, the state a process sees at the start of its run is the
+ *                     initial inventory minus the cached consumption of earlier runs,
+ *                     clamped at zero (clamp: max(0, max(0, x-a) - b) = max(0, x-a-b)).
+ *                     Checked against orc_alg1 in the tests.
+ *   orc_eval_at       The policy evaluated at every step of a GIVEN action sequence
+ *                     (the state that sequence induces), for self-consistency checks.
+ *   orc_reinforce     FP64 REINFORCE surrogate sum_t A_t log pi(a_t | s_t) and its
+ *                     gradient by hand-written backpropagation (Section 4.2 trains the
+ *                     policy by policy gradient).
+ *   orc_philox4x32_10 Philox4x32-10 from Salmon, Moraes, Dror and Shaw, "Parallel random
+ *                     numbers: as easy as 1, 2, 3" (SC'11): the counter-based generator
+ *                     that supplies the learned policy's Gumbel noise (the paper lets the
+ *                     disturbance w_t carry the policy's own randomness, Section 2).
+ *
+ * Semantics fixed by this oracle (readings of the paper, see the design notes):
+ *   - a warehouse w is feasible for an order of SKU k iff x[k][w] > 0 (Section 3 action
+ *     set); an order of quantity q sent to w ships min(q, x[k][w]); the rest is lost;
+ *   - greedy policy: the feasible warehouse of least cost[w][region], lowest index on
+ *     ties, lost sale iff none is feasible (Section 3.1 greedy policy, with inventory in
+ *     place of capacity);
+ *   - learned policy: z_w = mlp(cost[w][r], log1p(x[k][w]), E[r]) + Gumbel(t, traj, w),
+ *     argmax over feasible w, lowest index on exact ties;
+ *   - "passes" is the k at which Algorithm 1 returns (alpha^k == alpha^{k-1}).
+ *
+ * parity unpinned: none of the functions here; pins live in tests/test_oracle_*.py.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define LOST (-1)
+
+typedef struct {
+    int32_t N, K, R;
+    int64_t T;
+    const int32_t *sku, *region, *qty; /* [T], time order */
+    const int32_t *x0;                 /* [K][N] */
+    const int32_t *cost;               /* [N][R] */
+    const float *params;               /* NULL: greedy policy; else learned policy */
+    int32_t hidden, n_hidden_layers;
+    uint64_t rng_seed;
+    int32_t traj; /* trajectory index inside its batch (part of the Philox counter) */
+} orc_problem;
+
+/* ------------------------------------------------------------------------------------
+ * Philox4x32-10 (SC'11).  Round: two 32x32->64 products of counter words 0 and 2 with
+ * the round multipliers; the new counter is (hi1^c1^k0, lo1, hi0^c3^k1, lo0).  The key
+ * is bumped by the Weyl constants between rounds.
+ * ---------------------------------------------------------------------------------- */
+void orc_philox4x32_10(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4])
+{
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint32_t k0 = key_in[0], k1 = key_in[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t p0 = (uint64_t)M0 * c0;
+        uint64_t p1 = (uint64_t)M1 * c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+        k0 += W0;
+        k1 += W1;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Uniform in (0,1): 23 random bits, centred: ((u >> 9) + 0.5) * 2^-23.  Every value is
+ * exactly representable in binary32, so both precisions start from the same U. */
+double orc_uniform(uint64_t seed, int32_t traj, int64_t t, int32_t w)
+{
+    uint32_t ctr[4] = {(uint32_t)t, (uint32_t)traj, (uint32_t)w >> 2, 0u};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t out[4];
+    orc_philox4x32_10(ctr, key, out);
+    uint32_t u = out[w & 3];
+    return ((double)(u >> 9) + 0.5) * (1.0 / 8388608.0);
+}
+
+double orc_gumbel(uint64_t seed, int32_t traj, int64_t t, int32_t w)
+{
+    return -log(-log(orc_uniform(seed, traj, t, w)));
+}
+
+/* ------------------------------------------------------------------------------------
+ * The learned score in FP64.  Parameter pack (float32 on input):
+ *   E[R][16] | W1[H][18] | b1[H] | (W2[H][H] | b2[H] if two hidden layers) | w3[H] | b3
+ * Features f = [cost, log1p(x), E[r][0..15]]; h1 = relu(W1 f + b1);
+ * h2 = relu(W2 h1 + b2); s = w3 . h_last + b3.
+ * ---------------------------------------------------------------------------------- */
+typedef struct {
+    int H, L, R;
+    double *E, *W1, *b1, *W2, *b2, *w3, b3;
+    double *buf;
+} mlp64;
+
+static int64_t param_count(int R, int H, int L)
+{
+    int64_t n = (int64_t)R * 16 + (int64_t)H * 18 + H;
+    if (L == 2) n += (int64_t)H * H + H;
+    return n + H + 1;
+}
+
+int64_t orc_param_count(int32_t R, int32_t H, int32_t L) { return param_count(R, H, L); }
+
+static int mlp_load(mlp64 *m, const orc_problem *P)
+{
+    m->H = P->hidden; m->L = P->n_hidden_layers; m->R = P->R;
+    if (m->H <= 0 || (m->L != 1 && m->L != 2)) return -1;
+    int64_t n = param_count(m->R, m->H, m->L);
+    m->buf = (double *)malloc(sizeof(double) * (size_t)n);
+    if (!m->buf) return -1;
+    for (int64_t i = 0; i < n; ++i) m->buf[i] = (double)P->params[i];
+    double *p = m->buf;
+    m->E = p; p += (int64_t)m->R * 16;
+    m->W1 = p; p += (int64_t)m->H * 18;
+    m->b1 = p; p += m->H;
+    if (m->L == 2) { m->W2 = p; p += (int64_t)m->H * m->H; m->b2 = p; p += m->H; }
+    else { m->W2 = NULL; m->b2 = NULL; }
+    m->w3 = p; p += m->H;
+    m->b3 = *p;
+    return 0;
+}
+
+static void mlp_free(mlp64 *m) { free(m->buf); m->buf = NULL; }
+
+/* Forward for one (order, warehouse) row.  pre1/h1/pre2/h2 may be NULL when the caller
+ * does not need the activations (they are used by the backward pass). */
+static double mlp_forward(const mlp64 *m, double cost, double inv, int r, double *f,
+                          double *pre1, double *h1, double *pre2, double *h2)
+{
+    const int H = m->H;
+    double f_loc[18], a1[1024], z1[1024], a2[1024], z2[1024];
+    if (!f) f = f_loc;
+    if (!pre1) pre1 = a1;
+    if (!h1) h1 = z1;
+    if (!pre2) pre2 = a2;
+    if (!h2) h2 = z2;
+    f[0] = cost;
+    f[1] = log1p(inv);
+    for (int i = 0; i < 16; ++i) f[2 + i] = m->E[r * 16 + i];
+    for (int j = 0; j < H; ++j) {
+        double acc = m->b1[j];
+        for (int i = 0; i < 18; ++i) acc += m->W1[j * 18 + i] * f[i];
+        pre1[j] = acc;
+        h1[j] = acc > 0.0 ? acc : 0.0;
+    }
+    const double *hl = h1;
+    if (m->L == 2) {
+        for (int j = 0; j < H; ++j) {
+            double acc = m->b2[j];
+            for (int i = 0; i < H; ++i) acc += m->W2[j * H + i] * h1[i];
+            pre2[j] = acc;
+            h2[j] = acc > 0.0 ? acc : 0.0;
+        }
+        hl = h2;
+    }
+    double s = m->b3;
+    for (int j = 0; j < H; ++j) s += m->w3[j] * hl[j];
+    return s;
+}
+
+/* ------------------------------------------------------------------------------------
+ * The policy pi(s_t, w_t) for one order.  `x` is the inventory row of the order's SKU.
+ * Returns the chosen warehouse or LOST; for the learned policy also the two largest
+ * perturbed scores among feasible warehouses (z1 >= z2; -inf when absent).
+ * ---------------------------------------------------------------------------------- */
+static int32_t policy(const orc_problem *P, const mlp64 *m, int64_t t, const int32_t *x,
+                      double *z1, double *z2)
+{
+    const int N = P->N, R = P->R;
+    const int r = P->region[t];
+    int32_t best = LOST;
+    if (!P->params) {
+        int32_t best_cost = 0;
+        for (int w = 0; w < N; ++w) {
+            if (x[w] <= 0) continue;
+            int32_t c = P->cost[w * R + r];
+            if (best == LOST || c < best_cost) { best = w; best_cost = c; }
+        }
+        return best;
+    }
+    double top1 = -INFINITY, top2 = -INFINITY;
+    for (int w = 0; w < N; ++w) {
+        if (x[w] <= 0) continue;
+        double s = mlp_forward(m, (double)P->cost[w * R + r], (double)x[w], r, NULL, NULL,
+                               NULL, NULL, NULL);
+        double z = s + orc_gumbel(P->rng_seed, P->traj, t, w);
+        if (best == LOST || z > top1) { top2 = top1; top1 = z; best = w; }
+        else if (z > top2) top2 = z;
+    }
+    if (z1) *z1 = top1;
+    if (z2) *z2 = top2;
+    return best;
+}
+
+/* f(s, a, w) restricted to the order's SKU row: ship min(q, x[a]). Returns shipped. */
+static int32_t transition(int32_t *x, int32_t a, int32_t q)
+{
+    if (a == LOST) return 0;
+    int32_t sh = x[a] < q ? x[a] : q;
+    x[a] -= sh;
+    return sh;
+}
+
+static int check_problem(const orc_problem *P)
+{
+    if (P->N <= 0 || P->K <= 0 || P->R <= 0 || P->T < 0) return -1;
+    for (int64_t t = 0; t < P->T; ++t) {
+        if (P->sku[t] < 0 || P->sku[t] >= P->K) return -1;
+        if (P->region[t] < 0 || P->region[t] >= P->R) return -1;
+        if (P->qty[t] < 1) return -1;
+    }
+    for (int64_t i = 0; i < (int64_t)P->K * P->N; ++i)
+        if (P->x0[i] < 0) return -1;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------
+ * Serial rollout (the definition of the answer).
+ * ---------------------------------------------------------------------------------- */
+int orc_serial(const orc_problem *P, int32_t *actions, int32_t *shipped, int32_t *final_inv,
+               double *z1, double *z2)
+{
+    if (check_problem(P)) return -1;
+    const int N = P->N;
+    mlp64 m = {0};
+    if (P->params && mlp_load(&m, P)) return -1;
+    int32_t *x = (int32_t *)malloc(sizeof(int32_t) * (size_t)P->K * N);
+    if (!x) { mlp_free(&m); return -1; }
+    memcpy(x, P->x0, sizeof(int32_t) * (size_t)P->K * N);
+    for (int64_t t = 0; t < P->T; ++t) {
+        int32_t *xk = x + (int64_t)P->sku[t] * N;
+        double a1 = -INFINITY, a2 = -INFINITY;
+        int32_t a = policy(P, &m, t, xk, &a1, &a2);
+        int32_t sh = transition(xk, a, P->qty[t]);
+        actions[t] = a;
+        if (shipped) shipped[t] = sh;
+        if (z1) z1[t] = a1;
+        if (z2) z2[t] = a2;
+    }
+    if (final_inv) memcpy(final_inv, x, sizeof(int32_t) * (size_t)P->K * N);
+    free(x);
+    mlp_free(&m);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------
+ * Policy evaluated at the states induced by a given action sequence.
+ * choice[t] = pi(s_t) where s_t follows from actions[0..t-1]; z1/z2 as in policy();
+ * n_feasible[t] = |{w : x[w] > 0}|.  Any pointer but actions/choice may be NULL.
+ * Returns -2 if a given action is infeasible at its state (it cannot come from pi).
+ * ---------------------------------------------------------------------------------- */
+int orc_eval_at(const orc_problem *P, const int32_t *actions, int32_t *choice, double *z1,
+                double *z2, int32_t *n_feasible)
+{
+    if (check_problem(P)) return -1;
+    const int N = P->N;
+    mlp64 m = {0};
+    if (P->params && mlp_load(&m, P)) return -1;
+    int32_t *x = (int32_t *)malloc(sizeof(int32_t) * (size_t)P->K * N);
+    if (!x) { mlp_free(&m); return -1; }
+    memcpy(x, P->x0, sizeof(int32_t) * (size_t)P->K * N);
+    int rc = 0;
+    for (int64_t t = 0; t < P->T; ++t) {
+        int32_t *xk = x + (int64_t)P->sku[t] * N;
+        double a1 = -INFINITY, a2 = -INFINITY;
+        choice[t] = policy(P, &m, t, xk, &a1, &a2);
+        if (z1) z1[t] = a1;
+        if (z2) z2[t] = a2;
+        if (n_feasible) {
+            int32_t c = 0;
+            for (int w = 0; w < N; ++w) c += xk[w] > 0;
+            n_feasible[t] = c;
+        }
+        int32_t a = actions[t];
+        if (a != LOST && (a < 0 || a >= N || xk[a] <= 0)) { rc = -2; break; }
+        transition(xk, a, P->qty[t]);
+    }
+    free(x);
+    mlp_free(&m);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------------------
+ * Algorithm 1, literally.  worker[t] in [0, P) is the process owning step t.
+ * init_cache may be NULL (alpha^0 = lost sale everywhere).  caches (nullable) receives
+ * alpha^1 .. alpha^passes, T entries each (room for max_passes rows).
+ * Returns 0 when converged (passes = the k with alpha^k == alpha^{k-1}), 1 when
+ * max_passes was reached first (final_cache holds alpha^max_passes), < 0 on bad input.
+ * ---------------------------------------------------------------------------------- */
+int orc_alg1(const orc_problem *P, const int64_t *worker, int64_t n_workers,
+             const int32_t *init_cache, int32_t max_passes, int32_t *final_cache,
+             int32_t *passes, int32_t *caches)
+{
+    if (check_problem(P) || n_workers <= 0 || max_passes <= 0) return -1;
+    const int N = P->N;
+    const int64_t T = P->T, KN = (int64_t)P->K * N;
+    for (int64_t t = 0; t < T; ++t)
+        if (worker[t] < 0 || worker[t] >= n_workers) return -1;
+    mlp64 m = {0};
+    if (P->params && mlp_load(&m, P)) return -1;
+    int32_t *prev = (int32_t *)malloc(sizeof(int32_t) * (size_t)(T + 1));
+    int32_t *next = (int32_t *)malloc(sizeof(int32_t) * (size_t)(T + 1));
+    int32_t *x = (int32_t *)malloc(sizeof(int32_t) * (size_t)KN);
+    if (!prev || !next || !x) { free(prev); free(next); free(x); mlp_free(&m); return -1; }
+    for (int64_t t = 0; t < T; ++t) prev[t] = init_cache ? init_cache[t] : LOST;
+    int rc = 1;
+    int32_t k = 0;
+    for (k = 1; k <= max_passes; ++k) {
+        for (int64_t proc = 0; proc < n_workers; ++proc) {
+            memcpy(x, P->x0, sizeof(int32_t) * (size_t)KN); /* s_1^{k,m} = s_1 */
+            for (int64_t t = 0; t < T; ++t) {
+                int32_t *xk = x + (int64_t)P->sku[t] * N;
+                int32_t a;
+                if (worker[t] == proc) {
+                    a = policy(P, &m, t, xk, NULL, NULL);
+                    next[t] = a; /* alpha^k_t = a^{k,m}_t for t in T_m */
+                } else {
+                    a = prev[t];
+                    /* cached action if feasible at the local state, else a^phi */
+                    if (a != LOST && (a < 0 || a >= N || xk[a] <= 0)) a = LOST;
+                }
+                transition(xk, a, P->qty[t]);
+            }
+        }
+        if (caches) memcpy(caches + (int64_t)(k - 1) * T, next, sizeof(int32_t) * (size_t)T);
+        int same = 1;
+        for (int64_t t = 0; t < T; ++t)
+            if (next[t] != prev[t]) { same = 0; break; }
+        int32_t *tmp = prev; prev = next; next = tmp;
+        if (same) { rc = 0; break; }
+    }
+    if (k > max_passes) k = max_passes;
+    *passes = k;
+    memcpy(final_cache, prev, sizeof(int32_t) * (size_t)T);
+    free(prev); free(next); free(x);
+    mlp_free(&m);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------------------
+ * The same passes, per SKU.  Orders of SKU k in time order form its segment; a run is
+ * a maximal stretch of the segment owned by one process.  Each process must own at
+ * most one run per segment (true for blocks of the SKU-sorted order list, and for one
+ * process per step); otherwise -2.  Per pass and per segment, runs are visited in order:
+ *   entry state = max(0, x0[k] - E), E = cached consumption (sum of q over earlier runs'
+ *   orders sent to each warehouse under alpha^{k-1});
+ *   the run is walked with the process's own decisions.
+ * changed (nullable): number of steps with alpha^k != alpha^{k-1}, per pass.
+ * ---------------------------------------------------------------------------------- */
+int orc_picard_runs(const orc_problem *P, const int64_t *worker, const int32_t *init_cache,
+                    int32_t max_passes, int32_t *final_cache, int32_t *passes,
+                    int64_t *changed, int32_t *caches)
+{
+    if (check_problem(P) || max_passes <= 0) return -1;
+    const int N = P->N, K = P->K;
+    const int64_t T = P->T;
+    mlp64 m = {0};
+    if (P->params && mlp_load(&m, P)) return -1;
+    /* stable counting sort of steps by SKU */
+    int64_t *start = (int64_t *)calloc((size_t)K + 1, sizeof(int64_t));
+    int64_t *fill = (int64_t *)calloc((size_t)K + 1, sizeof(int64_t));
+    int64_t *pos = (int64_t *)malloc(sizeof(int64_t) * (size_t)(T + 1));
+    int32_t *prev = (int32_t *)malloc(sizeof(int32_t) * (size_t)(T + 1));
+    int32_t *next = (int32_t *)malloc(sizeof(int32_t) * (size_t)(T + 1));
+    int64_t *E = (int64_t *)malloc(sizeof(int64_t) * (size_t)N);
+    int32_t *x = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
+    int rc = 0;
+    if (!start || !fill || !pos || !prev || !next || !E || !x) { rc = -1; goto done; }
+    for (int64_t t = 0; t < T; ++t) start[P->sku[t] + 1]++;
+    for (int k = 0; k < K; ++k) start[k + 1] += start[k];
+    for (int64_t t = 0; t < T; ++t) {
+        int s = P->sku[t];
+        pos[start[s] + fill[s]++] = t;
+    }
+    /* each process owns at most one run per segment */
+    for (int k = 0; k < K && rc == 0; ++k) {
+        for (int64_t i = start[k]; i < start[k + 1]; ++i) {
+            if (i == start[k] || worker[pos[i]] == worker[pos[i - 1]]) continue;
+            for (int64_t j = start[k]; j < i; ++j)
+                if (worker[pos[j]] == worker[pos[i]]) { rc = -2; break; }
+            if (rc) break;
+        }
+    }
+    if (rc) goto done;
+    for (int64_t t = 0; t < T; ++t) prev[t] = init_cache ? init_cache[t] : LOST;
+    rc = 1;
+    int32_t k;
+    for (k = 1; k <= max_passes; ++k) {
+        for (int s = 0; s < K; ++s) {
+            for (int w = 0; w < N; ++w) E[w] = 0;
+            const int32_t *x0k = P->x0 + (int64_t)s * N;
+            int64_t i = start[s];
+            while (i < start[s + 1]) {
+                int64_t j = i;
+                while (j < start[s + 1] && worker[pos[j]] == worker[pos[i]]) ++j;
+                for (int w = 0; w < N; ++w) {
+                    int64_t v = (int64_t)x0k[w] - E[w];
+                    x[w] = v > 0 ? (int32_t)v : 0;
+                }
+                for (int64_t p = i; p < j; ++p) {
+                    int64_t t = pos[p];
+                    int32_t a = policy(P, &m, t, x, NULL, NULL);
+                    next[t] = a;
+                    transition(x, a, P->qty[t]);
+                }
+                for (int64_t p = i; p < j; ++p) {
+                    int64_t t = pos[p];
+                    if (prev[t] != LOST) E[prev[t]] += P->qty[t];
+                }
+                i = j;
+            }
+        }
+        int64_t nchg = 0;
+        for (int64_t t = 0; t < T; ++t) nchg += next[t] != prev[t];
+        if (changed) changed[k - 1] = nchg;
+        if (caches) memcpy(caches + (int64_t)(k - 1) * T, next, sizeof(int32_t) * (size_t)T);
+        int32_t *tmp = prev; prev = next; next = tmp;
+        if (nchg == 0) { rc = 0; break; }
+    }
+    if (k > max_passes) k = max_passes;
+    *passes = k;
+    memcpy(final_cache, prev, sizeof(int32_t) * (size_t)T);
+done:
+    free(start); free(fill); free(pos); free(prev); free(next); free(E); free(x);
+    mlp_free(&m);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------------------
+ * REINFORCE surrogate and gradient, FP64, at fixed actions.
+ *   L = sum_t A_t log pi(a_t | s_t),  pi(. | s) = softmax over feasible w of s_w
+ * (the Gumbel-max rule samples exactly from this softmax).  Steps with no feasible
+ * warehouse contribute 0 (then a_t must be the lost sale).  logp[t] (nullable) receives
+ * log pi(a_t | s_t); grad (nullable) the gradient in the parameter-pack layout.
+ * Returns -2 when an action is not in the feasible set of its state.
+ * ---------------------------------------------------------------------------------- */
+int orc_reinforce(const orc_problem *P, const int32_t *actions, const double *adv,
+                  double *logp, double *grad, double *objective)
+{
+    if (check_problem(P) || !P->params) return -1;
+    const int N = P->N, R = P->R;
+    mlp64 m = {0};
+    if (mlp_load(&m, P)) return -1;
+    const int H = m.H;
+    if (H > 1024) { mlp_free(&m); return -1; }
+    int64_t np = param_count(R, H, m.L);
+    double *g = grad ? grad : NULL;
+    if (g) memset(g, 0, sizeof(double) * (size_t)np);
+    double *gE = g, *gW1 = g ? g + (int64_t)R * 16 : NULL;
+    double *gb1 = gW1 ? gW1 + (int64_t)H * 18 : NULL;
+    double *gW2 = NULL, *gb2 = NULL, *gw3, *gb3;
+    if (m.L == 2 && g) { gW2 = gb1 + H; gb2 = gW2 + (int64_t)H * H; gw3 = gb2 + H; }
+    else gw3 = gb1 ? gb1 + H : NULL;
+    gb3 = gw3 ? gw3 + H : NULL;
+
+    int32_t *x = (int32_t *)malloc(sizeof(int32_t) * (size_t)P->K * N);
+    double *s = (double *)malloc(sizeof(double) * (size_t)N);
+    double *F = (double *)malloc(sizeof(double) * (size_t)N * 18);
+    double *PRE1 = (double *)malloc(sizeof(double) * (size_t)N * H);
+    double *H1 = (double *)malloc(sizeof(double) * (size_t)N * H);
+    double *PRE2 = (double *)malloc(sizeof(double) * (size_t)N * H);
+    double *H2 = (double *)malloc(sizeof(double) * (size_t)N * H);
+    double *dh = (double *)malloc(sizeof(double) * (size_t)H);
+    double *dp2 = (double *)malloc(sizeof(double) * (size_t)H);
+    double *dp1 = (double *)malloc(sizeof(double) * (size_t)H);
+    int rc = 0;
+    if (!x || !s || !F || !PRE1 || !H1 || !PRE2 || !H2 || !dh || !dp2 || !dp1) { rc = -1; goto out; }
+    memcpy(x, P->x0, sizeof(int32_t) * (size_t)P->K * N);
+    double L = 0.0;
+    for (int64_t t = 0; t < P->T; ++t) {
+        int32_t *xk = x + (int64_t)P->sku[t] * N;
+        const int r = P->region[t];
+        const int32_t a = actions[t];
+        int nf = 0;
+        for (int w = 0; w < N; ++w) nf += xk[w] > 0;
+        if (nf == 0) {
+            if (a != LOST) { rc = -2; break; }
+            if (logp) logp[t] = 0.0;
+            continue;
+        }
+        if (a < 0 || a >= N || xk[a] <= 0) { rc = -2; break; }
+        double mx = -INFINITY;
+        for (int w = 0; w < N; ++w) {
+            if (xk[w] <= 0) continue;
+            s[w] = mlp_forward(&m, (double)P->cost[w * R + r], (double)xk[w], r, F + w * 18,
+                               PRE1 + (int64_t)w * H, H1 + (int64_t)w * H,
+                               PRE2 + (int64_t)w * H, H2 + (int64_t)w * H);
+            if (s[w] > mx) mx = s[w];
+        }
+        double se = 0.0;
+        for (int w = 0; w < N; ++w)
+            if (xk[w] > 0) se += exp(s[w] - mx);
+        const double lse = mx + log(se);
+        const double lp = s[a] - lse;
+        if (logp) logp[t] = lp;
+        L += adv[t] * lp;
+        if (g) {
+            for (int w = 0; w < N; ++w) {
+                if (xk[w] <= 0) continue;
+                const double p = exp(s[w] - lse);
+                const double ds = adv[t] * ((w == a ? 1.0 : 0.0) - p);
+                const double *h1 = H1 + (int64_t)w * H, *h2 = H2 + (int64_t)w * H;
+                const double *pre1 = PRE1 + (int64_t)w * H, *pre2 = PRE2 + (int64_t)w * H;
+                const double *hl = m.L == 2 ? h2 : h1;
+                *gb3 += ds;
+                for (int j = 0; j < H; ++j) { gw3[j] += ds * hl[j]; dh[j] = ds * m.w3[j]; }
+                if (m.L == 2) {
+                    for (int j = 0; j < H; ++j) dp2[j] = pre2[j] > 0.0 ? dh[j] : 0.0;
+                    for (int j = 0; j < H; ++j) {
+                        gb2[j] += dp2[j];
+                        for (int i = 0; i < H; ++i) gW2[j * H + i] += dp2[j] * h1[i];
+                    }
+                    for (int i = 0; i < H; ++i) {
+                        double acc = 0.0;
+                        for (int j = 0; j < H; ++j) acc += m.W2[j * H + i] * dp2[j];
+                        dh[i] = acc;
+                    }
+                }
+                for (int j = 0; j < H; ++j) dp1[j] = pre1[j] > 0.0 ? dh[j] : 0.0;
+                const double *f = F + w * 18;
+                for (int j = 0; j < H; ++j) {
+                    gb1[j] += dp1[j];
+                    for (int i = 0; i < 18; ++i) gW1[j * 18 + i] += dp1[j] * f[i];
+                }
+                for (int i = 0; i < 16; ++i) {
+                    double acc = 0.0;
+                    for (int j = 0; j < H; ++j) acc += m.W1[j * 18 + 2 + i] * dp1[j];
+                    gE[r * 16 + i] += acc;
+                }
+            }
+        }
+        transition(xk, a, P->qty[t]);
+    }
+    if (objective) *objective = L;
+out:
+    free(x); free(s); free(F); free(PRE1); free(H1); free(PRE2); free(H2);
+    free(dh); free(dp2); free(dp1);
+    mlp_free(&m);
+    return rc;
+}
+
+/* Raw (noise-free) scores of every warehouse for region r at inventory row x. */
+int orc_mlp_scores(const orc_problem *P, int32_t r, const int32_t *x, double *s)
+{
+    if (!P->params || r < 0 || r >= P->R) return -1;
+    mlp64 m = {0};
+    if (mlp_load(&m, P)) return -1;
+    for (int w = 0; w < P->N; ++w)
+        s[w] = mlp_forward(&m, (double)P->cost[w * P->R + r], (double)x[w], r, NULL, NULL,
+                           NULL, NULL, NULL);
+    mlp_free(&m);
+    return 0;
+}

@@ -1,0 +1,196 @@
+"""Seeded synthetic fulfillment instances (inputs only; none of the method's arithmetic).
+
+The fulfillment-optimization model of Section 3 has I products (here K SKUs) stocked at
+J nodes (here N warehouses); every order carries a product and a reward vector.  The
+paper's own data (population-weighted nodes, zip-code distances; Appendix A.3, data
+generation) is not available, so every instance here is synthetic:
+
+* SKU of each order: Zipf with exponent 1.1 over K, P(k) proportional to (k+1)^-1.1
+  (the heavy-tailed demand shape Q_i ~ i^beta of Section 4.1, with beta = -1.1);
+* region of each order: uniform over R; the reward of warehouse w for region r is
+  -cost[w, r], with integer cost uniform in 1..100 (stands in for the distance reward);
+* quantity: 1, or a geometric(p=0.6) law truncated to 1..qmax and renormalised;
+* initial inventory x0[k, w] ~ Poisson(0.8 * T * P(k) * E[q] / N): the network holds
+  80% of expected demand (Appendix A.3), split evenly over warehouses;
+* learned-policy parameters: PyTorch-default-style uniform init, embedding ~ N(0, 1).
+
+This module is shared by the CPU oracle's tests and by the GPU path's tests and
+benchmark; it only draws numbers.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Dict, List, Optional
+
+import numpy as np
+
+EMB_DIM = 16
+N_FEATURES = 2 + EMB_DIM  # [cost, log1p(inventory), region embedding]
+
+# Named workloads (sizes as stated in the project brief).  T is either an int or a
+# (lo, hi) inclusive range drawn per trajectory from `t_seed`.
+WORKLOADS: Dict[str, dict] = {
+    "greedy_n10_k100_t1e4": dict(N=10, K=100, R=20, T=10_000, qmax=1, n_traj=1,
+                                 seed0=1, policy="greedy", block_len=100),
+    "greedy_n100_k1e5_t1e6": dict(N=100, K=100_000, R=200, T=1_000_000, qmax=1,
+                                  n_traj=1, seed0=2, policy="greedy"),
+    "greedy_batch256_n50_k2e4": dict(N=50, K=20_000, R=100, T=(10_000, 1_000_000),
+                                     t_seed=3999, qmax=3, n_traj=256, seed0=3000,
+                                     policy="greedy"),
+    "mlp_batch64_n100_k5e4_t2e5": dict(N=100, K=50_000, R=200, T=200_000, qmax=1,
+                                       n_traj=64, seed0=4000, theta_seed=4999,
+                                       policy="mlp"),
+    "mlp_batch16_n500_k1e6_t1e7": dict(N=500, K=1_000_000, R=500, T=10_000_000,
+                                       qmax=4, n_traj=16, seed0=5000, theta_seed=5999,
+                                       policy="mlp"),
+}
+
+
+@dataclasses.dataclass
+class Instance:
+    """A batch of independent trajectories, orders concatenated in CSR form."""
+    N: int
+    K: int
+    R: int
+    traj_offsets: np.ndarray  # int64 [n_traj + 1]
+    sku: np.ndarray           # int32 [sum T]
+    region: np.ndarray        # int32 [sum T]
+    qty: np.ndarray           # int32 [sum T]
+    x0: np.ndarray            # int32 [n_traj, K, N]
+    cost: np.ndarray          # int32 [n_traj, N, R]
+    rng_seed: int             # Philox key for the learned policy's Gumbel noise
+    params: Optional[np.ndarray] = None  # float32 flat learned-policy parameters
+    hidden: int = 64
+    n_hidden_layers: int = 2
+    name: str = ""
+
+    @property
+    def n_traj(self) -> int:
+        return int(self.traj_offsets.shape[0] - 1)
+
+    @property
+    def total_orders(self) -> int:
+        return int(self.traj_offsets[-1])
+
+    def horizon(self, b: int) -> int:
+        return int(self.traj_offsets[b + 1] - self.traj_offsets[b])
+
+    def trajectory(self, b: int) -> "Instance":
+        """Trajectory b as a one-trajectory instance (views, no copies)."""
+        lo, hi = int(self.traj_offsets[b]), int(self.traj_offsets[b + 1])
+        return dataclasses.replace(
+            self, traj_offsets=np.array([0, hi - lo], dtype=np.int64),
+            sku=self.sku[lo:hi], region=self.region[lo:hi], qty=self.qty[lo:hi],
+            x0=self.x0[b:b + 1], cost=self.cost[b:b + 1])
+
+
+def zipf_probs(K: int, exponent: float = 1.1) -> np.ndarray:
+    p = (np.arange(K, dtype=np.float64) + 1.0) ** (-exponent)
+    return p / p.sum()
+
+
+def qty_probs(qmax: int, p: float = 0.6) -> np.ndarray:
+    j = np.arange(1, qmax + 1, dtype=np.float64)
+    w = p * (1.0 - p) ** (j - 1)
+    return w / w.sum()
+
+
+def param_count(R: int, hidden: int = 64, n_hidden_layers: int = 2) -> int:
+    n = R * EMB_DIM + hidden * N_FEATURES + hidden
+    if n_hidden_layers == 2:
+        n += hidden * hidden + hidden
+    return n + hidden + 1
+
+
+def make_params(R: int, seed: int, hidden: int = 64, n_hidden_layers: int = 2) -> np.ndarray:
+    """Flat float32 pack: E[R][16] | W1[H][18] | b1[H] | (W2[H][H] | b2[H]) | w3[H] | b3."""
+    rng = np.random.default_rng(seed)
+    parts: List[np.ndarray] = [rng.standard_normal((R, EMB_DIM))]
+    a1 = 1.0 / np.sqrt(N_FEATURES)
+    parts += [rng.uniform(-a1, a1, (hidden, N_FEATURES)), rng.uniform(-a1, a1, hidden)]
+    ah = 1.0 / np.sqrt(hidden)
+    if n_hidden_layers == 2:
+        parts += [rng.uniform(-ah, ah, (hidden, hidden)), rng.uniform(-ah, ah, hidden)]
+    parts += [rng.uniform(-ah, ah, hidden), rng.uniform(-ah, ah, 1)]
+    out = np.concatenate([x.ravel() for x in parts]).astype(np.float32)
+    assert out.size == param_count(R, hidden, n_hidden_layers)
+    return out
+
+
+def make_trajectory(N: int, K: int, R: int, T: int, qmax: int, seed: int):
+    """One trajectory's orders, cost table and initial inventory."""
+    rng = np.random.default_rng(seed)
+    pk = zipf_probs(K)
+    cdf = np.cumsum(pk)
+    cdf[-1] = 1.0
+    sku = np.minimum(np.searchsorted(cdf, rng.random(T), side="right"), K - 1)
+    region = rng.integers(0, R, size=T)
+    if qmax == 1:
+        qty = np.ones(T, dtype=np.int32)
+        mean_q = 1.0
+    else:
+        pq = qty_probs(qmax)
+        qcdf = np.cumsum(pq)
+        qcdf[-1] = 1.0
+        qty = np.minimum(np.searchsorted(qcdf, rng.random(T), side="right"), qmax - 1) + 1
+        mean_q = float((np.arange(1, qmax + 1) * pq).sum())
+    cost = rng.integers(1, 101, size=(N, R))
+    lam = 0.8 * T * pk * mean_q / N
+    x0 = rng.poisson(lam[:, None], size=(K, N))
+    return (sku.astype(np.int32), region.astype(np.int32), qty.astype(np.int32),
+            cost.astype(np.int32), x0.astype(np.int32))
+
+
+def make_instance(name: str, **overrides) -> Instance:
+    """Build the named workload; keyword overrides shrink it (e.g. T=5000, n_traj=4)."""
+    cfg = dict(WORKLOADS[name])
+    cfg.update(overrides)
+    N, K, R, n_traj, qmax = cfg["N"], cfg["K"], cfg["R"], cfg["n_traj"], cfg["qmax"]
+    T = cfg["T"]
+    if isinstance(T, tuple):
+        lo, hi = T
+        Ts = np.random.default_rng(cfg["t_seed"]).integers(lo, hi + 1, size=n_traj)
+    else:
+        Ts = np.full(n_traj, int(T), dtype=np.int64)
+    offs = np.zeros(n_traj + 1, dtype=np.int64)
+    offs[1:] = np.cumsum(Ts)
+    total = int(offs[-1])
+    sku = np.empty(total, np.int32)
+    region = np.empty(total, np.int32)
+    qty = np.empty(total, np.int32)
+    x0 = np.empty((n_traj, K, N), np.int32)
+    cost = np.empty((n_traj, N, R), np.int32)
+    for b in range(n_traj):
+        s, r, q, c, x = make_trajectory(N, K, R, int(Ts[b]), qmax, cfg["seed0"] + b)
+        sl = slice(int(offs[b]), int(offs[b + 1]))
+        sku[sl], region[sl], qty[sl] = s, r, q
+        cost[b], x0[b] = c, x
+    params = None
+    hidden = cfg.get("hidden", 64)
+    nhl = cfg.get("n_hidden_layers", 2)
+    if cfg["policy"] == "mlp":
+        params = make_params(R, cfg["theta_seed"], hidden, nhl)
+    rng_seed = (int(cfg.get("theta_seed", 0)) << 32) | int(cfg["seed0"])
+    return Instance(N=N, K=K, R=R, traj_offsets=offs, sku=sku, region=region, qty=qty,
+                    x0=x0, cost=cost, rng_seed=rng_seed, params=params, hidden=hidden,
+                    n_hidden_layers=nhl, name=name)
+
+
+def random_tiny(seed: int, N: int = 4, K: int = 3, R: int = 3, T: int = 12, qmax: int = 1,
+                inv_max: int = 3, n_traj: int = 1, mlp: bool = False,
+                n_hidden_layers: int = 2) -> Instance:
+    """Small random instances for brute-force checks (uniform SKUs, small inventories)."""
+    rng = np.random.default_rng(seed)
+    Ts = rng.integers(max(1, T // 2), T + 1, size=n_traj) if n_traj > 1 else np.array([T])
+    offs = np.zeros(n_traj + 1, dtype=np.int64)
+    offs[1:] = np.cumsum(Ts)
+    total = int(offs[-1])
+    sku = rng.integers(0, K, total).astype(np.int32)
+    region = rng.integers(0, R, total).astype(np.int32)
+    qty = rng.integers(1, qmax + 1, total).astype(np.int32)
+    x0 = rng.integers(0, inv_max + 1, (n_traj, K, N)).astype(np.int32)
+    cost = rng.integers(1, 6, (n_traj, N, R)).astype(np.int32)
+    params = make_params(R, seed + 7919, 64, n_hidden_layers) if mlp else None
+    return Instance(N=N, K=K, R=R, traj_offsets=offs, sku=sku, region=region, qty=qty,
+                    x0=x0, cost=cost, rng_seed=int(rng.integers(0, 2**63)), params=params,
+                    n_hidden_layers=n_hidden_layers, name=f"tiny{seed}")
