@@ -1,0 +1,197 @@
+/*
+ * libpicard: Picard-iteration policy simulation for the fulfillment problem on MI355X.
+ *
+ * The problem (Section 2, problem statement): given an initial state s_1, a horizon T and
+ * disturbances w_1..w_T, produce the actions a_t = pi(s_t, w_t) of the serial rollout
+ * s_{t+1} = f(s_t, a_t, w_t).  Here the state is the inventory x[k][w] of K SKUs at N
+ * warehouses, an order (disturbance) carries a SKU, a region and a quantity, and the
+ * transition (Section 3, FO model, without node capacity) ships min(q, x[k][a]) from the
+ * chosen warehouse a; the always-feasible action a^phi is the lost sale PK_LOST.
+ *
+ * pk_picard_simulate computes that rollout with Algorithm 1 (the Picard iteration):
+ * steps are split among processes, every step keeps a cached action, each pass
+ * rebuilds every process's state from the cache, re-evaluates the policy on all
+ * process-owned steps at once and rewrites the cache, and the iteration stops at the
+ * first pass that changes nothing, whose cache equals the serial rollout
+ * (Proposition 2.1).
+ *
+ * Conventions shared by every entry point
+ *   - Array pointers are DEVICE pointers (memory of the current HIP device) unless
+ *     marked HOST.  The caller owns every buffer; the library only borrows them for the
+ *     duration of the call and never frees or keeps them.
+ *   - Work is enqueued on `stream` (0 = the null stream).  Calls that iterate to
+ *     convergence block the calling thread until the result is final.
+ *   - Orders of a batch of independent trajectories are concatenated: trajectory b owns
+ *     orders [traj_offsets[b], traj_offsets[b+1]) in time order.
+ *   - Scratch memory is the caller's `ws` buffer of `ws_bytes` bytes; its size comes from
+ *     pk_workspace_size for the same problem, policy and options.
+ *   - No exception or abort crosses this interface.  On any status other than PK_OK,
+ *     pk_last_error() returns a message (thread-local, valid until the next call).
+ *   - Host-side shape checks always run.  Device-side range checks of the inputs
+ *     (SKU, region, quantity, initial inventory, initial cache) run when
+ *     pk_picard_opts.validate (or the validate argument) is nonzero.
+ */
+#ifndef PICARD_H
+#define PICARD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PK_OK = 0,
+    PK_ERR_INVALID_ARG = -1,   /* a pointer, size or option is invalid, or validate found
+                                  an out-of-range input value */
+    PK_ERR_SHAPE = -2,         /* dimensions inconsistent or beyond the supported limits */
+    PK_ERR_HIP = -3,           /* a HIP runtime call failed */
+    PK_ERR_NOT_CONVERGED = -4, /* max_passes reached; outputs hold the last cache */
+    PK_ERR_WORKSPACE = -5,     /* ws is NULL or smaller than pk_workspace_size */
+    PK_ERR_UNSUPPORTED = -6    /* a valid request this build does not implement */
+} pk_status;
+
+#define PK_LOST (-1) /* the lost sale a^phi: no warehouse ships the order */
+
+/* Limits of this build (checked on the host, PK_ERR_SHAPE beyond them). */
+#define PK_MAX_WAREHOUSES 1024
+#define PK_MAX_REGIONS 4096
+
+/* The inputs s_1 and {w_t} of the problem statement (Section 2), instantiated for the
+ * FO model of Section 3 (products -> SKUs, nodes -> warehouses, reward r_w(w_t) ->
+ * -cost[w][region_t]). */
+typedef struct pk_problem {
+    int32_t n_warehouses;          /* N >= 1 */
+    int32_t n_skus;                /* K >= 1 */
+    int32_t n_regions;             /* R >= 1 */
+    int32_t n_traj;                /* trajectories in the batch, >= 1 */
+    const int64_t *traj_offsets;   /* HOST [n_traj+1], nondecreasing, traj_offsets[0] = 0,
+                                      total orders traj_offsets[n_traj] < 2^31 */
+    const int32_t *sku;            /* [total] in [0, K) */
+    const int32_t *region;         /* [total] in [0, R) */
+    const int32_t *qty;            /* [total] >= 1 */
+    const int32_t *init_inv;       /* [n_traj][K][N] x0 >= 0 */
+    const int32_t *cost;           /* [n_traj][N][R] order cost of warehouse w for region r */
+    uint64_t rng_seed;             /* Philox4x32-10 key of the learned policy's noise */
+} pk_problem;
+
+typedef enum { PK_POLICY_GREEDY = 0, PK_POLICY_MLP = 1 } pk_policy_kind;
+
+/* The policy pi.
+ * GREEDY (Section 3.1 greedy policy, inventory as the constraint): the warehouse with
+ *   stock (x > 0) of least cost[w][region], lowest index on ties; PK_LOST iff none.
+ * MLP (learned softmax policy, Section 4.2 trains a policy by policy gradient): score
+ *   s_w = mlp(cost[w][r], log1p(x[k][w]), E[r]) with two (or one) ReLU hidden layers
+ *   of width `hidden`; the action is argmax over warehouses with stock of
+ *   s_w + G(t, traj, w), G a Gumbel variate from Philox4x32-10 (key rng_seed, counter
+ *   (t, traj, w >> 2, 0), output word w & 3, U = ((u >> 9) + 0.5) 2^-23,
+ *   G = -log(-log U)), lowest index on exact ties; this samples softmax(s) over the
+ *   warehouses with stock.  The noise is part of the disturbance (Section 2).
+ * params (MLP only; DEVICE, float32, caller-owned), flat pack:
+ *   E[R][16] | W1[hidden][18] | b1[hidden] | (W2[hidden][hidden] | b2[hidden]) | w3[hidden] | b3
+ *   feature order [cost, log1p(inventory), E[region][0..15]]; W2/b2 absent with one layer. */
+typedef struct pk_policy {
+    int32_t kind;            /* pk_policy_kind */
+    int32_t n_hidden_layers; /* MLP: 1 or 2 */
+    int32_t hidden;          /* MLP: 64 */
+    int32_t emb_dim;         /* MLP: 16 */
+    const float *params;     /* MLP: device parameter pack; ignored by GREEDY */
+} pk_policy;
+
+/* Options of the Picard iteration (Algorithm 1 and Appendix A.3's restart rule). */
+typedef struct pk_picard_opts {
+    int32_t block_len;    /* Partition: the batch's orders sorted by (trajectory, SKU),
+                             ties in time order, are cut into blocks of block_len
+                             consecutive positions; block m is process m.  1 gives every
+                             step its own process; a block at least as long as every
+                             SKU's order list is a product partition (Section 3).
+                             0 = autotuned. */
+    int32_t max_passes;   /* cap on passes; 0 = (longest horizon) + 1, the bound of
+                             Proposition 2.1 plus the confirming pass */
+    int32_t use_frontier; /* 1: skip steps the restart rule proves unchanged (per SKU, the
+                             runs up to the first run that changed in the last pass);
+                             0: re-evaluate every step each pass.  Same results. */
+    int32_t graph_unroll; /* passes per captured HIP graph replay; 0 = automatic,
+                             1 = no graph (one host check per pass) */
+    const int32_t *init_cache; /* nullable [total], values in [-1, N): alpha^0 in time
+                                  order; NULL = lost sale everywhere (Algorithm 1) */
+    int32_t validate;     /* nonzero: device range checks of the inputs */
+} pk_picard_opts;
+
+/* Statistics of one pk_picard_simulate call (all optional). */
+typedef struct pk_stats {
+    int32_t *passes;         /* HOST nullable [n_traj]: k at which Algorithm 1 returns for
+                                each trajectory (its cache stopped changing) */
+    int32_t passes_max;      /* passes over the whole batch */
+    int32_t block_len;       /* block length used */
+    int64_t changed_total;   /* sum over passes of steps whose cached action changed */
+    int64_t runs_walked;     /* process runs evaluated (a run: one process's orders of one
+                                SKU) */
+    int64_t orders_walked;   /* policy evaluations performed over all passes */
+    int64_t near_ties;       /* MLP: evaluations whose top-two perturbed scores were within
+                                1e-5 relative (final pass) */
+    double walk_ms;          /* summed duration of the policy-evaluation kernel (measured
+                                with HIP events on `stream` when timing is requested) */
+    int64_t walk_launches;   /* launches of that kernel that did work */
+    int64_t walk_bytes;      /* algorithmic HBM bytes of those launches */
+    int32_t timing;          /* in: nonzero to record walk_ms / walk_bytes */
+} pk_stats;
+
+/* Bytes of scratch that pk_picard_simulate, pk_serial_simulate and pk_policy_grad need
+ * for this problem, policy and options (opts nullable = defaults).  Writes *bytes. */
+pk_status pk_workspace_size(const pk_problem *problem, const pk_policy *policy,
+                            const pk_picard_opts *opts, size_t *bytes);
+
+/* Serial rollout on the GPU (the sequential baseline): one workgroup per trajectory walks
+ * t = 1..T in time order, evaluating pi at s_t and applying f.  Same policy code as
+ * pk_picard_simulate.
+ * actions  [total] out: a_t in [-1, N)
+ * shipped  [total] out, nullable: units shipped, min(q_t, x[k_t][a_t]) (0 for a lost sale)
+ * final_inv [n_traj][K][N] out, nullable: inventory after the last order. */
+pk_status pk_serial_simulate(const pk_problem *problem, const pk_policy *policy, void *ws,
+                             size_t ws_bytes, int32_t *actions, int32_t *shipped,
+                             int32_t *final_inv, int32_t validate, void *stream);
+
+/* Picard iteration (Algorithm 1) to convergence.  Outputs as pk_serial_simulate; on
+ * PK_OK they equal the serial rollout.  On PK_ERR_NOT_CONVERGED, actions hold the cache
+ * after max_passes passes (shipped and final_inv are then unspecified) and stats, if
+ * given, are filled.  stats: HOST, nullable. */
+pk_status pk_picard_simulate(const pk_problem *problem, const pk_policy *policy,
+                             const pk_picard_opts *opts, void *ws, size_t ws_bytes,
+                             int32_t *actions, int32_t *shipped, int32_t *final_inv,
+                             pk_stats *stats, void *stream);
+
+/* REINFORCE at fixed actions (MLP policy only).  With the states s_t the actions induce
+ * (serially, per trajectory) and pi(.|s) = softmax over warehouses with stock of s_w,
+ *   logp[t] = log pi(a_t | s_t)  (0 when at most one warehouse has stock; then a_t must
+ *             be the lost sale iff none has),
+ *   grad    = d/dparams sum_t advantages[t] * logp[t], same layout as params.
+ * Activations are recomputed from the parameters, not stored.
+ * actions [total] in (must be feasible at their states, else PK_ERR_INVALID_ARG when
+ *         validate is set); advantages [total] in;
+ * logp [total] out, nullable; grad [n_params] out, nullable (float32; the sum is
+ * accumulated in float64); objective (HOST, nullable) out: sum_t A_t logp[t]. */
+pk_status pk_policy_grad(const pk_problem *problem, const pk_policy *policy,
+                         const int32_t *actions, const float *advantages, float *logp,
+                         float *grad, double *objective, void *ws, size_t ws_bytes,
+                         int32_t validate, void *stream);
+
+/* Choose block_len for pk_picard_simulate by timing candidate lengths on this instance
+ * (outputs are discarded).  Results are cached per (policy, N, R, K, horizon bucket) in
+ * this process, and in the JSON file named by $PICARD_AUTOTUNE_CACHE if set.
+ * best_block_len: HOST out. */
+pk_status pk_autotune(const pk_problem *problem, const pk_policy *policy, void *ws,
+                      size_t ws_bytes, int32_t *best_block_len, void *stream);
+
+/* Message for the last non-OK status on this thread ("" if none). */
+const char *pk_last_error(void);
+
+/* Library version string. */
+const char *pk_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PICARD_H */

@@ -1,0 +1,149 @@
+// Kernels shared by every pass of the Picard iteration (Algorithm 1), whatever the
+// policy: the entry-state scan, the end-of-pass bookkeeping (termination test and the
+// restart frontier of Appendix A.3), the consumption of a warm-start cache, and the
+// final unpermute.
+//
+// Entry state.  Under Algorithm 1 a process starts from s_1 and applies the cached
+// actions of the steps it does not own (lost sale if the cached warehouse is empty).
+// Restricted to one SKU, every such step lowers one warehouse's stock by q, clamped at
+// zero, and clamped decrements compose: max(0, max(0, x-a) - b) = max(0, x-a-b).  So a
+// run j of a segment starts from max(0, x0 - E_j) with E_j = sum of u_j' over the
+// earlier runs j' of the segment, u_j'[w] = sum of q over the run's orders whose cached
+// action is w.  E is an exclusive segmented scan of u.
+#include "pk_internal.h"
+
+namespace pk {
+
+namespace {
+
+// One workgroup per split segment (grid-stride).  Threads cover warehouses; runs are
+// scanned in order.  Runs up to the frontier are final and need no entry state.
+__global__ __launch_bounds__(256) void k_scan_entry(Prob P, Plan L, int skip_first_pass)
+{
+    Ctl *ctl = L.ctl;
+    if (ctl->done) return;
+    const int pass = ctl->pass;
+    const int32_t *fprev = L.fr[(pass - 1) & 1];
+    int32_t *fcur = L.fr[pass & 1];
+    const int n = ctl->n_split_seg;
+    const int N = P.N;
+    for (int i = blockIdx.x; i < n; i += gridDim.x) {
+        const int g = L.split_segs[i];
+        const int32_t f = fprev[g];
+        if (threadIdx.x == 0) fcur[g] = FR_NONE;
+        if (f == FR_NONE || (pass == 1 && skip_first_pass)) continue;
+        const int s0 = L.seg_sr0[g];
+        const int nsr = L.seg_sr0[g + 1] - s0;
+        const int jmin = f + 1 > 1 ? f + 1 : 1; // runs j > f need E_j; E_0 = 0
+        const int64_t row0 = L.sr_uidx[s0];
+        for (int w = threadIdx.x; w < N; w += blockDim.x) {
+            int32_t acc = 0;
+            int j = 0;
+            // the prefix over frozen runs (j < jmin): loads unrolled to keep several in flight
+            for (; j + 8 <= jmin; j += 8) {
+                int32_t v[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) v[k] = L.u[(row0 + j + k) * N + w];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) acc += v[k];
+            }
+            for (; j < jmin; ++j) acc += L.u[(row0 + j) * N + w];
+            for (; j < nsr; ++j) {
+                L.E[(row0 + j) * N + w] = acc;
+                acc += L.u[(row0 + j) * N + w];
+            }
+        }
+    }
+}
+
+__global__ void k_pass_end(Ctl *ctl)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (ctl->done) return;
+    ctl->changed_total += ctl->changed_this_pass;
+    ctl->changed_this_pass = 0;
+    ctl->work = 0;
+    if (!ctl->any_changed) {
+        ctl->done = 1;
+        ctl->passes_done = ctl->pass;
+    } else if (ctl->pass >= ctl->max_passes) {
+        ctl->done = 2;
+        ctl->passes_done = ctl->pass;
+    } else {
+        ctl->pass += 1;
+    }
+    ctl->any_changed = 0;
+}
+
+// u for every run of a split segment from the current cache (warm start).  One wave per
+// run; the run's histogram is built in LDS.
+__global__ __launch_bounds__(256) void k_consume(Prob P, Plan L)
+{
+    extern __shared__ int32_t lds[];
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    const int N = P.N;
+    int32_t *h = lds + wave * N;
+    const int n = L.ctl->n_split;
+    for (int item = blockIdx.x * 4 + wave; item < n; item += gridDim.x * 4) {
+        const int s = L.split_list[item];
+        for (int w = lane; w < N; w += WAVE) h[w] = 0;
+        wave_sync();
+        const int lo = L.sr_lo[s], hi = L.sr_lo[s + 1];
+        for (int p = lo + lane; p < hi; p += WAVE) {
+            const int a = L.s_alpha[p];
+            if (a >= 0) atomicAdd(&h[a], L.s_qty[p]);
+        }
+        wave_sync();
+        const int64_t row = L.sr_uidx[s];
+        for (int w = lane; w < N; w += WAVE) L.u[row * N + w] = h[w];
+        wave_sync();
+    }
+}
+
+__global__ void k_unpermute(Prob P, Plan L, int32_t *actions, int32_t *shipped)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P.total; p += stride) {
+        const int32_t o = L.perm[p];
+        actions[o] = L.s_alpha[p];
+        if (shipped) shipped[o] = L.s_ship[p];
+    }
+}
+
+} // namespace
+
+hipError_t launch_scan_entry(const Prob &P, const Plan &L, int n_seg_max, bool skip_first,
+                             hipStream_t st)
+{
+    int grid = n_seg_max < 4096 ? (n_seg_max > 0 ? n_seg_max : 1) : 4096;
+    hipLaunchKernelGGL(k_scan_entry, dim3(grid), dim3(256), 0, st, P, L, skip_first ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_pass_end(const Plan &L, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pass_end, dim3(1), dim3(64), 0, st, L.ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_consume(const Prob &P, const Plan &L, int64_t n_split_max, hipStream_t st)
+{
+    int64_t g = (n_split_max + 3) / 4;
+    if (g < 1) g = 1;
+    if (g > 8192) g = 8192;
+    hipLaunchKernelGGL(k_consume, dim3((unsigned)g), dim3(256), 4 * P.N * sizeof(int32_t), st, P,
+                       L);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpermute(const Prob &P, const Plan &L, int32_t *actions, int32_t *shipped,
+                            hipStream_t st)
+{
+    int64_t g = (P.total + 255) / 256;
+    if (g < 1) g = 1;
+    if (g > 8192) g = 8192;
+    hipLaunchKernelGGL(k_unpermute, dim3((unsigned)g), dim3(256), 0, st, P, L, actions, shipped);
+    return hipGetLastError();
+}
+
+} // namespace pk

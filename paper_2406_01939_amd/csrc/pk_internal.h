@@ -1,0 +1,130 @@
+// Internal declarations of libpicard (HIP, gfx950).  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/picard.h"
+
+namespace pk {
+
+constexpr int WAVE = 64;
+constexpr int LOST = PK_LOST;
+constexpr int32_t FR_ALL = -1;          // frontier: every run of the SKU is active
+constexpr int32_t FR_NONE = 0x7fffffff; // frontier: nothing changed (SKU converged)
+
+// Device view of the problem (pk_problem with the trajectory offsets on the device).
+struct Prob {
+    int32_t N, K, R, n_traj;
+    int64_t total;
+    const int32_t *sku, *region, *qty, *x0, *cost;
+    const int64_t *traj_off; // device [n_traj+1]
+    uint64_t seed;
+};
+
+// Control block in device memory: the pass loop runs without host round trips; every
+// pass kernel reads `pass`/`done` and the end-of-pass kernel advances them.
+struct Ctl {
+    int32_t pass;        // current pass (1-based)
+    int32_t done;        // 1 once a pass changed nothing
+    int32_t any_changed; // this pass
+    int32_t work;        // dynamic work counter of the walk
+    int32_t n_sr, n_seg, n_split, n_split_seg; // setup products
+    int32_t error;       // validate: nonzero if an input value was out of range
+    int32_t passes_done; // pass count at convergence
+    int32_t max_passes;
+    int32_t pad0;
+    unsigned long long changed_total;
+    unsigned long long runs_walked;
+    unsigned long long orders_walked;
+    unsigned long long near_ties;
+    unsigned long long bytes_walked; // algorithmic bytes of walk launches
+    unsigned long long walk_launch_active; // launches in which some run was walked
+    unsigned long long changed_this_pass;
+    unsigned long long orders_this_pass;
+};
+
+// Products of the per-call setup (partition and sort), all in the caller's workspace.
+struct Plan {
+    int32_t B;               // block length
+    int32_t n_keys;          // n_traj * K
+    int32_t *perm;           // [total] sorted position -> original order index
+    int32_t *s_key;          // [total] sorted (trajectory, SKU) key
+    int32_t *s_region;       // [total]
+    int32_t *s_qty;          // [total]
+    int32_t *s_alpha;        // [total] cached action (sorted order)
+    int32_t *s_ship;         // [total] units shipped (sorted order)
+    int32_t *s_t;            // [total] time index within the trajectory (learned only)
+    int32_t *sr_lo;          // [n_sr_max+1] first sorted position of each run
+    int32_t *sr_seg;         // [n_sr_max] segment (SKU list) of each run
+    int32_t *sr_uidx;        // [n_sr_max] row of u/E for runs of split segments, else -1
+    int32_t *seg_key;        // [n_seg_max]
+    int32_t *seg_sr0;        // [n_seg_max+1] first run of each segment
+    int32_t *split_list;     // [n_split_max] runs of split segments, in order
+    int32_t *split_segs;     // [n_seg_max] split segments
+    int32_t *fr[2];          // [n_seg_max] frontier per segment, by pass parity
+    int32_t *u;              // [n_split_max][N] cached consumption of each split run
+    int32_t *E;              // [n_split_max][N] consumption entering each split run
+    int16_t *rank;           // [n_traj][R][N] warehouses by (cost, index) per region
+    int32_t *traj_lcp;       // [n_traj] last pass in which the trajectory changed
+    Ctl *ctl;
+};
+
+// ---------------------------------------------------------------- wave helpers
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t lanemask_lt()
+{
+    int l = __lane_id();
+    return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+// Compiler barrier + LDS ordering point for one wavefront (no hardware cost).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave.
+__device__ __forceinline__ int wave_incl_sum(int v)
+{
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        int o = __shfl_up(v, d, WAVE);
+        if (__lane_id() >= d) v += o;
+    }
+    return v;
+}
+
+__device__ __forceinline__ int wave_sum(int v)
+{
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, WAVE);
+    return v;
+}
+
+__device__ __forceinline__ int traj_of(const int64_t *off, int n_traj, int64_t o)
+{
+    int lo = 0, hi = n_traj; // off[lo] <= o < off[hi]
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (off[mid] <= o) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------- host launchers
+// All return hipSuccess or the first HIP error.  `st` is the stream.
+hipError_t scan_i64(int64_t *data, int64_t n, bool inclusive, void *tmp, hipStream_t st);
+size_t scan_tmp_bytes(int64_t n);
+hipError_t scan_i32_excl(int32_t *data, int64_t n, void *tmp, hipStream_t st);
+
+hipError_t radix_sort_pairs(int32_t *keys, int32_t *vals, int32_t *keys_alt,
+                            int32_t *vals_alt, int64_t n, int key_bits, void *tmp,
+                            hipStream_t st, bool *result_in_alt);
+size_t radix_tmp_bytes(int64_t n);
+
+} // namespace pk

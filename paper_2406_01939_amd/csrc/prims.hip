@@ -1,0 +1,246 @@
+// Device primitives: prefix scan (reduce-then-scan) and a stable LSD radix sort of
+// (key, value) pairs.  Both serve the per-call setup that orders the batch's orders by
+// (trajectory, SKU) to form the SKU segments and process blocks.
+#include "pk_internal.h"
+
+namespace pk {
+
+namespace {
+
+constexpr int SCAN_THREADS = 256;
+constexpr int SCAN_ITEMS = 16;
+constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
+constexpr int SCAN_MID_THREADS = 1024;
+
+template <typename T>
+__device__ T block_excl_scan(T v, T *lds_wave, T *total)
+{
+    // inclusive within the wave
+    T x = v;
+    for (int d = 1; d < WAVE; d <<= 1) {
+        T o = __shfl_up(x, d, WAVE);
+        if (__lane_id() >= d) x += o;
+    }
+    const int wave = threadIdx.x / WAVE, nwaves = blockDim.x / WAVE;
+    if (__lane_id() == WAVE - 1) lds_wave[wave] = x;
+    __syncthreads();
+    T base = 0, tot = 0;
+    for (int w = 0; w < nwaves; ++w) {
+        T s = lds_wave[w];
+        if (w < wave) base += s;
+        tot += s;
+    }
+    __syncthreads();
+    if (total) *total = tot;
+    return base + x - v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(SCAN_THREADS) void k_tile_reduce(const T *in, int64_t n, T *partial)
+{
+    __shared__ T lds[SCAN_THREADS / WAVE];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    T acc = 0;
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        int64_t j = base + (int64_t)i * SCAN_THREADS + threadIdx.x;
+        if (j < n) acc += in[j];
+    }
+    for (int d = 32; d > 0; d >>= 1) acc += __shfl_xor(acc, d, WAVE);
+    if (__lane_id() == 0) lds[threadIdx.x / WAVE] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T s = 0;
+        for (int w = 0; w < SCAN_THREADS / WAVE; ++w) s += lds[w];
+        partial[blockIdx.x] = s;
+    }
+}
+
+// Exclusive scan of the tile partials with one block.
+template <typename T>
+__global__ __launch_bounds__(SCAN_MID_THREADS) void k_partial_scan(T *partial, int64_t nb)
+{
+    __shared__ T lds[SCAN_MID_THREADS / WAVE];
+    const int64_t per = (nb + SCAN_MID_THREADS - 1) / SCAN_MID_THREADS;
+    const int64_t lo = (int64_t)threadIdx.x * per;
+    const int64_t hi = lo + per < nb ? lo + per : nb;
+    T s = 0;
+    for (int64_t i = lo; i < hi; ++i) s += partial[i];
+    T total;
+    T run = block_excl_scan<T>(s, lds, &total);
+    for (int64_t i = lo; i < hi; ++i) {
+        T v = partial[i];
+        partial[i] = run;
+        run += v;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(SCAN_THREADS) void k_tile_scan(T *data, int64_t n, const T *partial,
+                                                            int inclusive)
+{
+    __shared__ T lds[SCAN_THREADS / WAVE];
+    __shared__ T stage[SCAN_TILE];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+    // coalesced load into LDS, then each thread scans a contiguous run of SCAN_ITEMS
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        int64_t j = base + (int64_t)i * SCAN_THREADS + threadIdx.x;
+        stage[i * SCAN_THREADS + threadIdx.x] = j < n ? data[j] : T(0);
+    }
+    __syncthreads();
+    T loc[SCAN_ITEMS];
+    T s = 0;
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        loc[i] = stage[threadIdx.x * SCAN_ITEMS + i];
+        s += loc[i];
+    }
+    T run = block_excl_scan<T>(s, lds, nullptr) + partial[blockIdx.x];
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        T v = loc[i];
+        stage[threadIdx.x * SCAN_ITEMS + i] = inclusive ? run + v : run;
+        run += v;
+    }
+    __syncthreads();
+    for (int i = 0; i < SCAN_ITEMS; ++i) {
+        int64_t j = base + (int64_t)i * SCAN_THREADS + threadIdx.x;
+        if (j < n) data[j] = stage[i * SCAN_THREADS + threadIdx.x];
+    }
+}
+
+template <typename T>
+hipError_t scan_impl(T *data, int64_t n, bool inclusive, void *tmp, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    T *partial = (T *)tmp;
+    hipLaunchKernelGGL(k_tile_reduce<T>, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, st, data,
+                       n, partial);
+    hipLaunchKernelGGL(k_partial_scan<T>, dim3(1), dim3(SCAN_MID_THREADS), 0, st, partial, nb);
+    hipLaunchKernelGGL(k_tile_scan<T>, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, st, data, n,
+                       partial, inclusive ? 1 : 0);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ radix sort
+constexpr int RX_THREADS = 256;
+constexpr int RX_CHUNKS = 8;
+constexpr int RX_TILE = RX_THREADS * RX_CHUNKS;
+
+__global__ __launch_bounds__(RX_THREADS) void k_radix_count(const int32_t *keys, int64_t n,
+                                                            int shift, int32_t *counts,
+                                                            int64_t n_tiles)
+{
+    __shared__ int32_t hist[256];
+    hist[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * RX_TILE;
+    for (int c = 0; c < RX_CHUNKS; ++c) {
+        int64_t i = base + c * RX_THREADS + threadIdx.x;
+        if (i < n) atomicAdd(&hist[(keys[i] >> shift) & 255], 1);
+    }
+    __syncthreads();
+    counts[(int64_t)threadIdx.x * n_tiles + blockIdx.x] = hist[threadIdx.x];
+}
+
+// Stable scatter: elements of a tile are ranked in index order, 256 at a time; within a
+// wave equal digits are matched with 8 ballots, across the 4 waves through LDS.
+__global__ __launch_bounds__(RX_THREADS) void k_radix_scatter(
+    const int32_t *keys, const int32_t *vals, int64_t n, int shift, const int32_t *offs,
+    int64_t n_tiles, int32_t *keys_out, int32_t *vals_out)
+{
+    __shared__ int32_t s_wcnt[RX_THREADS / WAVE][256];
+    __shared__ int32_t s_woff[RX_THREADS / WAVE][256];
+    __shared__ int32_t s_run[256];
+    __shared__ int32_t s_goff[256];
+    const int tid = threadIdx.x, wave = tid / WAVE;
+    s_run[tid] = 0;
+    s_goff[tid] = offs[(int64_t)tid * n_tiles + blockIdx.x];
+    for (int w = 0; w < RX_THREADS / WAVE; ++w) s_wcnt[w][tid] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * RX_TILE;
+    for (int c = 0; c < RX_CHUNKS; ++c) {
+        const int64_t i = base + c * RX_THREADS + tid;
+        const bool valid = i < n;
+        const int32_t k = valid ? keys[i] : 0;
+        const int32_t v = valid ? vals[i] : 0;
+        const int d = (k >> shift) & 255;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1;
+            const uint64_t m = __ballot(bit);
+            peers &= bit ? m : ~m;
+        }
+        const int rank = __popcll(peers & lanemask_lt());
+        if (valid && rank == 0) s_wcnt[wave][d] = __popcll(peers);
+        __syncthreads();
+        {
+            int run = s_run[tid];
+            for (int w = 0; w < RX_THREADS / WAVE; ++w) {
+                const int cnt = s_wcnt[w][tid];
+                s_woff[w][tid] = run;
+                run += cnt;
+                s_wcnt[w][tid] = 0;
+            }
+            s_run[tid] = run;
+        }
+        __syncthreads();
+        if (valid) {
+            const int64_t pos = (int64_t)s_goff[d] + s_woff[wave][d] + rank;
+            keys_out[pos] = k;
+            vals_out[pos] = v;
+        }
+    }
+}
+
+} // namespace
+
+hipError_t scan_i64(int64_t *data, int64_t n, bool inclusive, void *tmp, hipStream_t st)
+{
+    return scan_impl<int64_t>(data, n, inclusive, tmp, st);
+}
+
+hipError_t scan_i32_excl(int32_t *data, int64_t n, void *tmp, hipStream_t st)
+{
+    return scan_impl<int32_t>(data, n, false, tmp, st);
+}
+
+size_t scan_tmp_bytes(int64_t n)
+{
+    return (size_t)((n + SCAN_TILE - 1) / SCAN_TILE + 1) * sizeof(int64_t) + 256;
+}
+
+size_t radix_tmp_bytes(int64_t n)
+{
+    const int64_t n_tiles = (n + RX_TILE - 1) / RX_TILE;
+    const int64_t nc = 256 * n_tiles;
+    return (size_t)nc * sizeof(int32_t) + 256 + scan_tmp_bytes(nc);
+}
+
+hipError_t radix_sort_pairs(int32_t *keys, int32_t *vals, int32_t *keys_alt, int32_t *vals_alt,
+                            int64_t n, int key_bits, void *tmp, hipStream_t st,
+                            bool *result_in_alt)
+{
+    *result_in_alt = false;
+    if (n <= 1) return hipSuccess;
+    const int64_t n_tiles = (n + RX_TILE - 1) / RX_TILE;
+    int32_t *counts = (int32_t *)tmp;
+    void *scan_tmp = (char *)tmp + (((size_t)256 * n_tiles * sizeof(int32_t) + 255) & ~(size_t)255);
+    int32_t *ki = keys, *vi = vals, *ko = keys_alt, *vo = vals_alt;
+    const int passes = key_bits <= 0 ? 1 : (key_bits + 7) / 8;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = 8 * p;
+        hipLaunchKernelGGL(k_radix_count, dim3((unsigned)n_tiles), dim3(RX_THREADS), 0, st, ki,
+                           n, shift, counts, n_tiles);
+        hipError_t e = scan_i32_excl(counts, 256 * n_tiles, scan_tmp, st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)n_tiles), dim3(RX_THREADS), 0, st, ki,
+                           vi, n, shift, counts, n_tiles, ko, vo);
+        int32_t *t;
+        t = ki; ki = ko; ko = t;
+        t = vi; vi = vo; vo = t;
+        *result_in_alt = !*result_in_alt;
+    }
+    return hipGetLastError();
+}
+
+} // namespace pk

@@ -1,0 +1,265 @@
+// Per-call setup of the Picard iteration: the partition of the steps into processes.
+//
+// Orders of all trajectories are sorted (stably) by key = trajectory * K + SKU, so every
+// SKU's orders form a contiguous segment in time order.  Blocks of B consecutive sorted
+// positions are the processes (Section 2: each process m owns a disjoint set of steps
+// T_m).  A run is a block's part of one segment; because SKUs never interact without
+// node capacity (Assumption 1, inventory independence), a process's runs are independent
+// and a run is the unit of work on the GPU.
+#include "pk_internal.h"
+
+namespace pk {
+
+namespace {
+
+__global__ void k_make_keys(Prob P, int32_t *keys, int32_t *vals, int validate, Ctl *ctl)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < P.total; o += stride) {
+        const int b = traj_of(P.traj_off, P.n_traj, o);
+        int32_t s = P.sku[o];
+        if (validate) {
+            const int32_t r = P.region[o], q = P.qty[o];
+            if (s < 0 || s >= P.K || r < 0 || r >= P.R || q < 1) atomicOr(&ctl->error, 1);
+        }
+        s = s < 0 ? 0 : (s >= P.K ? P.K - 1 : s); // out-of-range input never indexes memory
+        keys[o] = b * P.K + s;
+        vals[o] = (int32_t)o;
+    }
+}
+
+__global__ void k_check_inv(const int32_t *x0, int64_t n, Ctl *ctl)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        if (x0[i] < 0) atomicOr(&ctl->error, 2);
+}
+
+// Gather the sorted order data and the run/segment start flags.  flags[p] packs the
+// run-start count in the low 32 bits and the segment-start count in the high 32 bits.
+__global__ void k_gather(Prob P, Plan L, const int32_t *init_cache, int validate,
+                         int64_t *flags, int want_t)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P.total; p += stride) {
+        const int32_t o = L.perm[p];
+        const int32_t key = L.s_key[p];
+        const int32_t r = P.region[o], q = P.qty[o];
+        L.s_region[p] = r < 0 ? 0 : (r >= P.R ? P.R - 1 : r);
+        L.s_qty[p] = q < 1 ? 1 : q;
+        int32_t a = LOST;
+        if (init_cache) {
+            a = init_cache[o];
+            if (a < LOST || a >= P.N) {
+                if (validate) atomicOr(&L.ctl->error, 4);
+                a = LOST;
+            }
+        }
+        L.s_alpha[p] = a;
+        if (want_t) {
+            const int b = key / P.K;
+            L.s_t[p] = (int32_t)(o - P.traj_off[b]);
+        }
+        const bool seg_start = p == 0 || L.s_key[p - 1] != key;
+        const bool run_start = seg_start || (p % L.B) == 0;
+        flags[p] = (run_start ? 1ll : 0ll) | (seg_start ? (1ll << 32) : 0ll);
+    }
+}
+
+// Run and segment tables from the inclusive scan of the flags.
+__global__ void k_tables(Prob P, Plan L, const int64_t *flags)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P.total; p += stride) {
+        const int64_t f = flags[p];
+        const int32_t sr = (int32_t)(f & 0xffffffffll) - 1;
+        const int32_t sg = (int32_t)(f >> 32) - 1;
+        const bool seg_start = p == 0 || L.s_key[p - 1] != L.s_key[p];
+        const bool run_start = seg_start || (p % L.B) == 0;
+        if (run_start) {
+            L.sr_lo[sr] = (int32_t)p;
+            L.sr_seg[sr] = sg;
+        }
+        if (seg_start) {
+            L.seg_key[sg] = L.s_key[p];
+            L.seg_sr0[sg] = sr;
+        }
+        if (p == P.total - 1) {
+            L.sr_lo[sr + 1] = (int32_t)P.total;
+            L.seg_sr0[sg + 1] = sr + 1;
+            L.ctl->n_sr = sr + 1;
+            L.ctl->n_seg = sg + 1;
+        }
+    }
+}
+
+// Per segment: number of runs if split (more than one run), else 0.  Also initialises
+// the frontiers (pass 1 evaluates everything).
+__global__ void k_split_count(Plan L, int32_t *cnt, int32_t *segcnt, int32_t n_seg_max)
+{
+    const int n_seg = L.ctl->n_seg;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_seg_max; g += stride) {
+        int32_t c = 0, s = 0;
+        if (g < n_seg) {
+            const int32_t nsr = L.seg_sr0[g + 1] - L.seg_sr0[g];
+            c = nsr > 1 ? nsr : 0;
+            s = nsr > 1 ? 1 : 0;
+            L.fr[0][g] = FR_ALL;
+            L.fr[1][g] = FR_NONE;
+        }
+        cnt[g] = c;
+        segcnt[g] = s;
+    }
+}
+
+__global__ void k_split_fill(Plan L, const int32_t *ubase, const int32_t *segbase,
+                             int32_t n_seg_max)
+{
+    const int n_seg = L.ctl->n_seg;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_seg; g += stride) {
+        const int32_t s0 = L.seg_sr0[g], s1 = L.seg_sr0[g + 1];
+        if (s1 - s0 > 1) {
+            const int32_t b = ubase[g];
+            for (int32_t s = s0; s < s1; ++s) {
+                L.sr_uidx[s] = b + (s - s0);
+                L.split_list[b + (s - s0)] = s;
+            }
+            L.split_segs[segbase[g]] = (int32_t)g;
+        } else {
+            L.sr_uidx[s0] = -1;
+        }
+        if (g == n_seg - 1) {
+            const int32_t last = s1 - s0 > 1 ? s1 - s0 : 0;
+            L.ctl->n_split = ubase[g] + last;
+            L.ctl->n_split_seg = segbase[g] + (s1 - s0 > 1 ? 1 : 0);
+        }
+    }
+}
+
+// rank[b][r][j] = the j-th warehouse in increasing (cost[b][w][r], w) order: one thread
+// per (b, r, w) counts the warehouses that precede w.
+__global__ void k_rank(Prob P, int16_t *rank)
+{
+    const int64_t n = (int64_t)P.n_traj * P.R * P.N;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const int w = (int)(i % P.N);
+        const int64_t br = i / P.N;
+        const int r = (int)(br % P.R);
+        const int b = (int)(br / P.R);
+        const int32_t *c = P.cost + (int64_t)b * P.N * P.R;
+        const int32_t cw = c[(int64_t)w * P.R + r];
+        int pos = 0;
+        for (int v = 0; v < P.N; ++v) {
+            const int32_t cv = c[(int64_t)v * P.R + r];
+            pos += (cv < cw) || (cv == cw && v < w);
+        }
+        rank[br * P.N + pos] = (int16_t)w;
+    }
+}
+
+__global__ void k_init_ctl(Ctl *ctl, int32_t *traj_lcp, int n_traj, int max_passes)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        Ctl c = {};
+        c.pass = 1;
+        c.max_passes = max_passes;
+        *ctl = c;
+    }
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < n_traj; b += gridDim.x * blockDim.x)
+        traj_lcp[b] = 0;
+}
+
+inline unsigned grid_for(int64_t n, int threads, int cap = 65535)
+{
+    int64_t g = (n + threads - 1) / threads;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+} // namespace
+
+// Reset the control block (must precede every other setup step).
+hipError_t setup_ctl(Plan &L, int n_traj, int max_passes, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_init_ctl, dim3(grid_for(n_traj, 256)), dim3(256), 0, st, L.ctl,
+                       L.traj_lcp, n_traj, max_passes);
+    return hipGetLastError();
+}
+
+// Sort, gather, and build the run / segment tables.  `scratch` must hold
+// 2*total int32 (ping-pong keys/values), total int64 (flags) and the primitives' tmp.
+hipError_t setup_plan(const Prob &P, Plan &L, const int32_t *init_cache, int validate,
+                      bool want_t, int32_t n_seg_max, void *scratch, hipStream_t st)
+{
+    hipError_t e;
+    const int64_t n = P.total;
+    if (n == 0) return hipSuccess;
+    char *s = (char *)scratch;
+    auto take = [&](size_t bytes) {
+        void *r = s;
+        s += (bytes + 255) & ~(size_t)255;
+        return r;
+    };
+    int32_t *keys_a = L.s_key;
+    int32_t *vals_a = L.perm;
+    int32_t *keys_b = (int32_t *)take(n * sizeof(int32_t));
+    int32_t *vals_b = (int32_t *)take(n * sizeof(int32_t));
+    int64_t *flags = (int64_t *)take(n * sizeof(int64_t));
+    void *tmp = take(radix_tmp_bytes(n) > scan_tmp_bytes(n) ? radix_tmp_bytes(n)
+                                                             : scan_tmp_bytes(n));
+
+    hipLaunchKernelGGL(k_make_keys, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, P, keys_a,
+                       vals_a, validate, L.ctl);
+    if (validate) {
+        const int64_t nx = (int64_t)P.n_traj * P.K * P.N;
+        hipLaunchKernelGGL(k_check_inv, dim3(grid_for(nx, 256, 8192)), dim3(256), 0, st, P.x0,
+                           nx, L.ctl);
+    }
+    int key_bits = 1;
+    while (key_bits < 31 && (1ll << key_bits) < (int64_t)L.n_keys) ++key_bits;
+    bool in_alt = false;
+    e = radix_sort_pairs(keys_a, vals_a, keys_b, vals_b, n, key_bits, tmp, st, &in_alt);
+    if (e != hipSuccess) return e;
+    if (in_alt) {
+        e = hipMemcpyAsync(keys_a, keys_b, n * sizeof(int32_t), hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return e;
+        e = hipMemcpyAsync(vals_a, vals_b, n * sizeof(int32_t), hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_gather, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, P, L,
+                       init_cache, validate, flags, want_t ? 1 : 0);
+    e = scan_i64(flags, n, true, tmp, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_tables, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, P, L, flags);
+    // split bookkeeping: counts per segment -> exclusive scans (reuse keys_b / vals_b)
+    int32_t *cnt = keys_b, *segcnt = vals_b;
+    hipLaunchKernelGGL(k_split_count, dim3(grid_for(n_seg_max, 256, 8192)), dim3(256), 0, st, L,
+                       cnt, segcnt, n_seg_max);
+    e = scan_i32_excl(cnt, n_seg_max, tmp, st);
+    if (e != hipSuccess) return e;
+    e = scan_i32_excl(segcnt, n_seg_max, tmp, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_split_fill, dim3(grid_for(n_seg_max, 256, 8192)), dim3(256), 0, st, L,
+                       cnt, segcnt, n_seg_max);
+    return hipGetLastError();
+}
+
+size_t setup_scratch_bytes(int64_t n)
+{
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    size_t t = radix_tmp_bytes(n) > scan_tmp_bytes(n) ? radix_tmp_bytes(n) : scan_tmp_bytes(n);
+    return al(n * 4) * 2 + al(n * 8) + al(t) + 1024;
+}
+
+hipError_t setup_rank(const Prob &P, int16_t *rank, hipStream_t st)
+{
+    const int64_t n = (int64_t)P.n_traj * P.R * P.N;
+    hipLaunchKernelGGL(k_rank, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, P, rank);
+    return hipGetLastError();
+}
+
+} // namespace pk

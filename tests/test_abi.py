@@ -1,0 +1,63 @@
+"""The C-ABI library loads and exports every entry point include/picard.h declares; the
+Python binding's structs match the header's sizes.  No compute calls (CPU only)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "picard.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pk_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_entry_points():
+    names = _declared()
+    for want in ("pk_picard_simulate", "pk_serial_simulate", "pk_policy_grad",
+                 "pk_workspace_size", "pk_autotune", "pk_last_error", "pk_version"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2406_01939_amd import api
+    L = api.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+    assert L.pk_version().decode().startswith("libpicard")
+    assert L.pk_last_error() is not None
+
+
+def test_struct_layouts():
+    from paper_2406_01939_amd import api
+    assert C.sizeof(api.pk_problem) == 4 * 4 + 6 * 8 + 8
+    assert C.sizeof(api.pk_policy) == 4 * 4 + 8
+    assert C.sizeof(api.pk_picard_opts) == 4 * 4 + 8 + 8
+    assert C.sizeof(api.pk_stats) == 8 + 4 + 4 + 4 * 8 + 8 + 8 + 8 + 8
+
+
+def test_host_validation_without_gpu():
+    """Shape errors are caught on the host before any device work."""
+    import numpy as np
+    from paper_2406_01939_amd import api
+    offs = np.array([0, 5], dtype=np.int64)
+    p = api.pk_problem(0, 1, 1, 1, offs.ctypes.data, 1, 1, 1, 1, 1, 0)
+    po = api.pk_policy(0, 0, 0, 0, None)
+    n = C.c_size_t(0)
+    st = api.lib().pk_workspace_size(C.byref(p), C.byref(po), None, C.byref(n))
+    assert st == api.PK_ERR_SHAPE
+    assert b"dimensions" in api.lib().pk_last_error()
+    p = api.pk_problem(2000, 1, 1, 1, offs.ctypes.data, 1, 1, 1, 1, 1, 0)
+    assert api.lib().pk_workspace_size(C.byref(p), C.byref(po), None, C.byref(n)) == api.PK_ERR_SHAPE
+    bad = np.array([0, 5, 3], dtype=np.int64)
+    p = api.pk_problem(2, 1, 1, 2, bad.ctypes.data, 1, 1, 1, 1, 1, 0)
+    assert api.lib().pk_workspace_size(C.byref(p), C.byref(po), None, C.byref(n)) == api.PK_ERR_SHAPE
+    p = api.pk_problem(2, 1, 1, 1, offs.ctypes.data, 1, 1, 1, 1, 1, 0)
+    assert api.lib().pk_workspace_size(C.byref(p), C.byref(po), None, C.byref(n)) == api.PK_OK
+    assert n.value > 0
+    po = api.pk_policy(7, 0, 0, 0, None)
+    assert api.lib().pk_workspace_size(C.byref(p), C.byref(po), None, C.byref(n)) == api.PK_ERR_INVALID_ARG

@@ -1,0 +1,222 @@
+"""GPU parity of the greedy path against the CPU oracle (bit-exact: integer work).
+
+Compared element by element: actions, units shipped and final inventory against the
+serial oracle; passes per trajectory and the cache after every pass against the
+oracle's Picard iteration under the same block partition.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2406_01939_amd.instances import make_instance, random_tiny
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2406_01939_amd import api as A
+    A.lib()
+    return A
+
+
+def _oracle_batch(oracle, inst, B=None):
+    """Serial results per trajectory (+ Picard passes under blocks of B if given)."""
+    acts, ships, fins, passes = [], [], [], []
+    workers = oracle.block_workers(inst, B) if B else None
+    for b in range(inst.n_traj):
+        r = oracle.serial(inst, b)
+        acts.append(r["actions"]); ships.append(r["shipped"]); fins.append(r["final_inv"])
+        if B:
+            lo, hi = int(inst.traj_offsets[b]), int(inst.traj_offsets[b + 1])
+            pr = oracle.picard_runs(inst, workers[lo:hi], b)
+            assert pr["converged"]
+            np.testing.assert_array_equal(pr["actions"], r["actions"])
+            passes.append(pr["passes"])
+    return (np.concatenate(acts) if acts else np.zeros(0, np.int32),
+            np.concatenate(ships) if ships else np.zeros(0, np.int32),
+            np.stack(fins), np.array(passes))
+
+
+def _check(out, inst, want_a, want_s, want_f):
+    np.testing.assert_array_equal(out["actions"].cpu().numpy(), want_a)
+    if out.get("shipped") is not None:
+        np.testing.assert_array_equal(out["shipped"].cpu().numpy(), want_s)
+    if out.get("final_inv") is not None:
+        np.testing.assert_array_equal(out["final_inv"].cpu().numpy(), want_f)
+
+
+@pytest.mark.parametrize("B", [1, 2, 3, 7, 64, 1000])
+@pytest.mark.parametrize("seed", range(4))
+def test_tiny_batches(api, oracle, seed, B):
+    inst = random_tiny(seed, N=1 + seed * 3, K=4, R=3, T=150, qmax=1 + seed % 3, inv_max=5,
+                       n_traj=3)
+    _say(f"case tiny seed={seed} B={B} total={inst.total_orders}")
+    want_a, want_s, want_f, want_p = _oracle_batch(oracle, inst, B)
+    prob = api.DeviceProblem.from_instance(inst)
+    out = api.pk_picard_simulate(prob, "greedy", block_len=B, validate=True)
+    _check(out, inst, want_a, want_s, want_f)
+    np.testing.assert_array_equal(out["passes"], want_p)
+
+
+def test_every_pass_matches_oracle_cache(api, oracle):
+    inst = make_instance("greedy_n10_k100_t1e4")
+    B = 100
+    w = oracle.block_workers(inst, B)
+    ref = oracle.picard_runs(inst, w, record=True)
+    prob = api.DeviceProblem.from_instance(inst)
+    _say(f"case small workload passes={ref['passes']}")
+    for k in range(1, ref["passes"] + 1):
+        out = api.pk_picard_simulate(prob, "greedy", block_len=B, max_passes=k,
+                                     raise_not_converged=False)
+        np.testing.assert_array_equal(out["actions"].cpu().numpy(), ref["caches"][k - 1])
+        if k < ref["passes"]:
+            assert out["status"] == api.PK_ERR_NOT_CONVERGED
+        else:
+            assert out["status"] == api.PK_OK
+    assert int(out["passes"][0]) == ref["passes"]
+
+
+@pytest.mark.parametrize("B", [100, 1, 17, 10_000])
+def test_small_workload(api, oracle, B):
+    inst = make_instance("greedy_n10_k100_t1e4")
+    _say(f"case small workload B={B}")
+    want_a, want_s, want_f, want_p = _oracle_batch(oracle, inst, B)
+    prob = api.DeviceProblem.from_instance(inst)
+    out = api.pk_picard_simulate(prob, "greedy", block_len=B)
+    _check(out, inst, want_a, want_s, want_f)
+    np.testing.assert_array_equal(out["passes"], want_p)
+    if B >= 10_000:
+        assert out["passes"][0] <= 2  # product partition
+
+
+def test_serial_sweep_matches_oracle(api, oracle):
+    inst = random_tiny(11, N=70, K=5, R=4, T=400, qmax=3, inv_max=6, n_traj=5)
+    _say("case serial sweep tiny batch")
+    want_a, want_s, want_f, _ = _oracle_batch(oracle, inst)
+    prob = api.DeviceProblem.from_instance(inst)
+    out = api.pk_serial_simulate(prob, "greedy")
+    _check(out, inst, want_a, want_s, want_f)
+    inst = make_instance("greedy_n10_k100_t1e4")
+    want_a, want_s, want_f, _ = _oracle_batch(oracle, inst)
+    out = api.pk_serial_simulate(api.DeviceProblem.from_instance(inst), "greedy")
+    _check(out, inst, want_a, want_s, want_f)
+
+
+def test_edge_cases(api, oracle):
+    # a batch with empty trajectories in it
+    inst = random_tiny(21, N=3, K=2, R=2, T=20, n_traj=3)
+    inst.traj_offsets = np.array([0, 0, 10, 10], dtype=np.int64)
+    inst.sku, inst.region, inst.qty = inst.sku[:10], inst.region[:10], inst.qty[:10]
+    _say("case empty trajectories")
+    want_a, want_s, want_f, want_p = _oracle_batch(oracle, inst, 4)
+    prob = api.DeviceProblem.from_instance(inst)
+    out = api.pk_picard_simulate(prob, "greedy", block_len=4)
+    _check(out, inst, want_a, want_s, want_f)
+    assert list(out["passes"]) == [1, want_p[1], 1]
+    # no orders at all
+    inst0 = random_tiny(22, N=3, K=2, R=2, T=5)
+    inst0.traj_offsets = np.array([0, 0], dtype=np.int64)
+    inst0.sku = inst0.sku[:0]; inst0.region = inst0.region[:0]; inst0.qty = inst0.qty[:0]
+    _say("case no orders")
+    out = api.pk_picard_simulate(api.DeviceProblem.from_instance(inst0), "greedy", block_len=4)
+    np.testing.assert_array_equal(out["final_inv"].cpu().numpy(), inst0.x0)
+    # no stock anywhere: every order is lost, the first pass already equals alpha^0
+    inst1 = random_tiny(23, N=4, K=3, R=2, T=50)
+    inst1.x0[:] = 0
+    _say("case no stock")
+    out = api.pk_picard_simulate(api.DeviceProblem.from_instance(inst1), "greedy", block_len=5)
+    assert (out["actions"].cpu().numpy() == -1).all() and out["passes"][0] == 1
+    # one warehouse, one order
+    inst2 = random_tiny(24, N=1, K=1, R=1, T=1, inv_max=1)
+    _say("case single order")
+    want_a, want_s, want_f, _ = _oracle_batch(oracle, inst2)
+    out = api.pk_picard_simulate(api.DeviceProblem.from_instance(inst2), "greedy", block_len=1)
+    _check(out, inst2, want_a, want_s, want_f)
+
+
+def test_warm_start(api, oracle):
+    inst = random_tiny(31, N=6, K=3, R=3, T=300, qmax=2, inv_max=8, n_traj=2)
+    want_a, want_s, want_f, _ = _oracle_batch(oracle, inst)
+    prob = api.DeviceProblem.from_instance(inst)
+    _say("case warm start from the serial actions")
+    init = torch.from_numpy(want_a).cuda()
+    out = api.pk_picard_simulate(prob, "greedy", block_len=16, init_cache=init, validate=True)
+    _check(out, inst, want_a, want_s, want_f)
+    assert list(out["passes"]) == [1, 1]
+    _say("case warm start from a random cache")
+    rnd = np.random.default_rng(0).integers(-1, inst.N, inst.total_orders).astype(np.int32)
+    out = api.pk_picard_simulate(prob, "greedy", block_len=16,
+                                 init_cache=torch.from_numpy(rnd).cuda(), validate=True)
+    _check(out, inst, want_a, want_s, want_f)
+    w = oracle.block_workers(inst, 16)
+    for b in range(inst.n_traj):
+        lo, hi = int(inst.traj_offsets[b]), int(inst.traj_offsets[b + 1])
+        pr = oracle.picard_runs(inst, w[lo:hi], b, init_cache=rnd[lo:hi])
+        assert out["passes"][b] == pr["passes"]
+
+
+def test_errors(api):
+    inst = random_tiny(41, N=4, K=3, R=2, T=40)
+    prob = api.DeviceProblem.from_instance(inst)
+    _say("case errors")
+    bad = api.DeviceProblem.from_instance(inst)
+    bad.sku = bad.sku.clone()
+    bad.sku[3] = 99
+    with pytest.raises(api.PicardError) as e:
+        api.pk_picard_simulate(bad, "greedy", block_len=4, validate=True)
+    assert e.value.status == api.PK_ERR_INVALID_ARG
+    bad = api.DeviceProblem.from_instance(inst)
+    bad.init_inv = bad.init_inv.clone()
+    bad.init_inv[0, 0, 0] = -3
+    with pytest.raises(api.PicardError) as e:
+        api.pk_picard_simulate(bad, "greedy", block_len=4, validate=True)
+    assert e.value.status == api.PK_ERR_INVALID_ARG
+    # workspace too small
+    import ctypes as C
+    p, po = prob.c_problem(), prob.c_policy("greedy")
+    o = api.pk_picard_opts(4, 0, 1, 0, None, 0)
+    ws = torch.empty(64, dtype=torch.uint8, device="cuda")
+    act = torch.empty(prob.total, dtype=torch.int32, device="cuda")
+    st = api.lib().pk_picard_simulate(C.byref(p), C.byref(po), C.byref(o), ws.data_ptr(), 64,
+                                      act.data_ptr(), None, None, None, None)
+    assert st == api.PK_ERR_WORKSPACE
+    # not converged: max_passes = 1 returns the first cache
+    out = api.pk_picard_simulate(prob, "greedy", block_len=1, max_passes=1,
+                                 raise_not_converged=False)
+    assert out["status"] == api.PK_ERR_NOT_CONVERGED
+
+
+def test_at_scale_1m_orders(api, oracle):
+    """The benchmark workload (N=100, K=1e5, R=200, T=1e6) at full size, bit-exact."""
+    inst = make_instance("greedy_n100_k1e5_t1e6")
+    B = 1024
+    _say(f"case 1M orders B={B}")
+    want_a, want_s, want_f, want_p = _oracle_batch(oracle, inst, B)
+    prob = api.DeviceProblem.from_instance(inst)
+    out = api.pk_picard_simulate(prob, "greedy", block_len=B)
+    _check(out, inst, want_a, want_s, want_f)
+    np.testing.assert_array_equal(out["passes"], want_p)
+    _say(f"passes={out['passes']} stats={out['stats']}")
+
+
+def test_batched_uneven_horizons(api, oracle):
+    """Batched trajectories of uneven horizon (N=50, K=2e4, R=100, q in 1..3), reduced to
+    16 trajectories with horizons in [1e4, 1e5]."""
+    inst = make_instance("greedy_batch256_n50_k2e4", n_traj=16, T=(10_000, 100_000))
+    B = 256
+    _say(f"case batch16 total={inst.total_orders}")
+    want_a, want_s, want_f, want_p = _oracle_batch(oracle, inst, B)
+    prob = api.DeviceProblem.from_instance(inst)
+    out = api.pk_picard_simulate(prob, "greedy", block_len=B)
+    _check(out, inst, want_a, want_s, want_f)
+    np.testing.assert_array_equal(out["passes"], want_p)
