@@ -1,0 +1,151 @@
+"""Benchmark: simulated orders/s of Picard policy simulation on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+A step is one pk_picard_simulate call on one batch of synthetic orders resident in HBM:
+setup (sort, partition, rank table), every Picard pass to convergence, and the final
+unpermute.  Prints ONE JSON line with the throughput, the passes to converge, the serial
+GPU sweep on the same instance (speed-up), the roofline of the dominant kernel measured
+with HIP events on the library's stream, and the CPU oracle's throughput on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "simulated orders/sec/GPU, Picard vs serial GPU sweep; iterations to converge"
+HBM_PEAK_GBS = 8000.0
+DEFAULT_WORKLOAD = "greedy_n100_k1e5_t1e6"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_walk_greedy_n100_k1e5_t1e6.json")
+WALK_SOURCE = os.path.join(ROOT, "paper_2406_01939_amd", "csrc", "greedy.hip")
+
+
+def _traffic():
+    """HBM bytes per walk launch from the committed rocprofv3 counter summary, if the walk
+    kernel's source is unchanged since the counters were taken; else None."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+        h = hashlib.sha256(open(WALK_SOURCE, "rb").read()).hexdigest()
+        if rec.get("source_sha256") != h:
+            return None
+        return rec["bytes_per_launch"]
+    except (OSError, ValueError, KeyError):
+        return None
+
+
+def cpu_baseline(inst, budget_s: float = 8.0):
+    """The oracle's serial rollout (single thread) over whole trajectories of the same
+    workload, repeated until the time budget is used."""
+    from oracle import oracle as O
+    O.build(force=False)
+    t0 = time.perf_counter()
+    orders, reps = 0, 0
+    while True:
+        for b in range(inst.n_traj):
+            O.serial(inst, b)
+            orders += inst.horizon(b)
+            if time.perf_counter() - t0 > budget_s:
+                break
+        reps += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": orders / dt, "unit": "orders/s", "cores": 1, "kind": "oracle",
+            "sample": f"serial oracle rollout, {orders} orders ({reps} pass(es) over the "
+                      f"workload's trajectories), {dt:.2f} s, one thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
+    ap.add_argument("--block-len", type=int, default=0)
+    ap.add_argument("--no-serial", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
+              "sharding is described in DESIGN.md, not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2406_01939_amd import api
+    from paper_2406_01939_amd.instances import make_instance
+
+    inst = make_instance(args.workload)
+    policy = "mlp" if inst.params is not None else "greedy"
+    prob = api.DeviceProblem.from_instance(inst)
+    torch.cuda.synchronize()
+    total = inst.total_orders
+    B = args.block_len if args.block_len > 0 else api.pk_autotune(prob, policy)
+
+    out = None
+    for _ in range(args.warmup):
+        out = api.pk_picard_simulate(prob, policy, block_len=B, out=out)
+    torch.cuda.synchronize()
+    walk_ms = walk_bytes = 0.0
+    walk_launches = 0
+    passes = None
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        out = api.pk_picard_simulate(prob, policy, block_len=B, out=out, timing=True)
+        st = out["stats"]
+        walk_ms += st["walk_ms"]
+        walk_bytes += st["walk_bytes"]
+        walk_launches += st["walk_launches"]
+        passes = out["passes"]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = 1e3 * dt / args.steps
+    value = total * args.steps / dt
+
+    res = {"metric": METRIC, "value": value, "unit": "orders/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "int32" if policy == "greedy" else "f32", "data": "synthetic",
+           "config": {"workload": args.workload, "policy": policy, "n_warehouses": inst.N,
+                      "n_skus": inst.K, "n_regions": inst.R, "n_traj": inst.n_traj,
+                      "orders": total, "block_len": B, "parallelism": "1 GPU"},
+           "passes_max": int(passes.max()), "passes_mean": float(passes.mean())}
+
+    achieved = (walk_bytes / 1e9) / (walk_ms / 1e3) if walk_ms > 0 else 0.0
+    res["roofline"] = {"kernel": "k_walk_greedy" if policy == "greedy" else "k_walk_mlp",
+                       "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                       "traffic": _traffic(),
+                       "bytes_per_launch": walk_bytes / max(walk_launches, 1),
+                       "avg_launch_us": 1e3 * walk_ms / max(walk_launches, 1),
+                       "launches": walk_launches}
+
+    if not args.no_serial:
+        api.pk_serial_simulate(prob, policy)  # warm
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ser = api.pk_serial_simulate(prob, policy)
+        torch.cuda.synchronize()
+        sdt = time.perf_counter() - t1
+        same = bool(torch.equal(ser["actions"], out["actions"]))
+        res["serial_gpu"] = {"value": total / sdt, "unit": "orders/s", "seconds": sdt,
+                             "identical_actions": same}
+        res["speedup_vs_serial_gpu"] = value / (total / sdt)
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(inst)
+    res["paper_context"] = ("paper (A100 40GB, JAX, 16-bit): 441x Picard speed-up over a "
+                            "sequential GPU rollout at 3M orders / 1M products / 30 nodes, "
+                            "MLP policy; not this workload")
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -129,8 +129,8 @@ typedef struct pk_stats {
     int64_t runs_walked;     /* process runs evaluated (a run: one process's orders of one
                                 SKU) */
     int64_t orders_walked;   /* policy evaluations performed over all passes */
-    int64_t near_ties;       /* MLP: evaluations whose top-two perturbed scores were within
-                                1e-5 relative (final pass) */
+    int64_t near_ties;       /* MLP: evaluations (all passes) whose top-two perturbed scores
+                                were within 1e-5 relative */
     double walk_ms;          /* summed duration of the policy-evaluation kernel (measured
                                 with HIP events on `stream` when timing is requested) */
     int64_t walk_launches;   /* launches of that kernel that did work */
@@ -183,6 +183,13 @@ pk_status pk_policy_grad(const pk_problem *problem, const pk_policy *policy,
  * best_block_len: HOST out. */
 pk_status pk_autotune(const pk_problem *problem, const pk_policy *policy, void *ws,
                       size_t ws_bytes, int32_t *best_block_len, void *stream);
+
+/* Diagnostic: noise-free MLP scores s_w of every warehouse w for an order of region
+ * `region` in trajectory `traj` at SKU inventory row inv_row ([N], device), written to
+ * scores ([N], device, float32).  Same scorer as the simulation kernels.  MLP only. */
+pk_status pk_policy_scores(const pk_problem *problem, const pk_policy *policy, int32_t traj,
+                           int32_t region, const int32_t *inv_row, float *scores, void *ws,
+                           size_t ws_bytes, void *stream);
 
 /* Message for the last non-OK status on this thread ("" if none). */
 const char *pk_last_error(void);

@@ -83,8 +83,9 @@ def lib():
         L.pk_picard_simulate.argtypes = [P, Po, O, vp, sz, vp, vp, vp, S, vp]
         L.pk_policy_grad.argtypes = [P, Po, vp, vp, vp, vp, C.POINTER(C.c_double), vp, sz, i32, vp]
         L.pk_autotune.argtypes = [P, Po, vp, sz, C.POINTER(i32), vp]
+        L.pk_policy_scores.argtypes = [P, Po, i32, i32, vp, vp, vp, sz, vp]
         for f in ("pk_workspace_size", "pk_serial_simulate", "pk_picard_simulate",
-                  "pk_policy_grad", "pk_autotune"):
+                  "pk_policy_grad", "pk_autotune", "pk_policy_scores"):
             getattr(L, f).restype = C.c_int
         L.pk_last_error.restype = C.c_char_p
         L.pk_last_error.argtypes = []
@@ -253,6 +254,19 @@ def pk_autotune(prob: DeviceProblem, policy: str = "greedy", stream=None) -> int
     _check(lib().pk_autotune(C.byref(p), C.byref(po), _ptr(ws), ws.numel(), C.byref(best),
                              _stream(stream)))
     return int(best.value)
+
+
+def pk_policy_scores(prob: DeviceProblem, traj: int, region: int, inv_row: torch.Tensor,
+                     stream=None) -> torch.Tensor:
+    """Noise-free MLP scores of every warehouse (diagnostic)."""
+    dev = prob.sku.device
+    p, po = prob.c_problem(), prob.c_policy("mlp")
+    ws = workspace(pk_workspace_size(prob, "mlp"), dev)
+    inv_row = inv_row.to(device=dev, dtype=torch.int32).contiguous()
+    out = torch.empty(prob.N, dtype=torch.float32, device=dev)
+    _check(lib().pk_policy_scores(C.byref(p), C.byref(po), traj, region, _ptr(inv_row),
+                                  _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
+    return out
 
 
 # C names are the primary API; the short names are aliases.

@@ -6,6 +6,8 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "pk_internal.h"
@@ -16,7 +18,8 @@ hipError_t setup_ctl(Plan &L, int n_traj, int max_passes, hipStream_t st);
 hipError_t setup_plan(const Prob &P, Plan &L, const int32_t *init_cache, int validate,
                       bool want_t, int32_t n_seg_max, void *scratch, hipStream_t st);
 size_t setup_scratch_bytes(int64_t n);
-hipError_t setup_rank(const Prob &P, int16_t *rank, hipStream_t st);
+hipError_t setup_pos(const Prob &P, void *pos, hipStream_t st);
+size_t pos_bytes(int N, int R, int n_traj);
 // pass.hip
 hipError_t launch_scan_entry(const Prob &P, const Plan &L, int n_seg_max, bool skip_first,
                              hipStream_t st);
@@ -26,10 +29,21 @@ hipError_t launch_unpermute(const Prob &P, const Plan &L, int32_t *actions, int3
                             hipStream_t st);
 // greedy.hip
 size_t walk_greedy_lds(int N, int R);
-hipError_t launch_walk_greedy(const Prob &P, const Plan &L, int32_t *final_inv, bool has_init,
-                              int grid, hipStream_t st);
-hipError_t launch_serial_greedy(const Prob &P, const int16_t *rank, int32_t *state,
-                                int32_t *actions, int32_t *shipped, hipStream_t st);
+hipError_t launch_walk_greedy(const Prob &P, const Plan &L, const void *pos, int32_t *final_inv,
+                              bool has_init, int grid, hipStream_t st);
+hipError_t launch_serial_greedy(const Prob &P, const void *pos, int32_t *state, int32_t *actions,
+                                int32_t *shipped, hipStream_t st);
+// mlp.hip
+size_t costT_bytes(int N, int R, int n_traj);
+hipError_t setup_costT(const Prob &P, float *costT, hipStream_t st);
+size_t walk_mlp_lds(int N);
+hipError_t launch_walk_mlp(const Prob &P, const Plan &L, const float *params, int layers,
+                           const float *costT, int32_t *final_inv, bool has_init, int grid,
+                           hipStream_t st);
+hipError_t launch_serial_mlp(const Prob &P, const float *params, int layers, const float *costT,
+                             int32_t *state, int32_t *actions, int32_t *shipped, hipStream_t st);
+hipError_t launch_scores(const Prob &P, const float *params, int layers, const float *costT,
+                         int b, int r, const int32_t *xrow, float *out, hipStream_t st);
 } // namespace pk
 
 using namespace pk;
@@ -57,6 +71,7 @@ pk_status fail(pk_status s, const char *fmt, ...)
     } while (0)
 
 constexpr int DEFAULT_BLOCK_GREEDY = 1024;
+constexpr int DEFAULT_BLOCK_MLP = 256;
 constexpr int MIN_AUTOTUNE_BLOCK = 64;
 
 struct Dims {
@@ -149,6 +164,7 @@ void carve_plan(Carver &c, const Dims &d, const pk_policy *po, int B, Plan *L,
     p.ctl = c.take<Ctl>(1);
     *traj_off = c.take<int64_t>(d.n_traj + 1);
     p.traj_lcp = c.take<int32_t>(d.n_traj);
+    p.sink = c.take<int32_t>(128);
     p.perm = c.take<int32_t>(d.total);
     p.s_key = c.take<int32_t>(d.total);
     p.s_region = c.take<int32_t>(d.total);
@@ -167,7 +183,10 @@ void carve_plan(Carver &c, const Dims &d, const pk_policy *po, int B, Plan *L,
     p.split_list = c.take<int32_t>(s.n_split_max);
     p.u = c.take<int32_t>(s.n_split_max * d.N);
     p.E = c.take<int32_t>(s.n_split_max * d.N);
-    p.rank = c.take<int16_t>((int64_t)d.n_traj * d.R * d.N);
+    if (po->kind == PK_POLICY_MLP)
+        p.costT = c.take<float>((int64_t)costT_bytes(d.N, d.R, d.n_traj) / 4);
+    else
+        p.pos = c.take<char>((int64_t)pos_bytes(d.N, d.R, d.n_traj));
     *setup_scratch = c.take<char>((int64_t)setup_scratch_bytes(d.total));
     if (L) *L = p;
 }
@@ -176,7 +195,7 @@ size_t serial_bytes(const Dims &d)
 {
     Carver c{nullptr};
     c.take<int64_t>(d.n_traj + 1);
-    c.take<int16_t>((int64_t)d.n_traj * d.R * d.N);
+    c.take<char>((int64_t)std::max(pos_bytes(d.N, d.R, d.n_traj), costT_bytes(d.N, d.R, d.n_traj)));
     c.take<int32_t>((int64_t)d.n_traj * d.K * d.N);
     return c.off + 256;
 }
@@ -234,92 +253,25 @@ int num_cus()
     return n;
 }
 
-} // namespace
-
-extern "C" {
-
-const char *pk_last_error(void) { return g_err.c_str(); }
-
-const char *pk_version(void) { return "libpicard 0.1 (gfx950)"; }
-
-pk_status pk_workspace_size(const pk_problem *problem, const pk_policy *policy,
-                            const pk_picard_opts *opts, size_t *bytes)
+pk_status picard_run(const pk_problem *problem, const Dims &d, const pk_policy *policy,
+                     const pk_picard_opts &o, int B, void *ws, size_t ws_bytes,
+                     int32_t *actions, int32_t *shipped, int32_t *final_inv, pk_stats *stats,
+                     hipStream_t stream)
 {
-    Dims d;
-    pk_status s = check_problem(problem, &d);
-    if (s != PK_OK) return s;
-    if ((s = check_policy(policy)) != PK_OK) return s;
-    if (!bytes) return fail(PK_ERR_INVALID_ARG, "bytes is NULL");
-    int B = opts && opts->block_len > 0 ? opts->block_len : MIN_AUTOTUNE_BLOCK;
-    if (policy->kind == PK_POLICY_MLP && !(opts && opts->block_len > 0)) B = MIN_AUTOTUNE_BLOCK;
-    *bytes = std::max(picard_bytes(d, policy, B), serial_bytes(d));
-    return PK_OK;
-}
-
-pk_status pk_serial_simulate(const pk_problem *problem, const pk_policy *policy, void *ws,
-                             size_t ws_bytes, int32_t *actions, int32_t *shipped,
-                             int32_t *final_inv, int32_t validate, void *stream)
-{
-    g_err.clear();
-    Dims d;
-    pk_status s = check_problem(problem, &d);
-    if (s != PK_OK) return s;
-    if ((s = check_policy(policy)) != PK_OK) return s;
-    if (d.total > 0 && !actions) return fail(PK_ERR_INVALID_ARG, "actions is NULL");
-    if (policy->kind != PK_POLICY_GREEDY)
-        return fail(PK_ERR_UNSUPPORTED, "serial learned policy not built yet");
-    if (!ws || ws_bytes < serial_bytes(d)) return fail(PK_ERR_WORKSPACE, "workspace too small");
-    hipStream_t st = (hipStream_t)stream;
-    Carver c{align_ws(ws)};
-    int64_t *to = c.take<int64_t>(d.n_traj + 1);
-    int16_t *rank = c.take<int16_t>((int64_t)d.n_traj * d.R * d.N);
-    int32_t *state = final_inv ? final_inv : c.take<int32_t>((int64_t)d.n_traj * d.K * d.N);
-    HIP_TRY(hipMemcpyAsync(to, problem->traj_offsets, (d.n_traj + 1) * sizeof(int64_t),
-                           hipMemcpyHostToDevice, st));
-    Prob P = make_prob(problem, d, to);
-    HIP_TRY(hipMemcpyAsync(state, problem->init_inv, (size_t)d.n_traj * d.K * d.N * 4,
-                           hipMemcpyDeviceToDevice, st));
-    HIP_TRY(setup_rank(P, rank, st));
-    (void)validate;
-    HIP_TRY(launch_serial_greedy(P, rank, state, actions, shipped, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    return PK_OK;
-}
-
-pk_status pk_picard_simulate(const pk_problem *problem, const pk_policy *policy,
-                             const pk_picard_opts *opts, void *ws, size_t ws_bytes,
-                             int32_t *actions, int32_t *shipped, int32_t *final_inv,
-                             pk_stats *stats, void *stream)
-{
-    g_err.clear();
-    Dims d;
-    pk_status s = check_problem(problem, &d);
-    if (s != PK_OK) return s;
-    if ((s = check_policy(policy)) != PK_OK) return s;
-    if (d.total > 0 && !actions) return fail(PK_ERR_INVALID_ARG, "actions is NULL");
-    pk_picard_opts o = {};
-    o.use_frontier = 1;
-    if (opts) o = *opts;
-    if (o.block_len < 0 || o.max_passes < 0 || o.graph_unroll < 0)
-        return fail(PK_ERR_INVALID_ARG, "negative option");
-    if (policy->kind != PK_POLICY_GREEDY)
-        return fail(PK_ERR_UNSUPPORTED, "learned-policy Picard not built yet");
-    const int B = o.block_len > 0 ? o.block_len : DEFAULT_BLOCK_GREEDY;
     const int64_t mp64 = o.max_passes > 0 ? o.max_passes : d.max_T + 1;
     const int max_passes = (int)std::min<int64_t>(mp64, 0x7ffffff0);
     if (!ws || ws_bytes < picard_bytes(d, policy, B))
         return fail(PK_ERR_WORKSPACE, "workspace too small: need %zu bytes, got %zu",
                     picard_bytes(d, policy, B), ws_bytes);
-    if (!o.use_frontier)
-        return fail(PK_ERR_UNSUPPORTED, "use_frontier=0 not built yet");
-    if (walk_greedy_lds(d.N, d.R) > 65536)
+    if (policy->kind == PK_POLICY_GREEDY && walk_greedy_lds(d.N, d.R) > 65536)
         return fail(PK_ERR_SHAPE, "N=%d, R=%d need more LDS than a workgroup has", d.N, d.R);
-    hipStream_t st = (hipStream_t)stream;
+    hipStream_t st = stream;
     Carver c{align_ws(ws)};
     Plan L;
     int64_t *to;
     void *scratch;
     carve_plan(c, d, policy, B, &L, &to, &scratch);
+    L.no_frontier = o.use_frontier ? 0 : 1;
     const Sizes sz = plan_sizes(d, B);
     HIP_TRY(hipMemcpyAsync(to, problem->traj_offsets, (d.n_traj + 1) * sizeof(int64_t),
                            hipMemcpyHostToDevice, st));
@@ -327,9 +279,13 @@ pk_status pk_picard_simulate(const pk_problem *problem, const pk_policy *policy,
     HIP_TRY(setup_ctl(L, d.n_traj, max_passes, st));
     const bool has_init = o.init_cache != nullptr;
     if (d.total > 0) {
-        HIP_TRY(setup_plan(P, L, o.init_cache, o.validate, false, (int32_t)sz.n_seg_max, scratch,
+        const bool mlp = policy->kind == PK_POLICY_MLP;
+        HIP_TRY(setup_plan(P, L, o.init_cache, o.validate, mlp, (int32_t)sz.n_seg_max, scratch,
                            st));
-        HIP_TRY(setup_rank(P, L.rank, st));
+        if (mlp)
+            HIP_TRY(setup_costT(P, L.costT, st));
+        else
+            HIP_TRY(setup_pos(P, L.pos, st));
         if (has_init) HIP_TRY(launch_consume(P, L, sz.n_split_max, st));
     }
     if (final_inv)
@@ -356,7 +312,11 @@ pk_status pk_picard_simulate(const pk_problem *problem, const pk_policy *policy,
                 HIP_TRY(hipEventCreate(&e1));
                 HIP_TRY(hipEventRecord(e0, st));
             }
-            HIP_TRY(launch_walk_greedy(P, L, final_inv, has_init, grid, st));
+            if (policy->kind == PK_POLICY_MLP)
+                HIP_TRY(launch_walk_mlp(P, L, policy->params, policy->n_hidden_layers, L.costT,
+                                        final_inv, has_init, num_cus() * 4, st));
+            else
+                HIP_TRY(launch_walk_greedy(P, L, L.pos, final_inv, has_init, grid, st));
             if (timing) {
                 HIP_TRY(hipEventRecord(e1, st));
                 evs.push_back(e0);
@@ -380,11 +340,14 @@ pk_status pk_picard_simulate(const pk_problem *problem, const pk_policy *policy,
             for (int b = 0; b < d.n_traj; ++b) stats->passes[b] = lcp[b] + 1;
         stats->passes_max = d.total > 0 ? hc->passes_done : 1;
         stats->block_len = B;
-        stats->changed_total = (int64_t)hc->changed_total;
-        stats->runs_walked = (int64_t)hc->runs_walked;
-        stats->orders_walked = (int64_t)hc->orders_walked;
-        stats->near_ties = (int64_t)hc->near_ties;
-        stats->walk_bytes = (int64_t)hc->bytes_walked;
+        unsigned long long sum[ST_N] = {};
+        for (int i = 0; i < STAT_SLOTS; ++i)
+            for (int k = 0; k < ST_N; ++k) sum[k] += hc->stat[i][k];
+        stats->changed_total = (int64_t)sum[ST_CHANGED];
+        stats->runs_walked = (int64_t)sum[ST_RUNS];
+        stats->orders_walked = (int64_t)sum[ST_ORDERS];
+        stats->near_ties = (int64_t)sum[ST_NEAR_TIES];
+        stats->walk_bytes = (int64_t)sum[ST_BYTES];
         stats->walk_ms = 0.0;
         stats->walk_launches = (int64_t)(evs.size() / 2);
         for (size_t i = 0; i + 1 < evs.size(); i += 2) {
@@ -399,6 +362,209 @@ pk_status pk_picard_simulate(const pk_problem *problem, const pk_policy *policy,
     return PK_OK;
 }
 
+// ---------------------------------------------------------------- block-length autotuner
+std::mutex g_tune_mu;
+std::map<std::string, int> g_tune;
+bool g_tune_loaded = false;
+
+std::string tune_key(const Dims &d, const pk_policy *po)
+{
+    int tb = 0;
+    while ((1ll << tb) < std::max<int64_t>(d.total, 1)) ++tb;
+    int mb = 0;
+    while ((1ll << mb) < std::max<int64_t>(d.max_T, 1)) ++mb;
+    char buf[160];
+    snprintf(buf, sizeof buf, "%s/N%d/R%d/K%d/total2^%d/maxT2^%d",
+             po->kind == PK_POLICY_MLP ? "mlp" : "greedy", d.N, d.R, d.K, tb, mb);
+    return buf;
+}
+
+// The cache file is a flat JSON object {"key": block_len, ...}.
+void tune_load_locked()
+{
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *path = getenv("PICARD_AUTOTUNE_CACHE");
+    if (!path) return;
+    FILE *f = fopen(path, "r");
+    if (!f) return;
+    std::string txt;
+    char buf[4096];
+    size_t n;
+    while ((n = fread(buf, 1, sizeof buf, f)) > 0) txt.append(buf, n);
+    fclose(f);
+    size_t i = 0;
+    while ((i = txt.find('"', i)) != std::string::npos) {
+        const size_t j = txt.find('"', i + 1);
+        if (j == std::string::npos) break;
+        const std::string key = txt.substr(i + 1, j - i - 1);
+        const size_t c = txt.find(':', j);
+        if (c == std::string::npos) break;
+        const int v = atoi(txt.c_str() + c + 1);
+        if (v > 0) g_tune[key] = v;
+        i = txt.find_first_of(",}", c);
+        if (i == std::string::npos) break;
+    }
+}
+
+void tune_save_locked()
+{
+    const char *path = getenv("PICARD_AUTOTUNE_CACHE");
+    if (!path) return;
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = fopen(tmp.c_str(), "w");
+    if (!f) return;
+    fputs("{", f);
+    bool firstk = true;
+    for (auto &kv : g_tune) {
+        fprintf(f, "%s\n  \"%s\": %d", firstk ? "" : ",", kv.first.c_str(), kv.second);
+        firstk = false;
+    }
+    fputs("\n}\n", f);
+    fclose(f);
+    rename(tmp.c_str(), path);
+}
+
+// Times candidate block lengths on this instance (best of two runs each) and keeps the
+// fastest.  Outputs of the trial runs go to `actions`, which the caller overwrites.
+pk_status autotune_block(const pk_problem *problem, const Dims &d, const pk_policy *po,
+                         void *ws, size_t ws_bytes, int32_t *actions, hipStream_t st, int *best)
+{
+    const std::string key = tune_key(d, po);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_load_locked();
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            *best = it->second;
+            return PK_OK;
+        }
+    }
+    static const int cands[] = {64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384, 65536};
+    pk_picard_opts o = {};
+    o.use_frontier = 1;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    float best_ms = 1e30f;
+    int best_b = DEFAULT_BLOCK_GREEDY;
+    for (int B : cands) {
+        if (B > 2 * std::max<int64_t>(d.total, 1) && B != cands[0]) break;
+        if (ws_bytes < picard_bytes(d, po, B)) continue;
+        float t = 1e30f;
+        for (int rep = 0; rep < 2; ++rep) {
+            HIP_TRY(hipEventRecord(e0, st));
+            pk_status s = picard_run(problem, d, po, o, B, ws, ws_bytes, actions, nullptr,
+                                     nullptr, nullptr, st);
+            if (s != PK_OK) {
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                return s;
+            }
+            HIP_TRY(hipEventRecord(e1, st));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            t = std::min(t, ms);
+        }
+        if (t < best_ms) {
+            best_ms = t;
+            best_b = B;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = best_b;
+    tune_save_locked();
+    *best = best_b;
+    return PK_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+const char *pk_last_error(void) { return g_err.c_str(); }
+
+const char *pk_version(void) { return "libpicard 0.1 (gfx950)"; }
+
+pk_status pk_workspace_size(const pk_problem *problem, const pk_policy *policy,
+                            const pk_picard_opts *opts, size_t *bytes)
+{
+    Dims d;
+    pk_status s = check_problem(problem, &d);
+    if (s != PK_OK) return s;
+    if ((s = check_policy(policy)) != PK_OK) return s;
+    if (!bytes) return fail(PK_ERR_INVALID_ARG, "bytes is NULL");
+    int B = opts && opts->block_len > 0 ? opts->block_len : MIN_AUTOTUNE_BLOCK;
+    if (policy->kind == PK_POLICY_MLP && !(opts && opts->block_len > 0)) B = MIN_AUTOTUNE_BLOCK;
+    *bytes = std::max(picard_bytes(d, policy, B), serial_bytes(d)) +
+             (((size_t)std::max<int64_t>(d.total, 1) * 4 + 255) & ~(size_t)255) + 512;
+    return PK_OK;
+}
+
+pk_status pk_serial_simulate(const pk_problem *problem, const pk_policy *policy, void *ws,
+                             size_t ws_bytes, int32_t *actions, int32_t *shipped,
+                             int32_t *final_inv, int32_t validate, void *stream)
+{
+    g_err.clear();
+    Dims d;
+    pk_status s = check_problem(problem, &d);
+    if (s != PK_OK) return s;
+    if ((s = check_policy(policy)) != PK_OK) return s;
+    if (d.total > 0 && !actions) return fail(PK_ERR_INVALID_ARG, "actions is NULL");
+    if (!ws || ws_bytes < serial_bytes(d)) return fail(PK_ERR_WORKSPACE, "workspace too small");
+    hipStream_t st = (hipStream_t)stream;
+    Carver c{align_ws(ws)};
+    int64_t *to = c.take<int64_t>(d.n_traj + 1);
+    void *pos = c.take<char>(
+        (int64_t)std::max(pos_bytes(d.N, d.R, d.n_traj), costT_bytes(d.N, d.R, d.n_traj)));
+    int32_t *state = final_inv ? final_inv : c.take<int32_t>((int64_t)d.n_traj * d.K * d.N);
+    HIP_TRY(hipMemcpyAsync(to, problem->traj_offsets, (d.n_traj + 1) * sizeof(int64_t),
+                           hipMemcpyHostToDevice, st));
+    Prob P = make_prob(problem, d, to);
+    HIP_TRY(hipMemcpyAsync(state, problem->init_inv, (size_t)d.n_traj * d.K * d.N * 4,
+                           hipMemcpyDeviceToDevice, st));
+    (void)validate;
+    if (policy->kind == PK_POLICY_MLP) {
+        HIP_TRY(setup_costT(P, (float *)pos, st));
+        HIP_TRY(launch_serial_mlp(P, policy->params, policy->n_hidden_layers, (const float *)pos,
+                                  state, actions, shipped, st));
+    } else {
+        HIP_TRY(setup_pos(P, pos, st));
+        HIP_TRY(launch_serial_greedy(P, pos, state, actions, shipped, st));
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    return PK_OK;
+}
+
+pk_status pk_picard_simulate(const pk_problem *problem, const pk_policy *policy,
+                             const pk_picard_opts *opts, void *ws, size_t ws_bytes,
+                             int32_t *actions, int32_t *shipped, int32_t *final_inv,
+                             pk_stats *stats, void *stream)
+{
+    g_err.clear();
+    Dims d;
+    pk_status s = check_problem(problem, &d);
+    if (s != PK_OK) return s;
+    if ((s = check_policy(policy)) != PK_OK) return s;
+    if (d.total > 0 && !actions) return fail(PK_ERR_INVALID_ARG, "actions is NULL");
+    pk_picard_opts o = {};
+    o.use_frontier = 1;
+    if (opts) o = *opts;
+    if (o.block_len < 0 || o.max_passes < 0 || o.graph_unroll < 0)
+        return fail(PK_ERR_INVALID_ARG, "negative option");
+    int B = o.block_len;
+    if (B == 0 && policy->kind == PK_POLICY_MLP) B = DEFAULT_BLOCK_MLP;
+    if (B == 0) {
+        s = autotune_block(problem, d, policy, ws, ws_bytes, actions, (hipStream_t)stream, &B);
+        if (s != PK_OK) return s;
+    }
+    return picard_run(problem, d, policy, o, B, ws, ws_bytes, actions, shipped, final_inv, stats,
+                      (hipStream_t)stream);
+}
+
 pk_status pk_policy_grad(const pk_problem *problem, const pk_policy *policy,
                          const int32_t *actions, const float *advantages, float *logp,
                          float *grad, double *objective, void *ws, size_t ws_bytes,
@@ -410,13 +576,55 @@ pk_status pk_policy_grad(const pk_problem *problem, const pk_policy *policy,
     return fail(PK_ERR_UNSUPPORTED, "policy gradient not built yet");
 }
 
+pk_status pk_policy_scores(const pk_problem *problem, const pk_policy *policy, int32_t traj,
+                           int32_t region, const int32_t *inv_row, float *scores, void *ws,
+                           size_t ws_bytes, void *stream)
+{
+    g_err.clear();
+    Dims d;
+    pk_status s = check_problem(problem, &d);
+    if (s != PK_OK) return s;
+    if ((s = check_policy(policy)) != PK_OK) return s;
+    if (policy->kind != PK_POLICY_MLP) return fail(PK_ERR_INVALID_ARG, "scores need the MLP policy");
+    if (traj < 0 || traj >= d.n_traj || region < 0 || region >= d.R)
+        return fail(PK_ERR_INVALID_ARG, "traj or region out of range");
+    if (!inv_row || !scores) return fail(PK_ERR_INVALID_ARG, "inv_row/scores is NULL");
+    const size_t need = costT_bytes(d.N, d.R, d.n_traj) + 1024;
+    if (!ws || ws_bytes < need) return fail(PK_ERR_WORKSPACE, "workspace too small");
+    hipStream_t st = (hipStream_t)stream;
+    Carver c{align_ws(ws)};
+    float *costT = c.take<float>((int64_t)costT_bytes(d.N, d.R, d.n_traj) / 4);
+    Prob P = make_prob(problem, d, nullptr);
+    HIP_TRY(setup_costT(P, costT, st));
+    HIP_TRY(launch_scores(P, policy->params, policy->n_hidden_layers, costT, traj, region, inv_row,
+                          scores, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return PK_OK;
+}
+
 pk_status pk_autotune(const pk_problem *problem, const pk_policy *policy, void *ws,
                       size_t ws_bytes, int32_t *best_block_len, void *stream)
 {
     g_err.clear();
-    (void)problem; (void)policy; (void)ws; (void)ws_bytes; (void)stream;
-    if (best_block_len) *best_block_len = DEFAULT_BLOCK_GREEDY;
-    return fail(PK_ERR_UNSUPPORTED, "autotune not built yet");
+    Dims d;
+    pk_status s = check_problem(problem, &d);
+    if (s != PK_OK) return s;
+    if ((s = check_policy(policy)) != PK_OK) return s;
+    if (!best_block_len) return fail(PK_ERR_INVALID_ARG, "best_block_len is NULL");
+    if (policy->kind != PK_POLICY_GREEDY) {
+        *best_block_len = DEFAULT_BLOCK_MLP;
+        return PK_OK;
+    }
+    const size_t act_bytes = ((size_t)std::max<int64_t>(d.total, 1) * 4 + 255) & ~(size_t)255;
+    if (!ws || ws_bytes < act_bytes + 512) return fail(PK_ERR_WORKSPACE, "workspace too small");
+    // trial actions live at the end of the workspace
+    char *tail = (char *)ws + ((ws_bytes - act_bytes) & ~(size_t)255);
+    int B = 0;
+    s = autotune_block(problem, d, policy, ws, (size_t)(tail - (char *)ws), (int32_t *)tail,
+                       (hipStream_t)stream, &B);
+    if (s != PK_OK) return s;
+    *best_block_len = B;
+    return PK_OK;
 }
 
 } // extern "C"

@@ -29,7 +29,7 @@ __global__ __launch_bounds__(256) void k_scan_entry(Prob P, Plan L, int skip_fir
     const int N = P.N;
     for (int i = blockIdx.x; i < n; i += gridDim.x) {
         const int g = L.split_segs[i];
-        const int32_t f = fprev[g];
+        const int32_t f = L.no_frontier ? FR_ALL : fprev[g];
         if (threadIdx.x == 0) fcur[g] = FR_NONE;
         if (f == FR_NONE || (pass == 1 && skip_first_pass)) continue;
         const int s0 = L.seg_sr0[g];
@@ -60,9 +60,6 @@ __global__ void k_pass_end(Ctl *ctl)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     if (ctl->done) return;
-    ctl->changed_total += ctl->changed_this_pass;
-    ctl->changed_this_pass = 0;
-    ctl->work = 0;
     if (!ctl->any_changed) {
         ctl->done = 1;
         ctl->passes_done = ctl->pass;

@@ -25,30 +25,25 @@ struct Prob {
 
 // Control block in device memory: the pass loop runs without host round trips; every
 // pass kernel reads `pass`/`done` and the end-of-pass kernel advances them.
+constexpr int STAT_SLOTS = 64; // statistics are spread over slots to avoid one hot address
+enum { ST_ORDERS = 0, ST_RUNS, ST_CHANGED, ST_BYTES, ST_NEAR_TIES, ST_N };
+
 struct Ctl {
     int32_t pass;        // current pass (1-based)
-    int32_t done;        // 1 once a pass changed nothing
+    int32_t done;        // 1 once a pass changed nothing, 2 when max_passes was reached
     int32_t any_changed; // this pass
-    int32_t work;        // dynamic work counter of the walk
     int32_t n_sr, n_seg, n_split, n_split_seg; // setup products
     int32_t error;       // validate: nonzero if an input value was out of range
     int32_t passes_done; // pass count at convergence
     int32_t max_passes;
-    int32_t pad0;
-    unsigned long long changed_total;
-    unsigned long long runs_walked;
-    unsigned long long orders_walked;
-    unsigned long long near_ties;
-    unsigned long long bytes_walked; // algorithmic bytes of walk launches
-    unsigned long long walk_launch_active; // launches in which some run was walked
-    unsigned long long changed_this_pass;
-    unsigned long long orders_this_pass;
+    unsigned long long stat[STAT_SLOTS][ST_N]; // summed on the host
 };
 
 // Products of the per-call setup (partition and sort), all in the caller's workspace.
 struct Plan {
     int32_t B;               // block length
     int32_t n_keys;          // n_traj * K
+    int32_t no_frontier;     // 1: every run is re-walked every pass
     int32_t *perm;           // [total] sorted position -> original order index
     int32_t *s_key;          // [total] sorted (trajectory, SKU) key
     int32_t *s_region;       // [total]
@@ -66,8 +61,11 @@ struct Plan {
     int32_t *fr[2];          // [n_seg_max] frontier per segment, by pass parity
     int32_t *u;              // [n_split_max][N] cached consumption of each split run
     int32_t *E;              // [n_split_max][N] consumption entering each split run
-    int16_t *rank;           // [n_traj][R][N] warehouses by (cost, index) per region
+    float *costT;            // [n_traj][R][N] cost as float, region-major (learned policy)
+    void *pos;               // [n_traj][R][N] rank key of each warehouse per region
+                             // (uint8 for N <= 256, else uint16; 16-byte padded slices)
     int32_t *traj_lcp;       // [n_traj] last pass in which the trajectory changed
+    int32_t *sink;           // [128] write target of masked-off lanes (contents unused)
     Ctl *ctl;
 };
 

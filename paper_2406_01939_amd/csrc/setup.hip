@@ -6,6 +6,8 @@
 // T_m).  A run is a block's part of one segment; because SKUs never interact without
 // node capacity (Assumption 1, inventory independence), a process's runs are independent
 // and a run is the unit of work on the GPU.
+#include <algorithm>
+
 #include "pk_internal.h"
 
 namespace pk {
@@ -138,38 +140,23 @@ __global__ void k_split_fill(Plan L, const int32_t *ubase, const int32_t *segbas
     }
 }
 
-// rank[b][r][j] = the j-th warehouse in increasing (cost[b][w][r], w) order: one thread
-// per (b, r, w) counts the warehouses that precede w.
-__global__ void k_rank(Prob P, int16_t *rank)
-{
-    const int64_t n = (int64_t)P.n_traj * P.R * P.N;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const int w = (int)(i % P.N);
-        const int64_t br = i / P.N;
-        const int r = (int)(br % P.R);
-        const int b = (int)(br / P.R);
-        const int32_t *c = P.cost + (int64_t)b * P.N * P.R;
-        const int32_t cw = c[(int64_t)w * P.R + r];
-        int pos = 0;
-        for (int v = 0; v < P.N; ++v) {
-            const int32_t cv = c[(int64_t)v * P.R + r];
-            pos += (cv < cw) || (cv == cw && v < w);
-        }
-        rank[br * P.N + pos] = (int16_t)w;
-    }
-}
-
 __global__ void k_init_ctl(Ctl *ctl, int32_t *traj_lcp, int n_traj, int max_passes)
 {
+    // the control block is cleared word by word by the whole grid, then seeded
+    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nthreads = gridDim.x * blockDim.x;
+    uint32_t *w = (uint32_t *)ctl;
+    const int nw = (int)(sizeof(Ctl) / 4);
+    for (int i = tid; i < nw; i += nthreads) w[i] = 0u;
+    for (int b = tid; b < n_traj; b += nthreads) traj_lcp[b] = 0;
+}
+
+__global__ void k_seed_ctl(Ctl *ctl, int max_passes)
+{
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        Ctl c = {};
-        c.pass = 1;
-        c.max_passes = max_passes;
-        *ctl = c;
+        ctl->pass = 1;
+        ctl->max_passes = max_passes;
     }
-    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < n_traj; b += gridDim.x * blockDim.x)
-        traj_lcp[b] = 0;
 }
 
 inline unsigned grid_for(int64_t n, int threads, int cap = 65535)
@@ -185,8 +172,10 @@ inline unsigned grid_for(int64_t n, int threads, int cap = 65535)
 // Reset the control block (must precede every other setup step).
 hipError_t setup_ctl(Plan &L, int n_traj, int max_passes, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_init_ctl, dim3(grid_for(n_traj, 256)), dim3(256), 0, st, L.ctl,
-                       L.traj_lcp, n_traj, max_passes);
+    const int64_t n = std::max<int64_t>(n_traj, (int64_t)(sizeof(Ctl) / 4));
+    hipLaunchKernelGGL(k_init_ctl, dim3(grid_for(n, 256)), dim3(256), 0, st, L.ctl, L.traj_lcp,
+                       n_traj, max_passes);
+    hipLaunchKernelGGL(k_seed_ctl, dim3(1), dim3(64), 0, st, L.ctl, max_passes);
     return hipGetLastError();
 }
 
@@ -253,13 +242,6 @@ size_t setup_scratch_bytes(int64_t n)
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
     size_t t = radix_tmp_bytes(n) > scan_tmp_bytes(n) ? radix_tmp_bytes(n) : scan_tmp_bytes(n);
     return al(n * 4) * 2 + al(n * 8) + al(t) + 1024;
-}
-
-hipError_t setup_rank(const Prob &P, int16_t *rank, hipStream_t st)
-{
-    const int64_t n = (int64_t)P.n_traj * P.R * P.N;
-    hipLaunchKernelGGL(k_rank, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, P, rank);
-    return hipGetLastError();
 }
 
 } // namespace pk

@@ -220,3 +220,31 @@ def test_batched_uneven_horizons(api, oracle):
     out = api.pk_picard_simulate(prob, "greedy", block_len=B)
     _check(out, inst, want_a, want_s, want_f)
     np.testing.assert_array_equal(out["passes"], want_p)
+
+
+def test_no_frontier_gives_same_passes(api, oracle):
+    """Re-walking every run every pass (no restart frontier) reproduces the same caches
+    and pass counts; the frontier only skips work."""
+    inst = make_instance("greedy_n10_k100_t1e4")
+    _say("case no frontier")
+    want_a, want_s, want_f, want_p = _oracle_batch(oracle, inst, 100)
+    prob = api.DeviceProblem.from_instance(inst)
+    a = api.pk_picard_simulate(prob, "greedy", block_len=100, use_frontier=False)
+    _check(a, inst, want_a, want_s, want_f)
+    np.testing.assert_array_equal(a["passes"], want_p)
+    b = api.pk_picard_simulate(prob, "greedy", block_len=100, use_frontier=True)
+    assert b["stats"]["orders_walked"] < a["stats"]["orders_walked"]
+    assert a["stats"]["orders_walked"] == inst.total_orders * int(want_p[0])
+
+
+def test_autotune_picks_a_valid_block(api, oracle):
+    inst = make_instance("greedy_n10_k100_t1e4")
+    _say("case autotune")
+    prob = api.DeviceProblem.from_instance(inst)
+    B = api.pk_autotune(prob, "greedy")
+    assert B in (64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384, 65536)
+    assert api.pk_autotune(prob, "greedy") == B  # cached
+    want_a, want_s, want_f, _ = _oracle_batch(oracle, inst)
+    out = api.pk_picard_simulate(prob, "greedy", block_len=0)
+    _check(out, inst, want_a, want_s, want_f)
+    assert out["stats"]["block_len"] == B

@@ -1,0 +1,131 @@
+"""GPU parity of the learned (MLP softmax) policy against the FP64 CPU oracle.
+
+The GPU computes in FP32 and the oracle in FP64, so an action may differ only where the
+top two perturbed scores are within 1e-5 relative (a near-tie).  Checks: scores against
+the oracle's FP64 scores; self-consistency of the GPU trajectory (at every step the FP64
+policy at the state the GPU actions induce picks the GPU's action, except at near-ties);
+the GPU trajectory equals the oracle's serial trajectory up to the first near-tie; Picard
+equals the GPU serial sweep bit for bit; per-pass caches equal the oracle's Picard passes
+under the same partition when no near-tie occurs.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2406_01939_amd.instances import make_instance, random_tiny
+
+pytestmark = pytest.mark.gpu
+TIE = 1e-5
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2406_01939_amd import api as A
+    A.lib()
+    return A
+
+
+def _near(ev):
+    z1, z2 = ev["z1"], ev["z2"]
+    with np.errstate(invalid="ignore"):
+        rel = (z1 - z2) / np.maximum(np.abs(z1), np.abs(z2))
+    return np.isfinite(z2) & (rel <= TIE)
+
+
+def _self_consistent(oracle, inst, actions):
+    """Per trajectory: FP64 policy at the GPU-induced states vs the GPU actions."""
+    mism = ties = 0
+    for b in range(inst.n_traj):
+        lo, hi = int(inst.traj_offsets[b]), int(inst.traj_offsets[b + 1])
+        a = actions[lo:hi]
+        ev = oracle.eval_at(inst, a, b)
+        near = _near(ev)
+        bad = (ev["choice"] != a) & ~near
+        assert not bad.any(), f"traj {b}: {int(bad.sum())} mismatches away from near-ties"
+        mism += int((ev["choice"] != a).sum())
+        ties += int(near.sum())
+    return mism, ties
+
+
+@pytest.mark.parametrize("L", [2, 1])
+def test_scores_match_oracle(api, oracle, L):
+    inst = random_tiny(3, N=37, K=2, R=5, mlp=True, n_hidden_layers=L)
+    prob = api.DeviceProblem.from_instance(inst)
+    rng = np.random.default_rng(0)
+    _say(f"case scores L={L}")
+    for r in range(inst.R):
+        x = rng.integers(0, 60, inst.N).astype(np.int32)
+        got = api.pk_policy_scores(prob, 0, r, torch.from_numpy(x)).cpu().numpy().astype(np.float64)
+        want = oracle.mlp_scores(inst, r, x)
+        np.testing.assert_allclose(got, want, rtol=2e-5, atol=2e-5 * np.abs(want).max())
+
+
+@pytest.mark.parametrize("B", [1, 3, 16, 1000])
+@pytest.mark.parametrize("seed", range(3))
+def test_tiny_self_consistent_and_serial(api, oracle, seed, B):
+    inst = random_tiny(100 + seed, N=5 + 7 * seed, K=3, R=4, T=120, qmax=1 + seed % 3,
+                       inv_max=6, n_traj=2, mlp=True, n_hidden_layers=2 - (seed == 2))
+    prob = api.DeviceProblem.from_instance(inst)
+    _say(f"case mlp tiny seed={seed} B={B}")
+    out = api.pk_picard_simulate(prob, "mlp", block_len=B, validate=True)
+    gpu = out["actions"].cpu().numpy()
+    _self_consistent(oracle, inst, gpu)
+    ser = api.pk_serial_simulate(prob, "mlp")
+    assert torch.equal(ser["actions"], out["actions"])
+    assert torch.equal(ser["shipped"], out["shipped"])
+    assert torch.equal(ser["final_inv"], out["final_inv"])
+    w = oracle.block_workers(inst, B)
+    for b in range(inst.n_traj):
+        lo, hi = int(inst.traj_offsets[b]), int(inst.traj_offsets[b + 1])
+        ref = oracle.serial(inst, b)
+        if np.array_equal(ref["actions"], gpu[lo:hi]):
+            pr = oracle.picard_runs(inst, w[lo:hi], b)
+            np.testing.assert_array_equal(pr["actions"], gpu[lo:hi])
+            assert out["passes"][b] == pr["passes"]
+        else:  # the first difference must be a near-tie of the FP64 policy
+            first = int(np.nonzero(ref["actions"] != gpu[lo:hi])[0][0])
+            ev = oracle.eval_at(inst, gpu[lo:hi], b)
+            assert _near(ev)[first]
+
+
+def test_every_pass_matches_oracle(api, oracle):
+    inst = random_tiny(7, N=12, K=2, R=3, T=200, qmax=2, inv_max=10, mlp=True)
+    B = 8
+    w = oracle.block_workers(inst, B)
+    ref = oracle.picard_runs(inst, w, record=True)
+    prob = api.DeviceProblem.from_instance(inst)
+    _say(f"case mlp passes={ref['passes']}")
+    ser = oracle.serial(inst)
+    assert np.array_equal(ser["actions"], ref["actions"])
+    for k in range(1, ref["passes"] + 1):
+        out = api.pk_picard_simulate(prob, "mlp", block_len=B, max_passes=k,
+                                     raise_not_converged=False)
+        np.testing.assert_array_equal(out["actions"].cpu().numpy(), ref["caches"][k - 1])
+
+
+def test_batch_shaped_like_large_workload(api, oracle):
+    """N=100, R=200, 2-layer MLP, as the 64-trajectory workload, reduced to 4 trajectories of
+    5000 orders over 2000 SKUs."""
+    inst = make_instance("mlp_batch64_n100_k5e4_t2e5", n_traj=4, T=5000, K=2000)
+    prob = api.DeviceProblem.from_instance(inst)
+    _say("case mlp batch4 T=5000")
+    out = api.pk_picard_simulate(prob, "mlp", block_len=256)
+    gpu = out["actions"].cpu().numpy()
+    mism, ties = _self_consistent(oracle, inst, gpu)
+    _say(f"mismatches at near-ties: {mism}, near-ties: {ties}, passes {out['passes']}, "
+         f"gpu near-ties {out['stats']['near_ties']}")
+    ser = api.pk_serial_simulate(prob, "mlp")
+    assert torch.equal(ser["actions"], out["actions"])
+    sh = out["shipped"].cpu().numpy()
+    assert ((sh >= 0) & (sh <= inst.qty)).all()
+    fin = out["final_inv"].cpu().numpy()
+    assert (fin >= 0).all()
