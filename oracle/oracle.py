@@ -41,29 +41,39 @@ _lib = None
 
 
 def lib():
+    """The oracle library.  PICARD_ORACLE_LIB names another build of the same source
+    (the mutation tests point it at deliberately broken copies)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB):
-            build(force=False)
-        L = C.CDLL(LIB)
-        P = C.POINTER(_Problem)
-        vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
-        L.orc_serial.argtypes = [P, vp, vp, vp, vp, vp]
-        L.orc_eval_at.argtypes = [P, vp, vp, vp, vp, vp]
-        L.orc_alg1.argtypes = [P, vp, i64, vp, i32, vp, vp, vp]
-        L.orc_picard_runs.argtypes = [P, vp, vp, i32, vp, vp, vp, vp]
-        L.orc_reinforce.argtypes = [P, vp, vp, vp, vp, vp]
-        L.orc_mlp_scores.argtypes = [P, i32, vp, vp]
-        L.orc_philox4x32_10.argtypes = [vp, vp, vp]
-        L.orc_philox4x32_10.restype = None
-        L.orc_uniform.argtypes = [C.c_uint64, i32, i64, i32]
-        L.orc_uniform.restype = C.c_double
-        L.orc_gumbel.argtypes = [C.c_uint64, i32, i64, i32]
-        L.orc_gumbel.restype = C.c_double
-        L.orc_param_count.argtypes = [i32, i32, i32]
-        L.orc_param_count.restype = C.c_int64
-        _lib = L
+        path = os.environ.get("PICARD_ORACLE_LIB")
+        if not path:
+            if not os.path.exists(LIB):
+                build(force=False)
+            path = LIB
+        _lib = load(path)
     return _lib
+
+
+def load(path: str):
+    """Load a build of picard_oracle.c and declare its entry points."""
+    L = C.CDLL(path)
+    P = C.POINTER(_Problem)
+    vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    L.orc_serial.argtypes = [P, vp, vp, vp, vp, vp]
+    L.orc_eval_at.argtypes = [P, vp, vp, vp, vp, vp]
+    L.orc_alg1.argtypes = [P, vp, i64, vp, i32, vp, vp, vp]
+    L.orc_picard_runs.argtypes = [P, vp, vp, i32, vp, vp, vp, vp]
+    L.orc_reinforce.argtypes = [P, vp, vp, vp, vp, vp]
+    L.orc_mlp_scores.argtypes = [P, i32, vp, vp]
+    L.orc_philox4x32_10.argtypes = [vp, vp, vp]
+    L.orc_philox4x32_10.restype = None
+    L.orc_uniform.argtypes = [C.c_uint64, i32, i64, i32]
+    L.orc_uniform.restype = C.c_double
+    L.orc_gumbel.argtypes = [C.c_uint64, i32, i64, i32]
+    L.orc_gumbel.restype = C.c_double
+    L.orc_param_count.argtypes = [i32, i32, i32]
+    L.orc_param_count.restype = C.c_int64
+    return L
 
 
 def _ptr(a: Optional[np.ndarray]):

@@ -63,12 +63,12 @@ def test_scores_match_torch(oracle, L):
 def _numpy_learned_serial(oracle, inst):
     E, W1, b1, W2, b2, w3, b3 = _unpack(inst.params, inst.R, L=inst.n_hidden_layers)
     x = inst.x0[0].astype(np.int64).copy()
-    acts, z1s = [], []
+    acts, z1s, z2s = [], [], []
     for t in range(inst.total_orders):
         k, r, q = inst.sku[t], inst.region[t], inst.qty[t]
         feas = np.nonzero(x[k] > 0)[0]
         if feas.size == 0:
-            acts.append(-1); z1s.append(-np.inf); continue
+            acts.append(-1); z1s.append(-np.inf); z2s.append(-np.inf); continue
         f = np.stack([inst.cost[0, feas, r].astype(np.float64), np.log1p(x[k, feas]),
                       *[np.full(feas.size, E[r, i]) for i in range(EMB_DIM)]], axis=1)
         h = np.maximum(f @ W1.T + b1, 0.0)
@@ -80,8 +80,9 @@ def _numpy_learned_serial(oracle, inst):
         i = int(np.argmax(z))  # first maximum: lowest index on exact ties
         a = int(feas[i])
         acts.append(a); z1s.append(z[i])
+        z2s.append(np.sort(z)[-2] if z.size > 1 else -np.inf)
         x[k, a] -= min(q, x[k, a])
-    return np.array(acts), np.array(z1s)
+    return np.array(acts), np.array(z1s), np.array(z2s)
 
 
 @pytest.mark.parametrize("seed", range(6))
@@ -89,16 +90,23 @@ def test_learned_serial_matches_numpy(oracle, seed):
     inst = random_tiny(seed + 40, N=6, K=3, R=4, T=80, qmax=2, inv_max=5, mlp=True,
                        n_hidden_layers=1 + seed % 2)
     r = oracle.serial(inst)
-    a, z1 = _numpy_learned_serial(oracle, inst)
+    a, z1, z2 = _numpy_learned_serial(oracle, inst)
     np.testing.assert_array_equal(r["actions"], a)
     m = a >= 0
     np.testing.assert_allclose(r["z1"][m], z1[m], rtol=1e-12, atol=1e-12)
+    # the runner-up score (the near-tie margin z1 - z2 is what parity tests key on)
+    np.testing.assert_array_equal(np.isinf(r["z2"]), np.isinf(z2))
+    f = np.isfinite(z2)
+    np.testing.assert_allclose(r["z2"][f], z2[f], rtol=1e-12, atol=1e-12)
 
 
 def test_uniform_is_binary32_exact_and_uniform(oracle):
     us = np.array([oracle.uniform(12345, 3, t, w) for t in range(2000) for w in range(4)])
     assert ((us > 0) & (us < 1)).all()
     np.testing.assert_array_equal(us, us.astype(np.float32).astype(np.float64))
+    # each value is the centre of one of 2^23 equal bins, so U and 1 - U are equally
+    # likely and neither 0 nor 1 can occur
+    np.testing.assert_array_equal(np.modf(us * 2.0**23)[0], 0.5)
     from scipy import stats
     assert stats.kstest(us, "uniform").pvalue > 1e-3
 

@@ -1,0 +1,113 @@
+"""Mutation check of the oracle's pins.
+
+Each case plants one plausible mistake in a copy of the oracle's C source (on the CPU,
+in a temporary directory), builds it, and runs the committed oracle pins against that
+build.  The pins must fail (pytest exit status 1: an assertion, not a crash).  A case
+that survives names a mistake the pins cannot see.
+
+The mistakes follow the passages they would break: the greedy rule and the fulfillment
+transition (Section 3 and 3.1), Algorithm 1's per-pass state reset and cached actions,
+the run-form entry state, the noise (Philox4x32-10 and the Gumbel-max rule), the MLP
+score (Section 3.2) and the REINFORCE gradient.
+"""
+import os
+import subprocess
+import sys
+import tempfile
+from concurrent.futures import ThreadPoolExecutor
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "picard_oracle.c")
+PINS = [os.path.join(ROOT, "tests", f) for f in
+        ("test_oracle_serial.py", "test_oracle_picard.py", "test_oracle_mlp.py")]
+
+# (name, text in the oracle, replacement)
+MUTANTS = [
+    ("greedy_tie_takes_last",
+     "if (best == LOST || c < best_cost)", "if (best == LOST || c <= best_cost)"),
+    ("greedy_empty_warehouse_feasible",
+     "if (x[w] <= 0) continue;\n            int32_t c",
+     "if (x[w] < 0) continue;\n            int32_t c"),
+    ("transition_ships_full_quantity",
+     "int32_t sh = x[a] < q ? x[a] : q;", "int32_t sh = q;"),
+    ("transition_ships_one_unit", "x[a] -= sh;", "x[a] -= sh > 0 ? 1 : 0;"),
+    ("alg1_state_not_reset_per_process",
+     "memcpy(x, P->x0, sizeof(int32_t) * (size_t)KN); /* s_1^{k,m} = s_1 */",
+     "if (proc == 0) memcpy(x, P->x0, sizeof(int32_t) * (size_t)KN);"),
+    ("alg1_own_steps_not_recorded", "next[t] = a; /* alpha^k_t",
+     "next[t] = prev[t]; /* alpha^k_t"),
+    ("runs_consumption_from_current_pass",
+     "if (prev[t] != LOST) E[prev[t]] += P->qty[t];",
+     "if (next[t] != LOST) E[next[t]] += P->qty[t];"),
+    ("runs_consumption_counts_orders",
+     "if (prev[t] != LOST) E[prev[t]] += P->qty[t];",
+     "if (prev[t] != LOST) E[prev[t]] += 1;"),
+    ("philox_multiplier_swapped",
+     "uint64_t p0 = (uint64_t)M0 * c0;", "uint64_t p0 = (uint64_t)M1 * c0;"),
+    ("philox_nine_rounds", "round < 10", "round < 9"),
+    ("philox_key_not_bumped", "k1 += W1;", "k1 += 0;"),
+    ("uniform_left_edge_of_bin", "(double)(u >> 9) + 0.5", "(double)(u >> 9) + 0.0"),
+    ("uniform_same_word_for_all", "uint32_t u = out[w & 3];", "uint32_t u = out[0];"),
+    ("gumbel_sign_flipped", "return -log(-log(", "return log(-log("),
+    ("learned_runner_up_dropped", "else if (z > top2) top2 = z;", ";"),
+    ("mlp_log_instead_of_log1p", "f[1] = log1p(inv);", "f[1] = log(inv + 2.0);"),
+    ("mlp_embedding_of_region_zero", "f[2 + i] = m->E[r * 16 + i];",
+     "f[2 + i] = m->E[i];"),
+    ("mlp_first_relu_dropped", "h1[j] = acc > 0.0 ? acc : 0.0;", "h1[j] = acc;"),
+    ("mlp_second_layer_transposed", "acc += m->W2[j * H + i] * h1[i];",
+     "acc += m->W2[i * H + j] * h1[i];"),
+    ("mlp_output_bias_dropped", "double s = m->b3;", "double s = 0.0;"),
+    ("param_pack_without_b2", "n += (int64_t)H * H + H;", "n += (int64_t)H * H;"),
+    ("reinforce_logp_without_normaliser", "const double lp = s[a] - lse;",
+     "const double lp = s[a] - mx;"),
+    ("reinforce_score_sign", "(w == a ? 1.0 : 0.0) - p", "(w == a ? 1.0 : 0.0) + p"),
+    ("reinforce_embedding_grad_offset", "m.W1[j * 18 + 2 + i] * dp1[j]",
+     "m.W1[j * 18 + 1 + i] * dp1[j]"),
+    ("reinforce_w2_grad_transposed", "gW2[j * H + i] += dp2[j] * h1[i];",
+     "gW2[i * H + j] += dp2[j] * h1[i];"),
+    ("reinforce_second_relu_mask_dropped", "dp2[j] = pre2[j] > 0.0 ? dh[j] : 0.0;",
+     "dp2[j] = dh[j];"),
+    ("reinforce_state_not_advanced",
+     "        transition(xk, a, P->qty[t]);\n    }\n    if (objective)",
+     "    }\n    if (objective)"),
+    ("eval_at_state_not_advanced",
+     "        transition(xk, a, P->qty[t]);\n    }\n    free(x);\n    mlp_free(&m);\n    return rc;",
+     "    }\n    free(x);\n    mlp_free(&m);\n    return rc;"),
+]
+
+
+def _run_pins_against(name, old, new, workdir):
+    src = open(SRC).read()
+    assert src.count(old) == 1, f"{name}: target text must occur once in the oracle"
+    csrc = os.path.join(workdir, name + ".c")
+    so = os.path.join(workdir, name + ".so")
+    open(csrc, "w").write(src.replace(old, new))
+    subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-w", csrc,
+                           "-o", so, "-lm"])
+    env = dict(os.environ, PICARD_ORACLE_LIB=so)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-m", "not gpu",
+                        "-p", "no:cacheprovider", *PINS],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    tail = "\n".join(r.stdout.splitlines()[-6:])
+    return r.returncode, tail
+
+
+@pytest.mark.slow
+def test_every_planted_mistake_fails_a_pin():
+    with tempfile.TemporaryDirectory() as d:
+        with ThreadPoolExecutor(max_workers=4) as pool:
+            futs = {name: pool.submit(_run_pins_against, name, old, new, d)
+                    for name, old, new in MUTANTS}
+            results = {name: f.result() for name, f in futs.items()}
+    survivors = {n: t for n, (rc, t) in results.items() if rc == 0}
+    crashed = {n: (rc, t) for n, (rc, t) in results.items() if rc not in (0, 1)}
+    assert not survivors, f"mistakes no pin catches: {sorted(survivors)}"
+    assert not crashed, f"pins crashed instead of failing: {crashed}"
+
+
+def test_mutant_targets_exist():
+    src = open(SRC).read()
+    for name, old, _ in MUTANTS:
+        assert src.count(old) == 1, name
