@@ -25,21 +25,39 @@ sys.path.insert(0, ROOT)
 METRIC = "simulated orders/sec/GPU, Picard vs serial GPU sweep; iterations to converge"
 HBM_PEAK_GBS = 8000.0
 DEFAULT_WORKLOAD = "greedy_n100_k1e5_t1e6"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_walk_greedy_n100_k1e5_t1e6.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_walk_greedy_n100_k1e5_t1e6_traffic.md")
 WALK_SOURCE = os.path.join(ROOT, "paper_2406_01939_amd", "csrc", "greedy.hip")
 
 
 def _traffic():
     """HBM bytes per walk launch from the committed rocprofv3 counter summary, if the walk
-    kernel's source is unchanged since the counters were taken; else None."""
+    kernel's source is unchanged since the counters were taken; else None.  The summary
+    carries `key: value` lines, among them `source_sha256` and `bytes_per_launch`."""
     try:
-        rec = json.load(open(TRAFFIC_FILE))
+        rec = {}
+        for line in open(TRAFFIC_FILE):
+            k, sep, v = line.partition(":")
+            if sep and k.strip() in ("source_sha256", "bytes_per_launch"):
+                rec[k.strip()] = v.strip().strip("`")
         h = hashlib.sha256(open(WALK_SOURCE, "rb").read()).hexdigest()
         if rec.get("source_sha256") != h:
             return None
-        return rec["bytes_per_launch"]
+        return float(rec["bytes_per_launch"])
     except (OSError, ValueError, KeyError):
         return None
+
+
+def copy_calibration(nbytes: int, reps: int = 3):
+    """A plain device-to-device copy of known size (the yardstick for the HBM byte
+    counters: FETCH_SIZE and WRITE_SIZE of one copy dispatch against nbytes)."""
+    import torch
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "reps": reps}))
 
 
 def cpu_baseline(inst, budget_s: float = 8.0):
@@ -73,11 +91,16 @@ def main():
     ap.add_argument("--block-len", type=int, default=0)
     ap.add_argument("--no-serial", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (counter yardstick)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
-              "sharding is described in DESIGN.md, not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the simulation "
+              "is not sharded across GPUs.", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration > 0:
+        copy_calibration(args.copy_calibration)
+        return
 
     import torch
     from paper_2406_01939_amd import api

@@ -44,6 +44,13 @@ hipError_t launch_serial_mlp(const Prob &P, const float *params, int layers, con
                              int32_t *state, int32_t *actions, int32_t *shipped, hipStream_t st);
 hipError_t launch_scores(const Prob &P, const float *params, int layers, const float *costT,
                          int b, int r, const int32_t *xrow, float *out, hipStream_t st);
+// grad.hip
+size_t grad_lds(int N, int layers);
+size_t grad_part_bytes(int n_wg, int R, int layers);
+hipError_t launch_grad(const Prob &P, const Plan &L, const float *params, int layers,
+                       const float *costT, const float *adv, float *logp_sorted, double *part,
+                       int n_wg, float *grad, double *objective_dev, float *logp_out,
+                       hipStream_t st);
 } // namespace pk
 
 using namespace pk;
@@ -72,6 +79,8 @@ pk_status fail(pk_status s, const char *fmt, ...)
 
 constexpr int DEFAULT_BLOCK_GREEDY = 1024;
 constexpr int DEFAULT_BLOCK_MLP = 256;
+constexpr int GRAD_BLOCK = 1024;  // run length of the gradient's state reconstruction
+constexpr int GRAD_MAX_WG = 512;  // workgroups (and FP64 partial sets) of the gradient
 constexpr int MIN_AUTOTUNE_BLOCK = 64;
 
 struct Dims {
@@ -181,6 +190,8 @@ void carve_plan(Carver &c, const Dims &d, const pk_policy *po, int B, Plan *L,
     p.fr[0] = c.take<int32_t>(s.n_seg_max);
     p.fr[1] = c.take<int32_t>(s.n_seg_max);
     p.split_list = c.take<int32_t>(s.n_split_max);
+    p.rd = c.take<RunDesc>(s.n_sr_max);
+    p.active = c.take<int32_t>(s.n_split_max);
     p.u = c.take<int32_t>(s.n_split_max * d.N);
     p.E = c.take<int32_t>(s.n_split_max * d.N);
     if (po->kind == PK_POLICY_MLP)
@@ -206,6 +217,18 @@ size_t picard_bytes(const Dims &d, const pk_policy *po, int B)
     int64_t *to;
     void *ss;
     carve_plan(c, d, po, B, nullptr, &to, &ss);
+    return c.off + 256;
+}
+
+size_t grad_bytes(const Dims &d, const pk_policy *po)
+{
+    Carver c{nullptr};
+    int64_t *to;
+    void *ss;
+    carve_plan(c, d, po, GRAD_BLOCK, nullptr, &to, &ss);
+    c.take<float>(d.total);
+    c.take<char>((int64_t)grad_part_bytes(GRAD_MAX_WG, d.R, po->n_hidden_layers));
+    c.take<double>(1);
     return c.off + 256;
 }
 
@@ -252,6 +275,75 @@ int num_cus()
         return 256;
     return n;
 }
+
+// ---------------------------------------------------------------- captured pass graphs
+// The instantiated graph of U passes is kept per thread and reused while every kernel
+// argument is unchanged (same problem, plan and output buffers).
+struct GraphKey {
+    unsigned char bytes[sizeof(Prob) + sizeof(Plan) + sizeof(pk_policy) + 64];
+    void set(const Prob &P, const Plan &L, const pk_policy *po, const int32_t *fin, bool hi,
+             int grid, int U, int nseg)
+    {
+        memset(bytes, 0, sizeof bytes);
+        size_t o = 0;
+        memcpy(bytes + o, &P, sizeof P); o += sizeof P;
+        memcpy(bytes + o, &L, sizeof L); o += sizeof L;
+        memcpy(bytes + o, po, sizeof *po); o += sizeof *po;
+        const int64_t extra[6] = {(int64_t)(uintptr_t)fin, hi, grid, U, nseg, 0};
+        memcpy(bytes + o, extra, sizeof extra);
+    }
+    bool operator==(const GraphKey &k) const { return memcmp(bytes, k.bytes, sizeof bytes) == 0; }
+};
+
+struct GraphCache {
+    bool valid = false;
+    int device = -1;
+    GraphKey key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap = nullptr;
+    ~GraphCache() { clear(); }
+    void clear()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        valid = false;
+    }
+    template <typename F> pk_status get(const GraphKey &k, F enqueue, hipGraphExec_t *out)
+    {
+        int dev = 0;
+        HIP_TRY(hipGetDevice(&dev));
+        if (valid && dev == device && k == key) {
+            *out = exec;
+            return PK_OK;
+        }
+        clear();
+        if (cap && dev != device) {
+            (void)hipStreamDestroy(cap);
+            cap = nullptr;
+        }
+        if (!cap) HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        device = dev;
+        HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+        pk_status e = enqueue(cap);
+        hipGraph_t g = nullptr;
+        const hipError_t ce = hipStreamEndCapture(cap, &g);
+        if (e != PK_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return e;
+        }
+        if (ce != hipSuccess) return fail(PK_ERR_HIP, "graph capture failed: %s", hipGetErrorString(ce));
+        graph = g;
+        HIP_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        key = k;
+        valid = true;
+        *out = exec;
+        return PK_OK;
+    }
+};
+thread_local GraphCache g_graph;
 
 pk_status picard_run(const pk_problem *problem, const Dims &d, const pk_policy *policy,
                      const pk_picard_opts &o, int B, void *ws, size_t ws_bytes,
@@ -302,27 +394,51 @@ pk_status picard_run(const pk_problem *problem, const Dims &d, const pk_policy *
     if (d.total == 0) {
         done = 1;
     }
+    // one pass = entry scan + walk (the walk's last workgroup ends the pass); the kernels
+    // return at once after convergence, so U passes are enqueued per host check
+    auto enqueue_pass = [&](hipStream_t s2, bool with_events) -> pk_status {
+        HIP_TRY(launch_scan_entry(P, L, (int)sz.n_seg_max, !has_init, s2));
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (with_events) {
+            HIP_TRY(hipEventCreate(&e0));
+            HIP_TRY(hipEventCreate(&e1));
+            HIP_TRY(hipEventRecord(e0, s2));
+        }
+        if (policy->kind == PK_POLICY_MLP)
+            HIP_TRY(launch_walk_mlp(P, L, policy->params, policy->n_hidden_layers, L.costT,
+                                    final_inv, has_init, num_cus() * 4, s2));
+        else
+            HIP_TRY(launch_walk_greedy(P, L, L.pos, final_inv, has_init, grid, s2));
+        if (with_events) {
+            HIP_TRY(hipEventRecord(e1, s2));
+            evs.push_back(e0);
+            evs.push_back(e1);
+        }
+        return PK_OK;
+    };
+    // U passes captured once as a HIP graph and replayed (not when timing each launch)
+    hipGraphExec_t gexec = nullptr;
+    if (!done && U > 1 && !timing && max_passes >= U) {
+        GraphKey key;
+        key.set(P, L, policy, final_inv, has_init, grid, U, (int)sz.n_seg_max);
+        pk_status gs = g_graph.get(key, [&](hipStream_t cs) -> pk_status {
+            for (int i = 0; i < U; ++i) {
+                pk_status e = enqueue_pass(cs, false);
+                if (e != PK_OK) return e;
+            }
+            return PK_OK;
+        }, &gexec);
+        if (gs != PK_OK) return gs;
+    }
     while (!done && launched < max_passes) {
         const int u = std::min(U, max_passes - launched);
-        for (int i = 0; i < u; ++i) {
-            HIP_TRY(launch_scan_entry(P, L, (int)sz.n_seg_max, !has_init, st));
-            hipEvent_t e0 = nullptr, e1 = nullptr;
-            if (timing) {
-                HIP_TRY(hipEventCreate(&e0));
-                HIP_TRY(hipEventCreate(&e1));
-                HIP_TRY(hipEventRecord(e0, st));
+        if (gexec && u == U) {
+            HIP_TRY(hipGraphLaunch(gexec, st));
+        } else {
+            for (int i = 0; i < u; ++i) {
+                pk_status e = enqueue_pass(st, timing);
+                if (e != PK_OK) return e;
             }
-            if (policy->kind == PK_POLICY_MLP)
-                HIP_TRY(launch_walk_mlp(P, L, policy->params, policy->n_hidden_layers, L.costT,
-                                        final_inv, has_init, num_cus() * 4, st));
-            else
-                HIP_TRY(launch_walk_greedy(P, L, L.pos, final_inv, has_init, grid, st));
-            if (timing) {
-                HIP_TRY(hipEventRecord(e1, st));
-                evs.push_back(e0);
-                evs.push_back(e1);
-            }
-            HIP_TRY(launch_pass_end(L, st));
         }
         launched += u;
         HIP_TRY(hipMemcpyAsync(hc, L.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
@@ -501,6 +617,7 @@ pk_status pk_workspace_size(const pk_problem *problem, const pk_policy *policy,
     if (policy->kind == PK_POLICY_MLP && !(opts && opts->block_len > 0)) B = MIN_AUTOTUNE_BLOCK;
     *bytes = std::max(picard_bytes(d, policy, B), serial_bytes(d)) +
              (((size_t)std::max<int64_t>(d.total, 1) * 4 + 255) & ~(size_t)255) + 512;
+    if (policy->kind == PK_POLICY_MLP) *bytes = std::max(*bytes, grad_bytes(d, policy));
     return PK_OK;
 }
 
@@ -571,9 +688,57 @@ pk_status pk_policy_grad(const pk_problem *problem, const pk_policy *policy,
                          int32_t validate, void *stream)
 {
     g_err.clear();
-    (void)problem; (void)policy; (void)actions; (void)advantages; (void)logp; (void)grad;
-    (void)objective; (void)ws; (void)ws_bytes; (void)validate; (void)stream;
-    return fail(PK_ERR_UNSUPPORTED, "policy gradient not built yet");
+    Dims d;
+    pk_status s = check_problem(problem, &d);
+    if (s != PK_OK) return s;
+    if ((s = check_policy(policy)) != PK_OK) return s;
+    if (policy->kind != PK_POLICY_MLP) return fail(PK_ERR_INVALID_ARG, "policy_grad needs the MLP policy");
+    if (d.total > 0 && (!actions || !advantages))
+        return fail(PK_ERR_INVALID_ARG, "actions/advantages is NULL");
+    if (!ws || ws_bytes < grad_bytes(d, policy))
+        return fail(PK_ERR_WORKSPACE, "workspace too small: need %zu bytes, got %zu",
+                    grad_bytes(d, policy), ws_bytes);
+    hipStream_t st = (hipStream_t)stream;
+    Carver c{align_ws(ws)};
+    Plan L;
+    int64_t *to;
+    void *scratch;
+    carve_plan(c, d, policy, GRAD_BLOCK, &L, &to, &scratch);
+    float *logp_sorted = c.take<float>(d.total);
+    double *part = c.take<double>((int64_t)grad_part_bytes(GRAD_MAX_WG, d.R, policy->n_hidden_layers) / 8);
+    double *obj_dev = c.take<double>(1);
+    const Sizes sz = plan_sizes(d, GRAD_BLOCK);
+    HIP_TRY(hipMemcpyAsync(to, problem->traj_offsets, (d.n_traj + 1) * sizeof(int64_t),
+                           hipMemcpyHostToDevice, st));
+    Prob P = make_prob(problem, d, to);
+    HIP_TRY(setup_ctl(L, d.n_traj, 1, st));
+    const int n_wg = std::min(GRAD_MAX_WG, std::max(1, num_cus() * 2));
+    if (d.total > 0) {
+        // states of the fixed actions: the actions are the cache, its consumption scanned
+        HIP_TRY(setup_plan(P, L, actions, validate, true, (int32_t)sz.n_seg_max, scratch, st));
+        HIP_TRY(setup_costT(P, L.costT, st));
+        HIP_TRY(launch_consume(P, L, sz.n_split_max, st));
+        HIP_TRY(launch_scan_entry(P, L, (int)sz.n_seg_max, false, st));
+        HIP_TRY(launch_grad(P, L, policy->params, policy->n_hidden_layers, L.costT, advantages,
+                            logp_sorted, part, n_wg, grad, obj_dev, logp, st));
+    } else {
+        HIP_TRY(hipMemsetAsync(obj_dev, 0, sizeof(double), st));
+        if (grad)
+            HIP_TRY(hipMemsetAsync(grad, 0,
+                                   ((size_t)d.R * 16 + 64 * 18 + 64 + 64 + 1 +
+                                    (policy->n_hidden_layers == 2 ? 64 * 64 + 64 : 0)) * 4, st));
+    }
+    Ctl *hc = g_pinned.get();
+    if (!hc) return fail(PK_ERR_HIP, "pinned host allocation failed");
+    double objv = 0.0;
+    HIP_TRY(hipMemcpyAsync(hc, L.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(&objv, obj_dev, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (objective) *objective = objv;
+    if (d.total > 0 && hc->error)
+        return fail(PK_ERR_INVALID_ARG, "input or action out of range / infeasible (code %d)",
+                    hc->error);
+    return PK_OK;
 }
 
 pk_status pk_policy_scores(const pk_problem *problem, const pk_policy *policy, int32_t traj,

@@ -96,15 +96,24 @@ __device__ __forceinline__ int least_key(const KeyT *row, const uint64_t *F, int
 // Choices: the wave keeps the set of warehouses with stock as a bitmask F and memoises
 // each region's choice; a memo is recomputed (least key over F) only when its warehouse
 // has emptied.  For long runs every region's memo is filled up front.
-// Orders: a 128-order window (this chunk and the next) lives in registers; after a
-// partial commit it is shifted across lanes, so only the part past the window is read
-// again.  Every global load and store in the chunk loop is issued unconditionally
-// (clamped addresses for loads, masked-off lanes store to `sink`), so waiting for a
-// prefetched register never waits for the stores issued after it.
+// Orders: the run is read in 64-order chunks into registers, two chunks ahead of use,
+// and each chunk is put into a 128-entry ring in LDS when the walk reaches it.  A step
+// reads its 64 orders from the ring at any offset, so a partial commit costs no memory
+// round trip, and a chunk's loads have at least one whole step to arrive.  The next
+// run's descriptor is loaded while the current run is walked.
 // The key table of the run's trajectory is read from LDS (one copy per workgroup for a
 // single trajectory, one per wave for small tables) or from global memory.
 // Per wave LDS: x[N] stock, tot[N] chunk demand, cons[N] run consumption (unclamped, for
-// u), bw[R] memo, count of warehouses with stock, F[ceil(N/64)].
+// u), bw[R] memo, count of warehouses with stock, F[ceil(N/64)], ring[128] of
+// (region, qty, cached action).
+template <typename KeyT> __host__ __device__ inline size_t walk_wave_bytes(int N, int R, int mode)
+{
+    const size_t tb = (size_t)tab_stride<KeyT>(N, R) * sizeof(KeyT);
+    const size_t ints = ((size_t)(3 * N + R + 2) * 4 + 15) & ~(size_t)15;
+    const size_t f = ((size_t)8 * ((N + 63) / 64) + 15) & ~(size_t)15;
+    return (mode == 1 ? tb : 0) + ints + f + 128 * sizeof(int4);
+}
+
 template <typename KeyT, int TABMODE> // 0: global table, 1: per-wave LDS, 2: per-WG LDS
 __global__ __launch_bounds__(256) void k_walk_greedy(Prob P, Plan L, const KeyT *key_g,
                                                      int32_t *final_inv, int has_init,
@@ -117,9 +126,9 @@ __global__ __launch_bounds__(256) void k_walk_greedy(Prob P, Plan L, const KeyT 
     const int npad = tab_npad<KeyT>(N);
     const size_t tab_bytes = (size_t)tab_stride<KeyT>(N, R) * sizeof(KeyT);
     const size_t ints_bytes = ((size_t)(3 * N + R + 2) * 4 + 15) & ~(size_t)15;
-    const size_t wave_bytes = ((TABMODE == 1 ? tab_bytes : 0) + ints_bytes + 8 * nw + 15) &
-                              ~(size_t)15; // keeps every wave's table 16-byte aligned
-    unsigned char *wb = smem + (TABMODE == 2 ? tab_bytes : 0) + wave * wave_bytes;
+    const size_t f_bytes = ((size_t)8 * nw + 15) & ~(size_t)15;
+    unsigned char *wb = smem + (TABMODE == 2 ? tab_bytes : 0) +
+                        wave * walk_wave_bytes<KeyT>(N, R, TABMODE);
     KeyT *wtab = (KeyT *)wb;
     const size_t ints_off = TABMODE == 1 ? tab_bytes : 0;
     int32_t *x = (int32_t *)(wb + ints_off);
@@ -128,6 +137,7 @@ __global__ __launch_bounds__(256) void k_walk_greedy(Prob P, Plan L, const KeyT 
     int32_t *bw = cons + N;
     int32_t *nfeas = bw + R;
     uint64_t *F = (uint64_t *)(wb + ints_off + ints_bytes);
+    int4 *ring = (int4 *)(wb + ints_off + ints_bytes + f_bytes);
     Ctl *ctl = L.ctl;
     if (ctl->done) return;
     if (TABMODE == 2) { // one trajectory: its table, once per workgroup
@@ -139,31 +149,33 @@ __global__ __launch_bounds__(256) void k_walk_greedy(Prob P, Plan L, const KeyT 
     }
     int tab_b = -1;
     const int pass = ctl->pass;
-    const int32_t *fprev = L.fr[(pass - 1) & 1];
     int32_t *fcur = L.fr[pass & 1];
-    const bool first = pass == 1;
-    const bool all = first || L.no_frontier;
-    const int n_items = all ? ctl->n_sr : ctl->n_split;
-    const bool need_E = !first || has_init;
+    // pass 1 (and the no-frontier mode) walks every run; later passes walk the runs past
+    // each SKU's frontier, listed by the entry scan
+    const bool all = pass == 1 || L.no_frontier;
+    const int n_items = all ? ctl->n_sr : ctl->n_active;
+    const bool need_E = pass > 1 || has_init;
+    int lcp_b = -1; // last trajectory this wave marked as changed in this pass
     unsigned long long n_orders = 0, n_runs = 0, n_changed = 0, n_bytes = 0;
 
     // static round-robin over the runs (no shared work counter: one hot address)
     const int n_waves = gridDim.x * (blockDim.x / WAVE);
-    for (int item = blockIdx.x * (blockDim.x / WAVE) + wave; item < n_items; item += n_waves) {
-        const int s = all ? item : L.split_list[item];
-        const int g = L.sr_seg[s];
-        const int s0 = L.seg_sr0[g];
-        const int j = s - s0;
-        if (!all) {
-            const int32_t f = fprev[g];
-            if (f == FR_NONE || j <= f) continue;
-        }
-        const int nsr = L.seg_sr0[g + 1] - s0;
-        const int lo = L.sr_lo[s], hi = L.sr_lo[s + 1];
-        const int key = L.seg_key[g];
+    int item = blockIdx.x * (blockDim.x / WAVE) + wave;
+    RunDesc d = {};
+    if (item < n_items) d = L.rd[all ? item : L.active[item]];
+    for (; item < n_items; item += n_waves) {
+        const int lo = d.lo, hi = d.hi, key = d.key, g = d.g, j = d.j, nsr = d.nsr;
+        const int uidx = d.uidx;
         const int b = key / P.K;
+        const int nxt = item + n_waves;
+        const int s_next = nxt < n_items ? (all ? nxt : L.active[nxt]) : -1;
+        // the run's first two chunks (loads clamped into the run)
+        const int nch = (hi - lo + WAVE - 1) / WAVE;
+        int ia = lo + lane < hi ? lo + lane : hi - 1;
+        int ra = L.s_region[ia], qa = L.s_qty[ia], oa = L.s_alpha[ia];
+        int ib = lo + WAVE + lane < hi ? lo + WAVE + lane : hi - 1;
+        int rb = L.s_region[ib], qb = L.s_qty[ib], ob = L.s_alpha[ib];
         const int32_t *x0row = P.x0 + (int64_t)key * N;
-        const int uidx = L.sr_uidx[s];
         const int32_t *Erow = (need_E && j > 0) ? L.E + (int64_t)uidx * N : nullptr;
         const KeyT *tab;
         if (TABMODE == 0) {
@@ -180,11 +192,6 @@ __global__ __launch_bounds__(256) void k_walk_greedy(Prob P, Plan L, const KeyT 
         } else {
             tab = (const KeyT *)smem;
         }
-        // order window: this chunk (positions lo + lane) and the next (lo + 64 + lane)
-        int idx = lo + lane < hi ? lo + lane : hi - 1;
-        int r = L.s_region[idx], q = L.s_qty[idx], old = L.s_alpha[idx];
-        idx = lo + WAVE + lane < hi ? lo + WAVE + lane : hi - 1;
-        int nr = L.s_region[idx], nq = L.s_qty[idx], nold = L.s_alpha[idx];
         int nf = 0;
         for (int k = 0; k < nw; ++k) {
             const int w = k * WAVE + lane;
@@ -201,10 +208,17 @@ __global__ __launch_bounds__(256) void k_walk_greedy(Prob P, Plan L, const KeyT 
             nf += __popcll(m);
         }
         if (lane == 0) *nfeas = nf;
+        ring[lane] = make_int4(ra, qa, oa, 0); // chunk 0
+        // next run's descriptor, and chunk 2 into the slot chunk 0 has left
+        RunDesc dn = {};
+        if (s_next >= 0) dn = L.rd[s_next];
+        ia = lo + 2 * WAVE + lane < hi ? lo + 2 * WAVE + lane : hi - 1;
+        ra = L.s_region[ia]; qa = L.s_qty[ia]; oa = L.s_alpha[ia];
+        int cw = 1; // chunks in the ring
         wave_sync();
         if (hi - lo >= 2 * WAVE) { // long run: every region's choice up front
-            for (int rb = 0; rb < R; rb += WAVE) {
-                const int rr = rb + lane;
+            for (int rb0 = 0; rb0 < R; rb0 += WAVE) {
+                const int rr = rb0 + lane;
                 const bool mine = rr < R;
                 const int c = least_key<KeyT>(tab + (int64_t)(mine ? rr : 0) * npad, F, npad, mine);
                 if (mine) bw[rr] = c;
@@ -216,8 +230,26 @@ __global__ __launch_bounds__(256) void k_walk_greedy(Prob P, Plan L, const KeyT 
         bool changed = false;
         int p = lo;
         while (p < hi) {
+            const int off = p - lo;
+            // the step reads positions off .. off+63: chunks up to (off + 63) / 64
+            const int need_c = (off + WAVE - 1) / WAVE + 1 < nch ? (off + WAVE - 1) / WAVE + 1 : nch;
+            if (cw < need_c) { // at most one new chunk per step (a step advances <= 64)
+                const int pc = lo + (cw + 2) * WAVE + lane;
+                const int ic = pc < hi ? pc : hi - 1;
+                if (cw & 1) {
+                    ring[WAVE + lane] = make_int4(rb, qb, ob, 0);
+                    rb = L.s_region[ic]; qb = L.s_qty[ic]; ob = L.s_alpha[ic];
+                } else {
+                    ring[lane] = make_int4(ra, qa, oa, 0);
+                    ra = L.s_region[ic]; qa = L.s_qty[ic]; oa = L.s_alpha[ic];
+                }
+                ++cw;
+                wave_sync();
+            }
             const int n = hi - p < WAVE ? hi - p : WAVE;
             const bool act = lane < n;
+            const int4 e = ring[(off + lane) & (2 * WAVE - 1)];
+            const int r = act ? e.x : 0, q = act ? e.y : 1, old = e.z;
             int a = LOST;
             if (*nfeas > 0) {
                 bool need = false;
@@ -287,28 +319,6 @@ __global__ __launch_bounds__(256) void k_walk_greedy(Prob P, Plan L, const KeyT 
             if (ne && lane == 0) *nfeas -= ne;
             wave_sync();
             p += cut;
-            // advance the window by `cut` orders
-            if (cut == WAVE) {
-                r = nr; q = nq; old = nold;
-            } else {
-                const int src = lane + cut; // 1..127
-                const int sl = src & (WAVE - 1);
-                const int r0 = __shfl(r, sl, WAVE), r1 = __shfl(nr, sl, WAVE);
-                const int q0 = __shfl(q, sl, WAVE), q1 = __shfl(nq, sl, WAVE);
-                const int o0 = __shfl(old, sl, WAVE), o1 = __shfl(nold, sl, WAVE);
-                r = src < WAVE ? r0 : r1;
-                q = src < WAVE ? q0 : q1;
-                old = src < WAVE ? o0 : o1;
-                nr = r1; nq = q1; nold = o1; // valid where lane + cut < 64 (see below)
-            }
-            // next chunk: lanes whose order is past the window are (re)loaded
-            const int np = p + WAVE + lane;
-            idx = np < hi ? np : hi - 1;
-            const int lr = L.s_region[idx], lq = L.s_qty[idx], lold = L.s_alpha[idx];
-            const bool keep = cut != WAVE && lane + cut < WAVE;
-            nr = keep ? nr : lr;
-            nq = keep ? nq : lq;
-            nold = keep ? nold : lold;
         }
         wave_sync();
         int wr = 0;
@@ -325,14 +335,17 @@ __global__ __launch_bounds__(256) void k_walk_greedy(Prob P, Plan L, const KeyT 
             if (any) {
                 atomicMin(&fcur[g], j);
                 // read first: most changed runs find these already set
-                if (L.traj_lcp[b] < pass) atomicMax(&L.traj_lcp[b], pass);
-                if (!ctl->any_changed) ctl->any_changed = 1;
+                if (b != lcp_b) { // once per trajectory and wave; read first (one hot word)
+                    if (L.traj_lcp[b] < pass) atomicMax(&L.traj_lcp[b], pass);
+                    lcp_b = b;
+                }
             }
             n_orders += hi - lo;
             n_runs += 1;
             n_bytes += 20ull * (hi - lo) + 4ull * N * (1 + (Erow ? 1 : 0) + wr);
         }
         wave_sync();
+        d = dn;
     }
     if (lane == 0 && n_runs) {
         unsigned long long *st = ctl->stat[(blockIdx.x * 4 + wave) % STAT_SLOTS];
@@ -341,6 +354,7 @@ __global__ __launch_bounds__(256) void k_walk_greedy(Prob P, Plan L, const KeyT 
         atomicAdd(&st[ST_CHANGED], n_changed);
         atomicAdd(&st[ST_BYTES], n_bytes);
     }
+    walk_finish(ctl, lcp_b >= 0);
 }
 
 // Serial sweep: one wave per trajectory walks its orders in time order.  The stock of
@@ -436,10 +450,8 @@ struct WalkCfg {
 template <typename KeyT> WalkCfg walk_cfg_t(int N, int R, int n_traj)
 {
     const size_t tb = (size_t)tab_stride<KeyT>(N, R) * sizeof(KeyT);
-    const size_t ints = ((size_t)(3 * N + R + 2) * 4 + 15) & ~(size_t)15;
-    const size_t f = 8 * (size_t)((N + 63) / 64);
-    const size_t per = (ints + f + 15) & ~(size_t)15;
-    const size_t per1 = (tb + ints + f + 15) & ~(size_t)15;
+    const size_t per = walk_wave_bytes<KeyT>(N, R, 0);
+    const size_t per1 = walk_wave_bytes<KeyT>(N, R, 1);
     if (n_traj == 1 && tb + 4 * per <= 64 * 1024) return {2, tb + 4 * per};
     if (tb <= 8 * 1024 && 4 * per1 <= 64 * 1024) return {1, 4 * per1};
     return {0, 4 * per};

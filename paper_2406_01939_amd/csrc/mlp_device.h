@@ -1,0 +1,210 @@
+// Device code of the learned policy shared by the simulation and gradient kernels:
+// Philox4x32-10 and the Gumbel noise, the MFMA scorer, argmax with runner-up.
+#pragma once
+
+#include <math.h>
+
+#include "pk_internal.h"
+
+namespace pk {
+namespace mlpdev {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------- Philox4x32-10 (SC'11)
+// Round: 32x32->64 products of counter words 0 and 2 with the round multipliers; new
+// counter (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0)); the key is
+// bumped by the Weyl constants between rounds.
+__device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int i = 0; i < 10; ++i) {
+        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// Gumbel variate of (order t of trajectory traj, warehouse w): counter (t, traj, w/4, 0),
+// word w%4; U = ((u >> 9) + 0.5) 2^-23 (exact in binary32); G = -log(-log U).
+__device__ __forceinline__ float gumbel(uint64_t seed, uint32_t traj, uint32_t t, uint32_t w)
+{
+    const uint4 o = philox10(make_uint4(t, traj, w >> 2, 0u), (uint32_t)seed,
+                             (uint32_t)(seed >> 32));
+    const uint32_t u = (w & 3) == 0 ? o.x : (w & 3) == 1 ? o.y : (w & 3) == 2 ? o.z : o.w;
+    const float U = ((float)(u >> 9) + 0.5f) * (1.0f / 8388608.0f);
+    return -logf(-logf(U));
+}
+
+// ---------------------------------------------------------------- MFMA scorer
+struct MlpLane {
+    float a1[20]; // layer 1 A operands, index t*5 + s
+    float a2[64]; // layer 2 A operands, index t*16 + s
+    float b1[16], b2[16], w3[16]; // index t*4 + v (hidden 16t + 4g + v)
+    float b3;
+    const float *E; // [R][16] in global memory
+    int two;        // two hidden layers
+};
+
+__device__ __forceinline__ void load_mlp(MlpLane &m, const float *params, int R, int layers)
+{
+    const int l = __lane_id(), i = l & 15, g = l >> 4;
+    const float *E = params;
+    const float *W1 = E + (int64_t)R * 16;
+    const float *b1 = W1 + 64 * 18;
+    const float *W2 = b1 + 64;
+    const float *b2 = W2 + 64 * 64;
+    const float *w3 = layers == 2 ? b2 + 64 : b1 + 64;
+    m.E = E;
+    m.two = layers == 2;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int s = 0; s < 5; ++s) {
+            const int k = 4 * s + g;
+            m.a1[t * 5 + s] = k < 18 ? W1[(16 * t + i) * 18 + k] : 0.0f;
+        }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            m.b1[t * 4 + v] = b1[16 * t + 4 * g + v];
+            m.w3[t * 4 + v] = w3[16 * t + 4 * g + v];
+            m.b2[t * 4 + v] = layers == 2 ? b2[16 * t + 4 * g + v] : 0.0f;
+        }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            const int h = 16 * (s >> 2) + 4 * g + (s & 3);
+            m.a2[t * 16 + s] = layers == 2 ? W2[(16 * t + i) * 64 + h] : 0.0f;
+        }
+    m.b3 = w3[64];
+}
+
+// Feature k = 4s + g of row l%16 for this lane: [cost, log1p x, E[r][0..15], 0, 0].
+__device__ __forceinline__ void lane_features(float f[5], float cost, float lx, const float *Er)
+{
+    const int g = __lane_id() >> 4;
+#pragma unroll
+    for (int s = 0; s < 5; ++s) {
+        const int k = 4 * s + g;
+        f[s] = k == 0 ? cost : k == 1 ? lx : (k < 18 ? Er[k - 2] : 0.0f);
+    }
+}
+
+// Score of row l%16 (returned in every lane of that column).
+__device__ __forceinline__ float mlp_tile(const MlpLane &m, const float f[5])
+{
+    v4f h[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < 5; ++s)
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(m.a1[t * 5 + s], f[s], acc, 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const float z = acc[v] + m.b1[t * 4 + v];
+            acc[v] = z > 0.f ? z : 0.f;
+        }
+        h[t] = acc;
+    }
+    if (m.two) {
+        v4f o[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < 16; ++s)
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(m.a2[t * 16 + s], h[s >> 2][s & 3], acc,
+                                                           0, 0, 0);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const float z = acc[v] + m.b2[t * 4 + v];
+                acc[v] = z > 0.f ? z : 0.f;
+            }
+            o[t] = acc;
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) h[t] = o[t];
+    }
+    float part = 0.f;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) part = fmaf(m.w3[t * 4 + v], h[t][v], part);
+    // sum over the four lane groups holding the same row: fixed order
+    const float p16 = __shfl_xor(part, 16, WAVE);
+    const float s01 = (__lane_id() & 16) ? p16 + part : part + p16; // (g0+g1) or (g2+g3)
+    const float p32 = __shfl_xor(s01, 32, WAVE);
+    const float tot = (__lane_id() & 32) ? p32 + s01 : s01 + p32;
+    return tot + m.b3;
+}
+
+// Combine two (best, second) pairs of perturbed scores; ties go to the lower warehouse.
+__device__ __forceinline__ void top2_merge(float &z1, int &w1, float &z2, float oz1, int ow1,
+                                           float oz2)
+{
+    const bool other = oz1 > z1 || (oz1 == z1 && ow1 < w1);
+    const float lose = other ? z1 : oz1;
+    const float sec = other ? oz2 : z2;
+    if (other) { z1 = oz1; w1 = ow1; }
+    z2 = lose > sec ? lose : sec;
+}
+
+// Scores of every warehouse of one order into zbuf (perturbed unless noise is false; -inf
+// without stock), by all waves of the workgroup: wave w takes tiles w, w + nwaves, ...
+__device__ __forceinline__ void score_order(const MlpLane &m, const float *costT_r, const float *Er,
+                                            const int32_t *x, int N, uint64_t seed, uint32_t traj,
+                                            uint32_t t, float *zbuf, float *sbuf, bool noise = true)
+{
+    const int wave = threadIdx.x / WAVE, nwaves = blockDim.x / WAVE;
+    const int lane = __lane_id();
+    const int ntiles = (N + 15) >> 4;
+    for (int tile = wave; tile < ntiles; tile += nwaves) {
+        const int w = tile * 16 + (lane & 15);
+        const bool valid = w < N;
+        const int xv = valid ? x[w] : 0;
+        float f[5];
+        lane_features(f, valid ? costT_r[w] : 0.f, log1pf((float)xv), Er);
+        const float s = mlp_tile(m, f);
+        if (lane < 16 && valid) {
+            const float z = xv > 0 ? (noise ? s + gumbel(seed, traj, t, (uint32_t)w) : s) : -INFINITY;
+            zbuf[w] = z;
+            if (sbuf) sbuf[w] = s;
+        }
+    }
+}
+
+// Argmax (with runner-up) over zbuf[0..N) by one wave.  Returns the warehouse or LOST.
+__device__ __forceinline__ int argmax_top2(const float *zbuf, int N, float &z1, float &z2)
+{
+    const int lane = __lane_id();
+    float b1 = -INFINITY, b2 = -INFINITY;
+    int w1 = 0x7fffffff;
+    for (int w = lane; w < N; w += WAVE) top2_merge(b1, w1, b2, zbuf[w], w, -INFINITY);
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        const float o1 = __shfl_xor(b1, d, WAVE);
+        const int ow = __shfl_xor(w1, d, WAVE);
+        const float o2 = __shfl_xor(b2, d, WAVE);
+        top2_merge(b1, w1, b2, o1, ow, o2);
+    }
+    z1 = b1;
+    z2 = b2;
+    return b1 == -INFINITY ? LOST : w1;
+}
+
+__device__ __forceinline__ bool near_tie(float z1, float z2)
+{
+    if (z2 == -INFINITY) return false;
+    const float a = fabsf(z1) > fabsf(z2) ? fabsf(z1) : fabsf(z2);
+    return (z1 - z2) <= 1e-5f * a;
+}
+
+} // namespace mlpdev
+} // namespace pk

@@ -16,8 +16,11 @@ namespace pk {
 
 namespace {
 
-// One workgroup per split segment (grid-stride).  Threads cover warehouses; runs are
-// scanned in order.  Runs up to the frontier are final and need no entry state.
+// One workgroup per split segment (grid-stride).  Threads cover warehouses; each thread
+// runs the scan over the segment's runs for its warehouse, 32 runs' consumption loaded
+// per batch so the loads overlap.  Runs up to the frontier are final and need no entry
+// state; their consumption only enters the prefix.  After the first pass the kernel also
+// lists the runs past the frontier (the ones the walk evaluates) in Plan::active.
 __global__ __launch_bounds__(256) void k_scan_entry(Prob P, Plan L, int skip_first_pass)
 {
     Ctl *ctl = L.ctl;
@@ -27,6 +30,10 @@ __global__ __launch_bounds__(256) void k_scan_entry(Prob P, Plan L, int skip_fir
     int32_t *fcur = L.fr[pass & 1];
     const int n = ctl->n_split_seg;
     const int N = P.N;
+    const int32_t *__restrict__ u = L.u;
+    int32_t *__restrict__ E = L.E;
+    constexpr int BATCH = 32;
+    __shared__ int32_t s_base;
     for (int i = blockIdx.x; i < n; i += gridDim.x) {
         const int g = L.split_segs[i];
         const int32_t f = L.no_frontier ? FR_ALL : fprev[g];
@@ -34,23 +41,31 @@ __global__ __launch_bounds__(256) void k_scan_entry(Prob P, Plan L, int skip_fir
         if (f == FR_NONE || (pass == 1 && skip_first_pass)) continue;
         const int s0 = L.seg_sr0[g];
         const int nsr = L.seg_sr0[g + 1] - s0;
+        if (pass > 1 && !L.no_frontier) { // list the runs this pass walks: j > f
+            const int j0 = f + 1;
+            const int cnt = nsr - j0;
+            if (cnt > 0) {
+                if (threadIdx.x == 0) s_base = atomicAdd(&ctl->n_active, cnt);
+                __syncthreads();
+                for (int k = threadIdx.x; k < cnt; k += blockDim.x) L.active[s_base + k] = s0 + j0 + k;
+                __syncthreads();
+            }
+        }
         const int jmin = f + 1 > 1 ? f + 1 : 1; // runs j > f need E_j; E_0 = 0
         const int64_t row0 = L.sr_uidx[s0];
         for (int w = threadIdx.x; w < N; w += blockDim.x) {
             int32_t acc = 0;
-            int j = 0;
-            // the prefix over frozen runs (j < jmin): loads unrolled to keep several in flight
-            for (; j + 8 <= jmin; j += 8) {
-                int32_t v[8];
+            for (int jb = 0; jb < nsr; jb += BATCH) {
+                int32_t v[BATCH];
 #pragma unroll
-                for (int k = 0; k < 8; ++k) v[k] = L.u[(row0 + j + k) * N + w];
+                for (int k = 0; k < BATCH; ++k)
+                    v[k] = jb + k < nsr ? u[(row0 + jb + k) * N + w] : 0;
 #pragma unroll
-                for (int k = 0; k < 8; ++k) acc += v[k];
-            }
-            for (; j < jmin; ++j) acc += L.u[(row0 + j) * N + w];
-            for (; j < nsr; ++j) {
-                L.E[(row0 + j) * N + w] = acc;
-                acc += L.u[(row0 + j) * N + w];
+                for (int k = 0; k < BATCH; ++k) {
+                    const int jj = jb + k;
+                    if (jj >= jmin && jj < nsr) E[(row0 + jj) * N + w] = acc;
+                    acc += v[k];
+                }
             }
         }
     }
@@ -59,17 +74,7 @@ __global__ __launch_bounds__(256) void k_scan_entry(Prob P, Plan L, int skip_fir
 __global__ void k_pass_end(Ctl *ctl)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    if (ctl->done) return;
-    if (!ctl->any_changed) {
-        ctl->done = 1;
-        ctl->passes_done = ctl->pass;
-    } else if (ctl->pass >= ctl->max_passes) {
-        ctl->done = 2;
-        ctl->passes_done = ctl->pass;
-    } else {
-        ctl->pass += 1;
-    }
-    ctl->any_changed = 0;
+    pass_end_body(ctl);
 }
 
 // u for every run of a split segment from the current cache (warm start).  One wave per

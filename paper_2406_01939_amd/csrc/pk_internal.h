@@ -36,7 +36,20 @@ struct Ctl {
     int32_t error;       // validate: nonzero if an input value was out of range
     int32_t passes_done; // pass count at convergence
     int32_t max_passes;
+    uint32_t wg_done;    // workgroups of the current walk launch that have finished
+    int32_t n_active;    // runs listed in Plan::active for the current pass
     unsigned long long stat[STAT_SLOTS][ST_N]; // summed on the host
+};
+
+// Everything a walk needs to start a run, in one 32-byte record (one load per run).
+struct RunDesc {
+    int32_t lo, hi; // sorted positions [lo, hi)
+    int32_t key;    // trajectory * K + SKU
+    int32_t g;      // segment
+    int32_t j;      // index of the run in its segment
+    int32_t nsr;    // runs in the segment
+    int32_t uidx;   // row of u/E (split segments), else -1
+    int32_t pad;
 };
 
 // Products of the per-call setup (partition and sort), all in the caller's workspace.
@@ -56,6 +69,8 @@ struct Plan {
     int32_t *sr_uidx;        // [n_sr_max] row of u/E for runs of split segments, else -1
     int32_t *seg_key;        // [n_seg_max]
     int32_t *seg_sr0;        // [n_seg_max+1] first run of each segment
+    RunDesc *rd;             // [n_sr_max] run descriptors
+    int32_t *active;         // [n_split_max] runs to walk in the current pass (after pass 1)
     int32_t *split_list;     // [n_split_max] runs of split segments, in order
     int32_t *split_segs;     // [n_seg_max] split segments
     int32_t *fr[2];          // [n_seg_max] frontier per segment, by pass parity
@@ -112,6 +127,48 @@ __device__ __forceinline__ int traj_of(const int64_t *off, int n_traj, int64_t o
         if (off[mid] <= o) lo = mid; else hi = mid;
     }
     return lo;
+}
+
+// End of a pass (one thread): a pass that changed nothing ends the iteration (Algorithm 1
+// returns); otherwise the next pass begins, unless max_passes is reached.
+__device__ __forceinline__ void pass_end_body(Ctl *ctl)
+{
+    if (ctl->done) return;
+    if (!ctl->any_changed) {
+        ctl->done = 1;
+        ctl->passes_done = ctl->pass;
+    } else if (ctl->pass >= ctl->max_passes) {
+        ctl->done = 2;
+        ctl->passes_done = ctl->pass;
+    } else {
+        ctl->pass += 1;
+    }
+    ctl->any_changed = 0;
+    ctl->n_active = 0;
+}
+
+// Called by every workgroup of a walk launch as its last action, with each wave's "some
+// run of mine changed" flag: the workgroup raises the pass's change flag once, and the
+// workgroup that finishes last (ticket) ends the pass.  Release fence before the ticket,
+// acquire fence in the last workgroup, so the other workgroups' flags are visible to it.
+__device__ __forceinline__ void walk_finish(Ctl *ctl, bool wave_changed)
+{
+    __shared__ int32_t s_changed;
+    if (threadIdx.x == 0) s_changed = 0;
+    __syncthreads();
+    if (wave_changed && __lane_id() == 0) s_changed = 1;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (s_changed) ctl->any_changed = 1;
+        __threadfence();
+        const unsigned prev = atomicAdd(&ctl->wg_done, 1u);
+        if (prev == gridDim.x - 1) {
+            __threadfence();
+            ctl->wg_done = 0;
+            pass_end_body(ctl);
+            __threadfence();
+        }
+    }
 }
 
 // ---------------------------------------------------------------- host launchers

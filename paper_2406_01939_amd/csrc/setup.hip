@@ -122,15 +122,19 @@ __global__ void k_split_fill(Plan L, const int32_t *ubase, const int32_t *segbas
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_seg; g += stride) {
         const int32_t s0 = L.seg_sr0[g], s1 = L.seg_sr0[g + 1];
+        const int32_t key = L.seg_key[g];
         if (s1 - s0 > 1) {
             const int32_t b = ubase[g];
             for (int32_t s = s0; s < s1; ++s) {
                 L.sr_uidx[s] = b + (s - s0);
                 L.split_list[b + (s - s0)] = s;
+                L.rd[s] = RunDesc{L.sr_lo[s], L.sr_lo[s + 1], key, (int32_t)g, s - s0, s1 - s0,
+                                  b + (s - s0), 0};
             }
             L.split_segs[segbase[g]] = (int32_t)g;
         } else {
             L.sr_uidx[s0] = -1;
+            L.rd[s0] = RunDesc{L.sr_lo[s0], L.sr_lo[s0 + 1], key, (int32_t)g, 0, 1, -1, 0};
         }
         if (g == n_seg - 1) {
             const int32_t last = s1 - s0 > 1 ? s1 - s0 : 0;

@@ -248,3 +248,50 @@ def test_autotune_picks_a_valid_block(api, oracle):
     out = api.pk_picard_simulate(prob, "greedy", block_len=0)
     _check(out, inst, want_a, want_s, want_f)
     assert out["stats"]["block_len"] == B
+
+
+def test_captured_graph_replays(api, oracle):
+    """The pass loop captured as a HIP graph (U passes per replay) gives the no-graph result
+    on every replay, with eager work and synchronisations between the replays."""
+    inst = make_instance("greedy_batch256_n50_k2e4", n_traj=8, T=(10_000, 50_000))
+    prob = api.DeviceProblem.from_instance(inst)
+    _say("case graph replays")
+    ref = api.pk_picard_simulate(prob, "greedy", block_len=128, graph_unroll=1)
+    want_a, want_s, want_f, want_p = _oracle_batch(oracle, inst, 128)
+    _check(ref, inst, want_a, want_s, want_f)
+    out = None
+    for rep in range(4):
+        out = api.pk_picard_simulate(prob, "greedy", block_len=128, graph_unroll=3, out=out)
+        junk = torch.randn(1 << 20, device="cuda").cumsum(0)  # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.equal(out["actions"], ref["actions"]), rep
+        assert torch.equal(out["shipped"], ref["shipped"]), rep
+        assert torch.equal(out["final_inv"], ref["final_inv"]), rep
+        np.testing.assert_array_equal(out["passes"], want_p)
+        del junk
+
+
+def test_batched_256_trajectories_full_size(api, oracle):
+    """Batched greedy workload at full size: 256 trajectories, horizons uniform in
+    [1e4, 1e6] (about 1.3e8 orders), N=50, K=2e4, R=100, quantities 1..3.  Actions, units
+    shipped and final inventory bit-exact against the serial oracle for every trajectory;
+    passes checked against the oracle's Picard iteration on a sample of trajectories."""
+    inst = make_instance("greedy_batch256_n50_k2e4")
+    prob = api.DeviceProblem.from_instance(inst)
+    _say(f"case batch256 full total={inst.total_orders}")
+    out = api.pk_picard_simulate(prob, "greedy", block_len=0)
+    B = out["stats"]["block_len"]
+    acts = out["actions"].cpu().numpy()
+    ship = out["shipped"].cpu().numpy()
+    fin = out["final_inv"].cpu().numpy()
+    w = oracle.block_workers(inst, B)
+    for b in range(inst.n_traj):
+        lo, hi = int(inst.traj_offsets[b]), int(inst.traj_offsets[b + 1])
+        r = oracle.serial(inst, b)
+        np.testing.assert_array_equal(acts[lo:hi], r["actions"])
+        np.testing.assert_array_equal(ship[lo:hi], r["shipped"])
+        np.testing.assert_array_equal(fin[b], r["final_inv"])
+        if b % 32 == 0:
+            pr = oracle.picard_runs(inst, w[lo:hi], b)
+            assert out["passes"][b] == pr["passes"], b
+    _say(f"B={B} passes max={out['passes'].max()} mean={out['passes'].mean():.2f}")

@@ -129,3 +129,17 @@ def test_batch_shaped_like_large_workload(api, oracle):
     assert ((sh >= 0) & (sh <= inst.qty)).all()
     fin = out["final_inv"].cpu().numpy()
     assert (fin >= 0).all()
+
+
+def test_wide_policy_shape(api, oracle):
+    """N=500 warehouses, R=500 regions, quantities 1..4 (the 16-trajectory learned
+    workload's policy shape), reduced to 2 trajectories of 3000 orders over 1e4 SKUs."""
+    inst = make_instance("mlp_batch16_n500_k1e6_t1e7", n_traj=2, T=3000, K=10_000)
+    prob = api.DeviceProblem.from_instance(inst)
+    _say("case mlp N=500 R=500")
+    out = api.pk_picard_simulate(prob, "mlp", block_len=128)
+    gpu = out["actions"].cpu().numpy()
+    mism, ties = _self_consistent(oracle, inst, gpu)
+    _say(f"mismatches at near-ties: {mism}, near-ties: {ties}, passes {out['passes']}")
+    ser = api.pk_serial_simulate(prob, "mlp")
+    assert torch.equal(ser["actions"], out["actions"])
