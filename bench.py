@@ -26,7 +26,7 @@ METRIC = "simulated orders/sec/GPU, Picard vs serial GPU sweep; iterations to co
 HBM_PEAK_GBS = 8000.0
 DEFAULT_WORKLOAD = "greedy_n100_k1e5_t1e6"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_walk_greedy_n100_k1e5_t1e6_traffic.md")
-WALK_SOURCE = os.path.join(ROOT, "paper_2406_01939_amd", "csrc", "greedy.hip")
+WALK_SOURCE = os.path.join(ROOT, "paper_2406_01939_amd", "csrc", "walk_greedy.hip")
 
 
 def _traffic():

@@ -49,7 +49,9 @@ typedef enum {
     PK_ERR_HIP = -3,           /* a HIP runtime call failed */
     PK_ERR_NOT_CONVERGED = -4, /* max_passes reached; outputs hold the last cache */
     PK_ERR_WORKSPACE = -5,     /* ws is NULL or smaller than pk_workspace_size */
-    PK_ERR_UNSUPPORTED = -6    /* a valid request this build does not implement */
+    PK_ERR_UNSUPPORTED = -6,   /* a valid request this build does not implement */
+    PK_ERR_INTERNAL = -7       /* a device-side consistency check failed (a defect of the
+                                  library, not of the input); outputs are undefined */
 } pk_status;
 
 #define PK_LOST (-1) /* the lost sale a^phi: no warehouse ships the order */

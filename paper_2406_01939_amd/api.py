@@ -25,12 +25,14 @@ PK_ERR_HIP = -3
 PK_ERR_NOT_CONVERGED = -4
 PK_ERR_WORKSPACE = -5
 PK_ERR_UNSUPPORTED = -6
+PK_ERR_INTERNAL = -7
 PK_LOST = -1
 PK_POLICY_GREEDY = 0
 PK_POLICY_MLP = 1
 
 STATUS_NAMES = {0: "PK_OK", -1: "PK_ERR_INVALID_ARG", -2: "PK_ERR_SHAPE", -3: "PK_ERR_HIP",
-                -4: "PK_ERR_NOT_CONVERGED", -5: "PK_ERR_WORKSPACE", -6: "PK_ERR_UNSUPPORTED"}
+                -4: "PK_ERR_NOT_CONVERGED", -5: "PK_ERR_WORKSPACE", -6: "PK_ERR_UNSUPPORTED",
+                -7: "PK_ERR_INTERNAL"}
 
 
 class PicardError(RuntimeError):

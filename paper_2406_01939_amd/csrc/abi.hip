@@ -27,10 +27,11 @@ hipError_t launch_pass_end(const Plan &L, hipStream_t st);
 hipError_t launch_consume(const Prob &P, const Plan &L, int64_t n_split_max, hipStream_t st);
 hipError_t launch_unpermute(const Prob &P, const Plan &L, int32_t *actions, int32_t *shipped,
                             hipStream_t st);
-// greedy.hip
+// walk_greedy.hip
 size_t walk_greedy_lds(int N, int R);
-hipError_t launch_walk_greedy(const Prob &P, const Plan &L, const void *pos, int32_t *final_inv,
+hipError_t launch_walk_greedy(const Prob &P, const Plan &L, const void *keys, int32_t *final_inv,
                               bool has_init, int grid, hipStream_t st);
+// greedy.hip
 hipError_t launch_serial_greedy(const Prob &P, const void *pos, int32_t *state, int32_t *actions,
                                 int32_t *shipped, hipStream_t st);
 // mlp.hip
@@ -472,6 +473,8 @@ pk_status picard_run(const pk_problem *problem, const Dims &d, const pk_policy *
         }
     }
     for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+    if (hc->error & ERR_NO_PROGRESS)
+        return fail(PK_ERR_INTERNAL, "walk made no progress (device state inconsistent)");
     if (hc->error) return fail(PK_ERR_INVALID_ARG, "input value out of range (code %d)", hc->error);
     if (d.total > 0 && hc->done != 1)
         return fail(PK_ERR_NOT_CONVERGED, "not converged after %d passes", hc->passes_done);

@@ -1,0 +1,28 @@
+// Key table of the greedy policy, shared by the Picard walk and the serial sweep.
+//
+// key[b][r][w] = (pos << S) | w, where pos is the position of warehouse w in region r's
+// increasing (cost[b][w][r], w) order: 16-bit keys with S = 8 when N <= 256, else 32-bit
+// keys with S = 16.  The least key among warehouses with stock names the greedy choice
+// (least cost, lowest index on ties).  Per trajectory the table holds R rows of npad
+// keys; rows are padded to 32 bytes with all-ones keys, which are never selected.
+#pragma once
+
+#include "pk_internal.h"
+
+namespace pk {
+
+template <typename KeyT> __host__ __device__ inline int tab_npad(int N)
+{
+    constexpr int per = 32 / (int)sizeof(KeyT);
+    return (N + per - 1) / per * per;
+}
+template <typename KeyT> __host__ __device__ inline int64_t tab_stride(int N, int R)
+{
+    return (int64_t)R * tab_npad<KeyT>(N);
+}
+template <typename KeyT> __host__ __device__ constexpr int key_shift()
+{
+    return sizeof(KeyT) == 2 ? 8 : 16;
+}
+
+} // namespace pk

@@ -28,6 +28,9 @@ struct Prob {
 constexpr int STAT_SLOTS = 64; // statistics are spread over slots to avoid one hot address
 enum { ST_ORDERS = 0, ST_RUNS, ST_CHANGED, ST_BYTES, ST_NEAR_TIES, ST_N };
 
+// Ctl::error bits set by device-side consistency checks (the validate bits are 1..8).
+constexpr int32_t ERR_NO_PROGRESS = 1 << 12; // a walk step could not commit any order
+
 struct Ctl {
     int32_t pass;        // current pass (1-based)
     int32_t done;        // 1 once a pass changed nothing, 2 when max_passes was reached
@@ -77,8 +80,7 @@ struct Plan {
     int32_t *u;              // [n_split_max][N] cached consumption of each split run
     int32_t *E;              // [n_split_max][N] consumption entering each split run
     float *costT;            // [n_traj][R][N] cost as float, region-major (learned policy)
-    void *pos;               // [n_traj][R][N] rank key of each warehouse per region
-                             // (uint8 for N <= 256, else uint16; 16-byte padded slices)
+    void *pos;               // greedy: key table of greedy_keys.h
     int32_t *traj_lcp;       // [n_traj] last pass in which the trajectory changed
     int32_t *sink;           // [128] write target of masked-off lanes (contents unused)
     Ctl *ctl;

@@ -144,6 +144,30 @@ def test_edge_cases(api, oracle):
     _check(out, inst2, want_a, want_s, want_f)
 
 
+def test_partial_ship_then_same_warehouse(api, oracle):
+    """Regression: in one step a warehouse's only order asks for more than its stock and
+    ships partially (no order is cut); the warehouse must leave the stock set, so an
+    order in the next step that prefers it goes elsewhere.  Two warehouses, region 0
+    prefers w0 and region 1 prefers w1."""
+    from paper_2406_01939_amd.instances import Instance
+    T = 66
+    region = np.ones(T, np.int32)
+    region[0] = 0
+    region[T - 1] = 0
+    qty = np.ones(T, np.int32)
+    qty[0] = 3
+    inst = Instance(N=2, K=1, R=2, traj_offsets=np.array([0, T], np.int64),
+                    sku=np.zeros(T, np.int32), region=region, qty=qty,
+                    x0=np.array([[[2, 1000]]], np.int32),
+                    cost=np.array([[[1, 9], [9, 1]]], np.int32), rng_seed=0)
+    want_a, want_s, want_f, _ = _oracle_batch(oracle, inst)
+    assert want_s[0] == 2 and want_a[T - 1] == 1 and want_f.ravel()[0] == 0
+    _say("case partial ship then the same warehouse")
+    for B in (T, 70, 1):
+        out = api.pk_picard_simulate(api.DeviceProblem.from_instance(inst), "greedy", block_len=B)
+        _check(out, inst, want_a, want_s, want_f)
+
+
 def test_warm_start(api, oracle):
     inst = random_tiny(31, N=6, K=3, R=3, T=300, qmax=2, inv_max=8, n_traj=2)
     want_a, want_s, want_f, _ = _oracle_batch(oracle, inst)
