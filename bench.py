@@ -87,6 +87,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup-seconds", type=float, default=0.5)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
     ap.add_argument("--block-len", type=int, default=0)
     ap.add_argument("--no-serial", action="store_true")
@@ -113,10 +114,15 @@ def main():
     total = inst.total_orders
     B = args.block_len if args.block_len > 0 else api.pk_autotune(prob, policy)
 
+    # warm-up: at least W steps and at least half a second of work (an idle GPU runs at
+    # low clocks for a while)
     out = None
-    for _ in range(args.warmup):
+    t_w = time.perf_counter()
+    k = 0
+    while k < args.warmup or time.perf_counter() - t_w < args.warmup_seconds:
         out = api.pk_picard_simulate(prob, policy, block_len=B, out=out)
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        k += 1
     walk_ms = walk_bytes = 0.0
     walk_launches = 0
     passes = None

@@ -283,18 +283,35 @@ int num_cus()
 struct GraphKey {
     unsigned char bytes[sizeof(Prob) + sizeof(Plan) + sizeof(pk_policy) + 64];
     void set(const Prob &P, const Plan &L, const pk_policy *po, const int32_t *fin, bool hi,
-             int grid, int U, int nseg)
+             int grid, int U, int nseg, bool timing)
     {
         memset(bytes, 0, sizeof bytes);
         size_t o = 0;
         memcpy(bytes + o, &P, sizeof P); o += sizeof P;
         memcpy(bytes + o, &L, sizeof L); o += sizeof L;
         memcpy(bytes + o, po, sizeof *po); o += sizeof *po;
-        const int64_t extra[6] = {(int64_t)(uintptr_t)fin, hi, grid, U, nseg, 0};
+        const int64_t extra[6] = {(int64_t)(uintptr_t)fin, hi, grid, U, nseg, timing};
         memcpy(bytes + o, extra, sizeof extra);
     }
     bool operator==(const GraphKey &k) const { return memcmp(bytes, k.bytes, sizeof bytes) == 0; }
 };
+
+// When timing is requested the graph also holds an event pair around every walk (event
+// record nodes added to the graph being captured); every replay records them again.
+pk_status record_in_capture(hipStream_t s, hipEvent_t e)
+{
+    hipStreamCaptureStatus cs;
+    unsigned long long id = 0;
+    hipGraph_t g = nullptr;
+    const hipGraphNode_t *deps = nullptr;
+    size_t nd = 0;
+    HIP_TRY(hipStreamGetCaptureInfo_v2(s, &cs, &id, &g, &deps, &nd));
+    if (cs != hipStreamCaptureStatusActive || !g) return fail(PK_ERR_HIP, "stream is not capturing");
+    hipGraphNode_t node = nullptr;
+    HIP_TRY(hipGraphAddEventRecordNode(&node, g, deps, nd, e));
+    HIP_TRY(hipStreamUpdateCaptureDependencies(s, &node, 1, hipStreamSetCaptureDependencies));
+    return PK_OK;
+}
 
 struct GraphCache {
     bool valid = false;
@@ -303,16 +320,20 @@ struct GraphCache {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t cap = nullptr;
+    std::vector<hipEvent_t> evs;
     ~GraphCache() { clear(); }
     void clear()
     {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
+        for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+        evs.clear();
         exec = nullptr;
         graph = nullptr;
         valid = false;
     }
-    template <typename F> pk_status get(const GraphKey &k, F enqueue, hipGraphExec_t *out)
+    template <typename F> pk_status get(const GraphKey &k, int n_events, F enqueue,
+                                        hipGraphExec_t *out)
     {
         int dev = 0;
         HIP_TRY(hipGetDevice(&dev));
@@ -327,6 +348,11 @@ struct GraphCache {
         }
         if (!cap) HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
         device = dev;
+        for (int i = 0; i < n_events; ++i) {
+            hipEvent_t e = nullptr;
+            HIP_TRY(hipEventCreate(&e));
+            evs.push_back(e);
+        }
         HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
         pk_status e = enqueue(cap);
         hipGraph_t g = nullptr;
@@ -396,11 +422,16 @@ pk_status picard_run(const pk_problem *problem, const Dims &d, const pk_policy *
         done = 1;
     }
     // one pass = entry scan + walk (the walk's last workgroup ends the pass); the kernels
-    // return at once after convergence, so U passes are enqueued per host check
-    auto enqueue_pass = [&](hipStream_t s2, bool with_events) -> pk_status {
+    // return at once after convergence, so U passes are enqueued per host check.
+    // Events around the walk: none (ge == nullptr, !with_events), created here, or the
+    // captured graph's pair ge[0], ge[1] recorded as graph nodes.
+    auto enqueue_pass = [&](hipStream_t s2, bool with_events, hipEvent_t *ge) -> pk_status {
         HIP_TRY(launch_scan_entry(P, L, (int)sz.n_seg_max, !has_init, s2));
         hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (with_events) {
+        if (ge) {
+            const pk_status r = record_in_capture(s2, ge[0]);
+            if (r != PK_OK) return r;
+        } else if (with_events) {
             HIP_TRY(hipEventCreate(&e0));
             HIP_TRY(hipEventCreate(&e1));
             HIP_TRY(hipEventRecord(e0, s2));
@@ -410,21 +441,26 @@ pk_status picard_run(const pk_problem *problem, const Dims &d, const pk_policy *
                                     final_inv, has_init, num_cus() * 4, s2));
         else
             HIP_TRY(launch_walk_greedy(P, L, L.pos, final_inv, has_init, grid, s2));
-        if (with_events) {
+        if (ge) {
+            const pk_status r = record_in_capture(s2, ge[1]);
+            if (r != PK_OK) return r;
+        } else if (with_events) {
             HIP_TRY(hipEventRecord(e1, s2));
             evs.push_back(e0);
             evs.push_back(e1);
         }
         return PK_OK;
     };
-    // U passes captured once as a HIP graph and replayed (not when timing each launch)
+    // U passes captured once as a HIP graph and replayed
     hipGraphExec_t gexec = nullptr;
-    if (!done && U > 1 && !timing && max_passes >= U) {
+    double graph_walk_ms = 0.0;
+    int64_t graph_walks = 0;
+    if (!done && U > 1 && max_passes >= U) {
         GraphKey key;
-        key.set(P, L, policy, final_inv, has_init, grid, U, (int)sz.n_seg_max);
-        pk_status gs = g_graph.get(key, [&](hipStream_t cs) -> pk_status {
+        key.set(P, L, policy, final_inv, has_init, grid, U, (int)sz.n_seg_max, timing);
+        pk_status gs = g_graph.get(key, timing ? 2 * U : 0, [&](hipStream_t cs) -> pk_status {
             for (int i = 0; i < U; ++i) {
-                pk_status e = enqueue_pass(cs, false);
+                pk_status e = enqueue_pass(cs, false, timing ? &g_graph.evs[2 * i] : nullptr);
                 if (e != PK_OK) return e;
             }
             return PK_OK;
@@ -433,17 +469,26 @@ pk_status picard_run(const pk_problem *problem, const Dims &d, const pk_policy *
     }
     while (!done && launched < max_passes) {
         const int u = std::min(U, max_passes - launched);
-        if (gexec && u == U) {
+        const bool replay = gexec && u == U;
+        if (replay) {
             HIP_TRY(hipGraphLaunch(gexec, st));
         } else {
             for (int i = 0; i < u; ++i) {
-                pk_status e = enqueue_pass(st, timing);
+                pk_status e = enqueue_pass(st, timing, nullptr);
                 if (e != PK_OK) return e;
             }
         }
         launched += u;
         HIP_TRY(hipMemcpyAsync(hc, L.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
+        if (replay && timing) {
+            for (int i = 0; i < U; ++i) {
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, g_graph.evs[2 * i], g_graph.evs[2 * i + 1]));
+                graph_walk_ms += ms;
+            }
+            graph_walks += U;
+        }
         done = hc->done;
     }
     if (d.total > 0) HIP_TRY(launch_unpermute(P, L, actions, shipped, st));
@@ -465,8 +510,8 @@ pk_status picard_run(const pk_problem *problem, const Dims &d, const pk_policy *
         stats->orders_walked = (int64_t)sum[ST_ORDERS];
         stats->near_ties = (int64_t)sum[ST_NEAR_TIES];
         stats->walk_bytes = (int64_t)sum[ST_BYTES];
-        stats->walk_ms = 0.0;
-        stats->walk_launches = (int64_t)(evs.size() / 2);
+        stats->walk_ms = graph_walk_ms;
+        stats->walk_launches = (int64_t)(evs.size() / 2) + graph_walks;
         for (size_t i = 0; i + 1 < evs.size(); i += 2) {
             float ms = 0.f;
             if (hipEventElapsedTime(&ms, evs[i], evs[i + 1]) == hipSuccess) stats->walk_ms += ms;
@@ -560,37 +605,53 @@ pk_status autotune_block(const pk_problem *problem, const Dims &d, const pk_poli
         }
     }
     static const int cands[] = {64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384, 65536};
+    constexpr int NC = (int)(sizeof(cands) / sizeof(cands[0]));
     pk_picard_opts o = {};
     o.use_frontier = 1;
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
+    auto run_ms = [&](int B, float *ms) -> pk_status {
+        HIP_TRY(hipEventRecord(e0, st));
+        pk_status s = picard_run(problem, d, po, o, B, ws, ws_bytes, actions, nullptr, nullptr,
+                                 nullptr, st);
+        if (s != PK_OK) return s;
+        HIP_TRY(hipEventRecord(e1, st));
+        HIP_TRY(hipEventSynchronize(e1));
+        HIP_TRY(hipEventElapsedTime(ms, e0, e1));
+        return PK_OK;
+    };
+    bool usable[NC];
+    for (int i = 0; i < NC; ++i)
+        usable[i] = (cands[i] <= 2 * std::max<int64_t>(d.total, 1) || i == 0) &&
+                    ws_bytes >= picard_bytes(d, po, cands[i]);
+    // warm-up (clocks ramp up on an idle GPU), then rounds over all candidates in turn so
+    // that drift affects every candidate alike; each keeps its best time
+    const int warm_b = ws_bytes >= picard_bytes(d, po, DEFAULT_BLOCK_GREEDY) ? DEFAULT_BLOCK_GREEDY : cands[0];
+    float spent = 0.f;
+    for (int k = 0; k < 200 && spent < 300.f; ++k) {
+        float ms = 0.f;
+        pk_status s = run_ms(warm_b, &ms);
+        if (s != PK_OK) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return s; }
+        spent += ms;
+    }
+    float t[NC];
+    for (int i = 0; i < NC; ++i) t[i] = 1e30f;
+    for (int round = 0; round < 3; ++round)
+        for (int i = 0; i < NC; ++i) {
+            if (!usable[i]) continue;
+            float ms = 0.f;
+            pk_status s = run_ms(cands[i], &ms);
+            if (s != PK_OK) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return s; }
+            t[i] = std::min(t[i], ms);
+        }
     float best_ms = 1e30f;
     int best_b = DEFAULT_BLOCK_GREEDY;
-    for (int B : cands) {
-        if (B > 2 * std::max<int64_t>(d.total, 1) && B != cands[0]) break;
-        if (ws_bytes < picard_bytes(d, po, B)) continue;
-        float t = 1e30f;
-        for (int rep = 0; rep < 2; ++rep) {
-            HIP_TRY(hipEventRecord(e0, st));
-            pk_status s = picard_run(problem, d, po, o, B, ws, ws_bytes, actions, nullptr,
-                                     nullptr, nullptr, st);
-            if (s != PK_OK) {
-                (void)hipEventDestroy(e0);
-                (void)hipEventDestroy(e1);
-                return s;
-            }
-            HIP_TRY(hipEventRecord(e1, st));
-            HIP_TRY(hipEventSynchronize(e1));
-            float ms = 0.f;
-            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-            t = std::min(t, ms);
+    for (int i = 0; i < NC; ++i)
+        if (usable[i] && t[i] < best_ms) {
+            best_ms = t[i];
+            best_b = cands[i];
         }
-        if (t < best_ms) {
-            best_ms = t;
-            best_b = B;
-        }
-    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     std::lock_guard<std::mutex> lk(g_tune_mu);

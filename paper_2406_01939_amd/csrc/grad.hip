@@ -198,18 +198,24 @@ __global__ __launch_bounds__(256) void k_grad(Prob P, Plan L, const float *param
                     d1s += d1;
                     wave_sync();
                 }
-                // this order's sums into the workgroup's FP64 accumulators
+                // this order's sums into the workgroup's FP64 accumulators, one wave after
+                // the other in a fixed order (the gradient is reproducible bit for bit)
+                for (int wv = 0; wv < 4; ++wv) {
+                    if (wave == wv) {
 #pragma unroll
-                for (int k = 0; k < 18; ++k) atomicAdd(&acc[oW1 + j * 18 + k], (double)aw1[k]);
-                atomicAdd(&acc[ob1 + j], (double)ab1);
-                if (two) {
+                        for (int k = 0; k < 18; ++k) acc[oW1 + j * 18 + k] += (double)aw1[k];
+                        acc[ob1 + j] += (double)ab1;
+                        if (two) {
 #pragma unroll
-                    for (int i = 0; i < H; ++i) atomicAdd(&acc[oW2 + j * H + i], (double)aw2[i]);
-                    atomicAdd(&acc[ob2 + j], (double)ab2);
+                            for (int i = 0; i < H; ++i) acc[oW2 + j * H + i] += (double)aw2[i];
+                            acc[ob2 + j] += (double)ab2;
+                        }
+                        acc[ow3 + j] += (double)aw3;
+                        if (lane == 0) acc[ob3] += (double)ab3;
+                        d1sum[j] += d1s;
+                    }
+                    __syncthreads();
                 }
-                atomicAdd(&acc[ow3 + j], (double)aw3);
-                if (lane == 0) atomicAdd(&acc[ob3], (double)ab3);
-                atomicAdd(&d1sum[j], d1s);
             }
             __syncthreads();
             if (wave == 0) {

@@ -16,7 +16,11 @@ namespace pk {
 
 namespace {
 
-// One workgroup per split segment (grid-stride).  Threads cover warehouses; each thread
+// Split segments are taken 256 at a time per workgroup, strided over the grid (segment
+// i goes to workgroup i mod grid, so the long segments of the most frequent SKUs, which
+// are neighbours in key order, land in different workgroups): each thread checks one
+// segment's frontier, the segments with runs to walk are gathered in LDS, and the
+// workgroup then scans them one by one.  In a scan, threads cover warehouses and each
 // runs the scan over the segment's runs for its warehouse, 32 runs' consumption loaded
 // per batch so the loads overlap.  Runs up to the frontier are final and need no entry
 // state; their consumption only enters the prefix.  After the first pass the kernel also
@@ -33,41 +37,58 @@ __global__ __launch_bounds__(256) void k_scan_entry(Prob P, Plan L, int skip_fir
     const int32_t *__restrict__ u = L.u;
     int32_t *__restrict__ E = L.E;
     constexpr int BATCH = 32;
-    __shared__ int32_t s_base;
-    for (int i = blockIdx.x; i < n; i += gridDim.x) {
-        const int g = L.split_segs[i];
-        const int32_t f = L.no_frontier ? FR_ALL : fprev[g];
-        if (threadIdx.x == 0) fcur[g] = FR_NONE;
-        if (f == FR_NONE || (pass == 1 && skip_first_pass)) continue;
-        const int s0 = L.seg_sr0[g];
-        const int nsr = L.seg_sr0[g + 1] - s0;
-        if (pass > 1 && !L.no_frontier) { // list the runs this pass walks: j > f
-            const int j0 = f + 1;
-            const int cnt = nsr - j0;
-            if (cnt > 0) {
-                if (threadIdx.x == 0) s_base = atomicAdd(&ctl->n_active, cnt);
-                __syncthreads();
-                for (int k = threadIdx.x; k < cnt; k += blockDim.x) L.active[s_base + k] = s0 + j0 + k;
-                __syncthreads();
+    __shared__ int32_t s_g[256], s_f[256];
+    __shared__ int32_t s_cnt, s_base;
+    for (int base = 0; base < n; base += gridDim.x * 256) {
+        if (threadIdx.x == 0) s_cnt = 0;
+        __syncthreads();
+        const int i = base + (int)threadIdx.x * (int)gridDim.x + (int)blockIdx.x;
+        if (i < n) {
+            const int g = L.split_segs[i];
+            const int32_t f = L.no_frontier ? FR_ALL : fprev[g];
+            fcur[g] = FR_NONE;
+            if (f != FR_NONE && !(pass == 1 && skip_first_pass)) {
+                const int k = atomicAdd(&s_cnt, 1);
+                s_g[k] = g;
+                s_f[k] = f;
             }
         }
-        const int jmin = f + 1 > 1 ? f + 1 : 1; // runs j > f need E_j; E_0 = 0
-        const int64_t row0 = L.sr_uidx[s0];
-        for (int w = threadIdx.x; w < N; w += blockDim.x) {
-            int32_t acc = 0;
-            for (int jb = 0; jb < nsr; jb += BATCH) {
-                int32_t v[BATCH];
+        __syncthreads();
+        const int cnt = s_cnt;
+        for (int t = 0; t < cnt; ++t) {
+            const int g = s_g[t];
+            const int32_t f = s_f[t];
+            const int s0 = L.seg_sr0[g];
+            const int nsr = L.seg_sr0[g + 1] - s0;
+            if (pass > 1 && !L.no_frontier) { // list the runs this pass walks: j > f
+                const int j0 = f + 1;
+                const int jc = nsr - j0;
+                if (jc > 0) {
+                    if (threadIdx.x == 0) s_base = atomicAdd(&ctl->n_active, jc);
+                    __syncthreads();
+                    for (int k = threadIdx.x; k < jc; k += blockDim.x) L.active[s_base + k] = s0 + j0 + k;
+                    __syncthreads();
+                }
+            }
+            const int jmin = f + 1 > 1 ? f + 1 : 1; // runs j > f need E_j; E_0 = 0
+            const int64_t row0 = L.sr_uidx[s0];
+            for (int w = threadIdx.x; w < N; w += blockDim.x) {
+                int32_t acc = 0;
+                for (int jb = 0; jb < nsr; jb += BATCH) {
+                    int32_t v[BATCH];
 #pragma unroll
-                for (int k = 0; k < BATCH; ++k)
-                    v[k] = jb + k < nsr ? u[(row0 + jb + k) * N + w] : 0;
+                    for (int k = 0; k < BATCH; ++k)
+                        v[k] = jb + k < nsr ? u[(row0 + jb + k) * N + w] : 0;
 #pragma unroll
-                for (int k = 0; k < BATCH; ++k) {
-                    const int jj = jb + k;
-                    if (jj >= jmin && jj < nsr) E[(row0 + jj) * N + w] = acc;
-                    acc += v[k];
+                    for (int k = 0; k < BATCH; ++k) {
+                        const int jj = jb + k;
+                        if (jj >= jmin && jj < nsr) E[(row0 + jj) * N + w] = acc;
+                        acc += v[k];
+                    }
                 }
             }
         }
+        __syncthreads();
     }
 }
 
@@ -117,7 +138,8 @@ __global__ void k_unpermute(Prob P, Plan L, int32_t *actions, int32_t *shipped)
 hipError_t launch_scan_entry(const Prob &P, const Plan &L, int n_seg_max, bool skip_first,
                              hipStream_t st)
 {
-    int grid = n_seg_max < 4096 ? (n_seg_max > 0 ? n_seg_max : 1) : 4096;
+    int grid = (n_seg_max + 255) / 256;
+    grid = grid < 1 ? 1 : (grid > 1024 ? 1024 : grid);
     hipLaunchKernelGGL(k_scan_entry, dim3(grid), dim3(256), 0, st, P, L, skip_first ? 1 : 0);
     return hipGetLastError();
 }

@@ -17,10 +17,18 @@ __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlan
 
 // The set of warehouses with stock of the run being walked, as a bitmask.  For N <= 128
 // its two 64-bit words are wave-uniform values in scalar registers; otherwise the words
-// live in LDS with a member count beside them.  clear() takes a wave-uniform warehouse.
+// live in LDS with a member count beside them.  With 16-bit keys the set is also kept
+// as key masks in LDS: M[d] covers keys 2d (low half) and 2d+1 (high half), all-ones
+// for a warehouse without stock, so a masked key is one OR.  clear() takes a
+// wave-uniform warehouse.
+__device__ __forceinline__ void mask_out(uint32_t *M, int a)
+{
+    if (M && __lane_id() == 0) M[a >> 1] |= (a & 1) ? 0xffff0000u : 0x0000ffffu;
+}
 template <bool SF> struct StockSet;
 template <> struct StockSet<true> {
     uint64_t w0 = 0, w1 = 0;
+    uint32_t *M = nullptr;
     __device__ __forceinline__ uint64_t word(int k) const { return k == 0 ? w0 : w1; }
     __device__ __forceinline__ bool has(int a) const { return ((a < 64 ? w0 : w1) >> (a & 63)) & 1ull; }
     __device__ __forceinline__ bool any() const { return (w0 | w1) != 0; }
@@ -28,11 +36,13 @@ template <> struct StockSet<true> {
     {
         if (a < 64) w0 &= ~(1ull << a);
         else w1 &= ~(1ull << (a - 64));
+        mask_out(M, a);
     }
 };
 template <> struct StockSet<false> {
     uint64_t *F = nullptr;
     int32_t *n = nullptr;
+    uint32_t *M = nullptr;
     __device__ __forceinline__ uint64_t word(int k) const { return F[k]; }
     __device__ __forceinline__ bool has(int a) const { return (F[a >> 6] >> (a & 63)) & 1ull; }
     __device__ __forceinline__ bool any() const { return *n > 0; }
@@ -42,19 +52,19 @@ template <> struct StockSet<false> {
             F[a >> 6] &= ~(1ull << (a & 63));
             *n -= 1;
         }
+        mask_out(M, a);
     }
 };
 
-// Folds 16 keys (32 bytes) into a packed 16-bit minimum; fb has one bit per key, set for
-// warehouses with stock (wave-uniform, so the pair masks are scalar values).
-__device__ __forceinline__ void fold16(pk_u16x2 &acc, uint4 v0, uint4 v1, uint32_t fb)
+// Folds 16 keys (32 bytes) into a packed 16-bit minimum, each pair ORed with its mask
+// (all-ones halves for warehouses without stock).
+__device__ __forceinline__ void fold16(pk_u16x2 &acc, uint4 v0, uint4 v1, uint4 m0, uint4 m1)
 {
     const uint32_t d[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+    const uint32_t o[8] = {m0.x, m0.y, m0.z, m0.w, m1.x, m1.y, m1.z, m1.w};
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-        const uint32_t two = (fb >> (2 * i)) & 3u;
-        const uint32_t off = ((two & 1u) ? 0u : 0x0000ffffu) | ((two & 2u) ? 0u : 0xffff0000u);
-        const uint32_t m = d[i] | off;
+        const uint32_t m = d[i] | o[i];
         pk_u16x2 mv;
         __builtin_memcpy(&mv, &m, 4);
         acc = __builtin_elementwise_min(acc, mv);
@@ -71,7 +81,8 @@ __device__ __forceinline__ int least_key_128(const uint16_t *row, const StockSet
                                              int npad, bool need)
 {
     const uint4 *row4 = (const uint4 *)row;
-    uint4 v[16];
+    const uint4 *M4 = (const uint4 *)fs.M;
+    uint4 v[16], m[16];
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
         const int at = s * 16 < npad ? 2 * s : 0;
@@ -81,12 +92,14 @@ __device__ __forceinline__ int least_key_128(const uint16_t *row, const StockSet
         } else {
             v[2 * s] = v[2 * s + 1] = make_uint4(~0u, ~0u, ~0u, ~0u);
         }
+        m[2 * s] = M4[at]; // one address for the whole wave
+        m[2 * s + 1] = M4[at + 1];
     }
     pk_u16x2 acc = {0xffff, 0xffff};
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
         const uint32_t fb = (uint32_t)(fs.word(s >> 2) >> ((16 * s) & 63)) & 0xffffu;
-        if (fb) fold16(acc, v[2 * s], v[2 * s + 1], fb); // wave-uniform
+        if (fb) fold16(acc, v[2 * s], v[2 * s + 1], m[2 * s], m[2 * s + 1]); // wave-uniform
     }
     const uint32_t best = acc.x < acc.y ? acc.x : acc.y;
     return best == 0xffffu ? LOST : (int)(best & 0xffu);
@@ -104,7 +117,8 @@ __device__ __forceinline__ int least_key(const KeyT *row, const FS &fs, int npad
         for (int base = 0; base < npad; base += STEP) {
             const uint32_t fb = (uint32_t)(fs.word(base >> 6) >> (base & 63)) & 0xffffu;
             if (fb == 0) continue; // wave-uniform
-            if (need) fold16(acc, row4[base / PER], row4[base / PER + 1], fb);
+            const uint4 *M4 = (const uint4 *)fs.M;
+            if (need) fold16(acc, row4[base / PER], row4[base / PER + 1], M4[base / PER], M4[base / PER + 1]);
         }
         const uint32_t best = acc.x < acc.y ? acc.x : acc.y;
         return best == 0xffffu ? LOST : (int)(best & 0xffu);
@@ -157,14 +171,18 @@ __device__ __forceinline__ int choose(const KeyT *row, const StockSet<SF> &fs, i
 // The key table of the run's trajectory is read from LDS (one copy per workgroup for a
 // single trajectory, one per wave for small tables) or from global memory.
 // Per wave LDS: x[N] stock, tot[N] step demand, cons[N] run consumption (unclamped, for
-// u), bw[R] memo, member count, F[ceil(N/64)], in-ring[128] (region | (old+1) << 12,
-// qty), out-ring[128] (action, shipped).
+// u), bw[R] memo, member count, F[ceil(N/64)], key masks M (16-bit keys), in-ring[128]
+// (region | (old+1) << 12, qty), out-ring[128] (action, shipped).
+template <typename KeyT> __host__ __device__ inline size_t mask_bytes(int N)
+{
+    return sizeof(KeyT) == 2 ? (size_t)tab_npad<KeyT>(N) * 2 : 0; // one bit pattern per key
+}
 template <typename KeyT> __host__ __device__ inline size_t walk_wave_bytes(int N, int R, int mode)
 {
     const size_t tb = (size_t)tab_stride<KeyT>(N, R) * sizeof(KeyT);
     const size_t ints = ((size_t)(3 * N + R + 1) * 4 + 15) & ~(size_t)15;
     const size_t f = ((size_t)8 * ((N + 63) / 64) + 15) & ~(size_t)15;
-    return (mode == 1 ? tb : 0) + ints + f + 2 * 128 * sizeof(int2);
+    return (mode == 1 ? tb : 0) + ints + f + mask_bytes<KeyT>(N) + 2 * 128 * sizeof(int2);
 }
 
 __device__ __forceinline__ int2 pack_in(int r, int q, int old) { return make_int2(r | ((old + 1) << 12), q); }
@@ -195,7 +213,8 @@ __global__ __launch_bounds__(256) void k_walk_greedy(Prob P, Plan L, const KeyT 
     int32_t *bw = cons + N;
     int32_t *nfeas = bw + R;
     uint64_t *F = (uint64_t *)(wb + ints_off + ints_bytes);
-    int2 *ring = (int2 *)(wb + ints_off + ints_bytes + f_bytes);
+    uint32_t *M = sizeof(KeyT) == 2 ? (uint32_t *)(wb + ints_off + ints_bytes + f_bytes) : nullptr;
+    int2 *ring = (int2 *)(wb + ints_off + ints_bytes + f_bytes + mask_bytes<KeyT>(N));
     int2 *oring = ring + 2 * WAVE;
     Ctl *ctl = L.ctl;
     if (ctl->done) return;
@@ -274,6 +293,15 @@ __global__ __launch_bounds__(256) void k_walk_greedy(Prob P, Plan L, const KeyT 
             fs.F = F;
             fs.n = nfeas;
             if (lane == 0) *nfeas = nf;
+            wave_sync();
+        }
+        fs.M = M;
+        if (M) { // key masks from the stock set
+            for (int dd = lane; dd < npad / 2; dd += WAVE) {
+                const int w = 2 * dd;
+                const bool s0 = w < N && fs.has(w), s1 = w + 1 < N && fs.has(w + 1);
+                M[dd] = (s0 ? 0u : 0x0000ffffu) | (s1 ? 0u : 0xffff0000u);
+            }
         }
         ring[lane] = pack_in(r0, q0, o0); // chunk 0
         RunDesc dn = {}; // the next run's descriptor

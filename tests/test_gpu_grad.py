@@ -93,6 +93,20 @@ def test_gradient_random_advantages_batch(api, oracle):
     _compare(oracle, inst, prob, api, out["actions"], adv)
 
 
+def test_gradient_is_reproducible(api):
+    """Two calls on the same input give the same gradient bit for bit (the accumulation
+    order is fixed)."""
+    inst = random_tiny(301, N=12, K=3, R=5, T=200, qmax=2, inv_max=5, mlp=True, n_traj=2)
+    prob = api.DeviceProblem.from_instance(inst)
+    _say("case reproducible gradient")
+    out = api.pk_picard_simulate(prob, "mlp", block_len=8)
+    adv = torch.randn(inst.total_orders, generator=torch.Generator().manual_seed(5)).cuda()
+    g1 = api.pk_policy_grad(prob, out["actions"], adv)
+    g2 = api.pk_policy_grad(prob, out["actions"], adv)
+    assert torch.equal(g1["grad"], g2["grad"])
+    assert g1["objective"] == g2["objective"]
+
+
 def test_autograd_function(api):
     from paper_2406_01939_amd.autograd import PicardReinforce, reward_to_go_advantages
     inst = random_tiny(300, N=10, K=3, R=4, T=120, qmax=2, inv_max=5, mlp=True)

@@ -293,6 +293,17 @@ def test_captured_graph_replays(api, oracle):
         assert torch.equal(out["final_inv"], ref["final_inv"]), rep
         np.testing.assert_array_equal(out["passes"], want_p)
         del junk
+    # timing inside the graph (event record nodes around every walk): same results, one
+    # duration per walk launch of every replay
+    _say("case graph replays with walk timing")
+    for rep in range(3):
+        out = api.pk_picard_simulate(prob, "greedy", block_len=128, graph_unroll=3, out=out,
+                                     timing=True)
+        torch.cuda.synchronize()
+        assert torch.equal(out["actions"], ref["actions"]), rep
+        st = out["stats"]
+        assert st["walk_launches"] % 3 == 0 and st["walk_launches"] >= int(want_p.max())
+        assert st["walk_ms"] > 0.0
 
 
 def test_batched_256_trajectories_full_size(api, oracle):
