@@ -7,6 +7,8 @@ setup (sort, partition, rank table), every Picard pass to convergence, and the f
 unpermute.  Prints ONE JSON line with the throughput, the passes to converge, the serial
 GPU sweep on the same instance (speed-up), the roofline of the dominant kernel measured
 with HIP events on the library's stream, and the CPU oracle's throughput on the host.
+For a greedy workload the line also carries a shorter run of the learned policy on its
+own workload ("learned": 64 trajectories of 2e5 orders, MFMA roofline of its walk).
 """
 from __future__ import annotations
 
@@ -25,6 +27,8 @@ sys.path.insert(0, ROOT)
 METRIC = "simulated orders/sec/GPU, Picard vs serial GPU sweep; iterations to converge"
 HBM_PEAK_GBS = 8000.0
 DEFAULT_WORKLOAD = "greedy_n100_k1e5_t1e6"
+LEARNED_WORKLOAD = "mlp_batch64_n100_k5e4_t2e5"
+FP32_PEAK_TFLOPS = 157.3
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_walk_greedy_n100_k1e5_t1e6_traffic.md")
 WALK_SOURCE = os.path.join(ROOT, "paper_2406_01939_amd", "csrc", "walk_greedy.hip")
 
@@ -92,6 +96,8 @@ def main():
     ap.add_argument("--block-len", type=int, default=0)
     ap.add_argument("--no-serial", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-policy leg (greedy workloads only)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter yardstick)")
     args = ap.parse_args()
@@ -107,67 +113,91 @@ def main():
     from paper_2406_01939_amd import api
     from paper_2406_01939_amd.instances import make_instance
 
-    inst = make_instance(args.workload)
-    policy = "mlp" if inst.params is not None else "greedy"
-    prob = api.DeviceProblem.from_instance(inst)
-    torch.cuda.synchronize()
-    total = inst.total_orders
-    B = args.block_len if args.block_len > 0 else api.pk_autotune(prob, policy)
-
-    # warm-up: at least W steps and at least half a second of work (an idle GPU runs at
-    # low clocks for a while)
-    out = None
-    t_w = time.perf_counter()
-    k = 0
-    while k < args.warmup or time.perf_counter() - t_w < args.warmup_seconds:
-        out = api.pk_picard_simulate(prob, policy, block_len=B, out=out)
+    def run(name, steps, warmup, warmup_s, block_len, serial):
+        """Time `steps` simulations of workload `name` (after the warm-up) and, if asked,
+        one serial GPU sweep of it; the walk kernel's roofline from the same steps."""
+        inst = make_instance(name)
+        policy = "mlp" if inst.params is not None else "greedy"
+        prob = api.DeviceProblem.from_instance(inst)
         torch.cuda.synchronize()
-        k += 1
-    walk_ms = walk_bytes = 0.0
-    walk_launches = 0
-    passes = None
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        out = api.pk_picard_simulate(prob, policy, block_len=B, out=out, timing=True)
-        st = out["stats"]
-        walk_ms += st["walk_ms"]
-        walk_bytes += st["walk_bytes"]
-        walk_launches += st["walk_launches"]
-        passes = out["passes"]
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms_per_step = 1e3 * dt / args.steps
-    value = total * args.steps / dt
+        total = inst.total_orders
+        B = block_len if block_len > 0 else api.pk_autotune(prob, policy)
+        # warm-up: at least `warmup` steps and `warmup_s` seconds of work (an idle GPU
+        # runs at low clocks for a while)
+        out = None
+        t_w = time.perf_counter()
+        k = 0
+        while k < warmup or time.perf_counter() - t_w < warmup_s:
+            out = api.pk_picard_simulate(prob, policy, block_len=B, out=out)
+            torch.cuda.synchronize()
+            k += 1
+        walk_ms = walk_bytes = walk_flops = 0.0
+        walk_launches = 0
+        passes = None
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            out = api.pk_picard_simulate(prob, policy, block_len=B, out=out, timing=True)
+            st = out["stats"]
+            walk_ms += st["walk_ms"]
+            walk_bytes += st["walk_bytes"]
+            walk_flops += st["walk_flops"]
+            walk_launches += st["walk_launches"]
+            passes = out["passes"]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        r = {"value": total * steps / dt, "ms_per_step": 1e3 * dt / steps, "inst": inst,
+             "policy": policy, "B": B, "passes": passes, "total": total}
+        avg_us = 1e3 * walk_ms / max(walk_launches, 1)
+        if policy == "greedy":
+            achieved = (walk_bytes / 1e9) / (walk_ms / 1e3) if walk_ms > 0 else 0.0
+            r["roofline"] = {"kernel": "k_walk_greedy", "bound": "hbm", "achieved": achieved,
+                             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                             "traffic": _traffic() if name == DEFAULT_WORKLOAD else None,
+                             "bytes_per_launch": walk_bytes / max(walk_launches, 1),
+                             "avg_launch_us": avg_us, "launches": walk_launches}
+        else:
+            achieved = (walk_flops / 1e12) / (walk_ms / 1e3) if walk_ms > 0 else 0.0
+            r["roofline"] = {"kernel": "k_walk_mlp", "bound": "mfma", "achieved": achieved,
+                             "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                             "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                             "flops_per_launch": walk_flops / max(walk_launches, 1),
+                             "avg_launch_us": avg_us, "launches": walk_launches}
+        if serial:
+            api.pk_serial_simulate(prob, policy)  # warm
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            ser = api.pk_serial_simulate(prob, policy)
+            torch.cuda.synchronize()
+            sdt = time.perf_counter() - t1
+            r["serial_gpu"] = {"value": total / sdt, "unit": "orders/s", "seconds": sdt,
+                               "identical_actions": bool(torch.equal(ser["actions"], out["actions"]))}
+            r["speedup_vs_serial_gpu"] = r["value"] / (total / sdt)
+        return r
 
-    res = {"metric": METRIC, "value": value, "unit": "orders/s", "n_gpus": 1,
-           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+    m = run(args.workload, args.steps, args.warmup, args.warmup_seconds, args.block_len,
+            not args.no_serial)
+    inst, policy, passes = m["inst"], m["policy"], m["passes"]
+    res = {"metric": METRIC, "value": m["value"], "unit": "orders/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": m["ms_per_step"],
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "int32" if policy == "greedy" else "f32", "data": "synthetic",
            "config": {"workload": args.workload, "policy": policy, "n_warehouses": inst.N,
                       "n_skus": inst.K, "n_regions": inst.R, "n_traj": inst.n_traj,
-                      "orders": total, "block_len": B, "parallelism": "1 GPU"},
-           "passes_max": int(passes.max()), "passes_mean": float(passes.mean())}
-
-    achieved = (walk_bytes / 1e9) / (walk_ms / 1e3) if walk_ms > 0 else 0.0
-    res["roofline"] = {"kernel": "k_walk_greedy" if policy == "greedy" else "k_walk_mlp",
-                       "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                       "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                       "traffic": _traffic(),
-                       "bytes_per_launch": walk_bytes / max(walk_launches, 1),
-                       "avg_launch_us": 1e3 * walk_ms / max(walk_launches, 1),
-                       "launches": walk_launches}
-
-    if not args.no_serial:
-        api.pk_serial_simulate(prob, policy)  # warm
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        ser = api.pk_serial_simulate(prob, policy)
-        torch.cuda.synchronize()
-        sdt = time.perf_counter() - t1
-        same = bool(torch.equal(ser["actions"], out["actions"]))
-        res["serial_gpu"] = {"value": total / sdt, "unit": "orders/s", "seconds": sdt,
-                             "identical_actions": same}
-        res["speedup_vs_serial_gpu"] = value / (total / sdt)
+                      "orders": m["total"], "block_len": m["B"], "parallelism": "1 GPU"},
+           "passes_max": int(passes.max()), "passes_mean": float(passes.mean()),
+           "roofline": m["roofline"]}
+    for k in ("serial_gpu", "speedup_vs_serial_gpu"):
+        if k in m:
+            res[k] = m[k]
+    if not args.no_learned and policy == "greedy":
+        # the learned policy on its own workload (64 trajectories), a shorter run
+        lm = run(LEARNED_WORKLOAD, 2, 1, 0.5, 0, True)
+        res["learned"] = {"workload": LEARNED_WORKLOAD, "value": lm["value"], "unit": "orders/s",
+                          "ms_per_step": lm["ms_per_step"], "orders": lm["total"],
+                          "block_len": lm["B"], "passes_max": int(lm["passes"].max()),
+                          "passes_mean": float(lm["passes"].mean()), "dtype": "f32",
+                          "roofline": lm["roofline"], "serial_gpu": lm["serial_gpu"],
+                          "speedup_vs_serial_gpu": lm["speedup_vs_serial_gpu"]}
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(inst)
     res["paper_context"] = ("paper (A100 40GB, JAX, 16-bit): 441x Picard speed-up over a "

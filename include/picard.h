@@ -137,6 +137,8 @@ typedef struct pk_stats {
                                 with HIP events on `stream` when timing is requested) */
     int64_t walk_launches;   /* launches of that kernel that did work */
     int64_t walk_bytes;      /* algorithmic HBM bytes of those launches */
+    int64_t walk_flops;      /* MLP: algorithmic FLOPs of the rows those launches scored
+                                (one row per order and warehouse with stock) */
     int32_t timing;          /* in: nonzero to record walk_ms / walk_bytes */
 } pk_stats;
 

@@ -63,7 +63,8 @@ class pk_stats(C.Structure):
     _fields_ = [("passes", C.c_void_p), ("passes_max", C.c_int32), ("block_len", C.c_int32),
                 ("changed_total", C.c_int64), ("runs_walked", C.c_int64),
                 ("orders_walked", C.c_int64), ("near_ties", C.c_int64), ("walk_ms", C.c_double),
-                ("walk_launches", C.c_int64), ("walk_bytes", C.c_int64), ("timing", C.c_int32)]
+                ("walk_launches", C.c_int64), ("walk_bytes", C.c_int64), ("walk_flops", C.c_int64),
+                ("timing", C.c_int32)]
 
 
 _lib = None

@@ -510,6 +510,7 @@ pk_status picard_run(const pk_problem *problem, const Dims &d, const pk_policy *
         stats->orders_walked = (int64_t)sum[ST_ORDERS];
         stats->near_ties = (int64_t)sum[ST_NEAR_TIES];
         stats->walk_bytes = (int64_t)sum[ST_BYTES];
+        stats->walk_flops = (int64_t)sum[ST_FLOPS];
         stats->walk_ms = graph_walk_ms;
         stats->walk_launches = (int64_t)(evs.size() / 2) + graph_walks;
         for (size_t i = 0; i + 1 < evs.size(); i += 2) {

@@ -28,8 +28,8 @@ namespace {
 using namespace mlpdev;
 
 // One workgroup walks one run (a process's orders of one SKU) from its entry state,
-// order by order: all waves score the order's warehouses, wave 0 takes the argmax and
-// applies f.  Same run bookkeeping as the greedy walk (entry state from the segmented
+// order by order: all waves score the order's warehouses with stock (kept as a list that
+// loses a warehouse when it empties), wave 0 takes the argmax and applies f.  Same run bookkeeping as the greedy walk (entry state from the segmented
 // scan, u of split runs, final inventory of a SKU's last run, restart frontier).
 __global__ __launch_bounds__(256) void k_walk_mlp(Prob P, Plan L, const float *params, int layers,
                                                   const float *costT, int32_t *final_inv,
@@ -40,7 +40,9 @@ __global__ __launch_bounds__(256) void k_walk_mlp(Prob P, Plan L, const float *p
     int32_t *x = (int32_t *)smem;
     int32_t *cons = x + N;
     float *zbuf = (float *)(cons + N);
-    int32_t *flag = (int32_t *)(zbuf + N); // [0] changed, [1] near ties
+    int32_t *sl = (int32_t *)(zbuf + N); // warehouses with stock
+    int32_t *pos = sl + N;               // index of each in sl
+    int32_t *flag = pos + N;             // [0] changed, [1] near ties, [2] stock list length
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     Ctl *ctl = L.ctl;
     if (ctl->done) return;
@@ -55,6 +57,7 @@ __global__ __launch_bounds__(256) void k_walk_mlp(Prob P, Plan L, const float *p
     const bool need_E = !first || has_init;
     int lcp_b = -1; // last trajectory this wave marked as changed in this pass
     unsigned long long n_orders = 0, n_runs = 0, n_changed = 0, n_bytes = 0, n_ties = 0;
+    unsigned long long n_rows = 0; // scored (order, warehouse with stock) rows
     for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
         const int s = all ? item : L.split_list[item];
         const int g = L.sr_seg[s];
@@ -78,15 +81,18 @@ __global__ __launch_bounds__(256) void k_walk_mlp(Prob P, Plan L, const float *p
         }
         if (threadIdx.x == 0) { flag[0] = 0; flag[1] = 0; }
         __syncthreads();
+        build_stock_list(x, N, sl, pos, &flag[2]);
+        __syncthreads();
         for (int p = lo; p < hi; ++p) {
             const int r = L.s_region[p];
             const uint32_t t = (uint32_t)L.s_t[p];
-            score_order(m, costT + ((int64_t)b * R + r) * N, m.E + (int64_t)r * 16, x, N, P.seed,
-                        (uint32_t)b, t, zbuf, nullptr);
+            const int nf = flag[2];
+            score_list(m, costT + ((int64_t)b * R + r) * N, m.E + (int64_t)r * 16, x, sl, nf, P.seed,
+                       (uint32_t)b, t, zbuf);
             __syncthreads();
             if (wave == 0) {
                 float z1, z2;
-                const int a = argmax_top2(zbuf, N, z1, z2);
+                const int a = argmax_list(zbuf, sl, nf, z1, z2);
                 if (lane == 0) {
                     const int q = L.s_qty[p];
                     int sh = 0;
@@ -94,7 +100,9 @@ __global__ __launch_bounds__(256) void k_walk_mlp(Prob P, Plan L, const float *p
                         sh = q < x[a] ? q : x[a];
                         x[a] -= sh;
                         cons[a] += q;
+                        if (x[a] == 0) drop_from_list(a, sl, pos, &flag[2]);
                     }
+                    n_rows += nf;
                     if (L.s_alpha[p] != a) { flag[0] += 1; }
                     if (near_tie(z1, z2)) flag[1] += 1;
                     L.s_alpha[p] = a;
@@ -136,14 +144,15 @@ __global__ __launch_bounds__(256) void k_walk_mlp(Prob P, Plan L, const float *p
         atomicAdd(&st[ST_CHANGED], n_changed);
         atomicAdd(&st[ST_BYTES], n_bytes);
         atomicAdd(&st[ST_NEAR_TIES], n_ties);
+        atomicAdd(&st[ST_FLOPS], n_rows * row_flops(layers));
     }
     walk_finish(ctl, lcp_b >= 0);
 }
 
 // Serial sweep: one workgroup per trajectory walks its orders in time order with the
 // trajectory's stock in `state` ([K][N], initialised to x0); per order the SKU's stock
-// row is read into LDS, scored by the same scorer, and the chosen warehouse's stock is
-// written back.
+// row is read into LDS, its warehouses with stock are listed and scored by the same
+// scorer, and the chosen warehouse's stock is written back.
 __global__ __launch_bounds__(256) void k_serial_mlp(Prob P, const float *params, int layers,
                                                    const float *costT, int32_t *state,
                                                    int32_t *actions, int32_t *shipped)
@@ -152,6 +161,9 @@ __global__ __launch_bounds__(256) void k_serial_mlp(Prob P, const float *params,
     const int N = P.N, R = P.R;
     int32_t *x = (int32_t *)smem;
     float *zbuf = (float *)(x + N);
+    int32_t *sl = (int32_t *)(zbuf + N);
+    int32_t *pos = sl + N;
+    int32_t *nfp = pos + N;
     const int b = blockIdx.x;
     if (b >= P.n_traj) return;
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
@@ -167,12 +179,15 @@ __global__ __launch_bounds__(256) void k_serial_mlp(Prob P, const float *params,
         int32_t *xk = xs + (int64_t)k * N;
         for (int w = threadIdx.x; w < N; w += blockDim.x) x[w] = xk[w];
         __syncthreads();
-        score_order(m, costT + ((int64_t)b * R + r) * N, m.E + (int64_t)r * 16, x, N, P.seed,
-                    (uint32_t)b, (uint32_t)(t - t0), zbuf, nullptr);
+        build_stock_list(x, N, sl, pos, nfp);
+        __syncthreads();
+        const int nf = *nfp;
+        score_list(m, costT + ((int64_t)b * R + r) * N, m.E + (int64_t)r * 16, x, sl, nf, P.seed,
+                   (uint32_t)b, (uint32_t)(t - t0), zbuf);
         __syncthreads();
         if (wave == 0) {
             float z1, z2;
-            const int a = argmax_top2(zbuf, N, z1, z2);
+            const int a = argmax_list(zbuf, sl, nf, z1, z2);
             if (lane == 0) {
                 int sh = 0;
                 if (a >= 0) {
@@ -236,7 +251,7 @@ hipError_t setup_costT(const Prob &P, float *costT, hipStream_t st)
     return hipGetLastError();
 }
 
-size_t walk_mlp_lds(int N) { return (size_t)N * 12 + 64; }
+size_t walk_mlp_lds(int N) { return (size_t)N * 20 + 64; }
 
 hipError_t launch_walk_mlp(const Prob &P, const Plan &L, const float *params, int layers,
                            const float *costT, int32_t *final_inv, bool has_init, int grid,
@@ -250,7 +265,7 @@ hipError_t launch_walk_mlp(const Prob &P, const Plan &L, const float *params, in
 hipError_t launch_serial_mlp(const Prob &P, const float *params, int layers, const float *costT,
                              int32_t *state, int32_t *actions, int32_t *shipped, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_serial_mlp, dim3(P.n_traj), dim3(256), (size_t)P.N * 8 + 64, st, P,
+    hipLaunchKernelGGL(k_serial_mlp, dim3(P.n_traj), dim3(256), (size_t)P.N * 16 + 64, st, P,
                        params, layers, costT, state, actions, shipped);
     return hipGetLastError();
 }

@@ -180,6 +180,91 @@ __device__ __forceinline__ void score_order(const MlpLane &m, const float *costT
     }
 }
 
+// Perturbed scores of the warehouses in the stock list sl[0..nf) into zbuf[w], by all
+// waves of the workgroup (tiles of 16 listed warehouses: wave w takes tiles w,
+// w + nwaves, ...).  Warehouses without stock are not scored.
+__device__ __forceinline__ void score_list(const MlpLane &m, const float *costT_r, const float *Er,
+                                           const int32_t *x, const int32_t *sl, int nf,
+                                           uint64_t seed, uint32_t traj, uint32_t t, float *zbuf)
+{
+    const int wave = threadIdx.x / WAVE, nwaves = blockDim.x / WAVE;
+    const int lane = __lane_id();
+    const int ntiles = (nf + 15) >> 4;
+    for (int tile = wave; tile < ntiles; tile += nwaves) {
+        const int i = tile * 16 + (lane & 15);
+        const bool valid = i < nf;
+        const int w = valid ? sl[i] : 0;
+        const int xv = valid ? x[w] : 0;
+        float f[5];
+        lane_features(f, valid ? costT_r[w] : 0.f, log1pf((float)xv), Er);
+        const float s = mlp_tile(m, f);
+        if (lane < 16 && valid) zbuf[w] = s + gumbel(seed, traj, t, (uint32_t)w);
+    }
+}
+
+// Argmax (with runner-up) of zbuf over the stock list sl[0..nf) by one wave.  Returns
+// the warehouse (lowest index on exact ties) or LOST when the list is empty.
+__device__ __forceinline__ int argmax_list(const float *zbuf, const int32_t *sl, int nf, float &z1,
+                                           float &z2)
+{
+    const int lane = __lane_id();
+    float b1 = -INFINITY, b2 = -INFINITY;
+    int w1 = 0x7fffffff;
+    for (int i = lane; i < nf; i += WAVE) {
+        const int w = sl[i];
+        top2_merge(b1, w1, b2, zbuf[w], w, -INFINITY);
+    }
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        const float o1 = __shfl_xor(b1, d, WAVE);
+        const int ow = __shfl_xor(w1, d, WAVE);
+        const float o2 = __shfl_xor(b2, d, WAVE);
+        top2_merge(b1, w1, b2, o1, ow, o2);
+    }
+    z1 = b1;
+    z2 = b2;
+    return b1 == -INFINITY ? LOST : w1;
+}
+
+// The list of warehouses with stock, x[w] > 0, in sl[0..*nf) with pos[w] its index
+// there; built by wave 0 (64 warehouses per ballot).  Callers synchronise after it.
+__device__ __forceinline__ void build_stock_list(const int32_t *x, int N, int32_t *sl, int32_t *pos,
+                                                 int32_t *nf)
+{
+    if (threadIdx.x >= WAVE) return;
+    const int lane = __lane_id();
+    int base = 0;
+    for (int c = 0; c < N; c += WAVE) {
+        const int w = c + lane;
+        const bool in = w < N && x[w] > 0;
+        const uint64_t m = __ballot(in);
+        if (in) {
+            const int i = base + __popcll(m & lanemask_lt());
+            sl[i] = w;
+            pos[w] = i;
+        }
+        base += __popcll(m);
+    }
+    if (lane == 0) *nf = base;
+}
+
+// Warehouse a has just emptied: drop it from the list (the last entry takes its place).
+__device__ __forceinline__ void drop_from_list(int a, int32_t *sl, int32_t *pos, int32_t *nf)
+{
+    const int i = pos[a];
+    const int last = sl[*nf - 1];
+    sl[i] = last;
+    pos[last] = i;
+    *nf -= 1;
+}
+
+// Algorithmic FLOPs of one scored row: 2 (18 * 64 + 64 * 64 + 64) with two hidden layers,
+// 2 (18 * 64 + 64) with one.
+__host__ __device__ inline unsigned long long row_flops(int layers)
+{
+    return layers == 2 ? 2ull * (18 * 64 + 64 * 64 + 64) : 2ull * (18 * 64 + 64);
+}
+
 // Argmax (with runner-up) over zbuf[0..N) by one wave.  Returns the warehouse or LOST.
 __device__ __forceinline__ int argmax_top2(const float *zbuf, int N, float &z1, float &z2)
 {

@@ -115,6 +115,7 @@ __global__ void k_split_count(Plan L, int32_t *cnt, int32_t *segcnt, int32_t n_s
     }
 }
 
+// Per segment: the list of split segments, and the split counts in the control block.
 __global__ void k_split_fill(Plan L, const int32_t *ubase, const int32_t *segbase,
                              int32_t n_seg_max)
 {
@@ -122,25 +123,30 @@ __global__ void k_split_fill(Plan L, const int32_t *ubase, const int32_t *segbas
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_seg; g += stride) {
         const int32_t s0 = L.seg_sr0[g], s1 = L.seg_sr0[g + 1];
-        const int32_t key = L.seg_key[g];
-        if (s1 - s0 > 1) {
-            const int32_t b = ubase[g];
-            for (int32_t s = s0; s < s1; ++s) {
-                L.sr_uidx[s] = b + (s - s0);
-                L.split_list[b + (s - s0)] = s;
-                L.rd[s] = RunDesc{L.sr_lo[s], L.sr_lo[s + 1], key, (int32_t)g, s - s0, s1 - s0,
-                                  b + (s - s0), 0};
-            }
-            L.split_segs[segbase[g]] = (int32_t)g;
-        } else {
-            L.sr_uidx[s0] = -1;
-            L.rd[s0] = RunDesc{L.sr_lo[s0], L.sr_lo[s0 + 1], key, (int32_t)g, 0, 1, -1, 0};
-        }
+        if (s1 - s0 > 1) L.split_segs[segbase[g]] = (int32_t)g;
         if (g == n_seg - 1) {
             const int32_t last = s1 - s0 > 1 ? s1 - s0 : 0;
             L.ctl->n_split = ubase[g] + last;
             L.ctl->n_split_seg = segbase[g] + (s1 - s0 > 1 ? 1 : 0);
         }
+    }
+}
+
+// Per run (one thread each): its row of u/E if its segment is split, its place in the
+// split list, and its descriptor.
+__global__ void k_run_desc(Plan L, const int32_t *ubase)
+{
+    const int n_sr = L.ctl->n_sr;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t si = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; si < n_sr; si += stride) {
+        const int32_t s = (int32_t)si;
+        const int32_t g = L.sr_seg[s];
+        const int32_t s0 = L.seg_sr0[g], s1 = L.seg_sr0[g + 1];
+        const bool split = s1 - s0 > 1;
+        const int32_t uidx = split ? ubase[g] + (s - s0) : -1;
+        L.sr_uidx[s] = uidx;
+        if (split) L.split_list[uidx] = s;
+        L.rd[s] = RunDesc{L.sr_lo[s], L.sr_lo[s + 1], L.seg_key[g], g, s - s0, s1 - s0, uidx, 0};
     }
 }
 
@@ -238,6 +244,8 @@ hipError_t setup_plan(const Prob &P, Plan &L, const int32_t *init_cache, int val
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_split_fill, dim3(grid_for(n_seg_max, 256, 8192)), dim3(256), 0, st, L,
                        cnt, segcnt, n_seg_max);
+    hipLaunchKernelGGL(k_run_desc, dim3(grid_for(n + n_seg_max, 256, 8192)), dim3(256), 0, st, L,
+                       cnt);
     return hipGetLastError();
 }
 
