@@ -51,6 +51,11 @@ def _traffic():
         return None
 
 
+def _progress(msg: str):
+    """One line per finished stage, on stderr (stdout carries only the result line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def copy_calibration(nbytes: int, reps: int = 3):
     """A plain device-to-device copy of known size (the yardstick for the HBM byte
     counters: FETCH_SIZE and WRITE_SIZE of one copy dispatch against nbytes)."""
@@ -96,6 +101,11 @@ def main():
     ap.add_argument("--block-len", type=int, default=0)
     ap.add_argument("--no-serial", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serial-prefix", type=int, default=0, metavar="M",
+                    help="time the serial sweep on the first M orders of each trajectory "
+                         "(for workloads whose full serial sweep runs for minutes)")
+    ap.add_argument("--with-grad", action="store_true",
+                    help="learned workloads: also time pk_policy_grad at the final actions")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-policy leg (greedy workloads only)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -113,13 +123,30 @@ def main():
     from paper_2406_01939_amd import api
     from paper_2406_01939_amd.instances import make_instance
 
-    def run(name, steps, warmup, warmup_s, block_len, serial):
+    def prefix_problem(prob, m):
+        """The same problem restricted to the first m orders of every trajectory (the
+        serial rollout of a prefix is the prefix of the serial rollout)."""
+        offs = prob.traj_offsets
+        idx = np.concatenate([np.arange(offs[b], min(offs[b] + m, offs[b + 1]))
+                              for b in range(prob.n_traj)])
+        new = np.zeros_like(offs)
+        new[1:] = np.cumsum(np.minimum(np.diff(offs), m))
+        it = torch.from_numpy(idx).cuda()
+        sub = api.DeviceProblem(N=prob.N, K=prob.K, R=prob.R, traj_offsets=new,
+                                sku=prob.sku[it].contiguous(), region=prob.region[it].contiguous(),
+                                qty=prob.qty[it].contiguous(), init_inv=prob.init_inv,
+                                cost=prob.cost, rng_seed=prob.rng_seed, params=prob.params,
+                                n_hidden_layers=prob.n_hidden_layers, hidden=prob.hidden)
+        return sub, it
+
+    def run(name, steps, warmup, warmup_s, block_len, serial, with_grad=False, serial_prefix=0):
         """Time `steps` simulations of workload `name` (after the warm-up) and, if asked,
         one serial GPU sweep of it; the walk kernel's roofline from the same steps."""
         inst = make_instance(name)
         policy = "mlp" if inst.params is not None else "greedy"
         prob = api.DeviceProblem.from_instance(inst)
         torch.cuda.synchronize()
+        _progress(f"{name}: {inst.total_orders} orders on the GPU")
         total = inst.total_orders
         B = block_len if block_len > 0 else api.pk_autotune(prob, policy)
         # warm-up: at least `warmup` steps and `warmup_s` seconds of work (an idle GPU
@@ -145,6 +172,7 @@ def main():
             passes = out["passes"]
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        _progress(f"{name}: {steps} timed simulations, {dt:.3f} s")
         r = {"value": total * steps / dt, "ms_per_step": 1e3 * dt / steps, "inst": inst,
              "policy": policy, "B": B, "passes": passes, "total": total}
         avg_us = 1e3 * walk_ms / max(walk_launches, 1)
@@ -163,19 +191,41 @@ def main():
                              "flops_per_launch": walk_flops / max(walk_launches, 1),
                              "avg_launch_us": avg_us, "launches": walk_launches}
         if serial:
-            api.pk_serial_simulate(prob, policy)  # warm
+            sprob, it, stotal = prob, None, total
+            if 0 < serial_prefix < int(np.diff(prob.traj_offsets).max()):
+                sprob, it = prefix_problem(prob, serial_prefix)
+                stotal = sprob.total
+            else:
+                api.pk_serial_simulate(sprob, policy)  # warm
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            ser = api.pk_serial_simulate(prob, policy)
+            ser = api.pk_serial_simulate(sprob, policy)
             torch.cuda.synchronize()
             sdt = time.perf_counter() - t1
-            r["serial_gpu"] = {"value": total / sdt, "unit": "orders/s", "seconds": sdt,
-                               "identical_actions": bool(torch.equal(ser["actions"], out["actions"]))}
-            r["speedup_vs_serial_gpu"] = r["value"] / (total / sdt)
+            _progress(f"{name}: serial sweep of {stotal} orders {sdt:.3f} s")
+            want = out["actions"] if it is None else out["actions"][it]
+            r["serial_gpu"] = {"value": stotal / sdt, "unit": "orders/s", "seconds": sdt,
+                               "orders": stotal,
+                               "identical_actions": bool(torch.equal(ser["actions"], want))}
+            if it is not None:
+                r["serial_gpu"]["prefix_per_trajectory"] = serial_prefix
+            r["speedup_vs_serial_gpu"] = r["value"] / (stotal / sdt)
+        if with_grad and policy == "mlp":
+            from paper_2406_01939_amd.autograd import reward_to_go_advantages
+            adv = reward_to_go_advantages(prob, out["actions"], out["shipped"])
+            _progress(f"{name}: policy gradient")
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            g = api.pk_policy_grad(prob, out["actions"], adv)
+            torch.cuda.synchronize()
+            gdt = time.perf_counter() - t2
+            _progress(f"{name}: policy gradient {gdt:.3f} s")
+            r["policy_grad"] = {"seconds": gdt, "orders_per_s": total / gdt,
+                                "objective": g["objective"]}
         return r
 
     m = run(args.workload, args.steps, args.warmup, args.warmup_seconds, args.block_len,
-            not args.no_serial)
+            not args.no_serial, args.with_grad, args.serial_prefix)
     inst, policy, passes = m["inst"], m["policy"], m["passes"]
     res = {"metric": METRIC, "value": m["value"], "unit": "orders/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": m["ms_per_step"],
@@ -186,7 +236,7 @@ def main():
                       "orders": m["total"], "block_len": m["B"], "parallelism": "1 GPU"},
            "passes_max": int(passes.max()), "passes_mean": float(passes.mean()),
            "roofline": m["roofline"]}
-    for k in ("serial_gpu", "speedup_vs_serial_gpu"):
+    for k in ("serial_gpu", "speedup_vs_serial_gpu", "policy_grad"):
         if k in m:
             res[k] = m[k]
     if not args.no_learned and policy == "greedy":
@@ -198,7 +248,7 @@ def main():
                           "passes_mean": float(lm["passes"].mean()), "dtype": "f32",
                           "roofline": lm["roofline"], "serial_gpu": lm["serial_gpu"],
                           "speedup_vs_serial_gpu": lm["speedup_vs_serial_gpu"]}
-    if not args.no_cpu:
+    if not args.no_cpu and inst.x0 is not None:
         res["cpu_baseline"] = cpu_baseline(inst)
     res["paper_context"] = ("paper (A100 40GB, JAX, 16-bit): 441x Picard speed-up over a "
                             "sequential GPU rollout at 3M orders / 1M products / 30 nodes, "

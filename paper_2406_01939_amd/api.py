@@ -143,10 +143,16 @@ class DeviceProblem:
     def from_instance(cls, inst, device="cuda") -> "DeviceProblem":
         def up(a, dt):
             return torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dt)
+        if inst.x0 is not None:
+            x0 = up(inst.x0, torch.int32)
+        else:  # drawn on the device by the instance's counter-based generators
+            x0 = torch.empty((inst.n_traj, inst.K, inst.N), dtype=torch.int32, device=device)
+            for b in range(inst.n_traj):
+                inst.x0_gen[b].device(b, inst.N, x0[b])
         return cls(N=inst.N, K=inst.K, R=inst.R,
                    traj_offsets=np.ascontiguousarray(inst.traj_offsets, dtype=np.int64),
                    sku=up(inst.sku, torch.int32), region=up(inst.region, torch.int32),
-                   qty=up(inst.qty, torch.int32), init_inv=up(inst.x0, torch.int32),
+                   qty=up(inst.qty, torch.int32), init_inv=x0,
                    cost=up(inst.cost, torch.int32), rng_seed=int(inst.rng_seed) & (2**64 - 1),
                    params=None if inst.params is None else up(inst.params, torch.float32),
                    n_hidden_layers=inst.n_hidden_layers, hidden=inst.hidden)

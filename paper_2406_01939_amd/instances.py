@@ -11,7 +11,11 @@ generation) is not available, so every instance here is synthetic:
   -cost[w, r], with integer cost uniform in 1..100 (stands in for the distance reward);
 * quantity: 1, or a geometric(p=0.6) law truncated to 1..qmax and renormalised;
 * initial inventory x0[k, w] ~ Poisson(0.8 * T * P(k) * E[q] / N): the network holds
-  80% of expected demand (Appendix A.3), split evenly over warehouses;
+  80% of expected demand (Appendix A.3), split evenly over warehouses.  For the largest
+  workload (16 x 1e6 SKUs x 500 warehouses = 8e9 values) the draws come from a
+  counter-based generator instead, so they can be made on the GPU and any row recomputed
+  on the CPU: a 32-bit hash of (seed, trajectory, SKU, warehouse) inverted through the
+  Poisson CDF of the SKU (`PoissonX0`);
 * learned-policy parameters: PyTorch-default-style uniform init, embedding ~ N(0, 1).
 
 This module is shared by the CPU oracle's tests and by the GPU path's tests and
@@ -42,8 +46,81 @@ WORKLOADS: Dict[str, dict] = {
                                        policy="mlp"),
     "mlp_batch16_n500_k1e6_t1e7": dict(N=500, K=1_000_000, R=500, T=10_000_000,
                                        qmax=4, n_traj=16, seed0=5000, theta_seed=5999,
-                                       policy="mlp"),
+                                       policy="mlp", x0_hashed=True),
 }
+
+_M32 = 0xFFFFFFFF
+
+
+def _fmix32(h, xp):
+    """MurmurHash3's 32-bit finaliser on non-negative integers below 2^32, for numpy
+    (uint64 arrays) and torch (int64 tensors) alike; products wrap mod 2^64 and only their
+    low 32 bits are kept."""
+    h = h ^ (h >> 16)
+    h = (h * 0x85EBCA6B) & _M32
+    h = h ^ (h >> 13)
+    h = (h * 0xC2B2AE35) & _M32
+    return h ^ (h >> 16)
+
+
+class PoissonX0:
+    """Counter-based Poisson draws x0[b, k, w] ~ Poisson(lam_k).
+
+    u = hash(seed, b, k, w) is uniform on 32 bits; x0 = the number of thresholds
+    floor(2^32 F_k(j)), j = 0, 1, ..., that are <= u (inverse CDF, F_k the Poisson(lam_k)
+    CDF, tables cut where the tail is below 2^-32).  The thresholds of all SKUs are kept in
+    one sorted array with SKU k's shifted by k * 2^32, so one search per value finds its
+    count."""
+
+    _tables: Dict[bytes, tuple] = {}  # one table per distinct lam vector
+
+    def __init__(self, lam: np.ndarray, seed: int):
+        lam = np.asarray(lam, dtype=np.float64)
+        self.K = lam.size
+        self.seed = int(seed) & _M32
+        key = lam.tobytes()
+        if key not in PoissonX0._tables:
+            from scipy.stats import poisson
+            jmax = np.ceil(lam + 12.0 * np.sqrt(lam) + 4.0).astype(np.int64)
+            off = np.zeros(self.K + 1, dtype=np.int64)
+            off[1:] = np.cumsum(jmax)
+            k_of = np.repeat(np.arange(self.K, dtype=np.int64), jmax)
+            j = np.arange(int(off[-1]), dtype=np.int64) - off[k_of]
+            F = poisson.cdf(j, lam[k_of])
+            th = np.minimum(np.floor(F * 4294967296.0), 4294967295.0).astype(np.int64)
+            PoissonX0._tables = {key: (off, (k_of << 32) | th)}  # keep the latest only
+        self.off, self.table = PoissonX0._tables[key]  # table sorted: SKU-major
+
+    def _u(self, b, k, w, xp):
+        hb = _fmix32((self.seed ^ _fmix32(b + 0x9E3779B9, xp)) & _M32, xp)
+        h = _fmix32(hb ^ _fmix32(k + 0x7F4A7C15, xp), xp)
+        return _fmix32(h ^ _fmix32(w + 0x165667B1, xp), xp)
+
+    def rows(self, b: int, ks: np.ndarray, N: int) -> np.ndarray:
+        """x0[b, ks, :] on the CPU (int32 [len(ks), N])."""
+        ks = np.asarray(ks, dtype=np.uint64)
+        w = np.arange(N, dtype=np.uint64)
+        u = self._u(np.uint64(b), ks[:, None], w[None, :], np)
+        key = (ks[:, None].astype(np.int64) << 32) | u.astype(np.int64)
+        cnt = np.searchsorted(self.table, key, side="right") - self.off[ks.astype(np.int64)][:, None]
+        return cnt.astype(np.int32)
+
+    def device(self, b: int, N: int, out, chunk: int = 1 << 17):
+        """Fill out (a torch int32 [K, N] tensor on the GPU) with x0[b]."""
+        import torch
+        dev = out.device
+        table = torch.from_numpy(self.table).to(dev)
+        off = torch.from_numpy(self.off).to(dev)
+        w = torch.arange(N, device=dev, dtype=torch.int64)
+        hb = _fmix32((self.seed ^ _fmix32(torch.tensor(b + 0x9E3779B9, dtype=torch.int64, device=dev), torch)) & _M32, torch)
+        hw = _fmix32(w + 0x165667B1, torch)
+        for k0 in range(0, self.K, chunk):
+            k = torch.arange(k0, min(self.K, k0 + chunk), device=dev, dtype=torch.int64)
+            h = _fmix32(hb ^ _fmix32(k + 0x7F4A7C15, torch), torch)
+            u = _fmix32(h[:, None] ^ hw[None, :], torch)
+            key = (k[:, None] << 32) | u
+            cnt = torch.searchsorted(table, key, right=True) - off[k][:, None]
+            out[k0:k0 + k.numel()] = cnt.to(torch.int32)
 
 
 @dataclasses.dataclass
@@ -63,6 +140,13 @@ class Instance:
     hidden: int = 64
     n_hidden_layers: int = 2
     name: str = ""
+    x0_gen: Optional[List["PoissonX0"]] = None  # per trajectory, when x0 is None
+
+    def x0_rows(self, b: int, ks) -> np.ndarray:
+        """Initial inventory rows x0[b, ks, :] (from x0 or recomputed by its generator)."""
+        if self.x0 is not None:
+            return self.x0[b, np.asarray(ks)]
+        return self.x0_gen[b].rows(b, np.asarray(ks), self.N)
 
     @property
     def n_traj(self) -> int:
@@ -81,7 +165,8 @@ class Instance:
         return dataclasses.replace(
             self, traj_offsets=np.array([0, hi - lo], dtype=np.int64),
             sku=self.sku[lo:hi], region=self.region[lo:hi], qty=self.qty[lo:hi],
-            x0=self.x0[b:b + 1], cost=self.cost[b:b + 1])
+            x0=None if self.x0 is None else self.x0[b:b + 1], cost=self.cost[b:b + 1],
+            x0_gen=None if self.x0_gen is None else [self.x0_gen[b]])
 
 
 def zipf_probs(K: int, exponent: float = 1.1) -> np.ndarray:
@@ -117,9 +202,14 @@ def make_params(R: int, seed: int, hidden: int = 64, n_hidden_layers: int = 2) -
     return out
 
 
-def make_trajectory(N: int, K: int, R: int, T: int, qmax: int, seed: int):
-    """One trajectory's orders, cost table and initial inventory."""
+def make_trajectory(N: int, K: int, R: int, T: int, qmax: int, seed: int,
+                    x0_hashed: bool = False, T_orders: Optional[int] = None):
+    """One trajectory's orders, cost table and initial inventory (the inventory's scale
+    follows T; T_orders, if given, is the number of orders drawn; with x0_hashed the
+    inventory is returned as its generator)."""
     rng = np.random.default_rng(seed)
+    T_lam = T
+    T = T if T_orders is None else int(T_orders)
     pk = zipf_probs(K)
     cdf = np.cumsum(pk)
     cdf[-1] = 1.0
@@ -135,10 +225,13 @@ def make_trajectory(N: int, K: int, R: int, T: int, qmax: int, seed: int):
         qty = np.minimum(np.searchsorted(qcdf, rng.random(T), side="right"), qmax - 1) + 1
         mean_q = float((np.arange(1, qmax + 1) * pq).sum())
     cost = rng.integers(1, 101, size=(N, R))
-    lam = 0.8 * T * pk * mean_q / N
-    x0 = rng.poisson(lam[:, None], size=(K, N))
+    lam = 0.8 * T_lam * pk * mean_q / N
+    if x0_hashed:
+        x0 = PoissonX0(lam, seed)
+    else:
+        x0 = rng.poisson(lam[:, None], size=(K, N)).astype(np.int32)
     return (sku.astype(np.int32), region.astype(np.int32), qty.astype(np.int32),
-            cost.astype(np.int32), x0.astype(np.int32))
+            cost.astype(np.int32), x0)
 
 
 def make_instance(name: str, **overrides) -> Instance:
@@ -147,24 +240,33 @@ def make_instance(name: str, **overrides) -> Instance:
     cfg.update(overrides)
     N, K, R, n_traj, qmax = cfg["N"], cfg["K"], cfg["R"], cfg["n_traj"], cfg["qmax"]
     T = cfg["T"]
+    hashed = bool(cfg.get("x0_hashed", False))
+    T_orders = cfg.get("T_orders")
     if isinstance(T, tuple):
         lo, hi = T
         Ts = np.random.default_rng(cfg["t_seed"]).integers(lo, hi + 1, size=n_traj)
     else:
         Ts = np.full(n_traj, int(T), dtype=np.int64)
+    To = Ts if T_orders is None else np.minimum(Ts, int(T_orders))
     offs = np.zeros(n_traj + 1, dtype=np.int64)
-    offs[1:] = np.cumsum(Ts)
+    offs[1:] = np.cumsum(To)
     total = int(offs[-1])
     sku = np.empty(total, np.int32)
     region = np.empty(total, np.int32)
     qty = np.empty(total, np.int32)
-    x0 = np.empty((n_traj, K, N), np.int32)
+    x0 = None if hashed else np.empty((n_traj, K, N), np.int32)
+    gens = [] if hashed else None
     cost = np.empty((n_traj, N, R), np.int32)
     for b in range(n_traj):
-        s, r, q, c, x = make_trajectory(N, K, R, int(Ts[b]), qmax, cfg["seed0"] + b)
+        s, r, q, c, x = make_trajectory(N, K, R, int(Ts[b]), qmax, cfg["seed0"] + b, hashed,
+                                        int(To[b]))
         sl = slice(int(offs[b]), int(offs[b + 1]))
         sku[sl], region[sl], qty[sl] = s, r, q
-        cost[b], x0[b] = c, x
+        cost[b] = c
+        if hashed:
+            gens.append(x)
+        else:
+            x0[b] = x
     params = None
     hidden = cfg.get("hidden", 64)
     nhl = cfg.get("n_hidden_layers", 2)
@@ -173,7 +275,7 @@ def make_instance(name: str, **overrides) -> Instance:
     rng_seed = (int(cfg.get("theta_seed", 0)) << 32) | int(cfg["seed0"])
     return Instance(N=N, K=K, R=R, traj_offsets=offs, sku=sku, region=region, qty=qty,
                     x0=x0, cost=cost, rng_seed=rng_seed, params=params, hidden=hidden,
-                    n_hidden_layers=nhl, name=name)
+                    n_hidden_layers=nhl, name=name, x0_gen=gens)
 
 
 def random_tiny(seed: int, N: int = 4, K: int = 3, R: int = 3, T: int = 12, qmax: int = 1,

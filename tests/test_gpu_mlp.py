@@ -134,7 +134,8 @@ def test_batch_shaped_like_large_workload(api, oracle):
 def test_wide_policy_shape(api, oracle):
     """N=500 warehouses, R=500 regions, quantities 1..4 (the 16-trajectory learned
     workload's policy shape), reduced to 2 trajectories of 3000 orders over 1e4 SKUs."""
-    inst = make_instance("mlp_batch16_n500_k1e6_t1e7", n_traj=2, T=3000, K=10_000)
+    inst = make_instance("mlp_batch16_n500_k1e6_t1e7", n_traj=2, T=3000, K=10_000,
+                         x0_hashed=False)
     prob = api.DeviceProblem.from_instance(inst)
     _say("case mlp N=500 R=500")
     out = api.pk_picard_simulate(prob, "mlp", block_len=128)
@@ -143,3 +144,50 @@ def test_wide_policy_shape(api, oracle):
     _say(f"mismatches at near-ties: {mism}, near-ties: {ties}, passes {out['passes']}")
     ser = api.pk_serial_simulate(prob, "mlp")
     assert torch.equal(ser["actions"], out["actions"])
+
+
+def test_large_workload_full_shape_prefix(api, oracle):
+    """The 16-trajectory learned workload at its full shape: N=500, K=1e6, R=500,
+    quantities 1..4, inventory drawn on the GPU for T=1e7 (8e9 values), orders cut to the
+    first 2e4 of each trajectory.  Picard equals the GPU serial sweep bit for bit; on 300
+    sampled orders the FP64 policy at the state the GPU actions induce picks the GPU's
+    action, except at near-ties."""
+    from paper_2406_01939_amd.instances import Instance
+    inst = make_instance("mlp_batch16_n500_k1e6_t1e7", T_orders=20_000)
+    _say(f"case large learned prefix total={inst.total_orders}")
+    prob = api.DeviceProblem.from_instance(inst)
+    out = api.pk_picard_simulate(prob, "mlp", block_len=256)
+    ser = api.pk_serial_simulate(prob, "mlp")
+    assert torch.equal(ser["actions"], out["actions"])
+    assert torch.equal(ser["shipped"], out["shipped"])
+    acts = out["actions"].cpu().numpy()
+    _say(f"passes {out['passes'].tolist()}, gpu near-ties {out['stats']['near_ties']}")
+    rng = np.random.default_rng(11)
+    ties = 0
+    for _ in range(300):
+        b = int(rng.integers(0, inst.n_traj))
+        lo, hi = int(inst.traj_offsets[b]), int(inst.traj_offsets[b + 1])
+        t = int(rng.integers(lo, hi))
+        k, r = int(inst.sku[t]), int(inst.region[t])
+        x = inst.x0_rows(b, [k])[0].astype(np.int64)
+        for u in np.nonzero(inst.sku[lo:t] == k)[0] + lo:  # earlier orders of this SKU
+            a = int(acts[u])
+            if a >= 0:
+                x[a] -= min(int(inst.qty[u]), x[a])
+        stocked = np.nonzero(x > 0)[0]
+        if stocked.size == 0:
+            assert acts[t] == -1
+            continue
+        sub = Instance(N=inst.N, K=1, R=inst.R, traj_offsets=np.array([0, 0], np.int64),
+                       sku=np.zeros(0, np.int32), region=np.zeros(0, np.int32),
+                       qty=np.zeros(0, np.int32), x0=np.zeros((1, 1, inst.N), np.int32),
+                       cost=inst.cost[b:b + 1], rng_seed=inst.rng_seed, params=inst.params)
+        s = oracle.mlp_scores(sub, r, x.astype(np.int32))
+        z = np.array([s[w] + oracle.gumbel(inst.rng_seed, b, t - lo, int(w)) for w in stocked])
+        order = np.argsort(-z, kind="stable")
+        best = int(stocked[order[0]])
+        if acts[t] != best:
+            z1, z2 = z[order[0]], z[order[1]]
+            assert (z1 - z2) <= TIE * max(abs(z1), abs(z2)), (b, t - lo, best, int(acts[t]))
+            ties += 1
+    _say(f"sampled mismatches at near-ties: {ties}")
