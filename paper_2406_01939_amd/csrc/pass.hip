@@ -20,11 +20,18 @@ namespace {
 // i goes to workgroup i mod grid, so the long segments of the most frequent SKUs, which
 // are neighbours in key order, land in different workgroups): each thread checks one
 // segment's frontier, the segments with runs to walk are gathered in LDS, and the
-// workgroup then scans them one by one.  In a scan, threads cover warehouses and each
-// runs the scan over the segment's runs for its warehouse, 32 runs' consumption loaded
-// per batch so the loads overlap.  Runs up to the frontier are final and need no entry
-// state; their consumption only enters the prefix.  After the first pass the kernel also
-// lists the runs past the frontier (the ones the walk evaluates) in Plan::active.
+// workgroup then scans them one by one.  A segment's u rows are contiguous; they pass
+// through LDS a tile of rows at a time, loaded by the whole workgroup with every load
+// in flight, and the exclusive scan down each warehouse's column is done in LDS (one
+// thread per column, its running sum carried from tile to tile) and written out as E.
+// Runs up to the frontier are final and need no entry state; their consumption only
+// enters the prefix.  After the first pass the kernel also lists the runs past the
+// frontier (the ones the walk evaluates) in Plan::active.
+constexpr int SCAN_TILE = 12288;   // ints of u per LDS tile (48 KB), a multiple of 256
+constexpr int SCAN_MAXC = 4;       // columns per thread
+static_assert(SCAN_MAXC * 256 >= PK_MAX_WAREHOUSES && SCAN_TILE >= PK_MAX_WAREHOUSES,
+              "every warehouse needs a column thread and a tile at least one row");
+
 __global__ __launch_bounds__(256) void k_scan_entry(Prob P, Plan L, int skip_first_pass)
 {
     Ctl *ctl = L.ctl;
@@ -36,9 +43,10 @@ __global__ __launch_bounds__(256) void k_scan_entry(Prob P, Plan L, int skip_fir
     const int N = P.N;
     const int32_t *__restrict__ u = L.u;
     int32_t *__restrict__ E = L.E;
-    constexpr int BATCH = 32;
     __shared__ int32_t s_g[256], s_f[256];
     __shared__ int32_t s_cnt, s_base;
+    __shared__ int32_t tile[SCAN_TILE];
+    const int rpt = SCAN_TILE / N; // rows per tile
     for (int base = 0; base < n; base += gridDim.x * 256) {
         if (threadIdx.x == 0) s_cnt = 0;
         __syncthreads();
@@ -72,20 +80,54 @@ __global__ __launch_bounds__(256) void k_scan_entry(Prob P, Plan L, int skip_fir
             }
             const int jmin = f + 1 > 1 ? f + 1 : 1; // runs j > f need E_j; E_0 = 0
             const int64_t row0 = L.sr_uidx[s0];
-            for (int w = threadIdx.x; w < N; w += blockDim.x) {
-                int32_t acc = 0;
-                for (int jb = 0; jb < nsr; jb += BATCH) {
-                    int32_t v[BATCH];
+            int32_t acc[SCAN_MAXC];
 #pragma unroll
-                    for (int k = 0; k < BATCH; ++k)
-                        v[k] = jb + k < nsr ? u[(row0 + jb + k) * N + w] : 0;
+            for (int c = 0; c < SCAN_MAXC; ++c) acc[c] = 0;
+            for (int jt = 0; jt < nsr; jt += rpt) {
+                const int nr = nsr - jt < rpt ? nsr - jt : rpt;
+                const int nint = nr * N;
+                const int32_t *src = u + (row0 + jt) * N;
+                { // the tile: all of a thread's loads are issued before its first store
+                    int32_t v[SCAN_TILE / 256];
 #pragma unroll
-                    for (int k = 0; k < BATCH; ++k) {
-                        const int jj = jb + k;
-                        if (jj >= jmin && jj < nsr) E[(row0 + jj) * N + w] = acc;
-                        acc += v[k];
+                    for (int k = 0; k < SCAN_TILE / 256; ++k) {
+                        const int at = k * 256 + (int)threadIdx.x;
+                        v[k] = at < nint ? src[at] : 0;
+                    }
+#pragma unroll
+                    for (int k = 0; k < SCAN_TILE / 256; ++k) {
+                        const int at = k * 256 + (int)threadIdx.x;
+                        if (at < nint) tile[at] = v[k];
                     }
                 }
+                __syncthreads();
+                // exclusive scan down each column, in place
+#pragma unroll
+                for (int c = 0; c < SCAN_MAXC; ++c) {
+                    const int w = c * 256 + (int)threadIdx.x;
+                    if (w < N) {
+                        int32_t a = acc[c];
+                        for (int r0 = 0; r0 < nr; r0 += 8) { // 8 rows' loads, then their sums
+                            int32_t v[8];
+#pragma unroll
+                            for (int k = 0; k < 8; ++k) v[k] = r0 + k < nr ? tile[(r0 + k) * N + w] : 0;
+#pragma unroll
+                            for (int k = 0; k < 8; ++k) {
+                                if (r0 + k < nr) tile[(r0 + k) * N + w] = a;
+                                a += v[k];
+                            }
+                        }
+                        acc[c] = a;
+                    }
+                }
+                __syncthreads();
+                // E rows j >= jmin of this tile
+                const int r0 = jmin > jt ? jmin - jt : 0;
+                if (r0 < nr) {
+                    int32_t *dst = E + (row0 + jt) * N;
+                    for (int at = r0 * N + (int)threadIdx.x; at < nint; at += 256) dst[at] = tile[at];
+                }
+                __syncthreads();
             }
         }
         __syncthreads();

@@ -25,10 +25,33 @@ __device__ __forceinline__ void mask_out(uint32_t *M, int a)
 {
     if (M && __lane_id() == 0) M[a >> 1] |= (a & 1) ? 0xffff0000u : 0x0000ffffu;
 }
+// mask_out for any lane (two warehouses share a mask word: atomic)
+__device__ __forceinline__ void mask_out_lane(uint32_t *M, int a)
+{
+    if (M) atomicOr(&M[a >> 1], (a & 1) ? 0xffff0000u : 0x0000ffffu);
+}
+// drop() removes, at once, the warehouses of the lanes with emp set (at most one lane per
+// warehouse); every lane of the wave calls it.
 template <bool SF> struct StockSet;
 template <> struct StockSet<true> {
     uint64_t w0 = 0, w1 = 0;
     uint32_t *M = nullptr;
+    uint64_t *clr = nullptr; // two zeroed words of LDS
+    __device__ __forceinline__ void drop(bool emp, int a)
+    {
+        if (emp) {
+            atomicOr(&clr[a >> 6], 1ull << (a & 63));
+            mask_out_lane(M, a);
+        }
+        wave_sync();
+        const uint64_t c0 = clr[0], c1 = clr[1];
+        const uint32_t c0l = uni((int)(uint32_t)c0), c0h = uni((int)(uint32_t)(c0 >> 32));
+        const uint32_t c1l = uni((int)(uint32_t)c1), c1h = uni((int)(uint32_t)(c1 >> 32));
+        w0 &= ~(((uint64_t)c0h << 32) | c0l);
+        w1 &= ~(((uint64_t)c1h << 32) | c1l);
+        wave_sync();
+        if (__lane_id() < 2) clr[__lane_id()] = 0;
+    }
     __device__ __forceinline__ uint64_t word(int k) const { return k == 0 ? w0 : w1; }
     __device__ __forceinline__ bool has(int a) const { return ((a < 64 ? w0 : w1) >> (a & 63)) & 1ull; }
     __device__ __forceinline__ bool any() const { return (w0 | w1) != 0; }
@@ -53,6 +76,16 @@ template <> struct StockSet<false> {
             *n -= 1;
         }
         mask_out(M, a);
+    }
+    __device__ __forceinline__ void drop(bool emp, int a)
+    {
+        const int ne = __popcll(__ballot(emp));
+        if (emp) {
+            atomicAnd(&F[a >> 6], ~(1ull << (a & 63)));
+            mask_out_lane(M, a);
+        }
+        if (__lane_id() == 0) *n -= ne;
+        wave_sync();
     }
 };
 
@@ -170,9 +203,11 @@ __device__ __forceinline__ int choose(const KeyT *row, const StockSet<SF> &fs, i
 // chunk at a time.  The next run's descriptor is loaded while the current run is walked.
 // The key table of the run's trajectory is read from LDS (one copy per workgroup for a
 // single trajectory, one per wave for small tables) or from global memory.
-// Per wave LDS: x[N] stock, tot[N] step demand, cons[N] run consumption (unclamped, for
-// u), bw[R] memo, member count, F[ceil(N/64)], key masks M (16-bit keys), in-ring[128]
-// (region | (old+1) << 12, qty), out-ring[128] (action, shipped).
+// Per wave LDS: lm[N] (64-bit: the step's lanes per warehouse for unit demand; as int32,
+// the step's demand per warehouse otherwise; zero between steps), x[N] stock, cons[N] run
+// consumption (unclamped, for u), bw[R] memo, member count, F[ceil(N/64)] and two
+// zeroed words, key masks M (16-bit keys), in-ring[128] (region | (old+1) << 12, qty),
+// out-ring[128] (action, shipped).
 template <typename KeyT> __host__ __device__ inline size_t mask_bytes(int N)
 {
     return sizeof(KeyT) == 2 ? (size_t)tab_npad<KeyT>(N) * 2 : 0; // one bit pattern per key
@@ -180,8 +215,8 @@ template <typename KeyT> __host__ __device__ inline size_t mask_bytes(int N)
 template <typename KeyT> __host__ __device__ inline size_t walk_wave_bytes(int N, int R, int mode)
 {
     const size_t tb = (size_t)tab_stride<KeyT>(N, R) * sizeof(KeyT);
-    const size_t ints = ((size_t)(3 * N + R + 1) * 4 + 15) & ~(size_t)15;
-    const size_t f = ((size_t)8 * ((N + 63) / 64) + 15) & ~(size_t)15;
+    const size_t ints = ((size_t)8 * N + (size_t)(2 * N + R + 1) * 4 + 15) & ~(size_t)15;
+    const size_t f = ((size_t)8 * ((N + 63) / 64) + 16 + 15) & ~(size_t)15;
     return (mode == 1 ? tb : 0) + ints + f + mask_bytes<KeyT>(N) + 2 * 128 * sizeof(int2);
 }
 
@@ -201,18 +236,21 @@ __global__ __launch_bounds__(256) void k_walk_greedy(Prob P, Plan L, const KeyT 
     const int nw = (N + 63) / 64;
     const int npad = tab_npad<KeyT>(N);
     const size_t tab_bytes = (size_t)tab_stride<KeyT>(N, R) * sizeof(KeyT);
-    const size_t ints_bytes = ((size_t)(3 * N + R + 1) * 4 + 15) & ~(size_t)15;
-    const size_t f_bytes = ((size_t)8 * nw + 15) & ~(size_t)15;
+    const size_t ints_bytes = ((size_t)8 * N + (size_t)(2 * N + R + 1) * 4 + 15) & ~(size_t)15;
+    const size_t f_bytes = ((size_t)8 * nw + 16 + 15) & ~(size_t)15;
     unsigned char *wb = smem + (TABMODE == 2 ? tab_bytes : 0) +
                         wave * walk_wave_bytes<KeyT>(N, R, TABMODE);
     KeyT *wtab = (KeyT *)wb;
     const size_t ints_off = TABMODE == 1 ? tab_bytes : 0;
-    int32_t *x = (int32_t *)(wb + ints_off);
-    int32_t *tot = x + N;
-    int32_t *cons = tot + N;
+    uint64_t *lm = (uint64_t *)(wb + ints_off);
+    int32_t *tot = (int32_t *)lm;
+    int32_t *x = (int32_t *)(lm + N);
+    int32_t *cons = x + N;
     int32_t *bw = cons + N;
     int32_t *nfeas = bw + R;
     uint64_t *F = (uint64_t *)(wb + ints_off + ints_bytes);
+    uint64_t *clr = F + nw;
+    if (lane < 2) clr[lane] = 0;
     uint32_t *M = sizeof(KeyT) == 2 ? (uint32_t *)(wb + ints_off + ints_bytes + f_bytes) : nullptr;
     int2 *ring = (int2 *)(wb + ints_off + ints_bytes + f_bytes + mask_bytes<KeyT>(N));
     int2 *oring = ring + 2 * WAVE;
@@ -277,7 +315,7 @@ __global__ __launch_bounds__(256) void k_walk_greedy(Prob P, Plan L, const KeyT 
                 v = x0row[w] - (Erow ? Erow[w] : 0);
                 v = v > 0 ? v : 0;
                 x[w] = v;
-                tot[w] = 0;
+                lm[w] = 0;
                 cons[w] = 0;
             }
             const uint64_t m = __ballot(v > 0);
@@ -296,6 +334,7 @@ __global__ __launch_bounds__(256) void k_walk_greedy(Prob P, Plan L, const KeyT 
             wave_sync();
         }
         fs.M = M;
+        if constexpr (SF) fs.clr = clr;
         if (M) { // key masks from the stock set
             for (int dd = lane; dd < npad / 2; dd += WAVE) {
                 const int w = 2 * dd;
@@ -389,7 +428,22 @@ __global__ __launch_bounds__(256) void k_walk_greedy(Prob P, Plan L, const KeyT 
             int ship = q;
             int ta = 0;
             bool over = false; // some warehouse's demand in this step exceeds its stock
-            if (risky) {
+            uint64_t mk = 0;   // unit demand: the step's lanes on this lane's warehouse
+            int rank = 0;      // unit demand: earlier lanes on this lane's warehouse
+            if (risky && unit) {
+                // the lanes on each chosen warehouse as one 64-bit mask, built with
+                // order-free atomic ORs; an order finds its warehouse empty iff the
+                // number of earlier lanes on it reaches the stock
+                if (chose) atomicOr(&lm[a], 1ull << lane);
+                wave_sync();
+                mk = chose ? lm[a] : 0ull;
+                wave_sync();
+                if (chose) lm[a] = 0ull;
+                rank = __popcll(mk & lanemask_lt());
+                const uint64_t inv = __ballot(chose && rank >= xa);
+                over = inv != 0;
+                if (over) cut = __ffsll((long long)inv) - 1;
+            } else if (risky) {
                 if (chose) atomicAdd(&tot[a], q);
                 wave_sync();
                 ta = chose ? tot[a] : 0;
@@ -417,6 +471,8 @@ __global__ __launch_bounds__(256) void k_walk_greedy(Prob P, Plan L, const KeyT 
                     }
                     todo &= ~eq;
                 }
+            }
+            if (risky) {
                 cut = uni(cut);
                 if (cut == 0) {
                     // the first order's warehouse is in the stock set yet has no stock:
@@ -434,7 +490,19 @@ __global__ __launch_bounds__(256) void k_walk_greedy(Prob P, Plan L, const KeyT 
             n_changed += __popcll(__ballot(chg));
             const int sh = a >= 0 ? ship : 0;
             if (commit) oring[(off + lane) & (2 * WAVE - 1)] = make_int2(a, sh);
-            if (risky) {
+            if (risky && unit) {
+                // each warehouse's first lane applies the step's committed demand on it
+                // (orders past the stock are past the cut, so it never exceeds the stock)
+                const uint64_t cm = cut >= WAVE ? ~0ull : ((1ull << cut) - 1ull);
+                const int cnt = __popcll(mk & cm);
+                if (chose && rank == 0) {
+                    x[a] = xa - cnt;
+                    atomicAdd(&cons[a], cnt);
+                }
+                // the committed order that takes a warehouse's last unit empties it
+                const bool emp = commit && chose && rank == xa - 1;
+                if (__ballot(emp)) fs.drop(emp, a);
+            } else if (risky) {
                 uint64_t em;
                 if (!over) {
                     // no warehouse's demand exceeds its stock: every order ships in full
