@@ -777,7 +777,7 @@ pk_status pk_policy_grad(const pk_problem *problem, const pk_policy *policy,
                            hipMemcpyHostToDevice, st));
     Prob P = make_prob(problem, d, to);
     HIP_TRY(setup_ctl(L, d.n_traj, 1, st));
-    const int n_wg = std::min(GRAD_MAX_WG, std::max(1, num_cus() * 2));
+    const int n_wg = std::min(GRAD_MAX_WG, std::max(1, num_cus())); // one workgroup per CU
     if (d.total > 0) {
         // states of the fixed actions: the actions are the cache, its consumption scanned
         HIP_TRY(setup_plan(P, L, actions, validate, true, (int32_t)sz.n_seg_max, scratch, st));

@@ -96,10 +96,11 @@ __device__ __forceinline__ void lane_features(float f[5], float cost, float lx, 
     }
 }
 
-// Score of row l%16 (returned in every lane of that column).
-__device__ __forceinline__ float mlp_tile(const MlpLane &m, const float f[5])
+// Hidden activations of one 16-row tile: h1 = relu(W1 f + b1) and, with two layers,
+// h2 = relu(W2 h1 + b2) (one layer: h2 = h1).  D layout of the 16x16 MFMA: the lane holds
+// unit 16t + 4(l/16) + v of row l%16 in h[t][v].
+__device__ __forceinline__ void mlp_hidden(const MlpLane &m, const float f[5], v4f h1[4], v4f h2[4])
 {
-    v4f h[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         v4f acc = {0.f, 0.f, 0.f, 0.f};
@@ -111,27 +112,32 @@ __device__ __forceinline__ float mlp_tile(const MlpLane &m, const float f[5])
             const float z = acc[v] + m.b1[t * 4 + v];
             acc[v] = z > 0.f ? z : 0.f;
         }
-        h[t] = acc;
+        h1[t] = acc;
     }
     if (m.two) {
-        v4f o[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             v4f acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int s = 0; s < 16; ++s)
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(m.a2[t * 16 + s], h[s >> 2][s & 3], acc,
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(m.a2[t * 16 + s], h1[s >> 2][s & 3], acc,
                                                            0, 0, 0);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const float z = acc[v] + m.b2[t * 4 + v];
                 acc[v] = z > 0.f ? z : 0.f;
             }
-            o[t] = acc;
+            h2[t] = acc;
         }
+    } else {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) h[t] = o[t];
+        for (int t = 0; t < 4; ++t) h2[t] = h1[t];
     }
+}
+
+// Output layer of a tile: w3 . h + b3 for row l%16 (in every lane of that column).
+__device__ __forceinline__ float mlp_out(const MlpLane &m, const v4f h[4])
+{
     float part = 0.f;
 #pragma unroll
     for (int t = 0; t < 4; ++t)
@@ -143,6 +149,14 @@ __device__ __forceinline__ float mlp_tile(const MlpLane &m, const float f[5])
     const float p32 = __shfl_xor(s01, 32, WAVE);
     const float tot = (__lane_id() & 32) ? p32 + s01 : s01 + p32;
     return tot + m.b3;
+}
+
+// Score of row l%16 (returned in every lane of that column).
+__device__ __forceinline__ float mlp_tile(const MlpLane &m, const float f[5])
+{
+    v4f h1[4], h2[4];
+    mlp_hidden(m, f, h1, h2);
+    return mlp_out(m, h2);
 }
 
 // Combine two (best, second) pairs of perturbed scores; ties go to the lower warehouse.
