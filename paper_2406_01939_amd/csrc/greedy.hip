@@ -66,32 +66,36 @@ __global__ __launch_bounds__(64) void k_serial_greedy(Prob P, const KeyT *keys, 
 }
 
 // key[b][r][w] = (position of w in region r's increasing (cost[b][w][r], w) order) << S
-// | w: one thread per (b, r, w) counts the warehouses that precede w.  Row padding is
-// all-ones.
+// | w.  One workgroup per row (b, r): the row's costs are staged in LDS, then one thread
+// per w counts the warehouses that precede it.  Row padding is all-ones.
 template <typename KeyT>
-__global__ void k_keys(Prob P, KeyT *keys)
+__global__ __launch_bounds__(256) void k_keys(Prob P, KeyT *keys)
 {
-    const int npad = tab_npad<KeyT>(P.N);
-    const int64_t n = (int64_t)P.n_traj * P.R * npad;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const int w = (int)(i % npad);
-        const int64_t br = i / npad;
-        const int r = (int)(br % P.R);
-        const int b = (int)(br / P.R);
-        KeyT *dst = keys + b * tab_stride<KeyT>(P.N, P.R) + (int64_t)r * npad + w;
-        if (w >= P.N) {
-            *dst = (KeyT)~(KeyT)0;
-            continue;
+    __shared__ int32_t cs[PK_MAX_WAREHOUSES];
+    const int N = P.N, R = P.R;
+    const int npad = tab_npad<KeyT>(N);
+    const int64_t nrows = (int64_t)P.n_traj * R;
+    for (int64_t br = blockIdx.x; br < nrows; br += gridDim.x) {
+        const int r = (int)(br % R);
+        const int64_t b = br / R;
+        const int32_t *c = P.cost + b * N * R;
+        __syncthreads(); // the previous row's counts are done with cs
+        for (int v = threadIdx.x; v < N; v += blockDim.x) cs[v] = c[(int64_t)v * R + r];
+        __syncthreads();
+        KeyT *row = keys + b * tab_stride<KeyT>(N, R) + (int64_t)r * npad;
+        for (int w = threadIdx.x; w < npad; w += blockDim.x) {
+            if (w >= N) {
+                row[w] = (KeyT)~(KeyT)0;
+                continue;
+            }
+            const int32_t cw = cs[w];
+            uint32_t q = 0;
+            for (int v = 0; v < N; ++v) {
+                const int32_t cv = cs[v];
+                q += (cv < cw) || (cv == cw && v < w);
+            }
+            row[w] = (KeyT)((q << key_shift<KeyT>()) | (uint32_t)w);
         }
-        const int32_t *c = P.cost + (int64_t)b * P.N * P.R;
-        const int32_t cw = c[(int64_t)w * P.R + r];
-        uint32_t q = 0;
-        for (int v = 0; v < P.N; ++v) {
-            const int32_t cv = c[(int64_t)v * P.R + r];
-            q += (cv < cw) || (cv == cw && v < w);
-        }
-        *dst = (KeyT)((q << key_shift<KeyT>()) | (uint32_t)w);
     }
 }
 
@@ -107,13 +111,15 @@ size_t pos_bytes(int N, int R, int n_traj)
 
 hipError_t setup_pos(const Prob &P, void *keys, hipStream_t st)
 {
-    const int64_t n = (int64_t)P.n_traj * P.R * (P.N + 8);
-    int64_t g = (n + 255) / 256;
+    int64_t g = (int64_t)P.n_traj * P.R; // one workgroup per row
     g = g < 1 ? 1 : (g > 8192 ? 8192 : g);
+    const int threads = P.N <= 128 ? 128 : 256;
     if (keys16(P.N))
-        hipLaunchKernelGGL(k_keys<uint16_t>, dim3((unsigned)g), dim3(256), 0, st, P, (uint16_t *)keys);
+        hipLaunchKernelGGL(k_keys<uint16_t>, dim3((unsigned)g), dim3(threads), 0, st, P,
+                           (uint16_t *)keys);
     else
-        hipLaunchKernelGGL(k_keys<uint32_t>, dim3((unsigned)g), dim3(256), 0, st, P, (uint32_t *)keys);
+        hipLaunchKernelGGL(k_keys<uint32_t>, dim3((unsigned)g), dim3(threads), 0, st, P,
+                           (uint32_t *)keys);
     return hipGetLastError();
 }
 

@@ -24,8 +24,10 @@ namespace {
 // through LDS a tile of rows at a time, loaded by the whole workgroup with every load
 // in flight, and the exclusive scan down each warehouse's column is done in LDS (one
 // thread per column, its running sum carried from tile to tile) and written out as E.
-// Runs up to the frontier are final and need no entry state; their consumption only
-// enters the prefix.  After the first pass the kernel also lists the runs past the
+// Runs up to the frontier are final and need no entry state.  The scan resumes at the
+// frontier run f from its stored E_f: the previous pass's scan wrote it (f lies past that
+// pass's frontier), and no run before f changed since (f is the first run that changed),
+// so E_f is still exact.  After the first pass the kernel also lists the runs past the
 // frontier (the ones the walk evaluates) in Plan::active.
 constexpr int SCAN_TILE = 12288;   // ints of u per LDS tile (48 KB), a multiple of 256
 constexpr int SCAN_MAXC = 4;       // columns per thread
@@ -80,10 +82,17 @@ __global__ __launch_bounds__(256) void k_scan_entry(Prob P, Plan L, int skip_fir
             }
             const int jmin = f + 1 > 1 ? f + 1 : 1; // runs j > f need E_j; E_0 = 0
             const int64_t row0 = L.sr_uidx[s0];
+            // E_f was written by an earlier scan unless this is the first scan after a
+            // skipped one (then every run before f is all lost sales and E_f = 0 anyway)
+            const bool resume = f >= 1 && !L.no_frontier && (pass > 2 || (pass == 2 && !skip_first_pass));
+            const int jstart = resume ? f : 0;
             int32_t acc[SCAN_MAXC];
 #pragma unroll
-            for (int c = 0; c < SCAN_MAXC; ++c) acc[c] = 0;
-            for (int jt = 0; jt < nsr; jt += rpt) {
+            for (int c = 0; c < SCAN_MAXC; ++c) {
+                const int w = c * 256 + (int)threadIdx.x;
+                acc[c] = resume && w < N ? E[(row0 + f) * N + w] : 0;
+            }
+            for (int jt = jstart; jt < nsr; jt += rpt) {
                 const int nr = nsr - jt < rpt ? nsr - jt : rpt;
                 const int nint = nr * N;
                 const int32_t *src = u + (row0 + jt) * N;

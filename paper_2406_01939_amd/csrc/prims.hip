@@ -121,40 +121,53 @@ hipError_t scan_impl(T *data, int64_t n, bool inclusive, void *tmp, hipStream_t 
 }
 
 // ------------------------------------------------------------------ radix sort
+// Digits of up to RX_MAXBITS bits (RX_MAXB buckets): a 17-bit key takes two passes.
 constexpr int RX_THREADS = 256;
 constexpr int RX_CHUNKS = 8;
 constexpr int RX_TILE = RX_THREADS * RX_CHUNKS;
+constexpr int RX_MAXBITS = 9;
+constexpr int RX_MAXB = 1 << RX_MAXBITS;
+constexpr int RX_BPT = RX_MAXB / RX_THREADS; // buckets per thread in the per-bucket loops
 
 __global__ __launch_bounds__(RX_THREADS) void k_radix_count(const int32_t *keys, int64_t n,
-                                                            int shift, int32_t *counts,
+                                                            int shift, int bits, int32_t *counts,
                                                             int64_t n_tiles)
 {
-    __shared__ int32_t hist[256];
-    hist[threadIdx.x] = 0;
+    __shared__ int32_t hist[RX_MAXB];
+    const int nb = 1 << bits, mask = nb - 1;
+    for (int k = 0; k < RX_BPT; ++k) hist[k * RX_THREADS + threadIdx.x] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * RX_TILE;
     for (int c = 0; c < RX_CHUNKS; ++c) {
         int64_t i = base + c * RX_THREADS + threadIdx.x;
-        if (i < n) atomicAdd(&hist[(keys[i] >> shift) & 255], 1);
+        if (i < n) atomicAdd(&hist[(keys[i] >> shift) & mask], 1);
     }
     __syncthreads();
-    counts[(int64_t)threadIdx.x * n_tiles + blockIdx.x] = hist[threadIdx.x];
+    for (int k = 0; k < RX_BPT; ++k) {
+        const int d = k * RX_THREADS + threadIdx.x;
+        if (d < nb) counts[(int64_t)d * n_tiles + blockIdx.x] = hist[d];
+    }
 }
 
 // Stable scatter: elements of a tile are ranked in index order, 256 at a time; within a
-// wave equal digits are matched with 8 ballots, across the 4 waves through LDS.
+// wave equal digits are matched with one ballot per digit bit, across the 4 waves through
+// LDS.
 __global__ __launch_bounds__(RX_THREADS) void k_radix_scatter(
-    const int32_t *keys, const int32_t *vals, int64_t n, int shift, const int32_t *offs,
+    const int32_t *keys, const int32_t *vals, int64_t n, int shift, int bits, const int32_t *offs,
     int64_t n_tiles, int32_t *keys_out, int32_t *vals_out)
 {
-    __shared__ int32_t s_wcnt[RX_THREADS / WAVE][256];
-    __shared__ int32_t s_woff[RX_THREADS / WAVE][256];
-    __shared__ int32_t s_run[256];
-    __shared__ int32_t s_goff[256];
+    __shared__ int32_t s_wcnt[RX_THREADS / WAVE][RX_MAXB];
+    __shared__ int32_t s_woff[RX_THREADS / WAVE][RX_MAXB];
+    __shared__ int32_t s_run[RX_MAXB];
+    __shared__ int32_t s_goff[RX_MAXB];
     const int tid = threadIdx.x, wave = tid / WAVE;
-    s_run[tid] = 0;
-    s_goff[tid] = offs[(int64_t)tid * n_tiles + blockIdx.x];
-    for (int w = 0; w < RX_THREADS / WAVE; ++w) s_wcnt[w][tid] = 0;
+    const int nb = 1 << bits, mask = nb - 1;
+    for (int k = 0; k < RX_BPT; ++k) {
+        const int d = k * RX_THREADS + tid;
+        s_run[d] = 0;
+        s_goff[d] = d < nb ? offs[(int64_t)d * n_tiles + blockIdx.x] : 0;
+        for (int w = 0; w < RX_THREADS / WAVE; ++w) s_wcnt[w][d] = 0;
+    }
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * RX_TILE;
     for (int c = 0; c < RX_CHUNKS; ++c) {
@@ -162,10 +175,9 @@ __global__ __launch_bounds__(RX_THREADS) void k_radix_scatter(
         const bool valid = i < n;
         const int32_t k = valid ? keys[i] : 0;
         const int32_t v = valid ? vals[i] : 0;
-        const int d = (k >> shift) & 255;
+        const int d = (k >> shift) & mask;
         uint64_t peers = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
+        for (int b = 0; b < bits; ++b) { // bits is uniform
             const bool bit = (d >> b) & 1;
             const uint64_t m = __ballot(bit);
             peers &= bit ? m : ~m;
@@ -173,15 +185,16 @@ __global__ __launch_bounds__(RX_THREADS) void k_radix_scatter(
         const int rank = __popcll(peers & lanemask_lt());
         if (valid && rank == 0) s_wcnt[wave][d] = __popcll(peers);
         __syncthreads();
-        {
-            int run = s_run[tid];
+        for (int kk = 0; kk < RX_BPT; ++kk) {
+            const int dd = kk * RX_THREADS + tid;
+            int run = s_run[dd];
             for (int w = 0; w < RX_THREADS / WAVE; ++w) {
-                const int cnt = s_wcnt[w][tid];
-                s_woff[w][tid] = run;
+                const int cnt = s_wcnt[w][dd];
+                s_woff[w][dd] = run;
                 run += cnt;
-                s_wcnt[w][tid] = 0;
+                s_wcnt[w][dd] = 0;
             }
-            s_run[tid] = run;
+            s_run[dd] = run;
         }
         __syncthreads();
         if (valid) {
@@ -212,7 +225,7 @@ size_t scan_tmp_bytes(int64_t n)
 size_t radix_tmp_bytes(int64_t n)
 {
     const int64_t n_tiles = (n + RX_TILE - 1) / RX_TILE;
-    const int64_t nc = 256 * n_tiles;
+    const int64_t nc = (int64_t)RX_MAXB * n_tiles;
     return (size_t)nc * sizeof(int32_t) + 256 + scan_tmp_bytes(nc);
 }
 
@@ -224,17 +237,20 @@ hipError_t radix_sort_pairs(int32_t *keys, int32_t *vals, int32_t *keys_alt, int
     if (n <= 1) return hipSuccess;
     const int64_t n_tiles = (n + RX_TILE - 1) / RX_TILE;
     int32_t *counts = (int32_t *)tmp;
-    void *scan_tmp = (char *)tmp + (((size_t)256 * n_tiles * sizeof(int32_t) + 255) & ~(size_t)255);
+    void *scan_tmp = (char *)tmp + (((size_t)RX_MAXB * n_tiles * sizeof(int32_t) + 255) & ~(size_t)255);
     int32_t *ki = keys, *vi = vals, *ko = keys_alt, *vo = vals_alt;
-    const int passes = key_bits <= 0 ? 1 : (key_bits + 7) / 8;
+    const int kb = key_bits < 1 ? 1 : key_bits;
+    const int passes = (kb + RX_MAXBITS - 1) / RX_MAXBITS;
+    const int bits = (kb + passes - 1) / passes; // digit width, <= RX_MAXBITS
     for (int p = 0; p < passes; ++p) {
-        const int shift = 8 * p;
+        const int shift = bits * p;
+        const int64_t nc = ((int64_t)1 << bits) * n_tiles;
         hipLaunchKernelGGL(k_radix_count, dim3((unsigned)n_tiles), dim3(RX_THREADS), 0, st, ki,
-                           n, shift, counts, n_tiles);
-        hipError_t e = scan_i32_excl(counts, 256 * n_tiles, scan_tmp, st);
+                           n, shift, bits, counts, n_tiles);
+        hipError_t e = scan_i32_excl(counts, nc, scan_tmp, st);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)n_tiles), dim3(RX_THREADS), 0, st, ki,
-                           vi, n, shift, counts, n_tiles, ko, vo);
+                           vi, n, shift, bits, counts, n_tiles, ko, vo);
         int32_t *t;
         t = ki; ki = ko; ko = t;
         t = vi; vi = vo; vo = t;

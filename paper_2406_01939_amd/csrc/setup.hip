@@ -7,6 +7,7 @@
 // node capacity (Assumption 1, inventory independence), a process's runs are independent
 // and a run is the unit of work on the GPU.
 #include <algorithm>
+#include <stddef.h>
 
 #include "pk_internal.h"
 
@@ -95,46 +96,45 @@ __global__ void k_tables(Prob P, Plan L, const int64_t *flags)
     }
 }
 
-// Per segment: number of runs if split (more than one run), else 0.  Also initialises
-// the frontiers (pass 1 evaluates everything).
-__global__ void k_split_count(Plan L, int32_t *cnt, int32_t *segcnt, int32_t n_seg_max)
+// Per segment: (number of runs if split, else 0) | (1 if split) << 32, for one scan.  Also
+// initialises the frontiers (pass 1 evaluates everything).
+__global__ void k_split_count(Plan L, int64_t *cnt, int32_t n_seg_max)
 {
     const int n_seg = L.ctl->n_seg;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_seg_max; g += stride) {
-        int32_t c = 0, s = 0;
+        int64_t c = 0;
         if (g < n_seg) {
             const int32_t nsr = L.seg_sr0[g + 1] - L.seg_sr0[g];
-            c = nsr > 1 ? nsr : 0;
-            s = nsr > 1 ? 1 : 0;
+            c = nsr > 1 ? ((int64_t)nsr | (1ll << 32)) : 0;
             L.fr[0][g] = FR_ALL;
             L.fr[1][g] = FR_NONE;
         }
         cnt[g] = c;
-        segcnt[g] = s;
     }
 }
 
 // Per segment: the list of split segments, and the split counts in the control block.
-__global__ void k_split_fill(Plan L, const int32_t *ubase, const int32_t *segbase,
-                             int32_t n_seg_max)
+// base[g]: exclusive prefix over segments of (runs if split) | (1 if split) << 32.
+__global__ void k_split_fill(Plan L, const int64_t *base, int32_t n_seg_max)
 {
     const int n_seg = L.ctl->n_seg;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_seg; g += stride) {
         const int32_t s0 = L.seg_sr0[g], s1 = L.seg_sr0[g + 1];
-        if (s1 - s0 > 1) L.split_segs[segbase[g]] = (int32_t)g;
+        const int32_t ubase = (int32_t)(base[g] & 0xffffffffll), segbase = (int32_t)(base[g] >> 32);
+        if (s1 - s0 > 1) L.split_segs[segbase] = (int32_t)g;
         if (g == n_seg - 1) {
             const int32_t last = s1 - s0 > 1 ? s1 - s0 : 0;
-            L.ctl->n_split = ubase[g] + last;
-            L.ctl->n_split_seg = segbase[g] + (s1 - s0 > 1 ? 1 : 0);
+            L.ctl->n_split = ubase + last;
+            L.ctl->n_split_seg = segbase + (s1 - s0 > 1 ? 1 : 0);
         }
     }
 }
 
 // Per run (one thread each): its row of u/E if its segment is split, its place in the
 // split list, and its descriptor.
-__global__ void k_run_desc(Plan L, const int32_t *ubase)
+__global__ void k_run_desc(Plan L, const int64_t *base)
 {
     const int n_sr = L.ctl->n_sr;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -143,7 +143,7 @@ __global__ void k_run_desc(Plan L, const int32_t *ubase)
         const int32_t g = L.sr_seg[s];
         const int32_t s0 = L.seg_sr0[g], s1 = L.seg_sr0[g + 1];
         const bool split = s1 - s0 > 1;
-        const int32_t uidx = split ? ubase[g] + (s - s0) : -1;
+        const int32_t uidx = split ? (int32_t)(base[g] & 0xffffffffll) + (s - s0) : -1;
         L.sr_uidx[s] = uidx;
         if (split) L.split_list[uidx] = s;
         L.rd[s] = RunDesc{L.sr_lo[s], L.sr_lo[s + 1], L.seg_key[g], g, s - s0, s1 - s0, uidx, 0};
@@ -152,21 +152,15 @@ __global__ void k_run_desc(Plan L, const int32_t *ubase)
 
 __global__ void k_init_ctl(Ctl *ctl, int32_t *traj_lcp, int n_traj, int max_passes)
 {
-    // the control block is cleared word by word by the whole grid, then seeded
+    // the control block word by word: pass 1, the pass limit, everything else zero
     const int tid = blockIdx.x * blockDim.x + threadIdx.x;
     const int nthreads = gridDim.x * blockDim.x;
     uint32_t *w = (uint32_t *)ctl;
     const int nw = (int)(sizeof(Ctl) / 4);
-    for (int i = tid; i < nw; i += nthreads) w[i] = 0u;
+    const int i_pass = (int)(offsetof(Ctl, pass) / 4), i_max = (int)(offsetof(Ctl, max_passes) / 4);
+    for (int i = tid; i < nw; i += nthreads)
+        w[i] = i == i_pass ? 1u : (i == i_max ? (uint32_t)max_passes : 0u);
     for (int b = tid; b < n_traj; b += nthreads) traj_lcp[b] = 0;
-}
-
-__global__ void k_seed_ctl(Ctl *ctl, int max_passes)
-{
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        ctl->pass = 1;
-        ctl->max_passes = max_passes;
-    }
 }
 
 inline unsigned grid_for(int64_t n, int threads, int cap = 65535)
@@ -185,7 +179,6 @@ hipError_t setup_ctl(Plan &L, int n_traj, int max_passes, hipStream_t st)
     const int64_t n = std::max<int64_t>(n_traj, (int64_t)(sizeof(Ctl) / 4));
     hipLaunchKernelGGL(k_init_ctl, dim3(grid_for(n, 256)), dim3(256), 0, st, L.ctl, L.traj_lcp,
                        n_traj, max_passes);
-    hipLaunchKernelGGL(k_seed_ctl, dim3(1), dim3(64), 0, st, L.ctl, max_passes);
     return hipGetLastError();
 }
 
@@ -234,16 +227,15 @@ hipError_t setup_plan(const Prob &P, Plan &L, const int32_t *init_cache, int val
     e = scan_i64(flags, n, true, tmp, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_tables, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, P, L, flags);
-    // split bookkeeping: counts per segment -> exclusive scans (reuse keys_b / vals_b)
-    int32_t *cnt = keys_b, *segcnt = vals_b;
+    // split bookkeeping: packed counts per segment -> one exclusive scan (reuses flags:
+    // n_seg_max <= total)
+    int64_t *cnt = flags;
     hipLaunchKernelGGL(k_split_count, dim3(grid_for(n_seg_max, 256, 8192)), dim3(256), 0, st, L,
-                       cnt, segcnt, n_seg_max);
-    e = scan_i32_excl(cnt, n_seg_max, tmp, st);
-    if (e != hipSuccess) return e;
-    e = scan_i32_excl(segcnt, n_seg_max, tmp, st);
+                       cnt, n_seg_max);
+    e = scan_i64(cnt, n_seg_max, false, tmp, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_split_fill, dim3(grid_for(n_seg_max, 256, 8192)), dim3(256), 0, st, L,
-                       cnt, segcnt, n_seg_max);
+                       cnt, n_seg_max);
     hipLaunchKernelGGL(k_run_desc, dim3(grid_for(n + n_seg_max, 256, 8192)), dim3(256), 0, st, L,
                        cnt);
     return hipGetLastError();
