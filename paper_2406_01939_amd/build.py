@@ -22,7 +22,7 @@ ARCH = os.environ.get("PICARD_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-Wall",
-    "-Wno-unused-function", "-Wno-unused-variable",
+    "-Wno-unused-function", "-Wno-unused-variable", "-Wshadow",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I" + os.path.join(HERE, "..", "include"),
 ]
