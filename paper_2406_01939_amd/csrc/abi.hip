@@ -30,7 +30,7 @@ hipError_t launch_unpermute(const Prob &P, const Plan &L, int32_t *actions, int3
 // walk_greedy.hip
 size_t walk_greedy_lds(int N, int R);
 hipError_t launch_walk_greedy(const Prob &P, const Plan &L, const void *keys, int32_t *final_inv,
-                              bool has_init, int grid, hipStream_t st);
+                              bool has_init, int n_cus, hipStream_t st);
 // greedy.hip
 hipError_t launch_serial_greedy(const Prob &P, const void *pos, int32_t *state, int32_t *actions,
                                 int32_t *shipped, hipStream_t st);
@@ -412,7 +412,7 @@ pk_status picard_run(const pk_problem *problem, const Dims &d, const pk_policy *
                                hipMemcpyDeviceToDevice, st));
     Ctl *hc = g_pinned.get();
     if (!hc) return fail(PK_ERR_HIP, "pinned host allocation failed");
-    const int grid = num_cus() * 8;
+    const int grid = num_cus(); // the walk sizes its grid from the CU count
     const int U = o.graph_unroll > 0 ? o.graph_unroll : 8;
     const bool timing = stats && stats->timing;
     std::vector<hipEvent_t> evs;

@@ -107,32 +107,39 @@ __device__ __forceinline__ void fold16(pk_u16x2 &acc, uint4 v0, uint4 v1, uint4 
 // Least key among the warehouses with stock for one 16-byte aligned row of npad keys;
 // the warehouse it names, or LOST if none has stock.  Lanes with need == false only
 // follow along.
-// N <= 128 (16-bit keys, npad <= 128, stock set in registers): every load of the row is
-// issued before the first fold, so the row costs one LDS round trip.  Loads past the
-// row read its first 32 bytes instead; their stock bits are zero.
+// N <= 128 (16-bit keys, npad <= 128, stock set in registers): the row is taken in two
+// halves of four 16-key chunks; every load of a half is issued before its first fold,
+// and chunks whose warehouses have no stock are neither loaded nor folded (wave-uniform
+// tests on the stock bits).  Chunks past the row have no stock bits.
 __device__ __forceinline__ int least_key_128(const uint16_t *row, const StockSet<true> &fs,
                                              int npad, bool need)
 {
     const uint4 *row4 = (const uint4 *)row;
     const uint4 *M4 = (const uint4 *)fs.M;
-    uint4 v[16], m[16];
-#pragma unroll
-    for (int s = 0; s < 8; ++s) {
-        const int at = s * 16 < npad ? 2 * s : 0;
-        if (need) {
-            v[2 * s] = row4[at];
-            v[2 * s + 1] = row4[at + 1];
-        } else {
-            v[2 * s] = v[2 * s + 1] = make_uint4(~0u, ~0u, ~0u, ~0u);
-        }
-        m[2 * s] = M4[at]; // one address for the whole wave
-        m[2 * s + 1] = M4[at + 1];
-    }
     pk_u16x2 acc = {0xffff, 0xffff};
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
-        const uint32_t fb = (uint32_t)(fs.word(s >> 2) >> ((16 * s) & 63)) & 0xffffu;
-        if (fb) fold16(acc, v[2 * s], v[2 * s + 1], m[2 * s], m[2 * s + 1]); // wave-uniform
+    for (int h = 0; h < 2; ++h) {
+        const uint64_t word = fs.word(h); // chunks 4h .. 4h+3
+        uint4 v[8], m[8];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int s = 4 * h + c;
+            const uint32_t fb = (uint32_t)(word >> (16 * c)) & 0xffffu;
+            v[2 * c] = v[2 * c + 1] = m[2 * c] = m[2 * c + 1] = make_uint4(~0u, ~0u, ~0u, ~0u);
+            if (fb && s * 16 < npad) { // wave-uniform
+                if (need) {
+                    v[2 * c] = row4[2 * s];
+                    v[2 * c + 1] = row4[2 * s + 1];
+                }
+                m[2 * c] = M4[2 * s]; // one address for the whole wave
+                m[2 * c + 1] = M4[2 * s + 1];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const uint32_t fb = (uint32_t)(word >> (16 * c)) & 0xffffu;
+            if (fb && (4 * h + c) * 16 < npad) fold16(acc, v[2 * c], v[2 * c + 1], m[2 * c], m[2 * c + 1]);
+        }
     }
     const uint32_t best = acc.x < acc.y ? acc.x : acc.y;
     return best == 0xffffu ? LOST : (int)(best & 0xffu);
@@ -222,9 +229,10 @@ template <typename KeyT> __host__ __device__ inline size_t walk_wave_bytes(int N
 
 __device__ __forceinline__ int2 pack_in(int r, int q, int old) { return make_int2(r | ((old + 1) << 12), q); }
 
-template <typename KeyT, int TABMODE, bool SF> // TABMODE 0: global table, 1: per-wave LDS,
-                                               // 2: per-WG LDS; SF: stock set in registers
-__global__ __launch_bounds__(256) void k_walk_greedy(Prob P, Plan L, const KeyT *key_g,
+template <typename KeyT, int TABMODE, bool SF, int WPB> // TABMODE 0: global table, 1: per-wave
+                                                        // LDS, 2: per-WG LDS; SF: stock set in
+                                                        // registers; WPB waves per workgroup
+__global__ __launch_bounds__(WPB * 64) void k_walk_greedy(Prob P, Plan L, const KeyT *key_g,
                                                      int32_t *final_inv, int has_init,
                                                      int32_t *sink)
 {
@@ -274,9 +282,10 @@ __global__ __launch_bounds__(256) void k_walk_greedy(Prob P, Plan L, const KeyT 
     int lcp_b = -1; // last trajectory this wave marked as changed in this pass
     unsigned long long n_orders = 0, n_runs = 0, n_changed = 0, n_bytes = 0;
 
-    // static round-robin over the runs (no shared work counter: one hot address)
-    const int n_waves = gridDim.x * (blockDim.x / WAVE);
-    int item = blockIdx.x * (blockDim.x / WAVE) + wave;
+    // static round-robin over the runs (no shared work counter: one hot address), across
+    // workgroups first, so that a few long runs of a late pass land on different CUs
+    const int n_waves = gridDim.x * WPB;
+    int item = wave * gridDim.x + blockIdx.x;
     RunDesc d = {};
     if (item < n_items) d = L.rd[all ? item : L.active[item]];
     for (; item < n_items; item += n_waves) {
@@ -571,7 +580,7 @@ __global__ __launch_bounds__(256) void k_walk_greedy(Prob P, Plan L, const KeyT 
         d = dn;
     }
     if (lane == 0 && n_runs) {
-        unsigned long long *st = ctl->stat[(blockIdx.x * 4 + wave) % STAT_SLOTS];
+        unsigned long long *st = ctl->stat[(blockIdx.x * WPB + wave) % STAT_SLOTS];
         atomicAdd(&st[ST_ORDERS], n_orders);
         atomicAdd(&st[ST_RUNS], n_runs);
         atomicAdd(&st[ST_CHANGED], n_changed);
@@ -583,33 +592,44 @@ __global__ __launch_bounds__(256) void k_walk_greedy(Prob P, Plan L, const KeyT 
 struct WalkCfg {
     int mode;
     size_t lds;
+    int wpb; // waves per workgroup
 };
 
+// LDS per CU (gfx950).
+constexpr size_t CU_LDS = 160 * 1024;
+
+// One trajectory: its table once per workgroup, with 16 waves sharing it when they fit in
+// a CU's LDS (one workgroup per CU), else 4.  Batches: one table copy per wave when tables
+// are small, else the table in global memory; 4 waves per workgroup.
 template <typename KeyT> WalkCfg walk_cfg_t(int N, int R, int n_traj)
 {
     const size_t tb = (size_t)tab_stride<KeyT>(N, R) * sizeof(KeyT);
     const size_t per = walk_wave_bytes<KeyT>(N, R, 0);
     const size_t per1 = walk_wave_bytes<KeyT>(N, R, 1);
-    if (n_traj == 1 && tb + 4 * per <= 64 * 1024) return {2, tb + 4 * per};
-    if (tb <= 8 * 1024 && 4 * per1 <= 64 * 1024) return {1, 4 * per1};
-    return {0, 4 * per};
+    if (n_traj == 1 && tb + 16 * per <= CU_LDS) return {2, tb + 16 * per, 16};
+    if (n_traj == 1 && tb + 4 * per <= 64 * 1024) return {2, tb + 4 * per, 4};
+    if (tb <= 8 * 1024 && 4 * per1 <= 64 * 1024) return {1, 4 * per1, 4};
+    return {0, 4 * per, 4};
 }
 
 template <typename KeyT, bool SF>
 void launch_walk_t(const Prob &P, const Plan &L, const void *keys, int32_t *final_inv, int hi,
-                   int grid, hipStream_t st)
+                   int n_cus, hipStream_t st)
 {
     const WalkCfg c = walk_cfg_t<KeyT>(P.N, P.R, P.n_traj);
     const KeyT *t = (const KeyT *)keys;
-    if (c.mode == 2)
-        hipLaunchKernelGGL((k_walk_greedy<KeyT, 2, SF>), dim3(grid), dim3(256), c.lds, st, P, L,
-                           t, final_inv, hi, L.sink);
+    if (c.mode == 2 && c.wpb == 16) // one workgroup per CU
+        hipLaunchKernelGGL((k_walk_greedy<KeyT, 2, SF, 16>), dim3(n_cus), dim3(1024), c.lds, st,
+                           P, L, t, final_inv, hi, L.sink);
+    else if (c.mode == 2)
+        hipLaunchKernelGGL((k_walk_greedy<KeyT, 2, SF, 4>), dim3(n_cus * 8), dim3(256), c.lds, st,
+                           P, L, t, final_inv, hi, L.sink);
     else if (c.mode == 1)
-        hipLaunchKernelGGL((k_walk_greedy<KeyT, 1, SF>), dim3(grid), dim3(256), c.lds, st, P, L,
-                           t, final_inv, hi, L.sink);
+        hipLaunchKernelGGL((k_walk_greedy<KeyT, 1, SF, 4>), dim3(n_cus * 8), dim3(256), c.lds, st,
+                           P, L, t, final_inv, hi, L.sink);
     else
-        hipLaunchKernelGGL((k_walk_greedy<KeyT, 0, SF>), dim3(grid), dim3(256), c.lds, st, P, L,
-                           t, final_inv, hi, L.sink);
+        hipLaunchKernelGGL((k_walk_greedy<KeyT, 0, SF, 4>), dim3(n_cus * 8), dim3(256), c.lds, st,
+                           P, L, t, final_inv, hi, L.sink);
 }
 
 inline bool keys16_n(int N) { return N <= 256; }
@@ -622,14 +642,14 @@ size_t walk_greedy_lds(int N, int R)
 }
 
 hipError_t launch_walk_greedy(const Prob &P, const Plan &L, const void *keys, int32_t *final_inv,
-                              bool has_init, int grid, hipStream_t st)
+                              bool has_init, int n_cus, hipStream_t st)
 {
     if (P.N <= 128)
-        launch_walk_t<uint16_t, true>(P, L, keys, final_inv, has_init ? 1 : 0, grid, st);
+        launch_walk_t<uint16_t, true>(P, L, keys, final_inv, has_init ? 1 : 0, n_cus, st);
     else if (keys16_n(P.N))
-        launch_walk_t<uint16_t, false>(P, L, keys, final_inv, has_init ? 1 : 0, grid, st);
+        launch_walk_t<uint16_t, false>(P, L, keys, final_inv, has_init ? 1 : 0, n_cus, st);
     else
-        launch_walk_t<uint32_t, false>(P, L, keys, final_inv, has_init ? 1 : 0, grid, st);
+        launch_walk_t<uint32_t, false>(P, L, keys, final_inv, has_init ? 1 : 0, n_cus, st);
     return hipGetLastError();
 }
 
