@@ -27,6 +27,35 @@ namespace {
 
 using namespace mlpdev;
 
+// Per-order data of both learned kernels comes from LDS: the orders of a run (or a
+// trajectory) are staged 64 at a time, the next 64 loaded into registers meanwhile, and
+// each order's cost row and region embedding sit in a double buffer that is filled from
+// global memory while the previous order is scored.  CHUNK orders per stage.
+constexpr int CHUNK = 64;
+constexpr int MAX_CPT = PK_MAX_WAREHOUSES / 256; // cost values per thread (256 threads)
+
+// Loads the cost row of region r (N values, trajectory b) and its embedding into registers.
+__device__ __forceinline__ void load_row(const float *costT, const float *E, int b, int R, int N,
+                                         int r, float cn[MAX_CPT], float &en)
+{
+#pragma unroll
+    for (int k = 0; k < MAX_CPT; ++k) {
+        const int w = k * 256 + (int)threadIdx.x;
+        cn[k] = w < N ? costT[((int64_t)b * R + r) * N + w] : 0.f;
+    }
+    en = threadIdx.x < 16 ? E[(int64_t)r * 16 + threadIdx.x] : 0.f;
+}
+__device__ __forceinline__ void store_row(float *cbuf, float *ebuf, int N, const float cn[MAX_CPT],
+                                          float en)
+{
+#pragma unroll
+    for (int k = 0; k < MAX_CPT; ++k) {
+        const int w = k * 256 + (int)threadIdx.x;
+        if (w < N) cbuf[w] = cn[k];
+    }
+    if (threadIdx.x < 16) ebuf[threadIdx.x] = en;
+}
+
 // One workgroup walks one run (a process's orders of one SKU) from its entry state,
 // order by order: all waves score the order's warehouses with stock (kept as a list that
 // loses a warehouse when it empties), wave 0 takes the argmax and applies f.  Same run bookkeeping as the greedy walk (entry state from the segmented
@@ -151,15 +180,19 @@ __global__ __launch_bounds__(256) void k_walk_mlp(Prob P, Plan L, const float *p
 
 // Serial sweep: one workgroup per trajectory walks its orders in time order with the
 // trajectory's stock in `state` ([K][N], initialised to x0); per order the SKU's stock
-// row is read into LDS, its warehouses with stock are listed and scored by the same
-// scorer, and the chosen warehouse's stock is written back.
+// row is in LDS (requested during the previous order, or kept from it when both orders
+// have the same SKU), its warehouses with stock are listed and scored by the same scorer,
+// and the chosen warehouse's stock is written back.
 __global__ __launch_bounds__(256) void k_serial_mlp(Prob P, const float *params, int layers,
                                                    const float *costT, int32_t *state,
                                                    int32_t *actions, int32_t *shipped)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int N = P.N, R = P.R;
-    int32_t *x = (int32_t *)smem;
+    int4 *ordq = (int4 *)smem;                 // [2][CHUNK] (sku, region, qty, -)
+    float *cbuf = (float *)(ordq + 2 * CHUNK); // [2][N]
+    float *ebuf = cbuf + 2 * N;                // [2][16]
+    int32_t *x = (int32_t *)(ebuf + 32);
     float *zbuf = (float *)(x + N);
     int32_t *sl = (int32_t *)(zbuf + N);
     int32_t *pos = sl + N;
@@ -167,23 +200,67 @@ __global__ __launch_bounds__(256) void k_serial_mlp(Prob P, const float *params,
     const int b = blockIdx.x;
     if (b >= P.n_traj) return;
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    const int tid = threadIdx.x;
     MlpLane m;
     load_mlp(m, params, R, layers);
     const int64_t t0 = P.traj_off[b], t1 = P.traj_off[b + 1];
     int32_t *xs = state + (int64_t)b * P.K * N;
-    for (int64_t t = t0; t < t1; ++t) {
+    auto order_at = [&](int64_t t) -> int4 {
         int k = P.sku[t], r = P.region[t], q = P.qty[t];
         k = k < 0 ? 0 : (k >= P.K ? P.K - 1 : k); // out-of-range input never indexes memory
         r = r < 0 ? 0 : (r >= P.R ? P.R - 1 : r);
         q = q < 1 ? 1 : q;
+        return make_int4(k, r, q, 0);
+    };
+    if (t0 >= t1) return;
+    if (tid < CHUNK && t0 + tid < t1) ordq[tid] = order_at(t0 + tid);
+    int4 nq = make_int4(0, 0, 0, 0);
+    if (tid < CHUNK && t0 + CHUNK + tid < t1) nq = order_at(t0 + CHUNK + tid);
+    __syncthreads();
+    float cn[MAX_CPT], en;
+    load_row(costT, m.E, b, R, N, ordq[0].y, cn, en);
+    store_row(cbuf, ebuf, N, cn, en);
+    for (int w = tid; w < N; w += blockDim.x) x[w] = xs[(int64_t)ordq[0].x * N + w];
+    __syncthreads();
+    for (int64_t tt = t0; tt < t1; ++tt) {
+        const int64_t i = tt - t0;
+        const int slot = (int)((i / CHUNK) & 1), buf = (int)(i & 1);
+        if (i % CHUNK == 0 && i > 0) { // a new chunk: into the ring, the next one requested
+            if (tid < CHUNK) ordq[slot * CHUNK + tid] = nq;
+            if (tid < CHUNK && tt + CHUNK + tid < t1) nq = order_at(tt + CHUNK + tid);
+            __syncthreads();
+            // this order's rows were not prefetched: its cost row, and its stock row as the
+            // previous order left it (written back before the last barrier)
+            const int4 o0 = ordq[slot * CHUNK];
+            load_row(costT, m.E, b, R, N, o0.y, cn, en);
+            store_row(cbuf + buf * N, ebuf + buf * 16, N, cn, en);
+            for (int w = tid; w < N; w += blockDim.x) x[w] = xs[(int64_t)o0.x * N + w];
+            __syncthreads();
+        }
+        const int4 od = ordq[slot * CHUNK + (int)(i % CHUNK)];
+        const int k = od.x, q = od.z;
         int32_t *xk = xs + (int64_t)k * N;
-        for (int w = threadIdx.x; w < N; w += blockDim.x) x[w] = xk[w];
-        __syncthreads();
+        // the next order (same chunk): its row and, for another SKU, its stock row
+        const bool pf = i % CHUNK != CHUNK - 1 && tt + 1 < t1;
+        int kn = k;
+        int32_t xn[MAX_CPT];
+        if (pf) {
+            const int4 on = ordq[slot * CHUNK + (int)(i % CHUNK) + 1];
+            kn = on.x;
+            load_row(costT, m.E, b, R, N, on.y, cn, en);
+            if (kn != k) {
+#pragma unroll
+                for (int c = 0; c < MAX_CPT; ++c) {
+                    const int w = c * 256 + tid;
+                    xn[c] = w < N ? xs[(int64_t)kn * N + w] : 0;
+                }
+            }
+        }
         build_stock_list(x, N, sl, pos, nfp);
         __syncthreads();
         const int nf = *nfp;
-        score_list(m, costT + ((int64_t)b * R + r) * N, m.E + (int64_t)r * 16, x, sl, nf, P.seed,
-                   (uint32_t)b, (uint32_t)(t - t0), zbuf);
+        score_list(m, cbuf + buf * N, ebuf + buf * 16, x, sl, nf, P.seed, (uint32_t)b,
+                   (uint32_t)(tt - t0), zbuf);
         __syncthreads();
         if (wave == 0) {
             float z1, z2;
@@ -192,10 +269,24 @@ __global__ __launch_bounds__(256) void k_serial_mlp(Prob P, const float *params,
                 int sh = 0;
                 if (a >= 0) {
                     sh = q < x[a] ? q : x[a];
-                    xk[a] = x[a] - sh;
+                    x[a] -= sh;
+                    xk[a] = x[a];
                 }
-                actions[t] = a;
-                if (shipped) shipped[t] = sh;
+                actions[tt] = a;
+                if (shipped) shipped[tt] = sh;
+            }
+        }
+        __syncthreads();
+        // the next order's rows into LDS: its stock row is kept when it is the same SKU
+        // (updated above); when the next order opens a chunk both are read there
+        if (pf) {
+            store_row(cbuf + (buf ^ 1) * N, ebuf + (buf ^ 1) * 16, N, cn, en);
+            if (kn != k) {
+#pragma unroll
+                for (int c = 0; c < MAX_CPT; ++c) {
+                    const int w = c * 256 + tid;
+                    if (w < N) x[w] = xn[c];
+                }
             }
         }
         __threadfence_block();
@@ -265,7 +356,8 @@ hipError_t launch_walk_mlp(const Prob &P, const Plan &L, const float *params, in
 hipError_t launch_serial_mlp(const Prob &P, const float *params, int layers, const float *costT,
                              int32_t *state, int32_t *actions, int32_t *shipped, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_serial_mlp, dim3(P.n_traj), dim3(256), (size_t)P.N * 16 + 64, st, P,
+    hipLaunchKernelGGL(k_serial_mlp, dim3(P.n_traj), dim3(256),
+                       (size_t)2 * CHUNK * 16 + 128 + (size_t)P.N * 24 + 64, st, P,
                        params, layers, costT, state, actions, shipped);
     return hipGetLastError();
 }

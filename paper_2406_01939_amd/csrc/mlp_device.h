@@ -199,12 +199,17 @@ __device__ __forceinline__ void score_order(const MlpLane &m, const float *costT
 // w + nwaves, ...).  Warehouses without stock are not scored.
 __device__ __forceinline__ void score_list(const MlpLane &m, const float *costT_r, const float *Er,
                                            const int32_t *x, const int32_t *sl, int nf,
-                                           uint64_t seed, uint32_t traj, uint32_t t, float *zbuf)
+                                           uint64_t seed, uint32_t traj, uint32_t t, float *zbuf,
+                                           int first = -1, int step = 0)
 {
-    const int wave = threadIdx.x / WAVE, nwaves = blockDim.x / WAVE;
+    // by default the workgroup's waves share the tiles; first = 0, step = 1: one wave
+    if (first < 0) {
+        first = threadIdx.x / WAVE;
+        step = blockDim.x / WAVE;
+    }
     const int lane = __lane_id();
     const int ntiles = (nf + 15) >> 4;
-    for (int tile = wave; tile < ntiles; tile += nwaves) {
+    for (int tile = first; tile < ntiles; tile += step) {
         const int i = tile * 16 + (lane & 15);
         const bool valid = i < nf;
         const int w = valid ? sl[i] : 0;
@@ -214,6 +219,35 @@ __device__ __forceinline__ void score_list(const MlpLane &m, const float *costT_
         const float s = mlp_tile(m, f);
         if (lane < 16 && valid) zbuf[w] = s + gumbel(seed, traj, t, (uint32_t)w);
     }
+}
+
+// Top two of the (best, its warehouse, second) triples of the 64 lanes of a wave, by DPP:
+// the row totals (row_shr 1, 2, 4, 8), then rows 0-1 and 2-3 (row_bcast 15), then all four
+// (row_bcast 31) in lane 63, read from there.  Lanes a step does not reach keep the
+// identity (-inf, no warehouse).  Merging triples of disjoint sets gives the top two of
+// their union whatever the grouping, so the result equals a sequential scan's.
+__device__ __forceinline__ void wave_top2(float &b1, int &w1, float &b2)
+{
+    const int NEG = __float_as_int(-INFINITY);
+#define PK_TOP2_DPP(ctrl, rmask)                                                                 \
+    {                                                                                            \
+        const float o1 = __int_as_float(__builtin_amdgcn_update_dpp(NEG, __float_as_int(b1), ctrl, \
+                                                                    rmask, 0xf, false));         \
+        const int ow = __builtin_amdgcn_update_dpp(0x7fffffff, w1, ctrl, rmask, 0xf, false);     \
+        const float o2 = __int_as_float(__builtin_amdgcn_update_dpp(NEG, __float_as_int(b2), ctrl, \
+                                                                    rmask, 0xf, false));         \
+        top2_merge(b1, w1, b2, o1, ow, o2);                                                      \
+    }
+    PK_TOP2_DPP(0x111, 0xf) // row_shr:1
+    PK_TOP2_DPP(0x112, 0xf) // row_shr:2
+    PK_TOP2_DPP(0x114, 0xf) // row_shr:4
+    PK_TOP2_DPP(0x118, 0xf) // row_shr:8
+    PK_TOP2_DPP(0x142, 0xa) // row_bcast:15 into rows 1 and 3
+    PK_TOP2_DPP(0x143, 0xc) // row_bcast:31 into rows 2 and 3
+#undef PK_TOP2_DPP
+    b1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(b1), 63));
+    w1 = __builtin_amdgcn_readlane(w1, 63);
+    b2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(b2), 63));
 }
 
 // Argmax (with runner-up) of zbuf over the stock list sl[0..nf) by one wave.  Returns
@@ -228,13 +262,7 @@ __device__ __forceinline__ int argmax_list(const float *zbuf, const int32_t *sl,
         const int w = sl[i];
         top2_merge(b1, w1, b2, zbuf[w], w, -INFINITY);
     }
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-        const float o1 = __shfl_xor(b1, d, WAVE);
-        const int ow = __shfl_xor(w1, d, WAVE);
-        const float o2 = __shfl_xor(b2, d, WAVE);
-        top2_merge(b1, w1, b2, o1, ow, o2);
-    }
+    wave_top2(b1, w1, b2);
     z1 = b1;
     z2 = b2;
     return b1 == -INFINITY ? LOST : w1;
@@ -242,10 +270,17 @@ __device__ __forceinline__ int argmax_list(const float *zbuf, const int32_t *sl,
 
 // The list of warehouses with stock, x[w] > 0, in sl[0..*nf) with pos[w] its index
 // there; built by wave 0 (64 warehouses per ballot).  Callers synchronise after it.
+__device__ __forceinline__ void build_stock_list_wave(const int32_t *x, int N, int32_t *sl,
+                                                      int32_t *pos, int32_t *nf);
 __device__ __forceinline__ void build_stock_list(const int32_t *x, int N, int32_t *sl, int32_t *pos,
                                                  int32_t *nf)
 {
-    if (threadIdx.x >= WAVE) return;
+    if (threadIdx.x < WAVE) build_stock_list_wave(x, N, sl, pos, nf);
+}
+// The same, by the calling wave.
+__device__ __forceinline__ void build_stock_list_wave(const int32_t *x, int N, int32_t *sl,
+                                                      int32_t *pos, int32_t *nf)
+{
     const int lane = __lane_id();
     int base = 0;
     for (int c = 0; c < N; c += WAVE) {
@@ -286,13 +321,7 @@ __device__ __forceinline__ int argmax_top2(const float *zbuf, int N, float &z1, 
     float b1 = -INFINITY, b2 = -INFINITY;
     int w1 = 0x7fffffff;
     for (int w = lane; w < N; w += WAVE) top2_merge(b1, w1, b2, zbuf[w], w, -INFINITY);
-#pragma unroll
-    for (int d = 1; d < WAVE; d <<= 1) {
-        const float o1 = __shfl_xor(b1, d, WAVE);
-        const int ow = __shfl_xor(w1, d, WAVE);
-        const float o2 = __shfl_xor(b2, d, WAVE);
-        top2_merge(b1, w1, b2, o1, ow, o2);
-    }
+    wave_top2(b1, w1, b2);
     z1 = b1;
     z2 = b2;
     return b1 == -INFINITY ? LOST : w1;
