@@ -108,38 +108,54 @@ __global__ __launch_bounds__(256) void k_walk_mlp(Prob P, Plan L, const float *p
             x[w] = v > 0 ? v : 0;
             cons[w] = 0;
         }
-        if (threadIdx.x == 0) { flag[0] = 0; flag[1] = 0; }
         __syncthreads();
         build_stock_list(x, N, sl, pos, &flag[2]);
         __syncthreads();
+        int nf = flag[2];       // wave 0 keeps the list length; the others reread it
+        int run_chg = 0, run_ties = 0; // wave 0, lane 0
         for (int p = lo; p < hi; ++p) {
             const int r = L.s_region[p];
             const uint32_t t = (uint32_t)L.s_t[p];
-            const int nf = flag[2];
+            // wave 0's lane 0 needs the order's quantity and cached action after the argmax
+            int q = 0, old = 0;
+            if (threadIdx.x == 0) {
+                q = L.s_qty[p];
+                old = L.s_alpha[p];
+            }
+            if (wave != 0) nf = flag[2];
             score_list(m, costT + ((int64_t)b * R + r) * N, m.E + (int64_t)r * 16, x, sl, nf, P.seed,
-                       (uint32_t)b, t, zbuf);
+                       (uint32_t)b, t, zbuf, -1, 0, true);
             __syncthreads();
             if (wave == 0) {
                 float z1, z2;
-                const int a = argmax_list(zbuf, sl, nf, z1, z2);
+                const int a = argmax_zl(zbuf, sl, nf, z1, z2);
+                int emp = 0;
                 if (lane == 0) {
-                    const int q = L.s_qty[p];
                     int sh = 0;
-                    if (a >= 0) {
-                        sh = q < x[a] ? q : x[a];
-                        x[a] -= sh;
-                        cons[a] += q;
-                        if (x[a] == 0) drop_from_list(a, sl, pos, &flag[2]);
+                    if (a >= 0) { // the four reads are independent: one round trip
+                        const int xa = x[a], ca = cons[a], ia = pos[a], last = sl[nf - 1];
+                        sh = q < xa ? q : xa;
+                        x[a] = xa - sh;
+                        cons[a] = ca + q;
+                        if (xa == sh) { // emptied: the list's last entry takes its place
+                            sl[ia] = last;
+                            pos[last] = ia;
+                            flag[2] = nf - 1;
+                            emp = 1;
+                        }
                     }
                     n_rows += nf;
-                    if (L.s_alpha[p] != a) { flag[0] += 1; }
-                    if (near_tie(z1, z2)) flag[1] += 1;
+                    run_chg += old != a;
+                    run_ties += near_tie(z1, z2);
                     L.s_alpha[p] = a;
                     L.s_ship[p] = sh;
                 }
+                nf -= __builtin_amdgcn_readlane(emp, 0);
             }
             __syncthreads();
         }
+        if (threadIdx.x == 0) { flag[0] = run_chg; flag[1] = run_ties; }
+        __syncthreads();
         int wr = 0;
         if (uidx >= 0) {
             for (int w = threadIdx.x; w < N; w += blockDim.x) L.u[(int64_t)uidx * N + w] = cons[w];
@@ -260,11 +276,11 @@ __global__ __launch_bounds__(256) void k_serial_mlp(Prob P, const float *params,
         __syncthreads();
         const int nf = *nfp;
         score_list(m, cbuf + buf * N, ebuf + buf * 16, x, sl, nf, P.seed, (uint32_t)b,
-                   (uint32_t)(tt - t0), zbuf);
+                   (uint32_t)(tt - t0), zbuf, -1, 0, true);
         __syncthreads();
         if (wave == 0) {
             float z1, z2;
-            const int a = argmax_list(zbuf, sl, nf, z1, z2);
+            const int a = argmax_zl(zbuf, sl, nf, z1, z2);
             if (lane == 0) {
                 int sh = 0;
                 if (a >= 0) {

@@ -194,13 +194,14 @@ __device__ __forceinline__ void score_order(const MlpLane &m, const float *costT
     }
 }
 
-// Perturbed scores of the warehouses in the stock list sl[0..nf) into zbuf[w], by all
-// waves of the workgroup (tiles of 16 listed warehouses: wave w takes tiles w,
-// w + nwaves, ...).  Warehouses without stock are not scored.
+// Perturbed scores of the warehouses in the stock list sl[0..nf) into zbuf[w] (or, with
+// by_list, into zbuf[i] for list entry i), by all waves of the workgroup (tiles of 16
+// listed warehouses: wave w takes tiles w, w + nwaves, ...).  Warehouses without stock
+// are not scored.
 __device__ __forceinline__ void score_list(const MlpLane &m, const float *costT_r, const float *Er,
                                            const int32_t *x, const int32_t *sl, int nf,
                                            uint64_t seed, uint32_t traj, uint32_t t, float *zbuf,
-                                           int first = -1, int step = 0)
+                                           int first = -1, int step = 0, bool by_list = false)
 {
     // by default the workgroup's waves share the tiles; first = 0, step = 1: one wave
     if (first < 0) {
@@ -217,7 +218,7 @@ __device__ __forceinline__ void score_list(const MlpLane &m, const float *costT_
         float f[5];
         lane_features(f, valid ? costT_r[w] : 0.f, log1pf((float)xv), Er);
         const float s = mlp_tile(m, f);
-        if (lane < 16 && valid) zbuf[w] = s + gumbel(seed, traj, t, (uint32_t)w);
+        if (lane < 16 && valid) zbuf[by_list ? i : w] = s + gumbel(seed, traj, t, (uint32_t)w);
     }
 }
 
@@ -262,6 +263,21 @@ __device__ __forceinline__ int argmax_list(const float *zbuf, const int32_t *sl,
         const int w = sl[i];
         top2_merge(b1, w1, b2, zbuf[w], w, -INFINITY);
     }
+    wave_top2(b1, w1, b2);
+    z1 = b1;
+    z2 = b2;
+    return b1 == -INFINITY ? LOST : w1;
+}
+
+// Argmax (with runner-up) of scores held in list order (zl[i] for warehouse sl[i]) by one
+// wave; the score and the warehouse of an entry are independent loads.
+__device__ __forceinline__ int argmax_zl(const float *zl, const int32_t *sl, int nf, float &z1,
+                                         float &z2)
+{
+    const int lane = __lane_id();
+    float b1 = -INFINITY, b2 = -INFINITY;
+    int w1 = 0x7fffffff;
+    for (int i = lane; i < nf; i += WAVE) top2_merge(b1, w1, b2, zl[i], sl[i], -INFINITY);
     wave_top2(b1, w1, b2);
     z1 = b1;
     z2 = b2;
