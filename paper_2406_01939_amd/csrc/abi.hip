@@ -438,7 +438,7 @@ pk_status picard_run(const pk_problem *problem, const Dims &d, const pk_policy *
         }
         if (policy->kind == PK_POLICY_MLP)
             HIP_TRY(launch_walk_mlp(P, L, policy->params, policy->n_hidden_layers, L.costT,
-                                    final_inv, has_init, num_cus() * 4, s2));
+                                    final_inv, has_init, num_cus() * 3, s2)); // resident: 3 per CU
         else
             HIP_TRY(launch_walk_greedy(P, L, L.pos, final_inv, has_init, grid, s2));
         if (ge) {

@@ -80,7 +80,8 @@ __global__ __launch_bounds__(256) void k_grad(Prob P, Plan L, const float *param
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     const int m = lane & 15, g = lane >> 4;
     const bool two = layers == 2;
-    float *W2T = (float *)smem;           // [64][RS] W2 by input unit: W2T[i][o] = W2[o][i]
+    float *W2s = (float *)smem;           // [64][W2S] W2 by output unit (the scorer's operands)
+    float *W2T = W2s + 64 * W2S;          // [64][RS] W2 by input unit: W2T[i][o] = W2[o][i]
     float *H1T = W2T + H * RS;            // [64][RS] h1 of the chunk's 64 rows, by unit
     float *DLT = H1T + H * RS;            // [64][RS] layer-2 deltas of the chunk, by unit
     float *red = DLT + H * RS;            // [GW][64] each wave's d1 summed over its rows
@@ -97,8 +98,9 @@ __global__ __launch_bounds__(256) void k_grad(Prob P, Plan L, const float *param
     const float *W1 = params + (int64_t)R * 16;
     const float *b1 = W1 + H * 18;
     const float *W2 = b1 + H;
+    stage_w2(W2s, params, R, layers); // read after the barrier below
     MlpLane mw;
-    load_mlp(mw, params, R, layers);
+    load_mlp(mw, params, R, layers, W2s);
     if (two)
         for (int i = threadIdx.x; i < H * H; i += blockDim.x) W2T[(i % H) * RS + i / H] = W2[i];
     float w1e[16]; // W1[lane][2 + k]: the embedding columns (wave 0 forms dE with them)
@@ -399,7 +401,7 @@ __global__ void k_unpermute_f32(const int32_t *perm, const float *src, float *ds
 size_t grad_lds(int N, int layers)
 {
     (void)layers;
-    return (size_t)(3 * H * RS + GW * H + H + 16 + 4) * 4 + 16 + (size_t)N * 16 + 16;
+    return w2_lds_bytes() + (size_t)(3 * H * RS + GW * H + H + 16 + 4) * 4 + 16 + (size_t)N * 16 + 16;
 }
 
 size_t grad_part_bytes(int n_wg, int R, int layers)

@@ -66,7 +66,8 @@ __global__ __launch_bounds__(256) void k_walk_mlp(Prob P, Plan L, const float *p
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int N = P.N, R = P.R;
-    int32_t *x = (int32_t *)smem;
+    float *W2s = (float *)smem;
+    int32_t *x = (int32_t *)(smem + w2_lds_bytes());
     int32_t *cons = x + N;
     float *zbuf = (float *)(cons + N);
     int32_t *sl = (int32_t *)(zbuf + N); // warehouses with stock
@@ -75,8 +76,9 @@ __global__ __launch_bounds__(256) void k_walk_mlp(Prob P, Plan L, const float *p
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     Ctl *ctl = L.ctl;
     if (ctl->done) return;
+    stage_w2(W2s, params, R, layers); // read after the first barrier of a run
     MlpLane m;
-    load_mlp(m, params, R, layers);
+    load_mlp(m, params, R, layers, W2s);
     const int pass = ctl->pass;
     const int32_t *fprev = L.fr[(pass - 1) & 1];
     int32_t *fcur = L.fr[pass & 1];
@@ -205,7 +207,8 @@ __global__ __launch_bounds__(256) void k_serial_mlp(Prob P, const float *params,
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int N = P.N, R = P.R;
-    int4 *ordq = (int4 *)smem;                 // [2][CHUNK] (sku, region, qty, -)
+    float *W2s = (float *)smem;
+    int4 *ordq = (int4 *)(smem + w2_lds_bytes()); // [2][CHUNK] (sku, region, qty, -)
     float *cbuf = (float *)(ordq + 2 * CHUNK); // [2][N]
     float *ebuf = cbuf + 2 * N;                // [2][16]
     int32_t *x = (int32_t *)(ebuf + 32);
@@ -217,8 +220,9 @@ __global__ __launch_bounds__(256) void k_serial_mlp(Prob P, const float *params,
     if (b >= P.n_traj) return;
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     const int tid = threadIdx.x;
+    stage_w2(W2s, params, R, layers); // read after the first barrier
     MlpLane m;
-    load_mlp(m, params, R, layers);
+    load_mlp(m, params, R, layers, W2s);
     const int64_t t0 = P.traj_off[b], t1 = P.traj_off[b + 1];
     int32_t *xs = state + (int64_t)b * P.K * N;
     auto order_at = [&](int64_t t) -> int4 {
@@ -318,11 +322,13 @@ __global__ __launch_bounds__(256) void k_scores(Prob P, const float *params, int
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int N = P.N;
-    int32_t *x = (int32_t *)smem;
+    float *W2s = (float *)smem;
+    int32_t *x = (int32_t *)(smem + w2_lds_bytes());
     float *zbuf = (float *)(x + N);
     float *sbuf = zbuf + N;
+    stage_w2(W2s, params, P.R, layers); // read after the barrier below
     MlpLane m;
-    load_mlp(m, params, P.R, layers);
+    load_mlp(m, params, P.R, layers, W2s);
     for (int w = threadIdx.x; w < N; w += blockDim.x) x[w] = xrow[w];
     __syncthreads();
     score_order(m, costT + ((int64_t)b * P.R + r) * N, m.E + (int64_t)r * 16, x, N, P.seed,
@@ -358,7 +364,7 @@ hipError_t setup_costT(const Prob &P, float *costT, hipStream_t st)
     return hipGetLastError();
 }
 
-size_t walk_mlp_lds(int N) { return (size_t)N * 20 + 64; }
+size_t walk_mlp_lds(int N) { return w2_lds_bytes() + (size_t)N * 20 + 64; }
 
 hipError_t launch_walk_mlp(const Prob &P, const Plan &L, const float *params, int layers,
                            const float *costT, int32_t *final_inv, bool has_init, int grid,
@@ -373,7 +379,7 @@ hipError_t launch_serial_mlp(const Prob &P, const float *params, int layers, con
                              int32_t *state, int32_t *actions, int32_t *shipped, hipStream_t st)
 {
     hipLaunchKernelGGL(k_serial_mlp, dim3(P.n_traj), dim3(256),
-                       (size_t)2 * CHUNK * 16 + 128 + (size_t)P.N * 24 + 64, st, P,
+                       w2_lds_bytes() + (size_t)2 * CHUNK * 16 + 128 + (size_t)P.N * 24 + 64, st, P,
                        params, layers, costT, state, actions, shipped);
     return hipGetLastError();
 }
@@ -381,7 +387,8 @@ hipError_t launch_serial_mlp(const Prob &P, const float *params, int layers, con
 hipError_t launch_scores(const Prob &P, const float *params, int layers, const float *costT,
                          int b, int r, const int32_t *xrow, float *out, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_scores, dim3(1), dim3(256), (size_t)P.N * 12 + 64, st, P, params, layers,
+    hipLaunchKernelGGL(k_scores, dim3(1), dim3(256), w2_lds_bytes() + (size_t)P.N * 12 + 64, st, P,
+                       params, layers,
                        costT, b, r, xrow, out);
     return hipGetLastError();
 }

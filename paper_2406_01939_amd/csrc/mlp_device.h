@@ -40,16 +40,30 @@ __device__ __forceinline__ float gumbel(uint64_t seed, uint32_t traj, uint32_t t
 }
 
 // ---------------------------------------------------------------- MFMA scorer
+// W2 in LDS by output unit, rows W2S floats apart: the layer-2 A operands of a lane are
+// four consecutive floats, and the 16-byte loads of 8 lanes fall on distinct banks.
+constexpr int W2S = 68;
+__host__ __device__ inline size_t w2_lds_bytes() { return (size_t)64 * W2S * sizeof(float); }
+
+// Copies W2 into LDS (every thread of the workgroup takes part; the caller synchronises).
+__device__ __forceinline__ void stage_w2(float *W2s, const float *params, int R, int layers)
+{
+    if (layers != 2) return;
+    const float *W2 = params + (int64_t)R * 16 + 64 * 18 + 64;
+    for (int i = threadIdx.x; i < 64 * 64; i += blockDim.x) W2s[(i >> 6) * W2S + (i & 63)] = W2[i];
+}
+
 struct MlpLane {
     float a1[20]; // layer 1 A operands, index t*5 + s
-    float a2[64]; // layer 2 A operands, index t*16 + s
     float b1[16], b2[16], w3[16]; // index t*4 + v (hidden 16t + 4g + v)
     float b3;
-    const float *E; // [R][16] in global memory
-    int two;        // two hidden layers
+    const float *E;   // [R][16] in global memory
+    const float *W2s; // W2 in LDS (stage_w2)
+    int two;          // two hidden layers
 };
 
-__device__ __forceinline__ void load_mlp(MlpLane &m, const float *params, int R, int layers)
+__device__ __forceinline__ void load_mlp(MlpLane &m, const float *params, int R, int layers,
+                                         const float *W2s)
 {
     const int l = __lane_id(), i = l & 15, g = l >> 4;
     const float *E = params;
@@ -59,6 +73,7 @@ __device__ __forceinline__ void load_mlp(MlpLane &m, const float *params, int R,
     const float *b2 = W2 + 64 * 64;
     const float *w3 = layers == 2 ? b2 + 64 : b1 + 64;
     m.E = E;
+    m.W2s = W2s;
     m.two = layers == 2;
 #pragma unroll
     for (int t = 0; t < 4; ++t)
@@ -75,13 +90,7 @@ __device__ __forceinline__ void load_mlp(MlpLane &m, const float *params, int R,
             m.w3[t * 4 + v] = w3[16 * t + 4 * g + v];
             m.b2[t * 4 + v] = layers == 2 ? b2[16 * t + 4 * g + v] : 0.0f;
         }
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-        for (int s = 0; s < 16; ++s) {
-            const int h = 16 * (s >> 2) + 4 * g + (s & 3);
-            m.a2[t * 16 + s] = layers == 2 ? W2[(16 * t + i) * 64 + h] : 0.0f;
-        }
+    (void)W2;
     m.b3 = w3[64];
 }
 
@@ -115,13 +124,19 @@ __device__ __forceinline__ void mlp_hidden(const MlpLane &m, const float f[5], v
         h1[t] = acc;
     }
     if (m.two) {
+        const int i = __lane_id() & 15, g = __lane_id() >> 4;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             v4f acc = {0.f, 0.f, 0.f, 0.f};
+            // step s = 4c + v takes W2[16t + i][16c + 4g + v] with h1 unit 16c + 4g + v
 #pragma unroll
-            for (int s = 0; s < 16; ++s)
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(m.a2[t * 16 + s], h1[s >> 2][s & 3], acc,
-                                                           0, 0, 0);
+            for (int c = 0; c < 4; ++c) {
+                const float4 wv = *(const float4 *)(m.W2s + (16 * t + i) * W2S + 16 * c + 4 * g);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wv.x, h1[c][0], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wv.y, h1[c][1], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wv.z, h1[c][2], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wv.w, h1[c][3], acc, 0, 0, 0);
+            }
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const float z = acc[v] + m.b2[t * 4 + v];
