@@ -99,6 +99,26 @@ def test_small_workload(api, oracle, B):
         assert out["passes"][0] <= 2  # product partition
 
 
+@pytest.mark.parametrize("N,R,n_traj,qmax", [
+    (200, 20, 1, 1),   # stock set in LDS (N > 128), 16-bit keys, one trajectory
+    (200, 20, 3, 2),   # the same, batched: key table in global memory
+    (300, 30, 1, 1),   # 32-bit keys (N > 256)
+    (300, 30, 2, 3),
+    (100, 1000, 1, 1), # one trajectory whose key table does not fit in LDS
+])
+@pytest.mark.parametrize("B", [97, 1000])  # short runs only; runs of several 64-order steps
+def test_wide_shapes(api, oracle, N, R, n_traj, qmax, B):
+    """Warehouse and region counts past the benchmark's: every layout of the walk (stock
+    set in registers or LDS, 16- or 32-bit keys, key table in LDS or global memory)."""
+    inst = random_tiny(100 + N + R, N=N, K=6, R=R, T=2500, qmax=qmax, inv_max=2, n_traj=n_traj)
+    _say(f"case wide N={N} R={R} n_traj={n_traj} B={B} total={inst.total_orders}")
+    want_a, want_s, want_f, want_p = _oracle_batch(oracle, inst, B)
+    prob = api.DeviceProblem.from_instance(inst)
+    out = api.pk_picard_simulate(prob, "greedy", block_len=B, validate=True)
+    _check(out, inst, want_a, want_s, want_f)
+    np.testing.assert_array_equal(out["passes"], want_p)
+
+
 def test_serial_sweep_matches_oracle(api, oracle):
     inst = random_tiny(11, N=70, K=5, R=4, T=400, qmax=3, inv_max=6, n_traj=5)
     _say("case serial sweep tiny batch")
