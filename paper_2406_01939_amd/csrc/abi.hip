@@ -626,7 +626,7 @@ pk_status autotune_block(const pk_problem *problem, const Dims &d, const pk_poli
             return PK_OK;
         }
     }
-    static const int cands[] = {64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384, 65536};
+    static const int cands[] = {64, 128, 256, 384, 512, 768, 1024, 1536, 2048, 4096, 8192, 16384, 65536};
     constexpr int NC = (int)(sizeof(cands) / sizeof(cands[0]));
     pk_picard_opts o = {};
     o.use_frontier = 1;
