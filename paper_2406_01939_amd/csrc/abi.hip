@@ -281,16 +281,21 @@ int num_cus()
 // The instantiated graph of U passes is kept per thread and reused while every kernel
 // argument is unchanged (same problem, plan and output buffers).
 struct GraphKey {
-    unsigned char bytes[sizeof(Prob) + sizeof(Plan) + sizeof(pk_policy) + 64];
+    unsigned char bytes[sizeof(Prob) + sizeof(Plan) + sizeof(pk_policy) + 80];
+    // setup: the graph also holds the per-call setup, which depends on the remaining
+    // arguments (the warm-start cache, validation, the pass limit seeded in the control
+    // block)
     void set(const Prob &P, const Plan &L, const pk_policy *po, const int32_t *fin, bool hi,
-             int grid, int U, int nseg, bool timing)
+             int grid, int U, int nseg, bool timing, bool setup = false,
+             const int32_t *init_cache = nullptr, int validate = 0, int max_passes = 0)
     {
         memset(bytes, 0, sizeof bytes);
         size_t o = 0;
         memcpy(bytes + o, &P, sizeof P); o += sizeof P;
         memcpy(bytes + o, &L, sizeof L); o += sizeof L;
         memcpy(bytes + o, po, sizeof *po); o += sizeof *po;
-        const int64_t extra[6] = {(int64_t)(uintptr_t)fin, hi, grid, U, nseg, timing};
+        const int64_t extra[10] = {(int64_t)(uintptr_t)fin, hi, grid, U, nseg, timing, setup,
+                                   (int64_t)(uintptr_t)init_cache, validate, max_passes};
         memcpy(bytes + o, extra, sizeof extra);
     }
     bool operator==(const GraphKey &k) const { return memcmp(bytes, k.bytes, sizeof bytes) == 0; }
@@ -313,15 +318,16 @@ pk_status record_in_capture(hipStream_t s, hipEvent_t e)
     return PK_OK;
 }
 
-struct GraphCache {
+// Captured graphs, a few per thread (least recently used dropped first), so that calls
+// alternating between problems or block lengths (the autotuner) keep theirs.
+struct GraphEntry {
     bool valid = false;
     int device = -1;
+    uint64_t used = 0;
     GraphKey key;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    hipStream_t cap = nullptr;
     std::vector<hipEvent_t> evs;
-    ~GraphCache() { clear(); }
     void clear()
     {
         if (exec) (void)hipGraphExecDestroy(exec);
@@ -332,41 +338,74 @@ struct GraphCache {
         graph = nullptr;
         valid = false;
     }
+};
+
+struct GraphCache {
+    static constexpr int SLOTS = 32; // the autotuner cycles through 13 block lengths x 2 graphs
+    GraphEntry slot[SLOTS];
+    uint64_t tick = 0;
+    hipStream_t cap = nullptr;
+    int cap_device = -1;
+    ~GraphCache()
+    {
+        for (GraphEntry &e : slot) e.clear();
+    }
+    // The entry for key k, captured by enqueue(stream, entry) on a miss; n_events events are
+    // created for the capture to record.
     template <typename F> pk_status get(const GraphKey &k, int n_events, F enqueue,
-                                        hipGraphExec_t *out)
+                                        GraphEntry **out)
     {
         int dev = 0;
         HIP_TRY(hipGetDevice(&dev));
-        if (valid && dev == device && k == key) {
-            *out = exec;
-            return PK_OK;
+        ++tick;
+        GraphEntry *victim = &slot[0];
+        for (GraphEntry &e : slot) {
+            if (e.valid && e.device == dev && e.key == k) {
+                e.used = tick;
+                *out = &e;
+                return PK_OK;
+            }
+            if (!e.valid) victim = &e;
+            else if (victim->valid && e.used < victim->used) victim = &e;
         }
-        clear();
-        if (cap && dev != device) {
+        victim->clear();
+        if (cap && dev != cap_device) {
             (void)hipStreamDestroy(cap);
             cap = nullptr;
         }
-        if (!cap) HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-        device = dev;
+        if (!cap) {
+            HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+            cap_device = dev;
+        }
         for (int i = 0; i < n_events; ++i) {
             hipEvent_t e = nullptr;
             HIP_TRY(hipEventCreate(&e));
-            evs.push_back(e);
+            victim->evs.push_back(e);
         }
         HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-        pk_status e = enqueue(cap);
+        pk_status e = enqueue(cap, *victim);
         hipGraph_t g = nullptr;
         const hipError_t ce = hipStreamEndCapture(cap, &g);
         if (e != PK_OK) {
             if (g) (void)hipGraphDestroy(g);
+            victim->clear();
             return e;
         }
-        if (ce != hipSuccess) return fail(PK_ERR_HIP, "graph capture failed: %s", hipGetErrorString(ce));
-        graph = g;
-        HIP_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-        key = k;
-        valid = true;
-        *out = exec;
+        if (ce != hipSuccess) {
+            victim->clear();
+            return fail(PK_ERR_HIP, "graph capture failed: %s", hipGetErrorString(ce));
+        }
+        victim->graph = g;
+        const hipError_t ie = hipGraphInstantiate(&victim->exec, g, nullptr, nullptr, 0);
+        if (ie != hipSuccess) {
+            victim->clear();
+            return fail(PK_ERR_HIP, "graph instantiation failed: %s", hipGetErrorString(ie));
+        }
+        victim->key = k;
+        victim->device = dev;
+        victim->used = tick;
+        victim->valid = true;
+        *out = victim;
         return PK_OK;
     }
 };
@@ -406,21 +445,26 @@ pk_status picard_run(const pk_problem *problem, const Dims &d, const pk_policy *
     HIP_TRY(hipMemcpyAsync(to, problem->traj_offsets, (d.n_traj + 1) * sizeof(int64_t),
                            hipMemcpyHostToDevice, st));
     Prob P = make_prob(problem, d, to);
-    HIP_TRY(setup_ctl(L, d.n_traj, max_passes, st));
     const bool has_init = o.init_cache != nullptr;
-    if (d.total > 0) {
-        const bool mlp = policy->kind == PK_POLICY_MLP;
-        HIP_TRY(setup_plan(P, L, o.init_cache, o.validate, mlp, (int32_t)sz.n_seg_max, scratch,
-                           st));
-        if (mlp)
-            HIP_TRY(setup_costT(P, L.costT, st));
-        else
-            HIP_TRY(setup_pos(P, L.pos, st));
-        if (has_init) HIP_TRY(launch_consume(P, L, sz.n_split_max, st));
-    }
-    if (final_inv)
-        HIP_TRY(hipMemcpyAsync(final_inv, problem->init_inv, (size_t)d.n_traj * d.K * d.N * 4,
-                               hipMemcpyDeviceToDevice, st));
+    // the per-call setup: control block, sort and tables, policy tables, warm start, final
+    // inventory initialised to x0 (enqueued directly or captured with the first passes)
+    auto enqueue_setup = [&](hipStream_t s2) -> pk_status {
+        HIP_TRY(setup_ctl(L, d.n_traj, max_passes, s2));
+        if (d.total > 0) {
+            const bool mlp = policy->kind == PK_POLICY_MLP;
+            HIP_TRY(setup_plan(P, L, o.init_cache, o.validate, mlp, (int32_t)sz.n_seg_max,
+                               scratch, s2));
+            if (mlp)
+                HIP_TRY(setup_costT(P, L.costT, s2));
+            else
+                HIP_TRY(setup_pos(P, L.pos, s2));
+            if (has_init) HIP_TRY(launch_consume(P, L, sz.n_split_max, s2));
+        }
+        if (final_inv)
+            HIP_TRY(hipMemcpyAsync(final_inv, problem->init_inv,
+                                   (size_t)d.n_traj * d.K * d.N * 4, hipMemcpyDeviceToDevice, s2));
+        return PK_OK;
+    };
     Ctl *hc = g_pinned.get();
     if (!hc) return fail(PK_ERR_HIP, "pinned host allocation failed");
     const int grid = num_cus(); // the walk sizes its grid from the CU count
@@ -467,40 +511,55 @@ pk_status picard_run(const pk_problem *problem, const Dims &d, const pk_policy *
         }
         return PK_OK;
     };
-    // U passes captured once as a HIP graph and replayed
-    hipGraphExec_t gexec = nullptr;
+    // graphs: the setup with the first U passes, and U further passes, each captured once
+    // and replayed
+    GraphEntry *g_first = nullptr, *g_more = nullptr;
     double graph_walk_ms = 0.0;
     int64_t graph_walks = 0;
     if (!done && U > 1 && max_passes >= U) {
-        GraphKey key;
-        key.set(P, L, policy, final_inv, has_init, grid, U, (int)sz.n_seg_max, timing);
-        pk_status gs = g_graph.get(key, timing ? 2 * U : 0, [&](hipStream_t cs) -> pk_status {
-            for (int i = 0; i < U; ++i) {
-                pk_status e = enqueue_pass(cs, false, timing ? &g_graph.evs[2 * i] : nullptr);
-                if (e != PK_OK) return e;
-            }
-            return PK_OK;
-        }, &gexec);
-        if (gs != PK_OK) return gs;
+        for (int with_setup = 1; with_setup >= 0; --with_setup) {
+            GraphKey key;
+            key.set(P, L, policy, final_inv, has_init, grid, U, (int)sz.n_seg_max, timing,
+                    with_setup != 0, o.init_cache, o.validate, max_passes);
+            pk_status gs = g_graph.get(key, timing ? 2 * U : 0,
+                                       [&](hipStream_t cs, GraphEntry &ge) -> pk_status {
+                if (with_setup) {
+                    pk_status e = enqueue_setup(cs);
+                    if (e != PK_OK) return e;
+                }
+                for (int i = 0; i < U; ++i) {
+                    pk_status e = enqueue_pass(cs, false, timing ? &ge.evs[2 * i] : nullptr);
+                    if (e != PK_OK) return e;
+                }
+                return PK_OK;
+            }, with_setup ? &g_first : &g_more);
+            if (gs != PK_OK) return gs;
+        }
     }
+    if (!g_first) {
+        const pk_status e = enqueue_setup(st);
+        if (e != PK_OK) return e;
+    }
+    bool first = true;
     while (!done && launched < max_passes) {
         const int u = std::min(U, max_passes - launched);
-        const bool replay = gexec && u == U;
-        if (replay) {
-            HIP_TRY(hipGraphLaunch(gexec, st));
+        GraphEntry *ge = u == U ? (first ? g_first : g_more) : nullptr;
+        if (ge) {
+            HIP_TRY(hipGraphLaunch(ge->exec, st));
         } else {
             for (int i = 0; i < u; ++i) {
                 pk_status e = enqueue_pass(st, timing, nullptr);
                 if (e != PK_OK) return e;
             }
         }
+        first = false;
         launched += u;
         HIP_TRY(hipMemcpyAsync(hc, L.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
-        if (replay && timing) {
+        if (ge && timing) {
             for (int i = 0; i < U; ++i) {
                 float ms = 0.f;
-                HIP_TRY(hipEventElapsedTime(&ms, g_graph.evs[2 * i], g_graph.evs[2 * i + 1]));
+                HIP_TRY(hipEventElapsedTime(&ms, ge->evs[2 * i], ge->evs[2 * i + 1]));
                 graph_walk_ms += ms;
             }
             graph_walks += U;
