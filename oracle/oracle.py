@@ -262,3 +262,50 @@ def n_runs_per_segment(inst, worker: np.ndarray, b: int = 0) -> np.ndarray:
     new = np.ones(s.size, bool)
     new[1:] = (s[1:] != s[:-1]) | (ww[1:] != ww[:-1])
     return np.bincount(s[new], minlength=inst.K)
+
+
+# --------------------------------------------------------------------------------------
+# Policy-gradient loop (Section 4.2): REINFORCE advantages of a rollout, Adam update.
+# --------------------------------------------------------------------------------------
+def margin_rewards(inst, actions: np.ndarray, shipped: np.ndarray, revenue: int,
+                   b: int = 0) -> np.ndarray:
+    """Reward of every step of trajectory b: the chosen warehouse's margin on the units
+    it ships, (revenue - cost[a][region]) * shipped, and 0 for a lost sale (Section 3: an
+    order earns the reward of the node that serves it, nothing when unserved).  int64."""
+    lo, hi = int(inst.traj_offsets[b]), int(inst.traj_offsets[b + 1])
+    a = np.asarray(actions[lo:hi] if len(actions) == inst.total_orders else actions, np.int64)
+    s = np.asarray(shipped[lo:hi] if len(shipped) == inst.total_orders else shipped, np.int64)
+    reg = inst.region[lo:hi].astype(np.int64)
+    served = a >= 0
+    c = inst.cost[b][np.where(served, a, 0), reg].astype(np.int64)
+    return np.where(served, (int(revenue) - c) * s, 0).astype(np.int64)
+
+
+def advantages(inst, actions: np.ndarray, shipped: np.ndarray, revenue: int,
+               b: int = 0) -> dict:
+    """REINFORCE advantages of trajectory b: reward-to-go G_t = sum of r_u over u >= t,
+    minus its mean over the trajectory.  G and its sum are exact integers; the result is
+    rounded once, float32(double(G_t) - double(sum G) / T)."""
+    r = margin_rewards(inst, actions, shipped, revenue, b)
+    T = r.size
+    if T == 0:
+        return dict(rewards=r, rtg=r.copy(), advantages=np.zeros(0, np.float32), ret=0)
+    G = np.cumsum(r[::-1])[::-1].astype(np.int64)
+    S = int(G.sum())
+    A = (G.astype(np.float64) - np.float64(S) / np.float64(T)).astype(np.float32)
+    return dict(rewards=r, rtg=G, advantages=A, ret=int(G[0]))
+
+
+def adam_step(theta, g, m, v, step: int, lr: float, beta1: float = 0.9,
+              beta2: float = 0.999, eps: float = 1e-8, ascend: bool = True):
+    """One Adam step (Kingma and Ba, Algorithm 1) in float64: biased moment estimates,
+    their bias corrections by 1 - beta^step, and a move of lr * mhat / (sqrt(vhat) + eps)
+    up the gradient when ascending (the REINFORCE surrogate is maximised), down
+    otherwise.  Returns new (theta, m, v)."""
+    theta, g, m, v = (np.asarray(x, np.float64) for x in (theta, g, m, v))
+    m = beta1 * m + (1.0 - beta1) * g
+    v = beta2 * v + (1.0 - beta2) * g * g
+    mhat = m / (1.0 - beta1 ** step)
+    vhat = v / (1.0 - beta2 ** step)
+    move = lr * mhat / (np.sqrt(vhat) + eps)
+    return (theta + move if ascend else theta - move), m, v
