@@ -28,6 +28,7 @@ METRIC = "simulated orders/sec/GPU, Picard vs serial GPU sweep; iterations to co
 HBM_PEAK_GBS = 8000.0
 DEFAULT_WORKLOAD = "greedy_n100_k1e5_t1e6"
 LEARNED_WORKLOAD = "mlp_batch64_n100_k5e4_t2e5"
+REVENUE = 200  # per-unit price of the margin reward (revenue - cost) of the gradient legs
 FP32_PEAK_TFLOPS = 157.3
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_walk_greedy_n100_k1e5_t1e6_traffic.md")
 WALK_SOURCE = os.path.join(ROOT, "paper_2406_01939_amd", "csrc", "walk_greedy.hip")
@@ -108,6 +109,9 @@ def main():
                     help="learned workloads: also time pk_policy_grad at the final actions")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-policy leg (greedy workloads only)")
+    ap.add_argument("--pg-iters", type=int, default=0, metavar="K",
+                    help="also run K policy-gradient iterations (Section 4.2) on the learned "
+                         "workload with warm-started Picard, cold Picard and serial rollouts")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter yardstick)")
     args = ap.parse_args()
@@ -211,8 +215,8 @@ def main():
                 r["serial_gpu"]["prefix_per_trajectory"] = serial_prefix
             r["speedup_vs_serial_gpu"] = r["value"] / (stotal / sdt)
         if with_grad and policy == "mlp":
-            from paper_2406_01939_amd.autograd import reward_to_go_advantages
-            adv = reward_to_go_advantages(prob, out["actions"], out["shipped"])
+            adv = api.pk_reinforce_advantages(prob, out["actions"], out["shipped"],
+                                              REVENUE)["advantages"]
             _progress(f"{name}: policy gradient")
             torch.cuda.synchronize()
             t2 = time.perf_counter()
@@ -223,6 +227,38 @@ def main():
             r["policy_grad"] = {"seconds": gdt, "orders_per_s": total / gdt,
                                 "objective": g["objective"]}
         return r
+
+    def pg_loop(name, iters):
+        """End-to-end training (rollout, advantages, gradient, Adam step) for `iters`
+        iterations from the same initial parameters, once per rollout mode."""
+        from paper_2406_01939_amd.train import PolicyGradient
+        inst = make_instance(name)
+        prob = api.DeviceProblem.from_instance(inst)
+        p0 = prob.params.clone()
+        B = api.pk_autotune(prob, "mlp")
+        res = {"workload": name, "iterations": iters, "lr": 3e-3, "revenue": REVENUE,
+               "block_len": B}
+        finals = {}
+        for label, mode, warm in (("picard_warm", "picard", True),
+                                  ("picard_cold", "picard", False), ("serial", "serial", False)):
+            prob.params.copy_(p0)
+            pg = PolicyGradient(prob, lr=3e-3, revenue=REVENUE, rollout=mode, warm_start=warm,
+                                block_len=B)
+            hist = pg.run(iters, callback=lambda h, lab=label: _progress(
+                f"pg {lab} it {h.it}: passes {h.passes_max} rollout {h.rollout_ms:.0f} ms "
+                f"grad+adam {h.grad_ms:.0f} ms mean return {h.mean_return:.4g}"))
+            finals[label] = prob.params.clone()
+            res[label] = {"passes": [h.passes_max for h in hist],
+                          "rollout_s": sum(h.rollout_ms for h in hist) / 1e3,
+                          "total_s": sum(h.rollout_ms + h.grad_ms for h in hist) / 1e3,
+                          "mean_return": [h.mean_return for h in hist]}
+        res["identical_parameters"] = all(torch.equal(finals["serial"], finals[k])
+                                          for k in ("picard_warm", "picard_cold"))
+        for k in ("picard_warm", "picard_cold"):
+            res[f"rollout_speedup_{k}_vs_serial"] = res["serial"]["rollout_s"] / res[k]["rollout_s"]
+            res[f"loop_speedup_{k}_vs_serial"] = res["serial"]["total_s"] / res[k]["total_s"]
+        prob.params.copy_(p0)
+        return res
 
     m = run(args.workload, args.steps, args.warmup, args.warmup_seconds, args.block_len,
             not args.no_serial, args.with_grad, args.serial_prefix)
@@ -248,6 +284,8 @@ def main():
                           "passes_mean": float(lm["passes"].mean()), "dtype": "f32",
                           "roofline": lm["roofline"], "serial_gpu": lm["serial_gpu"],
                           "speedup_vs_serial_gpu": lm["speedup_vs_serial_gpu"]}
+    if args.pg_iters > 0:
+        res["policy_gradient_loop"] = pg_loop(LEARNED_WORKLOAD, args.pg_iters)
     if not args.no_cpu and inst.x0 is not None:
         res["cpu_baseline"] = cpu_baseline(inst)
     res["paper_context"] = ("paper (A100 40GB, JAX, 16-bit): 441x Picard speed-up over a "

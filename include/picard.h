@@ -195,6 +195,46 @@ pk_status pk_policy_scores(const pk_problem *problem, const pk_policy *policy, i
                            int32_t region, const int32_t *inv_row, float *scores, void *ws,
                            size_t ws_bytes, void *stream);
 
+/* Policy-gradient loop around the rollout (Section 4.2: each iteration rolls out the
+ * current policy, forms a policy gradient and takes an Adam step).  The three calls below
+ * with pk_picard_simulate (warm-started from the previous iterate's actions through
+ * pk_picard_opts.init_cache, the cache choice of Section 5) and pk_policy_grad make one
+ * iteration.
+ *
+ * Bytes of scratch pk_reinforce_advantages needs for this problem.  Writes *bytes. */
+pk_status pk_advantages_workspace_size(const pk_problem *problem, size_t *bytes);
+
+/* REINFORCE advantages of a rollout.  Step t earns the chosen warehouse's margin on the
+ * units it ships, r_t = (revenue - cost[a_t][region_t]) * shipped_t, and 0 for a lost
+ * sale (the FO model of Section 3 earns the chosen node's reward and nothing for an
+ * unserved order; `revenue` is the per-unit price that turns a cost into that reward).
+ *   advantages[t] = G_t - mean over the trajectory of G,  G_t = sum_{u >= t} r_u,
+ * with G, its sum and the rewards exact in int64 and one rounding at the end:
+ * float(double(G_t) - double(sum_b G) / T_b).  Synchronous (blocks until done).
+ * actions, shipped [total] in (as pk_picard_simulate writes them);
+ * advantages [total] out (float32); returns [n_traj] out, nullable: G at each
+ * trajectory's first order (its total reward; 0 for an empty trajectory).
+ * PK_ERR_INVALID_ARG if an action or region is out of range, shipped < 0, or a reward
+ * exceeds the bound that keeps the int64 sums exact: |r_t| <= min(2^31,
+ * 2^62 / (T_max (T_max + 1) / 2)), T_max the longest horizon. */
+pk_status pk_reinforce_advantages(const pk_problem *problem, const int32_t *actions,
+                                  const int32_t *shipped, int32_t revenue, float *advantages,
+                                  int64_t *returns, void *ws, size_t ws_bytes, void *stream);
+
+/* One Adam step (Kingma and Ba, Algorithm 1) on n float32 parameters, in float32:
+ *   m <- beta1 m + (1 - beta1) grad,  v <- beta2 v + (1 - beta2) grad^2,
+ *   params <- params + dir * lr * (m / (1 - beta1^step)) / (sqrt(v / (1 - beta2^step)) + eps)
+ * with dir = +1 when `ascend` is nonzero (maximise the objective whose gradient is grad,
+ * as for the REINFORCE surrogate) and -1 otherwise.  The hyperparameters are taken in
+ * double so that 1 - beta and the bias corrections are formed exactly before their one
+ * rounding to float32 (0.999 as a float would make 1 - beta2 wrong by 1.3e-5 relative).  params, m, v [n] in/out (m and v
+ * start at zero before step 1; the caller owns them); grad [n] in.  step >= 1 counts the
+ * calls.  Asynchronous on `stream`.  PK_ERR_INVALID_ARG for NULL pointers (n > 0),
+ * n < 0, step < 1, beta outside [0, 1), lr < 0 or eps <= 0. */
+pk_status pk_adam_step(float *params, const float *grad, float *m, float *v, int64_t n,
+                       int32_t step, double lr, double beta1, double beta2, double eps,
+                       int32_t ascend, void *stream);
+
 /* Message for the last non-OK status on this thread ("" if none). */
 const char *pk_last_error(void);
 

@@ -87,8 +87,13 @@ def lib():
         L.pk_policy_grad.argtypes = [P, Po, vp, vp, vp, vp, C.POINTER(C.c_double), vp, sz, i32, vp]
         L.pk_autotune.argtypes = [P, Po, vp, sz, C.POINTER(i32), vp]
         L.pk_policy_scores.argtypes = [P, Po, i32, i32, vp, vp, vp, sz, vp]
+        L.pk_advantages_workspace_size.argtypes = [P, C.POINTER(sz)]
+        L.pk_reinforce_advantages.argtypes = [P, vp, vp, i32, vp, vp, vp, sz, vp]
+        f64 = C.c_double
+        L.pk_adam_step.argtypes = [vp, vp, vp, vp, C.c_int64, i32, f64, f64, f64, f64, i32, vp]
         for f in ("pk_workspace_size", "pk_serial_simulate", "pk_picard_simulate",
-                  "pk_policy_grad", "pk_autotune", "pk_policy_scores"):
+                  "pk_policy_grad", "pk_autotune", "pk_policy_scores",
+                  "pk_advantages_workspace_size", "pk_reinforce_advantages", "pk_adam_step"):
             getattr(L, f).restype = C.c_int
         L.pk_last_error.restype = C.c_char_p
         L.pk_last_error.argtypes = []
@@ -276,6 +281,35 @@ def pk_policy_scores(prob: DeviceProblem, traj: int, region: int, inv_row: torch
     _check(lib().pk_policy_scores(C.byref(p), C.byref(po), traj, region, _ptr(inv_row),
                                   _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
     return out
+
+
+def pk_reinforce_advantages(prob: DeviceProblem, actions: torch.Tensor, shipped: torch.Tensor,
+                            revenue: int, want_returns=True, stream=None) -> dict:
+    """REINFORCE advantages of a rollout (reward-to-go minus its trajectory mean) and each
+    trajectory's total reward, from the margin reward (revenue - cost) * shipped."""
+    dev = prob.sku.device
+    p = prob.c_problem()
+    n = C.c_size_t(0)
+    _check(lib().pk_advantages_workspace_size(C.byref(p), C.byref(n)))
+    ws = workspace(int(n.value), dev)
+    adv = torch.empty(prob.total, dtype=torch.float32, device=dev)
+    ret = torch.empty(prob.n_traj, dtype=torch.int64, device=dev) if want_returns else None
+    _check(lib().pk_reinforce_advantages(C.byref(p), _ptr(actions), _ptr(shipped), int(revenue),
+                                         _ptr(adv), _ptr(ret), _ptr(ws), ws.numel(),
+                                         _stream(stream)))
+    return dict(advantages=adv, returns=ret)
+
+
+def pk_adam_step(params: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor,
+                 step: int, lr: float, beta1: float = 0.9, beta2: float = 0.999,
+                 eps: float = 1e-8, ascend: bool = True, stream=None) -> None:
+    """One in-place Adam step on float32 device tensors of equal length."""
+    for t in (params, grad, m, v):
+        if t.dtype != torch.float32 or not t.is_contiguous() or t.numel() != params.numel():
+            raise ValueError("params, grad, m and v must be contiguous float32 of equal length")
+    _check(lib().pk_adam_step(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), params.numel(),
+                              int(step), float(lr), float(beta1), float(beta2), float(eps),
+                              int(ascend), _stream(stream)))
 
 
 # C names are the primary API; the short names are aliases.

@@ -5,7 +5,7 @@ L(theta) = sum_t A_t log pi_theta(a_t | s_t) at fixed actions (the states are th
 actions induce); its backward calls pk_policy_grad, which recomputes the activations
 instead of storing them.  `actions` typically come from pk_picard_simulate with the same
 parameters (the Picard rollout of Section 2, used inside the policy-gradient loop of
-Section 4.2).
+Section 4.2) and `advantages` from pk_reinforce_advantages.
 """
 from __future__ import annotations
 
@@ -32,25 +32,3 @@ class PicardReinforce(torch.autograd.Function):
         r = api.pk_policy_grad(ctx.prob, actions, advantages, want_logp=False, want_grad=True)
         return grad_out * r["grad"], None, None, None
 
-
-def reward_to_go_advantages(prob: "api.DeviceProblem", actions: torch.Tensor,
-                            shipped: torch.Tensor, lost_penalty: float = 200.0) -> torch.Tensor:
-    """A_t = (reward-to-go of step t) - (its mean over the trajectory), with reward
-    r_t = -cost[a_t][region_t] * shipped_t - lost_penalty * (q_t - shipped_t).  A helper
-    for examples and tests: the advantages are an input of the gradient."""
-    offs = torch.as_tensor(prob.traj_offsets, device=actions.device)
-    traj = torch.repeat_interleave(torch.arange(prob.n_traj, device=actions.device),
-                                   offs[1:] - offs[:-1])
-    a = actions.long().clamp(min=0)
-    c = prob.cost[traj, a, prob.region.long()].double()
-    sh = shipped.double()
-    rew = torch.where(actions >= 0, -c * sh, torch.zeros_like(sh)) - lost_penalty * (
-        prob.qty.double() - sh)
-    out = torch.empty_like(rew)
-    for b in range(prob.n_traj):
-        lo, hi = int(prob.traj_offsets[b]), int(prob.traj_offsets[b + 1])
-        if hi == lo:
-            continue
-        rtg = torch.flip(torch.cumsum(torch.flip(rew[lo:hi], [0]), 0), [0])
-        out[lo:hi] = rtg - rtg.mean()
-    return out.float()

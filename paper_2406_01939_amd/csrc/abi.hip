@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -52,6 +53,15 @@ hipError_t launch_grad(const Prob &P, const Plan &L, const float *params, int la
                        const float *costT, const float *adv, float *logp_sorted, double *part,
                        int n_wg, float *grad, double *objective_dev, float *logp_out,
                        hipStream_t st);
+// train.hip
+size_t advantages_ws_bytes(int64_t total, int n_traj);
+hipError_t launch_advantages(const int64_t *offs_dev, int n_traj, int N, int R, int64_t total,
+                             const int32_t *region, const int32_t *actions,
+                             const int32_t *shipped, const int32_t *cost, int32_t revenue,
+                             int64_t rlim, int64_t *rew, unsigned long long *wsum, int32_t *err,
+                             void *scan_tmp, float *adv, int64_t *ret, hipStream_t st);
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, int64_t n,
+                       const AdamCoef &c, hipStream_t st);
 } // namespace pk
 
 using namespace pk;
@@ -934,6 +944,91 @@ pk_status pk_autotune(const pk_problem *problem, const pk_policy *policy, void *
                        (hipStream_t)stream, &B);
     if (s != PK_OK) return s;
     *best_block_len = B;
+    return PK_OK;
+}
+
+pk_status pk_advantages_workspace_size(const pk_problem *problem, size_t *bytes)
+{
+    g_err.clear();
+    Dims d;
+    pk_status s = check_problem(problem, &d);
+    if (s != PK_OK) return s;
+    if (!bytes) return fail(PK_ERR_INVALID_ARG, "bytes is NULL");
+    *bytes = advantages_ws_bytes(d.total, d.n_traj);
+    return PK_OK;
+}
+
+pk_status pk_reinforce_advantages(const pk_problem *problem, const int32_t *actions,
+                                  const int32_t *shipped, int32_t revenue, float *advantages,
+                                  int64_t *returns, void *ws, size_t ws_bytes, void *stream)
+{
+    g_err.clear();
+    Dims d;
+    pk_status s = check_problem(problem, &d);
+    if (s != PK_OK) return s;
+    if (d.total > 0 && (!actions || !shipped || !advantages))
+        return fail(PK_ERR_INVALID_ARG, "actions/shipped/advantages is NULL");
+    const size_t need = advantages_ws_bytes(d.total, d.n_traj);
+    if (!ws || ws_bytes < need)
+        return fail(PK_ERR_WORKSPACE, "workspace too small: need %zu bytes, got %zu", need,
+                    ws_bytes);
+    hipStream_t st = (hipStream_t)stream;
+    if (returns) HIP_TRY(hipMemsetAsync(returns, 0, (size_t)d.n_traj * sizeof(int64_t), st));
+    if (d.total == 0) {
+        HIP_TRY(hipStreamSynchronize(st));
+        return PK_OK;
+    }
+    // |r| <= rlim keeps every int64 sum exact: the weighted sum of a trajectory is at most
+    // rlim * T (T + 1) / 2 <= 2^62 and the batch prefix at most total * 2^31 < 2^62
+    const int64_t T = d.max_T;
+    const int64_t tri = T * (T + 1) / 2; // T < 2^31, so no overflow
+    const int64_t rlim = std::min<int64_t>(1ll << 31, (1ll << 62) / tri);
+    Carver c{align_ws(ws)};
+    int64_t *offs = c.take<int64_t>(d.n_traj + 1);
+    int64_t *rew = c.take<int64_t>(d.total);
+    unsigned long long *wsum = c.take<unsigned long long>(d.n_traj);
+    int32_t *err = c.take<int32_t>(1);
+    void *tmp = c.take<char>((int64_t)scan_tmp_bytes(d.total));
+    HIP_TRY(hipMemcpyAsync(offs, problem->traj_offsets, (d.n_traj + 1) * sizeof(int64_t),
+                           hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemsetAsync(wsum, 0, (size_t)d.n_traj * 8, st));
+    HIP_TRY(hipMemsetAsync(err, 0, 4, st));
+    HIP_TRY(launch_advantages(offs, d.n_traj, d.N, d.R, d.total, problem->region, actions,
+                              shipped, problem->cost, revenue, rlim, rew, wsum, err, tmp,
+                              advantages, returns, st));
+    int32_t herr = 0;
+    HIP_TRY(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (herr & 1) return fail(PK_ERR_INVALID_ARG, "an action, region or shipped count is out of range");
+    if (herr & 2)
+        return fail(PK_ERR_INVALID_ARG, "a reward exceeds %lld in magnitude (int64 sums would overflow)",
+                    (long long)rlim);
+    return PK_OK;
+}
+
+pk_status pk_adam_step(float *params, const float *grad, float *m, float *v, int64_t n,
+                       int32_t step, double lr, double beta1, double beta2, double eps,
+                       int32_t ascend, void *stream)
+{
+    g_err.clear();
+    if (n < 0) return fail(PK_ERR_INVALID_ARG, "n must be >= 0");
+    if (n > 0 && (!params || !grad || !m || !v))
+        return fail(PK_ERR_INVALID_ARG, "params/grad/m/v is NULL");
+    if (step < 1) return fail(PK_ERR_INVALID_ARG, "step must be >= 1");
+    if (!(beta1 >= 0.0 && beta1 < 1.0) || !(beta2 >= 0.0 && beta2 < 1.0))
+        return fail(PK_ERR_INVALID_ARG, "beta1/beta2 must lie in [0, 1)");
+    if (!(lr >= 0.0) || !(eps > 0.0)) return fail(PK_ERR_INVALID_ARG, "need lr >= 0 and eps > 0");
+    AdamCoef c;
+    c.lr = (float)lr;
+    c.b1 = (float)beta1;
+    c.b2 = (float)beta2;
+    c.omb1 = (float)(1.0 - beta1);
+    c.omb2 = (float)(1.0 - beta2);
+    c.bc1 = (float)(1.0 - std::pow(beta1, (double)step));
+    c.bc2 = (float)(1.0 - std::pow(beta2, (double)step));
+    c.eps = (float)eps;
+    c.dir = ascend ? 1.0f : -1.0f;
+    HIP_TRY(launch_adam(params, grad, m, v, n, c, (hipStream_t)stream));
     return PK_OK;
 }
 

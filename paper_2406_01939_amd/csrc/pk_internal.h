@@ -173,6 +173,11 @@ __device__ __forceinline__ void walk_finish(Ctl *ctl, bool wave_changed)
     }
 }
 
+// Coefficients of one Adam step, each rounded once to float32 from its double value.
+struct AdamCoef {
+    float lr, b1, b2, omb1, omb2, bc1, bc2, eps, dir;
+};
+
 // ---------------------------------------------------------------- host launchers
 // All return hipSuccess or the first HIP error.  `st` is the stream.
 hipError_t scan_i64(int64_t *data, int64_t n, bool inclusive, void *tmp, hipStream_t st);

@@ -31,7 +31,7 @@ import numpy as np
 EMB_DIM = 16
 N_FEATURES = 2 + EMB_DIM  # [cost, log1p(inventory), region embedding]
 
-# Named workloads (sizes as stated in the project brief).  T is either an int or a
+# Named benchmark workloads with their sizes.  T is either an int or a
 # (lo, hi) inclusive range drawn per trajectory from `t_seed`.
 WORKLOADS: Dict[str, dict] = {
     "greedy_n10_k100_t1e4": dict(N=10, K=100, R=20, T=10_000, qmax=1, n_traj=1,

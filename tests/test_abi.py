@@ -61,3 +61,30 @@ def test_host_validation_without_gpu():
     assert n.value > 0
     po = api.pk_policy(7, 0, 0, 0, None)
     assert api.lib().pk_workspace_size(C.byref(p), C.byref(po), None, C.byref(n)) == api.PK_ERR_INVALID_ARG
+
+
+def test_training_entry_points_validate_on_host():
+    """The policy-gradient entry points reject bad arguments before any device work."""
+    import numpy as np
+    from paper_2406_01939_amd import api
+    L = api.lib()
+    # Adam: step, betas, lr and eps are checked before the launch
+    assert L.pk_adam_step(None, None, None, None, 0, 1, 1e-3, 0.9, 0.999, 1e-8, 1, None) == api.PK_OK
+    assert L.pk_adam_step(None, None, None, None, 4, 1, 1e-3, 0.9, 0.999, 1e-8, 1, None) == api.PK_ERR_INVALID_ARG
+    assert L.pk_adam_step(None, None, None, None, -1, 1, 1e-3, 0.9, 0.999, 1e-8, 1, None) == api.PK_ERR_INVALID_ARG
+    assert L.pk_adam_step(None, None, None, None, 0, 0, 1e-3, 0.9, 0.999, 1e-8, 1, None) == api.PK_ERR_INVALID_ARG
+    assert L.pk_adam_step(None, None, None, None, 0, 1, 1e-3, 1.0, 0.999, 1e-8, 1, None) == api.PK_ERR_INVALID_ARG
+    assert L.pk_adam_step(None, None, None, None, 0, 1, -1.0, 0.9, 0.999, 1e-8, 1, None) == api.PK_ERR_INVALID_ARG
+    assert L.pk_adam_step(None, None, None, None, 0, 1, 1e-3, 0.9, 0.999, 0.0, 1, None) == api.PK_ERR_INVALID_ARG
+    assert b"eps" in L.pk_last_error()
+    # advantages: workspace size grows with the orders; NULL outputs and a small
+    # workspace are rejected
+    offs = np.array([0, 5, 5, 12], dtype=np.int64)
+    p = api.pk_problem(2, 1, 1, 3, offs.ctypes.data, 1, 1, 1, 1, 1, 0)
+    n = C.c_size_t(0)
+    assert L.pk_advantages_workspace_size(C.byref(p), C.byref(n)) == api.PK_OK
+    assert n.value >= 12 * 8 + 4 * 8
+    assert L.pk_reinforce_advantages(C.byref(p), None, None, 10, None, None, None, 0,
+                                     None) == api.PK_ERR_INVALID_ARG
+    assert L.pk_reinforce_advantages(C.byref(p), 1, 1, 10, 1, None, 1, 8,
+                                     None) == api.PK_ERR_WORKSPACE

@@ -15,6 +15,7 @@ from paper_2406_01939_amd.instances import make_instance, random_tiny
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-4
+REV = 20
 
 
 def _say(*a):
@@ -41,6 +42,19 @@ def _split(g, R, L):
         o += n
     assert o == g.size
     return parts
+
+
+def _oracle_rollout(oracle, inst, revenue=REV):
+    """Actions, shipped units and advantages of the oracle's serial rollout (FP64 policy),
+    batch-concatenated: the inputs both sides of a gradient comparison take."""
+    acts, ship, adv = [], [], []
+    for b in range(inst.n_traj):
+        s = oracle.serial(inst, b)
+        acts.append(s["actions"])
+        ship.append(s["shipped"])
+        adv.append(oracle.advantages(inst, s["actions"], s["shipped"], revenue, b)["advantages"])
+    cat = lambda xs: torch.from_numpy(np.concatenate(xs)).cuda()
+    return cat(acts), cat(ship), cat(adv)
 
 
 def _compare(oracle, inst, prob, api, actions, adv):
@@ -74,23 +88,21 @@ def _compare(oracle, inst, prob, api, actions, adv):
 @pytest.mark.parametrize("L", [2, 1])
 @pytest.mark.parametrize("seed", range(3))
 def test_tiny_gradient(api, oracle, seed, L):
-    from paper_2406_01939_amd.autograd import reward_to_go_advantages
     inst = random_tiny(200 + seed, N=6 + 9 * seed, K=3, R=5, T=150, qmax=1 + seed % 3,
                        inv_max=6, n_traj=2, mlp=True, n_hidden_layers=L)
     prob = api.DeviceProblem.from_instance(inst)
     _say(f"case grad tiny seed={seed} L={L}")
-    out = api.pk_picard_simulate(prob, "mlp", block_len=8)
-    adv = reward_to_go_advantages(prob, out["actions"], out["shipped"])
-    _compare(oracle, inst, prob, api, out["actions"], adv)
+    acts, _, adv = _oracle_rollout(oracle, inst)
+    _compare(oracle, inst, prob, api, acts, adv)
 
 
 def test_gradient_random_advantages_batch(api, oracle):
     inst = make_instance("mlp_batch64_n100_k5e4_t2e5", n_traj=2, T=3000, K=1000)
     prob = api.DeviceProblem.from_instance(inst)
     _say("case grad batch2 T=3000")
-    out = api.pk_picard_simulate(prob, "mlp", block_len=256)
+    acts, _, _ = _oracle_rollout(oracle, inst)
     adv = torch.randn(inst.total_orders, generator=torch.Generator().manual_seed(0)).cuda()
-    _compare(oracle, inst, prob, api, out["actions"], adv)
+    _compare(oracle, inst, prob, api, acts, adv)
 
 
 def test_gradient_is_reproducible(api):
@@ -108,12 +120,12 @@ def test_gradient_is_reproducible(api):
 
 
 def test_autograd_function(api):
-    from paper_2406_01939_amd.autograd import PicardReinforce, reward_to_go_advantages
+    from paper_2406_01939_amd.autograd import PicardReinforce
     inst = random_tiny(300, N=10, K=3, R=4, T=120, qmax=2, inv_max=5, mlp=True)
     prob = api.DeviceProblem.from_instance(inst)
     _say("case autograd")
     out = api.pk_picard_simulate(prob, "mlp", block_len=4)
-    adv = reward_to_go_advantages(prob, out["actions"], out["shipped"])
+    adv = api.pk_reinforce_advantages(prob, out["actions"], out["shipped"], REV)["advantages"]
     params = prob.params.clone().requires_grad_(True)
     L = PicardReinforce.apply(params, prob, out["actions"], adv)
     (2.0 * L).backward()
