@@ -157,7 +157,7 @@ def alg1(inst, worker: np.ndarray, n_workers: int, b: int = 0, init_cache=None,
 
 def picard_runs(inst, worker: np.ndarray, b: int = 0, init_cache=None,
                 max_passes: Optional[int] = None, record: bool = False) -> dict:
-    """Run-form Picard (same passes as Algorithm 1 for one-run-per-segment partitions)."""
+    """Run-form Picard: the same passes as Algorithm 1, for any partition."""
     B = _Bound(inst, b)
     T = B.T
     if max_passes is None:
@@ -170,8 +170,6 @@ def picard_runs(inst, worker: np.ndarray, b: int = 0, init_cache=None,
     caches = np.empty((max_passes, T), np.int32) if record else None
     rc = lib().orc_picard_runs(C.byref(B.p), _ptr(worker), _ptr(init), max_passes, _ptr(fin),
                                _ptr(passes), _ptr(changed), _ptr(caches))
-    if rc == -2:
-        raise ValueError("partition gives some process two runs of one SKU")
     _check(rc, "picard_runs")
     k = int(passes[0])
     return dict(actions=fin, passes=k, converged=rc == 0, changed=changed[:k],

@@ -14,12 +14,12 @@
  *                     that are infeasible locally are replaced by the always-feasible
  *                     action (lost sale).  O(P*T*N) per pass: tiny instances only.
  *   orc_picard_runs   The same passes, computed per SKU: by inventory independence
- *                     (Assumption 1) and with no capacity, SKUs never interact, and for
- *                     a partition where each process owns one contiguous run of a SKU's
- *                     orders, the state a process sees at the start of its run is the
- *                     initial inventory minus the cached consumption of earlier runs,
- *                     clamped at zero (clamp: max(0, max(0, x-a) - b) = max(0, x-a-b)).
- *                     Checked against orc_alg1 in the tests.
+ *                     (Assumption 1) and with no capacity, SKUs never interact.  A
+ *                     process reaching one of its runs of a SKU has applied the cached
+ *                     actions of the other processes' earlier orders and its own fresh
+ *                     actions of its earlier runs, so it sees the initial inventory
+ *                     minus both consumptions, clamped at zero (clamp: max(0,
+ *                     max(0, x-a) - b) = max(0, x-a-b)).  Checked against orc_alg1.
  *   orc_eval_at       The policy evaluated at every step of a GIVEN action sequence
  *                     (the state that sequence induces), for self-consistency checks.
  *   orc_reinforce     FP64 REINFORCE surrogate sum_t A_t log pi(a_t | s_t) and its
@@ -363,11 +363,12 @@ int orc_alg1(const orc_problem *P, const int64_t *worker, int64_t n_workers,
 
 /* ------------------------------------------------------------------------------------
  * The same passes, per SKU.  Orders of SKU k in time order form its segment; a run is
- * a maximal stretch of the segment owned by one process.  Each process must own at
- * most one run per segment (true for blocks of the SKU-sorted order list, and for one
- * process per step); otherwise -2.  Per pass and per segment, runs are visited in order:
- *   entry state = max(0, x0[k] - E), E = cached consumption (sum of q over earlier runs'
- *   orders sent to each warehouse under alpha^{k-1});
+ * a maximal stretch of the segment owned by one process.  Per pass and per segment,
+ * runs are visited in order:
+ *   entry state = max(0, x0[k] - E - D), E = cached consumption (sum of q over earlier
+ *   runs' orders sent to each warehouse under alpha^{k-1}), D = the run's process's own
+ *   correction: over its earlier runs of this segment, q at the warehouse it chose in
+ *   this pass minus q at the cached warehouse (0 when the process owns one run);
  *   the run is walked with the process's own decisions.
  * changed (nullable): number of steps with alpha^k != alpha^{k-1}, per pass.
  * ---------------------------------------------------------------------------------- */
@@ -387,25 +388,16 @@ int orc_picard_runs(const orc_problem *P, const int64_t *worker, const int32_t *
     int32_t *prev = (int32_t *)malloc(sizeof(int32_t) * (size_t)(T + 1));
     int32_t *next = (int32_t *)malloc(sizeof(int32_t) * (size_t)(T + 1));
     int64_t *E = (int64_t *)malloc(sizeof(int64_t) * (size_t)N);
+    int64_t *D = (int64_t *)malloc(sizeof(int64_t) * (size_t)N);
     int32_t *x = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
     int rc = 0;
-    if (!start || !fill || !pos || !prev || !next || !E || !x) { rc = -1; goto done; }
+    if (!start || !fill || !pos || !prev || !next || !E || !D || !x) { rc = -1; goto done; }
     for (int64_t t = 0; t < T; ++t) start[P->sku[t] + 1]++;
     for (int k = 0; k < K; ++k) start[k + 1] += start[k];
     for (int64_t t = 0; t < T; ++t) {
         int s = P->sku[t];
         pos[start[s] + fill[s]++] = t;
     }
-    /* each process owns at most one run per segment */
-    for (int k = 0; k < K && rc == 0; ++k) {
-        for (int64_t i = start[k]; i < start[k + 1]; ++i) {
-            if (i == start[k] || worker[pos[i]] == worker[pos[i - 1]]) continue;
-            for (int64_t j = start[k]; j < i; ++j)
-                if (worker[pos[j]] == worker[pos[i]]) { rc = -2; break; }
-            if (rc) break;
-        }
-    }
-    if (rc) goto done;
     for (int64_t t = 0; t < T; ++t) prev[t] = init_cache ? init_cache[t] : LOST;
     rc = 1;
     int32_t k;
@@ -417,8 +409,16 @@ int orc_picard_runs(const orc_problem *P, const int64_t *worker, const int32_t *
             while (i < start[s + 1]) {
                 int64_t j = i;
                 while (j < start[s + 1] && worker[pos[j]] == worker[pos[i]]) ++j;
+                /* the process's own earlier orders of this segment: fresh minus cached */
+                for (int w = 0; w < N; ++w) D[w] = 0;
+                for (int64_t p = start[s]; p < i; ++p) {
+                    int64_t t = pos[p];
+                    if (worker[t] != worker[pos[i]]) continue;
+                    if (next[t] != LOST) D[next[t]] += P->qty[t];
+                    if (prev[t] != LOST) D[prev[t]] -= P->qty[t];
+                }
                 for (int w = 0; w < N; ++w) {
-                    int64_t v = (int64_t)x0k[w] - E[w];
+                    int64_t v = (int64_t)x0k[w] - E[w] - D[w];
                     x[w] = v > 0 ? (int32_t)v : 0;
                 }
                 for (int64_t p = i; p < j; ++p) {
@@ -445,7 +445,7 @@ int orc_picard_runs(const orc_problem *P, const int64_t *worker, const int32_t *
     *passes = k;
     memcpy(final_cache, prev, sizeof(int32_t) * (size_t)T);
 done:
-    free(start); free(fill); free(pos); free(prev); free(next); free(E); free(x);
+    free(start); free(fill); free(pos); free(prev); free(next); free(E); free(D); free(x);
     mlp_free(&m);
     return rc;
 }

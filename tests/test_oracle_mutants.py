@@ -44,6 +44,10 @@ MUTANTS = [
     ("runs_consumption_counts_orders",
      "if (prev[t] != LOST) E[prev[t]] += P->qty[t];",
      "if (prev[t] != LOST) E[prev[t]] += 1;"),
+    ("runs_own_correction_dropped",
+     "int64_t v = (int64_t)x0k[w] - E[w] - D[w];", "int64_t v = (int64_t)x0k[w] - E[w];"),
+    ("runs_own_correction_cached_not_removed",
+     "if (prev[t] != LOST) D[prev[t]] -= P->qty[t];", ";"),
     ("philox_multiplier_swapped",
      "uint64_t p0 = (uint64_t)M0 * c0;", "uint64_t p0 = (uint64_t)M1 * c0;"),
     ("philox_nine_rounds", "round < 10", "round < 9"),

@@ -99,13 +99,34 @@ def test_run_count_bound_and_product_partition(oracle, seed):
     np.testing.assert_array_equal(r["actions"], ser)
 
 
-def test_runs_rejects_split_process(oracle):
+def test_runs_split_process_alternating(oracle):
+    """Each process owns two runs of the one SKU: the run form carries the process's own
+    fresh-minus-cached consumption from its first run to its second."""
     inst = random_tiny(5, N=3, K=1, R=1, T=6)
-    worker = np.array([0, 1, 0, 1, 0, 1])  # each process owns two runs of SKU 0
-    with pytest.raises(ValueError):
-        oracle.picard_runs(inst, worker)
-    r = oracle.alg1(inst, worker, 2)  # the literal algorithm handles any partition
-    np.testing.assert_array_equal(r["actions"], oracle.serial(inst)["actions"])
+    worker = np.array([0, 1, 0, 1, 0, 1])
+    lit = oracle.alg1(inst, worker, 2)
+    run = oracle.picard_runs(inst, worker, record=True)
+    assert lit["passes"] == run["passes"]
+    np.testing.assert_array_equal(lit["caches"], run["caches"])
+    np.testing.assert_array_equal(run["actions"], oracle.serial(inst)["actions"])
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_alg1_equals_runs_random_partitions(oracle, seed):
+    """Uniform random partitions (Section 4.1): a process owns scattered orders, so it
+    has many runs of one SKU.  Every pass's cache equals Algorithm 1's."""
+    rng = np.random.default_rng(4000 + seed)
+    mlp = seed % 4 == 1
+    inst = random_tiny(seed + 4100, N=4, K=1 + seed % 3, R=3, T=30, qmax=1 + seed % 3,
+                       inv_max=5, mlp=mlp)
+    T = inst.total_orders
+    P = int(rng.integers(2, 8))
+    worker = rng.integers(0, P, T)
+    init = rng.integers(-1, inst.N, T).astype(np.int32) if seed % 2 else None
+    lit = oracle.alg1(inst, worker, P, init_cache=init)
+    run = oracle.picard_runs(inst, worker, init_cache=init, record=True)
+    assert lit["passes"] == run["passes"]
+    np.testing.assert_array_equal(lit["caches"], run["caches"])
 
 
 def test_not_converged_reports_partial(oracle):
