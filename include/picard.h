@@ -119,6 +119,13 @@ typedef struct pk_picard_opts {
     const int32_t *init_cache; /* nullable [total], values in [-1, N): alpha^0 in time
                                   order; NULL = lost sale everywhere (Algorithm 1) */
     int32_t validate;     /* nonzero: device range checks of the inputs */
+    const int32_t *partition; /* nullable [total], values >= 0: the process of every order
+                                 (time order), any assignment, e.g. the uniform random
+                                 partitions of Section 4.1; block_len is then ignored.
+                                 A process may own several runs of one SKU; each run
+                                 starts from the state its process reaches under
+                                 Algorithm 1.  GREEDY policy only (PK_ERR_UNSUPPORTED for
+                                 MLP); PK_ERR_INVALID_ARG for a negative process. */
 } pk_picard_opts;
 
 /* Statistics of one pk_picard_simulate call (all optional). */

@@ -56,7 +56,7 @@ class pk_policy(C.Structure):
 class pk_picard_opts(C.Structure):
     _fields_ = [("block_len", C.c_int32), ("max_passes", C.c_int32),
                 ("use_frontier", C.c_int32), ("graph_unroll", C.c_int32),
-                ("init_cache", C.c_void_p), ("validate", C.c_int32)]
+                ("init_cache", C.c_void_p), ("validate", C.c_int32), ("partition", C.c_void_p)]
 
 
 class pk_stats(C.Structure):
@@ -195,7 +195,7 @@ def workspace(nbytes: int, device) -> torch.Tensor:
 
 def pk_workspace_size(prob: DeviceProblem, policy: str = "greedy", block_len: int = 0) -> int:
     p, po = prob.c_problem(), prob.c_policy(policy)
-    o = pk_picard_opts(block_len, 0, 1, 0, None, 0)
+    o = pk_picard_opts(block_len, 0, 1, 0, None, 0, None)
     n = C.c_size_t(0)
     _check(lib().pk_workspace_size(C.byref(p), C.byref(po), C.byref(o), C.byref(n)))
     return int(n.value)
@@ -218,12 +218,13 @@ def pk_serial_simulate(prob: DeviceProblem, policy: str = "greedy", want_shipped
 def pk_picard_simulate(prob: DeviceProblem, policy: str = "greedy", block_len: int = 0,
                        max_passes: int = 0, use_frontier: bool = True, graph_unroll: int = 0,
                        init_cache: Optional[torch.Tensor] = None, validate: bool = False,
+                       partition: Optional[torch.Tensor] = None,
                        want_shipped=True, want_final=True, timing=False, stream=None,
                        raise_not_converged=True, out: Optional[dict] = None) -> dict:
     dev = prob.sku.device
     p, po = prob.c_problem(), prob.c_policy(policy)
     o = pk_picard_opts(block_len, max_passes, int(use_frontier), graph_unroll,
-                       _ptr(init_cache), int(validate))
+                       _ptr(init_cache), int(validate), _ptr(partition))
     n = C.c_size_t(0)
     _check(lib().pk_workspace_size(C.byref(p), C.byref(po), C.byref(o), C.byref(n)))
     ws = workspace(int(n.value), dev)

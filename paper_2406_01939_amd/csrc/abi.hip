@@ -28,6 +28,9 @@ hipError_t launch_pass_end(const Plan &L, hipStream_t st);
 hipError_t launch_consume(const Prob &P, const Plan &L, int64_t n_split_max, hipStream_t st);
 hipError_t launch_unpermute(const Prob &P, const Plan &L, int32_t *actions, int32_t *shipped,
                             hipStream_t st);
+// walk_chain.hip
+hipError_t launch_walk_chain_greedy(const Prob &P, const Plan &L, int32_t *final_inv,
+                                    bool has_init, int n_cus, hipStream_t st);
 // walk_greedy.hip
 size_t walk_greedy_lds(int N, int R);
 hipError_t launch_walk_greedy(const Prob &P, const Plan &L, const void *keys, int32_t *final_inv,
@@ -195,6 +198,8 @@ void carve_plan(Carver &c, const Dims &d, const pk_policy *po, int B, Plan *L,
     p.sr_lo = c.take<int32_t>(s.n_sr_max + 1);
     p.sr_seg = c.take<int32_t>(s.n_sr_max);
     p.sr_uidx = c.take<int32_t>(s.n_sr_max);
+    p.ch_prevj = c.take<int32_t>(s.n_sr_max);
+    p.ch_next = c.take<int32_t>(s.n_sr_max);
     p.seg_key = c.take<int32_t>(s.n_seg_max);
     p.seg_sr0 = c.take<int32_t>(s.n_seg_max + 1);
     p.split_segs = c.take<int32_t>(s.n_seg_max);
@@ -451,6 +456,7 @@ pk_status picard_run(const pk_problem *problem, const Dims &d, const pk_policy *
     void *scratch;
     carve_plan(c, d, policy, B, &L, &to, &scratch);
     L.no_frontier = o.use_frontier ? 0 : 1;
+    L.worker = o.partition;
     const Sizes sz = plan_sizes(d, B);
     HIP_TRY(hipMemcpyAsync(to, problem->traj_offsets, (d.n_traj + 1) * sizeof(int64_t),
                            hipMemcpyHostToDevice, st));
@@ -509,6 +515,8 @@ pk_status picard_run(const pk_problem *problem, const Dims &d, const pk_policy *
         if (policy->kind == PK_POLICY_MLP)
             HIP_TRY(launch_walk_mlp(P, L, policy->params, policy->n_hidden_layers, L.costT,
                                     final_inv, has_init, num_cus() * 3, s2)); // resident: 3 per CU
+        else if (L.worker)
+            HIP_TRY(launch_walk_chain_greedy(P, L, final_inv, has_init, grid, s2));
         else
             HIP_TRY(launch_walk_greedy(P, L, L.pos, final_inv, has_init, grid, s2));
         if (ge) {
@@ -591,7 +599,7 @@ pk_status picard_run(const pk_problem *problem, const Dims &d, const pk_policy *
         if (stats->passes)
             for (int b = 0; b < d.n_traj; ++b) stats->passes[b] = lcp[b] + 1;
         stats->passes_max = d.total > 0 ? hc->passes_done : 1;
-        stats->block_len = B;
+        stats->block_len = o.partition ? 0 : B;
         unsigned long long sum[ST_N] = {};
         for (int i = 0; i < STAT_SLOTS; ++i)
             for (int k = 0; k < ST_N; ++k) sum[k] += hc->stat[i][k];
@@ -770,6 +778,7 @@ pk_status pk_workspace_size(const pk_problem *problem, const pk_policy *policy,
     if (!bytes) return fail(PK_ERR_INVALID_ARG, "bytes is NULL");
     int B = opts && opts->block_len > 0 ? opts->block_len : MIN_AUTOTUNE_BLOCK;
     if (policy->kind == PK_POLICY_MLP && !(opts && opts->block_len > 0)) B = MIN_AUTOTUNE_BLOCK;
+    if (opts && opts->partition) B = 1;
     *bytes = std::max(picard_bytes(d, policy, B), serial_bytes(d)) +
              (((size_t)std::max<int64_t>(d.total, 1) * 4 + 255) & ~(size_t)255) + 512;
     if (policy->kind == PK_POLICY_MLP) *bytes = std::max(*bytes, grad_bytes(d, policy));
@@ -827,6 +836,11 @@ pk_status pk_picard_simulate(const pk_problem *problem, const pk_policy *policy,
     if (opts) o = *opts;
     if (o.block_len < 0 || o.max_passes < 0 || o.graph_unroll < 0)
         return fail(PK_ERR_INVALID_ARG, "negative option");
+    if (o.partition) {
+        if (policy->kind != PK_POLICY_GREEDY)
+            return fail(PK_ERR_UNSUPPORTED, "a given partition needs the greedy policy");
+        o.block_len = 1; // sizes the plan for one run per order, the most a partition makes
+    }
     int B = o.block_len;
     if (B == 0 && policy->kind == PK_POLICY_MLP) B = DEFAULT_BLOCK_MLP;
     if (B == 0) {

@@ -30,6 +30,7 @@ enum { ST_ORDERS = 0, ST_RUNS, ST_CHANGED, ST_BYTES, ST_NEAR_TIES, ST_FLOPS, ST_
 
 // Ctl::error bits set by device-side consistency checks (the validate bits are 1..8).
 constexpr int32_t ERR_NO_PROGRESS = 1 << 12; // a walk step could not commit any order
+constexpr int32_t ERR_PARTITION = 1 << 4;    // a given partition names a negative process
 
 struct Ctl {
     int32_t pass;        // current pass (1-based)
@@ -81,6 +82,12 @@ struct Plan {
     int32_t *E;              // [n_split_max][N] consumption entering each split run
     float *costT;            // [n_traj][R][N] cost as float, region-major (learned policy)
     void *pos;               // greedy: key table of greedy_keys.h
+    const int32_t *worker;   // nullable [total] process of each order (original order);
+                             // null: blocks of B sorted positions are the processes
+    int32_t *ch_prevj;       // [n_sr_max] given partitions: index within its segment of the
+                             // previous run of the same process, -1 if none
+    int32_t *ch_next;        // [n_sr_max] given partitions: next run of the same process in
+                             // the segment, -1 if none
     int32_t *traj_lcp;       // [n_traj] last pass in which the trajectory changed
     int32_t *sink;           // [128] write target of masked-off lanes (contents unused)
     Ctl *ctl;

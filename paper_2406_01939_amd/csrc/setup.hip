@@ -38,6 +38,15 @@ __global__ void k_check_inv(const int32_t *x0, int64_t n, Ctl *ctl)
         if (x0[i] < 0) atomicOr(&ctl->error, 2);
 }
 
+// A run starts at every segment start and, inside a segment, where the process changes:
+// every B positions for block partitions, where the given process differs for others.
+__device__ __forceinline__ bool run_start_at(const Plan &L, int64_t p, bool seg_start)
+{
+    if (seg_start) return true;
+    if (L.worker) return L.worker[L.perm[p]] != L.worker[L.perm[p - 1]];
+    return (p % L.B) == 0;
+}
+
 // Gather the sorted order data and the run/segment start flags.  flags[p] packs the
 // run-start count in the low 32 bits and the segment-start count in the high 32 bits.
 __global__ void k_gather(Prob P, Plan L, const int32_t *init_cache, int validate,
@@ -59,12 +68,13 @@ __global__ void k_gather(Prob P, Plan L, const int32_t *init_cache, int validate
             }
         }
         L.s_alpha[p] = a;
+        if (L.worker && L.worker[o] < 0) atomicOr(&L.ctl->error, ERR_PARTITION);
         if (want_t) {
             const int b = key / P.K;
             L.s_t[p] = (int32_t)(o - P.traj_off[b]);
         }
         const bool seg_start = p == 0 || L.s_key[p - 1] != key;
-        const bool run_start = seg_start || (p % L.B) == 0;
+        const bool run_start = run_start_at(L, p, seg_start);
         flags[p] = (run_start ? 1ll : 0ll) | (seg_start ? (1ll << 32) : 0ll);
     }
 }
@@ -78,7 +88,7 @@ __global__ void k_tables(Prob P, Plan L, const int64_t *flags)
         const int32_t sr = (int32_t)(f & 0xffffffffll) - 1;
         const int32_t sg = (int32_t)(f >> 32) - 1;
         const bool seg_start = p == 0 || L.s_key[p - 1] != L.s_key[p];
-        const bool run_start = seg_start || (p % L.B) == 0;
+        const bool run_start = run_start_at(L, p, seg_start);
         if (run_start) {
             L.sr_lo[sr] = (int32_t)p;
             L.sr_seg[sr] = sg;
@@ -147,6 +157,50 @@ __global__ void k_run_desc(Plan L, const int64_t *base)
         L.sr_uidx[s] = uidx;
         if (split) L.split_list[uidx] = s;
         L.rd[s] = RunDesc{L.sr_lo[s], L.sr_lo[s + 1], L.seg_key[g], g, s - s0, s1 - s0, uidx, 0};
+    }
+}
+
+// Chains of a given partition: a process's runs of one segment, in order.  The runs are
+// sorted stably by process and then by segment, so each chain's runs become neighbours;
+// entries past the run count (keys 0x7fffffff) sort last and are ignored.
+__global__ void k_chain_keys(Plan L, int64_t n, int32_t *keys, int32_t *vals)
+{
+    const int n_sr = L.ctl->n_sr;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += stride) {
+        const bool run = s < n_sr;
+        keys[s] = run ? L.worker[L.perm[L.sr_lo[s]]] : 0x7fffffff;
+        vals[s] = (int32_t)s;
+        if (run) {
+            L.ch_prevj[s] = -1;
+            L.ch_next[s] = -1;
+        }
+    }
+}
+
+__global__ void k_chain_seg_keys(Plan L, int64_t n, const int32_t *vals, int32_t *keys)
+{
+    const int n_sr = L.ctl->n_sr;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const int32_t s = vals[i];
+        keys[i] = s < n_sr ? L.sr_seg[s] : 0x7fffffff;
+    }
+}
+
+// vals: runs in (segment, process, position) order; neighbours of one chain are linked.
+__global__ void k_chain_link(Plan L, int64_t n, const int32_t *vals)
+{
+    const int n_sr = L.ctl->n_sr;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i + 1 < n; i += stride) {
+        const int32_t s = vals[i], t = vals[i + 1];
+        if (s >= n_sr || t >= n_sr) continue;
+        const int32_t g = L.sr_seg[s];
+        if (L.sr_seg[t] != g) continue;
+        if (L.worker[L.perm[L.sr_lo[s]]] != L.worker[L.perm[L.sr_lo[t]]]) continue;
+        L.ch_next[s] = t;
+        L.ch_prevj[t] = s - L.seg_sr0[g];
     }
 }
 
@@ -238,6 +292,31 @@ hipError_t setup_plan(const Prob &P, Plan &L, const int32_t *init_cache, int val
                        cnt, n_seg_max);
     hipLaunchKernelGGL(k_run_desc, dim3(grid_for(n + n_seg_max, 256, 8192)), dim3(256), 0, st, L,
                        cnt);
+    if (L.worker) {
+        // chains: at most n runs; the scratch above is free again (keys_a/vals_a reuse the
+        // flags area, which holds 2n int32)
+        int32_t *ka = (int32_t *)flags, *va = ka + n;
+        hipLaunchKernelGGL(k_chain_keys, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, L, n,
+                           ka, va);
+        bool alt = false;
+        e = radix_sort_pairs(ka, va, keys_b, vals_b, n, 31, tmp, st, &alt);
+        if (e != hipSuccess) return e;
+        int32_t *v1 = alt ? vals_b : va;
+        int32_t *k2 = alt ? ka : keys_b, *v2 = alt ? va : vals_b; // the free pair
+        hipLaunchKernelGGL(k_chain_seg_keys, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, L,
+                           n, v1, k2);
+        if (v1 != v2) {
+            e = hipMemcpyAsync(v2, v1, n * sizeof(int32_t), hipMemcpyDeviceToDevice, st);
+            if (e != hipSuccess) return e;
+        }
+        int seg_bits = 1;
+        while (seg_bits < 31 && (1ll << seg_bits) < (int64_t)n_seg_max) ++seg_bits;
+        int32_t *k3 = k2 == ka ? keys_b : ka, *v3 = v2 == va ? vals_b : va;
+        e = radix_sort_pairs(k2, v2, k3, v3, n, seg_bits, tmp, st, &alt);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_chain_link, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, L, n,
+                           alt ? v3 : v2);
+    }
     return hipGetLastError();
 }
 

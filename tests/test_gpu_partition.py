@@ -1,0 +1,154 @@
+"""GPU parity of Picard under a partition given per order (greedy policy).
+
+Uniform random partitions (Section 4.1) give a process several runs of one SKU; product
+partitions (Section 3) one run per SKU.  Against the oracle's run form under the same
+partition (itself pinned pass by pass to the literal Algorithm 1): actions, units
+shipped, final inventory and passes bit-exact, the cache after every pass, warm starts,
+the no-frontier mode, ragged batches; at 1e6 orders the converged actions against the
+serial oracle.  Errors: a negative process, the learned policy.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2406_01939_amd.instances import make_instance, random_tiny
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2406_01939_amd import api as A
+    A.lib()
+    return A
+
+
+def _oracle(oracle, inst, worker, init=None, record=False):
+    acts, ships, fins, passes, caches = [], [], [], [], []
+    for b in range(inst.n_traj):
+        lo, hi = int(inst.traj_offsets[b]), int(inst.traj_offsets[b + 1])
+        s = oracle.serial(inst, b)
+        pr = oracle.picard_runs(inst, worker[lo:hi], b,
+                                init_cache=None if init is None else init[lo:hi], record=record)
+        assert pr["converged"]
+        np.testing.assert_array_equal(pr["actions"], s["actions"])
+        acts.append(s["actions"]); ships.append(s["shipped"]); fins.append(s["final_inv"])
+        passes.append(pr["passes"])
+        caches.append(pr["caches"])
+    return np.concatenate(acts), np.concatenate(ships), np.stack(fins), np.array(passes), caches
+
+
+def _run(api, prob, worker, **kw):
+    part = torch.from_numpy(np.ascontiguousarray(worker, dtype=np.int32)).cuda()
+    return api.pk_picard_simulate(prob, "greedy", partition=part, validate=True, **kw)
+
+
+@pytest.mark.parametrize("P", [2, 5, 40])
+@pytest.mark.parametrize("seed", range(4))
+def test_random_partition_tiny(api, oracle, seed, P):
+    inst = random_tiny(900 + seed, N=1 + 5 * seed, K=3, R=3, T=160, qmax=1 + seed % 3,
+                       inv_max=6, n_traj=3)
+    worker = np.random.default_rng(seed).integers(0, P, inst.total_orders)
+    _say(f"case partition tiny seed={seed} P={P}")
+    want_a, want_s, want_f, want_p, _ = _oracle(oracle, inst, worker)
+    out = _run(api, api.DeviceProblem.from_instance(inst), worker)
+    np.testing.assert_array_equal(out["actions"].cpu().numpy(), want_a)
+    np.testing.assert_array_equal(out["shipped"].cpu().numpy(), want_s)
+    np.testing.assert_array_equal(out["final_inv"].cpu().numpy(), want_f)
+    np.testing.assert_array_equal(out["passes"], want_p)
+    assert out["stats"]["block_len"] == 0
+
+
+def test_every_pass_matches_oracle_cache(api, oracle):
+    inst = make_instance("greedy_n10_k100_t1e4")
+    worker = np.random.default_rng(7).integers(0, 300, inst.total_orders)
+    _, _, _, want_p, caches = _oracle(oracle, inst, worker, record=True)
+    prob = api.DeviceProblem.from_instance(inst)
+    k_max = int(want_p[0])
+    _say(f"case partition every pass (passes={k_max})")
+    for k in range(1, k_max + 1):
+        out = _run(api, prob, worker, max_passes=k, raise_not_converged=False)
+        np.testing.assert_array_equal(out["actions"].cpu().numpy(), caches[0][k - 1])
+
+
+@pytest.mark.parametrize("frontier", [True, False])
+def test_warm_start_and_frontier(api, oracle, frontier):
+    inst = random_tiny(950, N=7, K=4, R=3, T=400, qmax=2, inv_max=9, n_traj=2)
+    rng = np.random.default_rng(3)
+    worker = rng.integers(0, 12, inst.total_orders)
+    init = rng.integers(-1, inst.N, inst.total_orders).astype(np.int32)
+    _say(f"case partition warm start frontier={frontier}")
+    want_a, want_s, want_f, want_p, _ = _oracle(oracle, inst, worker, init=init)
+    out = _run(api, api.DeviceProblem.from_instance(inst), worker,
+               init_cache=torch.from_numpy(init).cuda(), use_frontier=frontier)
+    np.testing.assert_array_equal(out["actions"].cpu().numpy(), want_a)
+    np.testing.assert_array_equal(out["final_inv"].cpu().numpy(), want_f)
+    np.testing.assert_array_equal(out["passes"], want_p)
+
+
+def test_product_partition_and_wide_warehouses(api, oracle):
+    """Products assigned to random processes (one run per SKU: two passes), and N above
+    one wave's 64 lanes."""
+    inst = random_tiny(960, N=150, K=6, R=4, T=300, qmax=2, inv_max=3, n_traj=2)
+    proc_of_sku = np.random.default_rng(1).integers(0, 4, inst.K)
+    worker = proc_of_sku[inst.sku]
+    _say("case product partition N=150")
+    want_a, want_s, want_f, want_p, _ = _oracle(oracle, inst, worker)
+    assert (want_p <= 2).all()
+    out = _run(api, api.DeviceProblem.from_instance(inst), worker)
+    np.testing.assert_array_equal(out["actions"].cpu().numpy(), want_a)
+    np.testing.assert_array_equal(out["final_inv"].cpu().numpy(), want_f)
+    np.testing.assert_array_equal(out["passes"], want_p)
+
+
+def test_batch_uniform_partition(api, oracle):
+    inst = make_instance("greedy_batch256_n50_k2e4", T=(2000, 6000), n_traj=4, K=300)
+    worker = np.random.default_rng(11).integers(0, 500, inst.total_orders)
+    _say("case partition batch of 4, 500 processes")
+    want_a, want_s, want_f, want_p, _ = _oracle(oracle, inst, worker)
+    out = _run(api, api.DeviceProblem.from_instance(inst), worker)
+    np.testing.assert_array_equal(out["actions"].cpu().numpy(), want_a)
+    np.testing.assert_array_equal(out["shipped"].cpu().numpy(), want_s)
+    np.testing.assert_array_equal(out["final_inv"].cpu().numpy(), want_f)
+    np.testing.assert_array_equal(out["passes"], want_p)
+
+
+def test_full_size_uniform_partition(api, oracle):
+    """1e6 orders, 1e4 processes: the converged actions equal the serial rollout."""
+    inst = make_instance("greedy_n100_k1e5_t1e6")
+    worker = np.random.default_rng(5).integers(0, 10_000, inst.total_orders)
+    want = oracle.serial(inst, 0)
+    _say("case partition N=100 K=1e5 T=1e6, 1e4 processes")
+    out = _run(api, api.DeviceProblem.from_instance(inst), worker)
+    np.testing.assert_array_equal(out["actions"].cpu().numpy(), want["actions"])
+    np.testing.assert_array_equal(out["final_inv"].cpu().numpy()[0], want["final_inv"])
+    _say("  passes", int(out["passes"][0]))
+
+
+def test_partition_errors(api):
+    inst = random_tiny(970, N=4, K=2, R=2, T=50)
+    prob = api.DeviceProblem.from_instance(inst)
+    worker = np.zeros(inst.total_orders, np.int32)
+    worker[10] = -3
+    _say("case partition negative process")
+    with pytest.raises(api.PicardError) as e:
+        _run(api, prob, worker)
+    assert e.value.status == api.PK_ERR_INVALID_ARG
+    inst2 = random_tiny(971, N=4, K=2, R=2, T=50, mlp=True)
+    prob2 = api.DeviceProblem.from_instance(inst2)
+    part = torch.zeros(inst2.total_orders, dtype=torch.int32, device="cuda")
+    with pytest.raises(api.PicardError) as e:
+        api.pk_picard_simulate(prob2, "mlp", partition=part)
+    assert e.value.status == api.PK_ERR_UNSUPPORTED
+    _say("case partition valid call after the errors")
+    out = _run(api, prob, np.zeros(inst.total_orders, np.int32))
+    assert out["status"] == api.PK_OK
