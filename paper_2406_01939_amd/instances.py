@@ -6,7 +6,8 @@ paper's own data (population-weighted nodes, zip-code distances; Appendix A.3, d
 generation) is not available, so every instance here is synthetic:
 
 * SKU of each order: Zipf with exponent 1.1 over K, P(k) proportional to (k+1)^-1.1
-  (the heavy-tailed demand shape Q_i ~ i^beta of Section 4.1, with beta = -1.1);
+  (the heavy-tailed demand shape Q_i ~ i^beta of Section 4.1, with beta = -1.1; the
+  `zipf` override sets another exponent, 0 for uniform demand);
 * region of each order: uniform over R; the reward of warehouse w for region r is
   -cost[w, r], with integer cost uniform in 1..100 (stands in for the distance reward);
 * quantity: 1, or a geometric(p=0.6) law truncated to 1..qmax and renormalised;
@@ -44,6 +45,10 @@ WORKLOADS: Dict[str, dict] = {
     "mlp_batch64_n100_k5e4_t2e5": dict(N=100, K=50_000, R=200, T=200_000, qmax=1,
                                        n_traj=64, seed0=4000, theta_seed=4999,
                                        policy="mlp"),
+    # Section 4.1's instance shape (J = 30 nodes, I = 1e6 products, T = 3e6 orders); the
+    # demand exponent is swept with the `zipf` override (beta = -zipf)
+    "greedy_n30_k1e6_t3e6": dict(N=30, K=1_000_000, R=200, T=3_000_000, qmax=1, n_traj=1,
+                                 seed0=6, policy="greedy"),
     "mlp_batch16_n500_k1e6_t1e7": dict(N=500, K=1_000_000, R=500, T=10_000_000,
                                        qmax=4, n_traj=16, seed0=5000, theta_seed=5999,
                                        policy="mlp", x0_hashed=True),
@@ -203,14 +208,15 @@ def make_params(R: int, seed: int, hidden: int = 64, n_hidden_layers: int = 2) -
 
 
 def make_trajectory(N: int, K: int, R: int, T: int, qmax: int, seed: int,
-                    x0_hashed: bool = False, T_orders: Optional[int] = None):
+                    x0_hashed: bool = False, T_orders: Optional[int] = None,
+                    zipf: float = 1.1):
     """One trajectory's orders, cost table and initial inventory (the inventory's scale
     follows T; T_orders, if given, is the number of orders drawn; with x0_hashed the
-    inventory is returned as its generator)."""
+    inventory is returned as its generator; zipf is the demand exponent, 0 = uniform)."""
     rng = np.random.default_rng(seed)
     T_lam = T
     T = T if T_orders is None else int(T_orders)
-    pk = zipf_probs(K)
+    pk = zipf_probs(K, zipf)
     cdf = np.cumsum(pk)
     cdf[-1] = 1.0
     sku = np.minimum(np.searchsorted(cdf, rng.random(T), side="right"), K - 1)
@@ -259,7 +265,7 @@ def make_instance(name: str, **overrides) -> Instance:
     cost = np.empty((n_traj, N, R), np.int32)
     for b in range(n_traj):
         s, r, q, c, x = make_trajectory(N, K, R, int(Ts[b]), qmax, cfg["seed0"] + b, hashed,
-                                        int(To[b]))
+                                        int(To[b]), float(cfg.get("zipf", 1.1)))
         sl = slice(int(offs[b]), int(offs[b + 1]))
         sku[sl], region[sl], qty[sl] = s, r, q
         cost[b] = c
