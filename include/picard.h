@@ -124,8 +124,8 @@ typedef struct pk_picard_opts {
                                  partitions of Section 4.1; block_len is then ignored.
                                  A process may own several runs of one SKU; each run
                                  starts from the state its process reaches under
-                                 Algorithm 1.  GREEDY policy only (PK_ERR_UNSUPPORTED for
-                                 MLP); PK_ERR_INVALID_ARG for a negative process. */
+                                 Algorithm 1.  PK_ERR_INVALID_ARG for a negative
+                                 process. */
 } pk_picard_opts;
 
 /* Statistics of one pk_picard_simulate call (all optional). */

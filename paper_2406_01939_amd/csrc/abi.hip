@@ -836,11 +836,8 @@ pk_status pk_picard_simulate(const pk_problem *problem, const pk_policy *policy,
     if (opts) o = *opts;
     if (o.block_len < 0 || o.max_passes < 0 || o.graph_unroll < 0)
         return fail(PK_ERR_INVALID_ARG, "negative option");
-    if (o.partition) {
-        if (policy->kind != PK_POLICY_GREEDY)
-            return fail(PK_ERR_UNSUPPORTED, "a given partition needs the greedy policy");
-        o.block_len = 1; // sizes the plan for one run per order, the most a partition makes
-    }
+    if (o.partition) o.block_len = 1; // sizes the plan for one run per order, the most
+                                      // a partition makes
     int B = o.block_len;
     if (B == 0 && policy->kind == PK_POLICY_MLP) B = DEFAULT_BLOCK_MLP;
     if (B == 0) {

@@ -59,7 +59,10 @@ __device__ __forceinline__ void store_row(float *cbuf, float *ebuf, int N, const
 // One workgroup walks one run (a process's orders of one SKU) from its entry state,
 // order by order: all waves score the order's warehouses with stock (kept as a list that
 // loses a warehouse when it empties), wave 0 takes the argmax and applies f.  Same run bookkeeping as the greedy walk (entry state from the segmented
-// scan, u of split runs, final inventory of a SKU's last run, restart frontier).
+// scan, u of split runs, final inventory of a SKU's last run, restart frontier).  Under a
+// given partition the workgroup goes on to its process's later runs of the SKU (its
+// chain), entering each at max(0, x0 - E_j - D), D the process's own fresh-minus-cached
+// consumption on its earlier runs, kept in LDS.
 __global__ __launch_bounds__(256) void k_walk_mlp(Prob P, Plan L, const float *params, int layers,
                                                   const float *costT, int32_t *final_inv,
                                                   int has_init)
@@ -73,6 +76,7 @@ __global__ __launch_bounds__(256) void k_walk_mlp(Prob P, Plan L, const float *p
     int32_t *sl = (int32_t *)(zbuf + N); // warehouses with stock
     int32_t *pos = sl + N;               // index of each in sl
     int32_t *flag = pos + N;             // [0] changed, [1] near ties, [2] stock list length
+    int32_t *dcor = flag + 4;            // given partitions: the process's own correction
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     Ctl *ctl = L.ctl;
     if (ctl->done) return;
@@ -90,14 +94,21 @@ __global__ __launch_bounds__(256) void k_walk_mlp(Prob P, Plan L, const float *p
     unsigned long long n_orders = 0, n_runs = 0, n_changed = 0, n_bytes = 0, n_ties = 0;
     unsigned long long n_rows = 0; // scored (order, warehouse with stock) rows
     for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
-        const int s = all ? item : L.split_list[item];
+        int s = all ? item : L.split_list[item];
+        {
+            const int g = L.sr_seg[s];
+            const int32_t f = all ? FR_ALL : fprev[g];
+            if (!all && (f == FR_NONE || s - L.seg_sr0[g] <= f)) continue;
+            // a given partition's chain is walked from its first run past the frontier
+            // (the process's earlier runs keep their actions and add nothing to D)
+            if (L.worker && L.ch_prevj[s] > f) continue;
+            if (L.worker)
+                for (int w = threadIdx.x; w < N; w += blockDim.x) dcor[w] = 0;
+        }
+      for (;;) {
         const int g = L.sr_seg[s];
         const int s0 = L.seg_sr0[g];
         const int j = s - s0;
-        if (!all) {
-            const int32_t f = fprev[g];
-            if (f == FR_NONE || j <= f) continue;
-        }
         const int nsr = L.seg_sr0[g + 1] - s0;
         const int lo = L.sr_lo[s], hi = L.sr_lo[s + 1];
         const int key = L.seg_key[g];
@@ -105,8 +116,9 @@ __global__ __launch_bounds__(256) void k_walk_mlp(Prob P, Plan L, const float *p
         const int32_t *x0row = P.x0 + (int64_t)key * N;
         const int uidx = L.sr_uidx[s];
         const int32_t *Erow = (need_E && j > 0) ? L.E + (int64_t)uidx * N : nullptr;
+        __syncthreads(); // dcor is final (set above, or by the chain's previous run)
         for (int w = threadIdx.x; w < N; w += blockDim.x) {
-            const int32_t v = x0row[w] - (Erow ? Erow[w] : 0);
+            const int32_t v = x0row[w] - (Erow ? Erow[w] : 0) - (L.worker ? dcor[w] : 0);
             x[w] = v > 0 ? v : 0;
             cons[w] = 0;
         }
@@ -151,6 +163,10 @@ __global__ __launch_bounds__(256) void k_walk_mlp(Prob P, Plan L, const float *p
                     run_ties += near_tie(z1, z2);
                     L.s_alpha[p] = a;
                     L.s_ship[p] = sh;
+                    if (L.worker) { // own correction: fresh minus cached
+                        if (a >= 0) dcor[a] += q;
+                        if (old >= 0) dcor[old] -= q;
+                    }
                 }
                 nf -= __builtin_amdgcn_readlane(emp, 0);
             }
@@ -183,6 +199,15 @@ __global__ __launch_bounds__(256) void k_walk_mlp(Prob P, Plan L, const float *p
             n_bytes += 24ull * (hi - lo) + 4ull * N * (1 + (Erow ? 1 : 0) + wr);
         }
         __syncthreads();
+        if (!L.worker) break;
+        const int nx = L.ch_next[s];
+        if (nx < 0) break;
+        if (nx <= s || nx >= ctl->n_sr) { // links always point forward: never loop
+            if (threadIdx.x == 0) atomicOr(&ctl->error, ERR_NO_PROGRESS);
+            break;
+        }
+        s = nx;
+      }
     }
     if (threadIdx.x == 0 && n_runs) {
         unsigned long long *st = ctl->stat[blockIdx.x % STAT_SLOTS];
@@ -364,7 +389,7 @@ hipError_t setup_costT(const Prob &P, float *costT, hipStream_t st)
     return hipGetLastError();
 }
 
-size_t walk_mlp_lds(int N) { return w2_lds_bytes() + (size_t)N * 20 + 64; }
+size_t walk_mlp_lds(int N) { return w2_lds_bytes() + (size_t)N * 24 + 64; }
 
 hipError_t launch_walk_mlp(const Prob &P, const Plan &L, const float *params, int layers,
                            const float *costT, int32_t *final_inv, bool has_init, int grid,
