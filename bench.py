@@ -13,6 +13,7 @@ own workload ("learned": 64 trajectories of 2e5 orders, MFMA roofline of its wal
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -112,10 +113,10 @@ def main():
     ap.add_argument("--pg-iters", type=int, default=0, metavar="K",
                     help="also run K policy-gradient iterations (Section 4.2) on the learned "
                          "workload with warm-started Picard, cold Picard and serial rollouts")
-    ap.add_argument("--partition-sweep", action="store_true",
+    ap.add_argument("--partition-sweep", nargs="?", const="greedy", choices=("greedy", "mlp"),
                     help="Section 4.1's partition contrast on the 3e6-order, 1e6-SKU, 30-"
                          "warehouse instance: product and uniform random partitions over 1e4 "
-                         "processes and autotuned blocks, demand exponent 0 to -1 (greedy)")
+                         "processes and autotuned blocks, demand exponent 0 to -1")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter yardstick)")
     args = ap.parse_args()
@@ -232,7 +233,8 @@ def main():
                                 "objective": g["objective"]}
         return r
 
-    def partition_sweep(M=10_000, betas=(0.0, -0.2, -0.4, -0.6, -0.8, -1.0), reps=3):
+    def partition_sweep(M=10_000, betas=(0.0, -0.2, -0.4, -0.6, -0.8, -1.0), reps=3,
+                        policy="greedy"):
         """Picard time (best of `reps`, after one warm-up call), passes and speed-up over
         the serial GPU sweep for three partitions of the same instance, per demand
         exponent beta (SKU k drawn with probability proportional to (k+1)^beta)."""
@@ -251,23 +253,30 @@ def main():
 
         for beta in betas:
             inst = make_instance(name, zipf=-beta)
+            if policy == "mlp":  # two hidden layers of 64, seeded (no trained weights)
+                from paper_2406_01939_amd.instances import make_params
+                inst = dataclasses.replace(inst, params=make_params(inst.R, 6999))
             prob = api.DeviceProblem.from_instance(inst)
             rng = np.random.default_rng(6)
             row = {"beta": beta, "top_sku_orders": int(np.bincount(inst.sku).max())}
-            sdt, ser = timed(lambda: api.pk_serial_simulate(prob, "greedy", want_final=False))
+            sdt, ser = timed(lambda: api.pk_serial_simulate(prob, policy, want_final=False))
             row["serial_s"] = sdt
+            _progress(f"partition sweep beta={beta}: serial sweep {sdt:.3f} s")
             parts = {"product": rng.integers(0, M, inst.K)[inst.sku],
                      "uniform": rng.integers(0, M, inst.total_orders)}
             for label, w in parts.items():
                 part = torch.from_numpy(w.astype(np.int32)).cuda()
-                dt, out = timed(lambda: api.pk_picard_simulate(prob, "greedy", partition=part,
+                dt, out = timed(lambda: api.pk_picard_simulate(prob, policy, partition=part,
                                                                want_final=False))
+                _progress(f"partition sweep beta={beta}: {label} {dt:.4f} s")
                 row[label] = {"seconds": dt, "passes": int(out["passes"].max()),
                               "speedup_vs_serial_gpu": sdt / dt,
                               "identical_actions": bool(torch.equal(out["actions"],
                                                                     ser["actions"]))}
-            B = api.pk_autotune(prob, "greedy")
-            dt, out = timed(lambda: api.pk_picard_simulate(prob, "greedy", block_len=B,
+            # the learned policy takes the library's default block (the autotuner would run
+            # a dozen multi-second simulations here)
+            B = api.pk_autotune(prob, policy) if policy == "greedy" else 256
+            dt, out = timed(lambda: api.pk_picard_simulate(prob, policy, block_len=B,
                                                            want_final=False))
             row["blocks"] = {"block_len": B, "seconds": dt, "passes": int(out["passes"].max()),
                              "speedup_vs_serial_gpu": sdt / dt,
@@ -278,8 +287,8 @@ def main():
                 f"{row[k]['speedup_vs_serial_gpu']:.0f}x)" for k in ("product", "uniform", "blocks")))
             rows.append(row)
             del prob
-        return {"workload": name, "processes": M, "timing": f"best of {reps} after a warm-up",
-                "rows": rows}
+        return {"workload": name, "policy": policy, "processes": M,
+                "timing": f"best of {reps} after a warm-up", "rows": rows}
 
     def pg_loop(name, iters):
         """End-to-end training (rollout, advantages, gradient, Adam step) for `iters`
@@ -339,8 +348,11 @@ def main():
                           "speedup_vs_serial_gpu": lm["speedup_vs_serial_gpu"]}
     if args.pg_iters > 0:
         res["policy_gradient_loop"] = pg_loop(LEARNED_WORKLOAD, args.pg_iters)
-    if args.partition_sweep:
+    if args.partition_sweep == "greedy":
         res["partition_sweep"] = partition_sweep()
+    elif args.partition_sweep == "mlp":
+        res["partition_sweep"] = partition_sweep(policy="mlp", betas=(0.0, -0.4, -0.8, -1.0),
+                                                 reps=1)
     if not args.no_cpu and inst.x0 is not None:
         res["cpu_baseline"] = cpu_baseline(inst)
     res["paper_context"] = ("paper (A100 40GB, JAX, 16-bit): 441x Picard speed-up over a "
