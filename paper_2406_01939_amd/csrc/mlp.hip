@@ -93,9 +93,16 @@ __global__ __launch_bounds__(256) void k_walk_mlp(Prob P, Plan L, const float *p
     int lcp_b = -1; // last trajectory this wave marked as changed in this pass
     unsigned long long n_orders = 0, n_runs = 0, n_changed = 0, n_bytes = 0, n_ties = 0;
     unsigned long long n_rows = 0; // scored (order, warehouse with stock) rows
-    for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
-        int s = all ? item : L.split_list[item];
-        {
+    // one loop over the runs this workgroup walks: the next item's run, or under a given
+    // partition the next run of the current chain
+    int item = blockIdx.x, s_next = -1;
+    for (;;) {
+        int s = s_next;
+        s_next = -1;
+        if (s < 0) {
+            if (item >= n_items) break;
+            s = all ? item : L.split_list[item];
+            item += gridDim.x;
             const int g = L.sr_seg[s];
             const int32_t f = all ? FR_ALL : fprev[g];
             if (!all && (f == FR_NONE || s - L.seg_sr0[g] <= f)) continue;
@@ -105,7 +112,6 @@ __global__ __launch_bounds__(256) void k_walk_mlp(Prob P, Plan L, const float *p
             if (L.worker)
                 for (int w = threadIdx.x; w < N; w += blockDim.x) dcor[w] = 0;
         }
-      for (;;) {
         const int g = L.sr_seg[s];
         const int s0 = L.seg_sr0[g];
         const int j = s - s0;
@@ -199,15 +205,12 @@ __global__ __launch_bounds__(256) void k_walk_mlp(Prob P, Plan L, const float *p
             n_bytes += 24ull * (hi - lo) + 4ull * N * (1 + (Erow ? 1 : 0) + wr);
         }
         __syncthreads();
-        if (!L.worker) break;
-        const int nx = L.ch_next[s];
-        if (nx < 0) break;
-        if (nx <= s || nx >= ctl->n_sr) { // links always point forward: never loop
-            if (threadIdx.x == 0) atomicOr(&ctl->error, ERR_NO_PROGRESS);
-            break;
+        if (L.worker) {
+            const int nx = L.ch_next[s];
+            if (nx > s && nx < ctl->n_sr) s_next = nx;
+            else if (nx >= 0 && threadIdx.x == 0) // links always point forward: never loop
+                atomicOr(&ctl->error, ERR_NO_PROGRESS);
         }
-        s = nx;
-      }
     }
     if (threadIdx.x == 0 && n_runs) {
         unsigned long long *st = ctl->stat[blockIdx.x % STAT_SLOTS];
