@@ -66,8 +66,9 @@ __global__ __launch_bounds__(ADV_THREADS) void k_rewards(
                 atomicOr(err, 1);
             } else {
                 const int64_t margin = (int64_t)revenue - cost[((int64_t)b * N + a) * R + reg];
-                const int64_t am = margin < 0 ? -margin : margin;
-                if (am != 0 && (int64_t)s > rlim / am) atomicOr(err, 2);
+                const uint64_t am = (uint64_t)(margin < 0 ? -margin : margin);
+                // |r| = am * s > rlim, with the product exact (am < 2^32, s < 2^31)
+                if (am * (uint64_t)s > (uint64_t)rlim) atomicOr(err, 2);
                 else r = margin * s;
             }
         }
