@@ -35,18 +35,19 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_walk_greedy_n100_k1e5_t1e6_traf
 WALK_SOURCE = os.path.join(ROOT, "paper_2406_01939_amd", "csrc", "walk_greedy.hip")
 
 
-def _traffic():
+def _traffic(block_len: int):
     """HBM bytes per walk launch from the committed rocprofv3 counter summary, if the walk
-    kernel's source is unchanged since the counters were taken; else None.  The summary
-    carries `key: value` lines, among them `source_sha256` and `bytes_per_launch`."""
+    kernel's source is unchanged since the counters were taken and they were taken at the
+    same block length; else None.  The summary carries `key: value` lines, among them
+    `source_sha256`, `block_len` and `bytes_per_launch`."""
     try:
         rec = {}
         for line in open(TRAFFIC_FILE):
             k, sep, v = line.partition(":")
-            if sep and k.strip() in ("source_sha256", "bytes_per_launch"):
+            if sep and k.strip() in ("source_sha256", "block_len", "bytes_per_launch"):
                 rec[k.strip()] = v.strip().strip("`")
         h = hashlib.sha256(open(WALK_SOURCE, "rb").read()).hexdigest()
-        if rec.get("source_sha256") != h:
+        if rec.get("source_sha256") != h or int(rec.get("block_len", -1)) != block_len:
             return None
         return float(rec["bytes_per_launch"])
     except (OSError, ValueError, KeyError):
@@ -189,7 +190,7 @@ def main():
             achieved = (walk_bytes / 1e9) / (walk_ms / 1e3) if walk_ms > 0 else 0.0
             r["roofline"] = {"kernel": "k_walk_greedy", "bound": "hbm", "achieved": achieved,
                              "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                             "traffic": _traffic() if name == DEFAULT_WORKLOAD else None,
+                             "traffic": _traffic(B) if name == DEFAULT_WORKLOAD else None,
                              "bytes_per_launch": walk_bytes / max(walk_launches, 1),
                              "avg_launch_us": avg_us, "launches": walk_launches}
         else:

@@ -25,6 +25,12 @@
  *   orc_reinforce     FP64 REINFORCE surrogate sum_t A_t log pi(a_t | s_t) and its
  *                     gradient by hand-written backpropagation (Section 4.2 trains the
  *                     policy by policy gradient).
+ *   orc_serial_cap, orc_alg1_cap, orc_picard_timeblocks_cap
+ *                     The serial rollout and Algorithm 1 with node capacity (Section 3,
+ *                     the full FO state (x_t, c_t)), greedy policy, unit demand; the
+ *                     last one computes Algorithm 1's passes for the partition into
+ *                     time blocks in one replay per pass.  Checked against each other
+ *                     and against the no-capacity functions where they coincide.
  *   orc_philox4x32_10 Philox4x32-10 from Salmon, Moraes, Dror and Shaw, "Parallel random
  *                     numbers: as easy as 1, 2, 3" (SC'11): the counter-based generator
  *                     that supplies the learned policy's Gumbel noise (the paper lets the
@@ -574,4 +580,192 @@ int orc_mlp_scores(const orc_problem *P, int32_t r, const int32_t *x, double *s)
                            NULL, NULL, NULL);
     mlp_free(&m);
     return 0;
+}
+
+/* ====================================================================================
+ * Node capacity (Section 3, the FO model in full): the state is (x_t, c_t); an order of
+ * SKU i may go to node j only if c_{t,j} > 0 and x_{t,i,j} > 0; shipping it lowers
+ * c_{t,j} and x_{t,i,j} by one.  The paper's transition is unit demand, so every order
+ * here must have q = 1.  Policy: greedy (least cost[j][region] among nodes with both
+ * capacity and stock, lowest index on ties; lost sale iff none), as in Section 3.1.
+ * cap0[N] >= 0 is c_1.
+ * ==================================================================================== */
+static int check_cap(const orc_problem *P, const int32_t *cap0)
+{
+    if (check_problem(P) || P->params) return -1;
+    for (int64_t t = 0; t < P->T; ++t)
+        if (P->qty[t] != 1) return -1;
+    for (int w = 0; w < P->N; ++w)
+        if (cap0[w] < 0) return -1;
+    return 0;
+}
+
+/* Greedy choice at state (x row of the order's SKU, capacities c). */
+static int32_t greedy_cap(const orc_problem *P, int64_t t, const int32_t *x, const int32_t *c)
+{
+    const int R = P->R, r = P->region[t];
+    int32_t best = LOST, best_cost = 0;
+    for (int w = 0; w < P->N; ++w) {
+        if (x[w] <= 0 || c[w] <= 0) continue;
+        const int32_t cw = P->cost[w * R + r];
+        if (best == LOST || cw < best_cost) { best = w; best_cost = cw; }
+    }
+    return best;
+}
+
+/* f with capacity: one unit leaves both counters when the action is a node. */
+static void transition_cap(int32_t *x, int32_t *c, int32_t a)
+{
+    if (a == LOST) return;
+    x[a] -= 1;
+    c[a] -= 1;
+}
+
+/* Serial rollout with capacity: the answer Picard must reach. */
+int orc_serial_cap(const orc_problem *P, const int32_t *cap0, int32_t *actions,
+                   int32_t *final_inv, int32_t *final_cap)
+{
+    if (check_cap(P, cap0)) return -1;
+    const int N = P->N;
+    int32_t *x = (int32_t *)malloc(sizeof(int32_t) * (size_t)P->K * N);
+    int32_t *c = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
+    if (!x || !c) { free(x); free(c); return -1; }
+    memcpy(x, P->x0, sizeof(int32_t) * (size_t)P->K * N);
+    memcpy(c, cap0, sizeof(int32_t) * (size_t)N);
+    for (int64_t t = 0; t < P->T; ++t) {
+        int32_t *xk = x + (int64_t)P->sku[t] * N;
+        const int32_t a = greedy_cap(P, t, xk, c);
+        transition_cap(xk, c, a);
+        actions[t] = a;
+    }
+    if (final_inv) memcpy(final_inv, x, sizeof(int32_t) * (size_t)P->K * N);
+    if (final_cap) memcpy(final_cap, c, sizeof(int32_t) * (size_t)N);
+    free(x);
+    free(c);
+    return 0;
+}
+
+/* Algorithm 1 with capacity, literally: every process keeps its own (x, c), walks
+ * t = 1..T, decides its own steps and replays the others' cached actions, each
+ * replaced by a lost sale when the node has no stock or no capacity left locally.
+ * Arguments and return value as orc_alg1.  O(P*T*N) per pass: tiny instances only. */
+int orc_alg1_cap(const orc_problem *P, const int32_t *cap0, const int64_t *worker,
+                 int64_t n_workers, const int32_t *init_cache, int32_t max_passes,
+                 int32_t *final_cache, int32_t *passes, int32_t *caches)
+{
+    if (check_cap(P, cap0) || n_workers <= 0 || max_passes <= 0) return -1;
+    const int N = P->N;
+    const int64_t T = P->T, KN = (int64_t)P->K * N;
+    for (int64_t t = 0; t < T; ++t)
+        if (worker[t] < 0 || worker[t] >= n_workers) return -1;
+    int32_t *prev = (int32_t *)malloc(sizeof(int32_t) * (size_t)(T + 1));
+    int32_t *next = (int32_t *)malloc(sizeof(int32_t) * (size_t)(T + 1));
+    int32_t *x = (int32_t *)malloc(sizeof(int32_t) * (size_t)KN);
+    int32_t *c = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
+    if (!prev || !next || !x || !c) { free(prev); free(next); free(x); free(c); return -1; }
+    for (int64_t t = 0; t < T; ++t) prev[t] = init_cache ? init_cache[t] : LOST;
+    int rc = 1;
+    int32_t k;
+    for (k = 1; k <= max_passes; ++k) {
+        for (int64_t proc = 0; proc < n_workers; ++proc) {
+            memcpy(x, P->x0, sizeof(int32_t) * (size_t)KN);
+            memcpy(c, cap0, sizeof(int32_t) * (size_t)N);
+            for (int64_t t = 0; t < T; ++t) {
+                int32_t *xk = x + (int64_t)P->sku[t] * N;
+                int32_t a;
+                if (worker[t] == proc) {
+                    a = greedy_cap(P, t, xk, c);
+                    next[t] = a;
+                } else {
+                    a = prev[t];
+                    if (a != LOST && (a < 0 || a >= N || xk[a] <= 0 || c[a] <= 0)) a = LOST;
+                }
+                transition_cap(xk, c, a);
+            }
+        }
+        if (caches) memcpy(caches + (int64_t)(k - 1) * T, next, sizeof(int32_t) * (size_t)T);
+        int same = 1;
+        for (int64_t t = 0; t < T; ++t)
+            if (next[t] != prev[t]) { same = 0; break; }
+        int32_t *tmp = prev; prev = next; next = tmp;
+        if (same) { rc = 0; break; }
+    }
+    if (k > max_passes) k = max_passes;
+    *passes = k;
+    memcpy(final_cache, prev, sizeof(int32_t) * (size_t)T);
+    free(prev); free(next); free(x); free(c);
+    return rc;
+}
+
+/* The same passes for the partition into time blocks: process m owns the B consecutive
+ * steps [mB, (m+1)B).  Every process replays the cached actions of all steps before
+ * its block, and nothing after its block reaches its decisions, so each process starts
+ * its block from one shared state: the replay of alpha^{k-1} (infeasible cached actions
+ * replaced by lost sales) up to the block.  One pass is then a single replay in time
+ * order; at the start of block m, process m walks its B steps with fresh decisions on a
+ * private copy of the shared state (the rows of the SKUs it meets, copied on first use,
+ * and the capacities), after which the replay applies the block's cached actions.
+ * O(T*N) per pass.  changed (nullable) receives |{t : alpha^k_t != alpha^{k-1}_t}| per
+ * pass.  Other arguments and the return value as orc_alg1. */
+int orc_picard_timeblocks_cap(const orc_problem *P, const int32_t *cap0, int64_t B,
+                              const int32_t *init_cache, int32_t max_passes,
+                              int32_t *final_cache, int32_t *passes, int64_t *changed,
+                              int32_t *caches)
+{
+    if (check_cap(P, cap0) || B <= 0 || max_passes <= 0) return -1;
+    const int N = P->N, K = P->K;
+    const int64_t T = P->T, KN = (int64_t)K * N;
+    int32_t *prev = (int32_t *)malloc(sizeof(int32_t) * (size_t)(T + 1));
+    int32_t *next = (int32_t *)malloc(sizeof(int32_t) * (size_t)(T + 1));
+    int32_t *x = (int32_t *)malloc(sizeof(int32_t) * (size_t)KN);     /* shared replay */
+    int32_t *xp = (int32_t *)malloc(sizeof(int32_t) * (size_t)KN);    /* private rows  */
+    int64_t *stamp = (int64_t *)malloc(sizeof(int64_t) * (size_t)K);  /* row copied in */
+    int32_t *c = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
+    int32_t *cp = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
+    if (!prev || !next || !x || !xp || !stamp || !c || !cp) {
+        free(prev); free(next); free(x); free(xp); free(stamp); free(c); free(cp);
+        return -1;
+    }
+    for (int64_t t = 0; t < T; ++t) prev[t] = init_cache ? init_cache[t] : LOST;
+    int rc = 1;
+    int32_t k;
+    for (k = 1; k <= max_passes; ++k) {
+        memcpy(x, P->x0, sizeof(int32_t) * (size_t)KN);
+        memcpy(c, cap0, sizeof(int32_t) * (size_t)N);
+        for (int64_t i = 0; i < K; ++i) stamp[i] = -1;
+        for (int64_t m = 0; m * B < T; ++m) {
+            const int64_t lo = m * B, hi = lo + B < T ? lo + B : T;
+            /* process m: fresh decisions from the shared state */
+            memcpy(cp, c, sizeof(int32_t) * (size_t)N);
+            for (int64_t t = lo; t < hi; ++t) {
+                const int64_t s = P->sku[t];
+                int32_t *xk = xp + s * N;
+                if (stamp[s] != m) {
+                    memcpy(xk, x + s * N, sizeof(int32_t) * (size_t)N);
+                    stamp[s] = m;
+                }
+                const int32_t a = greedy_cap(P, t, xk, cp);
+                transition_cap(xk, cp, a);
+                next[t] = a;
+            }
+            /* the shared replay applies the block's cached actions */
+            for (int64_t t = lo; t < hi; ++t) {
+                int32_t *xk = x + (int64_t)P->sku[t] * N;
+                int32_t a = prev[t];
+                if (a != LOST && (a < 0 || a >= N || xk[a] <= 0 || c[a] <= 0)) a = LOST;
+                transition_cap(xk, c, a);
+            }
+        }
+        if (caches) memcpy(caches + (int64_t)(k - 1) * T, next, sizeof(int32_t) * (size_t)T);
+        int64_t nch = 0;
+        for (int64_t t = 0; t < T; ++t) nch += next[t] != prev[t];
+        if (changed) changed[k - 1] = nch;
+        int32_t *tmp = prev; prev = next; next = tmp;
+        if (nch == 0) { rc = 0; break; }
+    }
+    if (k > max_passes) k = max_passes;
+    *passes = k;
+    memcpy(final_cache, prev, sizeof(int32_t) * (size_t)T);
+    free(prev); free(next); free(x); free(xp); free(stamp); free(c); free(cp);
+    return rc;
 }

@@ -17,7 +17,9 @@ generation) is not available, so every instance here is synthetic:
   counter-based generator instead, so they can be made on the GPU and any row recomputed
   on the CPU: a 32-bit hash of (seed, trajectory, SKU, warehouse) inverted through the
   Poisson CDF of the SKU (`PoissonX0`);
-* learned-policy parameters: PyTorch-default-style uniform init, embedding ~ N(0, 1).
+* learned-policy parameters: PyTorch-default-style uniform init, embedding ~ N(0, 1);
+* node capacity (unit-demand workloads): the network can process 80% of expected demand
+  (Appendix A.3), split evenly: c_1[w] = floor(0.8 * T / N) (`capacity`).
 
 This module is shared by the CPU oracle's tests and by the GPU path's tests and
 benchmark; it only draws numbers.
@@ -45,6 +47,11 @@ WORKLOADS: Dict[str, dict] = {
     "mlp_batch64_n100_k5e4_t2e5": dict(N=100, K=50_000, R=200, T=200_000, qmax=1,
                                        n_traj=64, seed0=4000, theta_seed=4999,
                                        policy="mlp"),
+    # the same two greedy shapes with node capacity (Section 3's full state (x, c))
+    "greedy_cap_n10_k100_t1e4": dict(N=10, K=100, R=20, T=10_000, qmax=1, n_traj=1,
+                                     seed0=1, policy="greedy", block_len=100, capacity=0.8),
+    "greedy_cap_n100_k1e5_t1e6": dict(N=100, K=100_000, R=200, T=1_000_000, qmax=1,
+                                      n_traj=1, seed0=2, policy="greedy", capacity=0.8),
     # Section 4.1's instance shape (J = 30 nodes, I = 1e6 products, T = 3e6 orders); the
     # demand exponent is swept with the `zipf` override (beta = -zipf)
     "greedy_n30_k1e6_t3e6": dict(N=30, K=1_000_000, R=200, T=3_000_000, qmax=1, n_traj=1,
@@ -282,6 +289,11 @@ def make_instance(name: str, **overrides) -> Instance:
     return Instance(N=N, K=K, R=R, traj_offsets=offs, sku=sku, region=region, qty=qty,
                     x0=x0, cost=cost, rng_seed=rng_seed, params=params, hidden=hidden,
                     n_hidden_layers=nhl, name=name, x0_gen=gens)
+
+
+def capacity(N: int, T: int, frac: float = 0.8) -> np.ndarray:
+    """Node capacities c_1 for T unit orders: frac of the demand, split evenly over N."""
+    return np.full(N, int(np.floor(frac * T / N)), dtype=np.int32)
 
 
 def random_tiny(seed: int, N: int = 4, K: int = 3, R: int = 3, T: int = 12, qmax: int = 1,

@@ -1,0 +1,258 @@
+"""Pins of the oracle with node capacity (Section 3: state (x_t, c_t), an order may go to
+node j only if c_{t,j} > 0 and x_{t,i,j} > 0, and shipping lowers both by one).
+
+* Hand-worked tiny cases.
+* Brute force: a dense pure-Python rollout, and numpy's argmin (first minimum) over the
+  costs masked to +inf, per step.
+* Reductions to the pinned no-capacity oracle: capacities that never bind; one SKU whose
+  stock equals the capacities (the two counters move together); unbounded stock, where
+  capacity plays the role of one shared SKU's stock.
+* Invariants: capacities and stock never negative; what left a node equals its capacity
+  drop.
+* Algorithm 1: any fixed point equals the serial rollout; Proposition 2.1 (k* <= T for
+  any partition and any initial cache); the time-block replay equals the literal
+  algorithm pass by pass.
+* Section 3.1, special case (stock never binds, greedy policy): Lemma 3.2's invariant
+  (every cached action is the serial one or a node already out of capacity at that
+  time) and the bound k* <= |Q_T| + 1, for any partition; Theorem 3.1 (Assumptions 1-3
+  hold for greedy) for the product partition with binding stock.
+"""
+import numpy as np
+import pytest
+
+from paper_2406_01939_amd.instances import capacity, random_tiny
+
+
+def _kstar(caches, serial_actions):
+    if np.all(serial_actions == -1):
+        return 0
+    for k, c in enumerate(caches, start=1):
+        if np.array_equal(c, serial_actions):
+            return k
+    raise AssertionError("never reached the serial trajectory")
+
+
+def _tiny(seed, **kw):
+    rng = np.random.default_rng(10_000 + seed)
+    inst = random_tiny(seed, qmax=1, **kw)
+    T = int(inst.traj_offsets[-1])
+    cap0 = rng.integers(0, max(2, T // inst.N + 2), inst.N).astype(np.int32)
+    return inst, cap0
+
+
+def _brute_serial(inst, cap0):
+    x = {(k, w): int(inst.x0[0][k, w]) for k in range(inst.K) for w in range(inst.N)}
+    c = [int(v) for v in cap0]
+    out = []
+    for t in range(int(inst.traj_offsets[-1])):
+        k, r = int(inst.sku[t]), int(inst.region[t])
+        best = None
+        for w in range(inst.N):
+            if x[(k, w)] > 0 and c[w] > 0:
+                if best is None or inst.cost[0][w, r] < inst.cost[0][best, r]:
+                    best = w
+        if best is None:
+            out.append(-1)
+        else:
+            out.append(best)
+            x[(k, best)] -= 1
+            c[best] -= 1
+    return np.array(out, np.int32)
+
+
+def test_hand_worked(oracle):
+    from paper_2406_01939_amd.instances import Instance
+    # two nodes, cost 1 and 2; node 0 can ship one unit, node 1 five; stock 5 each
+    inst = Instance(N=2, K=1, R=1, traj_offsets=np.array([0, 3], np.int64),
+                    sku=np.zeros(3, np.int32), region=np.zeros(3, np.int32),
+                    qty=np.ones(3, np.int32), x0=np.array([[[5, 5]]], np.int32),
+                    cost=np.array([[[1], [2]]], np.int32), rng_seed=0, params=None,
+                    name="hand")
+    r = oracle.serial_cap(inst, np.array([1, 5], np.int32))
+    assert r["actions"].tolist() == [0, 1, 1]
+    assert r["final_cap"].tolist() == [0, 3]
+    assert r["final_inv"].tolist() == [[4, 3]]
+    # no capacity anywhere: every order is lost
+    r = oracle.serial_cap(inst, np.array([0, 0], np.int32))
+    assert r["actions"].tolist() == [-1, -1, -1]
+    # stock binds before capacity at node 0
+    inst.x0[0][0, 0] = 1
+    r = oracle.serial_cap(inst, np.array([9, 9], np.int32))
+    assert r["actions"].tolist() == [0, 1, 1]
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_serial_brute_force(oracle, seed):
+    inst, cap0 = _tiny(seed, N=2 + seed % 5, K=1 + seed % 4, R=1 + seed % 3, T=20,
+                       inv_max=4)
+    r = oracle.serial_cap(inst, cap0)
+    assert np.array_equal(r["actions"], _brute_serial(inst, cap0))
+    # library special case: numpy's argmin returns the first minimum (lowest index)
+    x = inst.x0[0].astype(np.int64).copy()
+    c = cap0.astype(np.int64).copy()
+    for t in range(int(inst.traj_offsets[-1])):
+        k, reg = inst.sku[t], inst.region[t]
+        masked = np.where((x[k] > 0) & (c > 0), inst.cost[0][:, reg].astype(np.float64), np.inf)
+        a = -1 if np.isinf(masked.min()) else int(np.argmin(masked))
+        assert r["actions"][t] == a
+        if a >= 0:
+            x[k, a] -= 1
+            c[a] -= 1
+    # invariants
+    assert (r["final_cap"] >= 0).all() and (r["final_inv"] >= 0).all()
+    sent = np.bincount(r["actions"][r["actions"] >= 0], minlength=inst.N)
+    assert np.array_equal(cap0 - r["final_cap"], sent)
+    per = np.zeros((inst.K, inst.N), np.int64)
+    np.add.at(per, (inst.sku[r["actions"] >= 0], r["actions"][r["actions"] >= 0]), 1)
+    assert np.array_equal(inst.x0[0] - r["final_inv"], per)
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_reductions_to_no_capacity(oracle, seed):
+    inst, _ = _tiny(seed, N=2 + seed % 5, K=1 + seed % 4, R=1 + seed % 3, T=20, inv_max=4)
+    T = int(inst.traj_offsets[-1])
+    # capacities that never bind
+    big = np.full(inst.N, T, np.int32)
+    assert np.array_equal(oracle.serial_cap(inst, big)["actions"],
+                          oracle.serial(inst, greedy=True)["actions"])
+    # one SKU with stock equal to the capacities
+    one = _one_sku(inst)
+    assert np.array_equal(oracle.serial_cap(one, one.x0[0][0].copy())["actions"],
+                          oracle.serial(one, greedy=True)["actions"])
+    # unbounded stock: capacity acts as the stock of one shared SKU
+    rng = np.random.default_rng(seed)
+    cap0 = rng.integers(0, 4, inst.N).astype(np.int32)
+    free = _with_x0(inst, np.full((inst.K, inst.N), T, np.int32))
+    shared = _one_sku(inst)
+    shared.x0[0][0] = cap0
+    assert np.array_equal(oracle.serial_cap(free, cap0)["actions"],
+                          oracle.serial(shared, greedy=True)["actions"])
+
+
+def _with_x0(inst, x0):
+    import dataclasses
+    return dataclasses.replace(inst, x0=x0[None].astype(np.int32).copy())
+
+
+def _one_sku(inst):
+    import dataclasses
+    return dataclasses.replace(inst, K=1, sku=np.zeros_like(inst.sku),
+                               x0=inst.x0[:, :1, :].copy())
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_alg1_fixed_point_and_prop21(oracle, seed):
+    inst, cap0 = _tiny(seed, N=2 + seed % 4, K=1 + seed % 3, R=1 + seed % 3, T=12,
+                       inv_max=3)
+    T = int(inst.traj_offsets[-1])
+    rng = np.random.default_rng(seed)
+    ser = oracle.serial_cap(inst, cap0)["actions"]
+    for kind in range(3):
+        if kind == 0:
+            worker, P = np.arange(T), T
+        elif kind == 1:
+            P = 1 + seed % 4
+            worker = rng.integers(0, P, T)
+        else:
+            worker, P = inst.sku.astype(np.int64), inst.K
+        init = None if seed % 2 == 0 else rng.integers(-1, inst.N, T).astype(np.int32)
+        r = oracle.alg1_cap(inst, cap0, worker, P, init_cache=init)
+        assert r["converged"]
+        assert np.array_equal(r["actions"], ser)
+        assert r["passes"] <= T + 1                       # Proposition 2.1
+        # the returned pass is the first repeat: k* + 1 exactly
+        a0 = np.full(T, -1, np.int32) if init is None else init
+        seq = [a0] + list(r["caches"])
+        kstar = next(k for k, c in enumerate(seq) if np.array_equal(c, ser))
+        assert r["passes"] == kstar + 1
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_timeblocks_equal_alg1(oracle, seed):
+    inst, cap0 = _tiny(seed, N=2 + seed % 5, K=1 + seed % 4, R=1 + seed % 3, T=16,
+                       inv_max=3)
+    T = int(inst.traj_offsets[-1])
+    rng = np.random.default_rng(seed)
+    for B in (1, 2, 3, 5, T):
+        init = None if (seed + B) % 2 == 0 else rng.integers(-1, inst.N, T).astype(np.int32)
+        lit = oracle.alg1_cap(inst, cap0, oracle.time_block_workers(T, B), (T + B - 1) // B,
+                              init_cache=init)
+        tb = oracle.picard_timeblocks_cap(inst, cap0, B, init_cache=init, record=True)
+        assert lit["passes"] == tb["passes"]
+        assert np.array_equal(lit["caches"], tb["caches"])
+        prev = np.full(T, -1, np.int32) if init is None else init
+        for k, c in enumerate(tb["caches"]):
+            assert tb["changed"][k] == int((c != prev).sum())
+            prev = c
+        if B >= T:
+            assert tb["passes"] <= 2  # one process: exact in one pass
+
+
+def _tau(cap0, actions):
+    """tau_j = first t (0-based: the state before order t) with c_{t,j} = 0, T + 1 if no
+    order meets node j without capacity; Q_T = {j : tau_j <= T - 1}."""
+    T = len(actions)
+    tau = np.full(len(cap0), T + 1, np.int64)
+    c = cap0.astype(np.int64).copy()
+    for j in range(len(cap0)):
+        if c[j] == 0:
+            tau[j] = 0
+    for t, a in enumerate(actions):
+        if a >= 0:
+            c[a] -= 1
+            if c[a] == 0:
+                tau[a] = t + 1
+    return tau
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_special_case_bound_any_partition(oracle, seed):
+    """Stock never binds (x_1 = T), greedy: Lemma 3.2 and k* <= |Q_T| + 1."""
+    rng = np.random.default_rng(seed)
+    N, K, T = 2 + seed % 5, 1 + seed % 3, 18
+    inst = random_tiny(seed, N=N, K=K, R=1 + seed % 4, T=T, qmax=1)
+    inst = _with_x0(inst, np.full((K, N), T, np.int32))
+    cap0 = rng.integers(0, 6, N).astype(np.int32)
+    ser = oracle.serial_cap(inst, cap0)
+    tau = _tau(cap0, ser["actions"])
+    q_T = int((tau <= T - 1).sum())
+    assert q_T <= int((ser["final_cap"] == 0).sum())
+    for kind in range(3):
+        if kind == 0:
+            P = 1 + seed % 5
+            worker = rng.integers(0, P, T)
+        elif kind == 1:
+            B = 1 + seed % 4
+            worker, P = np.arange(T) // B, (T + B - 1) // B
+        else:
+            worker, P = np.arange(T), T
+        r = oracle.alg1_cap(inst, cap0, worker, P)
+        kstar = _kstar(r["caches"], ser["actions"])
+        assert kstar <= q_T + 1
+        for c in r["caches"]:
+            for t in range(T):
+                a = c[t]
+                assert a == ser["actions"][t] or (a >= 0 and tau[a] <= t)
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_theorem31_product_partition(oracle, seed):
+    """Product partition, stock and capacity both binding: k* <= |Q_T| + 1."""
+    inst, cap0 = _tiny(seed, N=2 + seed % 5, K=2 + seed % 3, R=1 + seed % 3, T=18,
+                       inv_max=4)
+    ser = oracle.serial_cap(inst, cap0)
+    q_T = int((_tau(cap0, ser["actions"]) <= len(ser["actions"]) - 1).sum())
+    r = oracle.alg1_cap(inst, cap0, inst.sku.astype(np.int64), inst.K)
+    assert _kstar(r["caches"], ser["actions"]) <= q_T + 1
+
+
+def test_capacity_generator():
+    c = capacity(10, 10_000)
+    assert c.dtype == np.int32 and c.tolist() == [800] * 10
+
+
+def test_rejects_multi_unit(oracle):
+    inst = random_tiny(3, N=3, K=2, R=2, T=10, qmax=3)
+    inst.qty[:] = 2
+    with pytest.raises(ValueError):
+        oracle.serial_cap(inst, np.ones(3, np.int32))

@@ -21,7 +21,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "picard_oracle.c")
 PINS = [os.path.join(ROOT, "tests", f) for f in
-        ("test_oracle_serial.py", "test_oracle_picard.py", "test_oracle_mlp.py")]
+        ("test_oracle_serial.py", "test_oracle_picard.py", "test_oracle_mlp.py",
+         "test_oracle_capacity.py")]
 
 # (name, text in the oracle, replacement)
 MUTANTS = [
@@ -79,6 +80,19 @@ MUTANTS = [
     ("eval_at_state_not_advanced",
      "        transition(xk, a, P->qty[t]);\n    }\n    free(x);\n    mlp_free(&m);\n    return rc;",
      "    }\n    free(x);\n    mlp_free(&m);\n    return rc;"),
+    # node capacity (Section 3, state (x, c))
+    ("cap_greedy_ignores_capacity", "if (x[w] <= 0 || c[w] <= 0) continue;",
+     "if (x[w] <= 0) continue;"),
+    ("cap_transition_keeps_capacity", "x[a] -= 1;\n    c[a] -= 1;", "x[a] -= 1;"),
+    # (a replayed action that ignores a node's exhausted capacity is not listed: it only
+    # lowers that node's stock, and a node without capacity is never chosen again, so
+    # every action is unchanged)
+    ("cap_blocks_rows_from_initial_stock", "memcpy(xk, x + s * N,", "memcpy(xk, P->x0 + s * N,"),
+    ("cap_blocks_capacity_from_initial", "memcpy(cp, c, sizeof(int32_t) * (size_t)N);",
+     "memcpy(cp, cap0, sizeof(int32_t) * (size_t)N);"),
+    ("cap_blocks_replay_of_fresh_actions",
+     "                int32_t a = prev[t];\n                if (a != LOST && (a < 0 || a >= N || xk[a] <= 0 || c[a] <= 0))",
+     "                int32_t a = next[t];\n                if (a != LOST && (a < 0 || a >= N || xk[a] <= 0 || c[a] <= 0))"),
 ]
 
 
