@@ -242,6 +242,47 @@ pk_status pk_adam_step(float *params, const float *grad, float *m, float *v, int
                        int32_t step, double lr, double beta1, double beta2, double eps,
                        int32_t ascend, void *stream);
 
+/* ---------------------------------------------------------------------------------
+ * Node capacity (Section 3: the FO state is (x_t, c_t); an order of SKU i may go to node
+ * j only while c_{t,j} > 0 and x_{t,i,j} > 0, and shipping it lowers both by one, so
+ * capacity couples the SKUs).  Greedy policy only (least cost[w][region], lowest index on
+ * ties, lost sale iff no node has both stock and capacity), unit demand only (every qty
+ * must be 1: the paper's transition), one trajectory (n_traj == 1), N <= 128, costs in
+ * [0, 2^24).  capacity: DEVICE [N] int32 >= 0, the capacities c_1.  Other arrays as for
+ * pk_picard_simulate.  Inputs are range-checked on the device on every call
+ * (PK_ERR_INVALID_ARG names the failing check).
+ *
+ * Bytes of scratch the two calls below need for this problem and block length (0 =
+ * the default, 128).  Writes *bytes. */
+pk_status pk_capacity_workspace_size(const pk_problem *problem, const int32_t *capacity,
+                                     int32_t block_len, size_t *bytes);
+
+/* Serial rollout with capacity (the comparator: one order at a time in time order).
+ * actions [T] out; final_inv [K][N] out, nullable; final_cap [N] out, nullable.
+ * Synchronous. */
+pk_status pk_serial_simulate_capacity(const pk_problem *problem, const int32_t *capacity,
+                                      void *ws, size_t ws_bytes, int32_t *actions,
+                                      int32_t *final_inv, int32_t *final_cap, void *stream);
+
+/* Algorithm 1 with capacity.  The processes are blocks of block_len consecutive orders in
+ * time (1..255; 0 = 128): process m owns orders [m B, (m+1) B).  init_cache [T] DEVICE,
+ * nullable (NULL: lost sale everywhere) is alpha^0.  max_passes 0 means T + 1
+ * (Proposition 2.1 bounds the passes by T + 1).  On return actions [T] holds the fixed
+ * point, which equals pk_serial_simulate_capacity's actions; final_inv [K][N] and
+ * final_cap [N] (both nullable) the state after the last order.  passes: HOST out, the
+ * pass whose cache repeated the previous one (k* + 1, k* the first pass whose cache is the
+ * serial trajectory).  changed: HOST [max_passes] out, nullable: orders whose action
+ * changed in each pass.  caches: DEVICE [max_passes][T] out, nullable: alpha^k after pass
+ * k.  Synchronous (the pass count is data-dependent).  PK_ERR_NOT_CONVERGED if
+ * max_passes passes end without a repeat (actions then holds the last cache and the
+ * final state is not written). */
+pk_status pk_picard_simulate_capacity(const pk_problem *problem, const int32_t *capacity,
+                                      int32_t block_len, int32_t max_passes,
+                                      const int32_t *init_cache, void *ws, size_t ws_bytes,
+                                      int32_t *actions, int32_t *final_inv, int32_t *final_cap,
+                                      int32_t *passes, int64_t *changed, int32_t *caches,
+                                      void *stream);
+
 /* Message for the last non-OK status on this thread ("" if none). */
 const char *pk_last_error(void);
 

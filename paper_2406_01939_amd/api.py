@@ -91,9 +91,15 @@ def lib():
         L.pk_reinforce_advantages.argtypes = [P, vp, vp, i32, vp, vp, vp, sz, vp]
         f64 = C.c_double
         L.pk_adam_step.argtypes = [vp, vp, vp, vp, C.c_int64, i32, f64, f64, f64, f64, i32, vp]
+        L.pk_capacity_workspace_size.argtypes = [P, vp, i32, C.POINTER(sz)]
+        L.pk_serial_simulate_capacity.argtypes = [P, vp, vp, sz, vp, vp, vp, vp]
+        L.pk_picard_simulate_capacity.argtypes = [P, vp, i32, i32, vp, vp, sz, vp, vp, vp,
+                                                  C.POINTER(i32), vp, vp, vp]
         for f in ("pk_workspace_size", "pk_serial_simulate", "pk_picard_simulate",
                   "pk_policy_grad", "pk_autotune", "pk_policy_scores",
-                  "pk_advantages_workspace_size", "pk_reinforce_advantages", "pk_adam_step"):
+                  "pk_advantages_workspace_size", "pk_reinforce_advantages", "pk_adam_step",
+                  "pk_capacity_workspace_size", "pk_serial_simulate_capacity",
+                  "pk_picard_simulate_capacity"):
             getattr(L, f).restype = C.c_int
         L.pk_last_error.restype = C.c_char_p
         L.pk_last_error.argtypes = []
@@ -311,6 +317,67 @@ def pk_adam_step(params: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: t
     _check(lib().pk_adam_step(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), params.numel(),
                               int(step), float(lr), float(beta1), float(beta2), float(eps),
                               int(ascend), _stream(stream)))
+
+
+def pk_capacity_workspace_size(prob: DeviceProblem, capacity: torch.Tensor,
+                               block_len: int = 0) -> int:
+    p = prob.c_problem()
+    n = C.c_size_t(0)
+    _check(lib().pk_capacity_workspace_size(C.byref(p), _ptr(capacity), int(block_len),
+                                            C.byref(n)))
+    return int(n.value)
+
+
+def _cap_tensor(prob: DeviceProblem, capacity) -> torch.Tensor:
+    c = torch.as_tensor(capacity).to(device=prob.sku.device, dtype=torch.int32).contiguous()
+    if c.numel() != prob.N:
+        raise ValueError("capacity must have one entry per warehouse")
+    return c
+
+
+def pk_serial_simulate_capacity(prob: DeviceProblem, capacity, want_final=True,
+                                stream=None) -> dict:
+    """Serial greedy sweep with node capacities (one order at a time on the GPU)."""
+    dev = prob.sku.device
+    cap = _cap_tensor(prob, capacity)
+    p = prob.c_problem()
+    ws = workspace(pk_capacity_workspace_size(prob, cap), dev)
+    actions = torch.empty(prob.total, dtype=torch.int32, device=dev)
+    final = torch.empty_like(prob.init_inv) if want_final else None
+    fcap = torch.empty(prob.N, dtype=torch.int32, device=dev) if want_final else None
+    _check(lib().pk_serial_simulate_capacity(C.byref(p), _ptr(cap), _ptr(ws), ws.numel(),
+                                             _ptr(actions), _ptr(final), _ptr(fcap),
+                                             _stream(stream)))
+    return dict(actions=actions, final_inv=final, final_cap=fcap)
+
+
+def pk_picard_simulate_capacity(prob: DeviceProblem, capacity, block_len: int = 0,
+                                max_passes: int = 0,
+                                init_cache: Optional[torch.Tensor] = None,
+                                want_final=True, record=False, stream=None,
+                                raise_not_converged=True) -> dict:
+    """Algorithm 1 with node capacities; processes are blocks of consecutive orders."""
+    dev = prob.sku.device
+    cap = _cap_tensor(prob, capacity)
+    p = prob.c_problem()
+    T = prob.total
+    mp = max_passes if max_passes > 0 else T + 1
+    ws = workspace(pk_capacity_workspace_size(prob, cap, block_len), dev)
+    actions = torch.empty(T, dtype=torch.int32, device=dev)
+    final = torch.empty_like(prob.init_inv) if want_final else None
+    fcap = torch.empty(prob.N, dtype=torch.int32, device=dev) if want_final else None
+    caches = torch.empty((mp, T), dtype=torch.int32, device=dev) if record else None
+    changed = np.zeros(mp, dtype=np.int64)
+    passes = C.c_int32(0)
+    status = lib().pk_picard_simulate_capacity(
+        C.byref(p), _ptr(cap), int(block_len), int(max_passes), _ptr(init_cache), _ptr(ws),
+        ws.numel(), _ptr(actions), _ptr(final), _ptr(fcap), C.byref(passes),
+        changed.ctypes.data, _ptr(caches), _stream(stream))
+    if status != PK_OK and not (status == PK_ERR_NOT_CONVERGED and not raise_not_converged):
+        _check(status)
+    k = int(passes.value)
+    return dict(actions=actions, final_inv=final, final_cap=fcap, passes=k, status=status,
+                changed=changed[:k], caches=None if caches is None else caches[:k])
 
 
 # C names are the primary API; the short names are aliases.

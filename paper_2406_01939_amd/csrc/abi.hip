@@ -760,6 +760,89 @@ pk_status autotune_block(const pk_problem *problem, const Dims &d, const pk_poli
     return PK_OK;
 }
 
+
+// ---------------------------------------------------------------- node capacity
+constexpr int DEFAULT_BLOCK_CAP = 128;
+
+pk_status check_capacity_problem(const pk_problem *pr, const int32_t *capacity, Dims *d)
+{
+    pk_status s = check_problem(pr, d);
+    if (s != PK_OK) return s;
+    if (d->n_traj != 1) return fail(PK_ERR_UNSUPPORTED, "capacity runs take one trajectory");
+    if (d->N > CAP_NPAD) return fail(PK_ERR_UNSUPPORTED, "capacity runs take N <= %d", CAP_NPAD);
+    if (!capacity) return fail(PK_ERR_INVALID_ARG, "capacity is NULL");
+    return PK_OK;
+}
+
+struct CapWs {
+    CapPlan L;
+    int32_t *keys, *vals, *keys_alt, *vals_alt, *first, *used, *state;
+    void *tmp;
+};
+
+// Carves (or measures, with base == nullptr) a capacity run's workspace.
+size_t carve_cap(char *base, const Dims &d, int B, bool picard, CapWs *w)
+{
+    Carver c{base};
+    CapWs x = {};
+    const int64_t T = d.total;
+    const int64_t nblk = std::max<int64_t>(1, (T + B - 1) / B);
+    const int64_t max_pieces = d.K + T / CAP_PIECE + 1;
+    x.L.ctl = c.take<CapCtl>(1);
+    x.L.keyT = c.take<uint32_t>((int64_t)d.R * CAP_NPAD);
+    x.used = c.take<int32_t>(CAP_NPAD);
+    if (picard) {
+        x.L.perm = c.take<int32_t>(T);
+        x.L.seg_off = c.take<int32_t>(d.K + 1);
+        x.L.slot = c.take<int32_t>(T);
+        x.L.sid = c.take<int32_t>(T);
+        x.L.piece_off = c.take<int32_t>(d.K + 1);
+        x.L.piece_seg = c.take<int32_t>(max_pieces);
+        x.L.pc = c.take<int32_t>(max_pieces * CAP_NPAD);
+        x.L.H = c.take<int32_t>((int64_t)d.N * nblk);
+        x.L.capE = c.take<int32_t>(nblk * CAP_NPAD);
+        x.L.X = c.take<uint8_t>(std::max<int64_t>(T, 1) * CAP_NPAD);
+        x.keys = c.take<int32_t>(T);
+        x.vals = c.take<int32_t>(T);
+        x.keys_alt = c.take<int32_t>(T);
+        x.vals_alt = c.take<int32_t>(T);
+        x.first = c.take<int32_t>(T);
+        x.tmp = c.take<char>((int64_t)std::max(radix_tmp_bytes(T),
+                                               scan_tmp_bytes(std::max<int64_t>(T, d.K + 1))));
+    } else {
+        x.state = c.take<int32_t>((int64_t)d.K * d.N);
+    }
+    x.L.T = (int32_t)T;
+    x.L.N = d.N;
+    x.L.K = d.K;
+    x.L.R = d.R;
+    x.L.B = B;
+    x.L.nblk = (int32_t)nblk;
+    x.L.max_pieces = max_pieces;
+    if (w) *w = x;
+    return c.off + 256;
+}
+
+void cap_bind(CapPlan &L, const pk_problem *pr, const int32_t *capacity, int32_t *actions)
+{
+    L.sku = pr->sku;
+    L.region = pr->region;
+    L.qty = pr->qty;
+    L.x0 = pr->init_inv;
+    L.cost = pr->cost;
+    L.cap0 = capacity;
+    L.alpha = actions;
+}
+
+pk_status cap_errors(const CapCtl &h)
+{
+    if (!h.error) return PK_OK;
+    return fail(PK_ERR_INVALID_ARG,
+                "invalid input (bits %#x: 1 quantity != 1, 2 SKU, 4 region, 8 negative stock, "
+                "16 negative capacity, 32 cost outside [0, 2^24), 64 initial cache outside [-1, N))",
+                h.error);
+}
+
 } // namespace
 
 extern "C" {
@@ -1040,6 +1123,111 @@ pk_status pk_adam_step(float *params, const float *grad, float *m, float *v, int
     c.eps = (float)eps;
     c.dir = ascend ? 1.0f : -1.0f;
     HIP_TRY(launch_adam(params, grad, m, v, n, c, (hipStream_t)stream));
+    return PK_OK;
+}
+
+pk_status pk_capacity_workspace_size(const pk_problem *problem, const int32_t *capacity,
+                                     int32_t block_len, size_t *bytes)
+{
+    g_err.clear();
+    Dims d;
+    pk_status s = check_capacity_problem(problem, capacity, &d);
+    if (s != PK_OK) return s;
+    if (!bytes) return fail(PK_ERR_INVALID_ARG, "bytes is NULL");
+    if (block_len < 0 || block_len > CAP_MAX_B)
+        return fail(PK_ERR_INVALID_ARG, "block_len must lie in [0, %d]", CAP_MAX_B);
+    const int B = block_len ? block_len : DEFAULT_BLOCK_CAP;
+    *bytes = std::max(carve_cap(nullptr, d, B, true, nullptr),
+                      carve_cap(nullptr, d, B, false, nullptr)) + 256;
+    return PK_OK;
+}
+
+pk_status pk_serial_simulate_capacity(const pk_problem *problem, const int32_t *capacity,
+                                      void *ws, size_t ws_bytes, int32_t *actions,
+                                      int32_t *final_inv, int32_t *final_cap, void *stream)
+{
+    g_err.clear();
+    Dims d;
+    pk_status s = check_capacity_problem(problem, capacity, &d);
+    if (s != PK_OK) return s;
+    if (d.total > 0 && !actions) return fail(PK_ERR_INVALID_ARG, "actions is NULL");
+    if (!ws || ws_bytes < carve_cap(nullptr, d, DEFAULT_BLOCK_CAP, false, nullptr))
+        return fail(PK_ERR_WORKSPACE, "workspace too small");
+    hipStream_t st = (hipStream_t)stream;
+    CapWs w;
+    carve_cap(align_ws(ws), d, DEFAULT_BLOCK_CAP, false, &w);
+    cap_bind(w.L, problem, capacity, actions);
+    int32_t *state = final_inv ? final_inv : w.state;
+    HIP_TRY(cap_check(w.L, nullptr, st));
+    CapCtl h;
+    HIP_TRY(hipMemcpyAsync(&h, w.L.ctl, sizeof h, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if ((s = cap_errors(h)) != PK_OK) return s;
+    HIP_TRY(cap_serial_setup(w.L, st));
+    HIP_TRY(hipMemcpyAsync(state, problem->init_inv, (size_t)d.K * d.N * 4,
+                           hipMemcpyDeviceToDevice, st));
+    HIP_TRY(cap_serial(w.L, state, actions, st));
+    if (final_cap) HIP_TRY(cap_finish(w.L, nullptr, final_cap, w.used, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return PK_OK;
+}
+
+pk_status pk_picard_simulate_capacity(const pk_problem *problem, const int32_t *capacity,
+                                      int32_t block_len, int32_t max_passes,
+                                      const int32_t *init_cache, void *ws, size_t ws_bytes,
+                                      int32_t *actions, int32_t *final_inv, int32_t *final_cap,
+                                      int32_t *passes, int64_t *changed, int32_t *caches,
+                                      void *stream)
+{
+    g_err.clear();
+    Dims d;
+    pk_status s = check_capacity_problem(problem, capacity, &d);
+    if (s != PK_OK) return s;
+    if (d.total > 0 && !actions) return fail(PK_ERR_INVALID_ARG, "actions is NULL");
+    if (block_len < 0 || block_len > CAP_MAX_B)
+        return fail(PK_ERR_INVALID_ARG, "block_len must lie in [0, %d]", CAP_MAX_B);
+    if (max_passes < 0) return fail(PK_ERR_INVALID_ARG, "max_passes must be >= 0");
+    const int B = block_len ? block_len : DEFAULT_BLOCK_CAP;
+    const int64_t T = d.total;
+    const int32_t mp = max_passes ? max_passes : (int32_t)std::min<int64_t>(T + 1, INT32_MAX);
+    if (!ws || ws_bytes < carve_cap(nullptr, d, B, true, nullptr))
+        return fail(PK_ERR_WORKSPACE, "workspace too small");
+    hipStream_t st = (hipStream_t)stream;
+    CapWs w;
+    carve_cap(align_ws(ws), d, B, true, &w);
+    cap_bind(w.L, problem, capacity, actions);
+    HIP_TRY(cap_check(w.L, init_cache, st));
+    CapCtl h;
+    HIP_TRY(hipMemcpyAsync(&h, w.L.ctl, sizeof h, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if ((s = cap_errors(h)) != PK_OK) return s;
+    HIP_TRY(cap_setup(w.L, w.keys, w.vals, w.keys_alt, w.vals_alt, w.first, w.tmp, st));
+    if (T > 0) {
+        if (init_cache)
+            HIP_TRY(hipMemcpyAsync(actions, init_cache, (size_t)T * 4, hipMemcpyDeviceToDevice, st));
+        else
+            HIP_TRY(hipMemsetAsync(actions, 0xff, (size_t)T * 4, st)); // all lost sales (-1)
+    }
+    int32_t k = 0;
+    bool converged = false;
+    for (k = 1; k <= mp; ++k) {
+        HIP_TRY(cap_pass(w.L, k == 1, st));
+        if (caches && T > 0)
+            HIP_TRY(hipMemcpyAsync(caches + (int64_t)(k - 1) * T, actions, (size_t)T * 4,
+                                   hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpyAsync(&h, w.L.ctl, sizeof h, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (changed) changed[k - 1] = h.changed;
+        if (h.changed == 0) {
+            converged = true;
+            break;
+        }
+    }
+    if (k > mp) k = mp;
+    if (passes) *passes = k;
+    if (!converged) return fail(PK_ERR_NOT_CONVERGED, "no fixed point after %d passes", mp);
+    HIP_TRY(cap_finish(w.L, final_inv, final_cap, w.used, st));
+    HIP_TRY(hipStreamSynchronize(st));
     return PK_OK;
 }
 

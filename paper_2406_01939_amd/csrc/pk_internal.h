@@ -196,4 +196,52 @@ hipError_t radix_sort_pairs(int32_t *keys, int32_t *vals, int32_t *keys_alt,
                             hipStream_t st, bool *result_in_alt);
 size_t radix_tmp_bytes(int64_t n);
 
+// ---------------------------------------------------------------- node capacity
+// (capacity.hip: Picard with the FO state (x, c) of Section 3, time-block processes)
+constexpr int CAP_NPAD = 128; // warehouses per row: two per lane
+constexpr int CAP_MAX_B = 255;
+constexpr int CAP_PIECE = 2048; // positions of the SKU-sorted list per entry wave
+constexpr uint32_t CAP_NONE = 0xffffffffu;
+
+// error bits of CapCtl::error
+constexpr int32_t CAP_ERR_QTY = 1, CAP_ERR_SKU = 2, CAP_ERR_REGION = 4, CAP_ERR_X0 = 8,
+                  CAP_ERR_CAP = 16, CAP_ERR_COST = 32, CAP_ERR_INIT = 64;
+
+struct CapCtl {
+    int32_t error;
+    int32_t changed;   // orders whose action changed in the current pass
+    int32_t first_blk; // first block with a change in the current pass
+    int32_t frontier;  // blocks <= frontier are not walked in the current pass
+    int32_t n_pieces;
+};
+
+struct CapPlan {
+    int32_t T, N, K, R, B, nblk;
+    int64_t max_pieces;
+    const int32_t *sku, *region, *qty, *x0, *cost, *cap0;
+    int32_t *alpha;      // [T] cache, time order (the caller's actions buffer)
+    int32_t *perm;       // [T] SKU-sorted position -> time index
+    int32_t *seg_off;    // [K+1]
+    int32_t *slot;       // [T] index in its block of the first order of its (block, SKU)
+    int32_t *sid;        // [T] row of X for the first order of each (block, SKU)
+    int32_t *piece_off;  // [K+1] first piece of each SKU
+    int32_t *piece_seg;  // [max_pieces] SKU of each piece
+    int32_t *pc;         // [max_pieces][CAP_NPAD] action counts, then their scan
+    int32_t *H;          // [N][nblk] passing cached actions per (node, block)
+    int32_t *capE;       // [nblk][CAP_NPAD] capacity at each block's start
+    uint32_t *keyT;      // [R][CAP_NPAD] (cost << 8) | w, all-ones past N
+    uint8_t *X;          // [T][CAP_NPAD] stock rows of the (block, SKU) pairs
+    CapCtl *ctl;
+};
+
+size_t cap_walk_lds(int B);
+hipError_t cap_check(CapPlan &L, const int32_t *init, hipStream_t st);
+hipError_t cap_setup(CapPlan &L, int32_t *keys, int32_t *vals, int32_t *keys_alt,
+                     int32_t *vals_alt, int32_t *first, void *tmp, hipStream_t st);
+hipError_t cap_pass(const CapPlan &L, bool first, hipStream_t st);
+hipError_t cap_finish(const CapPlan &L, int32_t *final_inv, int32_t *final_cap, int32_t *used,
+                      hipStream_t st);
+hipError_t cap_serial_setup(CapPlan &L, hipStream_t st);
+hipError_t cap_serial(const CapPlan &L, int32_t *state, int32_t *actions, hipStream_t st);
+
 } // namespace pk

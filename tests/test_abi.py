@@ -88,3 +88,27 @@ def test_training_entry_points_validate_on_host():
                                      None) == api.PK_ERR_INVALID_ARG
     assert L.pk_reinforce_advantages(C.byref(p), 1, 1, 10, 1, None, 1, 8,
                                      None) == api.PK_ERR_WORKSPACE
+
+
+def test_capacity_entry_points_validate_on_host():
+    """The capacity entry points reject unsupported shapes before any device work."""
+    import numpy as np
+    from paper_2406_01939_amd import api
+    L = api.lib()
+    n = C.c_size_t(0)
+    offs = np.array([0, 5], dtype=np.int64)
+    p = api.pk_problem(4, 2, 3, 1, offs.ctypes.data, 1, 1, 1, 1, 1, 0)
+    assert L.pk_capacity_workspace_size(C.byref(p), 1, 0, C.byref(n)) == api.PK_OK
+    assert n.value > 5 * 128  # stock rows of up to one (block, SKU) per order
+    assert L.pk_capacity_workspace_size(C.byref(p), None, 0, C.byref(n)) == api.PK_ERR_INVALID_ARG
+    assert L.pk_capacity_workspace_size(C.byref(p), 1, 256, C.byref(n)) == api.PK_ERR_INVALID_ARG
+    wide = api.pk_problem(129, 2, 3, 1, offs.ctypes.data, 1, 1, 1, 1, 1, 0)
+    assert L.pk_capacity_workspace_size(C.byref(wide), 1, 0, C.byref(n)) == api.PK_ERR_UNSUPPORTED
+    two = np.array([0, 5, 9], dtype=np.int64)
+    p2 = api.pk_problem(4, 2, 3, 2, two.ctypes.data, 1, 1, 1, 1, 1, 0)
+    assert L.pk_capacity_workspace_size(C.byref(p2), 1, 0, C.byref(n)) == api.PK_ERR_UNSUPPORTED
+    passes = C.c_int32(0)
+    assert L.pk_picard_simulate_capacity(C.byref(p), 1, 0, 0, None, None, 0, 1, None, None,
+                                         C.byref(passes), None, None, None) == api.PK_ERR_WORKSPACE
+    assert L.pk_serial_simulate_capacity(C.byref(p), 1, None, 0, 1, None, None,
+                                         None) == api.PK_ERR_WORKSPACE
