@@ -29,6 +29,7 @@ METRIC = "simulated orders/sec/GPU, Picard vs serial GPU sweep; iterations to co
 HBM_PEAK_GBS = 8000.0
 DEFAULT_WORKLOAD = "greedy_n100_k1e5_t1e6"
 LEARNED_WORKLOAD = "mlp_batch64_n100_k5e4_t2e5"
+CAPACITY_WORKLOAD = "greedy_cap_n100_k1e5_t1e6"
 REVENUE = 200  # per-unit price of the margin reward (revenue - cost) of the gradient legs
 FP32_PEAK_TFLOPS = 157.3
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_walk_greedy_n100_k1e5_t1e6_traffic.md")
@@ -118,6 +119,10 @@ def main():
                     help="Section 4.1's partition contrast on the 3e6-order, 1e6-SKU, 30-"
                          "warehouse instance: product and uniform random partitions over 1e4 "
                          "processes and autotuned blocks, demand exponent 0 to -1")
+    ap.add_argument("--no-capacity", action="store_true",
+                    help="skip the node-capacity leg (Section 3's full state, time blocks)")
+    ap.add_argument("--capacity-only", action="store_true",
+                    help="only run the node-capacity leg (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter yardstick)")
     args = ap.parse_args()
@@ -291,6 +296,57 @@ def main():
         return {"workload": name, "policy": policy, "processes": M,
                 "timing": f"best of {reps} after a warm-up", "rows": rows}
 
+    def capacity_leg(name=CAPACITY_WORKLOAD, blocks=(32, 64, 128, 255), reps=3, serial=True):
+        """Picard with node capacity (time-block processes) against the serial GPU sweep
+        with capacity, on the same instance; best of `reps` calls per block length after a
+        warm-up call."""
+        from paper_2406_01939_amd.instances import workload_capacity
+        inst = make_instance(name)
+        cap = torch.from_numpy(workload_capacity(name)).cuda()
+        prob = api.DeviceProblem.from_instance(inst)
+        total = inst.total_orders
+        rows = []
+        ref = None
+        for B in blocks:
+            out = api.pk_picard_simulate_capacity(prob, cap, block_len=B)
+            best = None
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                out = api.pk_picard_simulate_capacity(prob, cap, block_len=B)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                best = dt if best is None else min(best, dt)
+            if ref is None:
+                ref = out["actions"].clone()
+            same = bool(torch.equal(out["actions"], ref))
+            rows.append({"block_len": B, "seconds": best, "orders_per_s": total / best,
+                         "passes": out["passes"], "identical_across_blocks": same})
+            _progress(f"capacity {name} B={B}: {1e3 * best:.2f} ms, {out['passes']} passes")
+        top = min(rows, key=lambda r: r["seconds"])
+        res = {"workload": name, "orders": total, "value": top["orders_per_s"],
+               "unit": "orders/s", "block_len": top["block_len"], "passes": top["passes"],
+               "ms": 1e3 * top["seconds"], "blocks": rows,
+               "capacity_per_node": int(cap[0].item()),
+               "nodes_out_of_capacity": None}
+        if serial:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ser = api.pk_serial_simulate_capacity(prob, cap)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            res["serial_gpu"] = {"value": total / dt, "unit": "orders/s", "seconds": dt,
+                                 "identical_actions": bool(torch.equal(ser["actions"], ref))}
+            res["speedup_vs_serial_gpu"] = dt / top["seconds"]
+            res["nodes_out_of_capacity"] = int((ser["final_cap"] == 0).sum().item())
+            _progress(f"capacity serial sweep: {dt:.3f} s")
+        return res
+
+    if args.capacity_only:
+        print(json.dumps({"capacity": capacity_leg(serial=not args.no_serial,
+                                                   reps=max(1, args.steps))}))
+        return
+
     def pg_loop(name, iters):
         """End-to-end training (rollout, advantages, gradient, Adam step) for `iters`
         iterations from the same initial parameters, once per rollout mode."""
@@ -347,6 +403,8 @@ def main():
                           "passes_mean": float(lm["passes"].mean()), "dtype": "f32",
                           "roofline": lm["roofline"], "serial_gpu": lm["serial_gpu"],
                           "speedup_vs_serial_gpu": lm["speedup_vs_serial_gpu"]}
+    if not args.no_capacity and policy == "greedy":
+        res["capacity"] = capacity_leg(serial=not args.no_serial)
     if args.pg_iters > 0:
         res["policy_gradient_loop"] = pg_loop(LEARNED_WORKLOAD, args.pg_iters)
     if args.partition_sweep == "greedy":

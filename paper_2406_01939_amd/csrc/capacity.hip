@@ -39,13 +39,25 @@ namespace {
 
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Least of the 64 lanes' values, by DPP: row minima (row_shr 1, 2, 4, 8), then rows 0-1
+// and 2-3 (row_bcast 15), then all four (row_bcast 31) in lane 63, read from there.
+// Lanes a step does not reach keep the identity CAP_NONE.
 __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v)
 {
-    for (int d = WAVE / 2; d > 0; d >>= 1) {
-        const uint32_t o = (uint32_t)__shfl_xor((int)v, d, WAVE);
-        v = o < v ? o : v;
+#define PK_CAP_MIN_DPP(ctrl, rmask)                                                              \
+    {                                                                                            \
+        const uint32_t o = (uint32_t)__builtin_amdgcn_update_dpp((int)CAP_NONE, (int)v, ctrl,   \
+                                                                 rmask, 0xf, false);             \
+        v = o < v ? o : v;                                                                       \
     }
-    return v;
+    PK_CAP_MIN_DPP(0x111, 0xf) // row_shr:1
+    PK_CAP_MIN_DPP(0x112, 0xf) // row_shr:2
+    PK_CAP_MIN_DPP(0x114, 0xf) // row_shr:4
+    PK_CAP_MIN_DPP(0x118, 0xf) // row_shr:8
+    PK_CAP_MIN_DPP(0x142, 0xa) // row_bcast:15 into rows 1 and 3
+    PK_CAP_MIN_DPP(0x143, 0xc) // row_bcast:31 into rows 2 and 3
+#undef PK_CAP_MIN_DPP
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
 __device__ __forceinline__ uint8_t clamp255(int v) { return (uint8_t)(v < 0 ? 0 : (v > 255 ? 255 : v)); }
@@ -71,14 +83,24 @@ __global__ void k_cap_check(CapPlan L, int64_t n_x0, const int32_t *init)
     if (err) atomicOr(&L.ctl->error, err);
 }
 
-__global__ void k_cap_keys(CapPlan L, int32_t *keys, int32_t *vals, int32_t *hist)
+__global__ void k_cap_keys(CapPlan L, int32_t *keys, int32_t *vals)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < L.T; t += stride) {
-        const int32_t k = L.sku[t];
-        keys[t] = k;
+        keys[t] = L.sku[t];
         vals[t] = (int32_t)t;
-        atomicAdd(&hist[k], 1);
+    }
+}
+
+// seg_off[k] = first sorted position whose SKU is >= k, for k = 0..K: position i writes
+// the SKUs in (key[i-1], key[i]] (key[-1] = -1, key[T] = K), which covers each k once.
+__global__ void k_cap_seg_bounds(CapPlan L, const int32_t *skey)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= L.T; i += stride) {
+        const int prev = i > 0 ? skey[i - 1] : -1;
+        const int cur = i < L.T ? skey[i] : L.K;
+        for (int k = prev + 1; k <= cur; ++k) L.seg_off[k] = (int32_t)i;
     }
 }
 
@@ -122,27 +144,22 @@ __global__ void k_cap_piece_counts(CapPlan L, int32_t *cnt)
     }
 }
 
+// One descriptor per piece: SKU, sorted range and whether its SKU has several pieces.
 __global__ void k_cap_piece_fill(CapPlan L)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < L.K; k += stride) {
-        for (int p = L.piece_off[k]; p < L.piece_off[k + 1]; ++p) L.piece_seg[p] = (int32_t)k;
+        const int p0 = L.piece_off[k], p1 = L.piece_off[k + 1];
+        const int s0 = L.seg_off[k], s1 = L.seg_off[k + 1];
+        for (int p = p0; p < p1; ++p) {
+            const int lo = s0 + (p - p0) * CAP_PIECE;
+            L.piece[p] = make_int4((int)k, lo, min(lo + CAP_PIECE, s1), p1 - p0 > 1);
+        }
         if (k == L.K - 1) L.ctl->n_pieces = L.piece_off[L.K];
     }
 }
 
 // ---------------------------------------------------------------- one pass
-// Piece p of SKU k covers sorted positions [seg_off[k] + j*CAP_PIECE, ...) with j its
-// index in the SKU.
-__device__ __forceinline__ void piece_range(const CapPlan &L, int p, int &k, int &j, int &lo,
-                                            int &hi)
-{
-    k = L.piece_seg[p];
-    j = p - L.piece_off[k];
-    lo = L.seg_off[k] + j * CAP_PIECE;
-    hi = min(lo + CAP_PIECE, L.seg_off[k + 1]);
-}
-
 // Cached action counts per piece of the SKUs with more than one piece.
 __global__ __launch_bounds__(256) void k_cap_piece_count(CapPlan L)
 {
@@ -150,9 +167,9 @@ __global__ __launch_bounds__(256) void k_cap_piece_count(CapPlan L)
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     const int p = uni(blockIdx.x * 4 + wave);
     if (p >= L.ctl->n_pieces) return;
-    int k, j, lo, hi;
-    piece_range(L, p, k, j, lo, hi);
-    if (L.piece_off[k + 1] - L.piece_off[k] < 2) return;
+    const int4 pd = L.piece[p]; // SKU, lo, hi, several pieces
+    const int lo = pd.y, hi = pd.z;
+    if (!pd.w) return;
     u[wave][lane] = 0;
     u[wave][WAVE + lane] = 0;
     wave_sync();
@@ -175,83 +192,119 @@ __global__ __launch_bounds__(256) void k_cap_piece_scan(CapPlan L)
     const int p0 = L.piece_off[k], p1 = L.piece_off[k + 1];
     if (p1 - p0 < 2) return;
     int run0 = 0, run1 = 0;
-    for (int p = p0; p < p1; ++p) {
-        int32_t *row = L.pc + (int64_t)p * CAP_NPAD;
-        const int v0 = row[lane], v1 = row[WAVE + lane];
-        row[lane] = run0;
-        row[WAVE + lane] = run1;
-        run0 += v0;
-        run1 += v1;
+    constexpr int U = 8; // rows loaded together
+    for (int pb = p0; pb < p1; pb += U) {
+        int v0[U], v1[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int32_t *row = L.pc + (int64_t)min(pb + q, p1 - 1) * CAP_NPAD;
+            v0[q] = row[lane];
+            v1[q] = row[WAVE + lane];
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            if (pb + q < p1) {
+                int32_t *row = L.pc + (int64_t)(pb + q) * CAP_NPAD;
+                row[lane] = run0;
+                row[WAVE + lane] = run1;
+                run0 += v0[q];
+                run1 += v1[q];
+            }
+        }
     }
 }
 
+// The SKU-sorted position i of a piece: its order's time, cached action and, for the
+// first order of a (block, SKU), the row of X it starts (else -1).
+struct CapEnt {
+    int t, a, row;
+};
+
+__device__ __forceinline__ CapEnt cap_ent(const CapPlan &L, int i, int hi)
+{
+    CapEnt e = {0, LOST, -1};
+    if (i < hi) {
+        e.t = L.perm[i];
+        const int s = L.slot[e.t], r = L.sid[e.t];
+        e.a = L.alpha[e.t];
+        e.row = s == e.t % L.B ? r : -1;
+    }
+    return e;
+}
+
 // One wave per piece: stock rows at each (block, SKU)'s first order and passing cached
-// actions per (node, block).  Lane l holds nodes l and 64 + l.
+// actions per (node, block).  Lane l holds nodes l and 64 + l: their stock, the cached
+// actions of the SKU before the current position (ca, cb) and within the current
+// (block, SKU) (ua, ub), all in registers.  Positions come 64 at a time, the next chunk
+// loaded while the current one is counted.
 __global__ __launch_bounds__(256) void k_cap_entry(CapPlan L)
 {
-    __shared__ int32_t ush[4][CAP_NPAD];
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     const int p = uni(blockIdx.x * 4 + wave);
     if (p >= L.ctl->n_pieces) return;
-    int k, j, lo, hi;
-    piece_range(L, p, k, j, lo, hi);
-    int32_t *u = ush[wave];
+    const int4 pd = L.piece[p]; // SKU, lo, hi, several pieces
+    const int k = pd.x, lo = pd.y, hi = pd.z;
     const int N = L.N, B = L.B, nblk = L.nblk;
     const int frontier = L.ctl->frontier;
     const int w0 = lane, w1 = WAVE + lane;
     const int x0a = w0 < N ? L.x0[(int64_t)k * N + w0] : 0;
     const int x0b = w1 < N ? L.x0[(int64_t)k * N + w1] : 0;
-    int ca = 0, cb = 0; // cached actions of this SKU to each node before the position
-    if (L.piece_off[k + 1] - L.piece_off[k] > 1) {
+    int ca = 0, cb = 0;
+    if (pd.w) {
         const int32_t *row = L.pc + (int64_t)p * CAP_NPAD;
         ca = row[w0];
         cb = row[w1];
     }
-    u[w0] = 0;
-    u[w1] = 0;
-    wave_sync();
-    int cur = -1; // block of the (block, SKU) being accumulated
-    auto flush = [&](int m) {
-        wave_sync();
-        const int ua = u[w0], ub = u[w1];
-        const int pa = min(ua, max(0, x0a - ca)), pb = min(ub, max(0, x0b - cb));
-        if (pa > 0) atomicAdd(&L.H[(int64_t)w0 * nblk + m], pa);
-        if (pb > 0) atomicAdd(&L.H[(int64_t)w1 * nblk + m], pb);
-        ca += ua;
-        cb += ub;
-        u[w0] = 0;
-        u[w1] = 0;
-        wave_sync();
-    };
+    int ua = 0, ub = 0;
+    int cur = -1; // block of the (block, SKU) being counted
+    CapEnt e = cap_ent(L, lo + lane, hi);
     for (int base = lo; base < hi; base += WAVE) {
-        const int i = base + lane;
-        const bool valid = i < hi;
-        const int t = valid ? L.perm[i] : 0;
-        const int m = valid ? t / B : INT_MAX;
-        const int a = valid ? L.alpha[t] : LOST;
-        const bool first = valid && L.slot[t] == t - m * B;
+        const CapEnt nx = cap_ent(L, base + WAVE + lane, hi);
+        const bool valid = base + lane < hi;
+        const int m = valid ? e.t / B : INT_MAX;
         const uint64_t vmask = __ballot(valid);
         uint64_t done = 0;
-        while (done != vmask) { // pieces of equal block, in lane order
+        while (done != vmask) { // runs of equal block, in lane order
             const int p0 = __ffsll((long long)(vmask & ~done)) - 1;
             const int mm = uni(__shfl(m, p0, WAVE));
             if (mm != cur) {
-                if (cur >= 0) flush(cur);
+                if (cur >= 0) { // close the previous (block, SKU)
+                    const int pa = min(ua, max(0, x0a - ca)), pb = min(ub, max(0, x0b - cb));
+                    if (pa > 0) atomicAdd(&L.H[(int64_t)w0 * nblk + cur], pa);
+                    if (pb > 0) atomicAdd(&L.H[(int64_t)w1 * nblk + cur], pb);
+                    ca += ua;
+                    cb += ub;
+                    ua = ub = 0;
+                }
                 cur = mm;
-                const int f = __shfl((int)first, p0, WAVE);
-                if (f && mm > frontier) { // the block's stock row of this SKU
-                    const int tp = __shfl(t, p0, WAVE);
-                    uint8_t *xr = L.X + (int64_t)L.sid[tp] * CAP_NPAD;
+                const int row = uni(__shfl(e.row, p0, WAVE));
+                if (row >= 0 && mm > frontier) { // the block's stock row of this SKU
+                    uint8_t *xr = L.X + (int64_t)row * CAP_NPAD;
                     xr[w0] = clamp255(x0a - ca);
                     xr[w1] = clamp255(x0b - cb);
                 }
             }
             const bool in = valid && m == mm;
-            if (in && a >= 0) atomicAdd(&u[a], 1);
+            uint64_t rem = __ballot(in && e.a >= 0);
+            while (rem) { // count the run's cached actions per node, one node at a time
+                const int q = __ffsll((long long)rem) - 1;
+                const int v = uni(__shfl(e.a, q, WAVE));
+                const uint64_t mv = __ballot(in && e.a == v);
+                if (lane == (v & (WAVE - 1))) {
+                    if (v < WAVE) ua += __popcll(mv);
+                    else ub += __popcll(mv);
+                }
+                rem &= ~mv;
+            }
             done |= __ballot(in);
         }
+        e = nx;
     }
-    if (cur >= 0) flush(cur);
+    if (cur >= 0) {
+        const int pa = min(ua, max(0, x0a - ca)), pb = min(ub, max(0, x0b - cb));
+        if (pa > 0) atomicAdd(&L.H[(int64_t)w0 * nblk + cur], pa);
+        if (pb > 0) atomicAdd(&L.H[(int64_t)w1 * nblk + cur], pb);
+    }
 }
 
 // Per node, exclusive scan of the passing counts over blocks: capacity at each block's
@@ -279,14 +332,17 @@ __global__ __launch_bounds__(256) void k_cap_scan(CapPlan L)
     for (int b = b0; b < b1; ++b) {
         const int v = h[b];
         h[b] = 0;
-        L.capE[(int64_t)b * CAP_NPAD + w] = max(0, c0 - run);
+        L.capE[(int64_t)w * nblk + b] = max(0, c0 - run);
         run += v;
     }
 }
 
 // One wave per block: the block's orders in time order with fresh greedy decisions.
 // Lane l holds nodes 2l and 2l+1 (stock bytes as one 16-bit LDS word, capacities and keys
-// in registers).  A lane writes only its own stock word, so steps need no barrier.
+// in registers).  A lane writes only its own stock word, so steps need no barrier.  The
+// block's regions and stock-row slots sit in registers (order j in lane j % 64 of
+// register j / 64) and are read with readlane; each region's keys are loaded four orders
+// ahead.
 __global__ __launch_bounds__(64) void k_cap_walk(CapPlan L)
 {
     extern __shared__ __align__(16) unsigned char cap_smem[];
@@ -295,26 +351,58 @@ __global__ __launch_bounds__(64) void k_cap_walk(CapPlan L)
     if (m <= ctl->frontier) return;
     const int B = L.B;
     const int lo = m * B, hi = min(lo + B, L.T), n = hi - lo;
-    uint16_t *rows = (uint16_t *)cap_smem;              // [B][64] stock words
-    int32_t *reg = (int32_t *)(cap_smem + (size_t)B * CAP_NPAD); // [B]
-    int32_t *sl = reg + B;                                // [B]
-    int32_t *out = sl + B;                                // [B]
-    for (int j = lane; j < n; j += WAVE) {
-        reg[j] = L.region[lo + j];
-        sl[j] = L.slot[lo + j];
+    uint16_t *rows = (uint16_t *)cap_smem;                       // [B][64] stock words
+    int32_t *sd = (int32_t *)(cap_smem + (size_t)B * CAP_NPAD); // [B] row of X per slot
+    int32_t *out = sd + B;                                       // [B]
+    int rg[4], sv[4]; // regions and slots of orders lane, 64 + lane, 128 + lane, 192 + lane
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int j = q * WAVE + lane;
+        rg[q] = sv[q] = 0;
+        if (j < n) {
+            rg[q] = L.region[lo + j];
+            sv[q] = L.slot[lo + j];
+            sd[j] = sv[q] == j ? L.sid[lo + j] : -1;
+        }
     }
     __syncthreads();
-    const uint16_t *X16 = (const uint16_t *)L.X;
-    for (int j = 0; j < n; ++j)
-        if (sl[j] == j) rows[j * WAVE + lane] = X16[(int64_t)L.sid[lo + j] * WAVE + lane];
-    const int2 cv = *(const int2 *)(L.capE + (int64_t)m * CAP_NPAD + 2 * lane);
-    int c0 = 2 * lane < L.N ? cv.x : 0, c1 = 2 * lane + 1 < L.N ? cv.y : 0;
+    // stock rows of the block's SKUs: 16-byte pieces spread over the lanes, every load of a
+    // round issued before its stores
+    {
+        const uint4 *X4 = (const uint4 *)L.X;
+        uint4 *R4 = (uint4 *)rows;
+        const int n16 = n * (CAP_NPAD / 16);
+        for (int b0 = 0; b0 < n16; b0 += 4 * WAVE) {
+            int r[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int idx = b0 + q * WAVE + lane;
+                r[q] = idx < n16 ? sd[idx >> 3] : -1;
+            }
+            uint4 v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int idx = b0 + q * WAVE + lane;
+                v[q] = X4[(int64_t)(r[q] >= 0 ? r[q] : 0) * (CAP_NPAD / 16) + (idx & 7)];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (r[q] >= 0) R4[b0 + q * WAVE + lane] = v[q];
+        }
+    }
+    const int nblk = L.nblk;
+    int c0 = 2 * lane < L.N ? L.capE[(int64_t)(2 * lane) * nblk + m] : 0;
+    int c1 = 2 * lane + 1 < L.N ? L.capE[(int64_t)(2 * lane + 1) * nblk + m] : 0;
+    __syncthreads();
     const uint2 *K2 = (const uint2 *)L.keyT;
-    uint2 kc = K2[(int64_t)reg[0] * WAVE + lane];
-    for (int j = 0; j < n; ++j) {
-        const int jn = j + 1 < n ? j + 1 : j;
-        const uint2 kn = K2[(int64_t)reg[jn] * WAVE + lane]; // next step's keys
-        const int s = sl[j];
+    auto lane_val = [&](const int (&a)[4], int j) { // wave-uniform j < 256
+        const int q = j >> 6, l = j & (WAVE - 1);
+        const int v = q == 0 ? a[0] : q == 1 ? a[1] : q == 2 ? a[2] : a[3];
+        return __builtin_amdgcn_readlane(v, l);
+    };
+    // one step: least key among this lane's nodes with stock and capacity, then the wave's
+    auto step = [&](int jj, uint2 kc) {
+        const int s = lane_val(sv, jj);
         uint32_t xv = rows[s * WAVE + lane];
         const uint32_t ka = ((xv & 0xffu) && c0 > 0) ? kc.x : CAP_NONE;
         const uint32_t kb = ((xv >> 8) && c1 > 0) ? kc.y : CAP_NONE;
@@ -325,8 +413,21 @@ __global__ __launch_bounds__(64) void k_cap_walk(CapPlan L)
             else { --c0; xv -= 1u; }
             rows[s * WAVE + lane] = (uint16_t)xv;
         }
-        if (lane == 0) out[j] = a;
-        kc = kn;
+        if (lane == 0) out[jj] = a;
+    };
+    auto keys_at = [&](int jj) {
+        return K2[(int64_t)lane_val(rg, jj < n ? jj : n - 1) * WAVE + lane];
+    };
+    uint2 k0 = keys_at(0), k1 = keys_at(1), k2 = keys_at(2), k3 = keys_at(3);
+    for (int j = 0; j < n; j += 4) {
+        step(j, k0);
+        k0 = keys_at(j + 4);
+        if (j + 1 < n) step(j + 1, k1);
+        k1 = keys_at(j + 5);
+        if (j + 2 < n) step(j + 2, k2);
+        k2 = keys_at(j + 6);
+        if (j + 3 < n) step(j + 3, k3);
+        k3 = keys_at(j + 7);
     }
     __syncthreads();
     int nch = 0;
@@ -458,7 +559,7 @@ inline unsigned grid_for(int64_t n, int threads, int cap = 65535)
 
 } // namespace
 
-size_t cap_walk_lds(int B) { return (size_t)B * CAP_NPAD + (size_t)3 * B * 4; }
+size_t cap_walk_lds(int B) { return (size_t)B * CAP_NPAD + (size_t)2 * B * 4; }
 
 // Input checks of a capacity run (every later kernel indexes with these values): clears
 // the control block and sets CapCtl::error.  init: the initial cache, nullable.
@@ -478,13 +579,13 @@ hipError_t cap_setup(CapPlan &L, int32_t *keys, int32_t *vals, int32_t *keys_alt
                      int32_t *vals_alt, int32_t *first, void *tmp, hipStream_t st)
 {
     hipError_t e;
-    hipLaunchKernelGGL(k_cap_fill, dim3(grid_for(L.K + 1, 256)), dim3(256), 0, st, L.seg_off,
-                       (int64_t)L.K + 1, 0);
+    if (L.T == 0)
+        hipLaunchKernelGGL(k_cap_fill, dim3(grid_for(L.K + 1, 256)), dim3(256), 0, st, L.seg_off,
+                           (int64_t)L.K + 1, 0);
     hipLaunchKernelGGL(k_cap_keytab, dim3(grid_for((int64_t)L.R * CAP_NPAD, 256)), dim3(256), 0, st, L);
     if (L.T > 0) {
         hipLaunchKernelGGL(k_cap_keys, dim3(grid_for(L.T, 256, 8192)), dim3(256), 0, st, L, keys,
-                           vals, L.seg_off);
-        if ((e = scan_i32_excl(L.seg_off, (int64_t)L.K + 1, tmp, st)) != hipSuccess) return e;
+                           vals);
         int bits = 1;
         while (bits < 31 && (1ll << bits) < L.K) ++bits;
         bool in_alt = false;
@@ -492,6 +593,8 @@ hipError_t cap_setup(CapPlan &L, int32_t *keys, int32_t *vals, int32_t *keys_alt
             hipSuccess)
             return e;
         const int32_t *sorted = in_alt ? vals_alt : vals;
+        hipLaunchKernelGGL(k_cap_seg_bounds, dim3(grid_for(L.T + 1, 256, 8192)), dim3(256), 0, st,
+                           L, in_alt ? keys_alt : keys);
         if ((e = hipMemcpyAsync(L.perm, sorted, (size_t)L.T * 4, hipMemcpyDeviceToDevice, st)) !=
             hipSuccess)
             return e;

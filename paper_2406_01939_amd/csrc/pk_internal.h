@@ -200,7 +200,7 @@ size_t radix_tmp_bytes(int64_t n);
 // (capacity.hip: Picard with the FO state (x, c) of Section 3, time-block processes)
 constexpr int CAP_NPAD = 128; // warehouses per row: two per lane
 constexpr int CAP_MAX_B = 255;
-constexpr int CAP_PIECE = 2048; // positions of the SKU-sorted list per entry wave
+constexpr int CAP_PIECE = 512; // positions of the SKU-sorted list per entry wave
 constexpr uint32_t CAP_NONE = 0xffffffffu;
 
 // error bits of CapCtl::error
@@ -225,10 +225,10 @@ struct CapPlan {
     int32_t *slot;       // [T] index in its block of the first order of its (block, SKU)
     int32_t *sid;        // [T] row of X for the first order of each (block, SKU)
     int32_t *piece_off;  // [K+1] first piece of each SKU
-    int32_t *piece_seg;  // [max_pieces] SKU of each piece
+    int4 *piece;         // [max_pieces] SKU, first and end sorted position, several pieces
     int32_t *pc;         // [max_pieces][CAP_NPAD] action counts, then their scan
     int32_t *H;          // [N][nblk] passing cached actions per (node, block)
-    int32_t *capE;       // [nblk][CAP_NPAD] capacity at each block's start
+    int32_t *capE;       // [N][nblk] capacity at each block's start
     uint32_t *keyT;      // [R][CAP_NPAD] (cost << 8) | w, all-ones past N
     uint8_t *X;          // [T][CAP_NPAD] stock rows of the (block, SKU) pairs
     CapCtl *ctl;
