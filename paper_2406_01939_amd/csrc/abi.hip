@@ -796,12 +796,14 @@ size_t carve_cap(char *base, const Dims &d, int B, bool picard, CapWs *w)
         x.L.seg_off = c.take<int32_t>(d.K + 1);
         x.L.slot = c.take<int32_t>(T);
         x.L.sid = c.take<int32_t>(T);
+        x.L.srow = c.take<int32_t>(T);
         x.L.piece_off = c.take<int32_t>(d.K + 1);
         x.L.piece = c.take<int4>(max_pieces);
         x.L.pc = c.take<int32_t>(max_pieces * CAP_NPAD);
         x.L.H = c.take<int32_t>((int64_t)d.N * nblk);
         x.L.capE = c.take<int32_t>(nblk * d.N);
         x.L.X = c.take<uint8_t>(std::max<int64_t>(T, 1) * CAP_NPAD);
+        x.L.P = c.take<uint8_t>(T);
         x.keys = c.take<int32_t>(T);
         x.vals = c.take<int32_t>(T);
         x.keys_alt = c.take<int32_t>(T);

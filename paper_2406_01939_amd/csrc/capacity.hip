@@ -20,9 +20,10 @@
 //     scanned along each SKU (pieces cut long SKU segments for parallelism);
 //  2. k_cap_entry: one wave per piece walks its positions of the SKU-sorted list; at
 //     the first order of each (block, SKU) it writes that block's stock row of the SKU
-//     (clamped to 255: a block walk takes at most B <= 255 units from it), and it adds
-//     each (block, SKU)'s passing actions to the block's node counts H;
-//  3. k_cap_scan: per node, exclusive scan of H over blocks -> entry capacities;
+//     (clamped to 255: a block walk takes at most B <= 255 units from it), and it marks
+//     each cached action that passes its stock test (P);
+//  3. k_cap_hist, k_cap_scan: per block, the passing actions per node (H); per node, an
+//     exclusive scan of H over blocks -> entry capacities;
 //  4. k_cap_walk: one wave per block walks its orders in time order with fresh
 //     decisions, stock rows in LDS, capacities in registers; only blocks after the first
 //     block that changed in the previous pass are walked (an earlier block's inputs did
@@ -225,11 +226,21 @@ __device__ __forceinline__ CapEnt cap_ent(const CapPlan &L, int i, int hi)
     CapEnt e = {0, LOST, -1};
     if (i < hi) {
         e.t = L.perm[i];
-        const int s = L.slot[e.t], r = L.sid[e.t];
+        e.row = L.srow[i];
         e.a = L.alpha[e.t];
-        e.row = s == e.t % L.B ? r : -1;
     }
     return e;
+}
+
+// Row of X started at each sorted position (-1 unless the position's order is the first
+// of its (block, SKU)), in sorted order so that the entry stage reads it coalesced.
+__global__ void k_cap_srow(CapPlan L)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L.T; i += stride) {
+        const int t = L.perm[i];
+        L.srow[i] = L.slot[t] == t % L.B ? L.sid[t] : -1;
+    }
 }
 
 // One wave per piece: stock rows at each (block, SKU)'s first order and passing cached
@@ -244,7 +255,7 @@ __global__ __launch_bounds__(256) void k_cap_entry(CapPlan L)
     if (p >= L.ctl->n_pieces) return;
     const int4 pd = L.piece[p]; // SKU, lo, hi, several pieces
     const int k = pd.x, lo = pd.y, hi = pd.z;
-    const int N = L.N, B = L.B, nblk = L.nblk;
+    const int N = L.N, B = L.B;
     const int frontier = L.ctl->frontier;
     const int w0 = lane, w1 = WAVE + lane;
     const int x0a = w0 < N ? L.x0[(int64_t)k * N + w0] : 0;
@@ -269,9 +280,6 @@ __global__ __launch_bounds__(256) void k_cap_entry(CapPlan L)
             const int mm = uni(__shfl(m, p0, WAVE));
             if (mm != cur) {
                 if (cur >= 0) { // close the previous (block, SKU)
-                    const int pa = min(ua, max(0, x0a - ca)), pb = min(ub, max(0, x0b - cb));
-                    if (pa > 0) atomicAdd(&L.H[(int64_t)w0 * nblk + cur], pa);
-                    if (pb > 0) atomicAdd(&L.H[(int64_t)w1 * nblk + cur], pb);
                     ca += ua;
                     cb += ub;
                     ua = ub = 0;
@@ -286,11 +294,17 @@ __global__ __launch_bounds__(256) void k_cap_entry(CapPlan L)
             }
             const bool in = valid && m == mm;
             uint64_t rem = __ballot(in && e.a >= 0);
-            while (rem) { // count the run's cached actions per node, one node at a time
+            while (rem) { // the run's cached actions, one node at a time
                 const int q = __ffsll((long long)rem) - 1;
                 const int v = uni(__shfl(e.a, q, WAVE));
                 const uint64_t mv = __ballot(in && e.a == v);
-                if (lane == (v & (WAVE - 1))) {
+                // the node's stock and the SKU's earlier actions to it, from its lane
+                const int ol = v & (WAVE - 1);
+                const int before = __builtin_amdgcn_readlane(v < WAVE ? ca + ua : cb + ub, ol);
+                const int stock = __builtin_amdgcn_readlane(v < WAVE ? x0a : x0b, ol);
+                if (in && e.a == v) // ships iff fewer than `stock` earlier actions of the SKU
+                    L.P[e.t] = before + __popcll(mv & lanemask_lt()) < stock;
+                if (lane == ol) {
                     if (v < WAVE) ua += __popcll(mv);
                     else ub += __popcll(mv);
                 }
@@ -300,15 +314,31 @@ __global__ __launch_bounds__(256) void k_cap_entry(CapPlan L)
         }
         e = nx;
     }
-    if (cur >= 0) {
-        const int pa = min(ua, max(0, x0a - ca)), pb = min(ub, max(0, x0b - cb));
-        if (pa > 0) atomicAdd(&L.H[(int64_t)w0 * nblk + cur], pa);
-        if (pb > 0) atomicAdd(&L.H[(int64_t)w1 * nblk + cur], pb);
+}
+
+// Passing cached actions per (node, block): one wave per block of orders, counts in LDS.
+__global__ __launch_bounds__(256) void k_cap_hist(CapPlan L)
+{
+    __shared__ int32_t u[4][CAP_NPAD];
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    const int m = uni(blockIdx.x * 4 + wave);
+    if (m >= L.nblk) return;
+    u[wave][lane] = 0;
+    u[wave][WAVE + lane] = 0;
+    wave_sync();
+    const int lo = m * L.B, hi = min(lo + L.B, L.T);
+    for (int t = lo + lane; t < hi; t += WAVE) {
+        const int a = L.alpha[t];
+        if (a >= 0 && L.P[t]) atomicAdd(&u[wave][a], 1);
     }
+    wave_sync();
+    const int64_t nblk = L.nblk;
+    if (lane < L.N) L.H[lane * nblk + m] = u[wave][lane];
+    if (WAVE + lane < L.N) L.H[(WAVE + lane) * nblk + m] = u[wave][WAVE + lane];
 }
 
 // Per node, exclusive scan of the passing counts over blocks: capacity at each block's
-// start.  Clears H for the next pass.
+// start.
 __global__ __launch_bounds__(256) void k_cap_scan(CapPlan L)
 {
     __shared__ int32_t part[256];
@@ -331,7 +361,6 @@ __global__ __launch_bounds__(256) void k_cap_scan(CapPlan L)
     const int c0 = L.cap0[w];
     for (int b = b0; b < b1; ++b) {
         const int v = h[b];
-        h[b] = 0;
         L.capE[(int64_t)w * nblk + b] = max(0, c0 - run);
         run += v;
     }
@@ -603,13 +632,12 @@ hipError_t cap_setup(CapPlan &L, int32_t *keys, int32_t *vals, int32_t *keys_alt
             hipSuccess)
             return e;
         if ((e = scan_i32_excl(L.sid, L.T, tmp, st)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_cap_srow, dim3(grid_for(L.T, 256, 8192)), dim3(256), 0, st, L);
     }
     hipLaunchKernelGGL(k_cap_piece_counts, dim3(grid_for((int64_t)L.K + 1, 256)), dim3(256), 0, st, L,
                        L.piece_off);
     if ((e = scan_i32_excl(L.piece_off, (int64_t)L.K + 1, tmp, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_cap_piece_fill, dim3(grid_for(L.K, 256)), dim3(256), 0, st, L);
-    hipLaunchKernelGGL(k_cap_fill, dim3(grid_for((int64_t)L.N * L.nblk, 256, 8192)), dim3(256), 0,
-                       st, L.H, (int64_t)L.N * L.nblk, 0);
     return hipGetLastError();
 }
 
@@ -622,6 +650,7 @@ hipError_t cap_pass(const CapPlan &L, bool first, hipStream_t st)
     hipLaunchKernelGGL(k_cap_piece_count, dim3(gp), dim3(256), 0, st, L);
     hipLaunchKernelGGL(k_cap_piece_scan, dim3((unsigned)((L.K + 3) / 4)), dim3(256), 0, st, L);
     hipLaunchKernelGGL(k_cap_entry, dim3(gp), dim3(256), 0, st, L);
+    hipLaunchKernelGGL(k_cap_hist, dim3((unsigned)((L.nblk + 3) / 4)), dim3(256), 0, st, L);
     hipLaunchKernelGGL(k_cap_scan, dim3(L.N), dim3(256), 0, st, L);
     hipLaunchKernelGGL(k_cap_walk, dim3(L.nblk), dim3(64), cap_walk_lds(L.B), st, L);
     return hipGetLastError();

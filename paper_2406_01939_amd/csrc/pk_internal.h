@@ -224,6 +224,7 @@ struct CapPlan {
     int32_t *seg_off;    // [K+1]
     int32_t *slot;       // [T] index in its block of the first order of its (block, SKU)
     int32_t *sid;        // [T] row of X for the first order of each (block, SKU)
+    int32_t *srow;       // [T] sorted position -> row of X it starts, or -1
     int32_t *piece_off;  // [K+1] first piece of each SKU
     int4 *piece;         // [max_pieces] SKU, first and end sorted position, several pieces
     int32_t *pc;         // [max_pieces][CAP_NPAD] action counts, then their scan
@@ -231,6 +232,7 @@ struct CapPlan {
     int32_t *capE;       // [N][nblk] capacity at each block's start
     uint32_t *keyT;      // [R][CAP_NPAD] (cost << 8) | w, all-ones past N
     uint8_t *X;          // [T][CAP_NPAD] stock rows of the (block, SKU) pairs
+    uint8_t *P;          // [T] 1 if the order's cached action passes its stock test
     CapCtl *ctl;
 };
 
