@@ -64,9 +64,9 @@ def load(path: str):
     L.orc_alg1.argtypes = [P, vp, i64, vp, i32, vp, vp, vp]
     L.orc_picard_runs.argtypes = [P, vp, vp, i32, vp, vp, vp, vp]
     L.orc_reinforce.argtypes = [P, vp, vp, vp, vp, vp]
-    L.orc_serial_cap.argtypes = [P, vp, vp, vp, vp]
-    L.orc_alg1_cap.argtypes = [P, vp, vp, i64, vp, i32, vp, vp, vp]
-    L.orc_picard_timeblocks_cap.argtypes = [P, vp, i64, vp, i32, vp, vp, vp, vp]
+    L.orc_serial_cap.argtypes = [P, vp, i32, i32, vp, vp, vp]
+    L.orc_alg1_cap.argtypes = [P, vp, i32, i32, vp, i64, vp, i32, vp, vp, vp]
+    L.orc_picard_timeblocks_cap.argtypes = [P, vp, i32, i32, i64, vp, i32, vp, vp, vp, vp]
     L.orc_mlp_scores.argtypes = [P, i32, vp, vp]
     L.orc_philox4x32_10.argtypes = [vp, vp, vp]
     L.orc_philox4x32_10.restype = None
@@ -186,21 +186,22 @@ def _cap_array(inst, cap0) -> np.ndarray:
     return cap0
 
 
-def serial_cap(inst, cap0, b: int = 0) -> dict:
-    """Serial greedy rollout of trajectory b with node capacities cap0 (unit demand)."""
+def serial_cap(inst, cap0, b: int = 0, gamma=(0, 1)) -> dict:
+    """Serial rollout of trajectory b with node capacities cap0 (unit demand); gamma =
+    (num, den): 0 for the greedy policy, else the capacity-dependent policy."""
     B = _Bound(inst, b)
     B.p.params = None
     cap0 = _cap_array(inst, cap0)
     act = np.empty(B.T, np.int32)
     fin = np.empty((inst.K, inst.N), np.int32)
     fcap = np.empty(inst.N, np.int32)
-    _check(lib().orc_serial_cap(C.byref(B.p), _ptr(cap0), _ptr(act), _ptr(fin), _ptr(fcap)),
-           "serial_cap")
+    _check(lib().orc_serial_cap(C.byref(B.p), _ptr(cap0), int(gamma[0]), int(gamma[1]),
+                                _ptr(act), _ptr(fin), _ptr(fcap)), "serial_cap")
     return dict(actions=act, final_inv=fin, final_cap=fcap)
 
 
 def alg1_cap(inst, cap0, worker: np.ndarray, n_workers: int, b: int = 0, init_cache=None,
-             max_passes: Optional[int] = None, record: bool = True) -> dict:
+             max_passes: Optional[int] = None, record: bool = True, gamma=(0, 1)) -> dict:
     """Algorithm 1 with node capacities, taken literally (tiny instances only)."""
     B = _Bound(inst, b)
     B.p.params = None
@@ -213,8 +214,9 @@ def alg1_cap(inst, cap0, worker: np.ndarray, n_workers: int, b: int = 0, init_ca
     fin = np.empty(T, np.int32)
     passes = np.zeros(1, np.int32)
     caches = np.empty((max_passes, T), np.int32) if record else None
-    rc = lib().orc_alg1_cap(C.byref(B.p), _ptr(cap0), _ptr(worker), n_workers, _ptr(init),
-                            max_passes, _ptr(fin), _ptr(passes), _ptr(caches))
+    rc = lib().orc_alg1_cap(C.byref(B.p), _ptr(cap0), int(gamma[0]), int(gamma[1]),
+                            _ptr(worker), n_workers, _ptr(init), max_passes, _ptr(fin),
+                            _ptr(passes), _ptr(caches))
     _check(rc, "alg1_cap")
     k = int(passes[0])
     return dict(actions=fin, passes=k, converged=rc == 0,
@@ -222,7 +224,8 @@ def alg1_cap(inst, cap0, worker: np.ndarray, n_workers: int, b: int = 0, init_ca
 
 
 def picard_timeblocks_cap(inst, cap0, block_len: int, b: int = 0, init_cache=None,
-                          max_passes: Optional[int] = None, record: bool = False) -> dict:
+                          max_passes: Optional[int] = None, record: bool = False,
+                          gamma=(0, 1)) -> dict:
     """Algorithm 1's passes with node capacities for the partition into time blocks of
     block_len consecutive orders (one replay per pass)."""
     B = _Bound(inst, b)
@@ -236,9 +239,9 @@ def picard_timeblocks_cap(inst, cap0, block_len: int, b: int = 0, init_cache=Non
     passes = np.zeros(1, np.int32)
     changed = np.zeros(max_passes, np.int64)
     caches = np.empty((max_passes, T), np.int32) if record else None
-    rc = lib().orc_picard_timeblocks_cap(C.byref(B.p), _ptr(cap0), block_len, _ptr(init),
-                                         max_passes, _ptr(fin), _ptr(passes), _ptr(changed),
-                                         _ptr(caches))
+    rc = lib().orc_picard_timeblocks_cap(C.byref(B.p), _ptr(cap0), int(gamma[0]),
+                                         int(gamma[1]), block_len, _ptr(init), max_passes,
+                                         _ptr(fin), _ptr(passes), _ptr(changed), _ptr(caches))
     _check(rc, "picard_timeblocks_cap")
     k = int(passes[0])
     return dict(actions=fin, passes=k, converged=rc == 0, changed=changed[:k],

@@ -587,12 +587,14 @@ int orc_mlp_scores(const orc_problem *P, int32_t r, const int32_t *x, double *s)
  * SKU i may go to node j only if c_{t,j} > 0 and x_{t,i,j} > 0; shipping it lowers
  * c_{t,j} and x_{t,i,j} by one.  The paper's transition is unit demand, so every order
  * here must have q = 1.  Policy: greedy (least cost[j][region] among nodes with both
- * capacity and stock, lowest index on ties; lost sale iff none), as in Section 3.1.
- * cap0[N] >= 0 is c_1.
+ * capacity and stock, lowest index on ties; lost sale iff none), as in Section 3.1, or
+ * the capacity-dependent policy of the appendix's ablation (greedy_cap).  cap0[N] >= 0
+ * is c_1.
  * ==================================================================================== */
-static int check_cap(const orc_problem *P, const int32_t *cap0)
+static int check_cap(const orc_problem *P, const int32_t *cap0, int32_t gnum, int32_t gden)
 {
     if (check_problem(P) || P->params) return -1;
+    if (gnum < 0 || gden < 1 || gnum > 1000 || gden > 1000) return -1;
     for (int64_t t = 0; t < P->T; ++t)
         if (P->qty[t] != 1) return -1;
     for (int w = 0; w < P->N; ++w)
@@ -600,15 +602,49 @@ static int check_cap(const orc_problem *P, const int32_t *cap0)
     return 0;
 }
 
-/* Greedy choice at state (x row of the order's SKU, capacities c). */
-static int32_t greedy_cap(const orc_problem *P, int64_t t, const int32_t *x, const int32_t *c)
+/* The policy with capacity, at state (x row of the order's SKU, capacities c).
+ * gnum = 0: greedy, the feasible node of least cost[w][region], lowest index on ties.
+ * gnum > 0: the capacity-dependent policy of the appendix's ablation, gamma = gnum/gden:
+ * node w's rank in the region's (cost, index) order, rank_r(w) in 0..N-1, is worsened by
+ * gamma (N-1) (1 - c_w / M), M the largest remaining capacity of any node, so the node
+ * with the most capacity left can rise up to gamma (N-1) places.  Compared exactly as
+ *   gden rank_r(w) M + gnum (N-1) (M - c_w)   (both sides times gden M > 0),
+ * least first, lowest index on ties; lost sale iff no node is feasible. */
+static int32_t rank_in_region(const orc_problem *P, int r, int w)
+{
+    const int R = P->R;
+    const int32_t cw = P->cost[w * R + r];
+    int32_t k = 0;
+    for (int v = 0; v < P->N; ++v) {
+        const int32_t cv = P->cost[v * R + r];
+        if (cv < cw || (cv == cw && v < w)) ++k;
+    }
+    return k;
+}
+
+static int32_t greedy_cap(const orc_problem *P, int64_t t, const int32_t *x, const int32_t *c,
+                          int32_t gnum, int32_t gden)
 {
     const int R = P->R, r = P->region[t];
-    int32_t best = LOST, best_cost = 0;
+    int32_t best = LOST;
+    if (gnum == 0) {
+        int32_t best_cost = 0;
+        for (int w = 0; w < P->N; ++w) {
+            if (x[w] <= 0 || c[w] <= 0) continue;
+            const int32_t cw = P->cost[w * R + r];
+            if (best == LOST || cw < best_cost) { best = w; best_cost = cw; }
+        }
+        return best;
+    }
+    int64_t M = 0;
+    for (int w = 0; w < P->N; ++w)
+        if (c[w] > M) M = c[w];
+    int64_t best_s = 0;
     for (int w = 0; w < P->N; ++w) {
         if (x[w] <= 0 || c[w] <= 0) continue;
-        const int32_t cw = P->cost[w * R + r];
-        if (best == LOST || cw < best_cost) { best = w; best_cost = cw; }
+        const int64_t sc = (int64_t)gden * rank_in_region(P, r, w) * M +
+                           (int64_t)gnum * (P->N - 1) * (M - c[w]);
+        if (best == LOST || sc < best_s) { best = w; best_s = sc; }
     }
     return best;
 }
@@ -622,10 +658,10 @@ static void transition_cap(int32_t *x, int32_t *c, int32_t a)
 }
 
 /* Serial rollout with capacity: the answer Picard must reach. */
-int orc_serial_cap(const orc_problem *P, const int32_t *cap0, int32_t *actions,
-                   int32_t *final_inv, int32_t *final_cap)
+int orc_serial_cap(const orc_problem *P, const int32_t *cap0, int32_t gnum, int32_t gden,
+                   int32_t *actions, int32_t *final_inv, int32_t *final_cap)
 {
-    if (check_cap(P, cap0)) return -1;
+    if (check_cap(P, cap0, gnum, gden)) return -1;
     const int N = P->N;
     int32_t *x = (int32_t *)malloc(sizeof(int32_t) * (size_t)P->K * N);
     int32_t *c = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
@@ -634,7 +670,7 @@ int orc_serial_cap(const orc_problem *P, const int32_t *cap0, int32_t *actions,
     memcpy(c, cap0, sizeof(int32_t) * (size_t)N);
     for (int64_t t = 0; t < P->T; ++t) {
         int32_t *xk = x + (int64_t)P->sku[t] * N;
-        const int32_t a = greedy_cap(P, t, xk, c);
+        const int32_t a = greedy_cap(P, t, xk, c, gnum, gden);
         transition_cap(xk, c, a);
         actions[t] = a;
     }
@@ -649,11 +685,11 @@ int orc_serial_cap(const orc_problem *P, const int32_t *cap0, int32_t *actions,
  * t = 1..T, decides its own steps and replays the others' cached actions, each
  * replaced by a lost sale when the node has no stock or no capacity left locally.
  * Arguments and return value as orc_alg1.  O(P*T*N) per pass: tiny instances only. */
-int orc_alg1_cap(const orc_problem *P, const int32_t *cap0, const int64_t *worker,
-                 int64_t n_workers, const int32_t *init_cache, int32_t max_passes,
-                 int32_t *final_cache, int32_t *passes, int32_t *caches)
+int orc_alg1_cap(const orc_problem *P, const int32_t *cap0, int32_t gnum, int32_t gden,
+                 const int64_t *worker, int64_t n_workers, const int32_t *init_cache,
+                 int32_t max_passes, int32_t *final_cache, int32_t *passes, int32_t *caches)
 {
-    if (check_cap(P, cap0) || n_workers <= 0 || max_passes <= 0) return -1;
+    if (check_cap(P, cap0, gnum, gden) || n_workers <= 0 || max_passes <= 0) return -1;
     const int N = P->N;
     const int64_t T = P->T, KN = (int64_t)P->K * N;
     for (int64_t t = 0; t < T; ++t)
@@ -674,7 +710,7 @@ int orc_alg1_cap(const orc_problem *P, const int32_t *cap0, const int64_t *worke
                 int32_t *xk = x + (int64_t)P->sku[t] * N;
                 int32_t a;
                 if (worker[t] == proc) {
-                    a = greedy_cap(P, t, xk, c);
+                    a = greedy_cap(P, t, xk, c, gnum, gden);
                     next[t] = a;
                 } else {
                     a = prev[t];
@@ -707,12 +743,12 @@ int orc_alg1_cap(const orc_problem *P, const int32_t *cap0, const int64_t *worke
  * and the capacities), after which the replay applies the block's cached actions.
  * O(T*N) per pass.  changed (nullable) receives |{t : alpha^k_t != alpha^{k-1}_t}| per
  * pass.  Other arguments and the return value as orc_alg1. */
-int orc_picard_timeblocks_cap(const orc_problem *P, const int32_t *cap0, int64_t B,
-                              const int32_t *init_cache, int32_t max_passes,
-                              int32_t *final_cache, int32_t *passes, int64_t *changed,
-                              int32_t *caches)
+int orc_picard_timeblocks_cap(const orc_problem *P, const int32_t *cap0, int32_t gnum,
+                              int32_t gden, int64_t B, const int32_t *init_cache,
+                              int32_t max_passes, int32_t *final_cache, int32_t *passes,
+                              int64_t *changed, int32_t *caches)
 {
-    if (check_cap(P, cap0) || B <= 0 || max_passes <= 0) return -1;
+    if (check_cap(P, cap0, gnum, gden) || B <= 0 || max_passes <= 0) return -1;
     const int N = P->N, K = P->K;
     const int64_t T = P->T, KN = (int64_t)K * N;
     int32_t *prev = (int32_t *)malloc(sizeof(int32_t) * (size_t)(T + 1));
@@ -744,7 +780,7 @@ int orc_picard_timeblocks_cap(const orc_problem *P, const int32_t *cap0, int64_t
                     memcpy(xk, x + s * N, sizeof(int32_t) * (size_t)N);
                     stamp[s] = m;
                 }
-                const int32_t a = greedy_cap(P, t, xk, cp);
+                const int32_t a = greedy_cap(P, t, xk, cp, gnum, gden);
                 transition_cap(xk, cp, a);
                 next[t] = a;
             }

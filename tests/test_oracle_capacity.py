@@ -256,3 +256,99 @@ def test_rejects_multi_unit(oracle):
     inst.qty[:] = 2
     with pytest.raises(ValueError):
         oracle.serial_cap(inst, np.ones(3, np.int32))
+
+
+# ---------------------------------------------------------------- capacity-dependent policy
+def _brute_gamma(inst, cap0, gamma):
+    """The appendix's capacity-dependent policy from its description, in exact rationals:
+    score_w = rank_r(w) + gamma (N-1) (1 - c_w / M), M the largest remaining capacity,
+    least score among nodes with stock and capacity, lowest index on ties."""
+    from fractions import Fraction
+    g = Fraction(*gamma)
+    N = inst.N
+    x = inst.x0[0].astype(np.int64).copy()
+    c = [int(v) for v in cap0]
+    out = []
+    for t in range(int(inst.traj_offsets[-1])):
+        k, r = int(inst.sku[t]), int(inst.region[t])
+        order = sorted(range(N), key=lambda w: (int(inst.cost[0][w, r]), w))
+        rank = {w: i for i, w in enumerate(order)}
+        M = max(c)
+        best, bs = -1, None
+        for w in range(N):
+            if x[k, w] > 0 and c[w] > 0:
+                sc = rank[w] + g * (N - 1) * (1 - Fraction(c[w], M))
+                if bs is None or sc < bs:
+                    best, bs = w, sc
+        out.append(best)
+        if best >= 0:
+            x[k, best] -= 1
+            c[best] -= 1
+    return np.array(out, np.int32)
+
+
+@pytest.mark.parametrize("gamma", [(1, 2), (1, 1), (3, 1), (7, 3)])
+@pytest.mark.parametrize("seed", range(12))
+def test_gamma_policy_brute_force(oracle, seed, gamma):
+    inst, cap0 = _tiny(seed, N=2 + seed % 5, K=1 + seed % 3, R=1 + seed % 3, T=24, inv_max=4)
+    r = oracle.serial_cap(inst, cap0, gamma=gamma)
+    assert np.array_equal(r["actions"], _brute_gamma(inst, cap0, gamma))
+    # gamma = 0 (any denominator) is the greedy policy
+    assert np.array_equal(oracle.serial_cap(inst, cap0, gamma=(0, 7))["actions"],
+                          oracle.serial_cap(inst, cap0)["actions"])
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_gamma_large_picks_most_capacity(oracle, seed):
+    """gamma -> infinity: the feasible node with the most capacity left (the appendix's
+    limiting case), ties to the better-ranked node."""
+    inst, cap0 = _tiny(seed, N=3 + seed % 4, K=2, R=2, T=20, inv_max=4)
+    r = oracle.serial_cap(inst, cap0, gamma=(1000, 1))
+    x = inst.x0[0].astype(np.int64).copy()
+    c = cap0.astype(np.int64).copy()
+    for t in range(int(inst.traj_offsets[-1])):
+        k, reg = inst.sku[t], inst.region[t]
+        feas = [w for w in range(inst.N) if x[k, w] > 0 and c[w] > 0]
+        if not feas:
+            assert r["actions"][t] == -1
+            continue
+        a = min(feas, key=lambda w: (-c[w], int(inst.cost[0][w, reg]), w))
+        # the rank term decides only among equal capacities when gamma (N-1) / M exceeds N
+        if 1000 * (inst.N - 1) > inst.N * max(c.max(), 1) * 1:
+            assert r["actions"][t] == a
+        a = r["actions"][t]
+        x[k, a] -= 1
+        c[a] -= 1
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_gamma_picard(oracle, seed):
+    """Proposition 2.1 for the capacity-dependent policy (the bound of Theorem 3.1 does not
+    apply: the policy breaks Assumption 3), and the time-block replay against the literal
+    Algorithm 1 pass by pass."""
+    inst, cap0 = _tiny(seed, N=2 + seed % 5, K=1 + seed % 3, R=1 + seed % 3, T=16, inv_max=3)
+    T = int(inst.traj_offsets[-1])
+    gamma = [(1, 2), (1, 1), (2, 1)][seed % 3]
+    ser = oracle.serial_cap(inst, cap0, gamma=gamma)["actions"]
+    rng = np.random.default_rng(seed)
+    worker = rng.integers(0, 1 + seed % 4, T)
+    r = oracle.alg1_cap(inst, cap0, worker, 1 + seed % 4, gamma=gamma)
+    assert r["converged"] and np.array_equal(r["actions"], ser) and r["passes"] <= T + 1
+    for B in (1, 3, T):
+        lit = oracle.alg1_cap(inst, cap0, oracle.time_block_workers(T, B), (T + B - 1) // B,
+                              gamma=gamma)
+        tb = oracle.picard_timeblocks_cap(inst, cap0, B, record=True, gamma=gamma)
+        assert lit["passes"] == tb["passes"]
+        assert np.array_equal(lit["caches"], tb["caches"])
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_gamma_scale_is_the_largest_capacity_of_any_node(oracle, seed):
+    """M is the largest remaining capacity over every node, with or without stock of the
+    order's SKU (scarce stock, so that the node with the most capacity often has none)."""
+    rng = np.random.default_rng(30_000 + seed)
+    inst = random_tiny(seed, N=4 + seed % 4, K=3, R=2, T=30, qmax=1, inv_max=1)
+    cap0 = rng.integers(1, 12, inst.N).astype(np.int32)
+    gamma = [(1, 1), (2, 1), (1, 2), (5, 2)][seed % 4]
+    r = oracle.serial_cap(inst, cap0, gamma=gamma)
+    assert np.array_equal(r["actions"], _brute_gamma(inst, cap0, gamma))

@@ -81,8 +81,15 @@ MUTANTS = [
      "        transition(xk, a, P->qty[t]);\n    }\n    free(x);\n    mlp_free(&m);\n    return rc;",
      "    }\n    free(x);\n    mlp_free(&m);\n    return rc;"),
     # node capacity (Section 3, state (x, c))
-    ("cap_greedy_ignores_capacity", "if (x[w] <= 0 || c[w] <= 0) continue;",
-     "if (x[w] <= 0) continue;"),
+    ("cap_greedy_ignores_capacity",
+     "if (x[w] <= 0 || c[w] <= 0) continue;\n            const int32_t cw",
+     "if (x[w] <= 0) continue;\n            const int32_t cw"),
+    ("cap_gamma_ignores_capacity_level", "(int64_t)gnum * (P->N - 1) * (M - c[w]);",
+     "(int64_t)gnum * (P->N - 1) * M;"),
+    ("cap_gamma_rank_ties_reversed", "if (cv < cw || (cv == cw && v < w)) ++k;",
+     "if (cv < cw || (cv == cw && v > w)) ++k;"),
+    ("cap_gamma_max_over_feasible_only", "        if (c[w] > M) M = c[w];",
+     "        if (c[w] > M && x[w] > 0) M = c[w];"),
     ("cap_transition_keeps_capacity", "x[a] -= 1;\n    c[a] -= 1;", "x[a] -= 1;"),
     # (a replayed action that ignores a node's exhausted capacity is not listed: it only
     # lowers that node's stock, and a node without capacity is never chosen again, so
