@@ -342,9 +342,40 @@ def main():
             _progress(f"capacity serial sweep: {dt:.3f} s")
         return res
 
+    def gamma_ablation(name="greedy_cap_n10_k100_t1e4", B=100,
+                       gammas=((0, 1), (1, 2), (1, 1), (2, 1)), reps=3):
+        """The appendix's capacity-dependent policy ablation: passes and speed-up over the
+        serial GPU sweep per gamma, on the 1e4-order capacity workload."""
+        from paper_2406_01939_amd.instances import workload_capacity
+        inst = make_instance(name)
+        cap = torch.from_numpy(workload_capacity(name)).cuda()
+        prob = api.DeviceProblem.from_instance(inst)
+        rows = []
+        for g in gammas:
+            out = api.pk_picard_simulate_capacity(prob, cap, block_len=B, gamma=g)
+            best = None
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                out = api.pk_picard_simulate_capacity(prob, cap, block_len=B, gamma=g)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                best = dt if best is None else min(best, dt)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ser = api.pk_serial_simulate_capacity(prob, cap, gamma=g)
+            torch.cuda.synchronize()
+            ds = time.perf_counter() - t0
+            rows.append({"gamma": g[0] / g[1], "passes": out["passes"], "picard_ms": 1e3 * best,
+                         "serial_ms": 1e3 * ds, "speedup_vs_serial_gpu": ds / best,
+                         "identical_actions": bool(torch.equal(out["actions"], ser["actions"]))})
+            _progress(f"gamma {g[0]}/{g[1]}: {out['passes']} passes, {1e3 * best:.2f} ms")
+        return {"workload": name, "block_len": B, "rows": rows}
+
     if args.capacity_only:
         print(json.dumps({"capacity": capacity_leg(serial=not args.no_serial,
-                                                   reps=max(1, args.steps))}))
+                                                   reps=max(1, args.steps)),
+                          "capacity_gamma": gamma_ablation()}))
         return
 
     def pg_loop(name, iters):
@@ -405,6 +436,7 @@ def main():
                           "speedup_vs_serial_gpu": lm["speedup_vs_serial_gpu"]}
     if not args.no_capacity and policy == "greedy":
         res["capacity"] = capacity_leg(serial=not args.no_serial)
+        res["capacity_gamma"] = gamma_ablation()
     if args.pg_iters > 0:
         res["policy_gradient_loop"] = pg_loop(LEARNED_WORKLOAD, args.pg_iters)
     if args.partition_sweep == "greedy":

@@ -246,7 +246,12 @@ pk_status pk_adam_step(float *params, const float *grad, float *m, float *v, int
  * Node capacity (Section 3: the FO state is (x_t, c_t); an order of SKU i may go to node
  * j only while c_{t,j} > 0 and x_{t,i,j} > 0, and shipping it lowers both by one, so
  * capacity couples the SKUs).  Greedy policy only (least cost[w][region], lowest index on
- * ties, lost sale iff no node has both stock and capacity), unit demand only (every qty
+ * ties, lost sale iff no node has both stock and capacity) when gamma_num = 0, else the
+ * capacity-dependent policy of the appendix's ablation with gamma = gamma_num / gamma_den
+ * (0 <= gamma_num <= 1000, 1 <= gamma_den <= 1000): among the nodes with stock and
+ * capacity, the least rank_r(w) + gamma (N-1) (1 - c_w / M), rank_r(w) the node's position
+ * in the region's (cost, index) order and M the largest remaining capacity of any node,
+ * compared exactly in 64-bit integers, lowest index on ties.  Unit demand only (every qty
  * must be 1: the paper's transition), one trajectory (n_traj == 1), N <= 128, costs in
  * [0, 2^24).  capacity: DEVICE [N] int32 >= 0, the capacities c_1.  Other arrays as for
  * pk_picard_simulate.  Inputs are range-checked on the device on every call
@@ -261,8 +266,9 @@ pk_status pk_capacity_workspace_size(const pk_problem *problem, const int32_t *c
  * actions [T] out; final_inv [K][N] out, nullable; final_cap [N] out, nullable.
  * Synchronous. */
 pk_status pk_serial_simulate_capacity(const pk_problem *problem, const int32_t *capacity,
-                                      void *ws, size_t ws_bytes, int32_t *actions,
-                                      int32_t *final_inv, int32_t *final_cap, void *stream);
+                                      int32_t gamma_num, int32_t gamma_den, void *ws,
+                                      size_t ws_bytes, int32_t *actions, int32_t *final_inv,
+                                      int32_t *final_cap, void *stream);
 
 /* Algorithm 1 with capacity.  The processes are blocks of block_len consecutive orders in
  * time (1..255; 0 = 128): process m owns orders [m B, (m+1) B).  init_cache [T] DEVICE,
@@ -277,6 +283,7 @@ pk_status pk_serial_simulate_capacity(const pk_problem *problem, const int32_t *
  * max_passes passes end without a repeat (actions then holds the last cache and the
  * final state is not written). */
 pk_status pk_picard_simulate_capacity(const pk_problem *problem, const int32_t *capacity,
+                                      int32_t gamma_num, int32_t gamma_den,
                                       int32_t block_len, int32_t max_passes,
                                       const int32_t *init_cache, void *ws, size_t ws_bytes,
                                       int32_t *actions, int32_t *final_inv, int32_t *final_cap,

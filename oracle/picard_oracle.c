@@ -622,8 +622,19 @@ static int32_t rank_in_region(const orc_problem *P, int r, int w)
     return k;
 }
 
+/* rank_in_region for every (region, node), once per call: [R][N]; NULL when gnum = 0. */
+static int32_t *rank_table(const orc_problem *P, int32_t gnum)
+{
+    if (gnum == 0) return NULL;
+    int32_t *rk = (int32_t *)malloc(sizeof(int32_t) * (size_t)P->R * P->N);
+    if (!rk) return NULL;
+    for (int r = 0; r < P->R; ++r)
+        for (int w = 0; w < P->N; ++w) rk[(int64_t)r * P->N + w] = rank_in_region(P, r, w);
+    return rk;
+}
+
 static int32_t greedy_cap(const orc_problem *P, int64_t t, const int32_t *x, const int32_t *c,
-                          int32_t gnum, int32_t gden)
+                          int32_t gnum, int32_t gden, const int32_t *rk)
 {
     const int R = P->R, r = P->region[t];
     int32_t best = LOST;
@@ -642,7 +653,7 @@ static int32_t greedy_cap(const orc_problem *P, int64_t t, const int32_t *x, con
     int64_t best_s = 0;
     for (int w = 0; w < P->N; ++w) {
         if (x[w] <= 0 || c[w] <= 0) continue;
-        const int64_t sc = (int64_t)gden * rank_in_region(P, r, w) * M +
+        const int64_t sc = (int64_t)gden * rk[(int64_t)r * P->N + w] * M +
                            (int64_t)gnum * (P->N - 1) * (M - c[w]);
         if (best == LOST || sc < best_s) { best = w; best_s = sc; }
     }
@@ -663,14 +674,16 @@ int orc_serial_cap(const orc_problem *P, const int32_t *cap0, int32_t gnum, int3
 {
     if (check_cap(P, cap0, gnum, gden)) return -1;
     const int N = P->N;
+    int32_t *rk = rank_table(P, gnum);
+    if (gnum && !rk) return -1;
     int32_t *x = (int32_t *)malloc(sizeof(int32_t) * (size_t)P->K * N);
     int32_t *c = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
-    if (!x || !c) { free(x); free(c); return -1; }
+    if (!x || !c) { free(x); free(c); free(rk); return -1; }
     memcpy(x, P->x0, sizeof(int32_t) * (size_t)P->K * N);
     memcpy(c, cap0, sizeof(int32_t) * (size_t)N);
     for (int64_t t = 0; t < P->T; ++t) {
         int32_t *xk = x + (int64_t)P->sku[t] * N;
-        const int32_t a = greedy_cap(P, t, xk, c, gnum, gden);
+        const int32_t a = greedy_cap(P, t, xk, c, gnum, gden, rk);
         transition_cap(xk, c, a);
         actions[t] = a;
     }
@@ -678,6 +691,7 @@ int orc_serial_cap(const orc_problem *P, const int32_t *cap0, int32_t gnum, int3
     if (final_cap) memcpy(final_cap, c, sizeof(int32_t) * (size_t)N);
     free(x);
     free(c);
+    free(rk);
     return 0;
 }
 
@@ -694,11 +708,13 @@ int orc_alg1_cap(const orc_problem *P, const int32_t *cap0, int32_t gnum, int32_
     const int64_t T = P->T, KN = (int64_t)P->K * N;
     for (int64_t t = 0; t < T; ++t)
         if (worker[t] < 0 || worker[t] >= n_workers) return -1;
+    int32_t *rk = rank_table(P, gnum);
+    if (gnum && !rk) return -1;
     int32_t *prev = (int32_t *)malloc(sizeof(int32_t) * (size_t)(T + 1));
     int32_t *next = (int32_t *)malloc(sizeof(int32_t) * (size_t)(T + 1));
     int32_t *x = (int32_t *)malloc(sizeof(int32_t) * (size_t)KN);
     int32_t *c = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
-    if (!prev || !next || !x || !c) { free(prev); free(next); free(x); free(c); return -1; }
+    if (!prev || !next || !x || !c) { free(prev); free(next); free(x); free(c); free(rk); return -1; }
     for (int64_t t = 0; t < T; ++t) prev[t] = init_cache ? init_cache[t] : LOST;
     int rc = 1;
     int32_t k;
@@ -710,7 +726,7 @@ int orc_alg1_cap(const orc_problem *P, const int32_t *cap0, int32_t gnum, int32_
                 int32_t *xk = x + (int64_t)P->sku[t] * N;
                 int32_t a;
                 if (worker[t] == proc) {
-                    a = greedy_cap(P, t, xk, c, gnum, gden);
+                    a = greedy_cap(P, t, xk, c, gnum, gden, rk);
                     next[t] = a;
                 } else {
                     a = prev[t];
@@ -729,7 +745,7 @@ int orc_alg1_cap(const orc_problem *P, const int32_t *cap0, int32_t gnum, int32_
     if (k > max_passes) k = max_passes;
     *passes = k;
     memcpy(final_cache, prev, sizeof(int32_t) * (size_t)T);
-    free(prev); free(next); free(x); free(c);
+    free(prev); free(next); free(x); free(c); free(rk);
     return rc;
 }
 
@@ -750,6 +766,8 @@ int orc_picard_timeblocks_cap(const orc_problem *P, const int32_t *cap0, int32_t
 {
     if (check_cap(P, cap0, gnum, gden) || B <= 0 || max_passes <= 0) return -1;
     const int N = P->N, K = P->K;
+    int32_t *rk = rank_table(P, gnum);
+    if (gnum && !rk) return -1;
     const int64_t T = P->T, KN = (int64_t)K * N;
     int32_t *prev = (int32_t *)malloc(sizeof(int32_t) * (size_t)(T + 1));
     int32_t *next = (int32_t *)malloc(sizeof(int32_t) * (size_t)(T + 1));
@@ -759,7 +777,7 @@ int orc_picard_timeblocks_cap(const orc_problem *P, const int32_t *cap0, int32_t
     int32_t *c = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
     int32_t *cp = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
     if (!prev || !next || !x || !xp || !stamp || !c || !cp) {
-        free(prev); free(next); free(x); free(xp); free(stamp); free(c); free(cp);
+        free(prev); free(next); free(x); free(xp); free(stamp); free(c); free(cp); free(rk);
         return -1;
     }
     for (int64_t t = 0; t < T; ++t) prev[t] = init_cache ? init_cache[t] : LOST;
@@ -780,7 +798,7 @@ int orc_picard_timeblocks_cap(const orc_problem *P, const int32_t *cap0, int32_t
                     memcpy(xk, x + s * N, sizeof(int32_t) * (size_t)N);
                     stamp[s] = m;
                 }
-                const int32_t a = greedy_cap(P, t, xk, cp, gnum, gden);
+                const int32_t a = greedy_cap(P, t, xk, cp, gnum, gden, rk);
                 transition_cap(xk, cp, a);
                 next[t] = a;
             }
@@ -802,6 +820,6 @@ int orc_picard_timeblocks_cap(const orc_problem *P, const int32_t *cap0, int32_t
     if (k > max_passes) k = max_passes;
     *passes = k;
     memcpy(final_cache, prev, sizeof(int32_t) * (size_t)T);
-    free(prev); free(next); free(x); free(xp); free(stamp); free(c); free(cp);
+    free(prev); free(next); free(x); free(xp); free(stamp); free(c); free(cp); free(rk);
     return rc;
 }

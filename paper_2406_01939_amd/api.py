@@ -92,9 +92,9 @@ def lib():
         f64 = C.c_double
         L.pk_adam_step.argtypes = [vp, vp, vp, vp, C.c_int64, i32, f64, f64, f64, f64, i32, vp]
         L.pk_capacity_workspace_size.argtypes = [P, vp, i32, C.POINTER(sz)]
-        L.pk_serial_simulate_capacity.argtypes = [P, vp, vp, sz, vp, vp, vp, vp]
-        L.pk_picard_simulate_capacity.argtypes = [P, vp, i32, i32, vp, vp, sz, vp, vp, vp,
-                                                  C.POINTER(i32), vp, vp, vp]
+        L.pk_serial_simulate_capacity.argtypes = [P, vp, i32, i32, vp, sz, vp, vp, vp, vp]
+        L.pk_picard_simulate_capacity.argtypes = [P, vp, i32, i32, i32, i32, vp, vp, sz, vp, vp,
+                                                  vp, C.POINTER(i32), vp, vp, vp]
         for f in ("pk_workspace_size", "pk_serial_simulate", "pk_picard_simulate",
                   "pk_policy_grad", "pk_autotune", "pk_policy_scores",
                   "pk_advantages_workspace_size", "pk_reinforce_advantages", "pk_adam_step",
@@ -336,8 +336,9 @@ def _cap_tensor(prob: DeviceProblem, capacity) -> torch.Tensor:
 
 
 def pk_serial_simulate_capacity(prob: DeviceProblem, capacity, want_final=True,
-                                stream=None) -> dict:
-    """Serial greedy sweep with node capacities (one order at a time on the GPU)."""
+                                gamma=(0, 1), stream=None) -> dict:
+    """Serial sweep with node capacities (one order at a time on the GPU); gamma = (num,
+    den): 0 for the greedy policy, else the capacity-dependent policy."""
     dev = prob.sku.device
     cap = _cap_tensor(prob, capacity)
     p = prob.c_problem()
@@ -345,7 +346,8 @@ def pk_serial_simulate_capacity(prob: DeviceProblem, capacity, want_final=True,
     actions = torch.empty(prob.total, dtype=torch.int32, device=dev)
     final = torch.empty_like(prob.init_inv) if want_final else None
     fcap = torch.empty(prob.N, dtype=torch.int32, device=dev) if want_final else None
-    _check(lib().pk_serial_simulate_capacity(C.byref(p), _ptr(cap), _ptr(ws), ws.numel(),
+    _check(lib().pk_serial_simulate_capacity(C.byref(p), _ptr(cap), int(gamma[0]),
+                                             int(gamma[1]), _ptr(ws), ws.numel(),
                                              _ptr(actions), _ptr(final), _ptr(fcap),
                                              _stream(stream)))
     return dict(actions=actions, final_inv=final, final_cap=fcap)
@@ -354,9 +356,10 @@ def pk_serial_simulate_capacity(prob: DeviceProblem, capacity, want_final=True,
 def pk_picard_simulate_capacity(prob: DeviceProblem, capacity, block_len: int = 0,
                                 max_passes: int = 0,
                                 init_cache: Optional[torch.Tensor] = None,
-                                want_final=True, record=False, stream=None,
+                                want_final=True, record=False, gamma=(0, 1), stream=None,
                                 raise_not_converged=True) -> dict:
-    """Algorithm 1 with node capacities; processes are blocks of consecutive orders."""
+    """Algorithm 1 with node capacities; processes are blocks of consecutive orders;
+    gamma = (num, den) as for pk_serial_simulate_capacity."""
     dev = prob.sku.device
     cap = _cap_tensor(prob, capacity)
     p = prob.c_problem()
@@ -370,7 +373,8 @@ def pk_picard_simulate_capacity(prob: DeviceProblem, capacity, block_len: int = 
     changed = np.zeros(mp, dtype=np.int64)
     passes = C.c_int32(0)
     status = lib().pk_picard_simulate_capacity(
-        C.byref(p), _ptr(cap), int(block_len), int(max_passes), _ptr(init_cache), _ptr(ws),
+        C.byref(p), _ptr(cap), int(gamma[0]), int(gamma[1]), int(block_len), int(max_passes),
+        _ptr(init_cache), _ptr(ws),
         ws.numel(), _ptr(actions), _ptr(final), _ptr(fcap), C.byref(passes),
         changed.ctypes.data, _ptr(caches), _stream(stream))
     if status != PK_OK and not (status == PK_ERR_NOT_CONVERGED and not raise_not_converged):

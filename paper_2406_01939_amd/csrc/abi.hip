@@ -774,6 +774,14 @@ pk_status check_capacity_problem(const pk_problem *pr, const int32_t *capacity, 
     return PK_OK;
 }
 
+pk_status check_gamma(int32_t num, int32_t den)
+{
+    if (num < 0 || num > 1000 || den < 1 || den > 1000)
+        return fail(PK_ERR_INVALID_ARG, "gamma must be num/den with 0 <= num <= 1000, "
+                                        "1 <= den <= 1000 (got %d/%d)", num, den);
+    return PK_OK;
+}
+
 struct CapWs {
     CapPlan L;
     int32_t *keys, *vals, *keys_alt, *vals_alt, *first, *used, *state;
@@ -1145,13 +1153,15 @@ pk_status pk_capacity_workspace_size(const pk_problem *problem, const int32_t *c
 }
 
 pk_status pk_serial_simulate_capacity(const pk_problem *problem, const int32_t *capacity,
-                                      void *ws, size_t ws_bytes, int32_t *actions,
-                                      int32_t *final_inv, int32_t *final_cap, void *stream)
+                                      int32_t gamma_num, int32_t gamma_den, void *ws,
+                                      size_t ws_bytes, int32_t *actions, int32_t *final_inv,
+                                      int32_t *final_cap, void *stream)
 {
     g_err.clear();
     Dims d;
     pk_status s = check_capacity_problem(problem, capacity, &d);
     if (s != PK_OK) return s;
+    if ((s = check_gamma(gamma_num, gamma_den)) != PK_OK) return s;
     if (d.total > 0 && !actions) return fail(PK_ERR_INVALID_ARG, "actions is NULL");
     if (!ws || ws_bytes < carve_cap(nullptr, d, DEFAULT_BLOCK_CAP, false, nullptr))
         return fail(PK_ERR_WORKSPACE, "workspace too small");
@@ -1159,6 +1169,8 @@ pk_status pk_serial_simulate_capacity(const pk_problem *problem, const int32_t *
     CapWs w;
     carve_cap(align_ws(ws), d, DEFAULT_BLOCK_CAP, false, &w);
     cap_bind(w.L, problem, capacity, actions);
+    w.L.gnum = gamma_num;
+    w.L.gden = gamma_den;
     int32_t *state = final_inv ? final_inv : w.state;
     HIP_TRY(cap_check(w.L, nullptr, st));
     CapCtl h;
@@ -1175,6 +1187,7 @@ pk_status pk_serial_simulate_capacity(const pk_problem *problem, const int32_t *
 }
 
 pk_status pk_picard_simulate_capacity(const pk_problem *problem, const int32_t *capacity,
+                                      int32_t gamma_num, int32_t gamma_den,
                                       int32_t block_len, int32_t max_passes,
                                       const int32_t *init_cache, void *ws, size_t ws_bytes,
                                       int32_t *actions, int32_t *final_inv, int32_t *final_cap,
@@ -1186,6 +1199,7 @@ pk_status pk_picard_simulate_capacity(const pk_problem *problem, const int32_t *
     pk_status s = check_capacity_problem(problem, capacity, &d);
     if (s != PK_OK) return s;
     if (d.total > 0 && !actions) return fail(PK_ERR_INVALID_ARG, "actions is NULL");
+    if ((s = check_gamma(gamma_num, gamma_den)) != PK_OK) return s;
     if (block_len < 0 || block_len > CAP_MAX_B)
         return fail(PK_ERR_INVALID_ARG, "block_len must lie in [0, %d]", CAP_MAX_B);
     if (max_passes < 0) return fail(PK_ERR_INVALID_ARG, "max_passes must be >= 0");
@@ -1198,6 +1212,8 @@ pk_status pk_picard_simulate_capacity(const pk_problem *problem, const int32_t *
     CapWs w;
     carve_cap(align_ws(ws), d, B, true, &w);
     cap_bind(w.L, problem, capacity, actions);
+    w.L.gnum = gamma_num;
+    w.L.gden = gamma_den;
     HIP_TRY(cap_check(w.L, init_cache, st));
     CapCtl h;
     HIP_TRY(hipMemcpyAsync(&h, w.L.ctl, sizeof h, hipMemcpyDeviceToHost, st));

@@ -1,6 +1,8 @@
 // Picard iteration with node capacity (Section 3: the FO state is (x_t, c_t); an order of
 // SKU i may go to node j only while c_{t,j} > 0 and x_{t,i,j} > 0; shipping one unit lowers
-// both).  Unit demand, greedy policy (least cost, lowest index on ties), one trajectory.
+// both).  Unit demand, one trajectory; the greedy policy (least cost, lowest index on ties)
+// or the capacity-dependent policy of the appendix's ablation (cap_choose).  Nothing
+// below but the walk depends on the policy.
 //
 // Capacity couples the SKUs, so processes are blocks of B consecutive orders in time.
 // Under Algorithm 1, process m replays the cached actions of every order before its block
@@ -61,6 +63,64 @@ __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v)
     return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v)
+{
+#define PK_CAP_MAX_DPP(ctrl, rmask)                                                              \
+    {                                                                                            \
+        const uint32_t o = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, ctrl, rmask, 0xf,    \
+                                                                 false);                         \
+        v = o > v ? o : v;                                                                       \
+    }
+    PK_CAP_MAX_DPP(0x111, 0xf)
+    PK_CAP_MAX_DPP(0x112, 0xf)
+    PK_CAP_MAX_DPP(0x114, 0xf)
+    PK_CAP_MAX_DPP(0x118, 0xf)
+    PK_CAP_MAX_DPP(0x142, 0xa)
+    PK_CAP_MAX_DPP(0x143, 0xc)
+#undef PK_CAP_MAX_DPP
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v)
+{
+    for (int d = WAVE / 2; d > 0; d >>= 1) {
+        const uint64_t o = __shfl_xor(v, d, WAVE);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+// The policy's choice for one order, lane l holding nodes 2l and 2l+1: f0/f1 whether each
+// has stock and capacity, c0/c1 their capacities, kc their entries of the region's row of
+// the key table.
+//  * greedy (GAMMA false): kc = (cost << 8) | w; the least key wins (lowest index on ties);
+//  * capacity-dependent (the appendix's ablation, gamma = gnum / gden): kc = the node's
+//    rank in the region's (cost, index) order; the least
+//      gden rank M + gnum (N-1) (M - c),  M = the largest capacity of any node,
+//    wins, lowest index on ties (rank + gamma (N-1)(1 - c/M) times gden M > 0, in 64 bits).
+// Returns the node or LOST (wave-uniform).
+template <bool GAMMA>
+__device__ __forceinline__ int cap_choose(uint2 kc, bool f0, bool f1, int c0, int c1, int lane,
+                                          int nm1, int gnum, int gden)
+{
+    if constexpr (!GAMMA) {
+        const uint32_t ka = f0 ? kc.x : CAP_NONE, kb = f1 ? kc.y : CAP_NONE;
+        const uint32_t best = wave_min_u32(ka < kb ? ka : kb);
+        return best == CAP_NONE ? LOST : (int)(best & 0xffu);
+    } else {
+        const uint64_t M = wave_max_u32((uint32_t)max(max(c0, c1), 0));
+        const uint64_t none = ~0ull;
+        const uint64_t ka = f0 ? ((((uint64_t)gden * kc.x * M + (uint64_t)gnum * nm1 * (M - (uint64_t)c0)) << 8) |
+                                  (uint64_t)(2 * lane))
+                               : none;
+        const uint64_t kb = f1 ? ((((uint64_t)gden * kc.y * M + (uint64_t)gnum * nm1 * (M - (uint64_t)c1)) << 8) |
+                                  (uint64_t)(2 * lane + 1))
+                               : none;
+        const uint64_t best = wave_min_u64(ka < kb ? ka : kb);
+        return best == none ? LOST : (int)(best & 0xffu);
+    }
+}
+
 __device__ __forceinline__ uint8_t clamp255(int v) { return (uint8_t)(v < 0 ? 0 : (v > 255 ? 255 : v)); }
 
 // ---------------------------------------------------------------- setup
@@ -105,14 +165,27 @@ __global__ void k_cap_seg_bounds(CapPlan L, const int32_t *skey)
     }
 }
 
-// Greedy keys, region-major: one 512-byte row per region.
+// Key table, region-major, one 512-byte row per region: greedy keys (cost << 8) | w, or
+// for the capacity-dependent policy each node's rank in the region's (cost, index) order.
 __global__ void k_cap_keytab(CapPlan L)
 {
     const int64_t n = (int64_t)L.R * CAP_NPAD;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         const int r = (int)(i / CAP_NPAD), w = (int)(i % CAP_NPAD);
-        L.keyT[i] = w < L.N ? ((uint32_t)L.cost[(int64_t)w * L.R + r] << 8) | (uint32_t)w : CAP_NONE;
+        if (w >= L.N) {
+            L.keyT[i] = CAP_NONE;
+        } else if (L.gnum == 0) {
+            L.keyT[i] = ((uint32_t)L.cost[(int64_t)w * L.R + r] << 8) | (uint32_t)w;
+        } else { // rank of w in the region's (cost, index) order
+            const int32_t cw = L.cost[(int64_t)w * L.R + r];
+            uint32_t k = 0;
+            for (int v = 0; v < L.N; ++v) {
+                const int32_t cv = L.cost[(int64_t)v * L.R + r];
+                k += cv < cw || (cv == cw && v < w);
+            }
+            L.keyT[i] = k;
+        }
     }
 }
 
@@ -372,6 +445,7 @@ __global__ __launch_bounds__(256) void k_cap_scan(CapPlan L)
 // block's regions and stock-row slots sit in registers (order j in lane j % 64 of
 // register j / 64) and are read with readlane; each region's keys are loaded four orders
 // ahead.
+template <bool GAMMA>
 __global__ __launch_bounds__(64) void k_cap_walk(CapPlan L)
 {
     extern __shared__ __align__(16) unsigned char cap_smem[];
@@ -433,10 +507,8 @@ __global__ __launch_bounds__(64) void k_cap_walk(CapPlan L)
     auto step = [&](int jj, uint2 kc) {
         const int s = lane_val(sv, jj);
         uint32_t xv = rows[s * WAVE + lane];
-        const uint32_t ka = ((xv & 0xffu) && c0 > 0) ? kc.x : CAP_NONE;
-        const uint32_t kb = ((xv >> 8) && c1 > 0) ? kc.y : CAP_NONE;
-        const uint32_t best = wave_min_u32(ka < kb ? ka : kb);
-        const int a = best == CAP_NONE ? LOST : (int)(best & 0xffu);
+        const int a = cap_choose<GAMMA>(kc, (xv & 0xffu) && c0 > 0, (xv >> 8) && c1 > 0, c0, c1,
+                                        lane, L.N - 1, L.gnum, L.gden);
         if (a >= 0 && (a >> 1) == lane) {
             if (a & 1) { --c1; xv -= 0x100u; }
             else { --c0; xv -= 1u; }
@@ -516,6 +588,7 @@ __global__ void k_cap_final_cap(const int32_t *cap0, const int32_t *used, int N,
 // order; stock rows in global memory (`state`, a copy of x0), capacities in registers.
 // The next order's stock row and keys are loaded while the current order is decided; if
 // both orders share the SKU, the loaded row is corrected by the current order's unit.
+template <bool GAMMA>
 __global__ __launch_bounds__(64) void k_cap_serial(CapPlan L, int32_t *state, int32_t *actions)
 {
     const int lane = threadIdx.x, N = L.N;
@@ -550,10 +623,8 @@ __global__ __launch_bounds__(64) void k_cap_serial(CapPlan L, int32_t *state, in
             xnb = w1 < N ? state[(int64_t)kn * N + w1] : 0;
             kn2 = K2[(int64_t)rn * WAVE + lane];
         }
-        const uint32_t ka = (xa > 0 && c0 > 0) ? kc.x : CAP_NONE;
-        const uint32_t kb = (xb > 0 && c1 > 0) ? kc.y : CAP_NONE;
-        const uint32_t best = wave_min_u32(ka < kb ? ka : kb);
-        const int a = best == CAP_NONE ? LOST : (int)(best & 0xffu);
+        const int a = cap_choose<GAMMA>(kc, xa > 0 && c0 > 0, xb > 0 && c1 > 0, c0, c1, lane,
+                                        N - 1, L.gnum, L.gden);
         if (a >= 0 && (a >> 1) == lane) {
             if (a & 1) {
                 --c1;
@@ -652,7 +723,10 @@ hipError_t cap_pass(const CapPlan &L, bool first, hipStream_t st)
     hipLaunchKernelGGL(k_cap_entry, dim3(gp), dim3(256), 0, st, L);
     hipLaunchKernelGGL(k_cap_hist, dim3((unsigned)((L.nblk + 3) / 4)), dim3(256), 0, st, L);
     hipLaunchKernelGGL(k_cap_scan, dim3(L.N), dim3(256), 0, st, L);
-    hipLaunchKernelGGL(k_cap_walk, dim3(L.nblk), dim3(64), cap_walk_lds(L.B), st, L);
+    if (L.gnum == 0)
+        hipLaunchKernelGGL(k_cap_walk<false>, dim3(L.nblk), dim3(64), cap_walk_lds(L.B), st, L);
+    else
+        hipLaunchKernelGGL(k_cap_walk<true>, dim3(L.nblk), dim3(64), cap_walk_lds(L.B), st, L);
     return hipGetLastError();
 }
 
@@ -681,7 +755,10 @@ hipError_t cap_serial_setup(CapPlan &L, hipStream_t st)
 
 hipError_t cap_serial(const CapPlan &L, int32_t *state, int32_t *actions, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_cap_serial, dim3(1), dim3(64), 0, st, L, state, actions);
+    if (L.gnum == 0)
+        hipLaunchKernelGGL(k_cap_serial<false>, dim3(1), dim3(64), 0, st, L, state, actions);
+    else
+        hipLaunchKernelGGL(k_cap_serial<true>, dim3(1), dim3(64), 0, st, L, state, actions);
     return hipGetLastError();
 }
 

@@ -217,6 +217,7 @@ struct CapCtl {
 
 struct CapPlan {
     int32_t T, N, K, R, B, nblk;
+    int32_t gnum, gden;  // policy: 0 = greedy, else capacity-dependent, gamma = gnum / gden
     int64_t max_pieces;
     const int32_t *sku, *region, *qty, *x0, *cost, *cap0;
     int32_t *alpha;      // [T] cache, time order (the caller's actions buffer)
@@ -230,7 +231,7 @@ struct CapPlan {
     int32_t *pc;         // [max_pieces][CAP_NPAD] action counts, then their scan
     int32_t *H;          // [N][nblk] passing cached actions per (node, block)
     int32_t *capE;       // [N][nblk] capacity at each block's start
-    uint32_t *keyT;      // [R][CAP_NPAD] (cost << 8) | w, all-ones past N
+    uint32_t *keyT;      // [R][CAP_NPAD] (cost << 8) | w (greedy) or rank, all-ones past N
     uint8_t *X;          // [T][CAP_NPAD] stock rows of the (block, SKU) pairs
     uint8_t *P;          // [T] 1 if the order's cached action passes its stock test
     CapCtl *ctl;

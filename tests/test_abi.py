@@ -108,7 +108,15 @@ def test_capacity_entry_points_validate_on_host():
     p2 = api.pk_problem(4, 2, 3, 2, two.ctypes.data, 1, 1, 1, 1, 1, 0)
     assert L.pk_capacity_workspace_size(C.byref(p2), 1, 0, C.byref(n)) == api.PK_ERR_UNSUPPORTED
     passes = C.c_int32(0)
-    assert L.pk_picard_simulate_capacity(C.byref(p), 1, 0, 0, None, None, 0, 1, None, None,
-                                         C.byref(passes), None, None, None) == api.PK_ERR_WORKSPACE
-    assert L.pk_serial_simulate_capacity(C.byref(p), 1, None, 0, 1, None, None,
+    assert L.pk_picard_simulate_capacity(C.byref(p), 1, 0, 1, 0, 0, None, None, 0, 1, None,
+                                         None, C.byref(passes), None, None,
                                          None) == api.PK_ERR_WORKSPACE
+    assert L.pk_serial_simulate_capacity(C.byref(p), 1, 0, 1, None, 0, 1, None, None,
+                                         None) == api.PK_ERR_WORKSPACE
+    # gamma outside its range
+    assert L.pk_serial_simulate_capacity(C.byref(p), 1, 1, 0, None, 0, 1, None, None,
+                                         None) == api.PK_ERR_INVALID_ARG
+    assert L.pk_picard_simulate_capacity(C.byref(p), 1, 1001, 1, 0, 0, None, None, 0, 1, None,
+                                         None, C.byref(passes), None, None,
+                                         None) == api.PK_ERR_INVALID_ARG
+    assert b"gamma" in L.pk_last_error()

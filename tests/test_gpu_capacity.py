@@ -41,14 +41,15 @@ def _tiny(seed, **kw):
     return inst, cap0
 
 
-def _check_against_oracle(api, oracle, inst, cap0, B, init=None, record=True):
+def _check_against_oracle(api, oracle, inst, cap0, B, init=None, record=True, gamma=(0, 1)):
     T = int(inst.traj_offsets[-1])
     prob = api.DeviceProblem.from_instance(inst)
-    want = oracle.serial_cap(inst, cap0)
-    ref = oracle.picard_timeblocks_cap(inst, cap0, B, init_cache=init, record=record)
+    want = oracle.serial_cap(inst, cap0, gamma=gamma)
+    ref = oracle.picard_timeblocks_cap(inst, cap0, B, init_cache=init, record=record,
+                                       gamma=gamma)
     init_dev = None if init is None else torch.from_numpy(init).cuda()
     out = api.pk_picard_simulate_capacity(prob, cap0, block_len=B, init_cache=init_dev,
-                                          record=record)
+                                          record=record, gamma=gamma)
     np.testing.assert_array_equal(out["actions"].cpu().numpy(), want["actions"])
     np.testing.assert_array_equal(out["final_inv"].cpu().numpy()[0], want["final_inv"])
     np.testing.assert_array_equal(out["final_cap"].cpu().numpy(), want["final_cap"])
@@ -56,7 +57,7 @@ def _check_against_oracle(api, oracle, inst, cap0, B, init=None, record=True):
     np.testing.assert_array_equal(out["changed"], ref["changed"])
     if record:
         np.testing.assert_array_equal(out["caches"].cpu().numpy(), ref["caches"])
-    ser = api.pk_serial_simulate_capacity(prob, cap0)
+    ser = api.pk_serial_simulate_capacity(prob, cap0, gamma=gamma)
     np.testing.assert_array_equal(ser["actions"].cpu().numpy(), want["actions"])
     np.testing.assert_array_equal(ser["final_inv"].cpu().numpy()[0], want["final_inv"])
     np.testing.assert_array_equal(ser["final_cap"].cpu().numpy(), want["final_cap"])
@@ -150,3 +151,27 @@ def test_full_size(api, oracle):
     _say(f"  passes gpu {out['passes']} oracle {ref['passes']}")
     assert out["passes"] == ref["passes"]
     np.testing.assert_array_equal(out["changed"], ref["changed"])
+
+
+@pytest.mark.parametrize("gamma", [(1, 2), (1, 1), (1000, 1)])
+@pytest.mark.parametrize("B", [1, 5, 64])
+@pytest.mark.parametrize("seed", range(3))
+def test_gamma_tiny(api, oracle, seed, B, gamma):
+    """The capacity-dependent policy (the appendix's ablation), every pass."""
+    inst, cap0 = _tiny(seed + 80, N=2 + seed % 5, K=1 + seed % 3, R=1 + seed % 3, T=50,
+                       inv_max=3)
+    _say(f"capacity gamma={gamma} seed={seed} B={B}")
+    _check_against_oracle(api, oracle, inst, cap0, B, gamma=gamma)
+
+
+@pytest.mark.parametrize("gamma", [(1, 2), (1, 1)])
+def test_gamma_workloads(api, oracle, gamma):
+    """gamma 0.5 and 1 on the 1e4-order workload (every pass) and on N=128, 5003 orders."""
+    inst = make_instance("greedy_cap_n10_k100_t1e4")
+    _say(f"capacity gamma={gamma} workload n10 k100 t1e4 B=100")
+    out = _check_against_oracle(api, oracle, inst, workload_capacity("greedy_cap_n10_k100_t1e4"),
+                                100, gamma=gamma)
+    _say(f"  passes {out['passes']}")
+    wide = make_instance("greedy_cap_n10_k100_t1e4", N=128, K=3, R=7, T=5003)
+    _say(f"capacity gamma={gamma} wide N=128 T=5003 B=97")
+    _check_against_oracle(api, oracle, wide, capacity(wide.N, 5003, 0.5), 97, gamma=gamma)
