@@ -812,6 +812,7 @@ size_t carve_cap(char *base, const Dims &d, int B, bool picard, CapWs *w)
         x.L.capE = c.take<int32_t>(nblk * d.N);
         x.L.X = c.take<uint8_t>(std::max<int64_t>(T, 1) * CAP_NPAD);
         x.L.P = c.take<uint8_t>(T);
+        x.L.skuchg = c.take<int32_t>(d.K);
         x.keys = c.take<int32_t>(T);
         x.vals = c.take<int32_t>(T);
         x.keys_alt = c.take<int32_t>(T);

@@ -234,6 +234,15 @@ __global__ void k_cap_piece_fill(CapPlan L)
 }
 
 // ---------------------------------------------------------------- one pass
+// A SKU's stock rows, pass flags and piece counts depend on its own cached actions only:
+// after pass 1 they are rebuilt only for SKUs with an order whose action changed in the
+// previous pass (the others keep last pass's values, which are those of their unchanged
+// actions; frontier blocks only ever move forward, so no row they need was skipped).
+__device__ __forceinline__ bool cap_sku_stale(const CapPlan &L, int k, int pass)
+{
+    return pass == 1 || L.skuchg[k] == pass - 1;
+}
+
 // Cached action counts per piece of the SKUs with more than one piece.
 __global__ __launch_bounds__(256) void k_cap_piece_count(CapPlan L)
 {
@@ -243,7 +252,7 @@ __global__ __launch_bounds__(256) void k_cap_piece_count(CapPlan L)
     if (p >= L.ctl->n_pieces) return;
     const int4 pd = L.piece[p]; // SKU, lo, hi, several pieces
     const int lo = pd.y, hi = pd.z;
-    if (!pd.w) return;
+    if (!pd.w || !cap_sku_stale(L, pd.x, L.ctl->pass)) return;
     u[wave][lane] = 0;
     u[wave][WAVE + lane] = 0;
     wave_sync();
@@ -264,7 +273,7 @@ __global__ __launch_bounds__(256) void k_cap_piece_scan(CapPlan L)
     const int k = uni(blockIdx.x * 4 + wave);
     if (k >= L.K) return;
     const int p0 = L.piece_off[k], p1 = L.piece_off[k + 1];
-    if (p1 - p0 < 2) return;
+    if (p1 - p0 < 2 || !cap_sku_stale(L, k, L.ctl->pass)) return;
     int run0 = 0, run1 = 0;
     constexpr int U = 8; // rows loaded together
     for (int pb = p0; pb < p1; pb += U) {
@@ -328,6 +337,7 @@ __global__ __launch_bounds__(256) void k_cap_entry(CapPlan L)
     if (p >= L.ctl->n_pieces) return;
     const int4 pd = L.piece[p]; // SKU, lo, hi, several pieces
     const int k = pd.x, lo = pd.y, hi = pd.z;
+    if (!cap_sku_stale(L, k, L.ctl->pass)) return;
     const int N = L.N, B = L.B;
     const int frontier = L.ctl->frontier;
     const int w0 = lane, w1 = WAVE + lane;
@@ -532,9 +542,13 @@ __global__ __launch_bounds__(64) void k_cap_walk(CapPlan L)
     }
     __syncthreads();
     int nch = 0;
+    const int pass = ctl->pass;
     for (int j = lane; j < n; j += WAVE) {
         const int a = out[j];
-        nch += a != L.alpha[lo + j];
+        if (a != L.alpha[lo + j]) {
+            ++nch;
+            L.skuchg[L.sku[lo + j]] = pass;
+        }
         L.alpha[lo + j] = a;
     }
     nch = wave_sum(nch);
@@ -547,6 +561,7 @@ __global__ __launch_bounds__(64) void k_cap_walk(CapPlan L)
 __global__ void k_cap_pass_reset(CapCtl *ctl, int first)
 {
     if (threadIdx.x == 0) {
+        ctl->pass = first ? 1 : ctl->pass + 1;
         ctl->frontier = first ? -1 : (ctl->first_blk == INT_MAX ? INT_MAX : ctl->first_blk);
         ctl->changed = 0;
         ctl->first_blk = INT_MAX;

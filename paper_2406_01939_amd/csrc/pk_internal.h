@@ -209,6 +209,7 @@ constexpr int32_t CAP_ERR_QTY = 1, CAP_ERR_SKU = 2, CAP_ERR_REGION = 4, CAP_ERR_
 
 struct CapCtl {
     int32_t error;
+    int32_t pass;      // current pass, from 1
     int32_t changed;   // orders whose action changed in the current pass
     int32_t first_blk; // first block with a change in the current pass
     int32_t frontier;  // blocks <= frontier are not walked in the current pass
@@ -234,6 +235,7 @@ struct CapPlan {
     uint32_t *keyT;      // [R][CAP_NPAD] (cost << 8) | w (greedy) or rank, all-ones past N
     uint8_t *X;          // [T][CAP_NPAD] stock rows of the (block, SKU) pairs
     uint8_t *P;          // [T] 1 if the order's cached action passes its stock test
+    int32_t *skuchg;     // [K] last pass in which an order of the SKU changed its action
     CapCtl *ctl;
 };
 
