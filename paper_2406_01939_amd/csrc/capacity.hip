@@ -248,32 +248,34 @@ __global__ __launch_bounds__(256) void k_cap_piece_count(CapPlan L)
 {
     __shared__ int32_t u[4][CAP_NPAD];
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-    const int p = uni(blockIdx.x * 4 + wave);
-    if (p >= L.ctl->n_pieces) return;
-    const int4 pd = L.piece[p]; // SKU, lo, hi, several pieces
-    const int lo = pd.y, hi = pd.z;
-    if (!pd.w || !cap_sku_stale(L, pd.x, L.ctl->pass)) return;
-    u[wave][lane] = 0;
-    u[wave][WAVE + lane] = 0;
-    wave_sync();
-    for (int i = lo + lane; i < hi; i += WAVE) {
-        const int a = L.alpha[L.perm[i]];
-        if (a >= 0) atomicAdd(&u[wave][a], 1);
+    const int n_pieces = L.ctl->n_pieces, pass = L.ctl->pass;
+    for (int p = uni(blockIdx.x * 4 + wave); p < n_pieces; p += gridDim.x * 4) {
+        const int4 pd = L.piece[p]; // SKU, lo, hi, several pieces
+        const int lo = pd.y, hi = pd.z;
+        if (!pd.w || !cap_sku_stale(L, pd.x, pass)) continue;
+        u[wave][lane] = 0;
+        u[wave][WAVE + lane] = 0;
+        wave_sync();
+        for (int i = lo + lane; i < hi; i += WAVE) {
+            const int a = L.alpha[L.perm[i]];
+            if (a >= 0) atomicAdd(&u[wave][a], 1);
+        }
+        wave_sync();
+        int32_t *dst = L.pc + (int64_t)p * CAP_NPAD;
+        dst[lane] = u[wave][lane];
+        dst[WAVE + lane] = u[wave][WAVE + lane];
+        wave_sync();
     }
-    wave_sync();
-    int32_t *dst = L.pc + (int64_t)p * CAP_NPAD;
-    dst[lane] = u[wave][lane];
-    dst[WAVE + lane] = u[wave][WAVE + lane];
 }
 
 // Exclusive scan of the piece counts along each SKU with more than one piece.
 __global__ __launch_bounds__(256) void k_cap_piece_scan(CapPlan L)
 {
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-    const int k = uni(blockIdx.x * 4 + wave);
-    if (k >= L.K) return;
+    const int pass = L.ctl->pass;
+    for (int k = uni(blockIdx.x * 4 + wave); k < L.K; k += gridDim.x * 4) {
     const int p0 = L.piece_off[k], p1 = L.piece_off[k + 1];
-    if (p1 - p0 < 2 || !cap_sku_stale(L, k, L.ctl->pass)) return;
+    if (p1 - p0 < 2 || !cap_sku_stale(L, k, pass)) continue;
     int run0 = 0, run1 = 0;
     constexpr int U = 8; // rows loaded together
     for (int pb = p0; pb < p1; pb += U) {
@@ -294,6 +296,7 @@ __global__ __launch_bounds__(256) void k_cap_piece_scan(CapPlan L)
                 run1 += v1[q];
             }
         }
+    }
     }
 }
 
@@ -325,21 +328,34 @@ __global__ void k_cap_srow(CapPlan L)
     }
 }
 
-// One wave per piece: stock rows at each (block, SKU)'s first order and passing cached
-// actions per (node, block).  Lane l holds nodes l and 64 + l: their stock, the cached
-// actions of the SKU before the current position (ca, cb) and within the current
-// (block, SKU) (ua, ub), all in registers.  Positions come 64 at a time, the next chunk
-// loaded while the current one is counted.
+// One wave per piece: stock rows at each (block, SKU)'s first order and the pass flag of
+// every cached action.  Lane l holds nodes l and 64 + l: their stock and the SKU's cached
+// actions to them before the current chunk (ca, cb), in registers.  Positions come 64 at
+// a time (the next chunk loaded while the current one is used); per chunk, each node's
+// lanes form a 64-bit mask (one ballot per distinct node in the chunk), and every count
+// the chunk needs is a popcount of a mask below a lane:
+//  * the action of lane i to node a is the SKU's (c_a + popc(mask_a below i))-th to a and
+//    ships iff that is below the SKU's initial stock at a (the clamp);
+//  * the stock row starting at lane i is max(0, x0 - c - popc(mask below i)) per node.
+__device__ __forceinline__ void cap_entry_piece(const CapPlan &L, int p, int lane, int pass,
+                                                int frontier);
+
 __global__ __launch_bounds__(256) void k_cap_entry(CapPlan L)
 {
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-    const int p = uni(blockIdx.x * 4 + wave);
-    if (p >= L.ctl->n_pieces) return;
+    const int n_pieces = L.ctl->n_pieces, pass = L.ctl->pass;
+    const int frontier = L.ctl->frontier;
+    for (int p = uni(blockIdx.x * 4 + wave); p < n_pieces; p += gridDim.x * 4)
+        cap_entry_piece(L, p, lane, pass, frontier);
+}
+
+__device__ __forceinline__ void cap_entry_piece(const CapPlan &L, int p, int lane, int pass,
+                                                int frontier)
+{
     const int4 pd = L.piece[p]; // SKU, lo, hi, several pieces
     const int k = pd.x, lo = pd.y, hi = pd.z;
-    if (!cap_sku_stale(L, k, L.ctl->pass)) return;
+    if (!cap_sku_stale(L, k, pass)) return;
     const int N = L.N, B = L.B;
-    const int frontier = L.ctl->frontier;
     const int w0 = lane, w1 = WAVE + lane;
     const int x0a = w0 < N ? L.x0[(int64_t)k * N + w0] : 0;
     const int x0b = w1 < N ? L.x0[(int64_t)k * N + w1] : 0;
@@ -349,52 +365,49 @@ __global__ __launch_bounds__(256) void k_cap_entry(CapPlan L)
         ca = row[w0];
         cb = row[w1];
     }
-    int ua = 0, ub = 0;
-    int cur = -1; // block of the (block, SKU) being counted
+    const uint64_t below = lanemask_lt();
     CapEnt e = cap_ent(L, lo + lane, hi);
     for (int base = lo; base < hi; base += WAVE) {
         const CapEnt nx = cap_ent(L, base + WAVE + lane, hi);
         const bool valid = base + lane < hi;
-        const int m = valid ? e.t / B : INT_MAX;
-        const uint64_t vmask = __ballot(valid);
-        uint64_t done = 0;
-        while (done != vmask) { // runs of equal block, in lane order
-            const int p0 = __ffsll((long long)(vmask & ~done)) - 1;
-            const int mm = uni(__shfl(m, p0, WAVE));
-            if (mm != cur) {
-                if (cur >= 0) { // close the previous (block, SKU)
-                    ca += ua;
-                    cb += ub;
-                    ua = ub = 0;
-                }
-                cur = mm;
-                const int row = uni(__shfl(e.row, p0, WAVE));
-                if (row >= 0 && mm > frontier) { // the block's stock row of this SKU
-                    uint8_t *xr = L.X + (int64_t)row * CAP_NPAD;
-                    xr[w0] = clamp255(x0a - ca);
-                    xr[w1] = clamp255(x0b - cb);
-                }
+        const bool act = valid && e.a >= 0;
+        // each node's lanes in this chunk
+        uint64_t m0 = 0, m1 = 0;
+        uint64_t rem = __ballot(act);
+        while (rem) {
+            const int q = __ffsll((long long)rem) - 1;
+            const int v = uni(__shfl(e.a, q, WAVE));
+            const uint64_t mv = __ballot(act && e.a == v);
+            if (lane == (v & (WAVE - 1))) {
+                if (v < WAVE) m0 = mv;
+                else m1 = mv;
             }
-            const bool in = valid && m == mm;
-            uint64_t rem = __ballot(in && e.a >= 0);
-            while (rem) { // the run's cached actions, one node at a time
-                const int q = __ffsll((long long)rem) - 1;
-                const int v = uni(__shfl(e.a, q, WAVE));
-                const uint64_t mv = __ballot(in && e.a == v);
-                // the node's stock and the SKU's earlier actions to it, from its lane
-                const int ol = v & (WAVE - 1);
-                const int before = __builtin_amdgcn_readlane(v < WAVE ? ca + ua : cb + ub, ol);
-                const int stock = __builtin_amdgcn_readlane(v < WAVE ? x0a : x0b, ol);
-                if (in && e.a == v) // ships iff fewer than `stock` earlier actions of the SKU
-                    L.P[e.t] = before + __popcll(mv & lanemask_lt()) < stock;
-                if (lane == ol) {
-                    if (v < WAVE) ua += __popcll(mv);
-                    else ub += __popcll(mv);
-                }
-                rem &= ~mv;
-            }
-            done |= __ballot(in);
+            rem &= ~mv;
         }
+        // pass flags: the owner lane of each action's node supplies its mask, count, stock
+        // (every lane takes part in every shuffle: a lane reads only from active lanes)
+        const int ol = act ? (e.a & (WAVE - 1)) : 0;
+        const bool hiw = e.a >= WAVE;
+        const uint64_t ma0 = __shfl(m0, ol, WAVE), ma1 = __shfl(m1, ol, WAVE);
+        const int cn0 = __shfl(ca, ol, WAVE), cn1 = __shfl(cb, ol, WAVE);
+        const int st0 = __shfl(x0a, ol, WAVE), st1 = __shfl(x0b, ol, WAVE);
+        const uint64_t ma = hiw ? ma1 : ma0;
+        const int cnt = hiw ? cn1 : cn0, stock = hiw ? st1 : st0;
+        if (act) L.P[e.t] = cnt + __popcll(ma & below) < stock;
+        // stock rows of the (block, SKU)s that start in this chunk (walked blocks only)
+        const bool starts = valid && e.row >= 0 && e.t / B > frontier;
+        uint64_t rs = __ballot(starts);
+        while (rs) {
+            const int i = __ffsll((long long)rs) - 1;
+            const int row = uni(__shfl(e.row, i, WAVE));
+            const uint64_t bi = (1ull << i) - 1;
+            uint8_t *xr = L.X + (int64_t)row * CAP_NPAD;
+            xr[w0] = clamp255(x0a - ca - __popcll(m0 & bi));
+            xr[w1] = clamp255(x0b - cb - __popcll(m1 & bi));
+            rs &= rs - 1;
+        }
+        ca += __popcll(m0);
+        cb += __popcll(m1);
         e = nx;
     }
 }
@@ -732,9 +745,14 @@ hipError_t cap_pass(const CapPlan &L, bool first, hipStream_t st)
 {
     hipLaunchKernelGGL(k_cap_pass_reset, dim3(1), dim3(64), 0, st, L.ctl, first ? 1 : 0);
     if (L.T == 0) return hipGetLastError();
-    const unsigned gp = (unsigned)((L.max_pieces + 3) / 4);
+    // grid-stride launches: about eight 4-wave workgroups per CU loop over the pieces
+    // (most pieces are a rare SKU's few orders; one workgroup each would make the launch
+    // bound by workgroup dispatch)
+    const unsigned cap_wg = 8 * 256;
+    const unsigned gp = (unsigned)std::min<int64_t>((L.max_pieces + 3) / 4, cap_wg);
+    const unsigned gk = (unsigned)std::min<int64_t>((L.K + 3) / 4, cap_wg);
     hipLaunchKernelGGL(k_cap_piece_count, dim3(gp), dim3(256), 0, st, L);
-    hipLaunchKernelGGL(k_cap_piece_scan, dim3((unsigned)((L.K + 3) / 4)), dim3(256), 0, st, L);
+    hipLaunchKernelGGL(k_cap_piece_scan, dim3(gk), dim3(256), 0, st, L);
     hipLaunchKernelGGL(k_cap_entry, dim3(gp), dim3(256), 0, st, L);
     hipLaunchKernelGGL(k_cap_hist, dim3((unsigned)((L.nblk + 3) / 4)), dim3(256), 0, st, L);
     hipLaunchKernelGGL(k_cap_scan, dim3(L.N), dim3(256), 0, st, L);
