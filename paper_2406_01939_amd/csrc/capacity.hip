@@ -20,10 +20,11 @@
 // The pass:
 //  1. k_cap_piece_count / k_cap_piece_scan: cached action counts per (SKU piece, node),
 //     scanned along each SKU (pieces cut long SKU segments for parallelism);
-//  2. k_cap_entry: one wave per piece walks its positions of the SKU-sorted list; at
-//     the first order of each (block, SKU) it writes that block's stock row of the SKU
-//     (clamped to 255: a block walk takes at most B <= 255 units from it), and it marks
-//     each cached action that passes its stock test (P);
+//  2. k_cap_entry: one wave per piece takes its positions of the SKU-sorted list 64 at
+//     a time, with one lane mask per node; at the first order of each (block, SKU) it
+//     writes that block's stock row of the SKU (clamped to 255: a block walk takes at most
+//     B <= 255 units from it), and it marks each cached action that passes its stock test
+//     (P); after pass 1 only SKUs with a changed order are revisited (cap_sku_stale);
 //  3. k_cap_hist, k_cap_scan: per block, the passing actions per node (H); per node, an
 //     exclusive scan of H over blocks -> entry capacities;
 //  4. k_cap_walk: one wave per block walks its orders in time order with fresh
