@@ -813,6 +813,7 @@ size_t carve_cap(char *base, const Dims &d, int B, bool picard, CapWs *w)
         x.L.X = c.take<uint8_t>(std::max<int64_t>(T, 1) * CAP_NPAD);
         x.L.P = c.take<uint8_t>(T);
         x.L.skuchg = c.take<int32_t>(d.K);
+        x.L.chg = c.take<int32_t>(CAP_GROUP);
         x.keys = c.take<int32_t>(T);
         x.vals = c.take<int32_t>(T);
         x.keys_alt = c.take<int32_t>(T);
@@ -1227,23 +1228,31 @@ pk_status pk_picard_simulate_capacity(const pk_problem *problem, const int32_t *
         else
             HIP_TRY(hipMemsetAsync(actions, 0xff, (size_t)T * 4, st)); // all lost sales (-1)
     }
-    int32_t k = 0;
-    bool converged = false;
-    for (k = 1; k <= mp; ++k) {
-        HIP_TRY(cap_pass(w.L, k == 1, st));
-        if (caches && T > 0)
-            HIP_TRY(hipMemcpyAsync(caches + (int64_t)(k - 1) * T, actions, (size_t)T * 4,
-                                   hipMemcpyDeviceToDevice, st));
-        HIP_TRY(hipMemcpyAsync(&h, w.L.ctl, sizeof h, hipMemcpyDeviceToHost, st));
+    // passes go out CAP_GROUP at a time; the host then reads their change counts. A pass
+    // after the first one without change is a no-op (nothing lies past its restart point
+    // and no SKU changed), so the passes run past convergence leave the result as it is.
+    int32_t done_at = 0;
+    int32_t cg[CAP_GROUP];
+    for (int32_t k0 = 1; k0 <= mp && !done_at; k0 += CAP_GROUP) {
+        const int32_t kn = std::min<int32_t>(CAP_GROUP, mp - k0 + 1);
+        for (int32_t j = 0; j < kn; ++j) {
+            const int32_t k = k0 + j;
+            HIP_TRY(cap_pass(w.L, k == 1, st));
+            if (caches && T > 0)
+                HIP_TRY(hipMemcpyAsync(caches + (int64_t)(k - 1) * T, actions, (size_t)T * 4,
+                                       hipMemcpyDeviceToDevice, st));
+        }
+        HIP_TRY(hipMemcpyAsync(cg, w.L.chg, sizeof cg, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
-        if (changed) changed[k - 1] = h.changed;
-        if (h.changed == 0) {
-            converged = true;
-            break;
+        for (int32_t j = 0; j < kn && !done_at; ++j) {
+            const int32_t k = k0 + j;
+            const int32_t c = cg[(k - 1) % CAP_GROUP];
+            if (changed) changed[k - 1] = c;
+            if (c == 0) done_at = k;
         }
     }
-    if (k > mp) k = mp;
-    if (passes) *passes = k;
+    const bool converged = done_at > 0;
+    if (passes) *passes = converged ? done_at : mp;
     if (!converged) return fail(PK_ERR_NOT_CONVERGED, "no fixed point after %d passes", mp);
     HIP_TRY(cap_finish(w.L, final_inv, final_cap, w.used, st));
     HIP_TRY(hipStreamSynchronize(st));

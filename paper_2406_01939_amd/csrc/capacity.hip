@@ -567,18 +567,23 @@ __global__ __launch_bounds__(64) void k_cap_walk(CapPlan L)
     }
     nch = wave_sum(nch);
     if (lane == 0 && nch > 0) {
-        atomicAdd(&ctl->changed, nch);
+        atomicAdd(&L.chg[(pass - 1) % CAP_GROUP], nch);
         atomicMin(&ctl->first_blk, m);
     }
 }
 
-__global__ void k_cap_pass_reset(CapCtl *ctl, int first)
+// Starts a pass: its number, its restart point (the previous pass's first changed block;
+// INT_MAX after a pass without change, which makes the pass a no-op) and its change count
+// (slot (pass - 1) % CAP_GROUP of chg: the host reads a group of passes at once).
+__global__ void k_cap_pass_reset(CapPlan L, int first)
 {
     if (threadIdx.x == 0) {
-        ctl->pass = first ? 1 : ctl->pass + 1;
-        ctl->frontier = first ? -1 : (ctl->first_blk == INT_MAX ? INT_MAX : ctl->first_blk);
-        ctl->changed = 0;
+        CapCtl *ctl = L.ctl;
+        const int pass = first ? 1 : ctl->pass + 1;
+        ctl->pass = pass;
+        ctl->frontier = first ? -1 : ctl->first_blk;
         ctl->first_blk = INT_MAX;
+        L.chg[(pass - 1) % CAP_GROUP] = 0;
     }
 }
 
@@ -744,7 +749,7 @@ hipError_t cap_setup(CapPlan &L, int32_t *keys, int32_t *vals, int32_t *keys_alt
 // One Picard pass (launches only; the caller reads ctl afterwards).
 hipError_t cap_pass(const CapPlan &L, bool first, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_cap_pass_reset, dim3(1), dim3(64), 0, st, L.ctl, first ? 1 : 0);
+    hipLaunchKernelGGL(k_cap_pass_reset, dim3(1), dim3(64), 0, st, L, first ? 1 : 0);
     if (L.T == 0) return hipGetLastError();
     // grid-stride launches: about eight 4-wave workgroups per CU loop over the pieces
     // (most pieces are a rare SKU's few orders; one workgroup each would make the launch

@@ -201,6 +201,7 @@ size_t radix_tmp_bytes(int64_t n);
 constexpr int CAP_NPAD = 128; // warehouses per row: two per lane
 constexpr int CAP_MAX_B = 255;
 constexpr int CAP_PIECE = 512; // positions of the SKU-sorted list per entry wave
+constexpr int CAP_GROUP = 4;   // passes launched per host check of the change counts
 constexpr uint32_t CAP_NONE = 0xffffffffu;
 
 // error bits of CapCtl::error
@@ -210,7 +211,6 @@ constexpr int32_t CAP_ERR_QTY = 1, CAP_ERR_SKU = 2, CAP_ERR_REGION = 4, CAP_ERR_
 struct CapCtl {
     int32_t error;
     int32_t pass;      // current pass, from 1
-    int32_t changed;   // orders whose action changed in the current pass
     int32_t first_blk; // first block with a change in the current pass
     int32_t frontier;  // blocks <= frontier are not walked in the current pass
     int32_t n_pieces;
@@ -236,6 +236,7 @@ struct CapPlan {
     uint8_t *X;          // [T][CAP_NPAD] stock rows of the (block, SKU) pairs
     uint8_t *P;          // [T] 1 if the order's cached action passes its stock test
     int32_t *skuchg;     // [K] last pass in which an order of the SKU changed its action
+    int32_t *chg;        // [CAP_GROUP] orders whose action changed, per pass of a group
     CapCtl *ctl;
 };
 
