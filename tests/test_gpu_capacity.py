@@ -175,3 +175,24 @@ def test_gamma_workloads(api, oracle, gamma):
     wide = make_instance("greedy_cap_n10_k100_t1e4", N=128, K=3, R=7, T=5003)
     _say(f"capacity gamma={gamma} wide N=128 T=5003 B=97")
     _check_against_oracle(api, oracle, wide, capacity(wide.N, 5003, 0.5), 97, gamma=gamma)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_pass_limit(api, oracle, seed):
+    """Passes go out in groups: a limit one short of convergence returns PK_ERR_NOT_CONVERGED
+    with the oracle's cache after that many passes; a limit at convergence returns the
+    fixed point with the oracle's pass count."""
+    inst, cap0 = _tiny(seed + 200, N=5, K=3, R=3, T=80, inv_max=4)
+    ref = oracle.picard_timeblocks_cap(inst, cap0, 3, record=True)
+    k = ref["passes"]
+    assert k >= 3, "instance too easy for this test"
+    prob = api.DeviceProblem.from_instance(inst)
+    _say(f"capacity pass limit seed={seed} passes={k}")
+    out = api.pk_picard_simulate_capacity(prob, cap0, block_len=3, max_passes=k)
+    assert out["status"] == api.PK_OK and out["passes"] == k
+    np.testing.assert_array_equal(out["changed"], ref["changed"])
+    for lim in (k - 1, k - 2):
+        out = api.pk_picard_simulate_capacity(prob, cap0, block_len=3, max_passes=lim,
+                                              raise_not_converged=False)
+        assert out["status"] == api.PK_ERR_NOT_CONVERGED and out["passes"] == lim
+        np.testing.assert_array_equal(out["actions"].cpu().numpy(), ref["caches"][lim - 1])
