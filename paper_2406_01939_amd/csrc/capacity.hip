@@ -269,35 +269,72 @@ __global__ __launch_bounds__(256) void k_cap_piece_count(CapPlan L)
     }
 }
 
-// Exclusive scan of the piece counts along each SKU with more than one piece.
-__global__ __launch_bounds__(256) void k_cap_piece_scan(CapPlan L)
+// Exclusive scan of the piece counts along each SKU with more than one piece: one
+// workgroup per SKU, its four waves taking consecutive quarters of the SKU's pieces
+// (quarter sums, then each quarter's offset from the earlier ones, then its prefixes).
+__device__ __forceinline__ void pc_sum(const CapPlan &L, int q0, int q1, int lane, int &s0,
+                                       int &s1)
 {
-    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
-    const int pass = L.ctl->pass;
-    for (int k = uni(blockIdx.x * 4 + wave); k < L.K; k += gridDim.x * 4) {
-    const int p0 = L.piece_off[k], p1 = L.piece_off[k + 1];
-    if (p1 - p0 < 2 || !cap_sku_stale(L, k, pass)) continue;
-    int run0 = 0, run1 = 0;
     constexpr int U = 8; // rows loaded together
-    for (int pb = p0; pb < p1; pb += U) {
+    s0 = s1 = 0;
+    for (int pb = q0; pb < q1; pb += U) {
         int v0[U], v1[U];
 #pragma unroll
         for (int q = 0; q < U; ++q) {
-            const int32_t *row = L.pc + (int64_t)min(pb + q, p1 - 1) * CAP_NPAD;
+            const int32_t *row = L.pc + (int64_t)min(pb + q, q1 - 1) * CAP_NPAD;
             v0[q] = row[lane];
             v1[q] = row[WAVE + lane];
         }
 #pragma unroll
-        for (int q = 0; q < U; ++q) {
-            if (pb + q < p1) {
-                int32_t *row = L.pc + (int64_t)(pb + q) * CAP_NPAD;
-                row[lane] = run0;
-                row[WAVE + lane] = run1;
-                run0 += v0[q];
-                run1 += v1[q];
+        for (int q = 0; q < U; ++q)
+            if (pb + q < q1) {
+                s0 += v0[q];
+                s1 += v1[q];
+            }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_cap_piece_scan(CapPlan L)
+{
+    __shared__ int32_t qs[4][CAP_NPAD];
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    const int pass = L.ctl->pass;
+    for (int k = blockIdx.x; k < L.K; k += gridDim.x) { // uniform per workgroup
+        const int p0 = L.piece_off[k], p1 = L.piece_off[k + 1];
+        if (p1 - p0 < 2 || !cap_sku_stale(L, k, pass)) continue;
+        const int per = (p1 - p0 + 3) / 4;
+        const int q0 = min(p0 + wave * per, p1), q1 = min(q0 + per, p1);
+        int s0, s1;
+        pc_sum(L, q0, q1, lane, s0, s1);
+        qs[wave][lane] = s0;
+        qs[wave][WAVE + lane] = s1;
+        __syncthreads();
+        int run0 = 0, run1 = 0;
+        for (int v = 0; v < wave; ++v) {
+            run0 += qs[v][lane];
+            run1 += qs[v][WAVE + lane];
+        }
+        constexpr int U = 8; // rows loaded together, then rewritten
+        for (int pb = q0; pb < q1; pb += U) {
+            int v0[U], v1[U];
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                const int32_t *row = L.pc + (int64_t)min(pb + q, q1 - 1) * CAP_NPAD;
+                v0[q] = row[lane];
+                v1[q] = row[WAVE + lane];
+            }
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                if (pb + q < q1) {
+                    int32_t *row = L.pc + (int64_t)(pb + q) * CAP_NPAD;
+                    row[lane] = run0;
+                    row[WAVE + lane] = run1;
+                    run0 += v0[q];
+                    run1 += v1[q];
+                }
             }
         }
-    }
+        __syncthreads(); // qs is reused by the next SKU
     }
 }
 
@@ -756,7 +793,7 @@ hipError_t cap_pass(const CapPlan &L, bool first, hipStream_t st)
     // bound by workgroup dispatch)
     const unsigned cap_wg = 8 * 256;
     const unsigned gp = (unsigned)std::min<int64_t>((L.max_pieces + 3) / 4, cap_wg);
-    const unsigned gk = (unsigned)std::min<int64_t>((L.K + 3) / 4, cap_wg);
+    const unsigned gk = (unsigned)std::min<int64_t>(L.K, cap_wg);
     hipLaunchKernelGGL(k_cap_piece_count, dim3(gp), dim3(256), 0, st, L);
     hipLaunchKernelGGL(k_cap_piece_scan, dim3(gk), dim3(256), 0, st, L);
     hipLaunchKernelGGL(k_cap_entry, dim3(gp), dim3(256), 0, st, L);
