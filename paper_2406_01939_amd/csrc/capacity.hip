@@ -473,19 +473,21 @@ __global__ __launch_bounds__(256) void k_cap_hist(CapPlan L)
 
 // Per node, exclusive scan of the passing counts over blocks: capacity at each block's
 // start.
-__global__ __launch_bounds__(256) void k_cap_scan(CapPlan L)
+constexpr int CAP_SCAN_T = 1024; // threads per node's scan
+
+__global__ __launch_bounds__(CAP_SCAN_T) void k_cap_scan(CapPlan L)
 {
-    __shared__ int32_t part[256];
+    __shared__ int32_t part[CAP_SCAN_T];
     const int w = blockIdx.x, tid = threadIdx.x;
     const int nblk = L.nblk;
-    const int per = (nblk + 255) / 256;
+    const int per = (nblk + CAP_SCAN_T - 1) / CAP_SCAN_T;
     const int b0 = tid * per, b1 = min(b0 + per, nblk);
     int32_t *h = L.H + (int64_t)w * nblk;
     int s = 0;
     for (int b = b0; b < b1; ++b) s += h[b];
     part[tid] = s;
     __syncthreads();
-    for (int d = 1; d < 256; d <<= 1) {
+    for (int d = 1; d < CAP_SCAN_T; d <<= 1) {
         const int v = tid >= d ? part[tid - d] : 0;
         __syncthreads();
         part[tid] += v;
@@ -798,7 +800,7 @@ hipError_t cap_pass(const CapPlan &L, bool first, hipStream_t st)
     hipLaunchKernelGGL(k_cap_piece_scan, dim3(gk), dim3(256), 0, st, L);
     hipLaunchKernelGGL(k_cap_entry, dim3(gp), dim3(256), 0, st, L);
     hipLaunchKernelGGL(k_cap_hist, dim3((unsigned)((L.nblk + 3) / 4)), dim3(256), 0, st, L);
-    hipLaunchKernelGGL(k_cap_scan, dim3(L.N), dim3(256), 0, st, L);
+    hipLaunchKernelGGL(k_cap_scan, dim3(L.N), dim3(CAP_SCAN_T), 0, st, L);
     if (L.gnum == 0)
         hipLaunchKernelGGL(k_cap_walk<false>, dim3(L.nblk), dim3(64), cap_walk_lds(L.B), st, L);
     else
