@@ -651,6 +651,45 @@ __global__ __launch_bounds__(256) void k_cap_final(CapPlan L, int32_t *final_inv
     if (threadIdx.x < L.N && hist[threadIdx.x]) atomicAdd(&used[threadIdx.x], hist[threadIdx.x]);
 }
 
+// Final stock rows after convergence (every action of the fixed point ships one unit):
+// the last piece of each SKU writes x0 minus the SKU's actions per node, counted from its
+// piece prefix and its own positions (one ballot per distinct node per 64 positions).
+// Rows of SKUs without orders keep the copy of x0 made before.
+__global__ __launch_bounds__(256) void k_cap_final_rows(CapPlan L, int32_t *final_inv)
+{
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
+    const int n_pieces = L.ctl->n_pieces, N = L.N;
+    for (int p = uni(blockIdx.x * 4 + wave); p < n_pieces; p += gridDim.x * 4) {
+        const int4 pd = L.piece[p]; // SKU, lo, hi, several pieces
+        const int k = pd.x;
+        if (p != L.piece_off[k + 1] - 1) continue; // not the SKU's last piece
+        int ca = 0, cb = 0;
+        if (pd.w) {
+            const int32_t *row = L.pc + (int64_t)p * CAP_NPAD;
+            ca = row[lane];
+            cb = row[WAVE + lane];
+        }
+        for (int base = pd.y; base < pd.z; base += WAVE) {
+            const int i = base + lane;
+            const int a = i < pd.z ? L.alpha[L.perm[i]] : LOST;
+            uint64_t rem = __ballot(a >= 0);
+            while (rem) {
+                const int q = __ffsll((long long)rem) - 1;
+                const int v = uni(__shfl(a, q, WAVE));
+                const uint64_t mv = __ballot(a == v);
+                if (lane == (v & (WAVE - 1))) {
+                    if (v < WAVE) ca += __popcll(mv);
+                    else cb += __popcll(mv);
+                }
+                rem &= ~mv;
+            }
+        }
+        int32_t *fr = final_inv + (int64_t)k * N;
+        if (lane < N) fr[lane] = L.x0[(int64_t)k * N + lane] - ca;
+        if (WAVE + lane < N) fr[WAVE + lane] = L.x0[(int64_t)k * N + WAVE + lane] - cb;
+    }
+}
+
 __global__ void k_cap_final_cap(const int32_t *cap0, const int32_t *used, int N, int32_t *out)
 {
     const int w = threadIdx.x;
@@ -813,11 +852,16 @@ hipError_t cap_finish(const CapPlan &L, int32_t *final_inv, int32_t *final_cap, 
 {
     hipError_t e;
     hipLaunchKernelGGL(k_cap_fill, dim3(1), dim3(128), 0, st, used, (int64_t)L.N, 0);
-    if (final_inv &&
-        (e = hipMemcpyAsync(final_inv, L.x0, (size_t)L.K * L.N * 4, hipMemcpyDeviceToDevice, st)) !=
-            hipSuccess)
-        return e;
-    hipLaunchKernelGGL(k_cap_final, dim3(grid_for(L.T, 256, 2048)), dim3(256), 0, st, L, final_inv,
+    if (final_inv) {
+        if ((e = hipMemcpyAsync(final_inv, L.x0, (size_t)L.K * L.N * 4, hipMemcpyDeviceToDevice,
+                                st)) != hipSuccess)
+            return e;
+        if (L.T > 0)
+            hipLaunchKernelGGL(k_cap_final_rows,
+                               dim3((unsigned)std::min<int64_t>((L.max_pieces + 3) / 4, 8 * 256)),
+                               dim3(256), 0, st, L, final_inv);
+    }
+    hipLaunchKernelGGL(k_cap_final, dim3(grid_for(L.T, 256, 2048)), dim3(256), 0, st, L, nullptr,
                        used);
     if (final_cap)
         hipLaunchKernelGGL(k_cap_final_cap, dim3(1), dim3(CAP_NPAD), 0, st, L.cap0, used, L.N,
