@@ -456,7 +456,8 @@ __global__ __launch_bounds__(256) void k_cap_hist(CapPlan L)
     __shared__ int32_t u[4][CAP_NPAD];
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     const int m = uni(blockIdx.x * 4 + wave);
-    if (m >= L.nblk) return;
+    // after a pass without change nothing moves (no cached action changed)
+    if (m >= L.nblk || L.ctl->frontier == INT_MAX) return;
     u[wave][lane] = 0;
     u[wave][WAVE + lane] = 0;
     wave_sync();
@@ -479,6 +480,7 @@ __global__ __launch_bounds__(CAP_SCAN_T) void k_cap_scan(CapPlan L)
 {
     __shared__ int32_t part[CAP_SCAN_T];
     const int w = blockIdx.x, tid = threadIdx.x;
+    if (L.ctl->frontier == INT_MAX) return; // after a pass without change H is unchanged
     const int nblk = L.nblk;
     const int per = (nblk + CAP_SCAN_T - 1) / CAP_SCAN_T;
     const int b0 = tid * per, b1 = min(b0 + per, nblk);
