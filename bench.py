@@ -296,7 +296,8 @@ def main():
         return {"workload": name, "policy": policy, "processes": M,
                 "timing": f"best of {reps} after a warm-up", "rows": rows}
 
-    def capacity_leg(name=CAPACITY_WORKLOAD, blocks=(32, 64, 128, 255), reps=3, serial=True):
+    def capacity_leg(name=CAPACITY_WORKLOAD, blocks=(32, 48, 64, 96, 128, 255), reps=3,
+                     serial=True):
         """Picard with node capacity (time-block processes) against the serial GPU sweep
         with capacity, on the same instance; best of `reps` calls per block length after a
         warm-up call."""
