@@ -258,7 +258,7 @@ pk_status pk_adam_step(float *params, const float *grad, float *m, float *v, int
  * (PK_ERR_INVALID_ARG names the failing check).
  *
  * Bytes of scratch the two calls below need for this problem and block length (0 =
- * the default, 128).  Writes *bytes. */
+ * the default, 96).  Writes *bytes. */
 pk_status pk_capacity_workspace_size(const pk_problem *problem, const int32_t *capacity,
                                      int32_t block_len, size_t *bytes);
 
@@ -271,7 +271,7 @@ pk_status pk_serial_simulate_capacity(const pk_problem *problem, const int32_t *
                                       int32_t *final_cap, void *stream);
 
 /* Algorithm 1 with capacity.  The processes are blocks of block_len consecutive orders in
- * time (1..255; 0 = 128): process m owns orders [m B, (m+1) B).  init_cache [T] DEVICE,
+ * time (1..255; 0 = 96): process m owns orders [m B, (m+1) B).  init_cache [T] DEVICE,
  * nullable (NULL: lost sale everywhere) is alpha^0.  max_passes 0 means T + 1
  * (Proposition 2.1 bounds the passes by T + 1).  On return actions [T] holds the fixed
  * point, which equals pk_serial_simulate_capacity's actions; final_inv [K][N] and

@@ -133,12 +133,12 @@ def test_edge_cases(api, oracle):
 
 
 def test_full_size(api, oracle):
-    """N=100, K=1e5, R=200, T=1e6, 60% capacity, default blocks (128 orders): Picard equals
+    """N=100, K=1e5, R=200, T=1e6, 60% capacity, default blocks (96 orders): Picard equals
     the serial GPU sweep and the oracle's serial rollout; pass count and changed orders per
     pass equal the oracle's Algorithm 1 under the same blocks."""
     inst = make_instance("greedy_cap_n100_k1e5_t1e6")
     cap0 = workload_capacity("greedy_cap_n100_k1e5_t1e6")
-    _say("capacity full size n100 k1e5 t1e6 B=128")
+    _say("capacity full size n100 k1e5 t1e6 B=96")
     prob = api.DeviceProblem.from_instance(inst)
     out = api.pk_picard_simulate_capacity(prob, cap0)
     want = oracle.serial_cap(inst, cap0)
@@ -147,7 +147,7 @@ def test_full_size(api, oracle):
     np.testing.assert_array_equal(out["final_cap"].cpu().numpy(), want["final_cap"])
     ser = api.pk_serial_simulate_capacity(prob, cap0, want_final=False)
     np.testing.assert_array_equal(ser["actions"].cpu().numpy(), want["actions"])
-    ref = oracle.picard_timeblocks_cap(inst, cap0, 128)
+    ref = oracle.picard_timeblocks_cap(inst, cap0, 96)
     _say(f"  passes gpu {out['passes']} oracle {ref['passes']}")
     assert out["passes"] == ref["passes"]
     np.testing.assert_array_equal(out["changed"], ref["changed"])
