@@ -1221,7 +1221,11 @@ pk_status pk_picard_simulate_capacity(const pk_problem *problem, const int32_t *
     HIP_TRY(hipMemcpyAsync(&h, w.L.ctl, sizeof h, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     if ((s = cap_errors(h)) != PK_OK) return s;
+    w.L.first = w.first;
     HIP_TRY(cap_setup(w.L, w.keys, w.vals, w.keys_alt, w.vals_alt, w.first, w.tmp, st));
+    HIP_TRY(hipMemcpyAsync(&h, w.L.ctl, sizeof h, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    w.L.dmax = std::max(h.max_distinct, 1);
     if (T > 0) {
         if (init_cache)
             HIP_TRY(hipMemcpyAsync(actions, init_cache, (size_t)T * 4, hipMemcpyDeviceToDevice, st));

@@ -190,11 +190,13 @@ __global__ void k_cap_keytab(CapPlan L)
     }
 }
 
-// One wave per block: the index in the block of the first order of each order's SKU, and
-// a 0/1 flag for first orders (scanned into row ids afterwards).
+// One wave per block: a 0/1 flag for the first order of each (block, SKU) (scanned into
+// row ids afterwards) and each order's slot, the rank of its SKU's first order among the
+// block's first orders (the stock row it uses in the walk's LDS).  The largest number of
+// distinct SKUs in a block sizes the walk's LDS.
 __global__ __launch_bounds__(64) void k_cap_slots(CapPlan L, int32_t *first)
 {
-    __shared__ int32_t sk[CAP_MAX_B];
+    __shared__ int32_t sk[CAP_MAX_B], fo[CAP_MAX_B];
     const int m = blockIdx.x, lane = threadIdx.x;
     const int lo = m * L.B, hi = min(lo + L.B, L.T), n = hi - lo;
     for (int j = lane; j < n; j += WAVE) sk[j] = L.sku[lo + j];
@@ -203,9 +205,20 @@ __global__ __launch_bounds__(64) void k_cap_slots(CapPlan L, int32_t *first)
         int f = j;
         for (int i = 0; i < j; ++i)
             if (sk[i] == sk[j]) { f = i; break; }
-        L.slot[lo + j] = f;
+        fo[j] = f;
         first[lo + j] = f == j;
     }
+    __syncthreads();
+    int nd = 0;
+    for (int j = lane; j < n; j += WAVE) {
+        const int f = fo[j];
+        int c = 0;
+        for (int i = 0; i < f; ++i) c += fo[i] == i;
+        L.slot[lo + j] = c;
+        nd += f == j;
+    }
+    nd = wave_sum(nd);
+    if (lane == 0) atomicMax(&L.ctl->max_distinct, nd);
 }
 
 // Pieces of each SKU's segment: ceil(len / CAP_PIECE) of them.
@@ -362,7 +375,7 @@ __global__ void k_cap_srow(CapPlan L)
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L.T; i += stride) {
         const int t = L.perm[i];
-        L.srow[i] = L.slot[t] == t % L.B ? L.sid[t] : -1;
+        L.srow[i] = L.first[t] ? L.sid[t] : -1;
     }
 }
 
@@ -519,10 +532,12 @@ __global__ __launch_bounds__(64) void k_cap_walk(CapPlan L)
     if (m <= ctl->frontier) return;
     const int B = L.B;
     const int lo = m * B, hi = min(lo + B, L.T), n = hi - lo;
-    uint16_t *rows = (uint16_t *)cap_smem;                       // [B][64] stock words
-    int32_t *sd = (int32_t *)(cap_smem + (size_t)B * CAP_NPAD); // [B] row of X per slot
-    int32_t *out = sd + B;                                       // [B]
+    const int D = L.dmax; // stock rows per block (the most distinct SKUs of any block)
+    uint16_t *rows = (uint16_t *)cap_smem;                       // [D][64] stock words
+    int32_t *sd = (int32_t *)(cap_smem + (size_t)D * CAP_NPAD); // [D] row of X per slot
+    int32_t *out = sd + D;                                       // [B]
     int rg[4], sv[4]; // regions and slots of orders lane, 64 + lane, 128 + lane, 192 + lane
+    int nd = 0;       // distinct SKUs of this block
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int j = q * WAVE + lane;
@@ -530,16 +545,20 @@ __global__ __launch_bounds__(64) void k_cap_walk(CapPlan L)
         if (j < n) {
             rg[q] = L.region[lo + j];
             sv[q] = L.slot[lo + j];
-            sd[j] = sv[q] == j ? L.sid[lo + j] : -1;
+            if (L.first[lo + j]) {
+                sd[sv[q]] = L.sid[lo + j];
+                ++nd;
+            }
         }
     }
+    nd = wave_sum(nd);
     __syncthreads();
     // stock rows of the block's SKUs: 16-byte pieces spread over the lanes, every load of a
     // round issued before its stores
     {
         const uint4 *X4 = (const uint4 *)L.X;
         uint4 *R4 = (uint4 *)rows;
-        const int n16 = n * (CAP_NPAD / 16);
+        const int n16 = nd * (CAP_NPAD / 16);
         for (int b0 = 0; b0 < n16; b0 += 4 * WAVE) {
             int r[4];
 #pragma unroll
@@ -773,7 +792,7 @@ inline unsigned grid_for(int64_t n, int threads, int cap = 65535)
 
 } // namespace
 
-size_t cap_walk_lds(int B) { return (size_t)B * CAP_NPAD + (size_t)2 * B * 4; }
+size_t cap_walk_lds(int B, int D) { return (size_t)D * CAP_NPAD + (size_t)(D + B) * 4; }
 
 // Input checks of a capacity run (every later kernel indexes with these values): clears
 // the control block and sets CapCtl::error.  init: the initial cache, nullable.
@@ -843,9 +862,11 @@ hipError_t cap_pass(const CapPlan &L, bool first, hipStream_t st)
     hipLaunchKernelGGL(k_cap_hist, dim3((unsigned)((L.nblk + 3) / 4)), dim3(256), 0, st, L);
     hipLaunchKernelGGL(k_cap_scan, dim3(L.N), dim3(CAP_SCAN_T), 0, st, L);
     if (L.gnum == 0)
-        hipLaunchKernelGGL(k_cap_walk<false>, dim3(L.nblk), dim3(64), cap_walk_lds(L.B), st, L);
+        hipLaunchKernelGGL(k_cap_walk<false>, dim3(L.nblk), dim3(64), cap_walk_lds(L.B, L.dmax),
+                           st, L);
     else
-        hipLaunchKernelGGL(k_cap_walk<true>, dim3(L.nblk), dim3(64), cap_walk_lds(L.B), st, L);
+        hipLaunchKernelGGL(k_cap_walk<true>, dim3(L.nblk), dim3(64), cap_walk_lds(L.B, L.dmax),
+                           st, L);
     return hipGetLastError();
 }
 

@@ -214,17 +214,20 @@ struct CapCtl {
     int32_t first_blk; // first block with a change in the current pass
     int32_t frontier;  // blocks <= frontier are not walked in the current pass
     int32_t n_pieces;
+    int32_t max_distinct; // the most distinct SKUs in one block
 };
 
 struct CapPlan {
     int32_t T, N, K, R, B, nblk;
     int32_t gnum, gden;  // policy: 0 = greedy, else capacity-dependent, gamma = gnum / gden
+    int32_t dmax;        // stock rows per block in the walk's LDS (CapCtl::max_distinct)
     int64_t max_pieces;
     const int32_t *sku, *region, *qty, *x0, *cost, *cap0;
     int32_t *alpha;      // [T] cache, time order (the caller's actions buffer)
     int32_t *perm;       // [T] SKU-sorted position -> time index
     int32_t *seg_off;    // [K+1]
-    int32_t *slot;       // [T] index in its block of the first order of its (block, SKU)
+    int32_t *slot;       // [T] rank of its SKU among the block's distinct SKUs (LDS row)
+    int32_t *first;      // [T] 1 for the first order of each (block, SKU)
     int32_t *sid;        // [T] row of X for the first order of each (block, SKU)
     int32_t *srow;       // [T] sorted position -> row of X it starts, or -1
     int32_t *piece_off;  // [K+1] first piece of each SKU
@@ -240,7 +243,7 @@ struct CapPlan {
     CapCtl *ctl;
 };
 
-size_t cap_walk_lds(int B);
+size_t cap_walk_lds(int B, int D);
 hipError_t cap_check(CapPlan &L, const int32_t *init, hipStream_t st);
 hipError_t cap_setup(CapPlan &L, int32_t *keys, int32_t *vals, int32_t *keys_alt,
                      int32_t *vals_alt, int32_t *first, void *tmp, hipStream_t st);
