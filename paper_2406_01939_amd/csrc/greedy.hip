@@ -101,7 +101,7 @@ __global__ __launch_bounds__(256) void k_keys(Prob P, KeyT *keys)
 
 } // namespace
 
-bool keys16(int N) { return N <= 256; }
+bool keys16(int N) { return N <= 255; } // the all-ones key 0xffff is the no-stock sentinel
 
 size_t pos_bytes(int N, int R, int n_traj)
 {

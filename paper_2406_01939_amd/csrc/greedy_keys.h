@@ -1,8 +1,9 @@
 // Key table of the greedy policy, shared by the Picard walk and the serial sweep.
 //
 // key[b][r][w] = (pos << S) | w, where pos is the position of warehouse w in region r's
-// increasing (cost[b][w][r], w) order: 16-bit keys with S = 8 when N <= 256, else 32-bit
-// keys with S = 16.  The least key among warehouses with stock names the greedy choice
+// increasing (cost[b][w][r], w) order: 16-bit keys with S = 8 when N <= 255, else 32-bit
+// keys with S = 16.  (At N = 256 the key of warehouse 255 in last place would be 0xffff,
+// the all-ones value that stands for "no warehouse with stock".)  The least key among warehouses with stock names the greedy choice
 // (least cost, lowest index on ties).  Per trajectory the table holds R rows of npad
 // keys; rows are padded to 32 bytes with all-ones keys, which are never selected.
 #pragma once

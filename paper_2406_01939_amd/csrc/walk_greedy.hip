@@ -632,7 +632,7 @@ void launch_walk_t(const Prob &P, const Plan &L, const void *keys, int32_t *fina
                            P, L, t, final_inv, hi, L.sink);
 }
 
-inline bool keys16_n(int N) { return N <= 256; }
+inline bool keys16_n(int N) { return N <= 255; } // as keys16: 0xffff means no stock
 
 } // namespace
 

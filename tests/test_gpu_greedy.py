@@ -119,6 +119,31 @@ def test_wide_shapes(api, oracle, N, R, n_traj, qmax, B):
     np.testing.assert_array_equal(out["passes"], want_p)
 
 
+@pytest.mark.parametrize("N", [255, 256, 257])
+@pytest.mark.parametrize("n_traj", [1, 2])
+def test_last_warehouse_costliest_and_only_stock(api, oracle, N, n_traj):
+    """Key-width boundary: the costliest warehouse of every region is the last one and the
+    only one with stock.  Its key is the largest of the table (at N = 256 with 16-bit keys
+    it would be 0xffff, the value that stands for "no stock"), so Picard and the serial
+    sweep must still ship from it until it runs out."""
+    inst = random_tiny(400 + N, N=N, K=3, R=5, T=600, qmax=2, inv_max=0, n_traj=n_traj)
+    inst.cost[:] = np.random.default_rng(N).integers(1, 100, inst.cost.shape)
+    inst.cost[:, N - 1, :] = 100
+    inst.x0[:] = 0
+    inst.x0[:, :, N - 1] = 150
+    _say(f"case last warehouse only stock N={N} n_traj={n_traj} total={inst.total_orders}")
+    want_a, want_s, want_f, want_p = _oracle_batch(oracle, inst, 64)
+    assert (want_a == N - 1).any() and (want_a == -1).any()
+    prob = api.DeviceProblem.from_instance(inst)
+    for B in (64, 1000):
+        out = api.pk_picard_simulate(prob, "greedy", block_len=B, validate=True)
+        _check(out, inst, want_a, want_s, want_f)
+    out = api.pk_picard_simulate(prob, "greedy", block_len=64, validate=True)
+    np.testing.assert_array_equal(out["passes"], want_p)
+    ser = api.pk_serial_simulate(prob, "greedy")
+    _check(ser, inst, want_a, want_s, want_f)
+
+
 def test_serial_sweep_matches_oracle(api, oracle):
     inst = random_tiny(11, N=70, K=5, R=4, T=400, qmax=3, inv_max=6, n_traj=5)
     _say("case serial sweep tiny batch")
