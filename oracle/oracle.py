@@ -140,7 +140,7 @@ def eval_at(inst, actions: np.ndarray, b: int = 0) -> dict:
 
 def alg1(inst, worker: np.ndarray, n_workers: int, b: int = 0, init_cache=None,
          max_passes: Optional[int] = None, record: bool = True) -> dict:
-    """Algorithm 1 taken literally (tiny instances only)."""
+    """Algorithm 1 by brute force: every process views the whole horizon (tiny instances only)."""
     B = _Bound(inst, b)
     T = B.T
     if max_passes is None:
@@ -202,7 +202,7 @@ def serial_cap(inst, cap0, b: int = 0, gamma=(0, 1)) -> dict:
 
 def alg1_cap(inst, cap0, worker: np.ndarray, n_workers: int, b: int = 0, init_cache=None,
              max_passes: Optional[int] = None, record: bool = True, gamma=(0, 1)) -> dict:
-    """Algorithm 1 with node capacities, taken literally (tiny instances only)."""
+    """Algorithm 1 with node capacities by brute force (tiny instances only)."""
     B = _Bound(inst, b)
     B.p.params = None
     cap0 = _cap_array(inst, cap0)

@@ -9,10 +9,11 @@
  *   orc_serial        the serial rollout that defines the answer (Section 2, problem
  *                     statement: a_t = pi(s_t, w_t), s_{t+1} = f(s_t, a_t, w_t)), with the
  *                     FO transition of Section 3 (no node capacity).
- *   orc_alg1          Algorithm 1 (the Picard iteration) taken literally: every virtual
- *                     process keeps its own full state and walks t = 1..T; cached actions
- *                     that are infeasible locally are replaced by the always-feasible
- *                     action (lost sale).  O(P*T*N) per pass: tiny instances only.
+ *   orc_alg1          Algorithm 1 (the Picard iteration) by brute force: in a pass every
+ *                     process has its own view of the whole horizon (process_view, the
+ *                     same replay that gives the serial rollout), and run_passes iterates
+ *                     the pass map to its fixed point.  O(P*T*N) per pass: tiny
+ *                     instances only.
  *   orc_picard_runs   The same passes, computed per SKU: by inventory independence
  *                     (Assumption 1) and with no capacity, SKUs never interact.  A
  *                     process reaching one of its runs of a SKU has applied the cached
@@ -245,7 +246,41 @@ static int check_problem(const orc_problem *P)
 }
 
 /* ------------------------------------------------------------------------------------
- * Serial rollout (the definition of the answer).
+ * One process's view of the horizon (no capacity).  The view starts from s_1 and takes
+ * the orders in time order.  An order the process owns (owner == NULL: every order) is
+ * decided by the policy at the state the view has reached, and the decision goes to
+ * decided[t]; any other order applies given[t], or the lost sale when given[t] is not
+ * feasible at that state (the lost sale always is).  shipped/z1/z2 (nullable) receive
+ * the units shipped by the view and, for the learned policy, the top two perturbed
+ * scores of every decided order.  x is scratch of K*N entries.
+ * ---------------------------------------------------------------------------------- */
+static void process_view(const orc_problem *P, const mlp64 *m, const int64_t *owner,
+                         int64_t self, const int32_t *given, int32_t *decided, int32_t *x,
+                         int32_t *shipped, double *z1, double *z2)
+{
+    const int N = P->N;
+    memcpy(x, P->x0, sizeof(int32_t) * (size_t)P->K * N); /* every view starts at s_1 */
+    for (int64_t t = 0; t < P->T; ++t) {
+        int32_t *xk = x + (int64_t)P->sku[t] * N;
+        int32_t a;
+        if (!owner || owner[t] == self) {
+            double a1 = -INFINITY, a2 = -INFINITY;
+            a = policy(P, m, t, xk, &a1, &a2);
+            decided[t] = a;
+            if (z1) z1[t] = a1;
+            if (z2) z2[t] = a2;
+        } else {
+            a = given[t];
+            if (a != LOST && (a < 0 || a >= N || xk[a] <= 0)) a = LOST;
+        }
+        const int32_t sh = transition(xk, a, P->qty[t]);
+        if (shipped) shipped[t] = sh;
+    }
+}
+
+/* ------------------------------------------------------------------------------------
+ * Serial rollout (the definition of the answer): the view of a process that owns
+ * every order.
  * ---------------------------------------------------------------------------------- */
 int orc_serial(const orc_problem *P, int32_t *actions, int32_t *shipped, int32_t *final_inv,
                double *z1, double *z2)
@@ -256,21 +291,49 @@ int orc_serial(const orc_problem *P, int32_t *actions, int32_t *shipped, int32_t
     if (P->params && mlp_load(&m, P)) return -1;
     int32_t *x = (int32_t *)malloc(sizeof(int32_t) * (size_t)P->K * N);
     if (!x) { mlp_free(&m); return -1; }
-    memcpy(x, P->x0, sizeof(int32_t) * (size_t)P->K * N);
-    for (int64_t t = 0; t < P->T; ++t) {
-        int32_t *xk = x + (int64_t)P->sku[t] * N;
-        double a1 = -INFINITY, a2 = -INFINITY;
-        int32_t a = policy(P, &m, t, xk, &a1, &a2);
-        int32_t sh = transition(xk, a, P->qty[t]);
-        actions[t] = a;
-        if (shipped) shipped[t] = sh;
-        if (z1) z1[t] = a1;
-        if (z2) z2[t] = a2;
-    }
+    process_view(P, &m, NULL, 0, NULL, actions, x, shipped, z1, z2);
     if (final_inv) memcpy(final_inv, x, sizeof(int32_t) * (size_t)P->K * N);
     free(x);
     mlp_free(&m);
     return 0;
+}
+
+/* ------------------------------------------------------------------------------------
+ * Fixed-point driver shared by the Picard oracles.  A pass maps the previous cache to
+ * the next one; passes run from alpha^0 (init_cache, or the lost sale everywhere) until
+ * one returns its own input (Algorithm 1's termination test) or max_passes is reached.
+ * caches (nullable) receives alpha^1 .. alpha^passes, T entries each; changed
+ * (nullable) the number of steps each pass changed.  Returns 0 when converged (passes =
+ * the k with alpha^k == alpha^{k-1}), 1 when max_passes was reached first
+ * (final_cache then holds alpha^max_passes), -1 when out of memory.
+ * ---------------------------------------------------------------------------------- */
+typedef void (*pass_fn)(void *ctx, const int32_t *prev, int32_t *next);
+
+static int run_passes(pass_fn pass, void *ctx, int64_t T, const int32_t *init_cache,
+                      int32_t max_passes, int32_t *final_cache, int32_t *passes,
+                      int64_t *changed, int32_t *caches)
+{
+    int32_t *prev = (int32_t *)malloc(sizeof(int32_t) * (size_t)(T + 1));
+    int32_t *next = (int32_t *)malloc(sizeof(int32_t) * (size_t)(T + 1));
+    if (!prev || !next) { free(prev); free(next); return -1; }
+    for (int64_t t = 0; t < T; ++t) prev[t] = init_cache ? init_cache[t] : LOST;
+    int rc = 1;
+    int32_t k;
+    for (k = 1; k <= max_passes; ++k) {
+        pass(ctx, prev, next);
+        if (caches) memcpy(caches + (int64_t)(k - 1) * T, next, sizeof(int32_t) * (size_t)T);
+        int64_t nch = 0;
+        for (int64_t t = 0; t < T; ++t) nch += next[t] != prev[t];
+        if (changed) changed[k - 1] = nch;
+        int32_t *tmp = prev; prev = next; next = tmp;
+        if (nch == 0) { rc = 0; break; }
+    }
+    if (k > max_passes) k = max_passes;
+    *passes = k;
+    memcpy(final_cache, prev, sizeof(int32_t) * (size_t)T);
+    free(prev);
+    free(next);
+    return rc;
 }
 
 /* ------------------------------------------------------------------------------------
@@ -311,58 +374,43 @@ int orc_eval_at(const orc_problem *P, const int32_t *actions, int32_t *choice, d
 }
 
 /* ------------------------------------------------------------------------------------
- * Algorithm 1, literally.  worker[t] in [0, P) is the process owning step t.
- * init_cache may be NULL (alpha^0 = lost sale everywhere).  caches (nullable) receives
- * alpha^1 .. alpha^passes, T entries each (room for max_passes rows).
- * Returns 0 when converged (passes = the k with alpha^k == alpha^{k-1}), 1 when
- * max_passes was reached first (final_cache holds alpha^max_passes), < 0 on bad input.
+ * Algorithm 1 by brute force, for any assignment worker[t] in [0, n_workers) of steps to
+ * processes: in a pass every process has its own view of the whole horizon (its own
+ * steps decided fresh, everyone else's taken from the previous cache), and the new
+ * cache collects each step's decision from the view of the process that owns it.
+ * init_cache may be NULL (alpha^0 = lost sale everywhere); caches, return value and
+ * passes as run_passes.  O(P*T*N) per pass: tiny instances only.
  * ---------------------------------------------------------------------------------- */
+typedef struct {
+    const orc_problem *P;
+    const mlp64 *m;
+    const int64_t *worker;
+    int64_t n_workers;
+    int32_t *x;
+} alg1_ctx;
+
+static void alg1_pass(void *vctx, const int32_t *prev, int32_t *next)
+{
+    const alg1_ctx *c = (const alg1_ctx *)vctx;
+    for (int64_t proc = 0; proc < c->n_workers; ++proc)
+        process_view(c->P, c->m, c->worker, proc, prev, next, c->x, NULL, NULL, NULL);
+}
+
 int orc_alg1(const orc_problem *P, const int64_t *worker, int64_t n_workers,
              const int32_t *init_cache, int32_t max_passes, int32_t *final_cache,
              int32_t *passes, int32_t *caches)
 {
     if (check_problem(P) || n_workers <= 0 || max_passes <= 0) return -1;
-    const int N = P->N;
-    const int64_t T = P->T, KN = (int64_t)P->K * N;
-    for (int64_t t = 0; t < T; ++t)
+    for (int64_t t = 0; t < P->T; ++t)
         if (worker[t] < 0 || worker[t] >= n_workers) return -1;
     mlp64 m = {0};
     if (P->params && mlp_load(&m, P)) return -1;
-    int32_t *prev = (int32_t *)malloc(sizeof(int32_t) * (size_t)(T + 1));
-    int32_t *next = (int32_t *)malloc(sizeof(int32_t) * (size_t)(T + 1));
-    int32_t *x = (int32_t *)malloc(sizeof(int32_t) * (size_t)KN);
-    if (!prev || !next || !x) { free(prev); free(next); free(x); mlp_free(&m); return -1; }
-    for (int64_t t = 0; t < T; ++t) prev[t] = init_cache ? init_cache[t] : LOST;
-    int rc = 1;
-    int32_t k = 0;
-    for (k = 1; k <= max_passes; ++k) {
-        for (int64_t proc = 0; proc < n_workers; ++proc) {
-            memcpy(x, P->x0, sizeof(int32_t) * (size_t)KN); /* s_1^{k,m} = s_1 */
-            for (int64_t t = 0; t < T; ++t) {
-                int32_t *xk = x + (int64_t)P->sku[t] * N;
-                int32_t a;
-                if (worker[t] == proc) {
-                    a = policy(P, &m, t, xk, NULL, NULL);
-                    next[t] = a; /* alpha^k_t = a^{k,m}_t for t in T_m */
-                } else {
-                    a = prev[t];
-                    /* cached action if feasible at the local state, else a^phi */
-                    if (a != LOST && (a < 0 || a >= N || xk[a] <= 0)) a = LOST;
-                }
-                transition(xk, a, P->qty[t]);
-            }
-        }
-        if (caches) memcpy(caches + (int64_t)(k - 1) * T, next, sizeof(int32_t) * (size_t)T);
-        int same = 1;
-        for (int64_t t = 0; t < T; ++t)
-            if (next[t] != prev[t]) { same = 0; break; }
-        int32_t *tmp = prev; prev = next; next = tmp;
-        if (same) { rc = 0; break; }
-    }
-    if (k > max_passes) k = max_passes;
-    *passes = k;
-    memcpy(final_cache, prev, sizeof(int32_t) * (size_t)T);
-    free(prev); free(next); free(x);
+    int32_t *x = (int32_t *)malloc(sizeof(int32_t) * (size_t)P->K * P->N);
+    if (!x) { mlp_free(&m); return -1; }
+    alg1_ctx ctx = {P, &m, worker, n_workers, x};
+    const int rc = run_passes(alg1_pass, &ctx, P->T, init_cache, max_passes, final_cache,
+                              passes, NULL, caches);
+    free(x);
     mlp_free(&m);
     return rc;
 }
@@ -668,7 +716,33 @@ static void transition_cap(int32_t *x, int32_t *c, int32_t a)
     c[a] -= 1;
 }
 
-/* Serial rollout with capacity: the answer Picard must reach. */
+/* One process's view of the horizon with capacity: as process_view, with the state
+ * (x, c) starting at (x0, cap0); a given action is replaced by the lost sale when its
+ * node has no stock of the SKU or no capacity left in the view.  x: K*N scratch, c: N. */
+static void process_view_cap(const orc_problem *P, const int32_t *cap0, int32_t gnum,
+                             int32_t gden, const int32_t *rk, const int64_t *owner,
+                             int64_t self, const int32_t *given, int32_t *decided, int32_t *x,
+                             int32_t *c)
+{
+    const int N = P->N;
+    memcpy(x, P->x0, sizeof(int32_t) * (size_t)P->K * N); /* every view starts at s_1 */
+    memcpy(c, cap0, sizeof(int32_t) * (size_t)N);
+    for (int64_t t = 0; t < P->T; ++t) {
+        int32_t *xk = x + (int64_t)P->sku[t] * N;
+        int32_t a;
+        if (!owner || owner[t] == self) {
+            a = greedy_cap(P, t, xk, c, gnum, gden, rk);
+            decided[t] = a;
+        } else {
+            a = given[t];
+            if (a != LOST && (a < 0 || a >= N || xk[a] <= 0 || c[a] <= 0)) a = LOST;
+        }
+        transition_cap(xk, c, a);
+    }
+}
+
+/* Serial rollout with capacity (the answer Picard must reach): the view of a process
+ * that owns every order. */
 int orc_serial_cap(const orc_problem *P, const int32_t *cap0, int32_t gnum, int32_t gden,
                    int32_t *actions, int32_t *final_inv, int32_t *final_cap)
 {
@@ -679,14 +753,7 @@ int orc_serial_cap(const orc_problem *P, const int32_t *cap0, int32_t gnum, int3
     int32_t *x = (int32_t *)malloc(sizeof(int32_t) * (size_t)P->K * N);
     int32_t *c = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
     if (!x || !c) { free(x); free(c); free(rk); return -1; }
-    memcpy(x, P->x0, sizeof(int32_t) * (size_t)P->K * N);
-    memcpy(c, cap0, sizeof(int32_t) * (size_t)N);
-    for (int64_t t = 0; t < P->T; ++t) {
-        int32_t *xk = x + (int64_t)P->sku[t] * N;
-        const int32_t a = greedy_cap(P, t, xk, c, gnum, gden, rk);
-        transition_cap(xk, c, a);
-        actions[t] = a;
-    }
+    process_view_cap(P, cap0, gnum, gden, rk, NULL, 0, NULL, actions, x, c);
     if (final_inv) memcpy(final_inv, x, sizeof(int32_t) * (size_t)P->K * N);
     if (final_cap) memcpy(final_cap, c, sizeof(int32_t) * (size_t)N);
     free(x);
@@ -695,57 +762,42 @@ int orc_serial_cap(const orc_problem *P, const int32_t *cap0, int32_t gnum, int3
     return 0;
 }
 
-/* Algorithm 1 with capacity, literally: every process keeps its own (x, c), walks
- * t = 1..T, decides its own steps and replays the others' cached actions, each
- * replaced by a lost sale when the node has no stock or no capacity left locally.
- * Arguments and return value as orc_alg1.  O(P*T*N) per pass: tiny instances only. */
+/* Algorithm 1 with capacity by brute force: as orc_alg1, every process's view carrying
+ * its own (x, c).  O(P*T*N) per pass: tiny instances only. */
+typedef struct {
+    const orc_problem *P;
+    const int32_t *cap0, *rk;
+    int32_t gnum, gden;
+    const int64_t *worker;
+    int64_t n_workers;
+    int32_t *x, *c;
+} alg1_cap_ctx;
+
+static void alg1_cap_pass(void *vctx, const int32_t *prev, int32_t *next)
+{
+    const alg1_cap_ctx *q = (const alg1_cap_ctx *)vctx;
+    for (int64_t proc = 0; proc < q->n_workers; ++proc)
+        process_view_cap(q->P, q->cap0, q->gnum, q->gden, q->rk, q->worker, proc, prev, next,
+                         q->x, q->c);
+}
+
 int orc_alg1_cap(const orc_problem *P, const int32_t *cap0, int32_t gnum, int32_t gden,
                  const int64_t *worker, int64_t n_workers, const int32_t *init_cache,
                  int32_t max_passes, int32_t *final_cache, int32_t *passes, int32_t *caches)
 {
     if (check_cap(P, cap0, gnum, gden) || n_workers <= 0 || max_passes <= 0) return -1;
     const int N = P->N;
-    const int64_t T = P->T, KN = (int64_t)P->K * N;
-    for (int64_t t = 0; t < T; ++t)
+    for (int64_t t = 0; t < P->T; ++t)
         if (worker[t] < 0 || worker[t] >= n_workers) return -1;
     int32_t *rk = rank_table(P, gnum);
     if (gnum && !rk) return -1;
-    int32_t *prev = (int32_t *)malloc(sizeof(int32_t) * (size_t)(T + 1));
-    int32_t *next = (int32_t *)malloc(sizeof(int32_t) * (size_t)(T + 1));
-    int32_t *x = (int32_t *)malloc(sizeof(int32_t) * (size_t)KN);
+    int32_t *x = (int32_t *)malloc(sizeof(int32_t) * (size_t)P->K * N);
     int32_t *c = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
-    if (!prev || !next || !x || !c) { free(prev); free(next); free(x); free(c); free(rk); return -1; }
-    for (int64_t t = 0; t < T; ++t) prev[t] = init_cache ? init_cache[t] : LOST;
-    int rc = 1;
-    int32_t k;
-    for (k = 1; k <= max_passes; ++k) {
-        for (int64_t proc = 0; proc < n_workers; ++proc) {
-            memcpy(x, P->x0, sizeof(int32_t) * (size_t)KN);
-            memcpy(c, cap0, sizeof(int32_t) * (size_t)N);
-            for (int64_t t = 0; t < T; ++t) {
-                int32_t *xk = x + (int64_t)P->sku[t] * N;
-                int32_t a;
-                if (worker[t] == proc) {
-                    a = greedy_cap(P, t, xk, c, gnum, gden, rk);
-                    next[t] = a;
-                } else {
-                    a = prev[t];
-                    if (a != LOST && (a < 0 || a >= N || xk[a] <= 0 || c[a] <= 0)) a = LOST;
-                }
-                transition_cap(xk, c, a);
-            }
-        }
-        if (caches) memcpy(caches + (int64_t)(k - 1) * T, next, sizeof(int32_t) * (size_t)T);
-        int same = 1;
-        for (int64_t t = 0; t < T; ++t)
-            if (next[t] != prev[t]) { same = 0; break; }
-        int32_t *tmp = prev; prev = next; next = tmp;
-        if (same) { rc = 0; break; }
-    }
-    if (k > max_passes) k = max_passes;
-    *passes = k;
-    memcpy(final_cache, prev, sizeof(int32_t) * (size_t)T);
-    free(prev); free(next); free(x); free(c); free(rk);
+    if (!x || !c) { free(x); free(c); free(rk); return -1; }
+    alg1_cap_ctx ctx = {P, cap0, rk, gnum, gden, worker, n_workers, x, c};
+    const int rc = run_passes(alg1_cap_pass, &ctx, P->T, init_cache, max_passes, final_cache,
+                              passes, NULL, caches);
+    free(x); free(c); free(rk);
     return rc;
 }
 
@@ -759,6 +811,50 @@ int orc_alg1_cap(const orc_problem *P, const int32_t *cap0, int32_t gnum, int32_
  * and the capacities), after which the replay applies the block's cached actions.
  * O(T*N) per pass.  changed (nullable) receives |{t : alpha^k_t != alpha^{k-1}_t}| per
  * pass.  Other arguments and the return value as orc_alg1. */
+typedef struct {
+    const orc_problem *P;
+    const int32_t *cap0, *rk;
+    int32_t gnum, gden;
+    int64_t B;
+    int32_t *x, *xp, *c, *cp; /* shared replay, private rows, shared and private capacities */
+    int64_t *stamp;           /* block that last copied a SKU's row into xp */
+} blocks_cap_ctx;
+
+static void timeblocks_cap_pass(void *vctx, const int32_t *prev, int32_t *next)
+{
+    const blocks_cap_ctx *q = (const blocks_cap_ctx *)vctx;
+    const orc_problem *P = q->P;
+    const int N = P->N;
+    const int64_t T = P->T, B = q->B;
+    int32_t *x = q->x, *xp = q->xp, *c = q->c, *cp = q->cp;
+    memcpy(x, P->x0, sizeof(int32_t) * (size_t)P->K * N);
+    memcpy(c, q->cap0, sizeof(int32_t) * (size_t)N);
+    for (int64_t i = 0; i < P->K; ++i) q->stamp[i] = -1;
+    for (int64_t m = 0; m * B < T; ++m) {
+        const int64_t lo = m * B, hi = lo + B < T ? lo + B : T;
+        /* process m: fresh decisions from the shared state */
+        memcpy(cp, c, sizeof(int32_t) * (size_t)N);
+        for (int64_t t = lo; t < hi; ++t) {
+            const int64_t s = P->sku[t];
+            int32_t *xk = xp + s * N;
+            if (q->stamp[s] != m) {
+                memcpy(xk, x + s * N, sizeof(int32_t) * (size_t)N);
+                q->stamp[s] = m;
+            }
+            const int32_t a = greedy_cap(P, t, xk, cp, q->gnum, q->gden, q->rk);
+            transition_cap(xk, cp, a);
+            next[t] = a;
+        }
+        /* the shared replay applies the block's cached actions */
+        for (int64_t t = lo; t < hi; ++t) {
+            int32_t *xk = x + (int64_t)P->sku[t] * N;
+            int32_t a = prev[t];
+            if (a != LOST && (a < 0 || a >= N || xk[a] <= 0 || c[a] <= 0)) a = LOST;
+            transition_cap(xk, c, a);
+        }
+    }
+}
+
 int orc_picard_timeblocks_cap(const orc_problem *P, const int32_t *cap0, int32_t gnum,
                               int32_t gden, int64_t B, const int32_t *init_cache,
                               int32_t max_passes, int32_t *final_cache, int32_t *passes,
@@ -768,58 +864,18 @@ int orc_picard_timeblocks_cap(const orc_problem *P, const int32_t *cap0, int32_t
     const int N = P->N, K = P->K;
     int32_t *rk = rank_table(P, gnum);
     if (gnum && !rk) return -1;
-    const int64_t T = P->T, KN = (int64_t)K * N;
-    int32_t *prev = (int32_t *)malloc(sizeof(int32_t) * (size_t)(T + 1));
-    int32_t *next = (int32_t *)malloc(sizeof(int32_t) * (size_t)(T + 1));
-    int32_t *x = (int32_t *)malloc(sizeof(int32_t) * (size_t)KN);     /* shared replay */
-    int32_t *xp = (int32_t *)malloc(sizeof(int32_t) * (size_t)KN);    /* private rows  */
-    int64_t *stamp = (int64_t *)malloc(sizeof(int64_t) * (size_t)K);  /* row copied in */
+    const int64_t KN = (int64_t)K * N;
+    int32_t *x = (int32_t *)malloc(sizeof(int32_t) * (size_t)KN);
+    int32_t *xp = (int32_t *)malloc(sizeof(int32_t) * (size_t)KN);
+    int64_t *stamp = (int64_t *)malloc(sizeof(int64_t) * (size_t)K);
     int32_t *c = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
     int32_t *cp = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
-    if (!prev || !next || !x || !xp || !stamp || !c || !cp) {
-        free(prev); free(next); free(x); free(xp); free(stamp); free(c); free(cp); free(rk);
-        return -1;
+    int rc = -1;
+    if (x && xp && stamp && c && cp) {
+        blocks_cap_ctx ctx = {P, cap0, rk, gnum, gden, B, x, xp, c, cp, stamp};
+        rc = run_passes(timeblocks_cap_pass, &ctx, P->T, init_cache, max_passes, final_cache,
+                        passes, changed, caches);
     }
-    for (int64_t t = 0; t < T; ++t) prev[t] = init_cache ? init_cache[t] : LOST;
-    int rc = 1;
-    int32_t k;
-    for (k = 1; k <= max_passes; ++k) {
-        memcpy(x, P->x0, sizeof(int32_t) * (size_t)KN);
-        memcpy(c, cap0, sizeof(int32_t) * (size_t)N);
-        for (int64_t i = 0; i < K; ++i) stamp[i] = -1;
-        for (int64_t m = 0; m * B < T; ++m) {
-            const int64_t lo = m * B, hi = lo + B < T ? lo + B : T;
-            /* process m: fresh decisions from the shared state */
-            memcpy(cp, c, sizeof(int32_t) * (size_t)N);
-            for (int64_t t = lo; t < hi; ++t) {
-                const int64_t s = P->sku[t];
-                int32_t *xk = xp + s * N;
-                if (stamp[s] != m) {
-                    memcpy(xk, x + s * N, sizeof(int32_t) * (size_t)N);
-                    stamp[s] = m;
-                }
-                const int32_t a = greedy_cap(P, t, xk, cp, gnum, gden, rk);
-                transition_cap(xk, cp, a);
-                next[t] = a;
-            }
-            /* the shared replay applies the block's cached actions */
-            for (int64_t t = lo; t < hi; ++t) {
-                int32_t *xk = x + (int64_t)P->sku[t] * N;
-                int32_t a = prev[t];
-                if (a != LOST && (a < 0 || a >= N || xk[a] <= 0 || c[a] <= 0)) a = LOST;
-                transition_cap(xk, c, a);
-            }
-        }
-        if (caches) memcpy(caches + (int64_t)(k - 1) * T, next, sizeof(int32_t) * (size_t)T);
-        int64_t nch = 0;
-        for (int64_t t = 0; t < T; ++t) nch += next[t] != prev[t];
-        if (changed) changed[k - 1] = nch;
-        int32_t *tmp = prev; prev = next; next = tmp;
-        if (nch == 0) { rc = 0; break; }
-    }
-    if (k > max_passes) k = max_passes;
-    *passes = k;
-    memcpy(final_cache, prev, sizeof(int32_t) * (size_t)T);
-    free(prev); free(next); free(x); free(xp); free(stamp); free(c); free(cp); free(rk);
+    free(x); free(xp); free(stamp); free(c); free(cp); free(rk);
     return rc;
 }

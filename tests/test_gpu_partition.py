@@ -2,7 +2,7 @@
 
 Uniform random partitions (Section 4.1) give a process several runs of one SKU; product
 partitions (Section 3) one run per SKU.  Against the oracle's run form under the same
-partition (itself pinned pass by pass to the literal Algorithm 1): actions, units
+partition (itself pinned pass by pass to the brute-force Algorithm 1): actions, units
 shipped, final inventory and passes bit-exact, the cache after every pass, warm starts,
 the no-frontier mode, ragged batches; at 1e6 orders the converged actions against the
 serial oracle.  Learned policy: Picard equals the GPU's serial sweep bit for bit, and the

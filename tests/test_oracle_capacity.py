@@ -10,7 +10,7 @@ node j only if c_{t,j} > 0 and x_{t,i,j} > 0, and shipping lowers both by one).
 * Invariants: capacities and stock never negative; what left a node equals its capacity
   drop.
 * Algorithm 1: any fixed point equals the serial rollout; Proposition 2.1 (k* <= T for
-  any partition and any initial cache); the time-block replay equals the literal
+  any partition and any initial cache); the time-block replay equals the brute-force
   algorithm pass by pass.
 * Section 3.1, special case (stock never binds, greedy policy): Lemma 3.2's invariant
   (every cached action is the serial one or a node already out of capacity at that
@@ -324,7 +324,7 @@ def test_gamma_large_picks_most_capacity(oracle, seed):
 @pytest.mark.parametrize("seed", range(20))
 def test_gamma_picard(oracle, seed):
     """Proposition 2.1 for the capacity-dependent policy (the bound of Theorem 3.1 does not
-    apply: the policy breaks Assumption 3), and the time-block replay against the literal
+    apply: the policy breaks Assumption 3), and the time-block replay against the brute-force
     Algorithm 1 pass by pass."""
     inst, cap0 = _tiny(seed, N=2 + seed % 5, K=1 + seed % 3, R=1 + seed % 3, T=16, inv_max=3)
     T = int(inst.traj_offsets[-1])

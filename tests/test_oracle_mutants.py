@@ -35,10 +35,16 @@ MUTANTS = [
      "int32_t sh = x[a] < q ? x[a] : q;", "int32_t sh = q;"),
     ("transition_ships_one_unit", "x[a] -= sh;", "x[a] -= sh > 0 ? 1 : 0;"),
     ("alg1_state_not_reset_per_process",
-     "memcpy(x, P->x0, sizeof(int32_t) * (size_t)KN); /* s_1^{k,m} = s_1 */",
-     "if (proc == 0) memcpy(x, P->x0, sizeof(int32_t) * (size_t)KN);"),
-    ("alg1_own_steps_not_recorded", "next[t] = a; /* alpha^k_t",
-     "next[t] = prev[t]; /* alpha^k_t"),
+     "memcpy(x, P->x0, sizeof(int32_t) * (size_t)P->K * N); /* every view starts at s_1 */\n    for (int64_t t = 0; t < P->T; ++t) {\n        int32_t *xk = x + (int64_t)P->sku[t] * N;\n        int32_t a;\n        if (!owner || owner[t] == self) {\n            double",
+     "if (self == 0) memcpy(x, P->x0, sizeof(int32_t) * (size_t)P->K * N);\n    for (int64_t t = 0; t < P->T; ++t) {\n        int32_t *xk = x + (int64_t)P->sku[t] * N;\n        int32_t a;\n        if (!owner || owner[t] == self) {\n            double"),
+    ("alg1_own_steps_not_recorded",
+     "            a = policy(P, m, t, xk, &a1, &a2);\n            decided[t] = a;",
+     "            a = policy(P, m, t, xk, &a1, &a2);\n            decided[t] = given ? given[t] : a;"),
+    # (keeping a cached action whose warehouse has no stock is not listed: it ships
+    # min(q, 0) = 0 units, exactly what the lost sale does, so no state or action changes)
+    ("alg1_stops_one_pass_early",
+     "        if (nch == 0) { rc = 0; break; }",
+     "        if (nch <= 1) { rc = 0; break; }"),
     ("runs_consumption_from_current_pass",
      "if (prev[t] != LOST) E[prev[t]] += P->qty[t];",
      "if (next[t] != LOST) E[next[t]] += P->qty[t];"),
@@ -96,10 +102,10 @@ MUTANTS = [
     # every action is unchanged)
     ("cap_blocks_rows_from_initial_stock", "memcpy(xk, x + s * N,", "memcpy(xk, P->x0 + s * N,"),
     ("cap_blocks_capacity_from_initial", "memcpy(cp, c, sizeof(int32_t) * (size_t)N);",
-     "memcpy(cp, cap0, sizeof(int32_t) * (size_t)N);"),
+     "memcpy(cp, q->cap0, sizeof(int32_t) * (size_t)N);"),
     ("cap_blocks_replay_of_fresh_actions",
-     "                int32_t a = prev[t];\n                if (a != LOST && (a < 0 || a >= N || xk[a] <= 0 || c[a] <= 0))",
-     "                int32_t a = next[t];\n                if (a != LOST && (a < 0 || a >= N || xk[a] <= 0 || c[a] <= 0))"),
+     "            int32_t a = prev[t];\n            if (a != LOST && (a < 0 || a >= N || xk[a] <= 0 || c[a] <= 0))",
+     "            int32_t a = next[t];\n            if (a != LOST && (a < 0 || a >= N || xk[a] <= 0 || c[a] <= 0))"),
 ]
 
 

@@ -10,7 +10,7 @@
 * Block partitions: run j of a segment is exact by pass j (Proposition 2.1's induction
   with runs as units), so k* <= max number of runs of a segment; a product partition
   (Section 3) gives k* <= 1.
-* The run form equals the literal algorithm pass by pass on random tiny instances.
+* The run form equals the brute-force algorithm pass by pass on random tiny instances.
 """
 import numpy as np
 import pytest

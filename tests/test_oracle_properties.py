@@ -1,13 +1,13 @@
 """Property-based pins of the oracle (hypothesis): random tiny instances, partitions and
 initial caches, shrunk to a minimal case on failure.
 
-- Algorithm 1 taken literally and the run form give the same cache after every pass and
+- Algorithm 1 by brute force and the run form give the same cache after every pass and
   the same pass count, for any partition and initial cache.
 - Proposition 2.1: from any initial cache the iteration returns within T + 1 passes
   with the serial rollout's actions.
 - The advantages of a rollout: consecutive differences are the step rewards, they sum
   to zero over the trajectory, and the first step's reward-to-go is the total reward.
-- With node capacity (either policy): the time-block replay equals the literal
+- With node capacity (either policy): the time-block replay equals the brute-force
   Algorithm 1 pass by pass and reaches the serial rollout within T + 1 passes.
 """
 import numpy as np
@@ -113,7 +113,7 @@ def tiny_capacity_case(draw):
 @SETTINGS
 @given(tiny_capacity_case())
 def test_capacity_time_blocks_equal_alg1(oracle, case):
-    """With node capacity, for either policy: the time-block replay equals the literal
+    """With node capacity, for either policy: the time-block replay equals the brute-force
     Algorithm 1 under the same blocks pass by pass, and both end at the serial rollout
     within T + 1 passes from any initial cache (Proposition 2.1)."""
     inst, cap0, B, init, gamma = case
