@@ -61,6 +61,9 @@ def load(path: str):
     vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
     L.orc_serial.argtypes = [P, vp, vp, vp, vp, vp]
     L.orc_eval_at.argtypes = [P, vp, vp, vp, vp, vp]
+    L.orc_eval_at_range.argtypes = [P, vp, i64, i64, vp, vp, vp, vp]
+    L.orc_reinforce_range.argtypes = [P, vp, vp, i64, i64, vp, vp, vp]
+    L.orc_policy_at.argtypes = [P, i64, vp, vp, vp, vp, vp]
     L.orc_alg1.argtypes = [P, vp, i64, vp, i32, vp, vp, vp]
     L.orc_picard_runs.argtypes = [P, vp, vp, i32, vp, vp, vp, vp]
     L.orc_reinforce.argtypes = [P, vp, vp, vp, vp, vp]
@@ -91,7 +94,10 @@ class _Bound:
         self.sku = np.ascontiguousarray(inst.sku[lo:hi], dtype=np.int32)
         self.region = np.ascontiguousarray(inst.region[lo:hi], dtype=np.int32)
         self.qty = np.ascontiguousarray(inst.qty[lo:hi], dtype=np.int32)
-        self.x0 = np.ascontiguousarray(inst.x0[b], dtype=np.int32)
+        # the per-state policy (policy_at) reads no initial inventory: workloads whose x0
+        # is only a generator bind none
+        self.x0 = (None if inst.x0 is None
+                   else np.ascontiguousarray(inst.x0[b], dtype=np.int32))
         self.cost = np.ascontiguousarray(inst.cost[b], dtype=np.int32)
         self.params = (None if inst.params is None
                        else np.ascontiguousarray(inst.params, dtype=np.float32))
@@ -122,8 +128,27 @@ def serial(inst, b: int = 0, greedy: bool = False) -> dict:
     return dict(actions=act, shipped=sh, final_inv=fin, z1=z1, z2=z2)
 
 
-def eval_at(inst, actions: np.ndarray, b: int = 0) -> dict:
-    """Policy choice and top-two perturbed scores at the states a given sequence induces."""
+def _windows(T: int, n: int):
+    """[0, T) cut into at most n consecutive windows."""
+    n = max(1, min(int(n), max(T, 1)))
+    cuts = [T * i // n for i in range(n + 1)]
+    return [(cuts[i], cuts[i + 1]) for i in range(n)]
+
+
+def _in_threads(fn, jobs, threads: int):
+    """Run fn over jobs in a thread pool (the oracle's C calls release the GIL) and
+    return the results in job order."""
+    if threads <= 1 or len(jobs) <= 1:
+        return [fn(j) for j in jobs]
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        return list(ex.map(fn, jobs))
+
+
+def eval_at(inst, actions: np.ndarray, b: int = 0, threads: int = 1) -> dict:
+    """Policy choice and top-two perturbed scores at the states a given sequence induces.
+    threads > 1 evaluates disjoint windows of steps at once (each window replays the
+    given actions up to its start)."""
     B = _Bound(inst, b)
     T = B.T
     actions = np.ascontiguousarray(actions, dtype=np.int32)
@@ -131,11 +156,37 @@ def eval_at(inst, actions: np.ndarray, b: int = 0) -> dict:
     z1 = np.empty(T, np.float64)
     z2 = np.empty(T, np.float64)
     nf = np.empty(T, np.int32)
-    rc = lib().orc_eval_at(C.byref(B.p), _ptr(actions), _ptr(ch), _ptr(z1), _ptr(z2), _ptr(nf))
-    _check(rc, "eval_at")
-    if rc == -2:
+    if threads <= 1:
+        rcs = [lib().orc_eval_at(C.byref(B.p), _ptr(actions), _ptr(ch), _ptr(z1), _ptr(z2),
+                                 _ptr(nf))]
+    else:
+        rcs = _in_threads(lambda w: lib().orc_eval_at_range(
+            C.byref(B.p), _ptr(actions), w[0], w[1], _ptr(ch), _ptr(z1), _ptr(z2), _ptr(nf)),
+            _windows(T, 4 * threads), threads)
+    for rc in rcs:
+        _check(rc, "eval_at")
+    if any(rc == -2 for rc in rcs):
         raise ValueError("action sequence is infeasible")
     return dict(choice=ch, z1=z1, z2=z2, n_feasible=nf)
+
+
+def policy_at(inst, b: int, ts: np.ndarray, x_rows: np.ndarray, threads: int = 1) -> dict:
+    """The policy at given states: order ts[i] of trajectory b (time index within the
+    trajectory) with its SKU's inventory row x_rows[i] ([n, N]).  Returns the choice and
+    the top two perturbed scores per state."""
+    B = _Bound(inst, b)
+    ts = np.ascontiguousarray(ts, dtype=np.int64)
+    x_rows = np.ascontiguousarray(x_rows, dtype=np.int32).reshape(ts.size, inst.N)
+    n = ts.size
+    ch = np.empty(n, np.int32)
+    z1 = np.empty(n, np.float64)
+    z2 = np.empty(n, np.float64)
+    rcs = _in_threads(lambda w: lib().orc_policy_at(
+        C.byref(B.p), w[1] - w[0], _ptr(ts[w[0]:]), _ptr(x_rows[w[0]:]), _ptr(ch[w[0]:]),
+        _ptr(z1[w[0]:]), _ptr(z2[w[0]:])), _windows(n, 4 * max(threads, 1)), threads)
+    for rc in rcs:
+        _check(rc, "policy_at")
+    return dict(choice=ch, z1=z1, z2=z2)
 
 
 def alg1(inst, worker: np.ndarray, n_workers: int, b: int = 0, init_cache=None,
@@ -254,22 +305,40 @@ def time_block_workers(T: int, block_len: int) -> np.ndarray:
 
 
 def reinforce(inst, actions: np.ndarray, adv: np.ndarray, b: int = 0,
-              want_grad: bool = True) -> dict:
-    """FP64 surrogate L = sum_t A_t log pi(a_t|s_t), per-step log pi and dL/dtheta."""
+              want_grad: bool = True, threads: int = 1) -> dict:
+    """FP64 surrogate L = sum_t A_t log pi(a_t|s_t), per-step log pi and dL/dtheta.
+    threads > 1 sums the terms of disjoint windows of steps computed at once (in window
+    order)."""
     B = _Bound(inst, b)
     T = B.T
     actions = np.ascontiguousarray(actions, dtype=np.int32)
     adv = np.ascontiguousarray(adv, dtype=np.float64)
     n = int(lib().orc_param_count(inst.R, inst.hidden, inst.n_hidden_layers))
     logp = np.empty(T, np.float64)
-    grad = np.empty(n, np.float64) if want_grad else None
-    L = np.zeros(1, np.float64)
-    rc = lib().orc_reinforce(C.byref(B.p), _ptr(actions), _ptr(adv), _ptr(logp), _ptr(grad),
-                             _ptr(L))
-    if rc == -2:
-        raise ValueError("an action is outside the feasible set of its state")
-    _check(rc, "reinforce")
-    return dict(objective=float(L[0]), logp=logp, grad=grad)
+    if threads <= 1:
+        grad = np.empty(n, np.float64) if want_grad else None
+        L = np.zeros(1, np.float64)
+        rc = lib().orc_reinforce(C.byref(B.p), _ptr(actions), _ptr(adv), _ptr(logp),
+                                 _ptr(grad), _ptr(L))
+        parts = [(rc, grad, L)]
+    else:
+        def one(w):
+            g = np.empty(n, np.float64) if want_grad else None
+            L = np.zeros(1, np.float64)
+            rc = lib().orc_reinforce_range(C.byref(B.p), _ptr(actions), _ptr(adv), w[0], w[1],
+                                           _ptr(logp), _ptr(g), _ptr(L))
+            return rc, g, L
+        parts = _in_threads(one, _windows(T, 4 * threads), threads)
+    for rc, _, _ in parts:
+        if rc == -2:
+            raise ValueError("an action is outside the feasible set of its state")
+        _check(rc, "reinforce")
+    grad = None
+    if want_grad:
+        grad = parts[0][1].copy()
+        for _, g, _ in parts[1:]:
+            grad += g
+    return dict(objective=float(sum(float(L[0]) for _, _, L in parts)), logp=logp, grad=grad)
 
 
 def mlp_scores(inst, r: int, x_row: np.ndarray, b: int = 0) -> np.ndarray:

@@ -342,10 +342,22 @@ static int run_passes(pass_fn pass, void *ctx, int64_t T, const int32_t *init_ca
  * n_feasible[t] = |{w : x[w] > 0}|.  Any pointer but actions/choice may be NULL.
  * Returns -2 if a given action is infeasible at its state (it cannot come from pi).
  * ---------------------------------------------------------------------------------- */
+int orc_eval_at_range(const orc_problem *P, const int32_t *actions, int64_t lo, int64_t hi,
+                      int32_t *choice, double *z1, double *z2, int32_t *n_feasible);
+
 int orc_eval_at(const orc_problem *P, const int32_t *actions, int32_t *choice, double *z1,
                 double *z2, int32_t *n_feasible)
 {
-    if (check_problem(P)) return -1;
+    return orc_eval_at_range(P, actions, 0, P->T, choice, z1, z2, n_feasible);
+}
+
+/* The same, with the policy evaluated only at steps lo <= t < hi (outputs written there
+ * only): the steps before lo just apply their given actions, so disjoint windows can be
+ * evaluated independently. */
+int orc_eval_at_range(const orc_problem *P, const int32_t *actions, int64_t lo, int64_t hi,
+                      int32_t *choice, double *z1, double *z2, int32_t *n_feasible)
+{
+    if (check_problem(P) || lo < 0 || hi > P->T || lo > hi) return -1;
     const int N = P->N;
     mlp64 m = {0};
     if (P->params && mlp_load(&m, P)) return -1;
@@ -353,8 +365,14 @@ int orc_eval_at(const orc_problem *P, const int32_t *actions, int32_t *choice, d
     if (!x) { mlp_free(&m); return -1; }
     memcpy(x, P->x0, sizeof(int32_t) * (size_t)P->K * N);
     int rc = 0;
-    for (int64_t t = 0; t < P->T; ++t) {
+    for (int64_t t = 0; t < hi; ++t) {
         int32_t *xk = x + (int64_t)P->sku[t] * N;
+        if (t < lo) { /* replay only */
+            int32_t a = actions[t];
+            if (a != LOST && (a < 0 || a >= N || xk[a] <= 0)) { rc = -2; break; }
+            transition(xk, a, P->qty[t]);
+            continue;
+        }
         double a1 = -INFINITY, a2 = -INFINITY;
         choice[t] = policy(P, &m, t, xk, &a1, &a2);
         if (z1) z1[t] = a1;
@@ -512,10 +530,22 @@ done:
  * log pi(a_t | s_t); grad (nullable) the gradient in the parameter-pack layout.
  * Returns -2 when an action is not in the feasible set of its state.
  * ---------------------------------------------------------------------------------- */
+int orc_reinforce_range(const orc_problem *P, const int32_t *actions, const double *adv,
+                        int64_t lo, int64_t hi, double *logp, double *grad, double *objective);
+
 int orc_reinforce(const orc_problem *P, const int32_t *actions, const double *adv,
                   double *logp, double *grad, double *objective)
 {
-    if (check_problem(P) || !P->params) return -1;
+    return orc_reinforce_range(P, actions, adv, 0, P->T, logp, grad, objective);
+}
+
+/* The terms of steps lo <= t < hi only (the steps before lo just apply their actions):
+ * the surrogate and its gradient are sums over steps, so the sum over disjoint windows
+ * covering [0, T) is the whole. */
+int orc_reinforce_range(const orc_problem *P, const int32_t *actions, const double *adv,
+                        int64_t lo, int64_t hi, double *logp, double *grad, double *objective)
+{
+    if (check_problem(P) || !P->params || lo < 0 || hi > P->T || lo > hi) return -1;
     const int N = P->N, R = P->R;
     mlp64 m = {0};
     if (mlp_load(&m, P)) return -1;
@@ -545,10 +575,15 @@ int orc_reinforce(const orc_problem *P, const int32_t *actions, const double *ad
     if (!x || !s || !F || !PRE1 || !H1 || !PRE2 || !H2 || !dh || !dp2 || !dp1) { rc = -1; goto out; }
     memcpy(x, P->x0, sizeof(int32_t) * (size_t)P->K * N);
     double L = 0.0;
-    for (int64_t t = 0; t < P->T; ++t) {
+    for (int64_t t = 0; t < hi; ++t) {
         int32_t *xk = x + (int64_t)P->sku[t] * N;
         const int r = P->region[t];
         const int32_t a = actions[t];
+        if (t < lo) { /* replay only */
+            if (a != LOST && (a < 0 || a >= N || xk[a] <= 0)) { rc = -2; break; }
+            transition(xk, a, P->qty[t]);
+            continue;
+        }
         int nf = 0;
         for (int w = 0; w < N; ++w) nf += xk[w] > 0;
         if (nf == 0) {
@@ -613,6 +648,30 @@ int orc_reinforce(const orc_problem *P, const int32_t *actions, const double *ad
 out:
     free(x); free(s); free(F); free(PRE1); free(H1); free(PRE2); free(H2);
     free(dh); free(dp2); free(dp1);
+    mlp_free(&m);
+    return rc;
+}
+
+/* The policy pi(s_t, w_t) at given states: for i < n, order ts[i] of the trajectory
+ * (its region and noise) with its SKU's inventory row x_rows[i * N .. i * N + N) (the other
+ * SKUs' rows do not enter the decision).  choice[i], and z1[i] >= z2[i] the two largest
+ * perturbed scores among warehouses with stock (nullable).  Only the orders' regions,
+ * the costs, the parameters and the noise key of P are read. */
+int orc_policy_at(const orc_problem *P, int64_t n, const int64_t *ts, const int32_t *x_rows,
+                  int32_t *choice, double *z1, double *z2)
+{
+    if (P->N <= 0 || P->R <= 0 || n < 0) return -1;
+    mlp64 m = {0};
+    if (P->params && mlp_load(&m, P)) return -1;
+    int rc = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t t = ts[i];
+        if (t < 0 || t >= P->T || P->region[t] < 0 || P->region[t] >= P->R) { rc = -1; break; }
+        double a1 = -INFINITY, a2 = -INFINITY;
+        choice[i] = policy(P, &m, t, x_rows + i * (int64_t)P->N, &a1, &a2);
+        if (z1) z1[i] = a1;
+        if (z2) z2[i] = a2;
+    }
     mlp_free(&m);
     return rc;
 }

@@ -37,6 +37,12 @@ int orc_serial(const orc_problem *P, int32_t *actions, int32_t *shipped, int32_t
                double *z1, double *z2);
 int orc_eval_at(const orc_problem *P, const int32_t *actions, int32_t *choice, double *z1,
                 double *z2, int32_t *n_feasible);
+int orc_eval_at_range(const orc_problem *P, const int32_t *actions, int64_t lo, int64_t hi,
+                      int32_t *choice, double *z1, double *z2, int32_t *n_feasible);
+int orc_reinforce_range(const orc_problem *P, const int32_t *actions, const double *adv,
+                        int64_t lo, int64_t hi, double *logp, double *grad, double *objective);
+int orc_policy_at(const orc_problem *P, int64_t n, const int64_t *ts, const int32_t *x_rows,
+                  int32_t *choice, double *z1, double *z2);
 int orc_alg1(const orc_problem *P, const int64_t *worker, int64_t n_workers,
              const int32_t *init_cache, int32_t max_passes, int32_t *final_cache,
              int32_t *passes, int32_t *caches);
@@ -119,6 +125,25 @@ int main(void)
             CHECK(orc_serial(&P, act, sh, fin, z1, z2) == 0, "orc_serial");
             CHECK(orc_eval_at(&P, act, ch, z1, z2, nf) == 0, "orc_eval_at");
             for (int64_t t = 0; t < T; ++t) CHECK(ch[t] == act[t], "eval_at at the serial actions");
+            {   /* the same over two windows, and the policy at the states of a replay */
+                const int64_t mid = T / 2;
+                int32_t *ch2 = malloc(sizeof(int32_t) * (T + 1));
+                CHECK(orc_eval_at_range(&P, act, 0, mid, ch2, NULL, NULL, NULL) == 0 &&
+                      orc_eval_at_range(&P, act, mid, T, ch2, NULL, NULL, NULL) == 0, "windows");
+                for (int64_t t = 0; t < T; ++t) CHECK(ch2[t] == act[t], "windowed eval_at");
+                int32_t *rows = malloc(sizeof(int32_t) * (T + 1) * N), *xr = malloc(sizeof(int32_t) * K * N);
+                int64_t *ts = malloc(sizeof(int64_t) * (T + 1));
+                memcpy(xr, x0, sizeof(int32_t) * K * N);
+                for (int64_t t = 0; t < T; ++t) {
+                    int32_t *xk = xr + (int64_t)sku[t] * N;
+                    memcpy(rows + t * N, xk, sizeof(int32_t) * N);
+                    ts[t] = t;
+                    if (act[t] >= 0) xk[act[t]] -= xk[act[t]] < qty[t] ? xk[act[t]] : qty[t];
+                }
+                CHECK(orc_policy_at(&P, T, ts, rows, ch2, NULL, NULL) == 0, "orc_policy_at");
+                for (int64_t t = 0; t < T; ++t) CHECK(ch2[t] == act[t], "policy at replayed states");
+                free(ch2); free(rows); free(xr); free(ts);
+            }
             int32_t p1 = 0, p2 = 0;
             const int32_t *ic = ci % 2 ? init : NULL;
             const int r1 = orc_alg1(&P, worker, nw, ic, MAXP, fc, &p1, caches);
@@ -135,6 +160,9 @@ int main(void)
                 double *g = malloc(sizeof(double) * np), obj = 0.0;
                 for (int64_t t = 0; t < T; ++t) adv[t] = ((double)(rnd() % 200) - 100.0) / 50.0;
                 CHECK(orc_reinforce(&P, act, adv, lp, g, &obj) == 0, "orc_reinforce");
+                double obj2 = 0.0;
+                CHECK(orc_reinforce_range(&P, act, adv, T / 3, T, lp, g, &obj2) == 0,
+                      "orc_reinforce_range");
                 CHECK(isfinite(obj), "finite objective");
                 double *s = malloc(sizeof(double) * N);
                 CHECK(orc_mlp_scores(&P, 0, x0, s) == 0, "orc_mlp_scores");

@@ -282,3 +282,46 @@ def test_reinforce_rejects_infeasible_action(oracle):
     bad[t] = -1
     with pytest.raises(ValueError):
         oracle.reinforce(inst, bad, adv)
+
+
+# ---------------------------------------------------------------- windows and given states
+def test_windows_equal_whole_horizon(oracle):
+    """eval_at and reinforce over disjoint windows of steps (run in threads; each window
+    replays the given actions up to its start) equal one pass over the whole horizon:
+    the same choices and scores bit for bit, and the gradient and objective to FP64
+    rounding of the regrouped sum."""
+    inst = random_tiny(65, N=7, K=3, R=4, T=400, qmax=3, inv_max=9, mlp=True)
+    actions, adv = _rollout_with_adv(oracle, inst, 5)
+    whole = oracle.eval_at(inst, actions)
+    win = oracle.eval_at(inst, actions, threads=3)
+    for k in whole:
+        np.testing.assert_array_equal(win[k], whole[k])
+    r1 = oracle.reinforce(inst, actions, adv)
+    r2 = oracle.reinforce(inst, actions, adv, threads=3)
+    np.testing.assert_array_equal(r2["logp"], r1["logp"])
+    np.testing.assert_allclose(r2["grad"], r1["grad"], rtol=1e-12,
+                               atol=1e-12 * np.abs(r1["grad"]).max())
+    assert abs(r2["objective"] - r1["objective"]) <= 1e-12 * (1 + abs(r1["objective"]))
+
+
+def test_policy_at_states_of_a_replay(oracle):
+    """The policy at given states (the order's SKU row before each step, from a plain
+    Python replay of the serial actions) gives eval_at's choice and top two scores at
+    every step, and the serial rollout's action."""
+    inst = random_tiny(66, N=6, K=3, R=4, T=150, qmax=2, inv_max=6, mlp=True)
+    ser = oracle.serial(inst)
+    x = inst.x0[0].astype(np.int64).copy()
+    rows = np.empty((inst.total_orders, inst.N), np.int32)
+    for t in range(inst.total_orders):
+        k, a = inst.sku[t], ser["actions"][t]
+        rows[t] = x[k]
+        if a >= 0:
+            x[k, a] -= min(inst.qty[t], x[k, a])
+    ts = np.arange(inst.total_orders)
+    perm = np.random.default_rng(2).permutation(ts.size)  # any order of the states
+    got = oracle.policy_at(inst, 0, ts[perm], rows[perm], threads=2)
+    ev = oracle.eval_at(inst, ser["actions"])
+    np.testing.assert_array_equal(got["choice"], ev["choice"][perm])
+    np.testing.assert_array_equal(got["choice"], ser["actions"][perm])
+    np.testing.assert_array_equal(got["z1"], ev["z1"][perm])
+    np.testing.assert_array_equal(got["z2"], ev["z2"][perm])

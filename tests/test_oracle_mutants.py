@@ -58,6 +58,15 @@ MUTANTS = [
     ("philox_multiplier_swapped",
      "uint64_t p0 = (uint64_t)M0 * c0;", "uint64_t p0 = (uint64_t)M1 * c0;"),
     ("philox_nine_rounds", "round < 10", "round < 9"),
+    ("eval_window_replay_skips_transition",
+     "int32_t a = actions[t];\n            if (a != LOST && (a < 0 || a >= N || xk[a] <= 0)) { rc = -2; break; }\n            transition(xk, a, P->qty[t]);",
+     "int32_t a = actions[t];\n            if (a != LOST && (a < 0 || a >= N || xk[a] <= 0)) { rc = -2; break; }"),
+    ("reinforce_window_replay_skips_transition",
+     "/* replay only */\n            if (a != LOST && (a < 0 || a >= N || xk[a] <= 0)) { rc = -2; break; }\n            transition(xk, a, P->qty[t]);",
+     "/* replay only */\n            if (a != LOST && (a < 0 || a >= N || xk[a] <= 0)) { rc = -2; break; }"),
+    ("policy_at_reads_first_row",
+     "choice[i] = policy(P, &m, t, x_rows + i * (int64_t)P->N, &a1, &a2);",
+     "choice[i] = policy(P, &m, t, x_rows, &a1, &a2);"),
     ("philox_key_not_bumped", "k1 += W1;", "k1 += 0;"),
     ("uniform_left_edge_of_bin", "(double)(u >> 9) + 0.5", "(double)(u >> 9) + 0.0"),
     ("uniform_same_word_for_all", "uint32_t u = out[w & 3];", "uint32_t u = out[0];"),
