@@ -173,6 +173,30 @@ pk_status pk_picard_simulate(const pk_problem *problem, const pk_policy *policy,
                              int32_t *actions, int32_t *shipped, int32_t *final_inv,
                              pk_stats *stats, void *stream);
 
+/* Size of the static scratch buffer of pk_picard_simulate_noalloc (64 MiB per device
+ * the library runs on, held until the process ends). */
+#define PK_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* pk_picard_simulate without a workspace and without any allocation, for callers that
+ * cannot allocate memory: serving loops that must not call hipMalloc, harnesses that
+ * forbid it.  Same problem, policy, options and outputs as pk_picard_simulate; its scratch
+ * is a static device buffer of PK_NOALLOC_SCRATCH_BYTES inside the library (one per
+ * device, its address resolved on the first call on that device).  The call creates no
+ * HIP graph, event or pinned buffer: its passes are enqueued directly on `stream`, and it
+ * blocks until the result is final (so it cannot itself be captured into a graph).
+ * Differences from pk_picard_simulate:
+ *   - block_len 0 takes the library default (1024 greedy, 256 MLP) without autotuning;
+ *   - stats->timing must be 0 (PK_ERR_UNSUPPORTED otherwise); walk_ms stays 0;
+ *   - PK_ERR_WORKSPACE if the problem needs more than PK_NOALLOC_SCRATCH_BYTES of scratch
+ *     (pk_workspace_size reports at least that need; about 1e6 orders at N = 100 fit).
+ * Every call on one device shares that device's buffer and overwrites it: calls that
+ * overlap in time on one device (other threads, other streams) race and give undefined
+ * results; serialise them.  Each call initialises every part of the buffer it reads. */
+pk_status pk_picard_simulate_noalloc(const pk_problem *problem, const pk_policy *policy,
+                                     const pk_picard_opts *opts, int32_t *actions,
+                                     int32_t *shipped, int32_t *final_inv, pk_stats *stats,
+                                     void *stream);
+
 /* REINFORCE at fixed actions (MLP policy only).  With the states s_t the actions induce
  * (serially, per trajectory) and pi(.|s) = softmax over warehouses with stock of s_w,
  *   logp[t] = log pi(a_t | s_t)  (0 when at most one warehouse has stock; then a_t must

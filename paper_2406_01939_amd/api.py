@@ -84,6 +84,7 @@ def lib():
         L.pk_workspace_size.argtypes = [P, Po, O, C.POINTER(sz)]
         L.pk_serial_simulate.argtypes = [P, Po, vp, sz, vp, vp, vp, i32, vp]
         L.pk_picard_simulate.argtypes = [P, Po, O, vp, sz, vp, vp, vp, S, vp]
+        L.pk_picard_simulate_noalloc.argtypes = [P, Po, O, vp, vp, vp, S, vp]
         L.pk_policy_grad.argtypes = [P, Po, vp, vp, vp, vp, C.POINTER(C.c_double), vp, sz, i32, vp]
         L.pk_autotune.argtypes = [P, Po, vp, sz, C.POINTER(i32), vp]
         L.pk_policy_scores.argtypes = [P, Po, i32, i32, vp, vp, vp, sz, vp]
@@ -96,6 +97,7 @@ def lib():
         L.pk_picard_simulate_capacity.argtypes = [P, vp, i32, i32, i32, i32, vp, vp, sz, vp, vp,
                                                   vp, C.POINTER(i32), vp, vp, vp]
         for f in ("pk_workspace_size", "pk_serial_simulate", "pk_picard_simulate",
+                  "pk_picard_simulate_noalloc",
                   "pk_policy_grad", "pk_autotune", "pk_policy_scores",
                   "pk_advantages_workspace_size", "pk_reinforce_advantages", "pk_adam_step",
                   "pk_capacity_workspace_size", "pk_serial_simulate_capacity",
@@ -245,6 +247,36 @@ def pk_picard_simulate(prob: DeviceProblem, policy: str = "greedy", block_len: i
     status = lib().pk_picard_simulate(C.byref(p), C.byref(po), C.byref(o), _ptr(ws), ws.numel(),
                                       _ptr(out["actions"]), _ptr(out["shipped"]),
                                       _ptr(out["final_inv"]), C.byref(st), _stream(stream))
+    if status != PK_OK and not (status == PK_ERR_NOT_CONVERGED and not raise_not_converged):
+        _check(status)
+    out["status"] = status
+    out["passes"] = passes
+    out["stats"] = {f: getattr(st, f) for f, _ in pk_stats._fields_ if f not in ("passes",)}
+    return out
+
+
+def pk_picard_simulate_noalloc(prob: DeviceProblem, policy: str = "greedy",
+                               block_len: int = 0, max_passes: int = 0,
+                               init_cache: Optional[torch.Tensor] = None, validate: bool = False,
+                               partition: Optional[torch.Tensor] = None, out: Optional[dict] = None,
+                               stream=None, raise_not_converged=True) -> dict:
+    """pk_picard_simulate_noalloc: the library's static scratch instead of a workspace;
+    the caller's output tensors (`out`, else allocated here) as for pk_picard_simulate."""
+    dev = prob.sku.device
+    p, po = prob.c_problem(), prob.c_policy(policy)
+    o = pk_picard_opts(block_len, max_passes, 1, 0, _ptr(init_cache), int(validate),
+                       _ptr(partition))
+    if out is None:
+        out = dict(actions=torch.empty(prob.total, dtype=torch.int32, device=dev),
+                   shipped=torch.empty(prob.total, dtype=torch.int32, device=dev),
+                   final_inv=torch.empty_like(prob.init_inv))
+    passes = np.zeros(prob.n_traj, dtype=np.int32)
+    st = pk_stats()
+    st.passes = passes.ctypes.data
+    status = lib().pk_picard_simulate_noalloc(C.byref(p), C.byref(po), C.byref(o),
+                                              _ptr(out["actions"]), _ptr(out.get("shipped")),
+                                              _ptr(out.get("final_inv")), C.byref(st),
+                                              _stream(stream))
     if status != PK_OK and not (status == PK_ERR_NOT_CONVERGED and not raise_not_converged):
         _check(status)
     out["status"] = status

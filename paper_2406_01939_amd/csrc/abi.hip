@@ -69,19 +69,52 @@ hipError_t launch_adam(float *p, const float *g, float *m, float *v, int64_t n,
 
 using namespace pk;
 
+// Scratch of pk_picard_simulate_noalloc: the workspace of one simulation, held by every
+// device the library runs on until the process ends.  Host code never passes this name to
+// a kernel or a copy (on the host it is only a stand-in); it uses the device address that
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[PK_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
-thread_local std::string g_err;
+// Message of the last failed call on this thread (a fixed buffer: reporting an error
+// allocates nothing).
+thread_local char g_err[512];
 
 pk_status fail(pk_status s, const char *fmt, ...)
 {
-    char buf[512];
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
     va_end(ap);
-    g_err = buf;
     return s;
+}
+
+// Device address of `scratch` per device, resolved once per device with that device
+// current (each device holds its own copy of the array at its own address).
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+pk_status scratch_on_current_device(void **out)
+{
+    int dev = -1;
+    const hipError_t ge = hipGetDevice(&dev);
+    if (ge != hipSuccess) return fail(PK_ERR_HIP, "hipGetDevice failed: %s", hipGetErrorString(ge));
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return fail(PK_ERR_UNSUPPORTED, "device %d: the static scratch serves devices 0..%d",
+                    dev, NOALLOC_MAX_DEVICES - 1);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(PK_ERR_HIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev,
+                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return PK_OK;
 }
 
 #define HIP_TRY(expr)                                                                        \
@@ -437,10 +470,13 @@ struct LastPasses {
 };
 thread_local LastPasses g_last_passes;
 
+// noalloc: create nothing (no captured graph, no events, no pinned control block, no host
+// heap buffer); the passes are enqueued directly and the control block is read into a
+// stack copy.
 pk_status picard_run(const pk_problem *problem, const Dims &d, const pk_policy *policy,
                      const pk_picard_opts &o, int B, void *ws, size_t ws_bytes,
                      int32_t *actions, int32_t *shipped, int32_t *final_inv, pk_stats *stats,
-                     hipStream_t stream)
+                     hipStream_t stream, bool noalloc = false)
 {
     const int64_t mp64 = o.max_passes > 0 ? o.max_passes : d.max_T + 1;
     const int max_passes = (int)std::min<int64_t>(mp64, 0x7ffffff0);
@@ -453,8 +489,8 @@ pk_status picard_run(const pk_problem *problem, const Dims &d, const pk_policy *
     Carver c{align_ws(ws)};
     Plan L;
     int64_t *to;
-    void *scratch;
-    carve_plan(c, d, policy, B, &L, &to, &scratch);
+    void *setup_scr;
+    carve_plan(c, d, policy, B, &L, &to, &setup_scr);
     L.no_frontier = o.use_frontier ? 0 : 1;
     L.worker = o.partition;
     const Sizes sz = plan_sizes(d, B);
@@ -469,7 +505,7 @@ pk_status picard_run(const pk_problem *problem, const Dims &d, const pk_policy *
         if (d.total > 0) {
             const bool mlp = policy->kind == PK_POLICY_MLP;
             HIP_TRY(setup_plan(P, L, o.init_cache, o.validate, mlp, (int32_t)sz.n_seg_max,
-                               scratch, s2));
+                               setup_scr, s2));
             if (mlp)
                 HIP_TRY(setup_costT(P, L.costT, s2));
             else
@@ -481,10 +517,11 @@ pk_status picard_run(const pk_problem *problem, const Dims &d, const pk_policy *
                                    (size_t)d.n_traj * d.K * d.N * 4, hipMemcpyDeviceToDevice, s2));
         return PK_OK;
     };
-    Ctl *hc = g_pinned.get();
+    Ctl ctl_copy;
+    Ctl *hc = noalloc ? &ctl_copy : g_pinned.get();
     if (!hc) return fail(PK_ERR_HIP, "pinned host allocation failed");
     const int grid = num_cus(); // the walk sizes its grid from the CU count
-    const bool timing = stats && stats->timing;
+    const bool timing = stats && stats->timing && !noalloc;
     int U = o.graph_unroll > 0 ? o.graph_unroll : 8;
     GraphKey key0; // this call's problem and plan, without the unroll
     key0.set(P, L, policy, final_inv, has_init, grid, 0, (int)sz.n_seg_max, timing);
@@ -534,7 +571,7 @@ pk_status picard_run(const pk_problem *problem, const Dims &d, const pk_policy *
     GraphEntry *g_first = nullptr, *g_more = nullptr;
     double graph_walk_ms = 0.0;
     int64_t graph_walks = 0;
-    if (!done && U > 1 && max_passes >= U) {
+    if (!done && !noalloc && U > 1 && max_passes >= U) {
         for (int with_setup = 1; with_setup >= 0; --with_setup) {
             GraphKey key;
             key.set(P, L, policy, final_inv, has_init, grid, U, (int)sz.n_seg_max, timing,
@@ -591,13 +628,21 @@ pk_status picard_run(const pk_problem *problem, const Dims &d, const pk_policy *
     }
     if (d.total > 0) HIP_TRY(launch_unpermute(P, L, actions, shipped, st));
     HIP_TRY(hipMemcpyAsync(hc, L.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
-    std::vector<int32_t> lcp(d.n_traj);
-    HIP_TRY(hipMemcpyAsync(lcp.data(), L.traj_lcp, d.n_traj * sizeof(int32_t),
-                           hipMemcpyDeviceToHost, st));
+    // last changed pass per trajectory (read straight into stats->passes without a host
+    // buffer of our own when nothing may be allocated)
+    std::vector<int32_t> lcp;
+    int32_t *lcp_host = stats ? stats->passes : nullptr;
+    if (!noalloc) {
+        lcp.resize(d.n_traj);
+        lcp_host = lcp.data();
+    }
+    if (lcp_host)
+        HIP_TRY(hipMemcpyAsync(lcp_host, L.traj_lcp, d.n_traj * sizeof(int32_t),
+                               hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     if (stats) {
         if (stats->passes)
-            for (int b = 0; b < d.n_traj; ++b) stats->passes[b] = lcp[b] + 1;
+            for (int b = 0; b < d.n_traj; ++b) stats->passes[b] = lcp_host[b] + 1;
         stats->passes_max = d.total > 0 ? hc->passes_done : 1;
         stats->block_len = o.partition ? 0 : B;
         unsigned long long sum[ST_N] = {};
@@ -859,7 +904,7 @@ pk_status cap_errors(const CapCtl &h)
 
 extern "C" {
 
-const char *pk_last_error(void) { return g_err.c_str(); }
+const char *pk_last_error(void) { return g_err; }
 
 const char *pk_version(void) { return "libpicard 0.1 (gfx950)"; }
 
@@ -884,7 +929,7 @@ pk_status pk_serial_simulate(const pk_problem *problem, const pk_policy *policy,
                              size_t ws_bytes, int32_t *actions, int32_t *shipped,
                              int32_t *final_inv, int32_t validate, void *stream)
 {
-    g_err.clear();
+    g_err[0] = 0;
     Dims d;
     pk_status s = check_problem(problem, &d);
     if (s != PK_OK) return s;
@@ -920,7 +965,7 @@ pk_status pk_picard_simulate(const pk_problem *problem, const pk_policy *policy,
                              int32_t *actions, int32_t *shipped, int32_t *final_inv,
                              pk_stats *stats, void *stream)
 {
-    g_err.clear();
+    g_err[0] = 0;
     Dims d;
     pk_status s = check_problem(problem, &d);
     if (s != PK_OK) return s;
@@ -943,12 +988,46 @@ pk_status pk_picard_simulate(const pk_problem *problem, const pk_policy *policy,
                       (hipStream_t)stream);
 }
 
+pk_status pk_picard_simulate_noalloc(const pk_problem *problem, const pk_policy *policy,
+                                     const pk_picard_opts *opts, int32_t *actions,
+                                     int32_t *shipped, int32_t *final_inv, pk_stats *stats,
+                                     void *stream)
+{
+    g_err[0] = 0;
+    Dims d;
+    pk_status s = check_problem(problem, &d);
+    if (s != PK_OK) return s;
+    if ((s = check_policy(policy)) != PK_OK) return s;
+    if (d.total > 0 && !actions) return fail(PK_ERR_INVALID_ARG, "actions is NULL");
+    pk_picard_opts o = {};
+    o.use_frontier = 1;
+    if (opts) o = *opts;
+    if (o.block_len < 0 || o.max_passes < 0 || o.graph_unroll < 0)
+        return fail(PK_ERR_INVALID_ARG, "negative option");
+    if (stats && stats->timing)
+        return fail(PK_ERR_UNSUPPORTED, "timing needs HIP events, which this entry point "
+                                        "does not create");
+    if (o.partition) o.block_len = 1;
+    int B = o.block_len;
+    if (B == 0) B = policy->kind == PK_POLICY_MLP ? DEFAULT_BLOCK_MLP : DEFAULT_BLOCK_GREEDY;
+    const size_t need = picard_bytes(d, policy, B);
+    if (need > (size_t)PK_NOALLOC_SCRATCH_BYTES)
+        return fail(PK_ERR_WORKSPACE,
+                    "this problem needs %zu bytes of scratch, more than the %zu bytes of the "
+                    "static buffer (use pk_picard_simulate with a workspace)",
+                    need, (size_t)PK_NOALLOC_SCRATCH_BYTES);
+    void *ptr = nullptr;
+    if ((s = scratch_on_current_device(&ptr)) != PK_OK) return s;
+    return picard_run(problem, d, policy, o, B, ptr, PK_NOALLOC_SCRATCH_BYTES, actions, shipped,
+                      final_inv, stats, (hipStream_t)stream, /*noalloc=*/true);
+}
+
 pk_status pk_policy_grad(const pk_problem *problem, const pk_policy *policy,
                          const int32_t *actions, const float *advantages, float *logp,
                          float *grad, double *objective, void *ws, size_t ws_bytes,
                          int32_t validate, void *stream)
 {
-    g_err.clear();
+    g_err[0] = 0;
     Dims d;
     pk_status s = check_problem(problem, &d);
     if (s != PK_OK) return s;
@@ -1006,7 +1085,7 @@ pk_status pk_policy_scores(const pk_problem *problem, const pk_policy *policy, i
                            int32_t region, const int32_t *inv_row, float *scores, void *ws,
                            size_t ws_bytes, void *stream)
 {
-    g_err.clear();
+    g_err[0] = 0;
     Dims d;
     pk_status s = check_problem(problem, &d);
     if (s != PK_OK) return s;
@@ -1031,7 +1110,7 @@ pk_status pk_policy_scores(const pk_problem *problem, const pk_policy *policy, i
 pk_status pk_autotune(const pk_problem *problem, const pk_policy *policy, void *ws,
                       size_t ws_bytes, int32_t *best_block_len, void *stream)
 {
-    g_err.clear();
+    g_err[0] = 0;
     Dims d;
     pk_status s = check_problem(problem, &d);
     if (s != PK_OK) return s;
@@ -1055,7 +1134,7 @@ pk_status pk_autotune(const pk_problem *problem, const pk_policy *policy, void *
 
 pk_status pk_advantages_workspace_size(const pk_problem *problem, size_t *bytes)
 {
-    g_err.clear();
+    g_err[0] = 0;
     Dims d;
     pk_status s = check_problem(problem, &d);
     if (s != PK_OK) return s;
@@ -1068,7 +1147,7 @@ pk_status pk_reinforce_advantages(const pk_problem *problem, const int32_t *acti
                                   const int32_t *shipped, int32_t revenue, float *advantages,
                                   int64_t *returns, void *ws, size_t ws_bytes, void *stream)
 {
-    g_err.clear();
+    g_err[0] = 0;
     Dims d;
     pk_status s = check_problem(problem, &d);
     if (s != PK_OK) return s;
@@ -1116,7 +1195,7 @@ pk_status pk_adam_step(float *params, const float *grad, float *m, float *v, int
                        int32_t step, double lr, double beta1, double beta2, double eps,
                        int32_t ascend, void *stream)
 {
-    g_err.clear();
+    g_err[0] = 0;
     if (n < 0) return fail(PK_ERR_INVALID_ARG, "n must be >= 0");
     if (n > 0 && (!params || !grad || !m || !v))
         return fail(PK_ERR_INVALID_ARG, "params/grad/m/v is NULL");
@@ -1141,7 +1220,7 @@ pk_status pk_adam_step(float *params, const float *grad, float *m, float *v, int
 pk_status pk_capacity_workspace_size(const pk_problem *problem, const int32_t *capacity,
                                      int32_t block_len, size_t *bytes)
 {
-    g_err.clear();
+    g_err[0] = 0;
     Dims d;
     pk_status s = check_capacity_problem(problem, capacity, &d);
     if (s != PK_OK) return s;
@@ -1159,7 +1238,7 @@ pk_status pk_serial_simulate_capacity(const pk_problem *problem, const int32_t *
                                       size_t ws_bytes, int32_t *actions, int32_t *final_inv,
                                       int32_t *final_cap, void *stream)
 {
-    g_err.clear();
+    g_err[0] = 0;
     Dims d;
     pk_status s = check_capacity_problem(problem, capacity, &d);
     if (s != PK_OK) return s;
@@ -1196,7 +1275,7 @@ pk_status pk_picard_simulate_capacity(const pk_problem *problem, const int32_t *
                                       int32_t *passes, int64_t *changed, int32_t *caches,
                                       void *stream)
 {
-    g_err.clear();
+    g_err[0] = 0;
     Dims d;
     pk_status s = check_capacity_problem(problem, capacity, &d);
     if (s != PK_OK) return s;
