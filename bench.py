@@ -3,12 +3,18 @@
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 
 A step is one pk_picard_simulate call on one batch of synthetic orders resident in HBM:
-setup (sort, partition, rank table), every Picard pass to convergence, and the final
-unpermute.  Prints ONE JSON line with the throughput, the passes to converge, the serial
-GPU sweep on the same instance (speed-up), the roofline of the dominant kernel measured
-with HIP events on the library's stream, and the CPU oracle's throughput on the host.
-For a greedy workload the line also carries a shorter run of the learned policy on its
-own workload ("learned": 64 trajectories of 2e5 orders, MFMA roofline of its walk).
+setup (sort, partition, policy tables), every Picard pass to convergence, and the final
+unpermute.  The headline workload is the largest single-GPU configuration: 16
+trajectories of 1e7 orders each under the learned MLP softmax policy (N = 500
+warehouses, K = 1e6 SKUs, R = 500 regions, quantities 1..4).  The one JSON line carries
+its throughput, passes to converge, near-tie count, the serial GPU sweep on the same
+instance (a prefix of every trajectory), the roofline of its dominant kernel (the learned
+walk, FP32) measured with HIP events on the library's stream, and the CPU oracle's
+throughput on the host (one core, and one trajectory per core on all of them).  Two
+greedy legs follow, each with its own roofline and CPU baseline: 256 trajectories of
+uneven horizon ("batch") and one trajectory of 1e6 orders ("single").  Other legs
+(node capacity, the capacity-dependent policy, the policy-gradient loop, the partition
+sweep, the gradient) run only when asked for.
 """
 from __future__ import annotations
 
@@ -27,7 +33,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "simulated orders/sec/GPU, Picard vs serial GPU sweep; iterations to converge"
 HBM_PEAK_GBS = 8000.0
-DEFAULT_WORKLOAD = "greedy_n100_k1e5_t1e6"
+DEFAULT_WORKLOAD = "mlp_batch16_n500_k1e6_t1e7"
+BATCH_WORKLOAD = "greedy_batch256_n50_k2e4"
+SINGLE_WORKLOAD = "greedy_n100_k1e5_t1e6"
 LEARNED_WORKLOAD = "mlp_batch64_n100_k5e4_t2e5"
 CAPACITY_WORKLOAD = "greedy_cap_n100_k1e5_t1e6"
 REVENUE = 200  # per-unit price of the margin reward (revenue - cost) of the gradient legs
@@ -73,45 +81,119 @@ def copy_calibration(nbytes: int, reps: int = 3):
     print(json.dumps({"copy_bytes": nbytes, "reps": reps}))
 
 
-def cpu_baseline(inst, budget_s: float = 8.0):
-    """The oracle's serial rollout (single thread) over whole trajectories of the same
-    workload, repeated until the time budget is used."""
+def host_info():
+    """The host CPU's model name and the logical CPUs this process may run on."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return {"cpu_model": model, "nproc": avail, "os_cpu_count": os.cpu_count()}
+
+
+def _prefix_instance(inst, b: int, m: int):
+    """Trajectory b cut to its first m orders, as a one-trajectory instance whose SKUs are
+    renumbered to those the prefix orders (their initial inventory rows recomputed from
+    the workload's generator when it has no stored inventory).  SKUs never interact, so
+    the rollout of the prefix is the same computation."""
+    from paper_2406_01939_amd.instances import Instance
+    lo = int(inst.traj_offsets[b])
+    hi = min(lo + m, int(inst.traj_offsets[b + 1]))
+    sku = inst.sku[lo:hi]
+    uniq, inv = np.unique(sku, return_inverse=True)
+    return Instance(N=inst.N, K=int(uniq.size), R=inst.R,
+                    traj_offsets=np.array([0, hi - lo], dtype=np.int64),
+                    sku=inv.astype(np.int32), region=inst.region[lo:hi].copy(),
+                    qty=inst.qty[lo:hi].copy(), x0=inst.x0_rows(b, uniq)[None].copy(),
+                    cost=inst.cost[b:b + 1].copy(), rng_seed=inst.rng_seed, params=inst.params,
+                    hidden=inst.hidden, n_hidden_layers=inst.n_hidden_layers, name=inst.name)
+
+
+def cpu_baseline(inst, budget_s: float = 8.0, threads: int = 1):
+    """The oracle's serial rollout on the host, as it stands: whole trajectories of the
+    workload (or, for the learned policy, prefixes of them sized so that the sample
+    takes about budget_s), one trajectory per thread, repeated until budget_s has passed.
+    threads = 1 is the one-core baseline; more threads run different trajectories at once
+    (the oracle's C calls release the interpreter lock)."""
+    import threading
     from oracle import oracle as O
     O.build(force=False)
+    learned = inst.params is not None
+    nt = inst.n_traj
+    m = None
+    if learned:  # size the prefix: time a short one first
+        probe = _prefix_instance(inst, 0, 500)
+        t0 = time.perf_counter()
+        O.serial(probe, 0)
+        per = (time.perf_counter() - t0) / probe.total_orders
+        m = int(max(500, min(inst.horizon(0), 0.45 * budget_s / max(per, 1e-9))))
+    jobs = [_prefix_instance(inst, b, m) if learned else inst.trajectory(b)
+            for b in range(min(nt, threads))] if learned else None
+    lock = threading.Lock()
+    done = {"orders": 0, "runs": 0}
     t0 = time.perf_counter()
-    orders, reps = 0, 0
-    while True:
-        for b in range(inst.n_traj):
-            O.serial(inst, b)
-            orders += inst.horizon(b)
-            if time.perf_counter() - t0 > budget_s:
-                break
-        reps += 1
-        if time.perf_counter() - t0 > budget_s:
-            break
+
+    def worker(k):
+        i = k
+        while time.perf_counter() - t0 < budget_s:
+            if learned:
+                sub = jobs[k % len(jobs)]
+                O.serial(sub, 0)
+                n = sub.total_orders
+            else:
+                b = i % nt
+                O.serial(inst, b, greedy=True)
+                n = inst.horizon(b)
+                i += threads
+            with lock:
+                done["orders"] += n
+                done["runs"] += 1
+
+    ths = [threading.Thread(target=worker, args=(k,)) for k in range(threads)]
+    for th in ths:
+        th.start()
+    for th in ths:
+        th.join()
     dt = time.perf_counter() - t0
-    return {"value": orders / dt, "unit": "orders/s", "cores": 1, "kind": "oracle",
-            "sample": f"serial oracle rollout, {orders} orders ({reps} pass(es) over the "
-                      f"workload's trajectories), {dt:.2f} s, one thread"}
+    what = (f"prefixes of {m} orders of {min(nt, threads)} trajectories (FP64 learned policy)"
+            if learned else "whole trajectories of the workload (greedy policy)")
+    return {"value": done["orders"] / dt, "unit": "orders/s", "cores": threads, "kind": "oracle",
+            "sample": f"serial oracle rollout, {done['orders']} orders in {done['runs']} "
+                      f"rollouts: {what}, {dt:.2f} s, {threads} thread(s)"}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--warmup-seconds", type=float, default=0.5)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup-seconds", type=float, default=0.0)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
     ap.add_argument("--block-len", type=int, default=0)
     ap.add_argument("--no-serial", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--serial-prefix", type=int, default=0, metavar="M",
+    ap.add_argument("--cpu-seconds", type=float, default=8.0,
+                    help="time budget of each CPU-oracle sample")
+    ap.add_argument("--serial-prefix", type=int, default=-1, metavar="M",
                     help="time the serial sweep on the first M orders of each trajectory "
-                         "(for workloads whose full serial sweep runs for minutes)")
+                         "(default: 3e5 for workloads whose full serial sweep runs for "
+                         "minutes, else the whole workload)")
+    ap.add_argument("--legs", default="batch,single",
+                    help="comma-separated greedy legs after the headline: batch (256 "
+                         "trajectories of uneven horizon), single (one trajectory of 1e6 "
+                         "orders), learned64 (64 trajectories of 2e5 orders, learned); "
+                         "'' for none")
+    ap.add_argument("--legs-after-s", type=float, default=470.0,
+                    help="skip the remaining legs once the run has taken this long")
     ap.add_argument("--with-grad", action="store_true",
                     help="learned workloads: also time pk_policy_grad at the final actions")
-    ap.add_argument("--no-learned", action="store_true",
-                    help="skip the learned-policy leg (greedy workloads only)")
     ap.add_argument("--pg-iters", type=int, default=0, metavar="K",
                     help="also run K policy-gradient iterations (Section 4.2) on the learned "
                          "workload with warm-started Picard, cold Picard and serial rollouts")
@@ -119,8 +201,9 @@ def main():
                     help="Section 4.1's partition contrast on the 3e6-order, 1e6-SKU, 30-"
                          "warehouse instance: product and uniform random partitions over 1e4 "
                          "processes and autotuned blocks, demand exponent 0 to -1")
-    ap.add_argument("--no-capacity", action="store_true",
-                    help="skip the node-capacity leg (Section 3's full state, time blocks)")
+    ap.add_argument("--capacity", action="store_true",
+                    help="also run the node-capacity leg (Section 3's full state, time "
+                         "blocks) and the capacity-dependent policy's ablation")
     ap.add_argument("--capacity-only", action="store_true",
                     help="only run the node-capacity leg (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -154,17 +237,22 @@ def main():
                                 n_hidden_layers=prob.n_hidden_layers, hidden=prob.hidden)
         return sub, it
 
-    def run(name, steps, warmup, warmup_s, block_len, serial, with_grad=False, serial_prefix=0):
-        """Time `steps` simulations of workload `name` (after the warm-up) and, if asked,
-        one serial GPU sweep of it; the walk kernel's roofline from the same steps."""
+    def run(name, steps, warmup, warmup_s, block_len, serial, with_grad=False,
+            serial_prefix=-1, cpu=False, cpu_s=8.0):
+        """Time `steps` simulations of workload `name` (after `warmup` untimed ones) and,
+        if asked, one serial GPU sweep of it (of a prefix of every trajectory when
+        serial_prefix > 0) and the CPU oracle; the walk kernel's roofline from the timed
+        steps."""
+        t_gen = time.perf_counter()
         inst = make_instance(name)
         policy = "mlp" if inst.params is not None else "greedy"
         prob = api.DeviceProblem.from_instance(inst)
         torch.cuda.synchronize()
-        _progress(f"{name}: {inst.total_orders} orders on the GPU")
+        _progress(f"{name}: {inst.total_orders} orders on the GPU "
+                  f"({time.perf_counter() - t_gen:.1f} s to generate)")
         total = inst.total_orders
         B = block_len if block_len > 0 else api.pk_autotune(prob, policy)
-        # warm-up: at least `warmup` steps and `warmup_s` seconds of work (an idle GPU
+        # warm-up: `warmup` steps, and at least `warmup_s` seconds of work (an idle GPU
         # runs at low clocks for a while)
         out = None
         t_w = time.perf_counter()
@@ -173,39 +261,57 @@ def main():
             out = api.pk_picard_simulate(prob, policy, block_len=B, out=out)
             torch.cuda.synchronize()
             k += 1
-        walk_ms = walk_bytes = walk_flops = 0.0
-        walk_launches = 0
+        acc = dict(walk_ms=0.0, walk_bytes=0, walk_flops=0, walk_launches=0, near_ties=0,
+                   orders_walked=0, runs_walked=0, changed_total=0, scan_ms=0.0,
+                   scan_bytes=0, scan_launches=0)
         passes = None
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
             out = api.pk_picard_simulate(prob, policy, block_len=B, out=out, timing=True)
             st = out["stats"]
-            walk_ms += st["walk_ms"]
-            walk_bytes += st["walk_bytes"]
-            walk_flops += st["walk_flops"]
-            walk_launches += st["walk_launches"]
+            for key_ in acc:
+                acc[key_] += st.get(key_, 0)
             passes = out["passes"]
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         _progress(f"{name}: {steps} timed simulations, {dt:.3f} s")
         r = {"value": total * steps / dt, "ms_per_step": 1e3 * dt / steps, "inst": inst,
              "policy": policy, "B": B, "passes": passes, "total": total}
-        avg_us = 1e3 * walk_ms / max(walk_launches, 1)
+        per = max(steps, 1)
+        r["work"] = {"orders_walked_per_step": acc["orders_walked"] / per,
+                     "runs_walked_per_step": acc["runs_walked"] / per,
+                     "changed_per_step": acc["changed_total"] / per,
+                     "walk_ms_per_step": acc["walk_ms"] / per}
+        avg_us = 1e3 * acc["walk_ms"] / max(acc["walk_launches"], 1)
         if policy == "greedy":
-            achieved = (walk_bytes / 1e9) / (walk_ms / 1e3) if walk_ms > 0 else 0.0
+            achieved = (acc["walk_bytes"] / 1e9) / (acc["walk_ms"] / 1e3) if acc["walk_ms"] > 0 else 0.0
             r["roofline"] = {"kernel": "k_walk_greedy", "bound": "hbm", "achieved": achieved,
                              "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                             "traffic": _traffic(B) if name == DEFAULT_WORKLOAD else None,
-                             "bytes_per_launch": walk_bytes / max(walk_launches, 1),
-                             "avg_launch_us": avg_us, "launches": walk_launches}
+                             "traffic": _traffic(B) if name == SINGLE_WORKLOAD else None,
+                             "bytes_per_launch": acc["walk_bytes"] / max(acc["walk_launches"], 1),
+                             "avg_launch_us": avg_us, "launches": acc["walk_launches"]}
         else:
-            achieved = (walk_flops / 1e12) / (walk_ms / 1e3) if walk_ms > 0 else 0.0
+            achieved = (acc["walk_flops"] / 1e12) / (acc["walk_ms"] / 1e3) if acc["walk_ms"] > 0 else 0.0
             r["roofline"] = {"kernel": "k_walk_mlp", "bound": "mfma", "achieved": achieved,
                              "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                              "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
-                             "flops_per_launch": walk_flops / max(walk_launches, 1),
-                             "avg_launch_us": avg_us, "launches": walk_launches}
+                             "flops_per_launch": acc["walk_flops"] / max(acc["walk_launches"], 1),
+                             "avg_launch_us": avg_us, "launches": acc["walk_launches"]}
+            r["near_ties"] = {"evaluations_per_step": acc["near_ties"] / per,
+                              "orders_walked_per_step": acc["orders_walked"] / per,
+                              "rule": "top two perturbed scores within 1e-5 relative (FP32, "
+                                      "counted by the walk over all passes)"}
+        if acc["scan_launches"] > 0:
+            sa = (acc["scan_bytes"] / 1e9) / (acc["scan_ms"] / 1e3) if acc["scan_ms"] > 0 else 0.0
+            r["roofline_scan"] = {"kernel": "k_scan_entry", "bound": "hbm", "achieved": sa,
+                                  "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": sa / HBM_PEAK_GBS,
+                                  "bytes_per_launch": acc["scan_bytes"] / acc["scan_launches"],
+                                  "avg_launch_us": 1e3 * acc["scan_ms"] / acc["scan_launches"],
+                                  "launches": acc["scan_launches"]}
         if serial:
+            if serial_prefix < 0:  # the learned workloads' serial sweeps run for minutes
+                serial_prefix = 300_000 if (policy == "mlp" and total > 20_000_000) else 0
             sprob, it, stotal = prob, None, total
             if 0 < serial_prefix < int(np.diff(prob.traj_offsets).max()):
                 sprob, it = prefix_problem(prob, serial_prefix)
@@ -214,7 +320,7 @@ def main():
                 api.pk_serial_simulate(sprob, policy)  # warm
             torch.cuda.synchronize()
             t1 = time.perf_counter()
-            ser = api.pk_serial_simulate(sprob, policy)
+            ser = api.pk_serial_simulate(sprob, policy, want_final=False)
             torch.cuda.synchronize()
             sdt = time.perf_counter() - t1
             _progress(f"{name}: serial sweep of {stotal} orders {sdt:.3f} s")
@@ -225,6 +331,7 @@ def main():
             if it is not None:
                 r["serial_gpu"]["prefix_per_trajectory"] = serial_prefix
             r["speedup_vs_serial_gpu"] = r["value"] / (stotal / sdt)
+            del ser, sprob
         if with_grad and policy == "mlp":
             adv = api.pk_reinforce_advantages(prob, out["actions"], out["shipped"],
                                               REVENUE)["advantages"]
@@ -237,7 +344,20 @@ def main():
             _progress(f"{name}: policy gradient {gdt:.3f} s")
             r["policy_grad"] = {"seconds": gdt, "orders_per_s": total / gdt,
                                 "objective": g["objective"]}
+        del out, prob
+        torch.cuda.empty_cache()
+        if cpu:
+            one = cpu_baseline(inst, cpu_s, 1)
+            _progress(f"{name}: CPU oracle, one core: {one['value']:.4g} orders/s")
+            r["cpu_baseline"] = one
+            if inst.n_traj > 1:
+                nth = max(1, min(16, HOST["nproc"], inst.n_traj))
+                allc = cpu_baseline(inst, cpu_s, nth)
+                _progress(f"{name}: CPU oracle, {nth} cores: {allc['value']:.4g} orders/s")
+                r["cpu_baseline_all_cores"] = allc
         return r
+
+    HOST = host_info()
 
     def partition_sweep(M=10_000, betas=(0.0, -0.2, -0.4, -0.6, -0.8, -1.0), reps=3,
                         policy="greedy"):
@@ -411,8 +531,25 @@ def main():
         prob.params.copy_(p0)
         return res
 
+    def leg_summary(m, name):
+        """The fields of a secondary leg's object in the result line."""
+        out = {"workload": name, "value": m["value"], "unit": "orders/s",
+               "ms_per_step": m["ms_per_step"], "orders": m["total"], "block_len": m["B"],
+               "passes_max": int(m["passes"].max()), "passes_mean": float(m["passes"].mean()),
+               "dtype": "int32" if m["policy"] == "greedy" else "f32",
+               "roofline": m["roofline"], "work": m["work"]}
+        for k in ("roofline_scan", "near_ties", "serial_gpu", "speedup_vs_serial_gpu",
+                  "cpu_baseline", "cpu_baseline_all_cores", "policy_grad"):
+            if k in m:
+                out[k] = m[k]
+        if "cpu_baseline" in m:
+            out["speedup_vs_cpu_oracle_one_core"] = m["value"] / m["cpu_baseline"]["value"]
+        return out
+
+    cpu = not args.no_cpu
+    t_start = time.perf_counter()
     m = run(args.workload, args.steps, args.warmup, args.warmup_seconds, args.block_len,
-            not args.no_serial, args.with_grad, args.serial_prefix)
+            not args.no_serial, args.with_grad, args.serial_prefix, cpu, args.cpu_seconds)
     inst, policy, passes = m["inst"], m["policy"], m["passes"]
     res = {"metric": METRIC, "value": m["value"], "unit": "orders/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": m["ms_per_step"],
@@ -422,20 +559,34 @@ def main():
                       "n_skus": inst.K, "n_regions": inst.R, "n_traj": inst.n_traj,
                       "orders": m["total"], "block_len": m["B"], "parallelism": "1 GPU"},
            "passes_max": int(passes.max()), "passes_mean": float(passes.mean()),
-           "roofline": m["roofline"]}
-    for k in ("serial_gpu", "speedup_vs_serial_gpu", "policy_grad"):
+           "roofline": m["roofline"], "host": HOST}
+    for k in ("roofline_scan", "near_ties", "work", "serial_gpu", "speedup_vs_serial_gpu",
+              "policy_grad", "cpu_baseline", "cpu_baseline_all_cores"):
         if k in m:
             res[k] = m[k]
-    if not args.no_learned and policy == "greedy":
-        # the learned policy on its own workload (64 trajectories), a shorter run
-        lm = run(LEARNED_WORKLOAD, 2, 1, 0.5, 0, True)
-        res["learned"] = {"workload": LEARNED_WORKLOAD, "value": lm["value"], "unit": "orders/s",
-                          "ms_per_step": lm["ms_per_step"], "orders": lm["total"],
-                          "block_len": lm["B"], "passes_max": int(lm["passes"].max()),
-                          "passes_mean": float(lm["passes"].mean()), "dtype": "f32",
-                          "roofline": lm["roofline"], "serial_gpu": lm["serial_gpu"],
-                          "speedup_vs_serial_gpu": lm["speedup_vs_serial_gpu"]}
-    if not args.no_capacity and policy == "greedy":
+    if "cpu_baseline" in m:
+        res["speedup_vs_cpu_oracle_one_core"] = m["value"] / m["cpu_baseline"]["value"]
+    del m, inst
+    res["headline_seconds"] = time.perf_counter() - t_start
+    legs = {}
+    for leg in [x for x in args.legs.split(",") if x]:
+        name = {"batch": BATCH_WORKLOAD, "single": SINGLE_WORKLOAD,
+                "learned64": LEARNED_WORKLOAD}[leg]
+        if name == args.workload:
+            continue
+        if time.perf_counter() - t_start > args.legs_after_s:
+            legs[leg] = {"workload": name, "skipped": f"the run had taken more than "
+                                                      f"{args.legs_after_s:.0f} s"}
+            _progress(f"leg {leg} skipped: time")
+            continue
+        steps = 10 if leg != "learned64" else 2
+        lm = run(name, steps, 2 if leg != "learned64" else 1, 0.5, 0, not args.no_serial,
+                 cpu=cpu, cpu_s=min(args.cpu_seconds, 5.0))
+        legs[leg] = leg_summary(lm, name)
+        del lm
+    if legs:
+        res["legs"] = legs
+    if args.capacity:
         res["capacity"] = capacity_leg(serial=not args.no_serial)
         res["capacity_gamma"] = gamma_ablation()
     if args.pg_iters > 0:
@@ -445,13 +596,10 @@ def main():
     elif args.partition_sweep == "mlp":
         res["partition_sweep"] = partition_sweep(policy="mlp", betas=(0.0, -0.4, -0.8, -1.0),
                                                  reps=1)
-    if not args.no_cpu and inst.x0 is not None:
-        res["cpu_baseline"] = cpu_baseline(inst)
     res["paper_context"] = ("paper (A100 40GB, JAX, 16-bit): 441x Picard speed-up over a "
                             "sequential GPU rollout at 3M orders / 1M products / 30 nodes, "
                             "MLP policy; not this workload")
     print(json.dumps(res))
-
 
 if __name__ == "__main__":
     main()

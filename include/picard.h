@@ -147,6 +147,10 @@ typedef struct pk_stats {
     int64_t walk_flops;      /* MLP: algorithmic FLOPs of the rows those launches scored
                                 (one row per order and warehouse with stock) */
     int32_t timing;          /* in: nonzero to record walk_ms / walk_bytes */
+    double scan_ms;          /* summed duration of the entry-state scan kernel (timing) */
+    int64_t scan_launches;   /* launches of that kernel timed */
+    int64_t scan_bytes;      /* algorithmic HBM bytes of the scan's launches (u rows read,
+                                E rows written, frontier checks) */
 } pk_stats;
 
 /* Bytes of scratch that pk_picard_simulate, pk_serial_simulate and pk_policy_grad need

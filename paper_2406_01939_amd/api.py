@@ -64,7 +64,8 @@ class pk_stats(C.Structure):
                 ("changed_total", C.c_int64), ("runs_walked", C.c_int64),
                 ("orders_walked", C.c_int64), ("near_ties", C.c_int64), ("walk_ms", C.c_double),
                 ("walk_launches", C.c_int64), ("walk_bytes", C.c_int64), ("walk_flops", C.c_int64),
-                ("timing", C.c_int32)]
+                ("timing", C.c_int32), ("scan_ms", C.c_double), ("scan_launches", C.c_int64),
+                ("scan_bytes", C.c_int64)]
 
 
 _lib = None

@@ -40,7 +40,7 @@ hipError_t launch_serial_greedy(const Prob &P, const void *pos, int32_t *state, 
                                 int32_t *shipped, hipStream_t st);
 // mlp.hip
 size_t costT_bytes(int N, int R, int n_traj);
-hipError_t setup_costT(const Prob &P, float *costT, hipStream_t st);
+hipError_t setup_costT(const Prob &P, const float *params, float *costT, hipStream_t st);
 size_t walk_mlp_lds(int N);
 hipError_t launch_walk_mlp(const Prob &P, const Plan &L, const float *params, int layers,
                            const float *costT, int32_t *final_inv, bool has_init, int grid,
@@ -507,7 +507,7 @@ pk_status picard_run(const pk_problem *problem, const Dims &d, const pk_policy *
             HIP_TRY(setup_plan(P, L, o.init_cache, o.validate, mlp, (int32_t)sz.n_seg_max,
                                setup_scr, s2));
             if (mlp)
-                HIP_TRY(setup_costT(P, L.costT, s2));
+                HIP_TRY(setup_costT(P, policy->params, L.costT, s2));
             else
                 HIP_TRY(setup_pos(P, L.pos, s2));
             if (has_init) HIP_TRY(launch_consume(P, L, sz.n_split_max, s2));
@@ -539,28 +539,36 @@ pk_status picard_run(const pk_problem *problem, const Dims &d, const pk_policy *
     // Events around the walk: none (ge == nullptr, !with_events), created here, or the
     // captured graph's pair ge[0], ge[1] recorded as graph nodes.
     auto enqueue_pass = [&](hipStream_t s2, bool with_events, hipEvent_t *ge) -> pk_status {
-        HIP_TRY(launch_scan_entry(P, L, (int)sz.n_seg_max, !has_init, s2));
-        hipEvent_t e0 = nullptr, e1 = nullptr;
+        hipEvent_t es = nullptr, e0 = nullptr, e1 = nullptr;
         if (ge) {
             const pk_status r = record_in_capture(s2, ge[0]);
             if (r != PK_OK) return r;
         } else if (with_events) {
+            HIP_TRY(hipEventCreate(&es));
             HIP_TRY(hipEventCreate(&e0));
             HIP_TRY(hipEventCreate(&e1));
+            HIP_TRY(hipEventRecord(es, s2));
+        }
+        HIP_TRY(launch_scan_entry(P, L, (int)sz.n_seg_max, !has_init, s2));
+        if (ge) {
+            const pk_status r = record_in_capture(s2, ge[1]);
+            if (r != PK_OK) return r;
+        } else if (with_events) {
             HIP_TRY(hipEventRecord(e0, s2));
         }
         if (policy->kind == PK_POLICY_MLP)
             HIP_TRY(launch_walk_mlp(P, L, policy->params, policy->n_hidden_layers, L.costT,
-                                    final_inv, has_init, num_cus() * 3, s2)); // resident: 3 per CU
+                                    final_inv, has_init, num_cus() * 4, s2)); // resident: 4 per CU
         else if (L.worker)
             HIP_TRY(launch_walk_chain_greedy(P, L, final_inv, has_init, grid, s2));
         else
             HIP_TRY(launch_walk_greedy(P, L, L.pos, final_inv, has_init, grid, s2));
         if (ge) {
-            const pk_status r = record_in_capture(s2, ge[1]);
+            const pk_status r = record_in_capture(s2, ge[2]);
             if (r != PK_OK) return r;
         } else if (with_events) {
             HIP_TRY(hipEventRecord(e1, s2));
+            evs.push_back(es);
             evs.push_back(e0);
             evs.push_back(e1);
         }
@@ -569,21 +577,21 @@ pk_status picard_run(const pk_problem *problem, const Dims &d, const pk_policy *
     // graphs: the setup with the first U passes, and U further passes, each captured once
     // and replayed
     GraphEntry *g_first = nullptr, *g_more = nullptr;
-    double graph_walk_ms = 0.0;
+    double graph_walk_ms = 0.0, graph_scan_ms = 0.0;
     int64_t graph_walks = 0;
     if (!done && !noalloc && U > 1 && max_passes >= U) {
         for (int with_setup = 1; with_setup >= 0; --with_setup) {
             GraphKey key;
             key.set(P, L, policy, final_inv, has_init, grid, U, (int)sz.n_seg_max, timing,
                     with_setup != 0, o.init_cache, o.validate, max_passes);
-            pk_status gs = g_graph.get(key, timing ? 2 * U : 0,
+            pk_status gs = g_graph.get(key, timing ? 3 * U : 0,
                                        [&](hipStream_t cs, GraphEntry &ge) -> pk_status {
                 if (with_setup) {
                     pk_status e = enqueue_setup(cs);
                     if (e != PK_OK) return e;
                 }
                 for (int i = 0; i < U; ++i) {
-                    pk_status e = enqueue_pass(cs, false, timing ? &ge.evs[2 * i] : nullptr);
+                    pk_status e = enqueue_pass(cs, false, timing ? &ge.evs[3 * i] : nullptr);
                     if (e != PK_OK) return e;
                 }
                 return PK_OK;
@@ -613,8 +621,10 @@ pk_status picard_run(const pk_problem *problem, const Dims &d, const pk_policy *
         HIP_TRY(hipStreamSynchronize(st));
         if (ge && timing) {
             for (int i = 0; i < U; ++i) {
-                float ms = 0.f;
-                HIP_TRY(hipEventElapsedTime(&ms, ge->evs[2 * i], ge->evs[2 * i + 1]));
+                float ms = 0.f, sms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&sms, ge->evs[3 * i], ge->evs[3 * i + 1]));
+                HIP_TRY(hipEventElapsedTime(&ms, ge->evs[3 * i + 1], ge->evs[3 * i + 2]));
+                graph_scan_ms += sms;
                 graph_walk_ms += ms;
             }
             graph_walks += U;
@@ -654,11 +664,15 @@ pk_status picard_run(const pk_problem *problem, const Dims &d, const pk_policy *
         stats->near_ties = (int64_t)sum[ST_NEAR_TIES];
         stats->walk_bytes = (int64_t)sum[ST_BYTES];
         stats->walk_flops = (int64_t)sum[ST_FLOPS];
+        stats->scan_bytes = (int64_t)sum[ST_SCAN_BYTES];
         stats->walk_ms = graph_walk_ms;
-        stats->walk_launches = (int64_t)(evs.size() / 2) + graph_walks;
-        for (size_t i = 0; i + 1 < evs.size(); i += 2) {
-            float ms = 0.f;
-            if (hipEventElapsedTime(&ms, evs[i], evs[i + 1]) == hipSuccess) stats->walk_ms += ms;
+        stats->scan_ms = graph_scan_ms;
+        stats->walk_launches = (int64_t)(evs.size() / 3) + graph_walks;
+        stats->scan_launches = stats->walk_launches;
+        for (size_t i = 0; i + 2 < evs.size(); i += 3) {
+            float ms = 0.f, sms = 0.f;
+            if (hipEventElapsedTime(&sms, evs[i], evs[i + 1]) == hipSuccess) stats->scan_ms += sms;
+            if (hipEventElapsedTime(&ms, evs[i + 1], evs[i + 2]) == hipSuccess) stats->walk_ms += ms;
         }
     }
     for (hipEvent_t e : evs) (void)hipEventDestroy(e);
@@ -949,7 +963,7 @@ pk_status pk_serial_simulate(const pk_problem *problem, const pk_policy *policy,
                            hipMemcpyDeviceToDevice, st));
     (void)validate;
     if (policy->kind == PK_POLICY_MLP) {
-        HIP_TRY(setup_costT(P, (float *)pos, st));
+        HIP_TRY(setup_costT(P, policy->params, (float *)pos, st));
         HIP_TRY(launch_serial_mlp(P, policy->params, policy->n_hidden_layers, (const float *)pos,
                                   state, actions, shipped, st));
     } else {
@@ -1056,7 +1070,7 @@ pk_status pk_policy_grad(const pk_problem *problem, const pk_policy *policy,
     if (d.total > 0) {
         // states of the fixed actions: the actions are the cache, its consumption scanned
         HIP_TRY(setup_plan(P, L, actions, validate, true, (int32_t)sz.n_seg_max, scratch, st));
-        HIP_TRY(setup_costT(P, L.costT, st));
+        HIP_TRY(setup_costT(P, policy->params, L.costT, st));
         HIP_TRY(launch_consume(P, L, sz.n_split_max, st));
         HIP_TRY(launch_scan_entry(P, L, (int)sz.n_seg_max, false, st));
         HIP_TRY(launch_grad(P, L, policy->params, policy->n_hidden_layers, L.costT, advantages,
@@ -1100,7 +1114,7 @@ pk_status pk_policy_scores(const pk_problem *problem, const pk_policy *policy, i
     Carver c{align_ws(ws)};
     float *costT = c.take<float>((int64_t)costT_bytes(d.N, d.R, d.n_traj) / 4);
     Prob P = make_prob(problem, d, nullptr);
-    HIP_TRY(setup_costT(P, costT, st));
+    HIP_TRY(setup_costT(P, policy->params, costT, st));
     HIP_TRY(launch_scores(P, policy->params, policy->n_hidden_layers, costT, traj, region, inv_row,
                           scores, st));
     HIP_TRY(hipStreamSynchronize(st));

@@ -27,6 +27,13 @@ namespace {
 
 using namespace mlpdev;
 
+// The region terms of layer 1, W1[:,2:] E[r] + b1, follow the cost rows in the same
+// buffer: [R][64] floats after costT[n_traj][R][N].
+__device__ __forceinline__ const float *region_table(const float *costT, const Prob &P)
+{
+    return costT + (int64_t)P.n_traj * P.R * P.N;
+}
+
 // Per-order data of both learned kernels comes from LDS: the orders of a run (or a
 // trajectory) are staged 64 at a time, the next 64 loaded into registers meanwhile, and
 // each order's cost row and region embedding sit in a double buffer that is filled from
@@ -63,14 +70,15 @@ __device__ __forceinline__ void store_row(float *cbuf, float *ebuf, int N, const
 // given partition the workgroup goes on to its process's later runs of the SKU (its
 // chain), entering each at max(0, x0 - E_j - D), D the process's own fresh-minus-cached
 // consumption on its earlier runs, kept in LDS.
-__global__ __launch_bounds__(256) void k_walk_mlp(Prob P, Plan L, const float *params, int layers,
+__global__ __launch_bounds__(256, 4) void k_walk_mlp(Prob P, Plan L, const float *params, int layers,
                                                   const float *costT, int32_t *final_inv,
                                                   int has_init)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int N = P.N, R = P.R;
     float *W2s = (float *)smem;
-    int32_t *x = (int32_t *)(smem + w2_lds_bytes());
+    float *Vs = (float *)(smem + w2_lds_bytes());
+    int32_t *x = (int32_t *)(smem + w2_lds_bytes() + vec_lds_bytes());
     int32_t *cons = x + N;
     float *zbuf = (float *)(cons + N);
     int32_t *sl = (int32_t *)(zbuf + N); // warehouses with stock
@@ -80,9 +88,11 @@ __global__ __launch_bounds__(256) void k_walk_mlp(Prob P, Plan L, const float *p
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     Ctl *ctl = L.ctl;
     if (ctl->done) return;
-    stage_w2(W2s, params, R, layers); // read after the first barrier of a run
-    MlpLane m;
-    load_mlp(m, params, R, layers, W2s);
+    stage_w2(W2s, params, R, layers); // both read after the first barrier of a run
+    stage_vectors(Vs, params, R, layers);
+    ScoreLane m;
+    load_score_lane(m, params, R, layers, W2s, Vs);
+    const float *rtab = region_table(costT, P); // [R][64] region terms of layer 1
     const int pass = ctl->pass;
     const int32_t *fprev = L.fr[(pass - 1) & 1];
     int32_t *fcur = L.fr[pass & 1];
@@ -143,8 +153,10 @@ __global__ __launch_bounds__(256) void k_walk_mlp(Prob P, Plan L, const float *p
                 old = L.s_alpha[p];
             }
             if (wave != 0) nf = flag[2];
-            score_list(m, costT + ((int64_t)b * R + r) * N, m.E + (int64_t)r * 16, x, sl, nf, P.seed,
-                       (uint32_t)b, t, zbuf, -1, 0, true);
+            float pr[16];
+            load_region_term(pr, rtab, r);
+            score_rows(m, pr, costT + ((int64_t)b * R + r) * N, x, sl, nf, P.seed, (uint32_t)b, t,
+                       zbuf);
             __syncthreads();
             if (wave == 0) {
                 float z1, z2;
@@ -236,7 +248,8 @@ __global__ __launch_bounds__(256) void k_serial_mlp(Prob P, const float *params,
     extern __shared__ __align__(16) unsigned char smem[];
     const int N = P.N, R = P.R;
     float *W2s = (float *)smem;
-    int4 *ordq = (int4 *)(smem + w2_lds_bytes()); // [2][CHUNK] (sku, region, qty, -)
+    float *Vs = (float *)(smem + w2_lds_bytes());
+    int4 *ordq = (int4 *)(smem + w2_lds_bytes() + vec_lds_bytes()); // [2][CHUNK] (k, r, q, -)
     float *cbuf = (float *)(ordq + 2 * CHUNK); // [2][N]
     float *ebuf = cbuf + 2 * N;                // [2][16]
     int32_t *x = (int32_t *)(ebuf + 32);
@@ -248,9 +261,11 @@ __global__ __launch_bounds__(256) void k_serial_mlp(Prob P, const float *params,
     if (b >= P.n_traj) return;
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     const int tid = threadIdx.x;
-    stage_w2(W2s, params, R, layers); // read after the first barrier
-    MlpLane m;
-    load_mlp(m, params, R, layers, W2s);
+    stage_w2(W2s, params, R, layers); // both read after the first barrier
+    stage_vectors(Vs, params, R, layers);
+    ScoreLane m;
+    load_score_lane(m, params, R, layers, W2s, Vs);
+    const float *rtab = region_table(costT, P);
     const int64_t t0 = P.traj_off[b], t1 = P.traj_off[b + 1];
     int32_t *xs = state + (int64_t)b * P.K * N;
     auto order_at = [&](int64_t t) -> int4 {
@@ -266,7 +281,7 @@ __global__ __launch_bounds__(256) void k_serial_mlp(Prob P, const float *params,
     if (tid < CHUNK && t0 + CHUNK + tid < t1) nq = order_at(t0 + CHUNK + tid);
     __syncthreads();
     float cn[MAX_CPT], en;
-    load_row(costT, m.E, b, R, N, ordq[0].y, cn, en);
+    load_row(costT, params, b, R, N, ordq[0].y, cn, en);
     store_row(cbuf, ebuf, N, cn, en);
     for (int w = tid; w < N; w += blockDim.x) x[w] = xs[(int64_t)ordq[0].x * N + w];
     __syncthreads();
@@ -280,7 +295,7 @@ __global__ __launch_bounds__(256) void k_serial_mlp(Prob P, const float *params,
             // this order's rows were not prefetched: its cost row, and its stock row as the
             // previous order left it (written back before the last barrier)
             const int4 o0 = ordq[slot * CHUNK];
-            load_row(costT, m.E, b, R, N, o0.y, cn, en);
+            load_row(costT, params, b, R, N, o0.y, cn, en);
             store_row(cbuf + buf * N, ebuf + buf * 16, N, cn, en);
             for (int w = tid; w < N; w += blockDim.x) x[w] = xs[(int64_t)o0.x * N + w];
             __syncthreads();
@@ -295,7 +310,7 @@ __global__ __launch_bounds__(256) void k_serial_mlp(Prob P, const float *params,
         if (pf) {
             const int4 on = ordq[slot * CHUNK + (int)(i % CHUNK) + 1];
             kn = on.x;
-            load_row(costT, m.E, b, R, N, on.y, cn, en);
+            load_row(costT, params, b, R, N, on.y, cn, en);
             if (kn != k) {
 #pragma unroll
                 for (int c = 0; c < MAX_CPT; ++c) {
@@ -307,8 +322,10 @@ __global__ __launch_bounds__(256) void k_serial_mlp(Prob P, const float *params,
         build_stock_list(x, N, sl, pos, nfp);
         __syncthreads();
         const int nf = *nfp;
-        score_list(m, cbuf + buf * N, ebuf + buf * 16, x, sl, nf, P.seed, (uint32_t)b,
-                   (uint32_t)(tt - t0), zbuf, -1, 0, true);
+        float pr[16];
+        load_region_term(pr, rtab, od.y);
+        score_rows(m, pr, cbuf + buf * N, x, sl, nf, P.seed, (uint32_t)b, (uint32_t)(tt - t0),
+                   zbuf);
         __syncthreads();
         if (wave == 0) {
             float z1, z2;
@@ -351,16 +368,20 @@ __global__ __launch_bounds__(256) void k_scores(Prob P, const float *params, int
     extern __shared__ __align__(16) unsigned char smem[];
     const int N = P.N;
     float *W2s = (float *)smem;
-    int32_t *x = (int32_t *)(smem + w2_lds_bytes());
+    float *Vs = (float *)(smem + w2_lds_bytes());
+    int32_t *x = (int32_t *)(smem + w2_lds_bytes() + vec_lds_bytes());
     float *zbuf = (float *)(x + N);
     float *sbuf = zbuf + N;
-    stage_w2(W2s, params, P.R, layers); // read after the barrier below
-    MlpLane m;
-    load_mlp(m, params, P.R, layers, W2s);
+    stage_w2(W2s, params, P.R, layers); // both read after the barrier below
+    stage_vectors(Vs, params, P.R, layers);
+    ScoreLane m;
+    load_score_lane(m, params, P.R, layers, W2s, Vs);
     for (int w = threadIdx.x; w < N; w += blockDim.x) x[w] = xrow[w];
     __syncthreads();
-    score_order(m, costT + ((int64_t)b * P.R + r) * N, m.E + (int64_t)r * 16, x, N, P.seed,
-                (uint32_t)b, 0u, zbuf, sbuf);
+    float pr[16];
+    load_region_term(pr, region_table(costT, P), r);
+    score_all(m, pr, costT + ((int64_t)b * P.R + r) * N, x, N, sbuf);
+    (void)zbuf;
     __syncthreads();
     for (int w = threadIdx.x; w < N; w += blockDim.x) out[w] = sbuf[w];
 }
@@ -379,20 +400,46 @@ __global__ void k_cost_t(Prob P, float *costT)
     }
 }
 
+// Region terms of layer 1: table[r][u] = b1[u] + sum_i W1[u][2 + i] E[r][i], summed in
+// FP32 in the order i = 0..15 (one thread per (r, u)).
+__global__ void k_region_l1(const float *params, int R, float *table)
+{
+    const int64_t n = (int64_t)R * 64;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const float *W1 = params + (int64_t)R * 16;
+    const float *b1 = W1 + 64 * 18;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const int u = (int)(i & 63);
+        const int64_t r = i >> 6;
+        float acc = b1[u];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) acc = fmaf(W1[u * 18 + 2 + k], params[r * 16 + k], acc);
+        table[i] = acc;
+    }
+}
+
 } // namespace
 
-size_t costT_bytes(int N, int R, int n_traj) { return (size_t)n_traj * R * N * sizeof(float); }
+size_t costT_bytes(int N, int R, int n_traj)
+{
+    return ((size_t)n_traj * R * N + (size_t)R * 64) * sizeof(float);
+}
 
-hipError_t setup_costT(const Prob &P, float *costT, hipStream_t st)
+hipError_t setup_costT(const Prob &P, const float *params, float *costT, hipStream_t st)
 {
     const int64_t n = (int64_t)P.n_traj * P.R * P.N;
     int64_t g = (n + 255) / 256;
     g = g < 1 ? 1 : (g > 8192 ? 8192 : g);
     hipLaunchKernelGGL(k_cost_t, dim3((unsigned)g), dim3(256), 0, st, P, costT);
+    const int64_t nr = (int64_t)P.R * 64;
+    int64_t gr = (nr + 255) / 256;
+    gr = gr < 1 ? 1 : (gr > 4096 ? 4096 : gr);
+    hipLaunchKernelGGL(k_region_l1, dim3((unsigned)gr), dim3(256), 0, st, params, P.R,
+                       costT + n);
     return hipGetLastError();
 }
 
-size_t walk_mlp_lds(int N) { return w2_lds_bytes() + (size_t)N * 24 + 64; }
+size_t walk_mlp_lds(int N) { return w2_lds_bytes() + vec_lds_bytes() + (size_t)N * 24 + 64; }
 
 hipError_t launch_walk_mlp(const Prob &P, const Plan &L, const float *params, int layers,
                            const float *costT, int32_t *final_inv, bool has_init, int grid,
@@ -407,7 +454,9 @@ hipError_t launch_serial_mlp(const Prob &P, const float *params, int layers, con
                              int32_t *state, int32_t *actions, int32_t *shipped, hipStream_t st)
 {
     hipLaunchKernelGGL(k_serial_mlp, dim3(P.n_traj), dim3(256),
-                       w2_lds_bytes() + (size_t)2 * CHUNK * 16 + 128 + (size_t)P.N * 24 + 64, st, P,
+                       w2_lds_bytes() + vec_lds_bytes() + (size_t)2 * CHUNK * 16 + 128 +
+                           (size_t)P.N * 24 + 64,
+                       st, P,
                        params, layers, costT, state, actions, shipped);
     return hipGetLastError();
 }
@@ -415,7 +464,8 @@ hipError_t launch_serial_mlp(const Prob &P, const float *params, int layers, con
 hipError_t launch_scores(const Prob &P, const float *params, int layers, const float *costT,
                          int b, int r, const int32_t *xrow, float *out, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_scores, dim3(1), dim3(256), w2_lds_bytes() + (size_t)P.N * 12 + 64, st, P,
+    hipLaunchKernelGGL(k_scores, dim3(1), dim3(256),
+                       w2_lds_bytes() + vec_lds_bytes() + (size_t)P.N * 12 + 64, st, P,
                        params, layers,
                        costT, b, r, xrow, out);
     return hipGetLastError();

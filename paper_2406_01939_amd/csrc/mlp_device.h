@@ -1,5 +1,6 @@
 // Device code of the learned policy shared by the simulation and gradient kernels:
-// Philox4x32-10 and the Gumbel noise, the MFMA scorer, argmax with runner-up.
+// Philox4x32-10 and the Gumbel noise, the MFMA scorers (the gradient's, with layer 1 on
+// MFMA, and the simulation's, with layer 1 split by feature), argmax with runner-up.
 #pragma once
 
 #include <math.h>
@@ -172,6 +173,170 @@ __device__ __forceinline__ float mlp_tile(const MlpLane &m, const float f[5])
     v4f h1[4], h2[4];
     mlp_hidden(m, f, h1, h2);
     return mlp_out(m, h2);
+}
+
+// ---------------------------------------------------------------- policy scorer
+// The scorer of the simulation kernels (walk, serial sweep, diagnostic scores).  Layer 1
+// is split by feature: W1 f + b1 = W1[:,0] cost + W1[:,1] log1p(x) + (W1[:,2:] E[r] + b1),
+// and the last term depends on the order's region only, so it is tabulated per region
+// once per call (region_l1, FP32, fixed order) and layer 1 costs two FMAs per hidden unit
+// on the vector ALU; only the 64 x 64 layer 2 runs on MFMA, its bias as the accumulator's
+// initial value.  Lane l holds hidden units 16c + 4(l/16) + v of row l%16, the B-operand
+// (and D) layout of layer 2, so no data moves between the layers.
+struct ScoreLane {
+    const float *W2s; // W2 in LDS (stage_w2)
+    const float *Vs;  // [4][64] in LDS (stage_vectors): W1[:,0], W1[:,1], b2, w3 by unit
+    float b3;
+    int two;          // two hidden layers
+};
+
+// Bytes of LDS stage_vectors fills.
+__host__ __device__ inline size_t vec_lds_bytes() { return (size_t)4 * 64 * sizeof(float); }
+
+// Copies the per-unit vectors of the scorer into LDS: the cost and log1p(x) columns of W1,
+// b2 (zero with one hidden layer) and w3 (every thread takes part; the caller
+// synchronises).
+__device__ __forceinline__ void stage_vectors(float *Vs, const float *params, int R, int layers)
+{
+    const float *W1 = params + (int64_t)R * 16;
+    const float *b1 = W1 + 64 * 18;
+    const float *b2 = b1 + 64 + 64 * 64;
+    const float *w3 = layers == 2 ? b2 + 64 : b1 + 64;
+    for (int i = threadIdx.x; i < 4 * 64; i += blockDim.x) {
+        const int k = i >> 6, u = i & 63;
+        Vs[i] = k == 0 ? W1[u * 18] : k == 1 ? W1[u * 18 + 1] : k == 2 ? (layers == 2 ? b2[u] : 0.f)
+                                                                        : w3[u];
+    }
+}
+
+__device__ __forceinline__ void load_score_lane(ScoreLane &m, const float *params, int R,
+                                                int layers, const float *W2s, const float *Vs)
+{
+    const float *b1 = params + (int64_t)R * 16 + 64 * 18;
+    const float *w3 = layers == 2 ? b1 + 64 + 64 * 64 + 64 : b1 + 64;
+    m.W2s = W2s;
+    m.Vs = Vs;
+    m.two = layers == 2;
+    m.b3 = w3[64];
+}
+
+// The region term of the lane's units for region r: table [R][64] (region_l1).
+__device__ __forceinline__ void load_region_term(float pr[16], const float *table, int r)
+{
+    const int g = __lane_id() >> 4;
+    const float *row = table + (int64_t)r * 64 + 4 * g;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const float4 v = *(const float4 *)(row + 16 * c);
+        pr[c * 4 + 0] = v.x;
+        pr[c * 4 + 1] = v.y;
+        pr[c * 4 + 2] = v.z;
+        pr[c * 4 + 3] = v.w;
+    }
+}
+
+// Score of row l%16 (returned in every lane of that column) with the row's cost and
+// log1p(stock).
+__device__ __forceinline__ float score_tile(const ScoreLane &m, const float pr[16], float cost,
+                                            float lx)
+{
+    const int i = __lane_id() & 15, g = __lane_id() >> 4;
+    v4f h1[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const float4 wc = *(const float4 *)(m.Vs + 16 * c + 4 * g);
+        const float4 wl = *(const float4 *)(m.Vs + 64 + 16 * c + 4 * g);
+        const float a[4] = {wc.x, wc.y, wc.z, wc.w}, b[4] = {wl.x, wl.y, wl.z, wl.w};
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const float z = fmaf(b[v], lx, fmaf(a[v], cost, pr[c * 4 + v]));
+            h1[c][v] = z > 0.f ? z : 0.f;
+        }
+    }
+    v4f h2[4];
+    if (m.two) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const float4 bb = *(const float4 *)(m.Vs + 128 + 16 * t + 4 * g);
+            v4f acc = {bb.x, bb.y, bb.z, bb.w};
+            // step s = 4c + v takes W2[16t + i][16c + 4g + v] with h1 unit 16c + 4g + v
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const float4 wv = *(const float4 *)(m.W2s + (16 * t + i) * W2S + 16 * c + 4 * g);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wv.x, h1[c][0], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wv.y, h1[c][1], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wv.z, h1[c][2], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wv.w, h1[c][3], acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[v] = acc[v] > 0.f ? acc[v] : 0.f;
+            h2[t] = acc;
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) h2[t] = h1[t];
+    }
+    float part = 0.f;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const float4 w = *(const float4 *)(m.Vs + 192 + 16 * t + 4 * g);
+        part = fmaf(w.x, h2[t][0], part);
+        part = fmaf(w.y, h2[t][1], part);
+        part = fmaf(w.z, h2[t][2], part);
+        part = fmaf(w.w, h2[t][3], part);
+    }
+    // sum over the four lane groups holding the same row: fixed order
+    const float p16 = __shfl_xor(part, 16, WAVE);
+    const float s01 = (__lane_id() & 16) ? p16 + part : part + p16; // (g0+g1) or (g2+g3)
+    const float p32 = __shfl_xor(s01, 32, WAVE);
+    const float tot = (__lane_id() & 32) ? p32 + s01 : s01 + p32;
+    return tot + m.b3;
+}
+
+// Perturbed scores of the warehouses in the stock list sl[0..nf) into zl[i] (list order)
+// by all waves of the workgroup: wave w takes tiles w, w + nwaves, ... (16 listed
+// warehouses each), four at a time.  The noise of the four tiles' 64 rows is drawn first,
+// one row per lane (lane l: row l%16 of the group's tile l/16), and lane l adds it to the
+// score of that row, which it holds after scoring that tile.
+__device__ __forceinline__ void score_rows(const ScoreLane &m, const float pr[16],
+                                           const float *costT_r, const int32_t *x,
+                                           const int32_t *sl, int nf, uint64_t seed,
+                                           uint32_t traj, uint32_t t, float *zl)
+{
+    const int wave = threadIdx.x / WAVE, nwaves = blockDim.x / WAVE;
+    const int lane = __lane_id(), grp = lane >> 4;
+    const int ntiles = (nf + 15) >> 4;
+    for (int tb = wave; tb < ntiles; tb += 4 * nwaves) {
+        const int mi = (tb + grp * nwaves) * 16 + (lane & 15);
+        const float gn = mi < nf ? gumbel(seed, traj, t, (uint32_t)sl[mi]) : 0.f;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int tile = tb + k * nwaves;
+            if (tile >= ntiles) break;
+            const int i = tile * 16 + (lane & 15);
+            const bool valid = i < nf;
+            const int w = valid ? sl[i] : 0;
+            const int xv = valid ? x[w] : 0;
+            const float s = score_tile(m, pr, valid ? costT_r[w] : 0.f, log1pf((float)xv));
+            if (grp == k && valid) zl[i] = s + gn;
+        }
+    }
+}
+
+// Noise-free scores of every warehouse (diagnostic), into sbuf[w], by all waves.
+__device__ __forceinline__ void score_all(const ScoreLane &m, const float pr[16],
+                                          const float *costT_r, const int32_t *x, int N,
+                                          float *sbuf)
+{
+    const int wave = threadIdx.x / WAVE, nwaves = blockDim.x / WAVE;
+    const int lane = __lane_id();
+    for (int tile = wave; tile < (N + 15) >> 4; tile += nwaves) {
+        const int w = tile * 16 + (lane & 15);
+        const bool valid = w < N;
+        const int xv = valid ? x[w] : 0;
+        const float s = score_tile(m, pr, valid ? costT_r[w] : 0.f, log1pf((float)xv));
+        if (lane < 16 && valid) sbuf[w] = s;
+    }
 }
 
 // Combine two (best, second) pairs of perturbed scores; ties go to the lower warehouse.

@@ -49,6 +49,7 @@ __global__ __launch_bounds__(256) void k_scan_entry(Prob P, Plan L, int skip_fir
     __shared__ int32_t s_cnt, s_base;
     __shared__ int32_t tile[SCAN_TILE];
     const int rpt = SCAN_TILE / N; // rows per tile
+    unsigned long long n_bytes = 0; // algorithmic HBM bytes (thread 0 counts)
     for (int base = 0; base < n; base += gridDim.x * 256) {
         if (threadIdx.x == 0) s_cnt = 0;
         __syncthreads();
@@ -65,6 +66,12 @@ __global__ __launch_bounds__(256) void k_scan_entry(Prob P, Plan L, int skip_fir
         }
         __syncthreads();
         const int cnt = s_cnt;
+        if (threadIdx.x == 0) { // every checked segment: its id and frontier read, one write
+            const int checked = n - base < gridDim.x * 256 ? (n - base + (int)gridDim.x - 1 -
+                                                              (int)blockIdx.x) / (int)gridDim.x
+                                                           : 256;
+            n_bytes += 12ull * (checked > 0 ? checked : 0);
+        }
         for (int t = 0; t < cnt; ++t) {
             const int g = s_g[t];
             const int32_t f = s_f[t];
@@ -86,6 +93,10 @@ __global__ __launch_bounds__(256) void k_scan_entry(Prob P, Plan L, int skip_fir
             // skipped one (then every run before f is all lost sales and E_f = 0 anyway)
             const bool resume = f >= 1 && !L.no_frontier && (pass > 2 || (pass == 2 && !skip_first_pass));
             const int jstart = resume ? f : 0;
+            if (threadIdx.x == 0) // u rows read from jstart, E rows written from jmin, E_f read
+                n_bytes += 4ull * N * ((uint64_t)(nsr - jstart) + (nsr > jmin ? nsr - jmin : 0) +
+                                       (resume ? 1 : 0)) +
+                           (pass > 1 && !L.no_frontier && nsr > f + 1 ? 4ull * (nsr - f - 1) : 0);
             int32_t acc[SCAN_MAXC];
 #pragma unroll
             for (int c = 0; c < SCAN_MAXC; ++c) {
@@ -141,6 +152,8 @@ __global__ __launch_bounds__(256) void k_scan_entry(Prob P, Plan L, int skip_fir
         }
         __syncthreads();
     }
+    if (threadIdx.x == 0 && n_bytes)
+        atomicAdd(&ctl->stat[blockIdx.x % STAT_SLOTS][ST_SCAN_BYTES], n_bytes);
 }
 
 __global__ void k_pass_end(Ctl *ctl)

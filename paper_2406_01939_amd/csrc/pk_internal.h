@@ -26,7 +26,7 @@ struct Prob {
 // Control block in device memory: the pass loop runs without host round trips; every
 // pass kernel reads `pass`/`done` and the end-of-pass kernel advances them.
 constexpr int STAT_SLOTS = 64; // statistics are spread over slots to avoid one hot address
-enum { ST_ORDERS = 0, ST_RUNS, ST_CHANGED, ST_BYTES, ST_NEAR_TIES, ST_FLOPS, ST_N };
+enum { ST_ORDERS = 0, ST_RUNS, ST_CHANGED, ST_BYTES, ST_NEAR_TIES, ST_FLOPS, ST_SCAN_BYTES, ST_N };
 
 // Ctl::error bits set by device-side consistency checks (the validate bits are 1..8).
 constexpr int32_t ERR_NO_PROGRESS = 1 << 12; // a walk step could not commit any order
