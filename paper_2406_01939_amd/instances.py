@@ -322,3 +322,72 @@ def random_tiny(seed: int, N: int = 4, K: int = 3, R: int = 3, T: int = 12, qmax
     return Instance(N=N, K=K, R=R, traj_offsets=offs, sku=sku, region=region, qty=qty,
                     x0=x0, cost=cost, rng_seed=int(rng.integers(0, 2**63)), params=params,
                     n_hidden_layers=n_hidden_layers, name=f"tiny{seed}")
+
+
+# ---------------------------------------------------------------- OWMR inventory problem
+# One central warehouse and N retailers (the appendix's inventory-control extension): each
+# order is a demand at one retailer; retailers follow (s_n, S_n) order-up-to rules within
+# their capacity, the central warehouse an (s, S) rule.  The base case follows the
+# appendix's experiment: 4,000 stores, one year of 10,000 units a day as unit demands
+# (T = 3.65e6), stores ordering up to 20 when they fall to 10, and a central level that
+# lasts about a week (70,000 units); stores are drawn with weights (1 - alpha)^i.
+OWMR_WORKLOADS: Dict[str, dict] = {
+    "owmr_n4000_t3650000": dict(N=4000, T=3_650_000, s_ret=10, S_ret=20, cap=20, s0=10,
+                                S0=70_000, alpha=0.0, dmax=1, seed=7),
+    "owmr_n40_t10000": dict(N=40, T=10_000, s_ret=3, S_ret=8, cap=8, s0=10, S0=700,
+                            alpha=0.0, dmax=1, seed=8),
+}
+
+
+@dataclasses.dataclass
+class OwmrInstance:
+    N: int
+    retailer: np.ndarray  # int32 [T]
+    demand: np.ndarray    # int32 [T]
+    s_ret: np.ndarray     # int32 [N] reorder point
+    S_ret: np.ndarray     # int32 [N] order-up-to level
+    cap: np.ndarray       # int32 [N] capacity
+    x_init: np.ndarray    # int32 [N] stock at t = 0
+    s0: int
+    S0: int
+    x0_init: int
+    name: str = ""
+
+    @property
+    def T(self) -> int:
+        return int(self.retailer.size)
+
+
+def make_owmr_instance(name: str, **overrides) -> OwmrInstance:
+    """Build the named OWMR workload; overrides change its sizes or parameters."""
+    cfg = dict(OWMR_WORKLOADS[name])
+    cfg.update(overrides)
+    N, T = int(cfg["N"]), int(cfg["T"])
+    rng = np.random.default_rng(cfg["seed"])
+    w = (1.0 - float(cfg["alpha"])) ** np.arange(N, dtype=np.float64)
+    cdf = np.cumsum(w / w.sum())
+    cdf[-1] = 1.0
+    retailer = np.minimum(np.searchsorted(cdf, rng.random(T), side="right"), N - 1)
+    demand = rng.integers(1, int(cfg["dmax"]) + 1, T)
+    full = lambda v: np.full(N, int(v), dtype=np.int32)
+    return OwmrInstance(N=N, retailer=retailer.astype(np.int32), demand=demand.astype(np.int32),
+                        s_ret=full(cfg["s_ret"]), S_ret=full(cfg["S_ret"]), cap=full(cfg["cap"]),
+                        x_init=full(min(cfg["S_ret"], cfg["cap"])), s0=int(cfg["s0"]),
+                        S0=int(cfg["S0"]), x0_init=int(cfg["S0"]), name=name)
+
+
+def random_owmr(seed: int, N: int = 4, T: int = 40, dmax: int = 3, cap_max: int = 6,
+                s0=None, S0=None) -> OwmrInstance:
+    """Small random OWMR instances for brute-force checks: random retailer levels and
+    capacities, demands 0..dmax, a central level a few retailer orders deep."""
+    rng = np.random.default_rng(seed)
+    cap = rng.integers(1, cap_max + 1, N)
+    S_ret = rng.integers(0, cap + 3)  # a level above capacity is cut to it by the policy
+    s_ret = rng.integers(-1, S_ret + 1)
+    x_init = rng.integers(0, cap + 1)
+    S0 = int(rng.integers(cap.max(), 4 * cap.sum() + 2)) if S0 is None else int(S0)
+    s0 = int(rng.integers(-1, S0 // 2 + 1)) if s0 is None else int(s0)
+    i32 = lambda a: np.asarray(a, dtype=np.int32)
+    return OwmrInstance(N=N, retailer=i32(rng.integers(0, N, T)), demand=i32(rng.integers(0, dmax + 1, T)),
+                        s_ret=i32(s_ret), S_ret=i32(S_ret), cap=i32(cap), x_init=i32(x_init),
+                        s0=s0, S0=S0, x0_init=int(rng.integers(0, S0 + 1)), name=f"owmr{seed}")

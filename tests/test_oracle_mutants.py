@@ -118,17 +118,42 @@ MUTANTS = [
 ]
 
 
-def _run_pins_against(name, old, new, workdir):
-    src = open(SRC).read()
+# The inventory-control (OWMR) oracle: its own source, library variable and pins.
+OWMR_SRC = os.path.join(ROOT, "oracle", "owmr_oracle.c")
+OWMR_PINS = [os.path.join(ROOT, "tests", "test_oracle_owmr.py")]
+OWMR_MUTANTS = [
+    ("owmr_retailer_receives_full_order",
+     "const int64_t got = q < *x0 ? q : *x0;", "const int64_t got = q;"),
+    ("owmr_central_not_clamped",
+     "*x0 = reset ? P->S0 : (*x0 > q ? *x0 - q : 0);", "*x0 = reset ? P->S0 : *x0 - q;"),
+    ("owmr_reset_strict", "const int rs = x0 - qq <= P->s0;", "const int rs = x0 - qq < P->s0;"),
+    ("owmr_order_ignores_capacity",
+     "const int64_t level = P->S_ret[n] < P->cap[n] ? P->S_ret[n] : P->cap[n];",
+     "const int64_t level = P->S_ret[n];"),
+    ("owmr_alg1_view_not_reset",
+     "for (int n = 0; n < P->N; ++n) c->x[n] = P->x_init[n]; /* every view starts at s_1 */",
+     "if (m == 0) for (int n = 0; n < P->N; ++n) c->x[n] = P->x_init[n];"),
+    ("owmr_runs_reset_window_off_by_one", "if (c->LR[t] >= a) {", "if (c->LR[t] > a) {"),
+    ("owmr_runs_counts_reset_order",
+     "const int64_t v = P->S0 - (c->Q[t] - c->Q[r + 1]);",
+     "const int64_t v = P->S0 - (c->Q[t] - c->Q[r]);"),
+    ("owmr_stops_one_pass_early",
+     "        if (same) { rc = 0; break; }", "        if (same || k > 1) { rc = 0; break; }"),
+]
+
+
+def _run_pins_against(name, old, new, workdir, src_path=SRC, env_var="PICARD_ORACLE_LIB",
+                      pins=PINS):
+    src = open(src_path).read()
     assert src.count(old) == 1, f"{name}: target text must occur once in the oracle"
     csrc = os.path.join(workdir, name + ".c")
     so = os.path.join(workdir, name + ".so")
     open(csrc, "w").write(src.replace(old, new))
     subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-w", csrc,
                            "-o", so, "-lm"])
-    env = dict(os.environ, PICARD_ORACLE_LIB=so)
+    env = dict(os.environ, **{env_var: so})
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-m", "not gpu",
-                        "-p", "no:cacheprovider", *PINS],
+                        "-p", "no:cacheprovider", *pins],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     tail = "\n".join(r.stdout.splitlines()[-6:])
     return r.returncode, tail
@@ -140,6 +165,9 @@ def test_every_planted_mistake_fails_a_pin():
         with ThreadPoolExecutor(max_workers=4) as pool:
             futs = {name: pool.submit(_run_pins_against, name, old, new, d)
                     for name, old, new in MUTANTS}
+            futs.update({name: pool.submit(_run_pins_against, name, old, new, d, OWMR_SRC,
+                                           "PICARD_OWMR_ORACLE_LIB", OWMR_PINS)
+                         for name, old, new in OWMR_MUTANTS})
             results = {name: f.result() for name, f in futs.items()}
     survivors = {n: t for n, (rc, t) in results.items() if rc == 0}
     crashed = {n: (rc, t) for n, (rc, t) in results.items() if rc not in (0, 1)}
@@ -150,4 +178,7 @@ def test_every_planted_mistake_fails_a_pin():
 def test_mutant_targets_exist():
     src = open(SRC).read()
     for name, old, _ in MUTANTS:
+        assert src.count(old) == 1, name
+    src = open(OWMR_SRC).read()
+    for name, old, _ in OWMR_MUTANTS:
         assert src.count(old) == 1, name
