@@ -185,11 +185,11 @@ def main():
                     help="time the serial sweep on the first M orders of each trajectory "
                          "(default: 3e5 for workloads whose full serial sweep runs for "
                          "minutes, else the whole workload)")
-    ap.add_argument("--legs", default="batch,single",
+    ap.add_argument("--legs", default="batch,single,owmr",
                     help="comma-separated greedy legs after the headline: batch (256 "
                          "trajectories of uneven horizon), single (one trajectory of 1e6 "
-                         "orders), learned64 (64 trajectories of 2e5 orders, learned); "
-                         "'' for none")
+                         "orders), learned64 (64 trajectories of 2e5 orders, learned), owmr "
+                         "(the inventory-control workload); '' for none")
     ap.add_argument("--legs-after-s", type=float, default=470.0,
                     help="skip the remaining legs once the run has taken this long")
     ap.add_argument("--with-grad", action="store_true",
@@ -277,7 +277,8 @@ def main():
         dt = time.perf_counter() - t0
         _progress(f"{name}: {steps} timed simulations, {dt:.3f} s")
         r = {"value": total * steps / dt, "ms_per_step": 1e3 * dt / steps, "inst": inst,
-             "policy": policy, "B": B, "passes": passes, "total": total}
+             "policy": policy, "B": B, "passes": passes, "total": total,
+             "walk_waves": out["stats"]["walk_waves"]}
         per = max(steps, 1)
         r["work"] = {"orders_walked_per_step": acc["orders_walked"] / per,
                      "runs_walked_per_step": acc["runs_walked"] / per,
@@ -358,6 +359,59 @@ def main():
         return r
 
     HOST = host_info()
+
+    def owmr_leg(name="owmr_n4000_t3650000", steps=5, cpu_s=5.0):
+        """The OWMR inventory workload (the appendix's base case shape): Picard with one
+        process per retailer against the serial GPU sweep and the CPU oracle.  Its passes
+        are an exclusive scan of the packed cache and a per-retailer walk; the roofline is
+        the algorithmic bytes of whole passes (scan: 16 B per order; reset list: 8 B; walk:
+        32 B read and 8 B written per order) over the simulation time."""
+        from paper_2406_01939_amd import owmr_api as ow
+        from paper_2406_01939_amd.instances import make_owmr_instance
+        inst = make_owmr_instance(name)
+        prob = ow.DeviceOwmr.from_instance(inst)
+        out = ow.picard_simulate(prob)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            out = ow.picard_simulate(prob)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        ser = ow.serial_simulate(prob)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ser = ow.serial_simulate(prob)
+        torch.cuda.synchronize()
+        sdt = time.perf_counter() - t1
+        same = bool(torch.equal(ser["q"], out["q"]) and torch.equal(ser["reset"], out["reset"]))
+        bytes_sim = out["passes"] * inst.T * (16 + 8 + 40)
+        achieved = bytes_sim / dt / 1e9
+        res = {"workload": name, "retailers": inst.N, "orders": inst.T, "value": inst.T / dt,
+               "unit": "orders/s", "ms_per_step": 1e3 * dt, "steps": steps,
+               "passes": out["passes"], "resets_R": ser["R"],
+               "bound_2R_plus_2": 2 * ser["R"] + 2, "dtype": "int64",
+               "roofline": {"kernel": "whole passes (scan + reset list + retailer walk)",
+                            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+               "serial_gpu": {"value": inst.T / sdt, "unit": "orders/s", "seconds": sdt,
+                              "identical_actions": same},
+               "speedup_vs_serial_gpu": sdt / dt}
+        _progress(f"{name}: Picard {1e3 * dt:.2f} ms ({out['passes']} passes, R = {ser['R']}), "
+                  f"serial GPU {1e3 * sdt:.1f} ms")
+        if cpu_s > 0:
+            from oracle import owmr as O
+            O.build(force=False)
+            n, t2 = 0, time.perf_counter()
+            while time.perf_counter() - t2 < cpu_s:
+                O.serial(inst)
+                n += 1
+            cdt = (time.perf_counter() - t2) / n
+            res["cpu_baseline"] = {"value": inst.T / cdt, "unit": "orders/s", "cores": 1,
+                                   "kind": "oracle", "sample": f"{n} serial oracle rollouts of "
+                                   f"the whole workload, {cdt * 1e3:.1f} ms each, one thread"}
+            res["speedup_vs_cpu_oracle_one_core"] = cdt / dt
+        del prob
+        return res
 
     def partition_sweep(M=10_000, betas=(0.0, -0.2, -0.4, -0.6, -0.8, -1.0), reps=3,
                         policy="greedy"):
@@ -557,7 +611,8 @@ def main():
            "dtype": "int32" if policy == "greedy" else "f32", "data": "synthetic",
            "config": {"workload": args.workload, "policy": policy, "n_warehouses": inst.N,
                       "n_skus": inst.K, "n_regions": inst.R, "n_traj": inst.n_traj,
-                      "orders": m["total"], "block_len": m["B"], "parallelism": "1 GPU"},
+                      "orders": m["total"], "block_len": m["B"], "parallelism": "1 GPU",
+                      "walk_waves": m["walk_waves"]},
            "passes_max": int(passes.max()), "passes_mean": float(passes.mean()),
            "roofline": m["roofline"], "host": HOST}
     for k in ("roofline_scan", "near_ties", "work", "serial_gpu", "speedup_vs_serial_gpu",
@@ -570,6 +625,12 @@ def main():
     res["headline_seconds"] = time.perf_counter() - t_start
     legs = {}
     for leg in [x for x in args.legs.split(",") if x]:
+        if leg == "owmr":
+            if time.perf_counter() - t_start > args.legs_after_s:
+                legs[leg] = {"skipped": "time"}
+                continue
+            legs[leg] = owmr_leg(cpu_s=min(args.cpu_seconds, 5.0) if cpu else 0.0)
+            continue
         name = {"batch": BATCH_WORKLOAD, "single": SINGLE_WORKLOAD,
                 "learned64": LEARNED_WORKLOAD}[leg]
         if name == args.workload:

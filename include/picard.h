@@ -126,6 +126,9 @@ typedef struct pk_picard_opts {
                                  starts from the state its process reaches under
                                  Algorithm 1.  PK_ERR_INVALID_ARG for a negative
                                  process. */
+    int32_t walk_waves;   /* MLP: waves per workgroup of the run walk, 4 or 8; 0 = the
+                             autotuned choice for this problem when block_len is the tuned
+                             one, else 4.  Same results either way. */
 } pk_picard_opts;
 
 /* Statistics of one pk_picard_simulate call (all optional). */
@@ -151,6 +154,7 @@ typedef struct pk_stats {
     int64_t scan_launches;   /* launches of that kernel timed */
     int64_t scan_bytes;      /* algorithmic HBM bytes of the scan's launches (u rows read,
                                 E rows written, frontier checks) */
+    int32_t walk_waves;      /* MLP: waves per workgroup of the run walk used */
 } pk_stats;
 
 /* Bytes of scratch that pk_picard_simulate, pk_serial_simulate and pk_policy_grad need
@@ -216,10 +220,15 @@ pk_status pk_policy_grad(const pk_problem *problem, const pk_policy *policy,
                          float *grad, double *objective, void *ws, size_t ws_bytes,
                          int32_t validate, void *stream);
 
-/* Choose block_len for pk_picard_simulate by timing candidate lengths on this instance
- * (outputs are discarded).  Results are cached per (policy, N, R, K, horizon bucket) in
- * this process, and in the JSON file named by $PICARD_AUTOTUNE_CACHE if set.
- * best_block_len: HOST out. */
+/* Choose block_len (and, for the MLP policy, the run walk's waves per workgroup) for
+ * pk_picard_simulate by timing candidates on this instance (outputs are discarded).
+ * Greedy: every candidate length from 64 to 65536, best of three rounds.  MLP: whole
+ * simulations, from 2048 up and then down by factors of two while the time falls (a
+ * candidate is abandoned once it is slower than the best), then 8 waves per workgroup at
+ * the best length.  Results are cached per (policy, N, R, K, total and horizon buckets) in
+ * this process, read from the JSON file named by $PICARD_AUTOTUNE_CACHE if set, else from
+ * autotune_mi355x.json beside the library (results the autotuner recorded on MI355X),
+ * and new results are written to $PICARD_AUTOTUNE_CACHE only.  best_block_len: HOST out. */
 pk_status pk_autotune(const pk_problem *problem, const pk_policy *policy, void *ws,
                       size_t ws_bytes, int32_t *best_block_len, void *stream);
 
@@ -317,6 +326,52 @@ pk_status pk_picard_simulate_capacity(const pk_problem *problem, const int32_t *
                                       int32_t *actions, int32_t *final_inv, int32_t *final_cap,
                                       int32_t *passes, int64_t *changed, int32_t *caches,
                                       void *stream);
+
+/* ---------------------------------------------------------------------------------
+ * One Warehouse Multi-Retailer inventory control (the appendix's extension "Inventory
+ * Control with Replenishment"): one central warehouse and N retailers.  Order t is a
+ * demand of d_t >= 0 units at retailer n_t.  The retailer, at stock x before the demand,
+ * keeps p = (x - d_t)^+ and orders q = min(S_n, c_n) - p if p <= s_n (and that is
+ * positive), else 0; the central warehouse, at stock x_0, resets (orders up to S0) iff
+ * x_0 - q <= s0.  The retailer receives min(q, x_0); x_0 becomes S0 after a reset, else
+ * (x_0 - q)^+.  The action of order t is (q_t, reset_t).  Integer arithmetic throughout. */
+typedef struct pk_owmr_problem {
+    int32_t n_retailers;      /* N >= 1 */
+    int32_t reserved;         /* 0 */
+    int64_t n_orders;         /* T >= 0, < 2^31 */
+    const int32_t *retailer;  /* [T] in [0, N) */
+    const int32_t *demand;    /* [T] >= 0 */
+    const int32_t *s_ret;     /* [N] reorder points s_n */
+    const int32_t *S_ret;     /* [N] order-up-to levels S_n >= 0 */
+    const int32_t *cap;       /* [N] capacities c_n >= 0, with T c_n < 2^40 */
+    const int32_t *x_init;    /* [N] retailer stock at t = 0, in [0, c_n] */
+    int64_t s0, S0, x0_init;  /* central (s, S) rule and its stock at t = 0 (S0, x0_init >= 0) */
+} pk_owmr_problem;
+
+/* Bytes of scratch the two OWMR calls need.  Writes *bytes. */
+pk_status pk_owmr_workspace_size(const pk_owmr_problem *problem, size_t *bytes);
+
+/* The serial rollout (one order at a time, on the GPU).  q, reset [T] out (int32);
+ * final_x [N] out, nullable (retailer stock after the last order); final_x0, resets:
+ * HOST out, nullable (central stock after the last order; R, the number of resets).
+ * PK_ERR_INVALID_ARG for out-of-range inputs (checked on the device).  Synchronous. */
+pk_status pk_owmr_serial_simulate(const pk_owmr_problem *problem, void *ws, size_t ws_bytes,
+                                  int32_t *q, int32_t *reset, int32_t *final_x,
+                                  int64_t *final_x0, int64_t *resets, void *stream);
+
+/* Algorithm 1 with one process per retailer (the appendix's allocation of the orders of
+ * retailer n to process n).  init_q, init_reset: DEVICE [T] nullable (NULL: no order and
+ * no reset everywhere) is alpha^0.  max_passes 0 means T + 1 (Proposition 2.1).  Outputs
+ * as pk_owmr_serial_simulate; on PK_OK they equal the serial rollout.  passes: HOST out
+ * (k* + 1).  changed: HOST [max_passes] out, nullable: orders whose action changed in each
+ * pass.  caches: DEVICE [max_passes][T] int64 out, nullable: alpha^k after pass k packed as
+ * reset * 2^40 + q.  PK_ERR_NOT_CONVERGED when max_passes end without a repeat (q and
+ * reset then hold the last cache).  Synchronous. */
+pk_status pk_owmr_picard_simulate(const pk_owmr_problem *problem, int32_t max_passes,
+                                  const int32_t *init_q, const int32_t *init_reset, void *ws,
+                                  size_t ws_bytes, int32_t *q, int32_t *reset, int32_t *final_x,
+                                  int64_t *final_x0, int32_t *passes, int64_t *changed,
+                                  int64_t *caches, void *stream);
 
 /* Message for the last non-OK status on this thread ("" if none). */
 const char *pk_last_error(void);

@@ -56,7 +56,8 @@ class pk_policy(C.Structure):
 class pk_picard_opts(C.Structure):
     _fields_ = [("block_len", C.c_int32), ("max_passes", C.c_int32),
                 ("use_frontier", C.c_int32), ("graph_unroll", C.c_int32),
-                ("init_cache", C.c_void_p), ("validate", C.c_int32), ("partition", C.c_void_p)]
+                ("init_cache", C.c_void_p), ("validate", C.c_int32), ("partition", C.c_void_p),
+                ("walk_waves", C.c_int32)]
 
 
 class pk_stats(C.Structure):
@@ -65,7 +66,7 @@ class pk_stats(C.Structure):
                 ("orders_walked", C.c_int64), ("near_ties", C.c_int64), ("walk_ms", C.c_double),
                 ("walk_launches", C.c_int64), ("walk_bytes", C.c_int64), ("walk_flops", C.c_int64),
                 ("timing", C.c_int32), ("scan_ms", C.c_double), ("scan_launches", C.c_int64),
-                ("scan_bytes", C.c_int64)]
+                ("scan_bytes", C.c_int64), ("walk_waves", C.c_int32)]
 
 
 _lib = None
@@ -229,11 +230,12 @@ def pk_picard_simulate(prob: DeviceProblem, policy: str = "greedy", block_len: i
                        init_cache: Optional[torch.Tensor] = None, validate: bool = False,
                        partition: Optional[torch.Tensor] = None,
                        want_shipped=True, want_final=True, timing=False, stream=None,
-                       raise_not_converged=True, out: Optional[dict] = None) -> dict:
+                       raise_not_converged=True, out: Optional[dict] = None,
+                       walk_waves: int = 0) -> dict:
     dev = prob.sku.device
     p, po = prob.c_problem(), prob.c_policy(policy)
     o = pk_picard_opts(block_len, max_passes, int(use_frontier), graph_unroll,
-                       _ptr(init_cache), int(validate), _ptr(partition))
+                       _ptr(init_cache), int(validate), _ptr(partition), walk_waves)
     n = C.c_size_t(0)
     _check(lib().pk_workspace_size(C.byref(p), C.byref(po), C.byref(o), C.byref(n)))
     ws = workspace(int(n.value), dev)

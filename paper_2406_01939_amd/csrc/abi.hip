@@ -1,7 +1,10 @@
 // C-ABI entry points of libpicard (declared in include/picard.h).
 #include <hip/hip_runtime.h>
 
+#include <dlfcn.h>
+
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -43,8 +46,8 @@ size_t costT_bytes(int N, int R, int n_traj);
 hipError_t setup_costT(const Prob &P, const float *params, float *costT, hipStream_t st);
 size_t walk_mlp_lds(int N);
 hipError_t launch_walk_mlp(const Prob &P, const Plan &L, const float *params, int layers,
-                           const float *costT, int32_t *final_inv, bool has_init, int grid,
-                           hipStream_t st);
+                           const float *costT, int32_t *final_inv, bool has_init, int n_cus,
+                           int waves, hipStream_t st);
 hipError_t launch_serial_mlp(const Prob &P, const float *params, int layers, const float *costT,
                              int32_t *state, int32_t *actions, int32_t *shipped, hipStream_t st);
 hipError_t launch_scores(const Prob &P, const float *params, int layers, const float *costT,
@@ -125,7 +128,7 @@ pk_status scratch_on_current_device(void **out)
     } while (0)
 
 constexpr int DEFAULT_BLOCK_GREEDY = 1024;
-constexpr int DEFAULT_BLOCK_MLP = 256;
+constexpr int DEFAULT_BLOCK_MLP = 1024;
 constexpr int GRAD_BLOCK = 1024;  // run length of the gradient's state reconstruction
 constexpr int GRAD_MAX_WG = 512;  // workgroups (and FP64 partial sets) of the gradient
 constexpr int MIN_AUTOTUNE_BLOCK = 64;
@@ -344,6 +347,8 @@ struct GraphKey {
         memcpy(bytes + o, po, sizeof *po); o += sizeof *po;
         const int64_t extra[10] = {(int64_t)(uintptr_t)fin, hi, grid, U, nseg, timing, setup,
                                    (int64_t)(uintptr_t)init_cache, validate, max_passes};
+        static_assert(sizeof(extra) + sizeof(P) + sizeof(L) + sizeof(pk_policy) <= sizeof(bytes),
+                      "graph key too small");
         memcpy(bytes + o, extra, sizeof extra);
     }
     bool operator==(const GraphKey &k) const { return memcmp(bytes, k.bytes, sizeof bytes) == 0; }
@@ -473,11 +478,15 @@ thread_local LastPasses g_last_passes;
 // noalloc: create nothing (no captured graph, no events, no pinned control block, no host
 // heap buffer); the passes are enqueued directly and the control block is read into a
 // stack copy.
+// abort_ms > 0 (the autotuner): give up, with PK_ERR_NOT_CONVERGED, once the call has
+// taken longer than that (checked whenever the host reads the control block).
 pk_status picard_run(const pk_problem *problem, const Dims &d, const pk_policy *policy,
                      const pk_picard_opts &o, int B, void *ws, size_t ws_bytes,
                      int32_t *actions, int32_t *shipped, int32_t *final_inv, pk_stats *stats,
-                     hipStream_t stream, bool noalloc = false)
+                     hipStream_t stream, bool noalloc = false, double abort_ms = 0.0)
 {
+    const auto t_call = std::chrono::steady_clock::now();
+    const int waves = o.walk_waves == 8 ? 8 : 4;
     const int64_t mp64 = o.max_passes > 0 ? o.max_passes : d.max_T + 1;
     const int max_passes = (int)std::min<int64_t>(mp64, 0x7ffffff0);
     if (!ws || ws_bytes < picard_bytes(d, policy, B))
@@ -523,8 +532,9 @@ pk_status picard_run(const pk_problem *problem, const Dims &d, const pk_policy *
     const int grid = num_cus(); // the walk sizes its grid from the CU count
     const bool timing = stats && stats->timing && !noalloc;
     int U = o.graph_unroll > 0 ? o.graph_unroll : 8;
+    const int gridw = grid * 16 + waves; // the walks' launch shape, part of every graph key
     GraphKey key0; // this call's problem and plan, without the unroll
-    key0.set(P, L, policy, final_inv, has_init, grid, 0, (int)sz.n_seg_max, timing);
+    key0.set(P, L, policy, final_inv, has_init, gridw, 0, (int)sz.n_seg_max, timing);
     if (o.graph_unroll <= 0 && g_last_passes.valid && g_last_passes.key == key0 &&
         g_last_passes.passes >= 2 && g_last_passes.passes <= 64)
         U = g_last_passes.passes;
@@ -558,7 +568,7 @@ pk_status picard_run(const pk_problem *problem, const Dims &d, const pk_policy *
         }
         if (policy->kind == PK_POLICY_MLP)
             HIP_TRY(launch_walk_mlp(P, L, policy->params, policy->n_hidden_layers, L.costT,
-                                    final_inv, has_init, num_cus() * 4, s2)); // resident: 4 per CU
+                                    final_inv, has_init, num_cus(), waves, s2));
         else if (L.worker)
             HIP_TRY(launch_walk_chain_greedy(P, L, final_inv, has_init, grid, s2));
         else
@@ -582,7 +592,7 @@ pk_status picard_run(const pk_problem *problem, const Dims &d, const pk_policy *
     if (!done && !noalloc && U > 1 && max_passes >= U) {
         for (int with_setup = 1; with_setup >= 0; --with_setup) {
             GraphKey key;
-            key.set(P, L, policy, final_inv, has_init, grid, U, (int)sz.n_seg_max, timing,
+            key.set(P, L, policy, final_inv, has_init, gridw, U, (int)sz.n_seg_max, timing,
                     with_setup != 0, o.init_cache, o.validate, max_passes);
             pk_status gs = g_graph.get(key, timing ? 3 * U : 0,
                                        [&](hipStream_t cs, GraphEntry &ge) -> pk_status {
@@ -630,6 +640,10 @@ pk_status picard_run(const pk_problem *problem, const Dims &d, const pk_policy *
             graph_walks += U;
         }
         done = hc->done;
+        if (!done && abort_ms > 0.0 &&
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_call)
+                    .count() > abort_ms)
+            return fail(PK_ERR_NOT_CONVERGED, "abandoned after %.0f ms (autotuner)", abort_ms);
     }
     if (d.total > 0 && hc->done == 1 && hc->passes_done >= 1) {
         g_last_passes.valid = true;
@@ -655,6 +669,7 @@ pk_status picard_run(const pk_problem *problem, const Dims &d, const pk_policy *
             for (int b = 0; b < d.n_traj; ++b) stats->passes[b] = lcp_host[b] + 1;
         stats->passes_max = d.total > 0 ? hc->passes_done : 1;
         stats->block_len = o.partition ? 0 : B;
+        stats->walk_waves = policy->kind == PK_POLICY_MLP ? waves : 0;
         unsigned long long sum[ST_N] = {};
         for (int i = 0; i < STAT_SLOTS; ++i)
             for (int k = 0; k < ST_N; ++k) sum[k] += hc->stat[i][k];
@@ -685,8 +700,12 @@ pk_status picard_run(const pk_problem *problem, const Dims &d, const pk_policy *
 }
 
 // ---------------------------------------------------------------- block-length autotuner
+struct Tuned {
+    int block_len = 0;
+    int waves = 4; // learned walk: waves per workgroup
+};
 std::mutex g_tune_mu;
-std::map<std::string, int> g_tune;
+std::map<std::string, Tuned> g_tune;
 bool g_tune_loaded = false;
 
 std::string tune_key(const Dims &d, const pk_policy *po)
@@ -701,32 +720,63 @@ std::string tune_key(const Dims &d, const pk_policy *po)
     return buf;
 }
 
-// The cache file is a flat JSON object {"key": block_len, ...}.
-void tune_load_locked()
+// The results file beside the library: what the autotuner recorded on MI355X.
+std::string shipped_tune_path()
 {
-    if (g_tune_loaded) return;
-    g_tune_loaded = true;
-    const char *path = getenv("PICARD_AUTOTUNE_CACHE");
-    if (!path) return;
-    FILE *f = fopen(path, "r");
+    Dl_info info;
+    if (!dladdr((void *)&shipped_tune_path, &info) || !info.dli_fname) return "";
+    std::string p = info.dli_fname;
+    const size_t slash = p.rfind('/');
+    return (slash == std::string::npos ? std::string(".") : p.substr(0, slash)) +
+           "/autotune_mi355x.json";
+}
+
+// A flat JSON object {"key": {"block_len": B, "waves": W}, ...} (a bare number is a block
+// length).  Entries already held are kept.
+void tune_read_locked(const std::string &path)
+{
+    FILE *f = fopen(path.c_str(), "r");
     if (!f) return;
     std::string txt;
     char buf[4096];
     size_t n;
     while ((n = fread(buf, 1, sizeof buf, f)) > 0) txt.append(buf, n);
     fclose(f);
-    size_t i = 0;
-    while ((i = txt.find('"', i)) != std::string::npos) {
+    size_t i = txt.find('{');
+    while (i != std::string::npos && (i = txt.find('"', i + 1)) != std::string::npos) {
         const size_t j = txt.find('"', i + 1);
         if (j == std::string::npos) break;
         const std::string key = txt.substr(i + 1, j - i - 1);
-        const size_t c = txt.find(':', j);
+        size_t c = txt.find(':', j);
         if (c == std::string::npos) break;
-        const int v = atoi(txt.c_str() + c + 1);
-        if (v > 0) g_tune[key] = v;
-        i = txt.find_first_of(",}", c);
-        if (i == std::string::npos) break;
+        ++c;
+        while (c < txt.size() && isspace((unsigned char)txt[c])) ++c;
+        Tuned t;
+        if (c < txt.size() && txt[c] == '{') {
+            const size_t e = txt.find('}', c);
+            if (e == std::string::npos) break;
+            const std::string obj = txt.substr(c, e - c);
+            const size_t pb = obj.find("\"block_len\"");
+            const size_t pw = obj.find("\"waves\"");
+            if (pb != std::string::npos) t.block_len = atoi(obj.c_str() + obj.find(':', pb) + 1);
+            if (pw != std::string::npos) t.waves = atoi(obj.c_str() + obj.find(':', pw) + 1);
+            i = e;
+        } else {
+            t.block_len = atoi(txt.c_str() + c);
+            i = c;
+        }
+        if (t.block_len > 0 && (t.waves == 4 || t.waves == 8) && !g_tune.count(key))
+            g_tune[key] = t;
     }
+}
+
+void tune_load_locked()
+{
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *path = getenv("PICARD_AUTOTUNE_CACHE");
+    if (path) tune_read_locked(path);
+    else tune_read_locked(shipped_tune_path());
 }
 
 void tune_save_locked()
@@ -739,7 +789,8 @@ void tune_save_locked()
     fputs("{", f);
     bool firstk = true;
     for (auto &kv : g_tune) {
-        fprintf(f, "%s\n  \"%s\": %d", firstk ? "" : ",", kv.first.c_str(), kv.second);
+        fprintf(f, "%s\n  \"%s\": {\"block_len\": %d, \"waves\": %d}", firstk ? "" : ",",
+                kv.first.c_str(), kv.second.block_len, kv.second.waves);
         firstk = false;
     }
     fputs("\n}\n", f);
@@ -747,78 +798,190 @@ void tune_save_locked()
     rename(tmp.c_str(), path);
 }
 
-// Times candidate block lengths on this instance (best of two runs each) and keeps the
-// fastest.  Outputs of the trial runs go to `actions`, which the caller overwrites.
+// The cached choice for this problem, if any.
+bool tune_lookup(const Dims &d, const pk_policy *po, Tuned *t)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    auto it = g_tune.find(tune_key(d, po));
+    if (it == g_tune.end()) return false;
+    *t = it->second;
+    return true;
+}
+
+// Times candidates on this instance and keeps the fastest.  Outputs of the trial runs go
+// to `actions`, which the caller overwrites.
+//  Greedy: every block length of the ladder, best of three rounds after a warm-up.
+//  MLP (whole simulations take seconds at scale): from 2048 upwards while the time falls,
+//  then downwards if 2048 stayed best; a candidate is abandoned as soon as it has taken
+//  longer than the best so far; then 8 waves per workgroup at the best length.  Short
+//  problems (under 0.2 s a run) keep the better of two runs per candidate.
 pk_status autotune_block(const pk_problem *problem, const Dims &d, const pk_policy *po,
-                         void *ws, size_t ws_bytes, int32_t *actions, hipStream_t st, int *best)
+                         void *ws, size_t ws_bytes, int32_t *actions, hipStream_t st,
+                         Tuned *best)
 {
     const std::string key = tune_key(d, po);
-    {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        tune_load_locked();
-        auto it = g_tune.find(key);
-        if (it != g_tune.end()) {
-            *best = it->second;
-            return PK_OK;
-        }
-    }
-    static const int cands[] = {64, 128, 256, 384, 512, 768, 1024, 1536, 2048, 4096, 8192, 16384, 65536};
-    constexpr int NC = (int)(sizeof(cands) / sizeof(cands[0]));
+    if (tune_lookup(d, po, best)) return PK_OK;
     pk_picard_opts o = {};
     o.use_frontier = 1;
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
-    auto run_ms = [&](int B, float *ms) -> pk_status {
-        HIP_TRY(hipEventRecord(e0, st));
+    auto run_ms = [&](int B, int waves, double abort_ms, double *ms) -> pk_status {
+        o.walk_waves = waves;
+        o.graph_unroll = po->kind == PK_POLICY_MLP ? 2 : 0;
+        HIP_TRY(hipStreamSynchronize(st));
+        const auto t0 = std::chrono::steady_clock::now();
         pk_status s = picard_run(problem, d, po, o, B, ws, ws_bytes, actions, nullptr, nullptr,
-                                 nullptr, st);
-        if (s != PK_OK) return s;
-        HIP_TRY(hipEventRecord(e1, st));
-        HIP_TRY(hipEventSynchronize(e1));
-        HIP_TRY(hipEventElapsedTime(ms, e0, e1));
-        return PK_OK;
+                                 nullptr, st, false, abort_ms);
+        HIP_TRY(hipStreamSynchronize(st));
+        *ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+                  .count();
+        if (s == PK_ERR_NOT_CONVERGED && abort_ms > 0.0) {
+            g_err[0] = 0;
+            *ms = 1e30; // abandoned
+            return PK_OK;
+        }
+        return s;
     };
-    bool usable[NC];
-    for (int i = 0; i < NC; ++i)
-        usable[i] = (cands[i] <= 2 * std::max<int64_t>(d.total, 1) || i == 0) &&
-                    ws_bytes >= picard_bytes(d, po, cands[i]);
-    // warm-up (clocks ramp up on an idle GPU), then rounds over all candidates in turn so
-    // that drift affects every candidate alike; each keeps its best time
-    const int warm_b = ws_bytes >= picard_bytes(d, po, DEFAULT_BLOCK_GREEDY) ? DEFAULT_BLOCK_GREEDY : cands[0];
-    float spent = 0.f;
-    for (int k = 0; k < 200 && spent < 300.f; ++k) {
-        float ms = 0.f;
-        pk_status s = run_ms(warm_b, &ms);
-        if (s != PK_OK) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return s; }
-        spent += ms;
+    Tuned pick;
+    if (po->kind == PK_POLICY_MLP) {
+        static const int ladder[] = {256, 512, 1024, 2048, 4096, 8192, 16384, 32768};
+        constexpr int NL = (int)(sizeof(ladder) / sizeof(ladder[0]));
+        auto usable = [&](int i) {
+            return i >= 0 && i < NL && (ladder[i] <= 2 * std::max<int64_t>(d.total, 1) || i == 0) &&
+                   ws_bytes >= picard_bytes(d, po, ladder[i]);
+        };
+        int i0 = 3; // 2048
+        while (i0 > 0 && !usable(i0)) --i0;
+        double t = 0.0, tb = 0.0;
+        pk_status s = run_ms(ladder[i0], 4, 0.0, &t); // also the warm-up
+        if (s != PK_OK) return s;
+        const bool twice = t < 200.0;
+        auto measure = [&](int B, int waves, double abort, double *out) -> pk_status {
+            pk_status r = run_ms(B, waves, abort, out);
+            if (r != PK_OK || !twice) return r;
+            double again = 0.0;
+            r = run_ms(B, waves, abort, &again);
+            *out = std::min(*out, again);
+            return r;
+        };
+        if ((s = measure(ladder[i0], 4, 0.0, &tb)) != PK_OK) return s;
+        int bi = i0;
+        for (int i = i0 + 1; usable(i); ++i) { // upwards
+            if ((s = measure(ladder[i], 4, tb, &t)) != PK_OK) return s;
+            if (t >= tb) break;
+            tb = t;
+            bi = i;
+        }
+        if (bi == i0)
+            for (int i = i0 - 1; usable(i); --i) { // downwards
+                if ((s = measure(ladder[i], 4, tb, &t)) != PK_OK) return s;
+                if (t >= tb) break;
+                tb = t;
+                bi = i;
+            }
+        pick.block_len = ladder[bi];
+        if ((s = measure(pick.block_len, 8, tb, &t)) != PK_OK) return s;
+        if (t < tb) pick.waves = 8;
+    } else {
+        static const int cands[] = {64, 128, 256, 384, 512, 768, 1024, 1536, 2048, 4096, 8192, 16384, 65536};
+        constexpr int NC = (int)(sizeof(cands) / sizeof(cands[0]));
+        bool usable[NC];
+        for (int i = 0; i < NC; ++i)
+            usable[i] = (cands[i] <= 2 * std::max<int64_t>(d.total, 1) || i == 0) &&
+                        ws_bytes >= picard_bytes(d, po, cands[i]);
+        // warm-up (clocks ramp up on an idle GPU), then rounds over all candidates in turn
+        // so that drift affects every candidate alike; each keeps its best time
+        const int warm_b = ws_bytes >= picard_bytes(d, po, DEFAULT_BLOCK_GREEDY) ? DEFAULT_BLOCK_GREEDY : cands[0];
+        double spent = 0.0;
+        for (int k = 0; k < 200 && spent < 300.0; ++k) {
+            double ms = 0.0;
+            pk_status s = run_ms(warm_b, 4, 0.0, &ms);
+            if (s != PK_OK) return s;
+            spent += ms;
+        }
+        double t[NC];
+        for (int i = 0; i < NC; ++i) t[i] = 1e30;
+        for (int round = 0; round < 3; ++round)
+            for (int i = 0; i < NC; ++i) {
+                if (!usable[i]) continue;
+                double ms = 0.0;
+                pk_status s = run_ms(cands[i], 4, 0.0, &ms);
+                if (s != PK_OK) return s;
+                t[i] = std::min(t[i], ms);
+            }
+        double best_ms = 1e30;
+        pick.block_len = DEFAULT_BLOCK_GREEDY;
+        for (int i = 0; i < NC; ++i)
+            if (usable[i] && t[i] < best_ms) {
+                best_ms = t[i];
+                pick.block_len = cands[i];
+            }
     }
-    float t[NC];
-    for (int i = 0; i < NC; ++i) t[i] = 1e30f;
-    for (int round = 0; round < 3; ++round)
-        for (int i = 0; i < NC; ++i) {
-            if (!usable[i]) continue;
-            float ms = 0.f;
-            pk_status s = run_ms(cands[i], &ms);
-            if (s != PK_OK) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return s; }
-            t[i] = std::min(t[i], ms);
-        }
-    float best_ms = 1e30f;
-    int best_b = DEFAULT_BLOCK_GREEDY;
-    for (int i = 0; i < NC; ++i)
-        if (usable[i] && t[i] < best_ms) {
-            best_ms = t[i];
-            best_b = cands[i];
-        }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune[key] = best_b;
+    g_tune[key] = pick;
     tune_save_locked();
-    *best = best_b;
+    *best = pick;
     return PK_OK;
 }
 
+
+// ---------------------------------------------------------------- OWMR inventory control
+pk_status check_owmr(const pk_owmr_problem *pr, OwmrDev *P)
+{
+    if (!pr) return fail(PK_ERR_INVALID_ARG, "problem is NULL");
+    if (pr->n_retailers < 1 || pr->n_orders < 0 || pr->n_orders >= (1ll << 31) - 1)
+        return fail(PK_ERR_SHAPE, "need N >= 1 and 0 <= T < 2^31 (N=%d T=%lld)", pr->n_retailers,
+                    (long long)pr->n_orders);
+    if (pr->n_retailers > (1 << 24)) return fail(PK_ERR_SHAPE, "N=%d exceeds 2^24", pr->n_retailers);
+    if (pr->S0 < 0 || pr->x0_init < 0 || pr->S0 >= (1ll << 40) || pr->x0_init >= (1ll << 40))
+        return fail(PK_ERR_INVALID_ARG, "S0 and x0_init must be in [0, 2^40)");
+    if (!pr->s_ret || !pr->S_ret || !pr->cap || !pr->x_init ||
+        (pr->n_orders > 0 && (!pr->retailer || !pr->demand)))
+        return fail(PK_ERR_INVALID_ARG, "a problem array is NULL");
+    P->N = pr->n_retailers;
+    P->T = pr->n_orders;
+    P->retailer = pr->retailer;
+    P->demand = pr->demand;
+    P->s_ret = pr->s_ret;
+    P->S_ret = pr->S_ret;
+    P->cap = pr->cap;
+    P->x_init = pr->x_init;
+    P->s0 = pr->s0;
+    P->S0 = pr->S0;
+    P->x0_init = pr->x0_init;
+    return PK_OK;
+}
+
+struct OwmrWs {
+    int32_t *keys, *keys_alt, *vals, *vals_alt, *sd, *cnt, *err, *fx;
+    int64_t *V, *S, *rq, *fx0v, *x0;
+    unsigned long long *resets;
+    OwmrCtl *ctl;
+    void *rtmp, *stmp;
+};
+
+size_t carve_owmr(char *base, const OwmrDev &P, OwmrWs *w)
+{
+    Carver c{base};
+    const int64_t T = std::max<int64_t>(P.T, 1);
+    w->ctl = c.take<OwmrCtl>(1);
+    w->err = c.take<int32_t>(4);
+    w->x0 = c.take<int64_t>(1);
+    w->resets = c.take<unsigned long long>(1);
+    w->keys = c.take<int32_t>(T);
+    w->keys_alt = c.take<int32_t>(T);
+    w->vals = c.take<int32_t>(T);
+    w->vals_alt = c.take<int32_t>(T);
+    w->sd = c.take<int32_t>(T);
+    w->cnt = c.take<int32_t>((int64_t)P.N + 1);
+    w->fx = c.take<int32_t>(P.N);
+    w->V = c.take<int64_t>(T);
+    w->S = c.take<int64_t>(T);
+    w->rq = c.take<int64_t>(T + 1);
+    w->fx0v = c.take<int64_t>(P.N);
+    w->rtmp = c.take<char>((int64_t)owmr_radix_tmp(T));
+    w->stmp = c.take<char>((int64_t)std::max(scan_tmp_bytes(T), scan_tmp_bytes((int64_t)P.N + 1)));
+    return c.off + 256;
+}
 
 // ---------------------------------------------------------------- node capacity
 constexpr int DEFAULT_BLOCK_CAP = 96; // fastest of 32..255 on the 1e6-order capacity workload
@@ -920,6 +1083,119 @@ extern "C" {
 
 const char *pk_last_error(void) { return g_err; }
 
+pk_status pk_owmr_workspace_size(const pk_owmr_problem *problem, size_t *bytes)
+{
+    g_err[0] = 0;
+    OwmrDev P;
+    pk_status s = check_owmr(problem, &P);
+    if (s != PK_OK) return s;
+    if (!bytes) return fail(PK_ERR_INVALID_ARG, "bytes is NULL");
+    OwmrWs w;
+    *bytes = carve_owmr(nullptr, P, &w);
+    return PK_OK;
+}
+
+pk_status pk_owmr_serial_simulate(const pk_owmr_problem *problem, void *ws, size_t ws_bytes,
+                                  int32_t *q, int32_t *reset, int32_t *final_x,
+                                  int64_t *final_x0, int64_t *resets, void *stream)
+{
+    g_err[0] = 0;
+    OwmrDev P;
+    pk_status s = check_owmr(problem, &P);
+    if (s != PK_OK) return s;
+    if (P.T > 0 && (!q || !reset)) return fail(PK_ERR_INVALID_ARG, "q/reset is NULL");
+    OwmrWs w;
+    if (!ws || ws_bytes < carve_owmr(nullptr, P, &w))
+        return fail(PK_ERR_WORKSPACE, "workspace too small");
+    carve_owmr(align_ws(ws), P, &w);
+    hipStream_t st = (hipStream_t)stream;
+    int32_t *perm = nullptr;
+    HIP_TRY(owmr_launch_setup(P, w.keys, w.keys_alt, w.vals, w.vals_alt, w.rtmp, w.cnt, w.stmp,
+                              w.sd, w.err, &perm, st)); // (input checks; the sort is unused)
+    int32_t herr = 0;
+    HIP_TRY(hipMemcpyAsync(&herr, w.err, sizeof herr, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (herr) return fail(PK_ERR_INVALID_ARG, "an OWMR input is out of range");
+    if (P.N > 40 * 1024) return fail(PK_ERR_SHAPE, "the serial sweep keeps N <= 40960 stocks in LDS");
+    HIP_TRY(owmr_launch_serial(P, q, reset, w.x0, final_x ? final_x : w.fx, w.resets, st));
+    int64_t hx0 = 0;
+    unsigned long long hr = 0;
+    HIP_TRY(hipMemcpyAsync(&hx0, w.x0, sizeof hx0, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(&hr, w.resets, sizeof hr, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (final_x0) *final_x0 = hx0;
+    if (resets) *resets = (int64_t)hr;
+    return PK_OK;
+}
+
+pk_status pk_owmr_picard_simulate(const pk_owmr_problem *problem, int32_t max_passes,
+                                  const int32_t *init_q, const int32_t *init_reset, void *ws,
+                                  size_t ws_bytes, int32_t *q, int32_t *reset, int32_t *final_x,
+                                  int64_t *final_x0, int32_t *passes, int64_t *changed,
+                                  int64_t *caches, void *stream)
+{
+    g_err[0] = 0;
+    OwmrDev P;
+    pk_status s = check_owmr(problem, &P);
+    if (s != PK_OK) return s;
+    if (P.T > 0 && (!q || !reset)) return fail(PK_ERR_INVALID_ARG, "q/reset is NULL");
+    if (!passes) return fail(PK_ERR_INVALID_ARG, "passes is NULL");
+    if (max_passes < 0) return fail(PK_ERR_INVALID_ARG, "max_passes < 0");
+    if ((init_q == nullptr) != (init_reset == nullptr))
+        return fail(PK_ERR_INVALID_ARG, "give both init_q and init_reset, or neither");
+    const int32_t mp = max_passes > 0 ? max_passes : (int32_t)std::min<int64_t>(P.T + 1, 0x7ffffff0);
+    if ((changed || caches) && max_passes <= 0)
+        return fail(PK_ERR_INVALID_ARG, "recording passes needs max_passes > 0");
+    OwmrWs w;
+    if (!ws || ws_bytes < carve_owmr(nullptr, P, &w))
+        return fail(PK_ERR_WORKSPACE, "workspace too small");
+    carve_owmr(align_ws(ws), P, &w);
+    hipStream_t st = (hipStream_t)stream;
+    int32_t *perm = nullptr;
+    HIP_TRY(owmr_launch_setup(P, w.keys, w.keys_alt, w.vals, w.vals_alt, w.rtmp, w.cnt, w.stmp,
+                              w.sd, w.err, &perm, st));
+    HIP_TRY(owmr_launch_init(P, init_q, init_reset, w.V, w.ctl, mp, st));
+    int32_t herr = 0;
+    HIP_TRY(hipMemcpyAsync(&herr, w.err, sizeof herr, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (herr) return fail(PK_ERR_INVALID_ARG, "an OWMR input is out of range");
+    // passes go out eight at a time (every kernel returns at once after convergence),
+    // one at a time when each pass's cache is recorded
+    const int U = caches ? 1 : 8;
+    OwmrCtl hc = {};
+    int launched = 0;
+    while (launched < mp) {
+        const int u = std::min(U, mp - launched);
+        for (int i = 0; i < u; ++i)
+            HIP_TRY(owmr_launch_pass(P, w.ctl, perm, w.sd, w.cnt, w.V, w.S, w.rq, w.stmp, w.fx0v,
+                                     final_x ? final_x : w.fx,
+                                     caches ? caches + (int64_t)(launched + i) * P.T : nullptr, st));
+        launched += u;
+        HIP_TRY(hipMemcpyAsync(&hc, w.ctl, sizeof hc, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (changed)
+            for (int k = launched - u; k < launched && k < (hc.done ? hc.passes_done : launched); ++k)
+                changed[k] = (int64_t)hc.changed_log[k & 7];
+        if (hc.done) break;
+    }
+    *passes = hc.done ? hc.passes_done : launched;
+    if (P.T > 0) HIP_TRY(owmr_launch_unpack(P, w.V, q, reset, st));
+    if (final_x0) {
+        int64_t x0 = P.x0_init;
+        if (P.T > 0) { // the last order's retailer sees the exact central stock after it
+            int32_t nl = 0;
+            HIP_TRY(hipMemcpyAsync(&nl, P.retailer + P.T - 1, sizeof nl, hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            HIP_TRY(hipMemcpyAsync(&x0, w.fx0v + nl, sizeof x0, hipMemcpyDeviceToHost, st));
+        }
+        HIP_TRY(hipStreamSynchronize(st));
+        *final_x0 = x0;
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    if (hc.done != 1) return fail(PK_ERR_NOT_CONVERGED, "not converged after %d passes", *passes);
+    return PK_OK;
+}
+
 const char *pk_version(void) { return "libpicard 0.1 (gfx950)"; }
 
 pk_status pk_workspace_size(const pk_problem *problem, const pk_policy *policy,
@@ -990,14 +1266,21 @@ pk_status pk_picard_simulate(const pk_problem *problem, const pk_policy *policy,
     if (opts) o = *opts;
     if (o.block_len < 0 || o.max_passes < 0 || o.graph_unroll < 0)
         return fail(PK_ERR_INVALID_ARG, "negative option");
+    if (o.walk_waves != 0 && o.walk_waves != 4 && o.walk_waves != 8)
+        return fail(PK_ERR_INVALID_ARG, "walk_waves must be 0, 4 or 8 (got %d)", o.walk_waves);
     if (o.partition) o.block_len = 1; // sizes the plan for one run per order, the most
                                       // a partition makes
     int B = o.block_len;
-    if (B == 0 && policy->kind == PK_POLICY_MLP) B = DEFAULT_BLOCK_MLP;
+    Tuned t;
+    const bool tuned = tune_lookup(d, policy, &t);
+    if (B == 0 && policy->kind == PK_POLICY_MLP) // learned: the recorded choice, else the
+        B = tuned ? t.block_len : DEFAULT_BLOCK_MLP; // default (tuning takes minutes)
     if (B == 0) {
-        s = autotune_block(problem, d, policy, ws, ws_bytes, actions, (hipStream_t)stream, &B);
+        s = autotune_block(problem, d, policy, ws, ws_bytes, actions, (hipStream_t)stream, &t);
         if (s != PK_OK) return s;
+        B = t.block_len;
     }
+    if (o.walk_waves == 0) o.walk_waves = tuned && t.block_len == B ? t.waves : 4;
     return picard_run(problem, d, policy, o, B, ws, ws_bytes, actions, shipped, final_inv, stats,
                       (hipStream_t)stream);
 }
@@ -1018,6 +1301,8 @@ pk_status pk_picard_simulate_noalloc(const pk_problem *problem, const pk_policy 
     if (opts) o = *opts;
     if (o.block_len < 0 || o.max_passes < 0 || o.graph_unroll < 0)
         return fail(PK_ERR_INVALID_ARG, "negative option");
+    if (o.walk_waves != 0 && o.walk_waves != 4 && o.walk_waves != 8)
+        return fail(PK_ERR_INVALID_ARG, "walk_waves must be 0, 4 or 8 (got %d)", o.walk_waves);
     if (stats && stats->timing)
         return fail(PK_ERR_UNSUPPORTED, "timing needs HIP events, which this entry point "
                                         "does not create");
@@ -1056,8 +1341,8 @@ pk_status pk_policy_grad(const pk_problem *problem, const pk_policy *policy,
     Carver c{align_ws(ws)};
     Plan L;
     int64_t *to;
-    void *scratch;
-    carve_plan(c, d, policy, GRAD_BLOCK, &L, &to, &scratch);
+    void *setup_scr;
+    carve_plan(c, d, policy, GRAD_BLOCK, &L, &to, &setup_scr);
     float *logp_sorted = c.take<float>(d.total);
     double *part = c.take<double>((int64_t)grad_part_bytes(GRAD_MAX_WG, d.R, policy->n_hidden_layers) / 8);
     double *obj_dev = c.take<double>(1);
@@ -1069,7 +1354,7 @@ pk_status pk_policy_grad(const pk_problem *problem, const pk_policy *policy,
     const int n_wg = std::min(GRAD_MAX_WG, std::max(1, num_cus())); // one workgroup per CU
     if (d.total > 0) {
         // states of the fixed actions: the actions are the cache, its consumption scanned
-        HIP_TRY(setup_plan(P, L, actions, validate, true, (int32_t)sz.n_seg_max, scratch, st));
+        HIP_TRY(setup_plan(P, L, actions, validate, true, (int32_t)sz.n_seg_max, setup_scr, st));
         HIP_TRY(setup_costT(P, policy->params, L.costT, st));
         HIP_TRY(launch_consume(P, L, sz.n_split_max, st));
         HIP_TRY(launch_scan_entry(P, L, (int)sz.n_seg_max, false, st));
@@ -1130,19 +1415,15 @@ pk_status pk_autotune(const pk_problem *problem, const pk_policy *policy, void *
     if (s != PK_OK) return s;
     if ((s = check_policy(policy)) != PK_OK) return s;
     if (!best_block_len) return fail(PK_ERR_INVALID_ARG, "best_block_len is NULL");
-    if (policy->kind != PK_POLICY_GREEDY) {
-        *best_block_len = DEFAULT_BLOCK_MLP;
-        return PK_OK;
-    }
     const size_t act_bytes = ((size_t)std::max<int64_t>(d.total, 1) * 4 + 255) & ~(size_t)255;
     if (!ws || ws_bytes < act_bytes + 512) return fail(PK_ERR_WORKSPACE, "workspace too small");
     // trial actions live at the end of the workspace
     char *tail = (char *)ws + ((ws_bytes - act_bytes) & ~(size_t)255);
-    int B = 0;
+    Tuned t;
     s = autotune_block(problem, d, policy, ws, (size_t)(tail - (char *)ws), (int32_t *)tail,
-                       (hipStream_t)stream, &B);
+                       (hipStream_t)stream, &t);
     if (s != PK_OK) return s;
-    *best_block_len = B;
+    *best_block_len = t.block_len;
     return PK_OK;
 }
 

@@ -39,28 +39,26 @@ __device__ __forceinline__ const float *region_table(const float *costT, const P
 // each order's cost row and region embedding sit in a double buffer that is filled from
 // global memory while the previous order is scored.  CHUNK orders per stage.
 constexpr int CHUNK = 64;
-constexpr int MAX_CPT = PK_MAX_WAREHOUSES / 256; // cost values per thread (256 threads)
-
-// Loads the cost row of region r (N values, trajectory b) and its embedding into registers.
-__device__ __forceinline__ void load_row(const float *costT, const float *E, int b, int R, int N,
-                                         int r, float cn[MAX_CPT], float &en)
+// Loads the cost row of region r (N values, trajectory b) into registers (CPT values per
+// thread of a THREADS-thread workgroup).
+template <int THREADS, int CPT = PK_MAX_WAREHOUSES / THREADS>
+__device__ __forceinline__ void load_row(const float *costT, int b, int R, int N, int r,
+                                         float cn[CPT])
 {
 #pragma unroll
-    for (int k = 0; k < MAX_CPT; ++k) {
-        const int w = k * 256 + (int)threadIdx.x;
+    for (int k = 0; k < CPT; ++k) {
+        const int w = k * THREADS + (int)threadIdx.x;
         cn[k] = w < N ? costT[((int64_t)b * R + r) * N + w] : 0.f;
     }
-    en = threadIdx.x < 16 ? E[(int64_t)r * 16 + threadIdx.x] : 0.f;
 }
-__device__ __forceinline__ void store_row(float *cbuf, float *ebuf, int N, const float cn[MAX_CPT],
-                                          float en)
+template <int THREADS, int CPT = PK_MAX_WAREHOUSES / THREADS>
+__device__ __forceinline__ void store_row(float *cbuf, int N, const float cn[CPT])
 {
 #pragma unroll
-    for (int k = 0; k < MAX_CPT; ++k) {
-        const int w = k * 256 + (int)threadIdx.x;
+    for (int k = 0; k < CPT; ++k) {
+        const int w = k * THREADS + (int)threadIdx.x;
         if (w < N) cbuf[w] = cn[k];
     }
-    if (threadIdx.x < 16) ebuf[threadIdx.x] = en;
 }
 
 // One workgroup walks one run (a process's orders of one SKU) from its entry state,
@@ -70,7 +68,11 @@ __device__ __forceinline__ void store_row(float *cbuf, float *ebuf, int N, const
 // given partition the workgroup goes on to its process's later runs of the SKU (its
 // chain), entering each at max(0, x0 - E_j - D), D the process's own fresh-minus-cached
 // consumption on its earlier runs, kept in LDS.
-__global__ __launch_bounds__(256, 4) void k_walk_mlp(Prob P, Plan L, const float *params, int layers,
+// WPB waves per workgroup (4 or 8): the tiles of an order are shared by more waves with 8
+// (shorter orders, for wide N), at half the resident workgroups per CU (four waves per SIMD
+// either way).
+template <int WPB>
+__global__ __launch_bounds__(WPB * 64, 16 / WPB) void k_walk_mlp(Prob P, Plan L, const float *params, int layers,
                                                   const float *costT, int32_t *final_inv,
                                                   int has_init)
 {
@@ -241,18 +243,19 @@ __global__ __launch_bounds__(256, 4) void k_walk_mlp(Prob P, Plan L, const float
 // row is in LDS (requested during the previous order, or kept from it when both orders
 // have the same SKU), its warehouses with stock are listed and scored by the same scorer,
 // and the chosen warehouse's stock is written back.
-__global__ __launch_bounds__(256) void k_serial_mlp(Prob P, const float *params, int layers,
-                                                   const float *costT, int32_t *state,
-                                                   int32_t *actions, int32_t *shipped)
+template <int THREADS>
+__global__ __launch_bounds__(THREADS) void k_serial_mlp(Prob P, const float *params, int layers,
+                                                       const float *costT, int32_t *state,
+                                                       int32_t *actions, int32_t *shipped)
 {
+    constexpr int CPT = PK_MAX_WAREHOUSES / THREADS; // cost and stock values per thread
     extern __shared__ __align__(16) unsigned char smem[];
     const int N = P.N, R = P.R;
     float *W2s = (float *)smem;
     float *Vs = (float *)(smem + w2_lds_bytes());
     int4 *ordq = (int4 *)(smem + w2_lds_bytes() + vec_lds_bytes()); // [2][CHUNK] (k, r, q, -)
     float *cbuf = (float *)(ordq + 2 * CHUNK); // [2][N]
-    float *ebuf = cbuf + 2 * N;                // [2][16]
-    int32_t *x = (int32_t *)(ebuf + 32);
+    int32_t *x = (int32_t *)(cbuf + 2 * N);
     float *zbuf = (float *)(x + N);
     int32_t *sl = (int32_t *)(zbuf + N);
     int32_t *pos = sl + N;
@@ -280,9 +283,9 @@ __global__ __launch_bounds__(256) void k_serial_mlp(Prob P, const float *params,
     int4 nq = make_int4(0, 0, 0, 0);
     if (tid < CHUNK && t0 + CHUNK + tid < t1) nq = order_at(t0 + CHUNK + tid);
     __syncthreads();
-    float cn[MAX_CPT], en;
-    load_row(costT, params, b, R, N, ordq[0].y, cn, en);
-    store_row(cbuf, ebuf, N, cn, en);
+    float cn[CPT];
+    load_row<THREADS>(costT, b, R, N, ordq[0].y, cn);
+    store_row<THREADS>(cbuf, N, cn);
     for (int w = tid; w < N; w += blockDim.x) x[w] = xs[(int64_t)ordq[0].x * N + w];
     __syncthreads();
     for (int64_t tt = t0; tt < t1; ++tt) {
@@ -295,8 +298,8 @@ __global__ __launch_bounds__(256) void k_serial_mlp(Prob P, const float *params,
             // this order's rows were not prefetched: its cost row, and its stock row as the
             // previous order left it (written back before the last barrier)
             const int4 o0 = ordq[slot * CHUNK];
-            load_row(costT, params, b, R, N, o0.y, cn, en);
-            store_row(cbuf + buf * N, ebuf + buf * 16, N, cn, en);
+            load_row<THREADS>(costT, b, R, N, o0.y, cn);
+            store_row<THREADS>(cbuf + buf * N, N, cn);
             for (int w = tid; w < N; w += blockDim.x) x[w] = xs[(int64_t)o0.x * N + w];
             __syncthreads();
         }
@@ -306,15 +309,15 @@ __global__ __launch_bounds__(256) void k_serial_mlp(Prob P, const float *params,
         // the next order (same chunk): its row and, for another SKU, its stock row
         const bool pf = i % CHUNK != CHUNK - 1 && tt + 1 < t1;
         int kn = k;
-        int32_t xn[MAX_CPT];
+        int32_t xn[CPT];
         if (pf) {
             const int4 on = ordq[slot * CHUNK + (int)(i % CHUNK) + 1];
             kn = on.x;
-            load_row(costT, params, b, R, N, on.y, cn, en);
+            load_row<THREADS>(costT, b, R, N, on.y, cn);
             if (kn != k) {
 #pragma unroll
-                for (int c = 0; c < MAX_CPT; ++c) {
-                    const int w = c * 256 + tid;
+                for (int c = 0; c < CPT; ++c) {
+                    const int w = c * THREADS + tid;
                     xn[c] = w < N ? xs[(int64_t)kn * N + w] : 0;
                 }
             }
@@ -345,11 +348,11 @@ __global__ __launch_bounds__(256) void k_serial_mlp(Prob P, const float *params,
         // the next order's rows into LDS: its stock row is kept when it is the same SKU
         // (updated above); when the next order opens a chunk both are read there
         if (pf) {
-            store_row(cbuf + (buf ^ 1) * N, ebuf + (buf ^ 1) * 16, N, cn, en);
+            store_row<THREADS>(cbuf + (buf ^ 1) * N, N, cn);
             if (kn != k) {
 #pragma unroll
-                for (int c = 0; c < MAX_CPT; ++c) {
-                    const int w = c * 256 + tid;
+                for (int c = 0; c < CPT; ++c) {
+                    const int w = c * THREADS + tid;
                     if (w < N) x[w] = xn[c];
                 }
             }
@@ -442,22 +445,32 @@ hipError_t setup_costT(const Prob &P, const float *params, float *costT, hipStre
 size_t walk_mlp_lds(int N) { return w2_lds_bytes() + vec_lds_bytes() + (size_t)N * 24 + 64; }
 
 hipError_t launch_walk_mlp(const Prob &P, const Plan &L, const float *params, int layers,
-                           const float *costT, int32_t *final_inv, bool has_init, int grid,
-                           hipStream_t st)
+                           const float *costT, int32_t *final_inv, bool has_init, int n_cus,
+                           int waves, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_walk_mlp, dim3(grid), dim3(256), walk_mlp_lds(P.N), st, P, L, params,
-                       layers, costT, final_inv, has_init ? 1 : 0);
+    // persistent: as many workgroups as stay resident (four waves per SIMD)
+    if (waves == 8)
+        hipLaunchKernelGGL(k_walk_mlp<8>, dim3(n_cus * 2), dim3(512), walk_mlp_lds(P.N), st, P, L,
+                           params, layers, costT, final_inv, has_init ? 1 : 0);
+    else
+        hipLaunchKernelGGL(k_walk_mlp<4>, dim3(n_cus * 4), dim3(256), walk_mlp_lds(P.N), st, P, L,
+                           params, layers, costT, final_inv, has_init ? 1 : 0);
     return hipGetLastError();
 }
 
 hipError_t launch_serial_mlp(const Prob &P, const float *params, int layers, const float *costT,
                              int32_t *state, int32_t *actions, int32_t *shipped, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_serial_mlp, dim3(P.n_traj), dim3(256),
-                       w2_lds_bytes() + vec_lds_bytes() + (size_t)2 * CHUNK * 16 + 128 +
-                           (size_t)P.N * 24 + 64,
-                       st, P,
-                       params, layers, costT, state, actions, shipped);
+    // a trajectory's orders go one at a time, so its workgroup should score each order's
+    // tiles with as many waves as the tiles keep busy: 16 waves for wide orders, else 4
+    const size_t lds = w2_lds_bytes() + vec_lds_bytes() + (size_t)2 * CHUNK * 16 +
+                       (size_t)P.N * 24 + 64;
+    if (P.N > 256)
+        hipLaunchKernelGGL(k_serial_mlp<1024>, dim3(P.n_traj), dim3(1024), lds, st, P, params,
+                           layers, costT, state, actions, shipped);
+    else
+        hipLaunchKernelGGL(k_serial_mlp<256>, dim3(P.n_traj), dim3(256), lds, st, P, params,
+                           layers, costT, state, actions, shipped);
     return hipGetLastError();
 }
 

@@ -196,6 +196,36 @@ hipError_t radix_sort_pairs(int32_t *keys, int32_t *vals, int32_t *keys_alt,
                             hipStream_t st, bool *result_in_alt);
 size_t radix_tmp_bytes(int64_t n);
 
+// ---------------------------------------------------------------- OWMR inventory control
+// (owmr.hip: one central warehouse and N retailers, one process per retailer)
+struct OwmrDev {
+    int32_t N;
+    int64_t T;
+    const int32_t *retailer, *demand, *s_ret, *S_ret, *cap, *x_init;
+    int64_t s0, S0, x0_init;
+};
+
+struct OwmrCtl {
+    int32_t pass, done, passes_done, max_passes;
+    int32_t error;
+    unsigned long long changed;          // steps whose action changed in the current pass
+    unsigned long long changed_log[8];   // the last eight passes' counts, by pass % 8
+};
+
+size_t owmr_radix_tmp(int64_t T);
+hipError_t owmr_launch_setup(const OwmrDev &P, int32_t *keys, int32_t *keys_alt, int32_t *vals,
+                             int32_t *vals_alt, void *rtmp, int32_t *cnt, void *stmp,
+                             int32_t *sd, int32_t *err, int32_t **perm, hipStream_t st);
+hipError_t owmr_launch_init(const OwmrDev &P, const int32_t *iq, const int32_t *ir, int64_t *V,
+                            OwmrCtl *ctl, int32_t max_passes, hipStream_t st);
+hipError_t owmr_launch_pass(const OwmrDev &P, OwmrCtl *ctl, const int32_t *perm, const int32_t *sd,
+                            const int32_t *seg, int64_t *V, int64_t *S, int64_t *rq, void *stmp,
+                            int64_t *fx0v, int32_t *fx, int64_t *caches, hipStream_t st);
+hipError_t owmr_launch_unpack(const OwmrDev &P, const int64_t *V, int32_t *q, int32_t *r,
+                              hipStream_t st);
+hipError_t owmr_launch_serial(const OwmrDev &P, int32_t *q, int32_t *r, int64_t *fx0, int32_t *fx,
+                              unsigned long long *resets, hipStream_t st);
+
 // ---------------------------------------------------------------- node capacity
 // (capacity.hip: Picard with the FO state (x, c) of Section 3, time-block processes)
 constexpr int CAP_NPAD = 128; // warehouses per row: two per lane

@@ -36,8 +36,8 @@ def test_struct_layouts():
     from paper_2406_01939_amd import api
     assert C.sizeof(api.pk_problem) == 4 * 4 + 6 * 8 + 8
     assert C.sizeof(api.pk_policy) == 4 * 4 + 8
-    assert C.sizeof(api.pk_picard_opts) == 4 * 4 + 8 + 8 + 8
-    assert C.sizeof(api.pk_stats) == 8 + 4 + 4 + 4 * 8 + 8 + 8 + 8 + 8 + 8 + 8 + 8 + 8
+    assert C.sizeof(api.pk_picard_opts) == 4 * 4 + 8 + 8 + 8 + 8
+    assert C.sizeof(api.pk_stats) == 8 + 4 + 4 + 4 * 8 + 8 + 8 + 8 + 8 + 8 + 8 + 8 + 8 + 8
 
 
 def test_host_validation_without_gpu():

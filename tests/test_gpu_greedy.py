@@ -157,6 +157,51 @@ def test_serial_sweep_matches_oracle(api, oracle):
     _check(out, inst, want_a, want_s, want_f)
 
 
+@pytest.mark.parametrize("N,K,T,qmax", [(1, 1, 300, 3), (64, 1, 1000, 2), (65, 2, 777, 3),
+                                         (128, 3, 1500, 1), (100, 7, 2049, 3), (129, 2, 500, 2)])
+def test_serial_sweep_prefetch_window(api, oracle, N, K, T, qmax):
+    """The serial sweep loads an order's stock row several orders ahead; with one to seven
+    SKUs almost every order shares its SKU with one of the orders decided since, so its row
+    must come from the most recent of them, not from memory.  Warehouse counts on both sides
+    of one and two per lane (64, 65, 128, 129), horizons not a multiple of 16 or 64, and
+    enough stock that warehouses run out mid-way."""
+    demand = 0.75 * T * (qmax + 1) / 2  # per trajectory, about
+    inst = random_tiny(500 + N + K, N=N, K=K, R=5, T=T, qmax=qmax,
+                       inv_max=max(1, int(demand / (K * N))), n_traj=3)  # stock ~ half of it
+    _say(f"case serial prefetch window N={N} K={K} T={T} total={inst.total_orders}")
+    want_a, want_s, want_f, _ = _oracle_batch(oracle, inst)
+    assert (want_a == -1).any() and (want_a >= 0).any()
+    out = api.pk_serial_simulate(api.DeviceProblem.from_instance(inst), "greedy")
+    _check(out, inst, want_a, want_s, want_f)
+
+
+def test_serial_sweep_full_workloads(api, oracle):
+    """The serial sweep on the 1e6-order workload and on the 256-trajectory batch
+    (1.2e8 orders, quantities 1..3), bit-exact against the oracle's serial rollouts (run
+    in threads, one trajectory each)."""
+    from concurrent.futures import ThreadPoolExecutor
+    for name in ("greedy_n100_k1e5_t1e6", "greedy_batch256_n50_k2e4"):
+        inst = make_instance(name)
+        _say(f"case serial sweep full {name}: {inst.total_orders} orders")
+        prob = api.DeviceProblem.from_instance(inst)
+        out = api.pk_serial_simulate(prob, "greedy")
+        acts = out["actions"].cpu().numpy()
+        ship = out["shipped"].cpu().numpy()
+        fin = out["final_inv"].cpu().numpy()
+        del out, prob
+
+        def one(b):
+            lo, hi = int(inst.traj_offsets[b]), int(inst.traj_offsets[b + 1])
+            r = oracle.serial(inst, b)
+            return (np.array_equal(r["actions"], acts[lo:hi]) and
+                    np.array_equal(r["shipped"], ship[lo:hi]) and
+                    np.array_equal(r["final_inv"], fin[b]))
+
+        with ThreadPoolExecutor(max_workers=16) as ex:
+            ok = list(ex.map(one, range(inst.n_traj)))
+        assert all(ok), [b for b, v in enumerate(ok) if not v][:10]
+
+
 def test_edge_cases(api, oracle):
     # a batch with empty trajectories in it
     inst = random_tiny(21, N=3, K=2, R=2, T=20, n_traj=3)
