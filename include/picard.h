@@ -129,6 +129,12 @@ typedef struct pk_picard_opts {
     int32_t walk_waves;   /* MLP: waves per workgroup of the run walk, 4 or 8; 0 = the
                              autotuned choice for this problem when block_len is the tuned
                              one, else 4.  Same results either way. */
+    int32_t lane_max;     /* greedy, N <= 128, block partitions: in the first pass, runs of
+                             at most lane_max orders are walked one per GPU lane (64 runs
+                             of similar length per wavefront), longer ones a wavefront per
+                             run.  0 = chosen from the workload (the orders per resident
+                             lane, up to 510; none below 64); -1 = none; otherwise at most
+                             510.  Same results either way. */
 } pk_picard_opts;
 
 /* Statistics of one pk_picard_simulate call (all optional). */

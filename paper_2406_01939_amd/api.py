@@ -57,7 +57,7 @@ class pk_picard_opts(C.Structure):
     _fields_ = [("block_len", C.c_int32), ("max_passes", C.c_int32),
                 ("use_frontier", C.c_int32), ("graph_unroll", C.c_int32),
                 ("init_cache", C.c_void_p), ("validate", C.c_int32), ("partition", C.c_void_p),
-                ("walk_waves", C.c_int32)]
+                ("walk_waves", C.c_int32), ("lane_max", C.c_int32)]
 
 
 class pk_stats(C.Structure):
@@ -231,11 +231,11 @@ def pk_picard_simulate(prob: DeviceProblem, policy: str = "greedy", block_len: i
                        partition: Optional[torch.Tensor] = None,
                        want_shipped=True, want_final=True, timing=False, stream=None,
                        raise_not_converged=True, out: Optional[dict] = None,
-                       walk_waves: int = 0) -> dict:
+                       walk_waves: int = 0, lane_max: int = 0) -> dict:
     dev = prob.sku.device
     p, po = prob.c_problem(), prob.c_policy(policy)
     o = pk_picard_opts(block_len, max_passes, int(use_frontier), graph_unroll,
-                       _ptr(init_cache), int(validate), _ptr(partition), walk_waves)
+                       _ptr(init_cache), int(validate), _ptr(partition), walk_waves, lane_max)
     n = C.c_size_t(0)
     _check(lib().pk_workspace_size(C.byref(p), C.byref(po), C.byref(o), C.byref(n)))
     ws = workspace(int(n.value), dev)

@@ -21,9 +21,10 @@ namespace pk {
 hipError_t setup_ctl(Plan &L, int n_traj, int max_passes, hipStream_t st);
 hipError_t setup_plan(const Prob &P, Plan &L, const int32_t *init_cache, int validate,
                       bool want_t, int32_t n_seg_max, void *scratch, hipStream_t st);
-size_t setup_scratch_bytes(int64_t n);
-hipError_t setup_pos(const Prob &P, void *pos, hipStream_t st);
+size_t setup_scratch_bytes(int64_t n, int n_traj);
+hipError_t setup_pos(const Prob &P, void *pos, uint8_t *pref, hipStream_t st);
 size_t pos_bytes(int N, int R, int n_traj);
+size_t pref_bytes(int N, int R, int n_traj);
 // pass.hip
 hipError_t launch_scan_entry(const Prob &P, const Plan &L, int n_seg_max, bool skip_first,
                              hipStream_t st);
@@ -250,7 +251,14 @@ void carve_plan(Carver &c, const Dims &d, const pk_policy *po, int B, Plan *L,
         p.costT = c.take<float>((int64_t)costT_bytes(d.N, d.R, d.n_traj) / 4);
     else
         p.pos = c.take<char>((int64_t)pos_bytes(d.N, d.R, d.n_traj));
-    *setup_scratch = c.take<char>((int64_t)setup_scratch_bytes(d.total));
+    if (po->kind != PK_POLICY_MLP && d.N <= PREF_MAX_N) { // the first pass's lane walk
+        p.pref = c.take<uint8_t>((int64_t)pref_bytes(d.N, d.R, d.n_traj));
+        p.wlist = c.take<int32_t>(s.n_sr_max);
+        p.s_rq = c.take<int32_t>(d.total);
+        p.rq_rb = region_bits(d.R);
+        p.pref_lds = pref_in_lds(d.N, d.R) ? 1 : 0;
+    }
+    *setup_scratch = c.take<char>((int64_t)setup_scratch_bytes(d.total, d.n_traj));
     if (L) *L = p;
 }
 
@@ -502,6 +510,13 @@ pk_status picard_run(const pk_problem *problem, const Dims &d, const pk_policy *
     carve_plan(c, d, policy, B, &L, &to, &setup_scr);
     L.no_frontier = o.use_frontier ? 0 : 1;
     L.worker = o.partition;
+    L.lane_max = o.lane_max > 0 ? std::min(o.lane_max, LANE_MAX_LEN)
+                                : (o.lane_max < 0 ? 0 : lane_max_for(d.total, d.N, d.R, num_cus()));
+    if (L.worker || L.lane_max == 0) { // given partitions walk chains; or no lane walk
+        L.wlist = nullptr;
+        L.s_rq = nullptr;
+    }
+    const bool lanes = L.wlist != nullptr;
     const Sizes sz = plan_sizes(d, B);
     HIP_TRY(hipMemcpyAsync(to, problem->traj_offsets, (d.n_traj + 1) * sizeof(int64_t),
                            hipMemcpyHostToDevice, st));
@@ -518,7 +533,7 @@ pk_status picard_run(const pk_problem *problem, const Dims &d, const pk_policy *
             if (mlp)
                 HIP_TRY(setup_costT(P, policy->params, L.costT, s2));
             else
-                HIP_TRY(setup_pos(P, L.pos, s2));
+                HIP_TRY(setup_pos(P, L.pos, L.pref, s2));
             if (has_init) HIP_TRY(launch_consume(P, L, sz.n_split_max, s2));
         }
         if (final_inv)
@@ -548,7 +563,9 @@ pk_status picard_run(const pk_problem *problem, const Dims &d, const pk_policy *
     // return at once after convergence, so U passes are enqueued per host check.
     // Events around the walk: none (ge == nullptr, !with_events), created here, or the
     // captured graph's pair ge[0], ge[1] recorded as graph nodes.
-    auto enqueue_pass = [&](hipStream_t s2, bool with_events, hipEvent_t *ge) -> pk_status {
+    // pass1: this is the call's first pass (the greedy lane walk runs before the walk)
+    auto enqueue_pass = [&](hipStream_t s2, bool with_events, hipEvent_t *ge,
+                            bool pass1) -> pk_status {
         hipEvent_t es = nullptr, e0 = nullptr, e1 = nullptr;
         if (ge) {
             const pk_status r = record_in_capture(s2, ge[0]);
@@ -571,8 +588,12 @@ pk_status picard_run(const pk_problem *problem, const Dims &d, const pk_policy *
                                     final_inv, has_init, num_cus(), waves, s2));
         else if (L.worker)
             HIP_TRY(launch_walk_chain_greedy(P, L, final_inv, has_init, grid, s2));
-        else
+        else {
+            if (lanes && pass1)
+                HIP_TRY(launch_walk_greedy_lane(P, L, final_inv, has_init,
+                                                std::min<int64_t>(d.total, sz.n_sr_max), s2));
             HIP_TRY(launch_walk_greedy(P, L, L.pos, final_inv, has_init, grid, s2));
+        }
         if (ge) {
             const pk_status r = record_in_capture(s2, ge[2]);
             if (r != PK_OK) return r;
@@ -601,7 +622,8 @@ pk_status picard_run(const pk_problem *problem, const Dims &d, const pk_policy *
                     if (e != PK_OK) return e;
                 }
                 for (int i = 0; i < U; ++i) {
-                    pk_status e = enqueue_pass(cs, false, timing ? &ge.evs[3 * i] : nullptr);
+                    pk_status e = enqueue_pass(cs, false, timing ? &ge.evs[3 * i] : nullptr,
+                                               with_setup && i == 0);
                     if (e != PK_OK) return e;
                 }
                 return PK_OK;
@@ -621,7 +643,7 @@ pk_status picard_run(const pk_problem *problem, const Dims &d, const pk_policy *
             HIP_TRY(hipGraphLaunch(ge->exec, st));
         } else {
             for (int i = 0; i < u; ++i) {
-                pk_status e = enqueue_pass(st, timing, nullptr);
+                pk_status e = enqueue_pass(st, timing, nullptr, launched == 0 && i == 0);
                 if (e != PK_OK) return e;
             }
         }
@@ -1243,7 +1265,7 @@ pk_status pk_serial_simulate(const pk_problem *problem, const pk_policy *policy,
         HIP_TRY(launch_serial_mlp(P, policy->params, policy->n_hidden_layers, (const float *)pos,
                                   state, actions, shipped, st));
     } else {
-        HIP_TRY(setup_pos(P, pos, st));
+        HIP_TRY(setup_pos(P, pos, nullptr, st));
         HIP_TRY(launch_serial_greedy(P, pos, state, actions, shipped, st));
     }
     HIP_TRY(hipStreamSynchronize(st));

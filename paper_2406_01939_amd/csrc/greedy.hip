@@ -234,9 +234,10 @@ __global__ __launch_bounds__(64) void k_serial_greedy_pipe(Prob P, const uint16_
 
 // key[b][r][w] = (position of w in region r's increasing (cost[b][w][r], w) order) << S
 // | w.  One workgroup per row (b, r): the row's costs are staged in LDS, then one thread
-// per w counts the warehouses that precede it.  Row padding is all-ones.
+// per w counts the warehouses that precede it.  Row padding is all-ones.  With pref (16-bit
+// keys, N <= 128) the row's preference list too: pref[b][r][position] = w.
 template <typename KeyT>
-__global__ __launch_bounds__(256) void k_keys(Prob P, KeyT *keys)
+__global__ __launch_bounds__(256) void k_keys(Prob P, KeyT *keys, uint8_t *pref)
 {
     __shared__ int32_t cs[PK_MAX_WAREHOUSES];
     const int N = P.N, R = P.R;
@@ -250,9 +251,11 @@ __global__ __launch_bounds__(256) void k_keys(Prob P, KeyT *keys)
         for (int v = threadIdx.x; v < N; v += blockDim.x) cs[v] = c[(int64_t)v * R + r];
         __syncthreads();
         KeyT *row = keys + b * tab_stride<KeyT>(N, R) + (int64_t)r * npad;
+        uint8_t *prow = pref ? pref + br * pref_npad(N) : nullptr; // pref_npad(N) == npad here
         for (int w = threadIdx.x; w < npad; w += blockDim.x) {
             if (w >= N) {
                 row[w] = (KeyT)~(KeyT)0;
+                if (prow) prow[w] = 127; // positions past N
                 continue;
             }
             const int32_t cw = cs[w];
@@ -262,6 +265,7 @@ __global__ __launch_bounds__(256) void k_keys(Prob P, KeyT *keys)
                 q += (cv < cw) || (cv == cw && v < w);
             }
             row[w] = (KeyT)((q << key_shift<KeyT>()) | (uint32_t)w);
+            if (prow) prow[q] = (uint8_t)w;
         }
     }
 }
@@ -276,17 +280,22 @@ size_t pos_bytes(int N, int R, int n_traj)
                      : (size_t)n_traj * tab_stride<uint32_t>(N, R) * 4;
 }
 
-hipError_t setup_pos(const Prob &P, void *keys, hipStream_t st)
+size_t pref_bytes(int N, int R, int n_traj)
+{
+    return N <= PREF_MAX_N ? (size_t)n_traj * R * pref_npad(N) : 0;
+}
+
+hipError_t setup_pos(const Prob &P, void *keys, uint8_t *pref, hipStream_t st)
 {
     int64_t g = (int64_t)P.n_traj * P.R; // one workgroup per row
     g = g < 1 ? 1 : (g > 8192 ? 8192 : g);
     const int threads = P.N <= 128 ? 128 : 256;
     if (keys16(P.N))
         hipLaunchKernelGGL(k_keys<uint16_t>, dim3((unsigned)g), dim3(threads), 0, st, P,
-                           (uint16_t *)keys);
+                           (uint16_t *)keys, P.N <= PREF_MAX_N ? pref : nullptr);
     else
         hipLaunchKernelGGL(k_keys<uint32_t>, dim3((unsigned)g), dim3(threads), 0, st, P,
-                           (uint32_t *)keys);
+                           (uint32_t *)keys, (uint8_t *)nullptr);
     return hipGetLastError();
 }
 

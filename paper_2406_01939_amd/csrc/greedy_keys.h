@@ -26,4 +26,9 @@ template <typename KeyT> __host__ __device__ constexpr int key_shift()
     return sizeof(KeyT) == 2 ? 8 : 16;
 }
 
+// Preference lists (N <= 128): pref[b][r][i] = the warehouse with key position i in region
+// r, i < N (the inverse of the key table's positions); rows padded to 16 bytes with 127,
+// a warehouse that never has stock when N < 128 (at N = 128 there is no padding).
+__host__ __device__ inline int pref_npad(int N) { return (N + 15) & ~15; }
+
 } // namespace pk

@@ -42,6 +42,10 @@ struct Ctl {
     int32_t max_passes;
     uint32_t wg_done;    // workgroups of the current walk launch that have finished
     int32_t n_active;    // runs listed in Plan::active for the current pass
+    int32_t n_wide;      // first pass: runs the wave-per-run walk takes (Plan::wlist head)
+    int32_t n_lane;      // first pass: runs walked one per lane (Plan::wlist after n_wide)
+    int32_t qty_unpacked; // setup: some quantity did not fit the sort key word
+    int32_t rq_bad;       // setup: some quantity did not fit Plan::s_rq (no lane walk)
     unsigned long long stat[STAT_SLOTS][ST_N]; // summed on the host
 };
 
@@ -82,6 +86,13 @@ struct Plan {
     int32_t *E;              // [n_split_max][N] consumption entering each split run
     float *costT;            // [n_traj][R][N] cost as float, region-major (learned policy)
     void *pos;               // greedy: key table of greedy_keys.h
+    uint8_t *pref;           // greedy, N <= 128: preference lists of greedy_keys.h
+    int32_t *wlist;          // nullable [n_sr_max] first-pass run list: runs longer than
+                             // lane_max in run order, then the others longest first
+    int32_t lane_max;        // the longest run the first pass walks one per lane
+    int32_t *s_rq;           // nullable [total] region | quantity << rq_rb (lane walk)
+    int32_t rq_rb;           // region bits of s_rq
+    int32_t pref_lds;        // 1: the lane walk may stage a trajectory's preference lists in LDS
     const int32_t *worker;   // nullable [total] process of each order (original order);
                              // null: blocks of B sorted positions are the processes
     int32_t *ch_prevj;       // [n_sr_max] given partitions: index within its segment of the
@@ -187,6 +198,18 @@ struct AdamCoef {
 
 // ---------------------------------------------------------------- host launchers
 // All return hipSuccess or the first HIP error.  `st` is the stream.
+
+// First pass of the greedy walk (N <= 128, block partitions): runs up to Plan::lane_max
+// orders (at most LANE_MAX_LEN) are walked one per lane (walk_lane.hip), longer ones a wave
+// per run.
+constexpr int LANE_MAX_LEN = 510;
+int lane_max_for(int64_t total, int N, int R, int n_cus);
+constexpr int PREF_MAX_N = 128; // the greedy preference lists (greedy_keys.h) exist up to here
+size_t walk_lane_lds(int N, int R);
+bool pref_in_lds(int N, int R);
+int region_bits(int R);
+hipError_t launch_walk_greedy_lane(const Prob &P, const Plan &L, int32_t *final_inv,
+                                   bool has_init, int64_t n_list, hipStream_t st);
 hipError_t scan_i64(int64_t *data, int64_t n, bool inclusive, void *tmp, hipStream_t st);
 size_t scan_tmp_bytes(int64_t n);
 hipError_t scan_i32_excl(int32_t *data, int64_t n, void *tmp, hipStream_t st);
@@ -195,6 +218,14 @@ hipError_t radix_sort_pairs(int32_t *keys, int32_t *vals, int32_t *keys_alt,
                             int32_t *vals_alt, int64_t n, int key_bits, void *tmp,
                             hipStream_t st, bool *result_in_alt);
 size_t radix_tmp_bytes(int64_t n);
+// Stable sort by bits [0, key_bits) within each segment [seg_off[s], seg_off[s+1]) (device
+// offsets, n_seg segments covering [0, n)); tmp of radix_tmp_bytes(n, n_seg).
+hipError_t radix_sort_pairs_seg(int32_t *keys, int32_t *vals, int32_t *keys_alt,
+                                int32_t *vals_alt, int64_t n, int key_bits,
+                                const int64_t *seg_off, int n_seg, void *tmp, hipStream_t st,
+                                bool *result_in_alt);
+size_t radix_tmp_bytes(int64_t n, int n_seg);
+int radix_passes(int key_bits);
 
 // ---------------------------------------------------------------- OWMR inventory control
 // (owmr.hip: one central warehouse and N retailers, one process per retailer)

@@ -1,11 +1,16 @@
 // Per-call setup of the Picard iteration: the partition of the steps into processes.
 //
-// Orders of all trajectories are sorted (stably) by key = trajectory * K + SKU, so every
-// SKU's orders form a contiguous segment in time order.  Blocks of B consecutive sorted
-// positions are the processes (Section 2: each process m owns a disjoint set of steps
-// T_m).  A run is a block's part of one segment; because SKUs never interact without
-// node capacity (Assumption 1, inventory independence), a process's runs are independent
-// and a run is the unit of work on the GPU.
+// Each trajectory's orders are sorted (stably) by SKU inside the trajectory's own range, so
+// the batch is ordered by key = trajectory * K + SKU and every SKU's orders form a
+// contiguous segment in time order.  Blocks of B consecutive sorted positions are the
+// processes (Section 2: each process m owns a disjoint set of steps T_m).  A run is a
+// block's part of one segment; because SKUs never interact without node capacity
+// (Assumption 1, inventory independence), a process's runs are independent and a run is
+// the unit of work on the GPU.
+//
+// The sort key word carries the SKU in its low bits and, when they fit, the order's region
+// and quantity above them (the sort looks at the SKU bits only), so the sorted order data
+// is read back in sequence instead of gathered through the permutation.
 #include <algorithm>
 #include <stddef.h>
 
@@ -15,20 +20,54 @@ namespace pk {
 
 namespace {
 
-__global__ void k_make_keys(Prob P, int32_t *keys, int32_t *vals, int validate, Ctl *ctl)
+// Bit fields of a sort key word: SKU in [0, kb), region in [kb, kb + rb), quantity above
+// (0 there when the quantity does not fit, which Ctl::qty_unpacked reports).  on: region
+// and quantity are packed (kb + rb <= 31).
+struct KeyPack {
+    int kb, rb, qb;
+    int on;
+};
+
+KeyPack key_pack(int K, int R)
+{
+    KeyPack k;
+    k.kb = 1;
+    while (k.kb < 31 && (1ll << k.kb) < (int64_t)K) ++k.kb;
+    k.rb = region_bits(R);
+    k.on = k.kb + k.rb <= 31;
+    k.qb = k.on ? 32 - k.kb - k.rb : 0;
+    return k;
+}
+
+__global__ void k_make_keys(Prob P, KeyPack kp, int32_t *keys, int32_t *vals, int validate,
+                            Ctl *ctl)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const uint32_t qcap = kp.on ? (uint32_t)((1ull << kp.qb) - 1ull) : 0u;
+    int unpacked = 0;
     for (int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; o < P.total; o += stride) {
-        const int b = traj_of(P.traj_off, P.n_traj, o);
         int32_t s = P.sku[o];
         if (validate) {
             const int32_t r = P.region[o], q = P.qty[o];
             if (s < 0 || s >= P.K || r < 0 || r >= P.R || q < 1) atomicOr(&ctl->error, 1);
         }
         s = s < 0 ? 0 : (s >= P.K ? P.K - 1 : s); // out-of-range input never indexes memory
-        keys[o] = b * P.K + s;
+        uint32_t w = (uint32_t)s;
+        if (kp.on) {
+            int32_t r = P.region[o], q = P.qty[o];
+            r = r < 0 ? 0 : (r >= P.R ? P.R - 1 : r);
+            q = q < 1 ? 1 : q;
+            uint32_t qw = (uint32_t)q;
+            if (qw > qcap) {
+                qw = 0;
+                unpacked = 1;
+            }
+            w |= ((uint32_t)r << kp.kb) | (kp.qb > 0 ? qw << (kp.kb + kp.rb) : 0u);
+        }
+        keys[o] = (int32_t)w;
         vals[o] = (int32_t)o;
     }
+    if (__ballot(unpacked) && __lane_id() == 0) atomicOr(&ctl->qty_unpacked, 1);
 }
 
 __global__ void k_check_inv(const int32_t *x0, int64_t n, Ctl *ctl)
@@ -47,18 +86,51 @@ __device__ __forceinline__ bool run_start_at(const Plan &L, int64_t p, bool seg_
     return (p % L.B) == 0;
 }
 
-// Gather the sorted order data and the run/segment start flags.  flags[p] packs the
-// run-start count in the low 32 bits and the segment-start count in the high 32 bits.
-__global__ void k_gather(Prob P, Plan L, const int32_t *init_cache, int validate,
-                         int64_t *flags, int want_t)
+// The sorted order data and the run/segment start flags, each workgroup over a contiguous
+// range of positions (its trajectory found once, then followed).  Region and quantity come
+// from the sorted key words, or through the permutation when they are not packed.
+// flags[p] packs the run-start count in the low 32 bits and the segment-start count in the
+// high 32 bits.
+constexpr int GATHER_PER_WG = 2048;
+
+__global__ __launch_bounds__(256) void k_gather(Prob P, Plan L, KeyPack kp, const int32_t *words,
+                                                const int32_t *init_cache, int validate,
+                                                int64_t *flags, int want_t)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < P.total; p += stride) {
+    __shared__ int s_b;
+    const int64_t p0 = (int64_t)blockIdx.x * GATHER_PER_WG;
+    if (p0 >= P.total) return;
+    if (threadIdx.x == 0) s_b = traj_of(P.traj_off, P.n_traj, p0);
+    __syncthreads();
+    int b = s_b;
+    const uint32_t kmask = (uint32_t)((1ull << kp.kb) - 1ull);
+    const uint32_t rmask = (uint32_t)((1ull << kp.rb) - 1ull);
+    const bool from_words = kp.on && !L.ctl->qty_unpacked;
+    const int64_t p1 = p0 + GATHER_PER_WG < P.total ? p0 + GATHER_PER_WG : P.total;
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+        while (p >= P.traj_off[b + 1]) ++b; // positions only grow; empty trajectories skipped
         const int32_t o = L.perm[p];
-        const int32_t key = L.s_key[p];
-        const int32_t r = P.region[o], q = P.qty[o];
-        L.s_region[p] = r < 0 ? 0 : (r >= P.R ? P.R - 1 : r);
-        L.s_qty[p] = q < 1 ? 1 : q;
+        const uint32_t w = (uint32_t)words[p];
+        const int32_t sku = (int32_t)(w & kmask);
+        int32_t r, q;
+        if (kp.on) {
+            r = (int32_t)((w >> kp.kb) & rmask);
+            q = from_words ? (int32_t)(w >> (kp.kb + kp.rb)) : P.qty[o];
+        } else {
+            r = P.region[o];
+            q = P.qty[o];
+        }
+        const int32_t key = b * P.K + sku;
+        L.s_key[p] = key;
+        r = r < 0 ? 0 : (r >= P.R ? P.R - 1 : r);
+        q = q < 1 ? 1 : q;
+        L.s_region[p] = r;
+        L.s_qty[p] = q;
+        if (L.s_rq) { // region | quantity << rq_rb for the first pass's lane walk
+            const bool fits = (int64_t)q < (1ll << (31 - L.rq_rb));
+            if (!fits) L.ctl->rq_bad = 1;
+            L.s_rq[p] = fits ? (int32_t)((uint32_t)r | ((uint32_t)q << L.rq_rb)) : r;
+        }
         int32_t a = LOST;
         if (init_cache) {
             a = init_cache[o];
@@ -69,11 +141,8 @@ __global__ void k_gather(Prob P, Plan L, const int32_t *init_cache, int validate
         }
         L.s_alpha[p] = a;
         if (L.worker && L.worker[o] < 0) atomicOr(&L.ctl->error, ERR_PARTITION);
-        if (want_t) {
-            const int b = key / P.K;
-            L.s_t[p] = (int32_t)(o - P.traj_off[b]);
-        }
-        const bool seg_start = p == 0 || L.s_key[p - 1] != key;
+        if (want_t) L.s_t[p] = (int32_t)(o - P.traj_off[b]);
+        const bool seg_start = p == P.traj_off[b] || (((uint32_t)words[p - 1]) & kmask) != (uint32_t)sku;
         const bool run_start = run_start_at(L, p, seg_start);
         flags[p] = (run_start ? 1ll : 0ll) | (seg_start ? (1ll << 32) : 0ll);
     }
@@ -204,6 +273,40 @@ __global__ void k_chain_link(Plan L, int64_t n, const int32_t *vals)
     }
 }
 
+// The first pass's run list: key 0 for runs longer than lane_max (the wave-per-run walk's,
+// kept in run order by the stable sort), lane_max + 1 - length for the others (longest
+// first), 511 past the run count.
+__global__ void k_lane_keys(Plan L, int64_t n, int32_t *keys, int32_t *vals)
+{
+    const int n_sr = L.ctl->n_sr;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += stride) {
+        int32_t k = 511;
+        if (s < n_sr) {
+            const int32_t len = L.sr_lo[s + 1] - L.sr_lo[s];
+            k = len > L.lane_max ? 0 : L.lane_max + 1 - len;
+        }
+        keys[s] = k;
+        vals[s] = (int32_t)s;
+    }
+}
+
+// Splits the sorted list: n_wide = the first position with a nonzero key (binary search).
+__global__ void k_lane_count(Plan L, const int32_t *keys)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int n_sr = L.ctl->n_sr;
+    int a = 0, b = n_sr; // keys[0, a) are 0, keys[b, n_sr) are not
+    while (a < b) {
+        const int m = a + (b - a) / 2;
+        if (keys[m] == 0) a = m + 1;
+        else b = m;
+    }
+    if (L.ctl->rq_bad) a = n_sr; // a quantity too large for the packed words: no lane walk
+    L.ctl->n_wide = a;
+    L.ctl->n_lane = n_sr - a;
+}
+
 __global__ void k_init_ctl(Ctl *ctl, int32_t *traj_lcp, int n_traj, int max_passes)
 {
     // the control block word by word: pass 1, the pass limit, everything else zero
@@ -236,8 +339,9 @@ hipError_t setup_ctl(Plan &L, int n_traj, int max_passes, hipStream_t st)
     return hipGetLastError();
 }
 
-// Sort, gather, and build the run / segment tables.  `scratch` must hold
-// 2*total int32 (ping-pong keys/values), total int64 (flags) and the primitives' tmp.
+// Sort, gather, and build the run / segment tables.  `scratch` (setup_scratch_bytes) holds
+// 3 total int32 (the sort's key words and its second value array), total int64 (flags) and
+// the primitives' tmp.
 hipError_t setup_plan(const Prob &P, Plan &L, const int32_t *init_cache, int validate,
                       bool want_t, int32_t n_seg_max, void *scratch, hipStream_t st)
 {
@@ -250,34 +354,39 @@ hipError_t setup_plan(const Prob &P, Plan &L, const int32_t *init_cache, int val
         s += (bytes + 255) & ~(size_t)255;
         return r;
     };
-    int32_t *keys_a = L.s_key;
-    int32_t *vals_a = L.perm;
+    int32_t *keys_a = (int32_t *)take(n * sizeof(int32_t));
     int32_t *keys_b = (int32_t *)take(n * sizeof(int32_t));
     int32_t *vals_b = (int32_t *)take(n * sizeof(int32_t));
     int64_t *flags = (int64_t *)take(n * sizeof(int64_t));
-    void *tmp = take(radix_tmp_bytes(n) > scan_tmp_bytes(n) ? radix_tmp_bytes(n)
-                                                             : scan_tmp_bytes(n));
+    const size_t tmp_b = std::max(radix_tmp_bytes(n, P.n_traj), scan_tmp_bytes(n));
+    void *tmp = take(tmp_b);
 
-    hipLaunchKernelGGL(k_make_keys, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, P, keys_a,
-                       vals_a, validate, L.ctl);
+    // each trajectory's orders sorted by SKU in place: an even pass count ends in the
+    // first pair, so the values start in the permutation array when the count is even
+    const KeyPack kp = key_pack(P.K, P.R);
+    const bool even = radix_passes(kp.kb) % 2 == 0;
+    int32_t *k_in = even ? keys_a : keys_b, *v_in = even ? L.perm : vals_b;
+    int32_t *k_alt = even ? keys_b : keys_a, *v_alt = even ? vals_b : L.perm;
+    hipLaunchKernelGGL(k_make_keys, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, P, kp, k_in,
+                       v_in, validate, L.ctl);
     if (validate) {
         const int64_t nx = (int64_t)P.n_traj * P.K * P.N;
         hipLaunchKernelGGL(k_check_inv, dim3(grid_for(nx, 256, 8192)), dim3(256), 0, st, P.x0,
                            nx, L.ctl);
     }
-    int key_bits = 1;
-    while (key_bits < 31 && (1ll << key_bits) < (int64_t)L.n_keys) ++key_bits;
     bool in_alt = false;
-    e = radix_sort_pairs(keys_a, vals_a, keys_b, vals_b, n, key_bits, tmp, st, &in_alt);
+    e = radix_sort_pairs_seg(k_in, v_in, k_alt, v_alt, n, kp.kb, P.traj_off, P.n_traj, tmp, st,
+                             &in_alt);
     if (e != hipSuccess) return e;
-    if (in_alt) {
-        e = hipMemcpyAsync(keys_a, keys_b, n * sizeof(int32_t), hipMemcpyDeviceToDevice, st);
-        if (e != hipSuccess) return e;
-        e = hipMemcpyAsync(vals_a, vals_b, n * sizeof(int32_t), hipMemcpyDeviceToDevice, st);
+    const int32_t *words = in_alt ? k_alt : k_in;
+    if ((in_alt ? v_alt : v_in) != L.perm) { // not reached with the placement above
+        e = hipMemcpyAsync(L.perm, in_alt ? v_alt : v_in, n * sizeof(int32_t),
+                           hipMemcpyDeviceToDevice, st);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_gather, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, P, L,
-                       init_cache, validate, flags, want_t ? 1 : 0);
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)((n + GATHER_PER_WG - 1) / GATHER_PER_WG)),
+                       dim3(256), 0, st, P, L, kp, words, init_cache, validate, flags,
+                       want_t ? 1 : 0);
     e = scan_i64(flags, n, true, tmp, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_tables, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, P, L, flags);
@@ -316,15 +425,37 @@ hipError_t setup_plan(const Prob &P, Plan &L, const int32_t *init_cache, int val
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_chain_link, dim3(grid_for(n, 256, 8192)), dim3(256), 0, st, L, n,
                            alt ? v3 : v2);
+    } else if (L.wlist) {
+        // the first pass's run list (at most min(n, run bound) runs: every run has an order)
+        const int64_t nb = (n + L.B - 1) / L.B;
+        const int64_t nl = std::min<int64_t>(n, nb + n_seg_max + 1);
+        int32_t *ka = (int32_t *)flags, *kb = keys_b, *va = vals_b;
+        hipLaunchKernelGGL(k_lane_keys, dim3(grid_for(nl, 256, 8192)), dim3(256), 0, st, L, nl,
+                           ka, va);
+        bool alt = false;
+        e = radix_sort_pairs(ka, va, kb, L.wlist, nl, 9, tmp, st, &alt);
+        if (e != hipSuccess) return e;
+        if (!alt) {
+            e = hipMemcpyAsync(L.wlist, va, nl * sizeof(int32_t), hipMemcpyDeviceToDevice, st);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(k_lane_count, dim3(1), dim3(64), 0, st, L, alt ? kb : ka);
     }
     return hipGetLastError();
 }
 
-size_t setup_scratch_bytes(int64_t n)
+int region_bits(int R)
+{
+    int b = 1;
+    while (b < 31 && (1ll << b) < (int64_t)R) ++b;
+    return b;
+}
+
+size_t setup_scratch_bytes(int64_t n, int n_traj)
 {
     auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
-    size_t t = radix_tmp_bytes(n) > scan_tmp_bytes(n) ? radix_tmp_bytes(n) : scan_tmp_bytes(n);
-    return al(n * 4) * 2 + al(n * 8) + al(t) + 1024;
+    const size_t t = std::max(radix_tmp_bytes(n, n_traj), scan_tmp_bytes(n));
+    return al(n * 4) * 3 + al(n * 8) + al(t) + 1024;
 }
 
 } // namespace pk

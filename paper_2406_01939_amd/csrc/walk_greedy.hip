@@ -275,9 +275,11 @@ __global__ __launch_bounds__(WPB * 64) void k_walk_greedy(Prob P, Plan L, const 
     const int pass = ctl->pass;
     int32_t *fcur = L.fr[pass & 1];
     // pass 1 (and the no-frontier mode) walks every run; later passes walk the runs past
-    // each SKU's frontier, listed by the entry scan
+    // each SKU's frontier, listed by the entry scan.  With a first-pass list, pass 1 walks
+    // only its long runs here (the lane walk has taken the others).
     const bool all = pass == 1 || L.no_frontier;
-    const int n_items = all ? ctl->n_sr : ctl->n_active;
+    const bool head = pass == 1 && L.wlist != nullptr;
+    const int n_items = head ? ctl->n_wide : (all ? ctl->n_sr : ctl->n_active);
     const bool need_E = pass > 1 || has_init;
     int lcp_b = -1; // last trajectory this wave marked as changed in this pass
     unsigned long long n_orders = 0, n_runs = 0, n_changed = 0, n_bytes = 0;
@@ -287,13 +289,13 @@ __global__ __launch_bounds__(WPB * 64) void k_walk_greedy(Prob P, Plan L, const 
     const int n_waves = gridDim.x * WPB;
     int item = wave * gridDim.x + blockIdx.x;
     RunDesc d = {};
-    if (item < n_items) d = L.rd[all ? item : L.active[item]];
+    if (item < n_items) d = L.rd[head ? L.wlist[item] : (all ? item : L.active[item])];
     for (; item < n_items; item += n_waves) {
         const int lo = uni(d.lo), hi = uni(d.hi), key = uni(d.key), g = uni(d.g);
         const int j = uni(d.j), nsr = uni(d.nsr), uidx = uni(d.uidx);
         const int b = key / P.K;
         const int nxt = item + n_waves;
-        const int s_next = nxt < n_items ? (all ? nxt : L.active[nxt]) : -1;
+        const int s_next = nxt < n_items ? (head ? L.wlist[nxt] : (all ? nxt : L.active[nxt])) : -1;
         // the run's first chunk (loads clamped into the run)
         const int nch = (hi - lo + WAVE - 1) / WAVE;
         const int i0 = lo + lane < hi ? lo + lane : hi - 1;

@@ -331,9 +331,10 @@ def test_batched_uneven_horizons(api, oracle):
     _say(f"case batch16 total={inst.total_orders}")
     want_a, want_s, want_f, want_p = _oracle_batch(oracle, inst, B)
     prob = api.DeviceProblem.from_instance(inst)
-    out = api.pk_picard_simulate(prob, "greedy", block_len=B)
-    _check(out, inst, want_a, want_s, want_f)
-    np.testing.assert_array_equal(out["passes"], want_p)
+    for lm in (0, 200):  # automatic (too little work: no lane walk), and lanes up to 200
+        out = api.pk_picard_simulate(prob, "greedy", block_len=B, lane_max=lm)
+        _check(out, inst, want_a, want_s, want_f)
+        np.testing.assert_array_equal(out["passes"], want_p)
 
 
 def test_no_frontier_gives_same_passes(api, oracle):
@@ -420,3 +421,70 @@ def test_batched_256_trajectories_full_size(api, oracle):
             pr = oracle.picard_runs(inst, w[lo:hi], b)
             assert out["passes"][b] == pr["passes"], b
     _say(f"B={B} passes max={out['passes'].max()} mean={out['passes'].mean():.2f}")
+
+
+@pytest.mark.parametrize("N", [16, 17, 48, 64, 65, 128])
+@pytest.mark.parametrize("warm", [False, True])
+def test_first_pass_lane_walk(api, oracle, N, warm):
+    """The first pass walks runs of up to lane_max orders one per lane and longer runs a wave
+    per run.  Run lengths on both sides of the limit (one SKU takes about half the orders,
+    in blocks of 700), every preference-row layout (16 to 64 candidates loaded ahead, or two
+    chunks of a longer row read further on demand), with and without an initial cache; the
+    same results without the lane walk."""
+    rng = np.random.default_rng(600 + N)
+    inst = random_tiny(600 + N + int(warm), N=N, K=40, R=7, T=4000, qmax=3, inv_max=3,
+                       n_traj=2)
+    inst.sku[rng.random(inst.total_orders) < 0.5] = 0
+    inst.x0[:, 0, :] = rng.integers(0, 40, (inst.n_traj, N))
+    B = 700
+    _say(f"case lane walk N={N} warm={warm} total={inst.total_orders}")
+    want_a, want_s, want_f, want_p = _oracle_batch(oracle, inst, B)
+    prob = api.DeviceProblem.from_instance(inst)
+    init = None
+    if warm:
+        init = rng.integers(-1, N, inst.total_orders).astype(np.int32)
+    init_d = None if init is None else torch.from_numpy(init).cuda()
+    out = api.pk_picard_simulate(prob, "greedy", block_len=B, validate=True, init_cache=init_d,
+                                 lane_max=510)
+    _check(out, inst, want_a, want_s, want_f)
+    off = api.pk_picard_simulate(prob, "greedy", block_len=B, init_cache=init_d, lane_max=-1)
+    assert torch.equal(off["actions"], out["actions"])
+    assert torch.equal(off["final_inv"], out["final_inv"])
+    np.testing.assert_array_equal(off["passes"], out["passes"])
+    w = oracle.block_workers(inst, B)
+    for b in range(inst.n_traj):
+        lo, hi = int(inst.traj_offsets[b]), int(inst.traj_offsets[b + 1])
+        pr = oracle.picard_runs(inst, w[lo:hi], b,
+                                init_cache=None if init is None else init[lo:hi])
+        assert out["passes"][b] == pr["passes"], b
+    assert out["stats"]["orders_walked"] >= inst.total_orders
+    # the first pass alone: the cache after one pass, against the oracle's
+    out1 = api.pk_picard_simulate(prob, "greedy", block_len=B, max_passes=1,
+                                  raise_not_converged=False, init_cache=init_d, lane_max=100)
+    for b in range(inst.n_traj):
+        lo, hi = int(inst.traj_offsets[b]), int(inst.traj_offsets[b + 1])
+        pr = oracle.picard_runs(inst, w[lo:hi], b, max_passes=1, record=True,
+                                init_cache=None if init is None else init[lo:hi])
+        np.testing.assert_array_equal(out1["actions"].cpu().numpy()[lo:hi], pr["caches"][0])
+
+
+@pytest.mark.parametrize("K,R,qmax", [
+    (70_000, 200, 3),      # 17 SKU bits: two sort passes, region and quantity packed above
+    (1 << 21, 2048, 2),    # 21 + 11 bits: region and quantity read through the permutation
+    (5_000, 300, 5_000),   # quantities too large for the key word's top bits
+])
+def test_setup_key_packing(api, oracle, K, R, qmax):
+    """The per-call setup sorts each trajectory's orders by SKU with region and quantity
+    carried in the key word when they fit: multi-pass sorts whose last digit stops below
+    the packed fields, key words with no room for them, and quantities past their field."""
+    inst = random_tiny(700 + K % 97 + R, N=5, K=K, R=R, T=6000, qmax=qmax, inv_max=4,
+                       n_traj=3)
+    inst.qty[::7] = np.minimum(inst.qty[::7], 2)
+    B = 64
+    _say(f"case key packing K={K} R={R} qmax={qmax} total={inst.total_orders}")
+    want_a, want_s, want_f, want_p = _oracle_batch(oracle, inst, B)
+    prob = api.DeviceProblem.from_instance(inst)
+    for lm in (0, 64):
+        out = api.pk_picard_simulate(prob, "greedy", block_len=B, validate=True, lane_max=lm)
+        _check(out, inst, want_a, want_s, want_f)
+        np.testing.assert_array_equal(out["passes"], want_p)
