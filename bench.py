@@ -40,23 +40,41 @@ LEARNED_WORKLOAD = "mlp_batch64_n100_k5e4_t2e5"
 CAPACITY_WORKLOAD = "greedy_cap_n100_k1e5_t1e6"
 REVENUE = 200  # per-unit price of the margin reward (revenue - cost) of the gradient legs
 FP32_PEAK_TFLOPS = 157.3
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_walk_greedy_n100_k1e5_t1e6_traffic.md")
-WALK_SOURCE = os.path.join(ROOT, "paper_2406_01939_amd", "csrc", "walk_greedy.hip")
+CSRC = os.path.join(ROOT, "paper_2406_01939_amd", "csrc")
+# HBM traffic of the dominant kernel per workload: the committed rocprofv3 counter summary
+# and the sources whose text it was measured on
+TRAFFIC = {
+    SINGLE_WORKLOAD: ("k_walk_greedy_n100_k1e5_t1e6_traffic.md", ("walk_greedy.hip",)),
+    BATCH_WORKLOAD: ("k_walk_greedy_batch256_n50_k2e4_traffic.md",
+                     ("walk_greedy.hip", "walk_lane.hip")),
+    DEFAULT_WORKLOAD: ("k_walk_mlp_batch16_n500_k1e6_t1e7_traffic.md",
+                       ("mlp.hip", "mlp_device.h")),
+}
 
 
-def _traffic(block_len: int):
-    """HBM bytes per walk launch from the committed rocprofv3 counter summary, if the walk
-    kernel's source is unchanged since the counters were taken and they were taken at the
-    same block length; else None.  The summary carries `key: value` lines, among them
-    `source_sha256`, `block_len` and `bytes_per_launch`."""
+def sources_sha256(names) -> str:
+    h = hashlib.sha256()
+    for n in names:
+        h.update(open(os.path.join(CSRC, n), "rb").read())
+    return h.hexdigest()
+
+
+def _traffic(workload: str, block_len: int):
+    """HBM bytes per walk launch from the committed rocprofv3 counter summary of this
+    workload, if the walk's sources are unchanged since the counters were taken and they
+    were taken at the same block length; else None.  The summary carries `key: value`
+    lines, among them `source_sha256`, `block_len` and `bytes_per_launch`."""
+    if workload not in TRAFFIC:
+        return None
+    fname, srcs = TRAFFIC[workload]
     try:
         rec = {}
-        for line in open(TRAFFIC_FILE):
+        for line in open(os.path.join(ROOT, "profiles", fname)):
             k, sep, v = line.partition(":")
             if sep and k.strip() in ("source_sha256", "block_len", "bytes_per_launch"):
                 rec[k.strip()] = v.strip().strip("`")
-        h = hashlib.sha256(open(WALK_SOURCE, "rb").read()).hexdigest()
-        if rec.get("source_sha256") != h or int(rec.get("block_len", -1)) != block_len:
+        if rec.get("source_sha256") != sources_sha256(srcs) or \
+                int(rec.get("block_len", -1)) != block_len:
             return None
         return float(rec["bytes_per_launch"])
     except (OSError, ValueError, KeyError):
@@ -287,16 +305,18 @@ def main():
         avg_us = 1e3 * acc["walk_ms"] / max(acc["walk_launches"], 1)
         if policy == "greedy":
             achieved = (acc["walk_bytes"] / 1e9) / (acc["walk_ms"] / 1e3) if acc["walk_ms"] > 0 else 0.0
-            r["roofline"] = {"kernel": "k_walk_greedy", "bound": "hbm", "achieved": achieved,
+            r["roofline"] = {"kernel": "k_walk_greedy (first pass: k_walk_greedy_lane, then "
+                                       "k_walk_greedy on the long runs)",
+                             "bound": "hbm", "achieved": achieved,
                              "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                             "traffic": _traffic(B) if name == SINGLE_WORKLOAD else None,
+                             "traffic": _traffic(name, B),
                              "bytes_per_launch": acc["walk_bytes"] / max(acc["walk_launches"], 1),
                              "avg_launch_us": avg_us, "launches": acc["walk_launches"]}
         else:
             achieved = (acc["walk_flops"] / 1e12) / (acc["walk_ms"] / 1e3) if acc["walk_ms"] > 0 else 0.0
             r["roofline"] = {"kernel": "k_walk_mlp", "bound": "mfma", "achieved": achieved,
                              "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                             "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                             "frac": achieved / FP32_PEAK_TFLOPS, "traffic": _traffic(name, B),
                              "flops_per_launch": acc["walk_flops"] / max(acc["walk_launches"], 1),
                              "avg_launch_us": avg_us, "launches": acc["walk_launches"]}
             r["near_ties"] = {"evaluations_per_step": acc["near_ties"] / per,

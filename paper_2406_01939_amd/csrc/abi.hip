@@ -30,8 +30,8 @@ hipError_t launch_scan_entry(const Prob &P, const Plan &L, int n_seg_max, bool s
                              hipStream_t st);
 hipError_t launch_pass_end(const Plan &L, hipStream_t st);
 hipError_t launch_consume(const Prob &P, const Plan &L, int64_t n_split_max, hipStream_t st);
-hipError_t launch_unpermute(const Prob &P, const Plan &L, int32_t *actions, int32_t *shipped,
-                            hipStream_t st);
+hipError_t unpermute_results(const Prob &P, const Plan &L, int32_t *actions, int32_t *shipped,
+                             void *scratch, bool tiles, hipStream_t st);
 // walk_chain.hip
 hipError_t launch_walk_chain_greedy(const Prob &P, const Plan &L, int32_t *final_inv,
                                     bool has_init, int n_cus, hipStream_t st);
@@ -672,7 +672,9 @@ pk_status picard_run(const pk_problem *problem, const Dims &d, const pk_policy *
         g_last_passes.key = key0;
         g_last_passes.passes = hc->passes_done;
     }
-    if (d.total > 0) HIP_TRY(launch_unpermute(P, L, actions, shipped, st));
+    if (d.total > 0)
+        HIP_TRY(unpermute_results(P, L, actions, shipped, setup_scr,
+                                  unpermute_fits(d.max_T, d.N - 1), st));
     HIP_TRY(hipMemcpyAsync(hc, L.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
     // last changed pass per trajectory (read straight into stats->passes without a host
     // buffer of our own when nothing may be allocated)

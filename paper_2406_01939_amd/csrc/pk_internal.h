@@ -226,6 +226,16 @@ hipError_t radix_sort_pairs_seg(int32_t *keys, int32_t *vals, int32_t *keys_alt,
                                 bool *result_in_alt);
 size_t radix_tmp_bytes(int64_t n, int n_seg);
 int radix_passes(int key_bits);
+// out_a[perm[p]] = a[p], out_b[perm[p]] = b[p] (b, out_b nullable) for a permutation within
+// each segment; segments of at most 2^20 elements and a in [-1, 4094] (unpermute_fits).
+// Four int32 arrays of n and radix_tmp_bytes(n, n_seg) of tmp.
+bool unpermute_fits(int64_t longest_segment, int32_t a_max);
+hipError_t unpermute_seg(const int32_t *perm, const int32_t *a, const int32_t *b, int64_t n,
+                         const int64_t *seg_off, int n_seg, int32_t *out_a, int32_t *out_b,
+                         int32_t *k0, int32_t *v0, int32_t *k1, int32_t *v1, void *tmp,
+                         hipStream_t st);
+hipError_t launch_unpermute(const Prob &P, const Plan &L, int32_t *actions, int32_t *shipped,
+                            hipStream_t st);
 
 // ---------------------------------------------------------------- OWMR inventory control
 // (owmr.hip: one central warehouse and N retailers, one process per retailer)

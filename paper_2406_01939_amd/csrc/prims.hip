@@ -124,7 +124,7 @@ hipError_t scan_impl(T *data, int64_t n, bool inclusive, void *tmp, hipStream_t 
 // ------------------------------------------------------------------ radix sort
 // Digits of up to RX_MAXBITS bits (RX_MAXB buckets): a 17-bit key takes two passes.
 constexpr int RX_THREADS = 256;
-constexpr int RX_CHUNKS = 8;
+constexpr int RX_CHUNKS = 16;
 constexpr int RX_TILE = RX_THREADS * RX_CHUNKS;
 constexpr int RX_MAXBITS = 9;
 constexpr int RX_MAXB = 1 << RX_MAXBITS;
@@ -139,6 +139,7 @@ constexpr int RX_BPT = RX_MAXB / RX_THREADS; // buckets per thread in the per-bu
 struct RxTile {
     int64_t lo, hi;       // element range
     int64_t cbase, cstep; // counts index of digit d: cbase + d * cstep
+    int seg;              // segmented: the tile's segment
 };
 
 template <bool SEG>
@@ -151,6 +152,7 @@ __device__ __forceinline__ bool rx_tile(int64_t t, int64_t n, int64_t n_tiles, i
         T.hi = T.lo + RX_TILE < n ? T.lo + RX_TILE : n;
         T.cbase = t;
         T.cstep = n_tiles;
+        T.seg = 0;
         return true;
     }
     __shared__ int s_seg;
@@ -173,6 +175,7 @@ __device__ __forceinline__ bool rx_tile(int64_t t, int64_t n, int64_t n_tiles, i
     T.hi = T.lo + RX_TILE < seg_off[sg + 1] ? T.lo + RX_TILE : seg_off[sg + 1];
     T.cbase = tf * nb + (t - tf);
     T.cstep = nt;
+    T.seg = sg;
     return true;
 }
 
@@ -199,36 +202,46 @@ __global__ __launch_bounds__(RX_THREADS) void k_radix_count(const int32_t *keys,
     }
 }
 
-// Stable scatter: elements of a tile are ranked in index order, 256 at a time; within a
-// wave equal digits are matched with one ballot per digit bit, across the 4 waves through
-// LDS.
+// Stable scatter.  Each wave ranks its own contiguous quarter of the tile, 64 elements at
+// a time in index order (equal digits matched with one ballot per digit bit), against
+// running per-digit counts of its own in LDS, so the waves need no barrier until the tile
+// is ranked; then each digit's count per wave becomes a per-wave offset, and every element
+// goes to its digit's offset for the tile plus its wave's offset plus its rank.
+constexpr int RX_PER_WAVE = RX_TILE / (RX_THREADS / WAVE); // elements per wave and tile
+constexpr int RX_ITEMS = RX_PER_WAVE / WAVE;                // per lane
+
 template <bool SEG>
 __global__ __launch_bounds__(RX_THREADS) void k_radix_scatter(
     const int32_t *keys, const int32_t *vals, int64_t n, int shift, int bits, const int32_t *offs,
     int64_t n_tiles, int32_t *keys_out, int32_t *vals_out, const int64_t *seg_off,
     const int32_t *tile_first, int n_seg)
 {
-    __shared__ int32_t s_wcnt[RX_THREADS / WAVE][RX_MAXB];
-    __shared__ int32_t s_woff[RX_THREADS / WAVE][RX_MAXB];
-    __shared__ int32_t s_run[RX_MAXB];
+    __shared__ int32_t s_wcnt[RX_THREADS / WAVE][RX_MAXB]; // per wave: running digit counts
     __shared__ int32_t s_goff[RX_MAXB];
-    const int tid = threadIdx.x, wave = tid / WAVE;
+    const int tid = threadIdx.x, wave = tid / WAVE, lane = tid % WAVE;
     const int nb = 1 << bits, mask = nb - 1;
     RxTile T;
     if (!rx_tile<SEG>(blockIdx.x, n, n_tiles, nb, seg_off, tile_first, n_seg, T)) return;
     for (int k = 0; k < RX_BPT; ++k) {
         const int d = k * RX_THREADS + tid;
-        s_run[d] = 0;
         s_goff[d] = d < nb ? offs[T.cbase + (int64_t)d * T.cstep] : 0;
         for (int w = 0; w < RX_THREADS / WAVE; ++w) s_wcnt[w][d] = 0;
     }
     __syncthreads();
-    for (int c = 0; c < RX_CHUNKS; ++c) {
-        const int64_t i = T.lo + c * RX_THREADS + tid;
+    const int64_t base = T.lo + (int64_t)wave * RX_PER_WAVE;
+    int32_t kr[RX_ITEMS], vr[RX_ITEMS], rk[RX_ITEMS];
+#pragma unroll
+    for (int c = 0; c < RX_ITEMS; ++c) {
+        const int64_t i = base + c * WAVE + lane;
+        kr[c] = i < T.hi ? keys[i] : 0;
+        vr[c] = i < T.hi ? vals[i] : 0;
+    }
+    int32_t *cnt = s_wcnt[wave];
+#pragma unroll
+    for (int c = 0; c < RX_ITEMS; ++c) {
+        const int64_t i = base + c * WAVE + lane;
         const bool valid = i < T.hi;
-        const int32_t k = valid ? keys[i] : 0;
-        const int32_t v = valid ? vals[i] : 0;
-        const int d = (k >> shift) & mask;
+        const int d = (kr[c] >> shift) & mask;
         uint64_t peers = __ballot(valid);
         for (int b = 0; b < bits; ++b) { // bits is uniform
             const bool bit = (d >> b) & 1;
@@ -236,25 +249,86 @@ __global__ __launch_bounds__(RX_THREADS) void k_radix_scatter(
             peers &= bit ? m : ~m;
         }
         const int rank = __popcll(peers & lanemask_lt());
-        if (valid && rank == 0) s_wcnt[wave][d] = __popcll(peers);
-        __syncthreads();
-        for (int kk = 0; kk < RX_BPT; ++kk) {
-            const int dd = kk * RX_THREADS + tid;
-            int run = s_run[dd];
-            for (int w = 0; w < RX_THREADS / WAVE; ++w) {
-                const int cnt = s_wcnt[w][dd];
-                s_woff[w][dd] = run;
-                run += cnt;
-                s_wcnt[w][dd] = 0;
-            }
-            s_run[dd] = run;
+        const int before = valid ? cnt[d] : 0;
+        wave_sync();
+        if (valid && rank == 0) cnt[d] = before + __popcll(peers);
+        wave_sync();
+        rk[c] = before + rank;
+    }
+    __syncthreads();
+    // per digit: the waves' counts into offsets (wave order is index order)
+    for (int k = 0; k < RX_BPT; ++k) {
+        const int d = k * RX_THREADS + tid;
+        int run = 0;
+        for (int w = 0; w < RX_THREADS / WAVE; ++w) {
+            const int c = s_wcnt[w][d];
+            s_wcnt[w][d] = run;
+            run += c;
         }
-        __syncthreads();
-        if (valid) {
-            const int64_t pos = (int64_t)s_goff[d] + s_woff[wave][d] + rank;
-            keys_out[pos] = k;
-            vals_out[pos] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < RX_ITEMS; ++c) {
+        const int64_t i = base + c * WAVE + lane;
+        if (i < T.hi) {
+            const int d = (kr[c] >> shift) & mask;
+            const int64_t pos = (int64_t)s_goff[d] + cnt[d] + rk[c];
+            keys_out[pos] = kr[c];
+            vals_out[pos] = vr[c];
         }
+    }
+}
+
+// Inverse permutation within segments, in two passes.  perm maps a position p of segment s
+// to an index of the same segment; out[perm[p]] = in[p] for two arrays.  First the pairs go
+// into key words (index within the segment | (a + 1) << 20) sorted by the index's tile of
+// RX_TILE (bits 12 and up, one radix pass within each segment); since perm is a bijection
+// within a segment, the pairs bound for its tile t then occupy exactly the positions of
+// tile t.  Then each tile is placed through LDS and written out in order.
+constexpr int UP_LOW = 12;  // log2(RX_TILE)
+constexpr int UP_IDX = 20;  // index bits: segments of at most 2^20 elements
+static_assert((1 << UP_LOW) == RX_TILE, "tile of the inverse permutation");
+
+__global__ __launch_bounds__(256) void k_unperm_keys(const int32_t *perm, const int32_t *a,
+                                                     const int32_t *b, int64_t n,
+                                                     const int64_t *seg_off, int n_seg,
+                                                     int32_t *keys, int32_t *vals)
+{
+    __shared__ int s_seg;
+    const int64_t p0 = (int64_t)blockIdx.x * RX_TILE;
+    if (p0 >= n) return;
+    if (threadIdx.x == 0) s_seg = traj_of(seg_off, n_seg, p0);
+    __syncthreads();
+    int sg = s_seg;
+    const int64_t p1 = p0 + RX_TILE < n ? p0 + RX_TILE : n;
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+        while (p >= seg_off[sg + 1]) ++sg;
+        const uint32_t idx = (uint32_t)(perm[p] - seg_off[sg]);
+        keys[p] = (int32_t)(idx | ((uint32_t)(a[p] + 1) << UP_IDX));
+        vals[p] = b ? b[p] : 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_unperm_place(const int32_t *keys, const int32_t *vals,
+                                                      int64_t n, const int64_t *seg_off,
+                                                      const int32_t *tile_first, int n_seg,
+                                                      int64_t n_tiles, int32_t *out_a,
+                                                      int32_t *out_b)
+{
+    __shared__ int32_t sa[RX_TILE], sb[RX_TILE];
+    RxTile T;
+    if (!rx_tile<true>(blockIdx.x, n, n_tiles, 1, seg_off, tile_first, n_seg, T)) return;
+    const int cnt = (int)(T.hi - T.lo);
+    for (int j = threadIdx.x; j < cnt; j += blockDim.x) {
+        const uint32_t k = (uint32_t)keys[T.lo + j];
+        const int at = (int)(k & (RX_TILE - 1));
+        sa[at] = (int32_t)(k >> UP_IDX) - 1;
+        sb[at] = vals[T.lo + j];
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < cnt; j += blockDim.x) {
+        out_a[T.lo + j] = sa[j];
+        if (out_b) out_b[T.lo + j] = sb[j];
     }
 }
 
@@ -300,10 +374,11 @@ int radix_passes(int key_bits)
 }
 
 // seg_off: nullable device [n_seg + 1] segment bounds (sorted among themselves).
+// Sorts by bits [bit_lo, key_bits) of the keys.
 static hipError_t radix_sort_impl(int32_t *keys, int32_t *vals, int32_t *keys_alt,
                                   int32_t *vals_alt, int64_t n, int key_bits, void *tmp,
                                   hipStream_t st, bool *result_in_alt, const int64_t *seg_off,
-                                  int n_seg)
+                                  int n_seg, int bit_lo = 0)
 {
     *result_in_alt = false;
     if (n <= 1) return hipSuccess;
@@ -320,14 +395,14 @@ static hipError_t radix_sort_impl(int32_t *keys, int32_t *vals, int32_t *keys_al
         if (e != hipSuccess) return e;
     }
     int32_t *ki = keys, *vi = vals, *ko = keys_alt, *vo = vals_alt;
-    const int passes = radix_passes(key_bits);
-    const int kb = key_bits < 1 ? 1 : key_bits;
+    const int kb = key_bits - bit_lo < 1 ? 1 : key_bits - bit_lo; // bits sorted
+    const int passes = radix_passes(kb);
     const int bits = (kb + passes - 1) / passes; // digit width, <= RX_MAXBITS
     for (int p = 0; p < passes; ++p) {
-        const int shift = bits * p;
+        const int shift = bit_lo + bits * p;
         // the last digit stops at the key's own bits (the key words may carry other fields
         // above them)
-        const int bp = kb - shift < bits ? kb - shift : bits;
+        const int bp = kb - bits * p < bits ? kb - bits * p : bits;
         const int64_t nc = ((int64_t)1 << bp) * n_tiles;
         if (seg)
             hipLaunchKernelGGL(k_radix_count<true>, dim3((unsigned)n_tiles), dim3(RX_THREADS), 0,
@@ -359,6 +434,33 @@ hipError_t radix_sort_pairs(int32_t *keys, int32_t *vals, int32_t *keys_alt, int
 {
     return radix_sort_impl(keys, vals, keys_alt, vals_alt, n, key_bits, tmp, st, result_in_alt,
                            nullptr, 0);
+}
+
+bool unpermute_fits(int64_t longest_segment, int32_t a_max)
+{
+    return longest_segment <= (1ll << UP_IDX) && a_max + 1 < (1 << (32 - UP_IDX));
+}
+
+hipError_t unpermute_seg(const int32_t *perm, const int32_t *a, const int32_t *b, int64_t n,
+                         const int64_t *seg_off, int n_seg, int32_t *out_a, int32_t *out_b,
+                         int32_t *k0, int32_t *v0, int32_t *k1, int32_t *v1, void *tmp,
+                         hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    const unsigned g = (unsigned)((n + RX_TILE - 1) / RX_TILE);
+    hipLaunchKernelGGL(k_unperm_keys, dim3(g), dim3(256), 0, st, perm, a, b, n, seg_off, n_seg,
+                       k0, v0);
+    bool alt = false;
+    hipError_t e = radix_sort_impl(k0, v0, k1, v1, n, UP_IDX, tmp, st, &alt, seg_off, n_seg,
+                                   UP_LOW);
+    if (e != hipSuccess) return e;
+    const int64_t n_tiles = (n + RX_TILE - 1) / RX_TILE + n_seg;
+    const int32_t *tile_first =
+        (const int32_t *)((char *)tmp + (((size_t)RX_MAXB * n_tiles * sizeof(int32_t) + 255) &
+                                         ~(size_t)255));
+    hipLaunchKernelGGL(k_unperm_place, dim3((unsigned)n_tiles), dim3(256), 0, st, alt ? k1 : k0,
+                       alt ? v1 : v0, n, seg_off, tile_first, n_seg, n_tiles, out_a, out_b);
+    return hipGetLastError();
 }
 
 hipError_t radix_sort_pairs_seg(int32_t *keys, int32_t *vals, int32_t *keys_alt,

@@ -339,6 +339,31 @@ hipError_t setup_ctl(Plan &L, int n_traj, int max_passes, hipStream_t st)
     return hipGetLastError();
 }
 
+// The setup scratch: three int32 arrays and an int64 array of `total` entries, then the
+// primitives' tmp.
+struct ScratchArrays {
+    int32_t *keys_a, *keys_b, *vals_b;
+    int64_t *flags;
+    void *tmp;
+};
+
+ScratchArrays scratch_arrays(void *scratch, int64_t n)
+{
+    char *s = (char *)scratch;
+    auto take = [&](size_t bytes) {
+        void *r = s;
+        s += (bytes + 255) & ~(size_t)255;
+        return r;
+    };
+    ScratchArrays a;
+    a.keys_a = (int32_t *)take(n * sizeof(int32_t));
+    a.keys_b = (int32_t *)take(n * sizeof(int32_t));
+    a.vals_b = (int32_t *)take(n * sizeof(int32_t));
+    a.flags = (int64_t *)take(n * sizeof(int64_t));
+    a.tmp = s;
+    return a;
+}
+
 // Sort, gather, and build the run / segment tables.  `scratch` (setup_scratch_bytes) holds
 // 3 total int32 (the sort's key words and its second value array), total int64 (flags) and
 // the primitives' tmp.
@@ -348,18 +373,10 @@ hipError_t setup_plan(const Prob &P, Plan &L, const int32_t *init_cache, int val
     hipError_t e;
     const int64_t n = P.total;
     if (n == 0) return hipSuccess;
-    char *s = (char *)scratch;
-    auto take = [&](size_t bytes) {
-        void *r = s;
-        s += (bytes + 255) & ~(size_t)255;
-        return r;
-    };
-    int32_t *keys_a = (int32_t *)take(n * sizeof(int32_t));
-    int32_t *keys_b = (int32_t *)take(n * sizeof(int32_t));
-    int32_t *vals_b = (int32_t *)take(n * sizeof(int32_t));
-    int64_t *flags = (int64_t *)take(n * sizeof(int64_t));
-    const size_t tmp_b = std::max(radix_tmp_bytes(n, P.n_traj), scan_tmp_bytes(n));
-    void *tmp = take(tmp_b);
+    const ScratchArrays sa = scratch_arrays(scratch, n);
+    int32_t *keys_a = sa.keys_a, *keys_b = sa.keys_b, *vals_b = sa.vals_b;
+    int64_t *flags = sa.flags;
+    void *tmp = sa.tmp;
 
     // each trajectory's orders sorted by SKU in place: an even pass count ends in the
     // first pair, so the values start in the permutation array when the count is even
@@ -442,6 +459,22 @@ hipError_t setup_plan(const Prob &P, Plan &L, const int32_t *init_cache, int val
         hipLaunchKernelGGL(k_lane_count, dim3(1), dim3(64), 0, st, L, alt ? kb : ka);
     }
     return hipGetLastError();
+}
+
+// Actions and units shipped back to time order, once per call.  Within each trajectory's
+// range the sorted position p holds time index perm[p]; with trajectories of at most 2^20
+// orders and N < 4095 the inverse permutation runs as a sort by destination tile and a
+// placement through LDS (both coalesced), else as one scattered write per element.
+hipError_t unpermute_results(const Prob &P, const Plan &L, int32_t *actions, int32_t *shipped,
+                             void *scratch, bool tiles, hipStream_t st)
+{
+    const int64_t n = P.total;
+    if (!tiles || n < 2) return launch_unpermute(P, L, actions, shipped, st);
+    const ScratchArrays sa = scratch_arrays(scratch, n);
+    int32_t *f = (int32_t *)sa.flags; // 2n int32
+    return unpermute_seg(L.perm, L.s_alpha, shipped ? L.s_ship : nullptr, n, P.traj_off,
+                         P.n_traj, actions, shipped, sa.keys_a, sa.keys_b, sa.vals_b, f,
+                         sa.tmp, st);
 }
 
 int region_bits(int R)

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 import torch
 
-from paper_2406_01939_amd.instances import make_instance, random_tiny
+from paper_2406_01939_amd.instances import Instance, make_instance, random_tiny
 
 pytestmark = pytest.mark.gpu
 
@@ -488,3 +488,23 @@ def test_setup_key_packing(api, oracle, K, R, qmax):
         out = api.pk_picard_simulate(prob, "greedy", block_len=B, validate=True, lane_max=lm)
         _check(out, inst, want_a, want_s, want_f)
         np.testing.assert_array_equal(out["passes"], want_p)
+
+
+def test_results_back_to_time_order_tile_edges(api, oracle):
+    """Actions and units shipped return to time order through a sort by destination tile
+    of 4096 orders and an in-LDS placement: trajectories empty, of one order, and just
+    below, at and above tile multiples."""
+    lens = [0, 1, 4095, 4096, 4097, 8197, 0, 3, 12288]
+    rng = np.random.default_rng(808)
+    base = random_tiny(808, N=7, K=30, R=5, T=sum(lens), qmax=3, inv_max=40)
+    offs = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    nt = len(lens)
+    inst = Instance(N=7, K=30, R=5, traj_offsets=offs, sku=base.sku, region=base.region,
+                    qty=base.qty, x0=rng.integers(0, 40, (nt, 30, 7)).astype(np.int32),
+                    cost=rng.integers(1, 6, (nt, 7, 5)).astype(np.int32), rng_seed=1)
+    _say(f"case unpermute tile edges total={inst.total_orders}")
+    want_a, want_s, want_f, want_p = _oracle_batch(oracle, inst, 100)
+    prob = api.DeviceProblem.from_instance(inst)
+    out = api.pk_picard_simulate(prob, "greedy", block_len=100, validate=True)
+    _check(out, inst, want_a, want_s, want_f)
+    np.testing.assert_array_equal(out["passes"], want_p)
