@@ -540,31 +540,49 @@ def main():
     def gamma_ablation(name="greedy_cap_n10_k100_t1e4", B=100,
                        gammas=((0, 1), (1, 2), (1, 1), (2, 1)), reps=3):
         """The appendix's capacity-dependent policy ablation: passes and speed-up over the
-        serial GPU sweep per gamma, on the 1e4-order capacity workload."""
-        from paper_2406_01939_amd.instances import workload_capacity
+        serial GPU sweep per gamma, on the 1e4-order capacity workload, in both readings of
+        the shadow price (every node priced relative to the most capacity left; only nodes
+        below a fifth of their capacity priced), and the bid-price policy (fixed dual
+        prices of stock and capacity, uniform on 0..50 against costs 1..100)."""
+        from paper_2406_01939_amd.instances import bid_prices, workload_capacity
         inst = make_instance(name)
-        cap = torch.from_numpy(workload_capacity(name)).cuda()
+        cap0 = workload_capacity(name)
+        cap = torch.from_numpy(cap0).cuda()
         prob = api.DeviceProblem.from_instance(inst)
+        low = max(1, int(cap0.max()) // 5)
+        cases = [dict(gamma=g) for g in gammas]
+        cases += [dict(gamma=g + (low,)) for g in gammas if g[0] > 0]
+        cases += [dict(bids=bid_prices(inst.K, inst.N, 1))]
         rows = []
-        for g in gammas:
-            out = api.pk_picard_simulate_capacity(prob, cap, block_len=B, gamma=g)
+        for kw in cases:
+            out = api.pk_picard_simulate_capacity(prob, cap, block_len=B, **kw)
             best = None
             for _ in range(reps):
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                out = api.pk_picard_simulate_capacity(prob, cap, block_len=B, gamma=g)
+                out = api.pk_picard_simulate_capacity(prob, cap, block_len=B, **kw)
                 torch.cuda.synchronize()
                 dt = time.perf_counter() - t0
                 best = dt if best is None else min(best, dt)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            ser = api.pk_serial_simulate_capacity(prob, cap, gamma=g)
+            ser = api.pk_serial_simulate_capacity(prob, cap, **kw)
             torch.cuda.synchronize()
             ds = time.perf_counter() - t0
-            rows.append({"gamma": g[0] / g[1], "passes": out["passes"], "picard_ms": 1e3 * best,
-                         "serial_ms": 1e3 * ds, "speedup_vs_serial_gpu": ds / best,
-                         "identical_actions": bool(torch.equal(out["actions"], ser["actions"]))})
-            _progress(f"gamma {g[0]}/{g[1]}: {out['passes']} passes, {1e3 * best:.2f} ms")
+            g = kw.get("gamma")
+            if g is None:
+                row = {"policy": "bid prices", "price": "fixed, uniform on 0..50"}
+            else:
+                row = {"policy": "greedy" if g[0] == 0 else "capacity-dependent",
+                       "gamma": g[0] / g[1],
+                       "price": "below %d of capacity left" % g[2] if len(g) > 2
+                                else "relative to the most capacity left"}
+            row.update({"passes": out["passes"], "picard_ms": 1e3 * best,
+                        "serial_ms": 1e3 * ds, "speedup_vs_serial_gpu": ds / best,
+                        "identical_actions": bool(torch.equal(out["actions"], ser["actions"]))})
+            rows.append(row)
+            _progress(f"capacity policy {kw if g is not None else 'bids'}: {out['passes']} "
+                      f"passes, {1e3 * best:.2f} ms")
         return {"workload": name, "block_len": B, "rows": rows}
 
     if args.capacity_only:

@@ -288,18 +288,38 @@ pk_status pk_adam_step(float *params, const float *grad, float *m, float *v, int
 /* ---------------------------------------------------------------------------------
  * Node capacity (Section 3: the FO state is (x_t, c_t); an order of SKU i may go to node
  * j only while c_{t,j} > 0 and x_{t,i,j} > 0, and shipping it lowers both by one, so
- * capacity couples the SKUs).  Greedy policy only (least cost[w][region], lowest index on
- * ties, lost sale iff no node has both stock and capacity) when gamma_num = 0, else the
- * capacity-dependent policy of the appendix's ablation with gamma = gamma_num / gamma_den
- * (0 <= gamma_num <= 1000, 1 <= gamma_den <= 1000): among the nodes with stock and
- * capacity, the least rank_r(w) + gamma (N-1) (1 - c_w / M), rank_r(w) the node's position
- * in the region's (cost, index) order and M the largest remaining capacity of any node,
- * compared exactly in 64-bit integers, lowest index on ties.  Unit demand only (every qty
- * must be 1: the paper's transition), one trajectory (n_traj == 1), N <= 128, costs in
- * [0, 2^24).  capacity: DEVICE [N] int32 >= 0, the capacities c_1.  Other arrays as for
- * pk_picard_simulate.  Inputs are range-checked on the device on every call
- * (PK_ERR_INVALID_ARG names the failing check).
- *
+ * capacity couples the SKUs).  The policy (pk_cap_policy, nullable: NULL is greedy) picks,
+ * among the nodes with both stock and capacity, the least of a score, lowest index on ties;
+ * a lost sale iff no node has both.  Scores:
+ *  - greedy (gamma_num = 0, no bid prices): cost[w][region] (Section 3.1's myopic policy);
+ *  - capacity-dependent (the appendix's ablation), gamma = gamma_num / gamma_den with
+ *    0 < gamma_num <= 1000, 1 <= gamma_den <= 1000: rank_r(w) + gamma (N-1) p_w,
+ *    rank_r(w) the node's position in the region's (cost, index) order and p_w a shadow
+ *    price in one of two readings of the appendix's description: gamma_low = 0:
+ *    p_w = 1 - c_w / M, M the largest remaining capacity of any node (every node priced);
+ *    gamma_low > 0: p_w = max(0, gamma_low - c_w) / gamma_low (only nodes with less than
+ *    gamma_low capacity left are priced).  Compared exactly in 64-bit integers;
+ *  - bid prices (bid_inv and/or bid_cap non-NULL, gamma_num = 0): cost[w][region] +
+ *    bid_inv[sku][w] + bid_cap[w], fixed prices of the unit of stock and of capacity the
+ *    order would use (the dual policy of Section 4.2 with its prices held fixed), each
+ *    price in [0, 2^24).
+ * Unit demand only (every qty must be 1: the paper's transition), one trajectory
+ * (n_traj == 1), N <= 128, costs in [0, 2^24).  capacity: DEVICE [N] int32 >= 0, the
+ * capacities c_1.  Other arrays as for pk_picard_simulate.  Inputs are range-checked on
+ * the device on every call (PK_ERR_INVALID_ARG names the failing check).
+ */
+typedef struct {
+    int32_t gamma_num;        /* 0: no capacity-dependent price */
+    int32_t gamma_den;        /* >= 1 */
+    int32_t gamma_low;        /* >= 0, see above */
+    int32_t reserved;         /* must be 0 */
+    const int32_t *bid_inv;   /* DEVICE [K][N] int32, nullable: price of a unit of SKU k's
+                                 stock at node w */
+    const int32_t *bid_cap;   /* DEVICE [N] int32, nullable: price of a unit of node w's
+                                 capacity */
+} pk_cap_policy;
+
+/*
  * Bytes of scratch the two calls below need for this problem and block length (0 =
  * the default, 96).  Writes *bytes. */
 pk_status pk_capacity_workspace_size(const pk_problem *problem, const int32_t *capacity,
@@ -309,7 +329,7 @@ pk_status pk_capacity_workspace_size(const pk_problem *problem, const int32_t *c
  * actions [T] out; final_inv [K][N] out, nullable; final_cap [N] out, nullable.
  * Synchronous. */
 pk_status pk_serial_simulate_capacity(const pk_problem *problem, const int32_t *capacity,
-                                      int32_t gamma_num, int32_t gamma_den, void *ws,
+                                      const pk_cap_policy *policy, void *ws,
                                       size_t ws_bytes, int32_t *actions, int32_t *final_inv,
                                       int32_t *final_cap, void *stream);
 
@@ -326,8 +346,7 @@ pk_status pk_serial_simulate_capacity(const pk_problem *problem, const int32_t *
  * max_passes passes end without a repeat (actions then holds the last cache and the
  * final state is not written). */
 pk_status pk_picard_simulate_capacity(const pk_problem *problem, const int32_t *capacity,
-                                      int32_t gamma_num, int32_t gamma_den,
-                                      int32_t block_len, int32_t max_passes,
+                                      const pk_cap_policy *policy, int32_t block_len, int32_t max_passes,
                                       const int32_t *init_cache, void *ws, size_t ws_bytes,
                                       int32_t *actions, int32_t *final_inv, int32_t *final_cap,
                                       int32_t *passes, int64_t *changed, int32_t *caches,

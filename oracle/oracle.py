@@ -67,9 +67,10 @@ def load(path: str):
     L.orc_alg1.argtypes = [P, vp, i64, vp, i32, vp, vp, vp]
     L.orc_picard_runs.argtypes = [P, vp, vp, i32, vp, vp, vp, vp]
     L.orc_reinforce.argtypes = [P, vp, vp, vp, vp, vp]
-    L.orc_serial_cap.argtypes = [P, vp, i32, i32, vp, vp, vp]
-    L.orc_alg1_cap.argtypes = [P, vp, i32, i32, vp, i64, vp, i32, vp, vp, vp]
-    L.orc_picard_timeblocks_cap.argtypes = [P, vp, i32, i32, i64, vp, i32, vp, vp, vp, vp]
+    Pol = C.POINTER(_CapPolicy)
+    L.orc_serial_cap.argtypes = [P, vp, Pol, vp, vp, vp]
+    L.orc_alg1_cap.argtypes = [P, vp, Pol, vp, i64, vp, i32, vp, vp, vp]
+    L.orc_picard_timeblocks_cap.argtypes = [P, vp, Pol, i64, vp, i32, vp, vp, vp, vp]
     L.orc_mlp_scores.argtypes = [P, i32, vp, vp]
     L.orc_philox4x32_10.argtypes = [vp, vp, vp]
     L.orc_philox4x32_10.restype = None
@@ -237,22 +238,54 @@ def _cap_array(inst, cap0) -> np.ndarray:
     return cap0
 
 
-def serial_cap(inst, cap0, b: int = 0, gamma=(0, 1)) -> dict:
+class _CapPolicy(C.Structure):
+    _fields_ = [("gnum", C.c_int32), ("gden", C.c_int32), ("glow", C.c_int32),
+                ("bid_inv", C.c_void_p), ("bid_cap", C.c_void_p)]
+
+
+def _policy(inst, gamma, bids):
+    """The C policy struct and the arrays it points into (kept alive by the caller).
+    gamma = (num, den) or (num, den, low); bids = None or (bid_inv [K][N] or None,
+    bid_cap [N] or None), int32."""
+    keep = []
+    bi = bc = None
+    if bids is not None:
+        if bids[0] is not None:
+            bi = np.ascontiguousarray(bids[0], dtype=np.int32)
+            if bi.shape != (inst.K, inst.N):
+                raise ValueError("bid_inv must be [K][N]")
+            keep.append(bi)
+        if bids[1] is not None:
+            bc = np.ascontiguousarray(bids[1], dtype=np.int32)
+            if bc.shape != (inst.N,):
+                raise ValueError("bid_cap must be [N]")
+            keep.append(bc)
+    pol = _CapPolicy(int(gamma[0]), int(gamma[1]), int(gamma[2]) if len(gamma) > 2 else 0,
+                     _ptr(bi), _ptr(bc))
+    return pol, keep
+
+
+def serial_cap(inst, cap0, b: int = 0, gamma=(0, 1), bids=None) -> dict:
     """Serial rollout of trajectory b with node capacities cap0 (unit demand); gamma =
-    (num, den): 0 for the greedy policy, else the capacity-dependent policy."""
+    (num, den) or (num, den, low): num 0 for the greedy policy, else the capacity-dependent
+    policy, its shadow price on every node relative to the most capacity left (low 0) or
+    only on nodes with less than low capacity left; bids = (bid_inv, bid_cap): the
+    bid-price policy (with num 0)."""
     B = _Bound(inst, b)
     B.p.params = None
     cap0 = _cap_array(inst, cap0)
     act = np.empty(B.T, np.int32)
     fin = np.empty((inst.K, inst.N), np.int32)
     fcap = np.empty(inst.N, np.int32)
-    _check(lib().orc_serial_cap(C.byref(B.p), _ptr(cap0), int(gamma[0]), int(gamma[1]),
-                                _ptr(act), _ptr(fin), _ptr(fcap)), "serial_cap")
+    pol, keep = _policy(inst, gamma, bids)
+    _check(lib().orc_serial_cap(C.byref(B.p), _ptr(cap0), C.byref(pol), _ptr(act), _ptr(fin),
+                                _ptr(fcap)), "serial_cap")
     return dict(actions=act, final_inv=fin, final_cap=fcap)
 
 
 def alg1_cap(inst, cap0, worker: np.ndarray, n_workers: int, b: int = 0, init_cache=None,
-             max_passes: Optional[int] = None, record: bool = True, gamma=(0, 1)) -> dict:
+             max_passes: Optional[int] = None, record: bool = True, gamma=(0, 1),
+             bids=None) -> dict:
     """Algorithm 1 with node capacities by brute force (tiny instances only)."""
     B = _Bound(inst, b)
     B.p.params = None
@@ -265,8 +298,9 @@ def alg1_cap(inst, cap0, worker: np.ndarray, n_workers: int, b: int = 0, init_ca
     fin = np.empty(T, np.int32)
     passes = np.zeros(1, np.int32)
     caches = np.empty((max_passes, T), np.int32) if record else None
-    rc = lib().orc_alg1_cap(C.byref(B.p), _ptr(cap0), int(gamma[0]), int(gamma[1]),
-                            _ptr(worker), n_workers, _ptr(init), max_passes, _ptr(fin),
+    pol, keep = _policy(inst, gamma, bids)
+    rc = lib().orc_alg1_cap(C.byref(B.p), _ptr(cap0), C.byref(pol), _ptr(worker), n_workers,
+                            _ptr(init), max_passes, _ptr(fin),
                             _ptr(passes), _ptr(caches))
     _check(rc, "alg1_cap")
     k = int(passes[0])
@@ -276,7 +310,7 @@ def alg1_cap(inst, cap0, worker: np.ndarray, n_workers: int, b: int = 0, init_ca
 
 def picard_timeblocks_cap(inst, cap0, block_len: int, b: int = 0, init_cache=None,
                           max_passes: Optional[int] = None, record: bool = False,
-                          gamma=(0, 1)) -> dict:
+                          gamma=(0, 1), bids=None) -> dict:
     """Algorithm 1's passes with node capacities for the partition into time blocks of
     block_len consecutive orders (one replay per pass)."""
     B = _Bound(inst, b)
@@ -290,8 +324,9 @@ def picard_timeblocks_cap(inst, cap0, block_len: int, b: int = 0, init_cache=Non
     passes = np.zeros(1, np.int32)
     changed = np.zeros(max_passes, np.int64)
     caches = np.empty((max_passes, T), np.int32) if record else None
-    rc = lib().orc_picard_timeblocks_cap(C.byref(B.p), _ptr(cap0), int(gamma[0]),
-                                         int(gamma[1]), block_len, _ptr(init), max_passes,
+    pol, keep = _policy(inst, gamma, bids)
+    rc = lib().orc_picard_timeblocks_cap(C.byref(B.p), _ptr(cap0), C.byref(pol), block_len,
+                                         _ptr(init), max_passes,
                                          _ptr(fin), _ptr(passes), _ptr(changed), _ptr(caches))
     _check(rc, "picard_timeblocks_cap")
     k = int(passes[0])

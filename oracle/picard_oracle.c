@@ -694,14 +694,25 @@ int orc_mlp_scores(const orc_problem *P, int32_t r, const int32_t *x, double *s)
  * SKU i may go to node j only if c_{t,j} > 0 and x_{t,i,j} > 0; shipping it lowers
  * c_{t,j} and x_{t,i,j} by one.  The paper's transition is unit demand, so every order
  * here must have q = 1.  Policy: greedy (least cost[j][region] among nodes with both
- * capacity and stock, lowest index on ties; lost sale iff none), as in Section 3.1, or
- * the capacity-dependent policy of the appendix's ablation (greedy_cap).  cap0[N] >= 0
- * is c_1.
+ * capacity and stock, lowest index on ties; lost sale iff none), as in Section 3.1, the
+ * capacity-dependent policy of the appendix's ablation, or a bid-price policy (greedy_cap).
+ * cap0[N] >= 0 is c_1.
  * ==================================================================================== */
-static int check_cap(const orc_problem *P, const int32_t *cap0, int32_t gnum, int32_t gden)
+/* The policy with capacity: the greedy policy (gnum = 0, no bid prices), the
+ * capacity-dependent policy of the appendix's ablation (gnum > 0), or a bid-price policy
+ * (bid_inv and/or bid_cap given, gnum = 0). */
+typedef struct {
+    int32_t gnum, gden, glow;
+    const int32_t *bid_inv; /* nullable [K][N]: price of a unit of SKU k's stock at node w */
+    const int32_t *bid_cap; /* nullable [N]: price of a unit of node w's capacity */
+} orc_cap_policy;
+
+static int check_cap(const orc_problem *P, const int32_t *cap0, const orc_cap_policy *pol)
 {
-    if (check_problem(P) || P->params) return -1;
-    if (gnum < 0 || gden < 1 || gnum > 1000 || gden > 1000) return -1;
+    if (check_problem(P) || P->params || !pol) return -1;
+    const int32_t gnum = pol->gnum, gden = pol->gden, glow = pol->glow;
+    if (gnum < 0 || gden < 1 || gnum > 1000 || gden > 1000 || glow < 0) return -1;
+    if ((pol->bid_inv || pol->bid_cap) && gnum != 0) return -1;
     for (int64_t t = 0; t < P->T; ++t)
         if (P->qty[t] != 1) return -1;
     for (int w = 0; w < P->N; ++w)
@@ -713,9 +724,13 @@ static int check_cap(const orc_problem *P, const int32_t *cap0, int32_t gnum, in
  * gnum = 0: greedy, the feasible node of least cost[w][region], lowest index on ties.
  * gnum > 0: the capacity-dependent policy of the appendix's ablation, gamma = gnum/gden:
  * node w's rank in the region's (cost, index) order, rank_r(w) in 0..N-1, is worsened by
- * gamma (N-1) (1 - c_w / M), M the largest remaining capacity of any node, so the node
- * with the most capacity left can rise up to gamma (N-1) places.  Compared exactly as
- *   gden rank_r(w) M + gnum (N-1) (M - c_w)   (both sides times gden M > 0),
+ * a shadow price gamma (N-1) p_w, in one of two readings:
+ *   glow = 0: p_w = 1 - c_w / M, M the largest remaining capacity of any node, so the
+ *     node with the most capacity left can rise up to gamma (N-1) places;
+ *   glow > 0: p_w = max(0, glow - c_w) / glow, only nodes with less than glow capacity
+ *     left pay a price, rising to gamma (N-1) as they empty.
+ * Compared exactly, with M = glow in the second reading, as
+ *   gden rank_r(w) M + gnum (N-1) M p_w   (both sides times gden M > 0),
  * least first, lowest index on ties; lost sale iff no node is feasible. */
 static int32_t rank_in_region(const orc_problem *P, int r, int w)
 {
@@ -741,10 +756,24 @@ static int32_t *rank_table(const orc_problem *P, int32_t gnum)
 }
 
 static int32_t greedy_cap(const orc_problem *P, int64_t t, const int32_t *x, const int32_t *c,
-                          int32_t gnum, int32_t gden, const int32_t *rk)
+                          const orc_cap_policy *pol, const int32_t *rk)
 {
     const int R = P->R, r = P->region[t];
+    const int32_t gnum = pol->gnum, gden = pol->gden, glow = pol->glow;
     int32_t best = LOST;
+    if (pol->bid_inv || pol->bid_cap) {
+        /* bid prices: the least cost plus the prices of the unit of stock and of capacity
+         * the order would use (the dual policy of Section 4.2 with fixed prices) */
+        const int32_t *bi = pol->bid_inv ? pol->bid_inv + (int64_t)P->sku[t] * P->N : NULL;
+        int64_t best_s = 0;
+        for (int w = 0; w < P->N; ++w) {
+            if (x[w] <= 0 || c[w] <= 0) continue;
+            const int64_t sc = (int64_t)P->cost[w * R + r] + (bi ? bi[w] : 0) +
+                               (pol->bid_cap ? pol->bid_cap[w] : 0);
+            if (best == LOST || sc < best_s) { best = w; best_s = sc; }
+        }
+        return best;
+    }
     if (gnum == 0) {
         int32_t best_cost = 0;
         for (int w = 0; w < P->N; ++w) {
@@ -754,14 +783,16 @@ static int32_t greedy_cap(const orc_problem *P, int64_t t, const int32_t *x, con
         }
         return best;
     }
-    int64_t M = 0;
-    for (int w = 0; w < P->N; ++w)
-        if (c[w] > M) M = c[w];
+    int64_t M = glow;
+    if (glow == 0)
+        for (int w = 0; w < P->N; ++w)
+            if (c[w] > M) M = c[w];
     int64_t best_s = 0;
     for (int w = 0; w < P->N; ++w) {
         if (x[w] <= 0 || c[w] <= 0) continue;
+        const int64_t price = glow == 0 ? M - c[w] : (c[w] < glow ? (int64_t)glow - c[w] : 0);
         const int64_t sc = (int64_t)gden * rk[(int64_t)r * P->N + w] * M +
-                           (int64_t)gnum * (P->N - 1) * (M - c[w]);
+                           (int64_t)gnum * (P->N - 1) * price;
         if (best == LOST || sc < best_s) { best = w; best_s = sc; }
     }
     return best;
@@ -778,8 +809,8 @@ static void transition_cap(int32_t *x, int32_t *c, int32_t a)
 /* One process's view of the horizon with capacity: as process_view, with the state
  * (x, c) starting at (x0, cap0); a given action is replaced by the lost sale when its
  * node has no stock of the SKU or no capacity left in the view.  x: K*N scratch, c: N. */
-static void process_view_cap(const orc_problem *P, const int32_t *cap0, int32_t gnum,
-                             int32_t gden, const int32_t *rk, const int64_t *owner,
+static void process_view_cap(const orc_problem *P, const int32_t *cap0,
+                             const orc_cap_policy *pol, const int32_t *rk, const int64_t *owner,
                              int64_t self, const int32_t *given, int32_t *decided, int32_t *x,
                              int32_t *c)
 {
@@ -790,7 +821,7 @@ static void process_view_cap(const orc_problem *P, const int32_t *cap0, int32_t 
         int32_t *xk = x + (int64_t)P->sku[t] * N;
         int32_t a;
         if (!owner || owner[t] == self) {
-            a = greedy_cap(P, t, xk, c, gnum, gden, rk);
+            a = greedy_cap(P, t, xk, c, pol, rk);
             decided[t] = a;
         } else {
             a = given[t];
@@ -802,17 +833,17 @@ static void process_view_cap(const orc_problem *P, const int32_t *cap0, int32_t 
 
 /* Serial rollout with capacity (the answer Picard must reach): the view of a process
  * that owns every order. */
-int orc_serial_cap(const orc_problem *P, const int32_t *cap0, int32_t gnum, int32_t gden,
+int orc_serial_cap(const orc_problem *P, const int32_t *cap0, const orc_cap_policy *pol,
                    int32_t *actions, int32_t *final_inv, int32_t *final_cap)
 {
-    if (check_cap(P, cap0, gnum, gden)) return -1;
+    if (check_cap(P, cap0, pol)) return -1;
     const int N = P->N;
-    int32_t *rk = rank_table(P, gnum);
-    if (gnum && !rk) return -1;
+    int32_t *rk = rank_table(P, pol->gnum);
+    if (pol->gnum && !rk) return -1;
     int32_t *x = (int32_t *)malloc(sizeof(int32_t) * (size_t)P->K * N);
     int32_t *c = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
     if (!x || !c) { free(x); free(c); free(rk); return -1; }
-    process_view_cap(P, cap0, gnum, gden, rk, NULL, 0, NULL, actions, x, c);
+    process_view_cap(P, cap0, pol, rk, NULL, 0, NULL, actions, x, c);
     if (final_inv) memcpy(final_inv, x, sizeof(int32_t) * (size_t)P->K * N);
     if (final_cap) memcpy(final_cap, c, sizeof(int32_t) * (size_t)N);
     free(x);
@@ -826,7 +857,7 @@ int orc_serial_cap(const orc_problem *P, const int32_t *cap0, int32_t gnum, int3
 typedef struct {
     const orc_problem *P;
     const int32_t *cap0, *rk;
-    int32_t gnum, gden;
+    const orc_cap_policy *pol;
     const int64_t *worker;
     int64_t n_workers;
     int32_t *x, *c;
@@ -836,24 +867,24 @@ static void alg1_cap_pass(void *vctx, const int32_t *prev, int32_t *next)
 {
     const alg1_cap_ctx *q = (const alg1_cap_ctx *)vctx;
     for (int64_t proc = 0; proc < q->n_workers; ++proc)
-        process_view_cap(q->P, q->cap0, q->gnum, q->gden, q->rk, q->worker, proc, prev, next,
-                         q->x, q->c);
+        process_view_cap(q->P, q->cap0, q->pol, q->rk, q->worker, proc, prev, next, q->x,
+                         q->c);
 }
 
-int orc_alg1_cap(const orc_problem *P, const int32_t *cap0, int32_t gnum, int32_t gden,
+int orc_alg1_cap(const orc_problem *P, const int32_t *cap0, const orc_cap_policy *pol,
                  const int64_t *worker, int64_t n_workers, const int32_t *init_cache,
                  int32_t max_passes, int32_t *final_cache, int32_t *passes, int32_t *caches)
 {
-    if (check_cap(P, cap0, gnum, gden) || n_workers <= 0 || max_passes <= 0) return -1;
+    if (check_cap(P, cap0, pol) || n_workers <= 0 || max_passes <= 0) return -1;
     const int N = P->N;
     for (int64_t t = 0; t < P->T; ++t)
         if (worker[t] < 0 || worker[t] >= n_workers) return -1;
-    int32_t *rk = rank_table(P, gnum);
-    if (gnum && !rk) return -1;
+    int32_t *rk = rank_table(P, pol->gnum);
+    if (pol->gnum && !rk) return -1;
     int32_t *x = (int32_t *)malloc(sizeof(int32_t) * (size_t)P->K * N);
     int32_t *c = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
     if (!x || !c) { free(x); free(c); free(rk); return -1; }
-    alg1_cap_ctx ctx = {P, cap0, rk, gnum, gden, worker, n_workers, x, c};
+    alg1_cap_ctx ctx = {P, cap0, rk, pol, worker, n_workers, x, c};
     const int rc = run_passes(alg1_cap_pass, &ctx, P->T, init_cache, max_passes, final_cache,
                               passes, NULL, caches);
     free(x); free(c); free(rk);
@@ -873,7 +904,7 @@ int orc_alg1_cap(const orc_problem *P, const int32_t *cap0, int32_t gnum, int32_
 typedef struct {
     const orc_problem *P;
     const int32_t *cap0, *rk;
-    int32_t gnum, gden;
+    const orc_cap_policy *pol;
     int64_t B;
     int32_t *x, *xp, *c, *cp; /* shared replay, private rows, shared and private capacities */
     int64_t *stamp;           /* block that last copied a SKU's row into xp */
@@ -900,7 +931,7 @@ static void timeblocks_cap_pass(void *vctx, const int32_t *prev, int32_t *next)
                 memcpy(xk, x + s * N, sizeof(int32_t) * (size_t)N);
                 q->stamp[s] = m;
             }
-            const int32_t a = greedy_cap(P, t, xk, cp, q->gnum, q->gden, q->rk);
+            const int32_t a = greedy_cap(P, t, xk, cp, q->pol, q->rk);
             transition_cap(xk, cp, a);
             next[t] = a;
         }
@@ -914,15 +945,15 @@ static void timeblocks_cap_pass(void *vctx, const int32_t *prev, int32_t *next)
     }
 }
 
-int orc_picard_timeblocks_cap(const orc_problem *P, const int32_t *cap0, int32_t gnum,
-                              int32_t gden, int64_t B, const int32_t *init_cache,
+int orc_picard_timeblocks_cap(const orc_problem *P, const int32_t *cap0,
+                              const orc_cap_policy *pol, int64_t B, const int32_t *init_cache,
                               int32_t max_passes, int32_t *final_cache, int32_t *passes,
                               int64_t *changed, int32_t *caches)
 {
-    if (check_cap(P, cap0, gnum, gden) || B <= 0 || max_passes <= 0) return -1;
+    if (check_cap(P, cap0, pol) || B <= 0 || max_passes <= 0) return -1;
     const int N = P->N, K = P->K;
-    int32_t *rk = rank_table(P, gnum);
-    if (gnum && !rk) return -1;
+    int32_t *rk = rank_table(P, pol->gnum);
+    if (pol->gnum && !rk) return -1;
     const int64_t KN = (int64_t)K * N;
     int32_t *x = (int32_t *)malloc(sizeof(int32_t) * (size_t)KN);
     int32_t *xp = (int32_t *)malloc(sizeof(int32_t) * (size_t)KN);
@@ -931,7 +962,7 @@ int orc_picard_timeblocks_cap(const orc_problem *P, const int32_t *cap0, int32_t
     int32_t *cp = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
     int rc = -1;
     if (x && xp && stamp && c && cp) {
-        blocks_cap_ctx ctx = {P, cap0, rk, gnum, gden, B, x, xp, c, cp, stamp};
+        blocks_cap_ctx ctx = {P, cap0, rk, pol, B, x, xp, c, cp, stamp};
         rc = run_passes(timeblocks_cap_pass, &ctx, P->T, init_cache, max_passes, final_cache,
                         passes, changed, caches);
     }

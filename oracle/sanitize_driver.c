@@ -52,13 +52,17 @@ int orc_picard_runs(const orc_problem *P, const int64_t *worker, const int32_t *
 int orc_reinforce(const orc_problem *P, const int32_t *actions, const double *adv,
                   double *logp, double *grad, double *objective);
 int orc_mlp_scores(const orc_problem *P, int32_t r, const int32_t *x, double *s);
-int orc_serial_cap(const orc_problem *P, const int32_t *cap0, int32_t gnum, int32_t gden,
+typedef struct {
+    int32_t gnum, gden, glow;
+    const int32_t *bid_inv, *bid_cap;
+} orc_cap_policy;
+int orc_serial_cap(const orc_problem *P, const int32_t *cap0, const orc_cap_policy *pol,
                    int32_t *actions, int32_t *final_inv, int32_t *final_cap);
-int orc_alg1_cap(const orc_problem *P, const int32_t *cap0, int32_t gnum, int32_t gden,
+int orc_alg1_cap(const orc_problem *P, const int32_t *cap0, const orc_cap_policy *pol,
                  const int64_t *worker, int64_t n_workers, const int32_t *init_cache,
                  int32_t max_passes, int32_t *final_cache, int32_t *passes, int32_t *caches);
-int orc_picard_timeblocks_cap(const orc_problem *P, const int32_t *cap0, int32_t gnum,
-                              int32_t gden, int64_t B, const int32_t *init_cache,
+int orc_picard_timeblocks_cap(const orc_problem *P, const int32_t *cap0,
+                              const orc_cap_policy *pol, int64_t B, const int32_t *init_cache,
                               int32_t max_passes, int32_t *final_cache, int32_t *passes,
                               int64_t *changed, int32_t *caches);
 
@@ -172,19 +176,25 @@ int main(void)
             int32_t *cap0 = malloc(sizeof(int32_t) * N), *fcap = malloc(sizeof(int32_t) * N);
             for (int w = 0; w < N; ++w) cap0[w] = uni(0, 6);
             const int32_t gnum = ci % 2 ? uni(1, 3) : 0, gden = uni(1, 2);
-            CHECK(orc_serial_cap(&P, cap0, gnum, gden, act, fin, fcap) == 0, "orc_serial_cap");
+            const int32_t glow = ci % 3 == 1 ? uni(1, 4) : 0;
+            int32_t *bi = malloc(sizeof(int32_t) * K * N), *bc = malloc(sizeof(int32_t) * N);
+            for (int64_t i = 0; i < (int64_t)K * N; ++i) bi[i] = uni(0, 4) - 2;
+            for (int w = 0; w < N; ++w) bc[w] = uni(0, 3);
+            const int bid = !gnum && ci % 5 == 2;
+            const orc_cap_policy pol = {gnum, gden, glow, bid ? bi : NULL, bid ? bc : NULL};
+            CHECK(orc_serial_cap(&P, cap0, &pol, act, fin, fcap) == 0, "orc_serial_cap");
             int32_t p1 = 0, p2 = 0;
             const int64_t B = uni(1, 7);
             for (int64_t t = 0; t < T; ++t) worker[t] = t / B;
             const int64_t nb = T > 0 ? (T + B - 1) / B : 1;
             const int32_t *ic = ci % 4 == 3 ? init : NULL;
-            const int r1 = orc_alg1_cap(&P, cap0, gnum, gden, worker, nb, ic, MAXP, fc, &p1, caches);
-            const int r2 = orc_picard_timeblocks_cap(&P, cap0, gnum, gden, B, ic, MAXP, fc2, &p2,
+            const int r1 = orc_alg1_cap(&P, cap0, &pol, worker, nb, ic, MAXP, fc, &p1, caches);
+            const int r2 = orc_picard_timeblocks_cap(&P, cap0, &pol, B, ic, MAXP, fc2, &p2,
                                                      changed, caches2);
             CHECK(r1 == r2 && p1 == p2, "alg1_cap and the time-block replay agree");
             CHECK(memcmp(caches, caches2, sizeof(int32_t) * T * p1) == 0, "per-pass caches (cap)");
             if (r1 == 0) CHECK(memcmp(fc, act, sizeof(int32_t) * T) == 0, "cap fixed point is serial");
-            free(cap0); free(fcap);
+            free(cap0); free(fcap); free(bi); free(bc);
         }
         uint32_t c[4] = {rnd(), rnd(), rnd(), rnd()}, k[2] = {rnd(), rnd()}, o[4];
         orc_philox4x32_10(c, k, o);

@@ -60,6 +60,11 @@ class pk_picard_opts(C.Structure):
                 ("walk_waves", C.c_int32), ("lane_max", C.c_int32)]
 
 
+class pk_cap_policy(C.Structure):
+    _fields_ = [("gamma_num", C.c_int32), ("gamma_den", C.c_int32), ("gamma_low", C.c_int32),
+                ("reserved", C.c_int32), ("bid_inv", C.c_void_p), ("bid_cap", C.c_void_p)]
+
+
 class pk_stats(C.Structure):
     _fields_ = [("passes", C.c_void_p), ("passes_max", C.c_int32), ("block_len", C.c_int32),
                 ("changed_total", C.c_int64), ("runs_walked", C.c_int64),
@@ -95,9 +100,10 @@ def lib():
         f64 = C.c_double
         L.pk_adam_step.argtypes = [vp, vp, vp, vp, C.c_int64, i32, f64, f64, f64, f64, i32, vp]
         L.pk_capacity_workspace_size.argtypes = [P, vp, i32, C.POINTER(sz)]
-        L.pk_serial_simulate_capacity.argtypes = [P, vp, i32, i32, vp, sz, vp, vp, vp, vp]
-        L.pk_picard_simulate_capacity.argtypes = [P, vp, i32, i32, i32, i32, vp, vp, sz, vp, vp,
-                                                  vp, C.POINTER(i32), vp, vp, vp]
+        CP = C.POINTER(pk_cap_policy)
+        L.pk_serial_simulate_capacity.argtypes = [P, vp, CP, vp, sz, vp, vp, vp, vp]
+        L.pk_picard_simulate_capacity.argtypes = [P, vp, CP, i32, i32, vp, vp, sz, vp, vp, vp,
+                                                  C.POINTER(i32), vp, vp, vp]
         for f in ("pk_workspace_size", "pk_serial_simulate", "pk_picard_simulate",
                   "pk_picard_simulate_noalloc",
                   "pk_policy_grad", "pk_autotune", "pk_policy_scores",
@@ -370,33 +376,58 @@ def _cap_tensor(prob: DeviceProblem, capacity) -> torch.Tensor:
     return c
 
 
+def _cap_policy(prob: DeviceProblem, gamma, bids):
+    """pk_cap_policy from gamma = (num, den) or (num, den, low) and bids = None or
+    (bid_inv [K][N] or None, bid_cap [N] or None); returns it with the device arrays it
+    points at (kept alive by the caller)."""
+    dev = prob.sku.device
+    keep = []
+    ptrs = [None, None]
+    if bids is not None:
+        for i, (b, shape) in enumerate(zip(bids, ((prob.K, prob.N), (prob.N,)))):
+            if b is None:
+                continue
+            t = torch.as_tensor(b).to(device=dev, dtype=torch.int32).contiguous()
+            if tuple(t.shape) != shape:
+                raise ValueError(f"bid prices must have shape {shape}, got {tuple(t.shape)}")
+            keep.append(t)
+            ptrs[i] = t.data_ptr()
+    pol = pk_cap_policy(int(gamma[0]), int(gamma[1]), int(gamma[2]) if len(gamma) > 2 else 0, 0,
+                        ptrs[0], ptrs[1])
+    return pol, keep
+
+
 def pk_serial_simulate_capacity(prob: DeviceProblem, capacity, want_final=True,
-                                gamma=(0, 1), stream=None) -> dict:
+                                gamma=(0, 1), bids=None, stream=None) -> dict:
     """Serial sweep with node capacities (one order at a time on the GPU); gamma = (num,
-    den): 0 for the greedy policy, else the capacity-dependent policy."""
+    den) or (num, den, low): num 0 for the greedy policy, else the capacity-dependent
+    policy, priced relative to the most capacity left (low 0) or only below low;
+    bids = (bid_inv [K][N] or None, bid_cap [N] or None): the bid-price policy (num 0)."""
     dev = prob.sku.device
     cap = _cap_tensor(prob, capacity)
+    pol, keep = _cap_policy(prob, gamma, bids)
     p = prob.c_problem()
     ws = workspace(pk_capacity_workspace_size(prob, cap), dev)
     actions = torch.empty(prob.total, dtype=torch.int32, device=dev)
     final = torch.empty_like(prob.init_inv) if want_final else None
     fcap = torch.empty(prob.N, dtype=torch.int32, device=dev) if want_final else None
-    _check(lib().pk_serial_simulate_capacity(C.byref(p), _ptr(cap), int(gamma[0]),
-                                             int(gamma[1]), _ptr(ws), ws.numel(),
-                                             _ptr(actions), _ptr(final), _ptr(fcap),
+    _check(lib().pk_serial_simulate_capacity(C.byref(p), _ptr(cap), C.byref(pol), _ptr(ws),
+                                             ws.numel(), _ptr(actions), _ptr(final), _ptr(fcap),
                                              _stream(stream)))
+    del keep
     return dict(actions=actions, final_inv=final, final_cap=fcap)
 
 
 def pk_picard_simulate_capacity(prob: DeviceProblem, capacity, block_len: int = 0,
                                 max_passes: int = 0,
                                 init_cache: Optional[torch.Tensor] = None,
-                                want_final=True, record=False, gamma=(0, 1), stream=None,
-                                raise_not_converged=True) -> dict:
+                                want_final=True, record=False, gamma=(0, 1), bids=None,
+                                stream=None, raise_not_converged=True) -> dict:
     """Algorithm 1 with node capacities; processes are blocks of consecutive orders;
-    gamma = (num, den) as for pk_serial_simulate_capacity."""
+    gamma and bids as for pk_serial_simulate_capacity."""
     dev = prob.sku.device
     cap = _cap_tensor(prob, capacity)
+    pol, keep = _cap_policy(prob, gamma, bids)
     p = prob.c_problem()
     T = prob.total
     mp = max_passes if max_passes > 0 else T + 1
@@ -408,10 +439,10 @@ def pk_picard_simulate_capacity(prob: DeviceProblem, capacity, block_len: int = 
     changed = np.zeros(mp, dtype=np.int64)
     passes = C.c_int32(0)
     status = lib().pk_picard_simulate_capacity(
-        C.byref(p), _ptr(cap), int(gamma[0]), int(gamma[1]), int(block_len), int(max_passes),
-        _ptr(init_cache), _ptr(ws),
-        ws.numel(), _ptr(actions), _ptr(final), _ptr(fcap), C.byref(passes),
-        changed.ctypes.data, _ptr(caches), _stream(stream))
+        C.byref(p), _ptr(cap), C.byref(pol), int(block_len), int(max_passes),
+        _ptr(init_cache), _ptr(ws), ws.numel(), _ptr(actions), _ptr(final), _ptr(fcap),
+        C.byref(passes), changed.ctypes.data, _ptr(caches), _stream(stream))
+    del keep
     if status != PK_OK and not (status == PK_ERR_NOT_CONVERGED and not raise_not_converged):
         _check(status)
     k = int(passes.value)

@@ -1008,6 +1008,7 @@ size_t carve_owmr(char *base, const OwmrDev &P, OwmrWs *w)
 }
 
 // ---------------------------------------------------------------- node capacity
+static_assert(sizeof(pk_cap_policy) == 32, "pk_cap_policy layout");
 constexpr int DEFAULT_BLOCK_CAP = 96; // fastest of 32..255 on the 1e6-order capacity workload
 
 pk_status check_capacity_problem(const pk_problem *pr, const int32_t *capacity, Dims *d)
@@ -1020,11 +1021,29 @@ pk_status check_capacity_problem(const pk_problem *pr, const int32_t *capacity, 
     return PK_OK;
 }
 
-pk_status check_gamma(int32_t num, int32_t den)
+// The policy of a capacity run into the plan (NULL: greedy).
+pk_status set_cap_policy(const pk_cap_policy *p, CapPlan &L)
 {
-    if (num < 0 || num > 1000 || den < 1 || den > 1000)
+    L.pol = CAP_GREEDY;
+    L.gnum = 0;
+    L.gden = 1;
+    L.glow = 0;
+    L.bid_inv = L.bid_cap = nullptr;
+    if (!p) return PK_OK;
+    if (p->gamma_num < 0 || p->gamma_num > 1000 || p->gamma_den < 1 || p->gamma_den > 1000)
         return fail(PK_ERR_INVALID_ARG, "gamma must be num/den with 0 <= num <= 1000, "
-                                        "1 <= den <= 1000 (got %d/%d)", num, den);
+                                        "1 <= den <= 1000 (got %d/%d)", p->gamma_num, p->gamma_den);
+    if (p->gamma_low < 0) return fail(PK_ERR_INVALID_ARG, "gamma_low must be >= 0 (got %d)", p->gamma_low);
+    if (p->reserved != 0) return fail(PK_ERR_INVALID_ARG, "pk_cap_policy.reserved must be 0");
+    const bool bids = p->bid_inv || p->bid_cap;
+    if (bids && p->gamma_num != 0)
+        return fail(PK_ERR_INVALID_ARG, "bid prices take gamma_num = 0");
+    L.gnum = p->gamma_num;
+    L.gden = p->gamma_den;
+    L.glow = p->gamma_low;
+    L.bid_inv = p->bid_inv;
+    L.bid_cap = p->bid_cap;
+    L.pol = bids ? CAP_BID : p->gamma_num > 0 ? CAP_GAMMA : CAP_GREEDY;
     return PK_OK;
 }
 
@@ -1097,7 +1116,8 @@ pk_status cap_errors(const CapCtl &h)
     if (!h.error) return PK_OK;
     return fail(PK_ERR_INVALID_ARG,
                 "invalid input (bits %#x: 1 quantity != 1, 2 SKU, 4 region, 8 negative stock, "
-                "16 negative capacity, 32 cost outside [0, 2^24), 64 initial cache outside [-1, N))",
+                "16 negative capacity, 32 cost outside [0, 2^24), 64 initial cache outside [-1, N), "
+                "128 bid price outside [0, 2^24))",
                 h.error);
 }
 
@@ -1553,7 +1573,7 @@ pk_status pk_capacity_workspace_size(const pk_problem *problem, const int32_t *c
 }
 
 pk_status pk_serial_simulate_capacity(const pk_problem *problem, const int32_t *capacity,
-                                      int32_t gamma_num, int32_t gamma_den, void *ws,
+                                      const pk_cap_policy *policy, void *ws,
                                       size_t ws_bytes, int32_t *actions, int32_t *final_inv,
                                       int32_t *final_cap, void *stream)
 {
@@ -1561,7 +1581,8 @@ pk_status pk_serial_simulate_capacity(const pk_problem *problem, const int32_t *
     Dims d;
     pk_status s = check_capacity_problem(problem, capacity, &d);
     if (s != PK_OK) return s;
-    if ((s = check_gamma(gamma_num, gamma_den)) != PK_OK) return s;
+    CapPlan pol = {};
+    if ((s = set_cap_policy(policy, pol)) != PK_OK) return s;
     if (d.total > 0 && !actions) return fail(PK_ERR_INVALID_ARG, "actions is NULL");
     if (!ws || ws_bytes < carve_cap(nullptr, d, DEFAULT_BLOCK_CAP, false, nullptr))
         return fail(PK_ERR_WORKSPACE, "workspace too small");
@@ -1569,8 +1590,7 @@ pk_status pk_serial_simulate_capacity(const pk_problem *problem, const int32_t *
     CapWs w;
     carve_cap(align_ws(ws), d, DEFAULT_BLOCK_CAP, false, &w);
     cap_bind(w.L, problem, capacity, actions);
-    w.L.gnum = gamma_num;
-    w.L.gden = gamma_den;
+    set_cap_policy(policy, w.L);
     int32_t *state = final_inv ? final_inv : w.state;
     HIP_TRY(cap_check(w.L, nullptr, st));
     CapCtl h;
@@ -1587,8 +1607,7 @@ pk_status pk_serial_simulate_capacity(const pk_problem *problem, const int32_t *
 }
 
 pk_status pk_picard_simulate_capacity(const pk_problem *problem, const int32_t *capacity,
-                                      int32_t gamma_num, int32_t gamma_den,
-                                      int32_t block_len, int32_t max_passes,
+                                      const pk_cap_policy *policy, int32_t block_len, int32_t max_passes,
                                       const int32_t *init_cache, void *ws, size_t ws_bytes,
                                       int32_t *actions, int32_t *final_inv, int32_t *final_cap,
                                       int32_t *passes, int64_t *changed, int32_t *caches,
@@ -1599,7 +1618,8 @@ pk_status pk_picard_simulate_capacity(const pk_problem *problem, const int32_t *
     pk_status s = check_capacity_problem(problem, capacity, &d);
     if (s != PK_OK) return s;
     if (d.total > 0 && !actions) return fail(PK_ERR_INVALID_ARG, "actions is NULL");
-    if ((s = check_gamma(gamma_num, gamma_den)) != PK_OK) return s;
+    CapPlan pol = {};
+    if ((s = set_cap_policy(policy, pol)) != PK_OK) return s;
     if (block_len < 0 || block_len > CAP_MAX_B)
         return fail(PK_ERR_INVALID_ARG, "block_len must lie in [0, %d]", CAP_MAX_B);
     if (max_passes < 0) return fail(PK_ERR_INVALID_ARG, "max_passes must be >= 0");
@@ -1612,8 +1632,7 @@ pk_status pk_picard_simulate_capacity(const pk_problem *problem, const int32_t *
     CapWs w;
     carve_cap(align_ws(ws), d, B, true, &w);
     cap_bind(w.L, problem, capacity, actions);
-    w.L.gnum = gamma_num;
-    w.L.gden = gamma_den;
+    set_cap_policy(policy, w.L);
     HIP_TRY(cap_check(w.L, init_cache, st));
     CapCtl h;
     HIP_TRY(hipMemcpyAsync(&h, w.L.ctl, sizeof h, hipMemcpyDeviceToHost, st));

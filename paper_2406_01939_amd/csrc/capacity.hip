@@ -1,8 +1,8 @@
 // Picard iteration with node capacity (Section 3: the FO state is (x_t, c_t); an order of
 // SKU i may go to node j only while c_{t,j} > 0 and x_{t,i,j} > 0; shipping one unit lowers
-// both).  Unit demand, one trajectory; the greedy policy (least cost, lowest index on ties)
-// or the capacity-dependent policy of the appendix's ablation (cap_choose).  Nothing
-// below but the walk depends on the policy.
+// both).  Unit demand, one trajectory; the greedy policy (least cost, lowest index on ties),
+// the capacity-dependent policy of the appendix's ablation or a bid-price policy
+// (cap_choose).  Nothing below but the key table and the walk depends on the policy.
 //
 // Capacity couples the SKUs, so processes are blocks of B consecutive orders in time.
 // Under Algorithm 1, process m replays the cached actions of every order before its block
@@ -93,33 +93,54 @@ __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v)
 
 // The policy's choice for one order, lane l holding nodes 2l and 2l+1: f0/f1 whether each
 // has stock and capacity, c0/c1 their capacities, kc their entries of the region's row of
-// the key table.
-//  * greedy (GAMMA false): kc = (cost << 8) | w; the least key wins (lowest index on ties);
-//  * capacity-dependent (the appendix's ablation, gamma = gnum / gden): kc = the node's
-//    rank in the region's (cost, index) order; the least
-//      gden rank M + gnum (N-1) (M - c),  M = the largest capacity of any node,
-//    wins, lowest index on ties (rank + gamma (N-1)(1 - c/M) times gden M > 0, in 64 bits).
+// the key table, bi their bid prices of the order's SKU (CAP_BID only).
+//  * CAP_GREEDY: kc = (cost << 8) | w; the least key wins (lowest index on ties);
+//  * CAP_GAMMA (the appendix's ablation, gamma = gnum / gden): kc = the node's rank in the
+//    region's (cost, index) order; the least
+//      gden rank M + gnum (N-1) p(c)
+//    wins, lowest index on ties (rank + gamma (N-1) p(c) / M times gden M > 0, in 64 bits),
+//    with glow = 0: M = the largest capacity of any node and p(c) = M - c; glow > 0:
+//    M = glow and p(c) = max(0, glow - c), a price only near exhaustion;
+//  * CAP_BID (fixed dual prices, Section 4.2's dual policy): kc = cost + bid_cap[w]; the
+//    least kc + bid_inv[sku][w] (below 2^26) wins, lowest index on ties.
 // Returns the node or LOST (wave-uniform).
-template <bool GAMMA>
-__device__ __forceinline__ int cap_choose(uint2 kc, bool f0, bool f1, int c0, int c1, int lane,
-                                          int nm1, int gnum, int gden)
+template <int POL>
+__device__ __forceinline__ int cap_choose(uint2 kc, uint2 bi, bool f0, bool f1, int c0, int c1,
+                                          int lane, int nm1, int gnum, int gden, int glow)
 {
-    if constexpr (!GAMMA) {
+    if constexpr (POL == CAP_GREEDY) {
         const uint32_t ka = f0 ? kc.x : CAP_NONE, kb = f1 ? kc.y : CAP_NONE;
         const uint32_t best = wave_min_u32(ka < kb ? ka : kb);
         return best == CAP_NONE ? LOST : (int)(best & 0xffu);
-    } else {
-        const uint64_t M = wave_max_u32((uint32_t)max(max(c0, c1), 0));
+    } else if constexpr (POL == CAP_BID) {
         const uint64_t none = ~0ull;
-        const uint64_t ka = f0 ? ((((uint64_t)gden * kc.x * M + (uint64_t)gnum * nm1 * (M - (uint64_t)c0)) << 8) |
+        const uint64_t ka = f0 ? (((uint64_t)(kc.x + bi.x) << 8) | (uint64_t)(2 * lane)) : none;
+        const uint64_t kb = f1 ? (((uint64_t)(kc.y + bi.y) << 8) | (uint64_t)(2 * lane + 1)) : none;
+        const uint64_t best = wave_min_u64(ka < kb ? ka : kb);
+        return best == none ? LOST : (int)(best & 0xffu);
+    } else {
+        const uint64_t M = glow > 0 ? (uint64_t)glow : wave_max_u32((uint32_t)max(max(c0, c1), 0));
+        const uint64_t p0 = glow > 0 ? (c0 < glow ? (uint64_t)(glow - c0) : 0ull) : M - (uint64_t)c0;
+        const uint64_t p1 = glow > 0 ? (c1 < glow ? (uint64_t)(glow - c1) : 0ull) : M - (uint64_t)c1;
+        const uint64_t none = ~0ull;
+        const uint64_t ka = f0 ? ((((uint64_t)gden * kc.x * M + (uint64_t)gnum * nm1 * p0) << 8) |
                                   (uint64_t)(2 * lane))
                                : none;
-        const uint64_t kb = f1 ? ((((uint64_t)gden * kc.y * M + (uint64_t)gnum * nm1 * (M - (uint64_t)c1)) << 8) |
+        const uint64_t kb = f1 ? ((((uint64_t)gden * kc.y * M + (uint64_t)gnum * nm1 * p1) << 8) |
                                   (uint64_t)(2 * lane + 1))
                                : none;
         const uint64_t best = wave_min_u64(ka < kb ? ka : kb);
         return best == none ? LOST : (int)(best & 0xffu);
     }
+}
+
+// The bid prices of SKU k's stock at this lane's two nodes (zero without bid_inv).
+__device__ __forceinline__ uint2 bid_row(const CapPlan &L, int k, int lane)
+{
+    if (!L.bid_inv) return make_uint2(0u, 0u);
+    const int32_t *row = L.bid_inv + (int64_t)k * L.N;
+    return make_uint2(2 * lane < L.N ? (uint32_t)row[2 * lane] : 0u,
+                      2 * lane + 1 < L.N ? (uint32_t)row[2 * lane + 1] : 0u);
 }
 
 __device__ __forceinline__ uint8_t clamp255(int v) { return (uint8_t)(v < 0 ? 0 : (v > 255 ? 255 : v)); }
@@ -142,6 +163,12 @@ __global__ void k_cap_check(CapPlan L, int64_t n_x0, const int32_t *init)
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)L.N * L.R;
          i += stride)
         if (L.cost[i] < 0 || L.cost[i] >= (1 << 24)) err |= CAP_ERR_COST;
+    if (L.bid_inv)
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_x0; i += stride)
+            if (L.bid_inv[i] < 0 || L.bid_inv[i] >= (1 << 24)) err |= CAP_ERR_BID;
+    if (L.bid_cap)
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < L.N; i += stride)
+            if (L.bid_cap[i] < 0 || L.bid_cap[i] >= (1 << 24)) err |= CAP_ERR_BID;
     if (err) atomicOr(&L.ctl->error, err);
 }
 
@@ -166,8 +193,9 @@ __global__ void k_cap_seg_bounds(CapPlan L, const int32_t *skey)
     }
 }
 
-// Key table, region-major, one 512-byte row per region: greedy keys (cost << 8) | w, or
-// for the capacity-dependent policy each node's rank in the region's (cost, index) order.
+// Key table, region-major, one 512-byte row per region: greedy keys (cost << 8) | w, for
+// the capacity-dependent policy each node's rank in the region's (cost, index) order, for
+// bid prices cost + bid_cap[w].
 __global__ void k_cap_keytab(CapPlan L)
 {
     const int64_t n = (int64_t)L.R * CAP_NPAD;
@@ -176,8 +204,11 @@ __global__ void k_cap_keytab(CapPlan L)
         const int r = (int)(i / CAP_NPAD), w = (int)(i % CAP_NPAD);
         if (w >= L.N) {
             L.keyT[i] = CAP_NONE;
-        } else if (L.gnum == 0) {
+        } else if (L.pol == CAP_GREEDY) {
             L.keyT[i] = ((uint32_t)L.cost[(int64_t)w * L.R + r] << 8) | (uint32_t)w;
+        } else if (L.pol == CAP_BID) {
+            L.keyT[i] = (uint32_t)L.cost[(int64_t)w * L.R + r] +
+                        (L.bid_cap ? (uint32_t)L.bid_cap[w] : 0u);
         } else { // rank of w in the region's (cost, index) order
             const int32_t cw = L.cost[(int64_t)w * L.R + r];
             uint32_t k = 0;
@@ -520,10 +551,10 @@ __global__ __launch_bounds__(CAP_SCAN_T) void k_cap_scan(CapPlan L)
 // One wave per block: the block's orders in time order with fresh greedy decisions.
 // Lane l holds nodes 2l and 2l+1 (stock bytes as one 16-bit LDS word, capacities and keys
 // in registers).  A lane writes only its own stock word, so steps need no barrier.  The
-// block's regions and stock-row slots sit in registers (order j in lane j % 64 of
-// register j / 64) and are read with readlane; each region's keys are loaded four orders
-// ahead.
-template <bool GAMMA>
+// block's regions and stock-row slots (and SKUs, for bid prices) sit in registers (order j
+// in lane j % 64 of register j / 64) and are read with readlane; each order's keys (and
+// bid prices) are loaded four orders ahead.
+template <int POL>
 __global__ __launch_bounds__(64) void k_cap_walk(CapPlan L)
 {
     extern __shared__ __align__(16) unsigned char cap_smem[];
@@ -537,14 +568,16 @@ __global__ __launch_bounds__(64) void k_cap_walk(CapPlan L)
     int32_t *sd = (int32_t *)(cap_smem + (size_t)D * CAP_NPAD); // [D] row of X per slot
     int32_t *out = sd + D;                                       // [B]
     int rg[4], sv[4]; // regions and slots of orders lane, 64 + lane, 128 + lane, 192 + lane
+    int sk[4];        // their SKUs (bid prices only)
     int nd = 0;       // distinct SKUs of this block
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int j = q * WAVE + lane;
-        rg[q] = sv[q] = 0;
+        rg[q] = sv[q] = sk[q] = 0;
         if (j < n) {
             rg[q] = L.region[lo + j];
             sv[q] = L.slot[lo + j];
+            if constexpr (POL == CAP_BID) sk[q] = L.sku[lo + j];
             if (L.first[lo + j]) {
                 sd[sv[q]] = L.sid[lo + j];
                 ++nd;
@@ -588,11 +621,11 @@ __global__ __launch_bounds__(64) void k_cap_walk(CapPlan L)
         return __builtin_amdgcn_readlane(v, l);
     };
     // one step: least key among this lane's nodes with stock and capacity, then the wave's
-    auto step = [&](int jj, uint2 kc) {
+    auto step = [&](int jj, uint2 kc, uint2 bi) {
         const int s = lane_val(sv, jj);
         uint32_t xv = rows[s * WAVE + lane];
-        const int a = cap_choose<GAMMA>(kc, (xv & 0xffu) && c0 > 0, (xv >> 8) && c1 > 0, c0, c1,
-                                        lane, L.N - 1, L.gnum, L.gden);
+        const int a = cap_choose<POL>(kc, bi, (xv & 0xffu) && c0 > 0, (xv >> 8) && c1 > 0, c0,
+                                      c1, lane, L.N - 1, L.gnum, L.gden, L.glow);
         if (a >= 0 && (a >> 1) == lane) {
             if (a & 1) { --c1; xv -= 0x100u; }
             else { --c0; xv -= 1u; }
@@ -603,16 +636,25 @@ __global__ __launch_bounds__(64) void k_cap_walk(CapPlan L)
     auto keys_at = [&](int jj) {
         return K2[(int64_t)lane_val(rg, jj < n ? jj : n - 1) * WAVE + lane];
     };
+    auto bids_at = [&](int jj) {
+        if constexpr (POL == CAP_BID) return bid_row(L, lane_val(sk, jj < n ? jj : n - 1), lane);
+        else return make_uint2(0u, 0u);
+    };
     uint2 k0 = keys_at(0), k1 = keys_at(1), k2 = keys_at(2), k3 = keys_at(3);
+    uint2 b0 = bids_at(0), b1 = bids_at(1), b2 = bids_at(2), b3 = bids_at(3);
     for (int j = 0; j < n; j += 4) {
-        step(j, k0);
+        step(j, k0, b0);
         k0 = keys_at(j + 4);
-        if (j + 1 < n) step(j + 1, k1);
+        b0 = bids_at(j + 4);
+        if (j + 1 < n) step(j + 1, k1, b1);
         k1 = keys_at(j + 5);
-        if (j + 2 < n) step(j + 2, k2);
+        b1 = bids_at(j + 5);
+        if (j + 2 < n) step(j + 2, k2, b2);
         k2 = keys_at(j + 6);
-        if (j + 3 < n) step(j + 3, k3);
+        b2 = bids_at(j + 6);
+        if (j + 3 < n) step(j + 3, k3, b3);
         k3 = keys_at(j + 7);
+        b3 = bids_at(j + 7);
     }
     __syncthreads();
     int nch = 0;
@@ -721,7 +763,7 @@ __global__ void k_cap_final_cap(const int32_t *cap0, const int32_t *used, int N,
 // order; stock rows in global memory (`state`, a copy of x0), capacities in registers.
 // The next order's stock row and keys are loaded while the current order is decided; if
 // both orders share the SKU, the loaded row is corrected by the current order's unit.
-template <bool GAMMA>
+template <int POL>
 __global__ __launch_bounds__(64) void k_cap_serial(CapPlan L, int32_t *state, int32_t *actions)
 {
     const int lane = threadIdx.x, N = L.N;
@@ -736,6 +778,8 @@ __global__ __launch_bounds__(64) void k_cap_serial(CapPlan L, int32_t *state, in
     int k = uni(__shfl(csk, 0, WAVE)), r = uni(__shfl(crg, 0, WAVE));
     int xa = w0 < N ? state[(int64_t)k * N + w0] : 0, xb = w1 < N ? state[(int64_t)k * N + w1] : 0;
     uint2 kc = K2[(int64_t)r * WAVE + lane];
+    uint2 bi = make_uint2(0u, 0u);
+    if constexpr (POL == CAP_BID) bi = bid_row(L, k, lane);
     int abuf = LOST;
     for (int t = 0; t < T; ++t) {
         const int tn = t + 1;
@@ -748,16 +792,17 @@ __global__ __launch_bounds__(64) void k_cap_serial(CapPlan L, int32_t *state, in
         }
         int kn = k, rn = r;
         int xna = 0, xnb = 0;
-        uint2 kn2 = kc;
+        uint2 kn2 = kc, bn = bi;
         if (tn < T) {
             kn = uni(__shfl(csk, tn & (WAVE - 1), WAVE));
             rn = uni(__shfl(crg, tn & (WAVE - 1), WAVE));
             xna = w0 < N ? state[(int64_t)kn * N + w0] : 0;
             xnb = w1 < N ? state[(int64_t)kn * N + w1] : 0;
             kn2 = K2[(int64_t)rn * WAVE + lane];
+            if constexpr (POL == CAP_BID) bn = bid_row(L, kn, lane);
         }
-        const int a = cap_choose<GAMMA>(kc, xa > 0 && c0 > 0, xb > 0 && c1 > 0, c0, c1, lane,
-                                        N - 1, L.gnum, L.gden);
+        const int a = cap_choose<POL>(kc, bi, xa > 0 && c0 > 0, xb > 0 && c1 > 0, c0, c1, lane,
+                                      N - 1, L.gnum, L.gden, L.glow);
         if (a >= 0 && (a >> 1) == lane) {
             if (a & 1) {
                 --c1;
@@ -779,6 +824,7 @@ __global__ __launch_bounds__(64) void k_cap_serial(CapPlan L, int32_t *state, in
         xa = xna;
         xb = xnb;
         kc = kn2;
+        bi = bn;
     }
 }
 
@@ -861,12 +907,13 @@ hipError_t cap_pass(const CapPlan &L, bool first, hipStream_t st)
     hipLaunchKernelGGL(k_cap_entry, dim3(gp), dim3(256), 0, st, L);
     hipLaunchKernelGGL(k_cap_hist, dim3((unsigned)((L.nblk + 3) / 4)), dim3(256), 0, st, L);
     hipLaunchKernelGGL(k_cap_scan, dim3(L.N), dim3(CAP_SCAN_T), 0, st, L);
-    if (L.gnum == 0)
-        hipLaunchKernelGGL(k_cap_walk<false>, dim3(L.nblk), dim3(64), cap_walk_lds(L.B, L.dmax),
-                           st, L);
+    const size_t lds = cap_walk_lds(L.B, L.dmax);
+    if (L.pol == CAP_GREEDY)
+        hipLaunchKernelGGL(k_cap_walk<CAP_GREEDY>, dim3(L.nblk), dim3(64), lds, st, L);
+    else if (L.pol == CAP_GAMMA)
+        hipLaunchKernelGGL(k_cap_walk<CAP_GAMMA>, dim3(L.nblk), dim3(64), lds, st, L);
     else
-        hipLaunchKernelGGL(k_cap_walk<true>, dim3(L.nblk), dim3(64), cap_walk_lds(L.B, L.dmax),
-                           st, L);
+        hipLaunchKernelGGL(k_cap_walk<CAP_BID>, dim3(L.nblk), dim3(64), lds, st, L);
     return hipGetLastError();
 }
 
@@ -900,10 +947,12 @@ hipError_t cap_serial_setup(CapPlan &L, hipStream_t st)
 
 hipError_t cap_serial(const CapPlan &L, int32_t *state, int32_t *actions, hipStream_t st)
 {
-    if (L.gnum == 0)
-        hipLaunchKernelGGL(k_cap_serial<false>, dim3(1), dim3(64), 0, st, L, state, actions);
+    if (L.pol == CAP_GREEDY)
+        hipLaunchKernelGGL(k_cap_serial<CAP_GREEDY>, dim3(1), dim3(64), 0, st, L, state, actions);
+    else if (L.pol == CAP_GAMMA)
+        hipLaunchKernelGGL(k_cap_serial<CAP_GAMMA>, dim3(1), dim3(64), 0, st, L, state, actions);
     else
-        hipLaunchKernelGGL(k_cap_serial<true>, dim3(1), dim3(64), 0, st, L, state, actions);
+        hipLaunchKernelGGL(k_cap_serial<CAP_BID>, dim3(1), dim3(64), 0, st, L, state, actions);
     return hipGetLastError();
 }
 

@@ -277,7 +277,9 @@ constexpr uint32_t CAP_NONE = 0xffffffffu;
 
 // error bits of CapCtl::error
 constexpr int32_t CAP_ERR_QTY = 1, CAP_ERR_SKU = 2, CAP_ERR_REGION = 4, CAP_ERR_X0 = 8,
-                  CAP_ERR_CAP = 16, CAP_ERR_COST = 32, CAP_ERR_INIT = 64;
+                  CAP_ERR_CAP = 16, CAP_ERR_COST = 32, CAP_ERR_INIT = 64, CAP_ERR_BID = 128;
+// Capacity policies (the walk's template argument)
+constexpr int CAP_GREEDY = 0, CAP_GAMMA = 1, CAP_BID = 2;
 
 struct CapCtl {
     int32_t error;
@@ -291,7 +293,12 @@ struct CapCtl {
 struct CapPlan {
     int32_t T, N, K, R, B, nblk;
     int32_t gnum, gden;  // policy: 0 = greedy, else capacity-dependent, gamma = gnum / gden
+    int32_t glow;        // capacity-dependent: 0 = price relative to the most capacity left,
+                         // else only nodes with less than glow left pay a price
     int32_t dmax;        // stock rows per block in the walk's LDS (CapCtl::max_distinct)
+    int32_t pol;         // CAP_GREEDY, CAP_GAMMA or CAP_BID
+    const int32_t *bid_inv; // [K][N] bid prices of stock, nullable (CAP_BID)
+    const int32_t *bid_cap; // [N] bid prices of capacity, nullable (CAP_BID)
     int64_t max_pieces;
     const int32_t *sku, *region, *qty, *x0, *cost, *cap0;
     int32_t *alpha;      // [T] cache, time order (the caller's actions buffer)
@@ -306,7 +313,8 @@ struct CapPlan {
     int32_t *pc;         // [max_pieces][CAP_NPAD] action counts, then their scan
     int32_t *H;          // [N][nblk] passing cached actions per (node, block)
     int32_t *capE;       // [N][nblk] capacity at each block's start
-    uint32_t *keyT;      // [R][CAP_NPAD] (cost << 8) | w (greedy) or rank, all-ones past N
+    uint32_t *keyT;      // [R][CAP_NPAD] (cost << 8) | w (greedy), rank (capacity-dependent)
+                         // or cost + bid_cap[w] (bid prices); all-ones past N
     uint8_t *X;          // [T][CAP_NPAD] stock rows of the (block, SKU) pairs
     uint8_t *P;          // [T] 1 if the order's cached action passes its stock test
     int32_t *skuchg;     // [K] last pass in which an order of the SKU changed its action

@@ -298,6 +298,15 @@ def capacity(N: int, T: int, frac: float = 0.8) -> np.ndarray:
     return np.full(N, int(np.floor(frac * T / N)), dtype=np.int32)
 
 
+def bid_prices(K: int, N: int, seed: int, spread: int = 50):
+    """Fixed dual prices for the bid-price policy with capacity: (bid_inv [K][N], the price
+    of a unit of each SKU's stock at each node; bid_cap [N], the price of a unit of each
+    node's capacity), int32 uniform on 0..spread (costs are 1..100)."""
+    rng = np.random.default_rng(60_000 + seed)
+    return (rng.integers(0, spread + 1, (K, N)).astype(np.int32),
+            rng.integers(0, spread + 1, N).astype(np.int32))
+
+
 def workload_capacity(name: str) -> np.ndarray:
     """The node capacities of a named capacity workload."""
     cfg = WORKLOADS[name]

@@ -38,6 +38,7 @@ def test_struct_layouts():
     assert C.sizeof(api.pk_policy) == 4 * 4 + 8
     assert C.sizeof(api.pk_picard_opts) == 4 * 4 + 8 + 8 + 8 + 8
     assert C.sizeof(api.pk_stats) == 8 + 4 + 4 + 4 * 8 + 8 + 8 + 8 + 8 + 8 + 8 + 8 + 8 + 8
+    assert C.sizeof(api.pk_cap_policy) == 4 * 4 + 8 + 8
 
 
 def test_host_validation_without_gpu():
@@ -108,15 +109,22 @@ def test_capacity_entry_points_validate_on_host():
     p2 = api.pk_problem(4, 2, 3, 2, two.ctypes.data, 1, 1, 1, 1, 1, 0)
     assert L.pk_capacity_workspace_size(C.byref(p2), 1, 0, C.byref(n)) == api.PK_ERR_UNSUPPORTED
     passes = C.c_int32(0)
-    assert L.pk_picard_simulate_capacity(C.byref(p), 1, 0, 1, 0, 0, None, None, 0, 1, None,
-                                         None, C.byref(passes), None, None,
+    CP = api.pk_cap_policy
+    greedy = CP(0, 1, 0, 0, None, None)
+    assert L.pk_picard_simulate_capacity(C.byref(p), 1, C.byref(greedy), 0, 0, None, None, 0, 1,
+                                         None, None, C.byref(passes), None, None,
                                          None) == api.PK_ERR_WORKSPACE
-    assert L.pk_serial_simulate_capacity(C.byref(p), 1, 0, 1, None, 0, 1, None, None,
+    assert L.pk_serial_simulate_capacity(C.byref(p), 1, None, None, 0, 1, None, None,
                                          None) == api.PK_ERR_WORKSPACE
-    # gamma outside its range
-    assert L.pk_serial_simulate_capacity(C.byref(p), 1, 1, 0, None, 0, 1, None, None,
-                                         None) == api.PK_ERR_INVALID_ARG
-    assert L.pk_picard_simulate_capacity(C.byref(p), 1, 1001, 1, 0, 0, None, None, 0, 1, None,
-                                         None, C.byref(passes), None, None,
-                                         None) == api.PK_ERR_INVALID_ARG
-    assert b"gamma" in L.pk_last_error()
+    # policies outside their ranges (checked before the workspace)
+    bad = [(CP(1, 0, 0, 0, None, None), b"gamma"), (CP(1001, 1, 0, 0, None, None), b"gamma"),
+           (CP(1, 1, -1, 0, None, None), b"gamma_low"), (CP(0, 1, 0, 7, None, None), b"reserved"),
+           (CP(1, 1, 0, 0, 1, None), b"bid prices"), (CP(2, 3, 0, 0, None, 1), b"bid prices")]
+    for pol, msg in bad:
+        assert L.pk_serial_simulate_capacity(C.byref(p), 1, C.byref(pol), None, 0, 1, None, None,
+                                             None) == api.PK_ERR_INVALID_ARG
+        assert msg in L.pk_last_error()
+        assert L.pk_picard_simulate_capacity(C.byref(p), 1, C.byref(pol), 0, 0, None, None, 0, 1,
+                                             None, None, C.byref(passes), None, None,
+                                             None) == api.PK_ERR_INVALID_ARG
+        assert msg in L.pk_last_error()

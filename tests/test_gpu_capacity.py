@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 import torch
 
-from paper_2406_01939_amd.instances import (capacity, make_instance, random_tiny,
+from paper_2406_01939_amd.instances import (bid_prices, capacity, make_instance, random_tiny,
                                              workload_capacity)
 
 pytestmark = pytest.mark.gpu
@@ -41,15 +41,16 @@ def _tiny(seed, **kw):
     return inst, cap0
 
 
-def _check_against_oracle(api, oracle, inst, cap0, B, init=None, record=True, gamma=(0, 1)):
+def _check_against_oracle(api, oracle, inst, cap0, B, init=None, record=True, gamma=(0, 1),
+                          bids=None):
     T = int(inst.traj_offsets[-1])
     prob = api.DeviceProblem.from_instance(inst)
-    want = oracle.serial_cap(inst, cap0, gamma=gamma)
+    want = oracle.serial_cap(inst, cap0, gamma=gamma, bids=bids)
     ref = oracle.picard_timeblocks_cap(inst, cap0, B, init_cache=init, record=record,
-                                       gamma=gamma)
+                                       gamma=gamma, bids=bids)
     init_dev = None if init is None else torch.from_numpy(init).cuda()
     out = api.pk_picard_simulate_capacity(prob, cap0, block_len=B, init_cache=init_dev,
-                                          record=record, gamma=gamma)
+                                          record=record, gamma=gamma, bids=bids)
     np.testing.assert_array_equal(out["actions"].cpu().numpy(), want["actions"])
     np.testing.assert_array_equal(out["final_inv"].cpu().numpy()[0], want["final_inv"])
     np.testing.assert_array_equal(out["final_cap"].cpu().numpy(), want["final_cap"])
@@ -57,7 +58,7 @@ def _check_against_oracle(api, oracle, inst, cap0, B, init=None, record=True, ga
     np.testing.assert_array_equal(out["changed"], ref["changed"])
     if record:
         np.testing.assert_array_equal(out["caches"].cpu().numpy(), ref["caches"])
-    ser = api.pk_serial_simulate_capacity(prob, cap0, gamma=gamma)
+    ser = api.pk_serial_simulate_capacity(prob, cap0, gamma=gamma, bids=bids)
     np.testing.assert_array_equal(ser["actions"].cpu().numpy(), want["actions"])
     np.testing.assert_array_equal(ser["final_inv"].cpu().numpy()[0], want["final_inv"])
     np.testing.assert_array_equal(ser["final_cap"].cpu().numpy(), want["final_cap"])
@@ -175,6 +176,86 @@ def test_gamma_workloads(api, oracle, gamma):
     wide = make_instance("greedy_cap_n10_k100_t1e4", N=128, K=3, R=7, T=5003)
     _say(f"capacity gamma={gamma} wide N=128 T=5003 B=97")
     _check_against_oracle(api, oracle, wide, capacity(wide.N, 5003, 0.5), 97, gamma=gamma)
+
+
+@pytest.mark.parametrize("gamma", [(1, 2, 2), (1, 1, 5), (1000, 1, 3)])
+@pytest.mark.parametrize("B", [1, 5, 64])
+@pytest.mark.parametrize("seed", range(3))
+def test_gamma_low_tiny(api, oracle, seed, B, gamma):
+    """The near-exhaustion reading (only nodes with less than `low` capacity left pay a
+    shadow price), every pass."""
+    inst, cap0 = _tiny(seed + 90, N=2 + seed % 5, K=1 + seed % 3, R=1 + seed % 3, T=50,
+                       inv_max=3)
+    _say(f"capacity gamma_low={gamma} seed={seed} B={B}")
+    _check_against_oracle(api, oracle, inst, cap0, B, gamma=gamma)
+
+
+@pytest.mark.parametrize("gamma", [(1, 2), (1, 1), (2, 1)])
+def test_gamma_low_workloads(api, oracle, gamma):
+    """The near-exhaustion reading on the 1e4-order workload (every pass; prices below a
+    fifth of each node's capacity) and on N=128, 5003 orders."""
+    name = "greedy_cap_n10_k100_t1e4"
+    inst = make_instance(name)
+    cap0 = workload_capacity(name)
+    g = gamma + (max(1, int(cap0.max()) // 5),)
+    _say(f"capacity gamma_low={g} workload n10 k100 t1e4 B=100")
+    out = _check_against_oracle(api, oracle, inst, cap0, 100, gamma=g)
+    _say(f"  passes {out['passes']}")
+    wide = make_instance(name, N=128, K=3, R=7, T=5003)
+    wc = capacity(wide.N, 5003, 0.5)
+    _say(f"capacity gamma_low wide N=128 T=5003 B=97")
+    _check_against_oracle(api, oracle, wide, wc, 97, gamma=gamma + (max(1, int(wc.max()) // 5),))
+
+
+@pytest.mark.parametrize("which", ["both", "inv", "cap"])
+@pytest.mark.parametrize("B", [1, 4, 64])
+@pytest.mark.parametrize("seed", range(3))
+def test_bid_prices_tiny(api, oracle, seed, B, which):
+    """The bid-price policy (least cost + price of the unit of stock + price of the unit of
+    capacity), with both price vectors or one of them, every pass."""
+    inst, cap0 = _tiny(seed + 300, N=2 + seed % 5, K=1 + seed % 3, R=1 + seed % 3, T=50,
+                       inv_max=3)
+    bi, bc = bid_prices(inst.K, inst.N, seed, spread=60)
+    bids = (bi if which != "cap" else None, bc if which != "inv" else None)
+    _say(f"capacity bids={which} seed={seed} B={B}")
+    _check_against_oracle(api, oracle, inst, cap0, B, bids=bids)
+
+
+def test_bid_prices_workloads(api, oracle):
+    """The bid-price policy on the 1e4-order workload (every pass) and on N=128, 5003
+    orders; zero prices are the greedy policy."""
+    name = "greedy_cap_n10_k100_t1e4"
+    inst = make_instance(name)
+    cap0 = workload_capacity(name)
+    _say("capacity bids workload n10 k100 t1e4 B=100")
+    out = _check_against_oracle(api, oracle, inst, cap0, 100,
+                                bids=bid_prices(inst.K, inst.N, 1))
+    _say(f"  passes {out['passes']}")
+    wide = make_instance(name, N=128, K=3, R=7, T=5003)
+    wc = capacity(wide.N, 5003, 0.5)
+    _say("capacity bids wide N=128 T=5003 B=97")
+    _check_against_oracle(api, oracle, wide, wc, 97, bids=bid_prices(wide.K, wide.N, 2))
+    prob = api.DeviceProblem.from_instance(inst)
+    z = api.pk_picard_simulate_capacity(prob, cap0, block_len=100,
+                                        bids=(np.zeros((inst.K, inst.N), np.int32),
+                                              np.zeros(inst.N, np.int32)))
+    np.testing.assert_array_equal(z["actions"].cpu().numpy(),
+                                  oracle.serial_cap(inst, cap0)["actions"])
+
+
+def test_bid_prices_rejected(api):
+    """Prices outside [0, 2^24) and bid prices with a capacity-dependent gamma are errors."""
+    inst, cap0 = _tiny(7, N=3, K=2, R=2, T=20)
+    prob = api.DeviceProblem.from_instance(inst)
+    bi, bc = bid_prices(inst.K, inst.N, 0)
+    for bad in ((bi - 100, None), (None, bc + (1 << 24))):
+        _say(f"capacity bids rejected")
+        with pytest.raises(api.PicardError, match=r"bits 0x80:"):
+            api.pk_picard_simulate_capacity(prob, cap0, block_len=4, bids=bad)
+        with pytest.raises(api.PicardError, match=r"bits 0x80:"):
+            api.pk_serial_simulate_capacity(prob, cap0, bids=bad)
+    with pytest.raises(api.PicardError, match="gamma_num = 0"):
+        api.pk_picard_simulate_capacity(prob, cap0, gamma=(1, 2), bids=(bi, bc))
 
 
 @pytest.mark.parametrize("seed", range(3))

@@ -352,3 +352,200 @@ def test_gamma_scale_is_the_largest_capacity_of_any_node(oracle, seed):
     gamma = [(1, 1), (2, 1), (1, 2), (5, 2)][seed % 4]
     r = oracle.serial_cap(inst, cap0, gamma=gamma)
     assert np.array_equal(r["actions"], _brute_gamma(inst, cap0, gamma))
+
+
+# ---------------------------------------------------------------- near-exhaustion reading
+def _brute_gamma_low(inst, cap0, gamma, low):
+    """The second reading of the appendix's capacity-dependent policy, in exact rationals
+    from its description: only nodes with less than `low` capacity left pay a shadow price,
+    rising linearly to gamma (N-1) as they empty; score_w = rank_r(w) + gamma (N-1)
+    max(0, low - c_w) / low, least among nodes with stock and capacity, lowest index on
+    ties."""
+    from fractions import Fraction
+    g = Fraction(*gamma)
+    N = inst.N
+    x = inst.x0[0].astype(np.int64).copy()
+    c = [int(v) for v in cap0]
+    out = []
+    for t in range(int(inst.traj_offsets[-1])):
+        k, r = int(inst.sku[t]), int(inst.region[t])
+        order = sorted(range(N), key=lambda w: (int(inst.cost[0][w, r]), w))
+        rank = {w: i for i, w in enumerate(order)}
+        best, bs = -1, None
+        for w in range(N):
+            if x[k, w] > 0 and c[w] > 0:
+                sc = rank[w] + g * (N - 1) * Fraction(max(0, low - c[w]), low)
+                if bs is None or sc < bs:
+                    best, bs = w, sc
+        out.append(best)
+        if best >= 0:
+            x[k, best] -= 1
+            c[best] -= 1
+    return np.array(out, np.int32)
+
+
+@pytest.mark.parametrize("gamma", [(1, 2), (1, 1), (3, 1), (7, 3)])
+@pytest.mark.parametrize("seed", range(12))
+def test_gamma_low_brute_force(oracle, seed, gamma):
+    inst, cap0 = _tiny(seed, N=2 + seed % 5, K=1 + seed % 3, R=1 + seed % 3, T=24, inv_max=4)
+    low = 1 + seed % 4
+    r = oracle.serial_cap(inst, cap0, gamma=gamma + (low,))
+    assert np.array_equal(r["actions"], _brute_gamma_low(inst, cap0, gamma, low))
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_gamma_low_without_scarce_nodes_is_greedy(oracle, seed):
+    """While no node falls below the threshold no price is charged: with every capacity
+    above `low` plus the horizon the policy is the greedy one, whatever gamma."""
+    inst, cap0 = _tiny(seed, N=2 + seed % 5, K=1 + seed % 3, R=1 + seed % 3, T=24, inv_max=4)
+    T = int(inst.traj_offsets[-1])
+    big = np.full(inst.N, 3 + T, np.int32)
+    g = oracle.serial_cap(inst, big)["actions"]
+    for gamma in ((1, 1), (1000, 1)):
+        assert np.array_equal(oracle.serial_cap(inst, big, gamma=gamma + (3,))["actions"], g)
+
+
+def test_gamma_low_hand_worked(oracle):
+    """Two nodes, one region, node 0 cheaper; low = 4, gamma = 1 (N - 1 = 1): node 0's
+    price is max(0, 4 - c0) / 4.  With c = (2, 9) node 0 scores 0 + 2/4 and node 1 scores
+    1: node 0 ships.  After that c0 = 1, score 3/4 < 1: node 0 again.  Then c0 = 0: node 1.
+    With gamma = 3: node 0 at c0 = 2 scores 6/4 > 1, so node 1 ships from the first order."""
+    inst = random_tiny(1, N=2, K=1, R=1, T=3, qmax=1, inv_max=5)
+    inst.x0[:] = 5
+    inst.cost[:] = np.array([[1], [2]], np.int32)
+    cap0 = np.array([2, 9], np.int32)
+    assert oracle.serial_cap(inst, cap0, gamma=(1, 1, 4))["actions"].tolist() == [0, 0, 1]
+    assert oracle.serial_cap(inst, cap0, gamma=(3, 1, 4))["actions"].tolist() == [1, 1, 1]
+    assert oracle.serial_cap(inst, cap0, gamma=(0, 1, 4))["actions"].tolist() == [0, 0, 1]
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_gamma_low_picard(oracle, seed):
+    """Proposition 2.1 for the near-exhaustion reading, and the time-block replay against
+    the brute-force Algorithm 1 pass by pass."""
+    inst, cap0 = _tiny(seed, N=2 + seed % 5, K=1 + seed % 3, R=1 + seed % 3, T=16, inv_max=3)
+    T = int(inst.traj_offsets[-1])
+    gamma = [(1, 2, 2), (1, 1, 3), (2, 1, 1)][seed % 3]
+    ser = oracle.serial_cap(inst, cap0, gamma=gamma)["actions"]
+    rng = np.random.default_rng(seed)
+    worker = rng.integers(0, 1 + seed % 4, T)
+    r = oracle.alg1_cap(inst, cap0, worker, 1 + seed % 4, gamma=gamma)
+    assert r["converged"] and np.array_equal(r["actions"], ser) and r["passes"] <= T + 1
+    for B in (1, 3, T):
+        lit = oracle.alg1_cap(inst, cap0, oracle.time_block_workers(T, B), (T + B - 1) // B,
+                              gamma=gamma)
+        tb = oracle.picard_timeblocks_cap(inst, cap0, B, record=True, gamma=gamma)
+        assert lit["passes"] == tb["passes"]
+        assert np.array_equal(lit["caches"], tb["caches"])
+
+
+def test_gamma_low_rejects_negative_threshold(oracle):
+    inst, cap0 = _tiny(0, N=3, K=2, R=2, T=10, inv_max=3)
+    with pytest.raises(ValueError):
+        oracle.serial_cap(inst, cap0, gamma=(1, 1, -1))
+
+
+# ---------------------------------------------------------------- bid-price policy
+def _bids(inst, seed, spread=4):
+    rng = np.random.default_rng(50_000 + seed)
+    bi = rng.integers(-spread, spread + 1, (inst.K, inst.N)).astype(np.int32)
+    bc = rng.integers(0, spread + 1, inst.N).astype(np.int32)
+    return bi, bc
+
+
+def _brute_bids(inst, cap0, bi, bc):
+    """The dual policy of Section 4.2 with fixed prices, from its definition: the node
+    maximising r_j - mu_inv(i, j) - mu_cap(j), with reward r_j = -cost[j][region], among the
+    nodes with stock and capacity; lowest index on ties."""
+    N = inst.N
+    x = inst.x0[0].astype(np.int64).copy()
+    c = [int(v) for v in cap0]
+    out = []
+    for t in range(int(inst.traj_offsets[-1])):
+        k, r = int(inst.sku[t]), int(inst.region[t])
+        best, bv = -1, None
+        for w in range(N):
+            if x[k, w] > 0 and c[w] > 0:
+                v = -int(inst.cost[0][w, r]) - int(bi[k, w]) - int(bc[w])
+                if bv is None or v > bv:
+                    best, bv = w, v
+        out.append(best)
+        if best >= 0:
+            x[k, best] -= 1
+            c[best] -= 1
+    return np.array(out, np.int32)
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_bid_price_brute_force(oracle, seed):
+    inst, cap0 = _tiny(seed, N=2 + seed % 5, K=1 + seed % 3, R=1 + seed % 3, T=24, inv_max=4)
+    bi, bc = _bids(inst, seed)
+    r = oracle.serial_cap(inst, cap0, bids=(bi, bc))
+    assert np.array_equal(r["actions"], _brute_bids(inst, cap0, bi, bc))
+    # one of the two price vectors alone
+    r1 = oracle.serial_cap(inst, cap0, bids=(None, bc))
+    assert np.array_equal(r1["actions"], _brute_bids(inst, cap0, 0 * bi, bc))
+    # zero prices are the greedy policy
+    z = oracle.serial_cap(inst, cap0, bids=(0 * bi, 0 * bc))
+    assert np.array_equal(z["actions"], oracle.serial_cap(inst, cap0)["actions"])
+
+
+def test_bid_price_hand_worked(oracle):
+    """Two nodes, costs 1 and 3 in the one region; a capacity price of 5 on node 0 moves
+    orders to node 1 (3 < 1 + 5) until node 1 runs out of capacity (2 units), then node 0."""
+    inst = random_tiny(2, N=2, K=1, R=1, T=4, qmax=1, inv_max=5)
+    inst.x0[:] = 5
+    inst.cost[:] = np.array([[1], [3]], np.int32)
+    cap0 = np.array([9, 2], np.int32)
+    bc = np.array([5, 0], np.int32)
+    assert oracle.serial_cap(inst, cap0, bids=(None, bc))["actions"].tolist() == [1, 1, 0, 0]
+    # a stock price of SKU 0 at node 1: 2 leaves node 1 ahead (3 + 2 = 5 < 1 + 5 = 6), 3
+    # ties it with node 0 (6 = 6: the lower index wins), 4 puts it behind
+    bi = np.array([[0, 2]], np.int32)
+    assert oracle.serial_cap(inst, cap0, bids=(bi, bc))["actions"].tolist() == [1, 1, 0, 0]
+    for p in (3, 4):
+        bi = np.array([[0, p]], np.int32)
+        assert oracle.serial_cap(inst, cap0, bids=(bi, bc))["actions"].tolist() == [0, 0, 0, 0]
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_bid_price_theorem_bound(oracle, seed):
+    """Fixed bid prices keep Assumptions 1-3 (the paper names bid-price policies as the
+    class that meets them), so Theorem 3.1's bound holds: with the product partition,
+    k* <= |Q_T| + 1, Q_T the nodes that run out of capacity in the serial rollout."""
+    inst, cap0 = _tiny(seed, N=2 + seed % 5, K=2 + seed % 3, R=1 + seed % 3, T=18, inv_max=4)
+    bi, bc = _bids(inst, seed)
+    ser = oracle.serial_cap(inst, cap0, bids=(bi, bc))
+    q_T = int((_tau(cap0, ser["actions"]) <= len(ser["actions"]) - 1).sum())
+    r = oracle.alg1_cap(inst, cap0, inst.sku.astype(np.int64), inst.K, bids=(bi, bc))
+    assert r["converged"] and np.array_equal(r["actions"], ser["actions"])
+    assert _kstar(r["caches"], ser["actions"]) <= q_T + 1
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_bid_price_picard(oracle, seed):
+    """Proposition 2.1 for the bid-price policy, and the time-block replay against the
+    brute-force Algorithm 1 pass by pass."""
+    inst, cap0 = _tiny(seed, N=2 + seed % 5, K=1 + seed % 3, R=1 + seed % 3, T=16, inv_max=3)
+    T = int(inst.traj_offsets[-1])
+    bids = _bids(inst, seed)
+    ser = oracle.serial_cap(inst, cap0, bids=bids)["actions"]
+    rng = np.random.default_rng(seed)
+    worker = rng.integers(0, 1 + seed % 4, T)
+    r = oracle.alg1_cap(inst, cap0, worker, 1 + seed % 4, bids=bids)
+    assert r["converged"] and np.array_equal(r["actions"], ser) and r["passes"] <= T + 1
+    for B in (1, 3, T):
+        lit = oracle.alg1_cap(inst, cap0, oracle.time_block_workers(T, B), (T + B - 1) // B,
+                              bids=bids)
+        tb = oracle.picard_timeblocks_cap(inst, cap0, B, record=True, bids=bids)
+        assert lit["passes"] == tb["passes"]
+        assert np.array_equal(lit["caches"], tb["caches"])
+
+
+def test_bid_price_rejects_mixed_policy_and_bad_shapes(oracle):
+    inst, cap0 = _tiny(0, N=3, K=2, R=2, T=10, inv_max=3)
+    bi, bc = _bids(inst, 0)
+    with pytest.raises(ValueError):
+        oracle.serial_cap(inst, cap0, gamma=(1, 1), bids=(bi, bc))
+    with pytest.raises(ValueError):
+        oracle.serial_cap(inst, cap0, bids=(bi[:, :2], bc))

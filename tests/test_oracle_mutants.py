@@ -99,13 +99,25 @@ MUTANTS = [
     ("cap_greedy_ignores_capacity",
      "if (x[w] <= 0 || c[w] <= 0) continue;\n            const int32_t cw",
      "if (x[w] <= 0) continue;\n            const int32_t cw"),
-    ("cap_gamma_ignores_capacity_level", "(int64_t)gnum * (P->N - 1) * (M - c[w]);",
-     "(int64_t)gnum * (P->N - 1) * M;"),
+    ("cap_gamma_ignores_capacity_level", "const int64_t price = glow == 0 ? M - c[w] :",
+     "const int64_t price = glow == 0 ? M :"),
+    ("cap_gamma_low_prices_every_node", "(c[w] < glow ? (int64_t)glow - c[w] : 0)",
+     "((int64_t)glow - c[w])"),
+    ("cap_gamma_low_scaled_by_largest_capacity", "int64_t M = glow;\n    if (glow == 0)",
+     "int64_t M = 0;\n    if (1)"),
     ("cap_gamma_rank_ties_reversed", "if (cv < cw || (cv == cw && v < w)) ++k;",
      "if (cv < cw || (cv == cw && v > w)) ++k;"),
-    ("cap_gamma_max_over_feasible_only", "        if (c[w] > M) M = c[w];",
-     "        if (c[w] > M && x[w] > 0) M = c[w];"),
+    ("cap_gamma_max_over_feasible_only", "            if (c[w] > M) M = c[w];",
+     "            if (c[w] > M && x[w] > 0) M = c[w];"),
     ("cap_transition_keeps_capacity", "x[a] -= 1;\n    c[a] -= 1;", "x[a] -= 1;"),
+    ("cap_bid_stock_price_of_sku_zero",
+     "pol->bid_inv ? pol->bid_inv + (int64_t)P->sku[t] * P->N : NULL;",
+     "pol->bid_inv ? pol->bid_inv : NULL;"),
+    ("cap_bid_capacity_price_ignored", "(pol->bid_cap ? pol->bid_cap[w] : 0);", "0;"),
+    ("cap_bid_prices_added_as_rewards", "(int64_t)P->cost[w * R + r] + (bi ? bi[w] : 0) +",
+     "(int64_t)P->cost[w * R + r] - (bi ? bi[w] : 0) +"),
+    ("cap_bid_ties_to_last", "if (best == LOST || sc < best_s) { best = w; best_s = sc; }\n        }\n        return best;\n    }\n    if (gnum == 0)",
+     "if (best == LOST || sc <= best_s) { best = w; best_s = sc; }\n        }\n        return best;\n    }\n    if (gnum == 0)"),
     # (a replayed action that ignores a node's exhausted capacity is not listed: it only
     # lowers that node's stock, and a node without capacity is never chosen again, so
     # every action is unchanged)
