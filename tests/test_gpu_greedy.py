@@ -158,19 +158,23 @@ def test_serial_sweep_matches_oracle(api, oracle):
 
 
 @pytest.mark.parametrize("N,K,T,qmax", [(1, 1, 300, 3), (64, 1, 1000, 2), (65, 2, 777, 3),
-                                         (128, 3, 1500, 1), (100, 7, 2049, 3), (129, 2, 500, 2)])
+                                         (128, 3, 1500, 1), (100, 7, 2049, 3), (129, 2, 500, 2),
+                                         (70, 2, 1024, 2), (66, 3, 1040, 3), (100, 1, 5, 2),
+                                         (3, 2, 16, 1), (90, 4, 64 + 15, 2)])
 def test_serial_sweep_prefetch_window(api, oracle, N, K, T, qmax):
     """The serial sweep loads an order's stock row several orders ahead; with one to seven
     SKUs almost every order shares its SKU with one of the orders decided since, so its row
     must come from the most recent of them, not from memory.  Warehouse counts on both sides
     of one and two per lane (64, 65, 128, 129), horizons not a multiple of 16 or 64, and
-    enough stock that warehouses run out mid-way."""
+    enough stock that warehouses run out mid-way; horizons that end a group of 16 orders
+    inside a chunk of 64, end a chunk, or stop short of one group."""
     demand = 0.75 * T * (qmax + 1) / 2  # per trajectory, about
     inst = random_tiny(500 + N + K, N=N, K=K, R=5, T=T, qmax=qmax,
                        inv_max=max(1, int(demand / (K * N))), n_traj=3)  # stock ~ half of it
     _say(f"case serial prefetch window N={N} K={K} T={T} total={inst.total_orders}")
     want_a, want_s, want_f, _ = _oracle_batch(oracle, inst)
-    assert (want_a == -1).any() and (want_a >= 0).any()
+    if T >= 100:
+        assert (want_a == -1).any() and (want_a >= 0).any()
     out = api.pk_serial_simulate(api.DeviceProblem.from_instance(inst), "greedy")
     _check(out, inst, want_a, want_s, want_f)
 
