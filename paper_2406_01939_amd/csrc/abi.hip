@@ -224,7 +224,7 @@ void carve_plan(Carver &c, const Dims &d, const pk_policy *po, int B, Plan *L,
     p.ctl = c.take<Ctl>(1);
     *traj_off = c.take<int64_t>(d.n_traj + 1);
     p.traj_lcp = c.take<int32_t>(d.n_traj);
-    p.sink = c.take<int32_t>(128);
+    p.sink = c.take<int32_t>(4 * 64); // four 64-lane rows of dummy stores
     p.perm = c.take<int32_t>(d.total);
     p.s_key = c.take<int32_t>(d.total);
     p.s_region = c.take<int32_t>(d.total);

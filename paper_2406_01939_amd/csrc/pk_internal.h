@@ -100,7 +100,7 @@ struct Plan {
     int32_t *ch_next;        // [n_sr_max] given partitions: next run of the same process in
                              // the segment, -1 if none
     int32_t *traj_lcp;       // [n_traj] last pass in which the trajectory changed
-    int32_t *sink;           // [128] write target of masked-off lanes (contents unused)
+    int32_t *sink;           // [256] write target of masked-off lanes (contents unused)
     Ctl *ctl;
 };
 

@@ -9,6 +9,8 @@ namespace pk {
 namespace {
 
 constexpr int UNKNOWN = -2;
+constexpr int RING_CH = 4;             // chunks of 64 orders in each LDS ring
+constexpr int RING = RING_CH * WAVE;   // ring entries
 
 typedef unsigned short pk_u16x2 __attribute__((ext_vector_type(2)));
 
@@ -203,18 +205,18 @@ __device__ __forceinline__ int choose(const KeyT *row, const StockSet<SF> &fs, i
 // Choices: each region's choice is memoised and recomputed (least key over the stock
 // set) only when its warehouse has emptied.  For long runs every region's memo is
 // filled up front.
-// Orders in: the run is read in 64-order chunks into registers, one chunk ahead of use,
-// and each chunk is put into a 128-entry ring in LDS when the walk reaches it; a step
-// reads its 64 orders from the ring at any offset.  Actions out: committed actions and
-// shipped units go to a second 128-entry ring and leave for global memory one whole
-// chunk at a time.  The next run's descriptor is loaded while the current run is walked.
+// Orders in: the run is read in 64-order chunks into registers, two chunks at a time and
+// two chunks ahead of use (a load has about two steps to arrive), and both are put into
+// a 256-entry ring in LDS when the walk reaches the first of them; a step reads its 64
+// orders from the ring at any offset.  Actions out: committed actions and shipped units
+// go to a second 256-entry ring and leave for global memory two whole chunks at a time.  The next run's descriptor is loaded while the current run is walked.
 // The key table of the run's trajectory is read from LDS (one copy per workgroup for a
 // single trajectory, one per wave for small tables) or from global memory.
 // Per wave LDS: lm[N] (64-bit: the step's lanes per warehouse for unit demand; as int32,
 // the step's demand per warehouse otherwise; zero between steps), x[N] stock, cons[N] run
 // consumption (unclamped, for u), bw[R] memo, member count, F[ceil(N/64)] and two
-// zeroed words, key masks M (16-bit keys), in-ring[128] (region | (old+1) << 12, qty),
-// out-ring[128] (action, shipped).
+// zeroed words, key masks M (16-bit keys), in-ring[256] (region | (old+1) << 12, qty),
+// out-ring[256] (action, shipped).
 template <typename KeyT> __host__ __device__ inline size_t mask_bytes(int N)
 {
     return sizeof(KeyT) == 2 ? (size_t)tab_npad<KeyT>(N) * 2 : 0; // one bit pattern per key
@@ -224,7 +226,7 @@ template <typename KeyT> __host__ __device__ inline size_t walk_wave_bytes(int N
     const size_t tb = (size_t)tab_stride<KeyT>(N, R) * sizeof(KeyT);
     const size_t ints = ((size_t)8 * N + (size_t)(2 * N + R + 1) * 4 + 15) & ~(size_t)15;
     const size_t f = ((size_t)8 * ((N + 63) / 64) + 16 + 15) & ~(size_t)15;
-    return (mode == 1 ? tb : 0) + ints + f + mask_bytes<KeyT>(N) + 2 * 128 * sizeof(int2);
+    return (mode == 1 ? tb : 0) + ints + f + mask_bytes<KeyT>(N) + 2 * RING * sizeof(int2);
 }
 
 __device__ __forceinline__ int2 pack_in(int r, int q, int old) { return make_int2(r | ((old + 1) << 12), q); }
@@ -261,7 +263,7 @@ __global__ __launch_bounds__(WPB * 64) void k_walk_greedy(Prob P, Plan L, const 
     if (lane < 2) clr[lane] = 0;
     uint32_t *M = sizeof(KeyT) == 2 ? (uint32_t *)(wb + ints_off + ints_bytes + f_bytes) : nullptr;
     int2 *ring = (int2 *)(wb + ints_off + ints_bytes + f_bytes + mask_bytes<KeyT>(N));
-    int2 *oring = ring + 2 * WAVE;
+    int2 *oring = ring + RING;
     Ctl *ctl = L.ctl;
     if (ctl->done) return;
     if (TABMODE == 2) { // one trajectory: its table, once per workgroup
@@ -356,16 +358,22 @@ __global__ __launch_bounds__(WPB * 64) void k_walk_greedy(Prob P, Plan L, const 
         ring[lane] = pack_in(r0, q0, o0); // chunk 0
         RunDesc dn = {}; // the next run's descriptor
         if (s_next >= 0) dn = L.rd[s_next];
-        // chunk 1 into the prefetch registers, followed by two stores to the sink: the
-        // same operations, in the same order, as every advance below, so the wait for
-        // the prefetch registers counts the same outstanding operations on every path
+        // chunks 1 and 2 into the prefetch registers, followed by four stores to the
+        // sink: the same operations, in the same order, as every advance below, so the
+        // wait for the prefetch registers counts the same outstanding operations on every
+        // path
         __builtin_amdgcn_sched_barrier(0);
         const int i1 = lo + WAVE + lane < hi ? lo + WAVE + lane : hi - 1;
+        const int i2 = lo + 2 * WAVE + lane < hi ? lo + 2 * WAVE + lane : hi - 1;
         int rs = L.s_region[i1], qs = L.s_qty[i1], os = L.s_alpha[i1];
+        int rs2 = L.s_region[i2], qs2 = L.s_qty[i2], os2 = L.s_alpha[i2];
+        sink[2 * WAVE + lane] = 0; // four stores to four places (none merged away)
+        sink[3 * WAVE + lane] = 0;
         sink[lane] = 0;
         sink[WAVE + lane] = 0;
         __builtin_amdgcn_sched_barrier(0);
         int cw = 1; // chunks in the in-ring
+        int fl = 0; // chunks of actions already out
         wave_sync();
         if (hi - lo >= 2 * WAVE) { // long run: every region's choice up front
             for (int rb0 = 0; rb0 < R; rb0 += WAVE) {
@@ -387,30 +395,42 @@ __global__ __launch_bounds__(WPB * 64) void k_walk_greedy(Prob P, Plan L, const 
             // the step reads positions off .. off+63: chunks up to (off + 63) / 64
             const int need_c = (off + WAVE - 1) / WAVE + 1 < nch ? (off + WAVE - 1) / WAVE + 1 : nch;
             if (cw < need_c) { // at most one new chunk per step (a step advances <= 64)
-                // chunk cw (loaded at the previous advance) into the ring, then chunk cw+1
-                // into the same registers (written before they are reloaded: no copies
-                // of registers whose loads are in flight)
-                ring[(cw & 1) * WAVE + lane] = pack_in(rs, qs, os);
+                // chunks cw and cw+1 (loaded at the previous advance) into the ring, then
+                // chunks cw+2 and cw+3 into the same registers (written before they are
+                // reloaded: no copies of registers whose loads are in flight).  The ring
+                // then holds chunks cw-1 .. cw+1 (the step reads from chunk cw-1 on).
+                ring[(cw & (RING_CH - 1)) * WAVE + lane] = pack_in(rs, qs, os);
+                ring[((cw + 1) & (RING_CH - 1)) * WAVE + lane] = pack_in(rs2, qs2, os2);
                 __builtin_amdgcn_sched_barrier(0);
-                const int pc = lo + (cw + 1) * WAVE + lane;
+                const int pc = lo + (cw + 2) * WAVE + lane;
                 const int ic = pc < hi ? pc : hi - 1;
+                const int ic2 = pc + WAVE < hi ? pc + WAVE : hi - 1;
                 rs = L.s_region[ic];
                 qs = L.s_qty[ic];
                 os = L.s_alpha[ic];
-                // chunk cw-2 is committed in full: out to global memory (stored to the
-                // sink before there is one, so every advance issues the same operations)
-                const int po = lo + (cw - 2) * WAVE + lane; // < hi: not the last chunk
-                const int2 o = oring[((cw - 2) * WAVE + lane) & (2 * WAVE - 1)];
-                int32_t *pa = cw >= 2 ? &L.s_alpha[po] : &sink[lane];
-                int32_t *ps = cw >= 2 ? &L.s_ship[po] : &sink[WAVE + lane];
-                *pa = o.x;
-                *ps = o.y;
-                ++cw;
+                rs2 = L.s_region[ic2];
+                qs2 = L.s_qty[ic2];
+                os2 = L.s_alpha[ic2];
+                // chunks cw-3 and cw-2 are committed in full: out to global memory
+                // (stored to the sink before there are any, so every advance issues the
+                // same operations; both precede chunk cw-1 < the last chunk: full)
+#pragma unroll
+                for (int k = 3; k >= 2; --k) {
+                    const int c = cw - k;
+                    const int po = lo + c * WAVE + lane;
+                    const int2 o = oring[(c * WAVE + lane) & (RING - 1)];
+                    int32_t *pa = c >= 0 ? &L.s_alpha[po] : &sink[(2 * (k - 2)) * WAVE + lane];
+                    int32_t *ps = c >= 0 ? &L.s_ship[po] : &sink[(2 * (k - 2) + 1) * WAVE + lane];
+                    *pa = o.x;
+                    *ps = o.y;
+                }
+                fl = cw - 1;
+                cw += 2;
                 wave_sync();
             }
             const int n = hi - p < WAVE ? hi - p : WAVE;
             const bool act = lane < n;
-            const int2 e = ring[(off + lane) & (2 * WAVE - 1)];
+            const int2 e = ring[(off + lane) & (RING - 1)];
             const int r = act ? (e.x & 0xfff) : 0, q = act ? e.y : 0, old = (e.x >> 12) - 1;
             int a = LOST;
             if (fs.any()) {
@@ -500,7 +520,7 @@ __global__ __launch_bounds__(WPB * 64) void k_walk_greedy(Prob P, Plan L, const 
             changed |= chg;
             n_changed += __popcll(__ballot(chg));
             const int sh = a >= 0 ? ship : 0;
-            if (commit) oring[(off + lane) & (2 * WAVE - 1)] = make_int2(a, sh);
+            if (commit) oring[(off + lane) & (RING - 1)] = make_int2(a, sh);
             if (risky && unit) {
                 // each warehouse's first lane applies the step's committed demand on it
                 // (orders past the stock are past the cut, so it never exceeds the stock)
@@ -546,10 +566,10 @@ __global__ __launch_bounds__(WPB * 64) void k_walk_greedy(Prob P, Plan L, const 
             wave_sync();
             p += cut;
         }
-        // the last (at most two) chunks of actions
-        for (int c = cw >= 2 ? cw - 2 : 0; c < nch; ++c) {
+        // the last (at most three) chunks of actions
+        for (int c = fl; c < nch; ++c) {
             const int po = lo + c * WAVE + lane;
-            const int2 o = oring[(c * WAVE + lane) & (2 * WAVE - 1)];
+            const int2 o = oring[(c * WAVE + lane) & (RING - 1)];
             int32_t *pa = po < hi ? &L.s_alpha[po] : &sink[lane];
             int32_t *ps = po < hi ? &L.s_ship[po] : &sink[WAVE + lane];
             *pa = o.x;
