@@ -87,6 +87,7 @@ __global__ __launch_bounds__(WPB * 64, 16 / WPB) void k_walk_mlp(Prob P, Plan L,
     int32_t *pos = sl + N;               // index of each in sl
     int32_t *flag = pos + N;             // [0] changed, [1] near ties, [2] stock list length
     int32_t *dcor = flag + 4;            // given partitions: the process's own correction
+    float *lxs = (float *)(dcor + N);    // log1p of each warehouse's stock (feature cache)
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     Ctl *ctl = L.ctl;
     if (ctl->done) return;
@@ -138,6 +139,7 @@ __global__ __launch_bounds__(WPB * 64, 16 / WPB) void k_walk_mlp(Prob P, Plan L,
         for (int w = threadIdx.x; w < N; w += blockDim.x) {
             const int32_t v = x0row[w] - (Erow ? Erow[w] : 0) - (L.worker ? dcor[w] : 0);
             x[w] = v > 0 ? v : 0;
+            lxs[w] = log1pf((float)(v > 0 ? v : 0));
             cons[w] = 0;
         }
         __syncthreads();
@@ -157,8 +159,8 @@ __global__ __launch_bounds__(WPB * 64, 16 / WPB) void k_walk_mlp(Prob P, Plan L,
             if (wave != 0) nf = flag[2];
             float pr[16];
             load_region_term(pr, rtab, r);
-            score_rows(m, pr, costT + ((int64_t)b * R + r) * N, x, sl, nf, P.seed, (uint32_t)b, t,
-                       zbuf);
+            score_rows(m, pr, costT + ((int64_t)b * R + r) * N, x, lxs, sl, nf, P.seed,
+                       (uint32_t)b, t, zbuf);
             __syncthreads();
             if (wave == 0) {
                 float z1, z2;
@@ -170,6 +172,7 @@ __global__ __launch_bounds__(WPB * 64, 16 / WPB) void k_walk_mlp(Prob P, Plan L,
                         const int xa = x[a], ca = cons[a], ia = pos[a], last = sl[nf - 1];
                         sh = q < xa ? q : xa;
                         x[a] = xa - sh;
+                        lxs[a] = log1pf((float)(xa - sh));
                         cons[a] = ca + q;
                         if (xa == sh) { // emptied: the list's last entry takes its place
                             sl[ia] = last;
@@ -327,7 +330,7 @@ __global__ __launch_bounds__(THREADS) void k_serial_mlp(Prob P, const float *par
         const int nf = *nfp;
         float pr[16];
         load_region_term(pr, rtab, od.y);
-        score_rows(m, pr, cbuf + buf * N, x, sl, nf, P.seed, (uint32_t)b, (uint32_t)(tt - t0),
+        score_rows(m, pr, cbuf + buf * N, x, nullptr, sl, nf, P.seed, (uint32_t)b, (uint32_t)(tt - t0),
                    zbuf);
         __syncthreads();
         if (wave == 0) {
@@ -442,7 +445,7 @@ hipError_t setup_costT(const Prob &P, const float *params, float *costT, hipStre
     return hipGetLastError();
 }
 
-size_t walk_mlp_lds(int N) { return w2_lds_bytes() + vec_lds_bytes() + (size_t)N * 24 + 64; }
+size_t walk_mlp_lds(int N) { return w2_lds_bytes() + vec_lds_bytes() + (size_t)N * 28 + 64; }
 
 hipError_t launch_walk_mlp(const Prob &P, const Plan &L, const float *params, int layers,
                            const float *costT, int32_t *final_inv, bool has_init, int n_cus,

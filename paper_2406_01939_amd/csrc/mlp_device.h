@@ -297,11 +297,13 @@ __device__ __forceinline__ float score_tile(const ScoreLane &m, const float pr[1
 // by all waves of the workgroup: wave w takes tiles w, w + nwaves, ... (16 listed
 // warehouses each), four at a time.  The noise of the four tiles' 64 rows is drawn first,
 // one row per lane (lane l: row l%16 of the group's tile l/16), and lane l adds it to the
-// score of that row, which it holds after scoring that tile.
+// score of that row, which it holds after scoring that tile.  lx (nullable): log1p of each
+// warehouse's stock, kept by the caller as the stock changes (the same value the row
+// would compute from x: log1pf costs more than the rest of a row's features).
 __device__ __forceinline__ void score_rows(const ScoreLane &m, const float pr[16],
                                            const float *costT_r, const int32_t *x,
-                                           const int32_t *sl, int nf, uint64_t seed,
-                                           uint32_t traj, uint32_t t, float *zl)
+                                           const float *lx, const int32_t *sl, int nf,
+                                           uint64_t seed, uint32_t traj, uint32_t t, float *zl)
 {
     const int wave = threadIdx.x / WAVE, nwaves = blockDim.x / WAVE;
     const int lane = __lane_id(), grp = lane >> 4;
@@ -316,8 +318,14 @@ __device__ __forceinline__ void score_rows(const ScoreLane &m, const float pr[16
             const int i = tile * 16 + (lane & 15);
             const bool valid = i < nf;
             const int w = valid ? sl[i] : 0;
-            const int xv = valid ? x[w] : 0;
-            const float s = score_tile(m, pr, valid ? costT_r[w] : 0.f, log1pf((float)xv));
+            float lv;
+            if (lx) {
+                lv = valid ? lx[w] : 0.f;
+            } else {
+                const int xv = valid ? x[w] : 0;
+                lv = log1pf((float)xv);
+            }
+            const float s = score_tile(m, pr, valid ? costT_r[w] : 0.f, lv);
             if (grp == k && valid) zl[i] = s + gn;
         }
     }
