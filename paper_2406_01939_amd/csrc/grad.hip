@@ -94,6 +94,7 @@ __global__ __launch_bounds__(256) void k_grad(Prob P, Plan L, const float *param
     int32_t *sl = (int32_t *)(sbuf + N);  // [N] warehouses with stock
     int32_t *pos = sl + N;                // [N] their index in sl
     int32_t *nfp = pos + N;               // [1] how many
+    float *lxs = (float *)(nfp + 4);      // [N] log1p of each warehouse's stock
     // parameter views
     const float *W1 = params + (int64_t)R * 16;
     const float *b1 = W1 + H * 18;
@@ -130,6 +131,7 @@ __global__ __launch_bounds__(256) void k_grad(Prob P, Plan L, const float *param
         for (int w = threadIdx.x; w < N; w += blockDim.x) {
             const int32_t v = x0row[w] - (Erow ? Erow[w] : 0);
             x[w] = v > 0 ? v : 0;
+            lxs[w] = log1pf((float)(v > 0 ? v : 0));
         }
         __syncthreads();
         build_stock_list(x, N, sl, pos, nfp);
@@ -148,9 +150,8 @@ __global__ __launch_bounds__(256) void k_grad(Prob P, Plan L, const float *param
                 const int i = tile * 16 + m;
                 const bool valid = i < nf;
                 const int w = valid ? sl[i] : 0;
-                const int xv = valid ? x[w] : 0;
                 float f[5];
-                lane_features(f, valid ? cr[w] : 0.f, log1pf((float)xv), Ebuf);
+                lane_features(f, valid ? cr[w] : 0.f, valid ? lxs[w] : 0.f, Ebuf);
                 const float sc = mlp_tile(mw, f);
                 if (lane < 16 && valid) sbuf[w] = sc;
             }
@@ -189,8 +190,7 @@ __global__ __launch_bounds__(256) void k_grad(Prob P, Plan L, const float *param
                         const int i = row0 + m;
                         const bool valid = i < nf;
                         const int w = valid ? sl[i] : 0;
-                        const int xv = valid ? x[w] : 0;
-                        const float cost = valid ? cr[w] : 0.f, lx = log1pf((float)xv);
+                        const float cost = valid ? cr[w] : 0.f, lx = valid ? lxs[w] : 0.f;
                         float f[5];
                         lane_features(f, cost, lx, Ebuf);
                         v4f h1[4], h2[4], d1[4];
@@ -327,6 +327,7 @@ __global__ __launch_bounds__(256) void k_grad(Prob P, Plan L, const float *param
                 const int xa = x[a];
                 const int nx = xa - (q < xa ? q : xa);
                 x[a] = nx;
+                lxs[a] = log1pf((float)nx);
                 if (xa > 0 && nx == 0) drop_from_list(a, sl, pos, nfp);
             }
             __syncthreads();
@@ -401,7 +402,7 @@ __global__ void k_unpermute_f32(const int32_t *perm, const float *src, float *ds
 size_t grad_lds(int N, int layers)
 {
     (void)layers;
-    return w2_lds_bytes() + (size_t)(3 * H * RS + GW * H + H + 16 + 4) * 4 + 16 + (size_t)N * 16 + 16;
+    return w2_lds_bytes() + (size_t)(3 * H * RS + GW * H + H + 16 + 4) * 4 + 16 + (size_t)N * 20 + 32;
 }
 
 size_t grad_part_bytes(int n_wg, int R, int layers)
