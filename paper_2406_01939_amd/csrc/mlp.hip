@@ -88,6 +88,9 @@ __global__ __launch_bounds__(WPB * 64, 16 / WPB) void k_walk_mlp(Prob P, Plan L,
     int32_t *flag = pos + N;             // [0] changed, [1] near ties, [2] stock list length
     int32_t *dcor = flag + 4;            // given partitions: the process's own correction
     float *lxs = (float *)(dcor + N);    // log1p of each warehouse's stock (feature cache)
+    float *cbs = lxs + N;                // [2][N] cost rows of this order's and the next's region
+    float *prs = (float *)(((uintptr_t)(cbs + 2 * N) + 15) & ~(uintptr_t)15); // [2][64] their
+                                         // region terms of layer 1
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     Ctl *ctl = L.ctl;
     if (ctl->done) return;
@@ -142,14 +145,25 @@ __global__ __launch_bounds__(WPB * 64, 16 / WPB) void k_walk_mlp(Prob P, Plan L,
             lxs[w] = log1pf((float)(v > 0 ? v : 0));
             cons[w] = 0;
         }
+        // the first order's region rows into buffer 0; the next order's region and time
+        const int rn = L.s_region[lo];
+        uint32_t tn = (uint32_t)L.s_t[lo];
+        for (int w = threadIdx.x; w < N; w += blockDim.x) cbs[w] = costT[((int64_t)b * R + rn) * N + w];
+        if (threadIdx.x < 64) prs[threadIdx.x] = rtab[(int64_t)rn * 64 + threadIdx.x];
+        int r1 = lo + 1 < hi ? L.s_region[lo + 1] : 0;
+        uint32_t t1 = lo + 1 < hi ? (uint32_t)L.s_t[lo + 1] : 0u;
         __syncthreads();
         build_stock_list(x, N, sl, pos, &flag[2]);
         __syncthreads();
         int nf = flag[2];       // wave 0 keeps the list length; the others reread it
         int run_chg = 0, run_ties = 0; // wave 0, lane 0
         for (int p = lo; p < hi; ++p) {
-            const int r = L.s_region[p];
-            const uint32_t t = (uint32_t)L.s_t[p];
+            const int cur = (p - lo) & 1;
+            const uint32_t t = tn;
+            const bool hn = p + 1 < hi;
+            // the region and time of the order after the next one
+            const int r2 = p + 2 < hi ? L.s_region[p + 2] : 0;
+            const uint32_t t2 = p + 2 < hi ? (uint32_t)L.s_t[p + 2] : 0u;
             // wave 0's lane 0 needs the order's quantity and cached action after the argmax
             int q = 0, old = 0;
             if (threadIdx.x == 0) {
@@ -158,9 +172,8 @@ __global__ __launch_bounds__(WPB * 64, 16 / WPB) void k_walk_mlp(Prob P, Plan L,
             }
             if (wave != 0) nf = flag[2];
             float pr[16];
-            load_region_term(pr, rtab, r);
-            score_rows(m, pr, costT + ((int64_t)b * R + r) * N, x, lxs, sl, nf, P.seed,
-                       (uint32_t)b, t, zbuf);
+            load_region_term(pr, prs + cur * 64, 0);
+            score_rows(m, pr, cbs + cur * N, x, lxs, sl, nf, P.seed, (uint32_t)b, t, zbuf);
             __syncthreads();
             if (wave == 0) {
                 float z1, z2;
@@ -193,6 +206,32 @@ __global__ __launch_bounds__(WPB * 64, 16 / WPB) void k_walk_mlp(Prob P, Plan L,
                 }
                 nf -= __builtin_amdgcn_readlane(emp, 0);
             }
+            if (wave != 0 && hn) {
+                // the next order's region rows into the other buffer (last read by the
+                // previous order's tiles) while wave 0 takes this order's argmax: all
+                // loads of a round issued before their stores
+                constexpr int NT = (WPB - 1) * WAVE;
+                const int tid = (int)threadIdx.x - WAVE;
+                const float *src = costT + ((int64_t)b * R + r1) * N;
+                float *dst = cbs + (cur ^ 1) * N;
+                for (int base = 0; base < N; base += 4 * NT) {
+                    float cv[4];
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int w = base + k * NT + tid;
+                        cv[k] = w < N ? src[w] : 0.f;
+                    }
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) {
+                        const int w = base + k * NT + tid;
+                        if (w < N) dst[w] = cv[k];
+                    }
+                }
+                if (tid < 64) prs[(cur ^ 1) * 64 + tid] = rtab[(int64_t)r1 * 64 + tid];
+            }
+            tn = t1;
+            r1 = r2;
+            t1 = t2;
             __syncthreads();
         }
         if (threadIdx.x == 0) { flag[0] = run_chg; flag[1] = run_ties; }
@@ -445,7 +484,7 @@ hipError_t setup_costT(const Prob &P, const float *params, float *costT, hipStre
     return hipGetLastError();
 }
 
-size_t walk_mlp_lds(int N) { return w2_lds_bytes() + vec_lds_bytes() + (size_t)N * 28 + 64; }
+size_t walk_mlp_lds(int N) { return w2_lds_bytes() + vec_lds_bytes() + (size_t)N * 36 + 64 + 16 + 512; }
 
 hipError_t launch_walk_mlp(const Prob &P, const Plan &L, const float *params, int layers,
                            const float *costT, int32_t *final_inv, bool has_init, int n_cus,
