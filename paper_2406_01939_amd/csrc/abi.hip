@@ -977,7 +977,7 @@ pk_status check_owmr(const pk_owmr_problem *pr, OwmrDev *P)
 
 struct OwmrWs {
     int32_t *keys, *keys_alt, *vals, *vals_alt, *sd, *cnt, *err, *fx;
-    int64_t *V, *S, *rq, *fx0v, *x0;
+    int64_t *V, *S, *rq, *fx0v, *x0, *sink;
     unsigned long long *resets;
     OwmrCtl *ctl;
     void *rtmp, *stmp;
@@ -1002,6 +1002,7 @@ size_t carve_owmr(char *base, const OwmrDev &P, OwmrWs *w)
     w->S = c.take<int64_t>(T);
     w->rq = c.take<int64_t>(T + 1);
     w->fx0v = c.take<int64_t>(P.N);
+    w->sink = c.take<int64_t>(64);
     w->rtmp = c.take<char>((int64_t)owmr_radix_tmp(T));
     w->stmp = c.take<char>((int64_t)std::max(scan_tmp_bytes(T), scan_tmp_bytes((int64_t)P.N + 1)));
     return c.off + 256;
@@ -1213,7 +1214,8 @@ pk_status pk_owmr_picard_simulate(const pk_owmr_problem *problem, int32_t max_pa
         for (int i = 0; i < u; ++i)
             HIP_TRY(owmr_launch_pass(P, w.ctl, perm, w.sd, w.cnt, w.V, w.S, w.rq, w.stmp, w.fx0v,
                                      final_x ? final_x : w.fx,
-                                     caches ? caches + (int64_t)(launched + i) * P.T : nullptr, st));
+                                     caches ? caches + (int64_t)(launched + i) * P.T : nullptr,
+                                     w.sink, st));
         launched += u;
         HIP_TRY(hipMemcpyAsync(&hc, w.ctl, sizeof hc, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));

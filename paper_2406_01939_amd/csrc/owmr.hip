@@ -15,8 +15,8 @@
 //   V[t] = reset_t * 2^40 + q_t   (the cache, time order)   and   S = exclusive scan of V,
 // the low 40 bits of S[t] are the orders before t and the high bits the resets before t;
 // the list of resets (their times and the order sums just after them) comes from one
-// scatter.  A pass is: scan V -> S, the reset list, the retailer walk (which rewrites V in
-// place and counts changes), the pass end.
+// scatter.  A pass is: scan V -> S (out of place), the reset list, the retailer walk
+// (which rewrites V in place and counts changes), the pass end.
 #include "pk_internal.h"
 
 namespace pk {
@@ -58,12 +58,6 @@ __global__ void k_ow_init(OwmrDev P, const int32_t *iq, const int32_t *ir, int64
         V[t] = iq ? (((int64_t)(ir[t] != 0) << OW_SHIFT) + (iq[t] > 0 ? iq[t] : 0)) : 0;
 }
 
-__global__ void k_ow_copy(const int64_t *V, int64_t *S, int64_t n)
-{
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) S[i] = V[i];
-}
-
 // The reset list: the j-th cached reset at time t gets rq[j] = orders up to and including
 // t (the low bits of S[t] + V[t]), the base of the central stock after it.
 __global__ void k_ow_resets(OwmrDev P, const OwmrCtl *ctl, const int64_t *V, const int64_t *S,
@@ -83,73 +77,107 @@ __global__ void k_ow_resets(OwmrDev P, const OwmrCtl *ctl, const int64_t *V, con
 // One lane per retailer walks its steps in time order (sorted positions seg[n] ..
 // seg[n+1]: time index perm[i], demand sd[i]).  Loads run in two stages ahead of the step
 // being decided: the time index and demand 2 DIST steps ahead (sequential per lane), then
-// the scan value and the old cache of the step DIST ahead (at that time index).
+// the scan value and the old cache of the step DIST ahead (at that time index), then the
+// reset base of the step DIST / 2 ahead (at its count of resets).  The
+// groups of DIST steps that every lane of the wave has run without a per-step test, their
+// look-ahead loads clamped into the lane's range, so the compiler counts the loads between
+// a prefetch and its use exactly; the rest run with the test.  Lanes past the last
+// retailer shadow it and write to the sink.  REC: write each pass's cache to `caches`.
+template <bool REC>
 __global__ __launch_bounds__(64) void k_ow_walk(OwmrDev P, OwmrCtl *ctl, const int32_t *perm,
                                                 const int32_t *sd, const int32_t *seg,
                                                 const int64_t *S, const int64_t *rq, int64_t *V,
                                                 int64_t *final_x0v, int32_t *final_x,
-                                                int64_t *caches)
+                                                int64_t *caches, int64_t *sink)
 {
     if (ctl->done) return;
-    const int n = blockIdx.x * 64 + threadIdx.x;
+    const int lane = threadIdx.x;
+    const int n0 = blockIdx.x * 64 + lane;
+    const bool valid = n0 < P.N;
+    const int n = valid ? n0 : P.N - 1;
     unsigned long long changed = 0;
-    if (n < P.N) {
-        const int32_t lo = seg[n], hi = seg[n + 1];
-        const int32_t s_n = P.s_ret[n], S_n = P.S_ret[n], c_n = P.cap[n];
-        int64_t x = P.x_init[n];
-        int64_t x0v = P.x0_init; // central stock after this retailer's previous step
-        int64_t s_a = 0;         // S at a = previous step + 1 (orders and resets before a)
-        int32_t at[OW_DIST], ad[OW_DIST];                  // stage A: i + 2 DIST
-        int32_t bt[OW_DIST], bd[OW_DIST];                  // stage B: i + DIST
-        int64_t bs[OW_DIST], bv[OW_DIST];
+    const int32_t lo = seg[n], hi = seg[n + 1];
+    const int32_t last = hi > lo ? hi - 1 : lo; // a position of the lane's range (or lo)
+    const int32_t s_n = P.s_ret[n], S_n = P.S_ret[n], c_n = P.cap[n];
+    int64_t x = P.x_init[n];
+    int64_t x0v = P.x0_init; // central stock after this retailer's previous step
+    int64_t s_a = 0;         // S at a = previous step + 1 (orders and resets before a)
+    int32_t at[OW_DIST], ad[OW_DIST];                  // stage A: i + 2 DIST
+    int32_t bt[OW_DIST], bd[OW_DIST];                  // stage B: i + DIST
+    int64_t bs[OW_DIST], bv[OW_DIST];
+    int64_t rqv[OW_DIST]; // stage C: the reset base of the step DIST / 2 ahead
+    const bool any = hi > lo;
 #pragma unroll
-        for (int k = 0; k < OW_DIST; ++k) {
-            const int32_t i = lo + k, j = lo + OW_DIST + k;
-            bt[k] = i < hi ? perm[i] : 0;
-            bd[k] = i < hi ? sd[i] : 0;
-            at[k] = j < hi ? perm[j] : 0;
-            ad[k] = j < hi ? sd[j] : 0;
-        }
+    for (int k = 0; k < OW_DIST; ++k) {
+        const int32_t i = lo + k, j = lo + OW_DIST + k;
+        bt[k] = any ? perm[i < hi ? i : last] : 0;
+        bd[k] = any ? sd[i < hi ? i : last] : 0;
+        at[k] = any ? perm[j < hi ? j : last] : 0;
+        ad[k] = any ? sd[j < hi ? j : last] : 0;
+    }
 #pragma unroll
-        for (int k = 0; k < OW_DIST; ++k) {
-            const bool ok = lo + k < hi;
-            bs[k] = ok ? S[bt[k]] : 0;
-            bv[k] = ok ? V[bt[k]] : 0;
-        }
-        for (int32_t i0 = lo; i0 < hi; i0 += OW_DIST) {
+    for (int k = 0; k < OW_DIST; ++k) {
+        bs[k] = any ? S[bt[k]] : 0;
+        bv[k] = any ? V[bt[k]] : 0;
+    }
+    // rq index of a step: its last cached reset before it (rq[0] when there is none: unused)
+    auto rq_at = [&](int64_t s_t) {
+        const int64_t c = s_t >> OW_SHIFT;
+        return rq[c > 0 ? c - 1 : 0];
+    };
 #pragma unroll
-            for (int k = 0; k < OW_DIST; ++k) {
-                const int32_t i = i0 + k;
-                if (i < hi) { // (the last group's tail: uniform per lane)
-                    const int32_t t = bt[k];
-                    const int64_t d = bd[k], s_t = bs[k], v_old = bv[k];
-                    // stage B takes over stage A's step (DIST ahead) and loads its values;
-                    // stage A loads the step 2 DIST ahead
-                    const bool okb = i + OW_DIST < hi, oka = i + 2 * OW_DIST < hi;
-                    bt[k] = at[k];
-                    bd[k] = ad[k];
-                    bs[k] = okb ? S[at[k]] : 0;
-                    bv[k] = okb ? V[at[k]] : 0;
-                    at[k] = oka ? perm[i + 2 * OW_DIST] : 0;
-                    ad[k] = oka ? sd[i + 2 * OW_DIST] : 0;
-                    // the central stock at t: resets and orders of the others' steps since a
-                    const int64_t c_t = s_t >> OW_SHIFT, c_a = s_a >> OW_SHIFT;
-                    const int64_t v = c_t > c_a ? P.S0 - ((s_t & OW_QMASK) - rq[c_t - 1])
-                                                : x0v - ((s_t & OW_QMASK) - (s_a & OW_QMASK));
-                    const int64_t x0 = v > 0 ? v : 0;
-                    const int64_t q = ow_order(x, d, s_n, S_n, c_n);
-                    const int reset = x0 - q <= P.s0;
-                    const int64_t v_new = ((int64_t)reset << OW_SHIFT) + q;
-                    changed += v_new != v_old;
-                    V[t] = v_new;
-                    if (caches) caches[t] = v_new;
-                    const int64_t p = x > d ? x - d : 0;
-                    x = p + (q < x0 ? q : x0);
-                    x0v = reset ? P.S0 : (x0 > q ? x0 - q : 0);
-                    s_a = s_t + v_old; // S at t + 1 in the previous pass's cache
-                }
-            }
-        }
+    for (int k = 0; k < OW_DIST; ++k) rqv[k] = k < OW_DIST / 2 ? rq_at(bs[k]) : 0;
+    // one step (step i of the lane, slot k of its group)
+    auto step = [&](int32_t i, int k) {
+        // stage C: the reset base of step i + DIST/2, whose S value arrived DIST/2 steps ago
+        const int kc = (k + OW_DIST / 2) & (OW_DIST - 1);
+        const int64_t rq_t = rqv[k];
+        rqv[kc] = rq_at(bs[kc]);
+        const int32_t t = bt[k];
+        const int64_t d = bd[k], s_t = bs[k], v_old = bv[k];
+        // stage B takes over stage A's step (DIST ahead) and loads its values; stage A
+        // loads the step 2 DIST ahead (clamped into the range: past it, unused)
+        const int32_t ia = i + 2 * OW_DIST < hi ? i + 2 * OW_DIST : last;
+        bt[k] = at[k];
+        bd[k] = ad[k];
+        bs[k] = S[at[k]];
+        bv[k] = V[at[k]];
+        at[k] = perm[ia];
+        ad[k] = sd[ia];
+        // the central stock at t: resets and orders of the others' steps since a
+        const int64_t c_t = s_t >> OW_SHIFT, c_a = s_a >> OW_SHIFT;
+        const int64_t v = c_t > c_a ? P.S0 - ((s_t & OW_QMASK) - rq_t)
+                                    : x0v - ((s_t & OW_QMASK) - (s_a & OW_QMASK));
+        const int64_t x0 = v > 0 ? v : 0;
+        const int64_t q = ow_order(x, d, s_n, S_n, c_n);
+        const int reset = x0 - q <= P.s0;
+        const int64_t v_new = ((int64_t)reset << OW_SHIFT) + q;
+        changed += valid && v_new != v_old;
+        *(valid ? &V[t] : &sink[lane]) = v_new;
+        if constexpr (REC) *(valid ? &caches[t] : &sink[lane]) = v_new;
+        const int64_t p = x > d ? x - d : 0;
+        x = p + (q < x0 ? q : x0);
+        x0v = reset ? P.S0 : (x0 > q ? x0 - q : 0);
+        s_a = s_t + v_old; // S at t + 1 in the previous pass's cache
+    };
+    // groups every lane runs in full (a wave-uniform count)
+    int32_t g_all = (hi - lo) / OW_DIST;
+    for (int o = 32; o > 0; o >>= 1) {
+        const int32_t other = __shfl_xor(g_all, o, 64);
+        g_all = other < g_all ? other : g_all;
+    }
+    g_all = __builtin_amdgcn_readfirstlane(g_all);
+    int32_t i0 = lo;
+    for (int32_t g = 0; g < g_all; ++g, i0 += OW_DIST) {
+#pragma unroll
+        for (int k = 0; k < OW_DIST; ++k) step(i0 + k, k);
+    }
+    for (; i0 < hi; i0 += OW_DIST) {
+#pragma unroll
+        for (int k = 0; k < OW_DIST; ++k)
+            if (i0 + k < hi) step(i0 + k, k); // (the last groups' tails: per lane)
+    }
+    if (valid) {
         final_x[n] = (int32_t)x;
         final_x0v[n] = x0v;
     }
@@ -338,16 +366,20 @@ hipError_t owmr_launch_init(const OwmrDev &P, const int32_t *iq, const int32_t *
 
 hipError_t owmr_launch_pass(const OwmrDev &P, OwmrCtl *ctl, const int32_t *perm, const int32_t *sd,
                             const int32_t *seg, int64_t *V, int64_t *S, int64_t *rq, void *stmp,
-                            int64_t *fx0v, int32_t *fx, int64_t *caches, hipStream_t st)
+                            int64_t *fx0v, int32_t *fx, int64_t *caches, int64_t *sink,
+                            hipStream_t st)
 {
     if (P.T > 0) {
-        hipLaunchKernelGGL(k_ow_copy, dim3(grid_for(P.T)), dim3(256), 0, st, V, S, P.T);
-        hipError_t e = scan_i64(S, P.T, false, stmp, st);
+        hipError_t e = scan_i64_to(V, S, P.T, false, stmp, st);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_ow_resets, dim3(grid_for(P.T)), dim3(256), 0, st, P, ctl, V, S, rq);
     }
-    hipLaunchKernelGGL(k_ow_walk, dim3((unsigned)((P.N + 63) / 64)), dim3(64), 0, st, P, ctl,
-                       perm, sd, seg, S, rq, V, fx0v, fx, caches);
+    if (caches)
+        hipLaunchKernelGGL(k_ow_walk<true>, dim3((unsigned)((P.N + 63) / 64)), dim3(64), 0, st, P,
+                           ctl, perm, sd, seg, S, rq, V, fx0v, fx, caches, sink);
+    else
+        hipLaunchKernelGGL(k_ow_walk<false>, dim3((unsigned)((P.N + 63) / 64)), dim3(64), 0, st, P,
+                           ctl, perm, sd, seg, S, rq, V, fx0v, fx, caches, sink);
     hipLaunchKernelGGL(k_ow_pass_end, dim3(1), dim3(64), 0, st, ctl);
     return hipGetLastError();
 }

@@ -211,6 +211,8 @@ int region_bits(int R);
 hipError_t launch_walk_greedy_lane(const Prob &P, const Plan &L, int32_t *final_inv,
                                    bool has_init, int64_t n_list, hipStream_t st);
 hipError_t scan_i64(int64_t *data, int64_t n, bool inclusive, void *tmp, hipStream_t st);
+hipError_t scan_i64_to(const int64_t *src, int64_t *dst, int64_t n, bool inclusive, void *tmp,
+                       hipStream_t st); // out of place
 size_t scan_tmp_bytes(int64_t n);
 hipError_t scan_i32_excl(int32_t *data, int64_t n, void *tmp, hipStream_t st);
 
@@ -261,7 +263,8 @@ hipError_t owmr_launch_init(const OwmrDev &P, const int32_t *iq, const int32_t *
                             OwmrCtl *ctl, int32_t max_passes, hipStream_t st);
 hipError_t owmr_launch_pass(const OwmrDev &P, OwmrCtl *ctl, const int32_t *perm, const int32_t *sd,
                             const int32_t *seg, int64_t *V, int64_t *S, int64_t *rq, void *stmp,
-                            int64_t *fx0v, int32_t *fx, int64_t *caches, hipStream_t st);
+                            int64_t *fx0v, int32_t *fx, int64_t *caches, int64_t *sink,
+                            hipStream_t st); // sink: [64] stores of lanes without a retailer
 hipError_t owmr_launch_unpack(const OwmrDev &P, const int64_t *V, int32_t *q, int32_t *r,
                               hipStream_t st);
 hipError_t owmr_launch_serial(const OwmrDev &P, int32_t *q, int32_t *r, int64_t *fx0, int32_t *fx,

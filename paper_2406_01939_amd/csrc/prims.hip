@@ -76,8 +76,8 @@ __global__ __launch_bounds__(SCAN_MID_THREADS) void k_partial_scan(T *partial, i
 }
 
 template <typename T>
-__global__ __launch_bounds__(SCAN_THREADS) void k_tile_scan(T *data, int64_t n, const T *partial,
-                                                            int inclusive)
+__global__ __launch_bounds__(SCAN_THREADS) void k_tile_scan(const T *src, T *data, int64_t n,
+                                                            const T *partial, int inclusive)
 {
     __shared__ T lds[SCAN_THREADS / WAVE];
     __shared__ T stage[SCAN_TILE];
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_tile_scan(T *data, int64_t n, 
     // coalesced load into LDS, then each thread scans a contiguous run of SCAN_ITEMS
     for (int i = 0; i < SCAN_ITEMS; ++i) {
         int64_t j = base + (int64_t)i * SCAN_THREADS + threadIdx.x;
-        stage[i * SCAN_THREADS + threadIdx.x] = j < n ? data[j] : T(0);
+        stage[i * SCAN_THREADS + threadIdx.x] = j < n ? src[j] : T(0);
     }
     __syncthreads();
     T loc[SCAN_ITEMS];
@@ -107,17 +107,18 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_tile_scan(T *data, int64_t n, 
     }
 }
 
+// Scan of src into data (src == data: in place).
 template <typename T>
-hipError_t scan_impl(T *data, int64_t n, bool inclusive, void *tmp, hipStream_t st)
+hipError_t scan_impl(const T *src, T *data, int64_t n, bool inclusive, void *tmp, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
     const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
     T *partial = (T *)tmp;
-    hipLaunchKernelGGL(k_tile_reduce<T>, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, st, data,
+    hipLaunchKernelGGL(k_tile_reduce<T>, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, st, src,
                        n, partial);
     hipLaunchKernelGGL(k_partial_scan<T>, dim3(1), dim3(SCAN_MID_THREADS), 0, st, partial, nb);
-    hipLaunchKernelGGL(k_tile_scan<T>, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, st, data, n,
-                       partial, inclusive ? 1 : 0);
+    hipLaunchKernelGGL(k_tile_scan<T>, dim3((unsigned)nb), dim3(SCAN_THREADS), 0, st, src, data,
+                       n, partial, inclusive ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -344,12 +345,18 @@ __global__ void k_seg_tiles(const int64_t *seg_off, int n_seg, int32_t *tile_fir
 
 hipError_t scan_i64(int64_t *data, int64_t n, bool inclusive, void *tmp, hipStream_t st)
 {
-    return scan_impl<int64_t>(data, n, inclusive, tmp, st);
+    return scan_impl<int64_t>(data, data, n, inclusive, tmp, st);
+}
+
+hipError_t scan_i64_to(const int64_t *src, int64_t *dst, int64_t n, bool inclusive, void *tmp,
+                       hipStream_t st)
+{
+    return scan_impl<int64_t>(src, dst, n, inclusive, tmp, st);
 }
 
 hipError_t scan_i32_excl(int32_t *data, int64_t n, void *tmp, hipStream_t st)
 {
-    return scan_impl<int32_t>(data, n, false, tmp, st);
+    return scan_impl<int32_t>(data, data, n, false, tmp, st);
 }
 
 size_t scan_tmp_bytes(int64_t n)
