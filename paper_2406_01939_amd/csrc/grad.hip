@@ -131,7 +131,7 @@ __global__ __launch_bounds__(256) void k_grad(Prob P, Plan L, const float *param
         for (int w = threadIdx.x; w < N; w += blockDim.x) {
             const int32_t v = x0row[w] - (Erow ? Erow[w] : 0);
             x[w] = v > 0 ? v : 0;
-            lxs[w] = log1pf((float)(v > 0 ? v : 0));
+            lxs[w] = log1p_stock(v > 0 ? v : 0);
         }
         __syncthreads();
         build_stock_list(x, N, sl, pos, nfp);
@@ -327,7 +327,7 @@ __global__ __launch_bounds__(256) void k_grad(Prob P, Plan L, const float *param
                 const int xa = x[a];
                 const int nx = xa - (q < xa ? q : xa);
                 x[a] = nx;
-                lxs[a] = log1pf((float)nx);
+                lxs[a] = log1p_stock(nx);
                 if (xa > 0 && nx == 0) drop_from_list(a, sl, pos, nfp);
             }
             __syncthreads();

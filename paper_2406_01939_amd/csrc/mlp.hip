@@ -142,7 +142,7 @@ __global__ __launch_bounds__(WPB * 64, 16 / WPB) void k_walk_mlp(Prob P, Plan L,
         for (int w = threadIdx.x; w < N; w += blockDim.x) {
             const int32_t v = x0row[w] - (Erow ? Erow[w] : 0) - (L.worker ? dcor[w] : 0);
             x[w] = v > 0 ? v : 0;
-            lxs[w] = log1pf((float)(v > 0 ? v : 0));
+            lxs[w] = log1p_stock(v > 0 ? v : 0);
             cons[w] = 0;
         }
         // the first order's region rows into buffer 0; the next order's region and time
@@ -185,7 +185,7 @@ __global__ __launch_bounds__(WPB * 64, 16 / WPB) void k_walk_mlp(Prob P, Plan L,
                         const int xa = x[a], ca = cons[a], ia = pos[a], last = sl[nf - 1];
                         sh = q < xa ? q : xa;
                         x[a] = xa - sh;
-                        lxs[a] = log1pf((float)(xa - sh));
+                        lxs[a] = log1p_stock(xa - sh);
                         cons[a] = ca + q;
                         if (xa == sh) { // emptied: the list's last entry takes its place
                             sl[ia] = last;
