@@ -55,6 +55,7 @@ hipError_t launch_scores(const Prob &P, const float *params, int layers, const f
                          int b, int r, const int32_t *xrow, float *out, hipStream_t st);
 // grad.hip
 size_t grad_lds(int N, int layers);
+int grad_wg_per_cu(int N);
 size_t grad_part_bytes(int n_wg, int R, int layers);
 hipError_t launch_grad(const Prob &P, const Plan &L, const float *params, int layers,
                        const float *costT, const float *adv, float *logp_sorted, double *part,
@@ -1397,7 +1398,8 @@ pk_status pk_policy_grad(const pk_problem *problem, const pk_policy *policy,
                            hipMemcpyHostToDevice, st));
     Prob P = make_prob(problem, d, to);
     HIP_TRY(setup_ctl(L, d.n_traj, 1, st));
-    const int n_wg = std::min(GRAD_MAX_WG, std::max(1, num_cus())); // one workgroup per CU
+    // two workgroups per CU where their LDS fits (two waves per SIMD), else one
+    const int n_wg = std::min(GRAD_MAX_WG, std::max(1, num_cus() * grad_wg_per_cu(d.N)));
     if (d.total > 0) {
         // states of the fixed actions: the actions are the cache, its consumption scanned
         HIP_TRY(setup_plan(P, L, actions, validate, true, (int32_t)sz.n_seg_max, setup_scr, st));

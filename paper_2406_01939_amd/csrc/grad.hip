@@ -10,21 +10,24 @@
 // States: with the actions fixed, a run's entry state is x0 - E (the segmented scan of
 // the runs' consumption, as in the Picard passes) and the run is walked applying the
 // fixed actions.  One workgroup of four waves per run, order by order, over the list of
-// warehouses with stock (rows):
-//   1. the waves score the rows with the MFMA scorer (no noise); wave 0 forms the softmax
-//      statistics and log pi(a_t);
-//   2. the rows are taken 64 at a time, one 16-row tile per wave.  A wave recomputes its
-//      tile's activations (D layout: lane holds unit 16t + 4(l/16) + v of row l%16), forms
-//      the layer-2 deltas dl = ds w3 [h2 > 0] and the layer-1 deltas d1 = [h1 > 0] W2^T dl
-//      (MFMA, W2^T from LDS), and keeps per-lane sums of the row-summed gradients (b1,
-//      b2, w3, the cost and log1p(x) columns of W1);
-//   3. h1 and dl of the 64 rows are stored by unit in LDS, so that dW2 = sum over rows of
-//      dl h1^T is an MFMA product over the rows; each wave owns 16 output units of dW2;
-//   4. per order the FP32 sums go into FP64 accumulators held by the lanes (each value
-//      owned by one lane of one wave); the order's d1 summed over its rows gives the
-//      embedding columns of dW1 (outer product with E[r]) and dE[r] (W1's embedding
-//      columns times it), the latter into a per-workgroup FP64 table in global memory.
-// At the end every wave writes its FP64 partial sums as one record and a final kernel sums
+// warehouses with stock (rows), 16-row tiles, wave w taking tiles w, w + 4, ...:
+//   1. each wave scores its tiles with the policy scorer's arithmetic (layer 1 from the
+//      per-region table on the vector ALU, layer 2 on MFMA; D layout: lane holds unit
+//      16t + 4(l/16) + v of row l%16) and keeps the activations of its first tile in
+//      registers; a running (max, sum of exp) per lane gives the wave's softmax partials,
+//      which the waves combine after one barrier;
+//   2. per chunk of 64 rows (one tile per wave) a wave forms its tile's layer-2 deltas
+//      dl = ds w3 [h2 > 0] and layer-1 deltas d1 = [h1 > 0] W2^T dl (MFMA, W2^T read from
+//      the staged W2) and sums the row-summed gradients of the tile (b1, w3, the cost and
+//      log1p(x) columns of W1) over its rows; later tiles are scored again here;
+//   3. h1 and dl of the chunk's 64 rows are stored by unit in LDS, so that dW2 = sum over
+//      rows of dl h1^T is an MFMA product over the rows; each wave owns 16 output units of
+//      dW2 (and of db2, the row sums of its dl rows);
+//   4. the order's d1 summed over its rows gives the embedding columns of dW1 (outer
+//      product with E[r]) and dE[r] (W1's embedding columns times it), the latter into a
+//      per-workgroup FP64 table in global memory.
+// Each lane sums its share of the gradient over runs of about 2048 orders in FP32 and adds
+// it to its wave's FP64 record (each value owned by one lane); a final kernel sums
 // the records in a fixed order: the gradient is reproducible bit for bit.
 #include "mlp_device.h"
 
@@ -35,9 +38,13 @@ namespace {
 using namespace mlpdev;
 
 constexpr int H = 64;
-constexpr int GW = 4;  // waves per workgroup
-constexpr int RS = 68; // LDS row stride (floats) of the by-unit tensors: 16 rows of a
-                       // half wave's D-layout stores start 16 banks apart
+constexpr int GW = 4;   // waves per workgroup
+constexpr int RS = 68;  // LDS row stride (floats) of the by-unit tensors: 16 rows of a
+                        // half wave's D-layout stores start 16 banks apart
+constexpr int W1ES = 17; // row stride of W1's embedding columns in LDS
+constexpr int FLUSH = 2048; // orders between additions of the FP32 sums to the FP64 records
+constexpr int KEEP = 1;  // tiles per wave whose activations stay in registers from the
+                         // scores to the backward pass (later tiles are scored again)
 
 __host__ __device__ inline int acc_count(int layers) // W1 b1 (W2 b2) w3 b3
 {
@@ -70,9 +77,78 @@ __device__ __forceinline__ float reduce_scatter16(const float v[16])
     return keep + __shfl_xor(send, 1, WAVE);
 }
 
-__global__ __launch_bounds__(256) void k_grad(Prob P, Plan L, const float *params, int layers,
-                                              const float *costT, const float *adv,
-                                              float *logp_sorted, double *part, double *dE_part)
+// Activations and score of one 16-row tile (the policy scorer's arithmetic): h1, h2 in the
+// D layout, the score of row l%16 returned in every lane of that column.
+__device__ __forceinline__ float tile_forward(const float *W2s, const float *Vs, bool two,
+                                              float b3, const float *prL, float cost, float lx,
+                                              v4f h1[4], v4f h2[4])
+{
+    const int i = __lane_id() & 15, g = __lane_id() >> 4;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const float4 wc = *(const float4 *)(Vs + 16 * c + 4 * g);
+        const float4 wl = *(const float4 *)(Vs + 64 + 16 * c + 4 * g);
+        const float4 pv = *(const float4 *)(prL + 16 * c + 4 * g);
+        const float a[4] = {wc.x, wc.y, wc.z, wc.w}, b[4] = {wl.x, wl.y, wl.z, wl.w};
+        const float pr[4] = {pv.x, pv.y, pv.z, pv.w};
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const float z = fmaf(b[v], lx, fmaf(a[v], cost, pr[v]));
+            h1[c][v] = z > 0.f ? z : 0.f;
+        }
+    }
+    if (two) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const float4 bb = *(const float4 *)(Vs + 128 + 16 * t + 4 * g);
+            v4f acc = {bb.x, bb.y, bb.z, bb.w};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const float4 wv = *(const float4 *)(W2s + (16 * t + i) * W2S + 16 * c + 4 * g);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wv.x, h1[c][0], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wv.y, h1[c][1], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wv.z, h1[c][2], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wv.w, h1[c][3], acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[v] = acc[v] > 0.f ? acc[v] : 0.f;
+            h2[t] = acc;
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) h2[t] = h1[t];
+    }
+    float part = 0.f;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const float4 w = *(const float4 *)(Vs + 192 + 16 * t + 4 * g);
+        part = fmaf(w.x, h2[t][0], part);
+        part = fmaf(w.y, h2[t][1], part);
+        part = fmaf(w.z, h2[t][2], part);
+        part = fmaf(w.w, h2[t][3], part);
+    }
+    const float p16 = __shfl_xor(part, 16, WAVE);
+    const float s01 = (__lane_id() & 16) ? p16 + part : part + p16;
+    const float p32 = __shfl_xor(s01, 32, WAVE);
+    const float tot = (__lane_id() & 32) ? p32 + s01 : s01 + p32;
+    return tot + b3;
+}
+
+// Running softmax partials of one lane over the rows it holds: (max, sum of exp(s - max)).
+__device__ __forceinline__ void online_lse(float &mx, float &se, float s)
+{
+    if (s > mx) {
+        se = se * expf(mx - s) + 1.f;
+        mx = s;
+    } else {
+        se += expf(s - mx);
+    }
+}
+
+__global__ __launch_bounds__(256, 2) void k_grad(Prob P, Plan L, const float *params, int layers,
+                                                 const float *costT, const float *region,
+                                                 const float *adv, float *logp_sorted,
+                                                 double *part, double *dE_part)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int N = P.N, R = P.R;
@@ -80,43 +156,82 @@ __global__ __launch_bounds__(256) void k_grad(Prob P, Plan L, const float *param
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x % WAVE;
     const int m = lane & 15, g = lane >> 4;
     const bool two = layers == 2;
-    float *W2s = (float *)smem;           // [64][W2S] W2 by output unit (the scorer's operands)
-    float *W2T = W2s + 64 * W2S;          // [64][RS] W2 by input unit: W2T[i][o] = W2[o][i]
-    float *H1T = W2T + H * RS;            // [64][RS] h1 of the chunk's 64 rows, by unit
+    float *W2s = (float *)smem;           // [64][W2S] W2 by output unit
+    float *Vs = W2s + 64 * W2S;           // [4][64] W1[:,0], W1[:,1], b2, w3
+    float *H1T = Vs + 4 * 64;             // [64][RS] h1 of the chunk's 64 rows, by unit
     float *DLT = H1T + H * RS;            // [64][RS] layer-2 deltas of the chunk, by unit
-    float *red = DLT + H * RS;            // [GW][64] each wave's d1 summed over its rows
-    float *d1o = red + GW * H;            // [64] the order's d1 summed over all rows
-    float *Ebuf = d1o + H;                // [16] embedding of the order's region
-    float *misc = Ebuf + 16;              // [0] max score, [1] log Z
-    int32_t *imisc = (int32_t *)(misc + 4); // [0] skip the order
-    int32_t *x = imisc + 4;               // [N] stock
+    float *W1E = DLT + H * RS;            // [64][W1ES] W1's embedding columns
+    float *red = W1E + H * W1ES;          // [GW][64] each wave's d1 summed over its rows
+    float *prL = red + GW * H;            // [2][64] region term of layer 1, by order parity
+    float *ErL = prL + 2 * H;             // [2][16] embedding of the order's region
+    float *smx = ErL + 2 * 16;            // [GW] wave softmax max, [GW] sum
+    int32_t *x = (int32_t *)(smx + 2 * GW); // [N] stock
     float *sbuf = (float *)(x + N);       // [N] scores
     int32_t *sl = (int32_t *)(sbuf + N);  // [N] warehouses with stock
     int32_t *pos = sl + N;                // [N] their index in sl
     int32_t *nfp = pos + N;               // [1] how many
     float *lxs = (float *)(nfp + 4);      // [N] log1p of each warehouse's stock
-    // parameter views
     const float *W1 = params + (int64_t)R * 16;
-    const float *b1 = W1 + H * 18;
-    const float *W2 = b1 + H;
-    stage_w2(W2s, params, R, layers); // read after the barrier below
-    MlpLane mw;
-    load_mlp(mw, params, R, layers, W2s);
-    if (two)
-        for (int i = threadIdx.x; i < H * H; i += blockDim.x) W2T[(i % H) * RS + i / H] = W2[i];
-    float w1e[16]; // W1[lane][2 + k]: the embedding columns (wave 0 forms dE with them)
-#pragma unroll
-    for (int k = 0; k < 16; ++k) w1e[k] = W1[lane * 18 + 2 + k];
-    __syncthreads();
-    // FP64 accumulators, each value owned by one lane of one wave
-    double gW2[16];                       // units o = 16 wave + 4g + v, inputs i = 16T + m
-#pragma unroll
-    for (int k = 0; k < 16; ++k) gW2[k] = 0.0;
-    double gb1 = 0.0, gb2 = 0.0, gw3 = 0.0, gc0 = 0.0, gc1 = 0.0, gb3 = 0.0, gobj = 0.0;
-    double gW1E[4] = {0.0, 0.0, 0.0, 0.0}; // W1[tid / 4][2 + 4 (tid % 4) + k]
+    const float b3 = W1[H * 18 + H + (two ? H * H + H : 0) + H];
+    stage_w2(W2s, params, R, layers);
+    stage_vectors(Vs, params, R, layers);
+    for (int i = threadIdx.x; i < H * 16; i += blockDim.x)
+        W1E[(i >> 4) * W1ES + (i & 15)] = W1[(i >> 4) * 18 + 2 + (i & 15)];
+    // the region term and embedding of order p into slot p & 1 (threads 0..79), written
+    // during order p - 1 and read after its closing barrier
+    auto stage_region = [&](int p) {
+        const int r = L.s_region[p], sl2 = p & 1;
+        if (threadIdx.x < H) prL[sl2 * H + threadIdx.x] = region[(int64_t)r * H + threadIdx.x];
+        else if (threadIdx.x < H + 16)
+            ErL[sl2 * 16 + threadIdx.x - H] = params[(int64_t)r * 16 + threadIdx.x - H];
+    };
+    // this wave's FP64 record (zeroed before the launch; each value owned by one lane), to
+    // which the FP32 sums of every run are added
+    double *rec = part + ((int64_t)blockIdx.x * GW + wave) * (nacc + 1);
+    const int oW1 = 0, ob1 = H * 18, oW2 = ob1 + H, ob2 = oW2 + (two ? H * H : 0);
+    const int ow3 = two ? ob2 + H : ob1 + H, ob3 = ow3 + H;
+    const int us = 16 * (m >> 2) + 4 * g + (m & 3); // unit of this lane's scattered sums
+    double gobj = 0.0;
     const v4f zero4 = {0.f, 0.f, 0.f, 0.f};
-    v4f aW2[4] = {zero4, zero4, zero4, zero4}; // this order's dW2 share (FP32)
     double *dEw = dE_part + (int64_t)blockIdx.x * R * 16;
+    // FP32 sums of this lane's share over the orders since the last flush, added to the
+    // wave's FP64 record every FLUSH orders or more (at the end of a run) and at the end
+    v4f aW2[4] = {zero4, zero4, zero4, zero4}; // dW2: units o = 16 wave + 4g + v, inputs 16T + m
+    float sb1 = 0.f, sw3 = 0.f, sc0 = 0.f, sc1 = 0.f, sb2 = 0.f, sb3 = 0.f;
+    float sW1E[4] = {0.f, 0.f, 0.f, 0.f}; // W1[tid / 4][2 + 4 (tid % 4) + k]
+    int pending = 0;
+    auto flush = [&]() {
+        if (two) {
+#pragma unroll
+            for (int T = 0; T < 4; ++T)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    rec[oW2 + (16 * wave + 4 * g + v) * H + 16 * T + m] += (double)aW2[T][v];
+            // db2 of unit 16 wave + m: the four lane groups' row sums, fixed order
+            const float p16 = __shfl_xor(sb2, 16, WAVE);
+            const float s01 = (lane & 16) ? p16 + sb2 : sb2 + p16;
+            const float p32 = __shfl_xor(s01, 32, WAVE);
+            const float tb2 = (lane & 32) ? p32 + s01 : s01 + p32;
+            if (g == 0) rec[ob2 + 16 * wave + m] += (double)tb2;
+        }
+        rec[ob1 + us] += (double)sb1;
+        rec[oW1 + us * 18] += (double)sc0;
+        rec[oW1 + us * 18 + 1] += (double)sc1;
+        rec[ow3 + us] += (double)sw3;
+        {
+            const int i = threadIdx.x >> 2, k0 = 4 * (threadIdx.x & 3);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) rec[oW1 + i * 18 + 2 + k0 + k] += (double)sW1E[k];
+        }
+        float t3 = sb3; // lanes of group 0 hold their rows' sums; butterfly in a fixed order
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) t3 += __shfl_xor(t3, d, WAVE);
+        if (lane == 0) rec[ob3] += (double)t3;
+        aW2[0] = aW2[1] = aW2[2] = aW2[3] = zero4;
+        sb1 = sw3 = sc0 = sc1 = sb2 = sb3 = 0.f;
+        sW1E[0] = sW1E[1] = sW1E[2] = sW1E[3] = 0.f;
+        pending = 0;
+    };
     const int n_items = L.ctl->n_sr;
     for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
         const int s = item;
@@ -133,6 +248,7 @@ __global__ __launch_bounds__(256) void k_grad(Prob P, Plan L, const float *param
             x[w] = v > 0 ? v : 0;
             lxs[w] = log1p_stock(v > 0 ? v : 0);
         }
+        if (lo < hi) stage_region(lo);
         __syncthreads();
         build_stock_list(x, N, sl, pos, nfp);
         __syncthreads();
@@ -140,92 +256,110 @@ __global__ __launch_bounds__(256) void k_grad(Prob P, Plan L, const float *param
             const int r = L.s_region[p];
             const int a = L.s_alpha[p];
             const float A = adv[L.perm[p]];
-            const float *cr = costT + ((int64_t)b * R + r) * N;
-            if (threadIdx.x < 16) Ebuf[threadIdx.x] = mw.E[(int64_t)r * 16 + threadIdx.x];
-            __syncthreads();
             const int nf = *nfp;
-            // 1. scores of the rows
-            const int ntiles = (nf + 15) >> 4;
-            for (int tile = wave; tile < ntiles; tile += GW) {
-                const int i = tile * 16 + m;
-                const bool valid = i < nf;
-                const int w = valid ? sl[i] : 0;
-                float f[5];
-                lane_features(f, valid ? cr[w] : 0.f, valid ? lxs[w] : 0.f, Ebuf);
-                const float sc = mlp_tile(mw, f);
-                if (lane < 16 && valid) sbuf[w] = sc;
-            }
-            __syncthreads();
-            if (wave == 0) {
+            const bool bad = a >= 0 ? (a >= N || x[a] <= 0) : nf > 0;
+            if (p + 1 < hi) stage_region(p + 1);
+            const float *prO = prL + (p & 1) * H, *ErO = ErL + (p & 1) * 16;
+            if (!bad && nf > 1) {
+                const float *cr = costT + ((int64_t)b * R + r) * N;
+                const double dEold = wave == 0 && lane < 16 ? dEw[(int64_t)r * 16 + lane] : 0.0;
+                // 1. scores; the first KEEP tiles' activations stay in registers
+                const int ntiles = (nf + 15) >> 4;
+                v4f k1[KEEP][4], k2[KEEP][4];
+                float ks[KEEP], kc[KEEP], kl[KEEP];
+                int kw[KEEP];
+                float lmx = -INFINITY, lse = 0.f;
+#pragma unroll
+                for (int j = 0; j < KEEP; ++j) {
+                    const int i = (wave + GW * j) * 16 + m;
+                    const bool valid = i < nf;
+                    const int w = valid ? sl[i] : 0;
+                    kw[j] = valid ? w : -1;
+                    kc[j] = valid ? cr[w] : 0.f;
+                    kl[j] = valid ? lxs[w] : 0.f;
+                    if (wave + GW * j < ntiles) {
+                        ks[j] = tile_forward(W2s, Vs, two, b3, prO, kc[j], kl[j], k1[j], k2[j]);
+                        if (valid) {
+                            online_lse(lmx, lse, ks[j]);
+                            if (g == 0) sbuf[w] = ks[j];
+                        }
+                    }
+                }
+                for (int tile = wave + KEEP * GW; tile < ntiles; tile += GW) {
+                    const int i = tile * 16 + m;
+                    const bool valid = i < nf;
+                    const int w = valid ? sl[i] : 0;
+                    v4f h1[4], h2[4];
+                    const float sc = tile_forward(W2s, Vs, two, b3, prO, valid ? cr[w] : 0.f,
+                                                  valid ? lxs[w] : 0.f, h1, h2);
+                    if (valid) {
+                        online_lse(lmx, lse, sc);
+                        if (g == 0) sbuf[w] = sc;
+                    }
+                }
+                // the wave's partials over the rows of lane group 0 (each row once), fixed order
+                {
+                    float wmx = g == 0 ? lmx : -INFINITY;
+#pragma unroll
+                    for (int d = 32; d > 0; d >>= 1) wmx = fmaxf(wmx, __shfl_xor(wmx, d, WAVE));
+                    float ws = g == 0 && lmx != -INFINITY ? lse * expf(lmx - wmx) : 0.f;
+#pragma unroll
+                    for (int d = 32; d > 0; d >>= 1) ws += __shfl_xor(ws, d, WAVE);
+                    if (lane == 0) {
+                        smx[wave] = wmx;
+                        smx[GW + wave] = ws;
+                    }
+                }
+                __syncthreads();
                 float mx = -INFINITY;
-                for (int i = lane; i < nf; i += WAVE) mx = fmaxf(mx, sbuf[sl[i]]);
 #pragma unroll
-                for (int d = 32; d > 0; d >>= 1) mx = fmaxf(mx, __shfl_xor(mx, d, WAVE));
+                for (int w = 0; w < GW; ++w) mx = fmaxf(mx, smx[w]);
                 float se = 0.f;
-                for (int i = lane; i < nf; i += WAVE) se += expf(sbuf[sl[i]] - mx);
 #pragma unroll
-                for (int d = 32; d > 0; d >>= 1) se += __shfl_xor(se, d, WAVE);
-                if (lane == 0) {
-                    const bool bad = a >= 0 ? (a >= N || x[a] <= 0) : nf > 0;
-                    if (bad) atomicOr(&L.ctl->error, 8);
-                    float lp = 0.f;
-                    if (!bad && nf > 1) lp = sbuf[a] - (mx + logf(se));
+                for (int w = 0; w < GW; ++w) se += smx[w] == -INFINITY ? 0.f : smx[GW + w] * expf(smx[w] - mx);
+                const float lz = logf(se);
+                if (threadIdx.x == 0) {
+                    const float lp = sbuf[a] - (mx + lz);
                     logp_sorted[p] = lp;
                     gobj += (double)A * (double)lp;
-                    misc[0] = mx;
-                    misc[1] = logf(se);
-                    imisc[0] = bad || nf <= 1 || A == 0.f;
                 }
-            }
-            __syncthreads();
-            if (!imisc[0]) {
-                const float mx = misc[0], lz = misc[1];
-                float pb1[16], pb2[16], pw3[16], pc0[16], pc1[16], pb3 = 0.f;
-#pragma unroll
-                for (int k = 0; k < 16; ++k) pb1[k] = pb2[k] = pw3[k] = pc0[k] = pc1[k] = 0.f;
-                for (int c0 = 0; c0 < nf; c0 += 64) {
-                    const int row0 = c0 + 16 * wave; // this wave's tile of the chunk
-                    if (row0 < nf) {
-                        // 2. activations and deltas of the tile
-                        const int i = row0 + m;
-                        const bool valid = i < nf;
-                        const int w = valid ? sl[i] : 0;
-                        const float cost = valid ? cr[w] : 0.f, lx = valid ? lxs[w] : 0.f;
-                        float f[5];
-                        lane_features(f, cost, lx, Ebuf);
-                        v4f h1[4], h2[4], d1[4];
-                        mlp_hidden(mw, f, h1, h2);
-                        const float ds =
-                            valid ? A * ((w == a ? 1.f : 0.f) - expf(sbuf[w] - mx - lz)) : 0.f;
-                        if (g == 0) pb3 += ds;
+                if (A != 0.f) {
+                    float o1 = 0.f; // this order's d1 summed over this wave's rows (scattered)
+                    // 2.-3. backward of one tile of this wave (rows past nf: zero deltas)
+                    auto backward = [&](const v4f h1[4], const v4f h2[4], float sc, int w,
+                                        float cost, float lx) {
+                        const float ds = w >= 0 ? A * ((w == a ? 1.f : 0.f) - expf(sc - mx - lz)) : 0.f;
+                        if (g == 0) sb3 += ds;
+                        v4f d1[4];
+                        float t3[16];
                         if (two) {
                             v4f dl[4];
 #pragma unroll
-                            for (int t = 0; t < 4; ++t)
+                            for (int t = 0; t < 4; ++t) {
+                                const float4 w3v = *(const float4 *)(Vs + 192 + 16 * t + 4 * g);
+                                const float w3a[4] = {w3v.x, w3v.y, w3v.z, w3v.w};
 #pragma unroll
                                 for (int v = 0; v < 4; ++v) {
-                                    dl[t][v] = h2[t][v] > 0.f ? ds * mw.w3[t * 4 + v] : 0.f;
-                                    pw3[t * 4 + v] = fmaf(ds, h2[t][v], pw3[t * 4 + v]);
-                                    pb2[t * 4 + v] += dl[t][v];
+                                    dl[t][v] = h2[t][v] > 0.f ? ds * w3a[v] : 0.f;
+                                    t3[t * 4 + v] = ds * h2[t][v];
                                 }
-                            // d1 = [h1 > 0] W2^T dl: A = W2^T (unit i = 16T + m, chunk units
-                            // o = 16t + 4g + v), B = dl in its D layout
+                            }
+                            // d1 = [h1 > 0] W2^T dl: A operand W2[o][i] (i = 16T + m, chunk
+                            // units o = 16t + 4g + v), B = dl in its D layout
 #pragma unroll
                             for (int T = 0; T < 4; ++T) {
                                 v4f acc = zero4;
 #pragma unroll
                                 for (int t = 0; t < 4; ++t) {
-                                    const float4 wv =
-                                        *(const float4 *)(W2T + (16 * T + m) * RS + 16 * t + 4 * g);
-                                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wv.x, dl[t][0], acc, 0, 0, 0);
-                                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wv.y, dl[t][1], acc, 0, 0, 0);
-                                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wv.z, dl[t][2], acc, 0, 0, 0);
-                                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wv.w, dl[t][3], acc, 0, 0, 0);
+                                    const float *wp = W2s + (16 * t + 4 * g) * W2S + 16 * T + m;
+                                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wp[0], dl[t][0], acc, 0, 0, 0);
+                                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wp[W2S], dl[t][1], acc, 0, 0, 0);
+                                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wp[2 * W2S], dl[t][2], acc, 0, 0, 0);
+                                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(wp[3 * W2S], dl[t][3], acc, 0, 0, 0);
                                 }
 #pragma unroll
                                 for (int v = 0; v < 4; ++v) d1[T][v] = h1[T][v] > 0.f ? acc[v] : 0.f;
                             }
-                            // 3. the tile's rows of h1 and dl, by unit
 #pragma unroll
                             for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -236,39 +370,48 @@ __global__ __launch_bounds__(256) void k_grad(Prob P, Plan L, const float *param
                                 }
                         } else {
 #pragma unroll
-                            for (int t = 0; t < 4; ++t)
+                            for (int t = 0; t < 4; ++t) {
+                                const float4 w3v = *(const float4 *)(Vs + 192 + 16 * t + 4 * g);
+                                const float w3a[4] = {w3v.x, w3v.y, w3v.z, w3v.w};
 #pragma unroll
                                 for (int v = 0; v < 4; ++v) {
-                                    d1[t][v] = h1[t][v] > 0.f ? ds * mw.w3[t * 4 + v] : 0.f;
-                                    pw3[t * 4 + v] = fmaf(ds, h1[t][v], pw3[t * 4 + v]);
+                                    d1[t][v] = h1[t][v] > 0.f ? ds * w3a[v] : 0.f;
+                                    t3[t * 4 + v] = ds * h1[t][v];
                                 }
+                            }
                         }
+                        // the tile's row sums (scattered over the lanes of each group), one
+                        // at a time (kept apart so that their temporaries do not pile up)
+                        sw3 += reduce_scatter16(t3);
+                        float tt[16];
 #pragma unroll
                         for (int t = 0; t < 4; ++t)
 #pragma unroll
-                            for (int v = 0; v < 4; ++v) {
-                                pb1[t * 4 + v] += d1[t][v];
-                                pc0[t * 4 + v] = fmaf(d1[t][v], cost, pc0[t * 4 + v]);
-                                pc1[t * 4 + v] = fmaf(d1[t][v], lx, pc1[t * 4 + v]);
-                            }
-                    } else if (two) { // no rows: zero deltas (and finite activations)
+                            for (int v = 0; v < 4; ++v) tt[t * 4 + v] = d1[t][v];
+                        o1 += reduce_scatter16(tt);
+                        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                         for (int t = 0; t < 4; ++t)
 #pragma unroll
-                            for (int v = 0; v < 4; ++v) {
-                                const int at = (16 * t + 4 * g + v) * RS + 16 * wave + m;
-                                H1T[at] = 0.f;
-                                DLT[at] = 0.f;
-                            }
-                    }
-                    if (two) {
-                        __syncthreads();
-                        // dW2[o][i] += sum over the chunk's rows of dl[o] h1[i]: this wave's
-                        // units o = 16 wave + ..; rows 16g + c (c < 16) are lane group g's
+                            for (int v = 0; v < 4; ++v) tt[t * 4 + v] = d1[t][v] * cost;
+                        sc0 += reduce_scatter16(tt);
+                        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                        for (int t = 0; t < 4; ++t)
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) tt[t * 4 + v] = d1[t][v] * lx;
+                        sc1 += reduce_scatter16(tt);
+                    };
+                    // dW2 over the chunk's rows (this wave's 16 output units), and their db2
+                    auto chunk_dw2 = [&]() {
                         const float4 *ap = (const float4 *)(DLT + (16 * wave + m) * RS + 16 * g);
                         const float4 a0 = ap[0], a1 = ap[1], a2 = ap[2], a3 = ap[3];
                         const float av[16] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w,
                                               a2.x, a2.y, a2.z, a2.w, a3.x, a3.y, a3.z, a3.w};
+                        float rs = 0.f;
+#pragma unroll
+                        for (int c = 0; c < 16; ++c) rs += av[c];
+                        sb2 += rs;
 #pragma unroll
                         for (int T = 0; T < 4; ++T) {
                             const float4 *bp = (const float4 *)(H1T + (16 * T + m) * RS + 16 * g);
@@ -279,50 +422,86 @@ __global__ __launch_bounds__(256) void k_grad(Prob P, Plan L, const float *param
                             for (int c = 0; c < 16; ++c)
                                 aW2[T] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[c], bv[c], aW2[T], 0, 0, 0);
                         }
-                        __syncthreads();
+                    };
+                    auto zero_tile = [&]() { // this wave has no tile in the chunk
+#pragma unroll
+                        for (int t = 0; t < 4; ++t)
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) {
+                                const int at = (16 * t + 4 * g + v) * RS + 16 * wave + m;
+                                H1T[at] = 0.f;
+                                DLT[at] = 0.f;
+                            }
+                    };
+                    const int nch = (nf + 63) >> 6;
+#pragma unroll
+                    for (int j = 0; j < KEEP; ++j) {
+                        if (j < nch) {
+                            if (wave + GW * j < ntiles)
+                                backward(k1[j], k2[j], ks[j], kw[j], kc[j], kl[j]);
+                            else if (two)
+                                zero_tile();
+                            if (two) {
+                                __syncthreads();
+                                chunk_dw2();
+                                if (j + 1 < nch) __syncthreads();
+                            }
+                        }
+                    }
+                    for (int j = KEEP; j < nch; ++j) {
+                        const int tile = wave + GW * j;
+                        if (tile < ntiles) {
+                            const int i = tile * 16 + m;
+                            const bool valid = i < nf;
+                            const int w = valid ? sl[i] : 0;
+                            const float cost = valid ? cr[w] : 0.f, lx = valid ? lxs[w] : 0.f;
+                            v4f h1[4], h2[4];
+                            const float sc = tile_forward(W2s, Vs, two, b3, prO, cost, lx, h1, h2);
+                            backward(h1, h2, sc, valid ? w : -1, cost, lx);
+                        } else if (two) {
+                            zero_tile();
+                        }
+                        if (two) {
+                            __syncthreads();
+                            chunk_dw2();
+                            if (j + 1 < nch) __syncthreads();
+                        }
+                    }
+                    // 4. the order's d1 over all rows: embedding columns of dW1 and dE[r]
+                    sb1 += o1;
+                    red[wave * H + us] = o1;
+                    __syncthreads();
+                    auto d1o_at = [&](int u) { // fixed order over the waves
+                        return ((red[u] + red[H + u]) + red[2 * H + u]) + red[3 * H + u];
+                    };
+                    {
+                        const float d = d1o_at(threadIdx.x >> 2);
+                        const float4 ev = *(const float4 *)(ErO + 4 * (threadIdx.x & 3));
+                        sW1E[0] = fmaf(ev.x, d, sW1E[0]);
+                        sW1E[1] = fmaf(ev.y, d, sW1E[1]);
+                        sW1E[2] = fmaf(ev.z, d, sW1E[2]);
+                        sW1E[3] = fmaf(ev.w, d, sW1E[3]);
+                    }
+                    if (wave == 0) { // dE[r][k] += sum_j W1[j][2 + k] d1o[j]
+                        const float d = d1o_at(lane);
+                        float v[16];
+#pragma unroll
+                        for (int k = 0; k < 16; ++k) v[k] = W1E[lane * W1ES + k] * d;
+                        float t = reduce_scatter16(v);
+                        t = t + __shfl_xor(t, 16, WAVE);
+                        t = t + __shfl_xor(t, 32, WAVE);
+                        if (lane < 16) dEw[(int64_t)r * 16 + lane] = dEold + (double)t;
                     }
                 }
-                // 4. the order's sums into FP64
-                if (two) {
-#pragma unroll
-                    for (int T = 0; T < 4; ++T) {
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) gW2[T * 4 + v] += (double)aW2[T][v];
-                        aW2[T] = zero4;
-                    }
-                    gb2 += (double)reduce_scatter16(pb2);
+            } else {
+                if (threadIdx.x == 0) {
+                    if (bad) atomicOr(&L.ctl->error, 8);
+                    logp_sorted[p] = 0.f;
                 }
-                const float rb1 = reduce_scatter16(pb1);
-                gb1 += (double)rb1;
-                gw3 += (double)reduce_scatter16(pw3);
-                gc0 += (double)reduce_scatter16(pc0);
-                gc1 += (double)reduce_scatter16(pc1);
-                gb3 += (double)pb3;
-                red[wave * H + 16 * (m >> 2) + 4 * g + (m & 3)] = rb1;
-                __syncthreads();
-                if (threadIdx.x < H)
-                    d1o[threadIdx.x] = ((red[threadIdx.x] + red[H + threadIdx.x]) +
-                                        red[2 * H + threadIdx.x]) + red[3 * H + threadIdx.x];
-                __syncthreads();
-                {
-                    const double d = (double)d1o[threadIdx.x >> 2];
-                    const int k0 = 4 * (threadIdx.x & 3);
-#pragma unroll
-                    for (int k = 0; k < 4; ++k) gW1E[k] += (double)Ebuf[k0 + k] * d;
-                }
-                if (wave == 0) { // dE[r][k] += sum_j W1[j][2 + k] d1o[j]
-                    const float d = d1o[lane];
-                    float v[16];
-#pragma unroll
-                    for (int k = 0; k < 16; ++k) v[k] = w1e[k] * d;
-                    float t = reduce_scatter16(v);
-                    t = t + __shfl_xor(t, 16, WAVE);
-                    t = t + __shfl_xor(t, 32, WAVE);
-                    if (lane < 16) dEw[(int64_t)r * 16 + lane] += (double)t;
-                }
+                __syncthreads(); // every thread has made the test above
             }
-            __syncthreads();
-            if (threadIdx.x == 0 && a >= 0 && a < N) { // the fixed action
+            // the fixed action: every read of this order's state is behind a barrier
+            if (threadIdx.x == 0 && a >= 0 && a < N) {
                 const int q = L.s_qty[p];
                 const int xa = x[a];
                 const int nx = xa - (q < xa ? q : xa);
@@ -332,33 +511,10 @@ __global__ __launch_bounds__(256) void k_grad(Prob P, Plan L, const float *param
             }
             __syncthreads();
         }
+        pending += hi - lo;
+        if (pending >= FLUSH) flush();
     }
-    // this wave's record (the records were zeroed; every value is written by its owner)
-    double *rec = part + ((int64_t)blockIdx.x * GW + wave) * (nacc + 1);
-    const int oW1 = 0, ob1 = H * 18, oW2 = ob1 + H, ob2 = oW2 + (two ? H * H : 0);
-    const int ow3 = two ? ob2 + H : ob1 + H, ob3 = ow3 + H;
-    const int u = 16 * (m >> 2) + 4 * g + (m & 3); // unit of this lane's scattered sums
-    rec[ob1 + u] = gb1;
-    rec[oW1 + u * 18] = gc0;
-    rec[oW1 + u * 18 + 1] = gc1;
-    rec[ow3 + u] = gw3;
-    if (two) {
-        rec[ob2 + u] = gb2;
-#pragma unroll
-        for (int T = 0; T < 4; ++T)
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-                rec[oW2 + (16 * wave + 4 * g + v) * H + 16 * T + m] = gW2[T * 4 + v];
-    }
-    {
-        const int i = threadIdx.x >> 2, k0 = 4 * (threadIdx.x & 3);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) rec[oW1 + i * 18 + 2 + k0 + k] = gW1E[k];
-    }
-    double t3 = gb3; // lanes of group 0 hold their rows' sums; butterfly in a fixed order
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1) t3 += __shfl_xor(t3, d, WAVE);
-    if (lane == 0) rec[ob3] = t3;
+    flush();
     if (wave == 0 && lane == 0) rec[nacc] = gobj;
 }
 
@@ -402,8 +558,11 @@ __global__ void k_unpermute_f32(const int32_t *perm, const float *src, float *ds
 size_t grad_lds(int N, int layers)
 {
     (void)layers;
-    return w2_lds_bytes() + (size_t)(3 * H * RS + GW * H + H + 16 + 4) * 4 + 16 + (size_t)N * 20 + 32;
+    return w2_lds_bytes() + vec_lds_bytes() +
+           (size_t)(2 * H * RS + H * W1ES + GW * H + 2 * H + 2 * 16 + 2 * GW) * 4 + (size_t)N * 20 + 16;
 }
+
+int grad_wg_per_cu(int N) { return 2 * grad_lds(N, 2) <= 160 * 1024 ? 2 : 1; }
 
 size_t grad_part_bytes(int n_wg, int R, int layers)
 {
@@ -419,8 +578,9 @@ hipError_t launch_grad(const Prob &P, const Plan &L, const float *params, int la
     double *dE_part = part + n_rec;
     const int64_t nz = n_rec + (int64_t)n_wg * P.R * 16; // records and dE tables start at 0
     hipLaunchKernelGGL(k_zero_f64, dim3(1024), dim3(256), 0, st, part, nz);
+    const float *region = costT + (int64_t)P.n_traj * P.R * P.N; // setup_costT's region table
     hipLaunchKernelGGL(k_grad, dim3(n_wg), dim3(256), grad_lds(P.N, layers), st, P, L, params,
-                       layers, costT, adv, logp_sorted, part, dE_part);
+                       layers, costT, region, adv, logp_sorted, part, dE_part);
     const int n = P.R * 16 + acc_count(layers) + 1;
     hipLaunchKernelGGL(k_grad_reduce, dim3((n + 255) / 256), dim3(256), 0, st, part, dE_part, n_wg,
                        P.R, layers, grad, objective_dev);
