@@ -51,8 +51,18 @@ __host__ __device__ inline int acc_count(int layers) // W1 b1 (W2 b2) w3 b3
     return H * 18 + H + (layers == 2 ? H * H + H : 0) + H + 1;
 }
 
+// Value of the lane that the DPP control CTRL selects (within each row of 16 lanes).
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, true));
+}
+
 // Sums over the 16 lanes of each lane group (l/16) of 16 values per lane, scattered: lane
-// m = l%16 gets the total of value m.  Butterfly with fixed pairings.
+// m = l%16 gets the total of value m.  Butterfly with fixed pairings, on DPP lane moves:
+// partners m ^ 8 (row rotation by 8), m ^ 7 (half-row mirror), m ^ 2 and m ^ 1 (quad
+// permutations); the decision bits 3, 2, 1, 0 of m pick which half a lane keeps, and the
+// four masks span the 16 lanes, so lane m ends with value m summed over all of them.
 __device__ __forceinline__ float reduce_scatter16(const float v[16])
 {
     const int m = __lane_id() & 15;
@@ -61,20 +71,20 @@ __device__ __forceinline__ float reduce_scatter16(const float v[16])
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         const float keep = b8 ? v[k + 8] : v[k], send = b8 ? v[k] : v[k + 8];
-        a8[k] = keep + __shfl_xor(send, 8, WAVE);
+        a8[k] = keep + dpp_f<0x128>(send);
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const float keep = b4 ? a8[k + 4] : a8[k], send = b4 ? a8[k] : a8[k + 4];
-        a4[k] = keep + __shfl_xor(send, 4, WAVE);
+        a4[k] = keep + dpp_f<0x141>(send);
     }
 #pragma unroll
     for (int k = 0; k < 2; ++k) {
         const float keep = b2 ? a4[k + 2] : a4[k], send = b2 ? a4[k] : a4[k + 2];
-        a2[k] = keep + __shfl_xor(send, 2, WAVE);
+        a2[k] = keep + dpp_f<0x4e>(send);
     }
     const float keep = b1 ? a2[1] : a2[0], send = b1 ? a2[0] : a2[1];
-    return keep + __shfl_xor(send, 1, WAVE);
+    return keep + dpp_f<0xb1>(send);
 }
 
 // Activations and score of one 16-row tile (the policy scorer's arithmetic): h1, h2 in the
@@ -165,7 +175,8 @@ __global__ __launch_bounds__(256, 2) void k_grad(Prob P, Plan L, const float *pa
     float *prL = red + GW * H;            // [2][64] region term of layer 1, by order parity
     float *ErL = prL + 2 * H;             // [2][16] embedding of the order's region
     float *smx = ErL + 2 * 16;            // [GW] wave softmax max, [GW] sum
-    int32_t *x = (int32_t *)(smx + 2 * GW); // [N] stock
+    float *crL = smx + 2 * GW;            // [2][N] cost row of the order's region, by parity
+    int32_t *x = (int32_t *)(crL + 2 * N); // [N] stock
     float *sbuf = (float *)(x + N);       // [N] scores
     int32_t *sl = (int32_t *)(sbuf + N);  // [N] warehouses with stock
     int32_t *pos = sl + N;                // [N] their index in sl
@@ -177,13 +188,31 @@ __global__ __launch_bounds__(256, 2) void k_grad(Prob P, Plan L, const float *pa
     stage_vectors(Vs, params, R, layers);
     for (int i = threadIdx.x; i < H * 16; i += blockDim.x)
         W1E[(i >> 4) * W1ES + (i & 15)] = W1[(i >> 4) * 18 + 2 + (i & 15)];
-    // the region term and embedding of order p into slot p & 1 (threads 0..79), written
-    // during order p - 1 and read after its closing barrier
-    auto stage_region = [&](int p) {
-        const int r = L.s_region[p], sl2 = p & 1;
-        if (threadIdx.x < H) prL[sl2 * H + threadIdx.x] = region[(int64_t)r * H + threadIdx.x];
-        else if (threadIdx.x < H + 16)
-            ErL[sl2 * 16 + threadIdx.x - H] = params[(int64_t)r * 16 + threadIdx.x - H];
+    // An order's rows that depend on its region only: layer 1's region term, the
+    // embedding and the cost row (of the run's trajectory), in slot p & 1 of the LDS
+    // copies.  Order p + 1's are loaded into registers when order p starts and written to
+    // the other slot before order p's closing barrier (the slot order p - 1 read).
+    struct Staged {
+        float t, c0, c1; // region term or embedding value (threads < 80); cost row at tid, tid + 256
+    };
+    auto stage_load = [&](int r, int b) {
+        Staged st;
+        const int t = threadIdx.x;
+        st.t = t < H ? region[(int64_t)r * H + t] : (t < H + 16 ? params[(int64_t)r * 16 + t - H] : 0.f);
+        const float *crn = costT + ((int64_t)b * R + r) * N;
+        st.c0 = t < N ? crn[t] : 0.f;
+        st.c1 = t + 256 < N ? crn[t + 256] : 0.f;
+        return st;
+    };
+    auto stage_store = [&](const Staged &st, int r, int b, int slot) {
+        const int t = threadIdx.x;
+        if (t < H) prL[slot * H + t] = st.t;
+        else if (t < H + 16) ErL[slot * 16 + t - H] = st.t;
+        float *cs = crL + slot * N;
+        if (t < N) cs[t] = st.c0;
+        if (t + 256 < N) cs[t + 256] = st.c1;
+        const float *crn = costT + ((int64_t)b * R + r) * N;
+        for (int w = t + 512; w < N; w += 256) cs[w] = crn[w];
     };
     // this wave's FP64 record (zeroed before the launch; each value owned by one lane), to
     // which the FP32 sums of every run are added
@@ -248,20 +277,41 @@ __global__ __launch_bounds__(256, 2) void k_grad(Prob P, Plan L, const float *pa
             x[w] = v > 0 ? v : 0;
             lxs[w] = log1p_stock(v > 0 ? v : 0);
         }
-        if (lo < hi) stage_region(lo);
+        // order lo's metadata and rows, and the region of order lo + 1
+        int r_cur = 0, a_cur = 0, q_cur = 0, r_nxt = 0;
+        float A_cur = 0.f;
+        if (lo < hi) {
+            r_cur = L.s_region[lo];
+            a_cur = L.s_alpha[lo];
+            q_cur = L.s_qty[lo];
+            A_cur = adv[L.perm[lo]];
+            stage_store(stage_load(r_cur, b), r_cur, b, lo & 1);
+        }
+        if (lo + 1 < hi) r_nxt = L.s_region[lo + 1];
         __syncthreads();
         build_stock_list(x, N, sl, pos, nfp);
         __syncthreads();
         for (int p = lo; p < hi; ++p) {
-            const int r = L.s_region[p];
-            const int a = L.s_alpha[p];
-            const float A = adv[L.perm[p]];
+            const int r = r_cur, a = a_cur, q = q_cur;
+            const float A = A_cur;
+            const bool more = p + 1 < hi;
+            // order p + 1's metadata (its advantage below, after the scores), the region of
+            // order p + 2 and order p + 1's rows, ahead of their use
+            int a_n = 0, q_n = 0, pm_n = 0, r_n2 = 0;
+            Staged st_n = {0.f, 0.f, 0.f};
+            if (more) {
+                a_n = L.s_alpha[p + 1];
+                q_n = L.s_qty[p + 1];
+                pm_n = L.perm[p + 1];
+                st_n = stage_load(r_nxt, b);
+            }
+            if (p + 2 < hi) r_n2 = L.s_region[p + 2];
+            float A_n = 0.f;
             const int nf = *nfp;
             const bool bad = a >= 0 ? (a >= N || x[a] <= 0) : nf > 0;
-            if (p + 1 < hi) stage_region(p + 1);
             const float *prO = prL + (p & 1) * H, *ErO = ErL + (p & 1) * 16;
+            const float *cr = crL + (p & 1) * N;
             if (!bad && nf > 1) {
-                const float *cr = costT + ((int64_t)b * R + r) * N;
                 const double dEold = wave == 0 && lane < 16 ? dEw[(int64_t)r * 16 + lane] : 0.0;
                 // 1. scores; the first KEEP tiles' activations stay in registers
                 const int ntiles = (nf + 15) >> 4;
@@ -310,6 +360,7 @@ __global__ __launch_bounds__(256, 2) void k_grad(Prob P, Plan L, const float *pa
                         smx[GW + wave] = ws;
                     }
                 }
+                if (more) A_n = adv[pm_n];
                 __syncthreads();
                 float mx = -INFINITY;
 #pragma unroll
@@ -494,15 +545,16 @@ __global__ __launch_bounds__(256, 2) void k_grad(Prob P, Plan L, const float *pa
                     }
                 }
             } else {
+                if (more) A_n = adv[pm_n];
                 if (threadIdx.x == 0) {
                     if (bad) atomicOr(&L.ctl->error, 8);
                     logp_sorted[p] = 0.f;
                 }
                 __syncthreads(); // every thread has made the test above
             }
+            if (more) stage_store(st_n, r_nxt, b, (p + 1) & 1);
             // the fixed action: every read of this order's state is behind a barrier
             if (threadIdx.x == 0 && a >= 0 && a < N) {
-                const int q = L.s_qty[p];
                 const int xa = x[a];
                 const int nx = xa - (q < xa ? q : xa);
                 x[a] = nx;
@@ -510,6 +562,11 @@ __global__ __launch_bounds__(256, 2) void k_grad(Prob P, Plan L, const float *pa
                 if (xa > 0 && nx == 0) drop_from_list(a, sl, pos, nfp);
             }
             __syncthreads();
+            r_cur = r_nxt;
+            a_cur = a_n;
+            q_cur = q_n;
+            A_cur = A_n;
+            r_nxt = r_n2;
         }
         pending += hi - lo;
         if (pending >= FLUSH) flush();
@@ -559,7 +616,7 @@ size_t grad_lds(int N, int layers)
 {
     (void)layers;
     return w2_lds_bytes() + vec_lds_bytes() +
-           (size_t)(2 * H * RS + H * W1ES + GW * H + 2 * H + 2 * 16 + 2 * GW) * 4 + (size_t)N * 20 + 16;
+           (size_t)(2 * H * RS + H * W1ES + GW * H + 2 * H + 2 * 16 + 2 * GW) * 4 + (size_t)N * 28 + 16;
 }
 
 int grad_wg_per_cu(int N) { return 2 * grad_lds(N, 2) <= 160 * 1024 ? 2 : 1; }
