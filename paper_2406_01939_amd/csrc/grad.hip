@@ -21,8 +21,8 @@
 //      the staged W2) and sums the row-summed gradients of the tile (b1, w3, the cost and
 //      log1p(x) columns of W1) over its rows; later tiles are scored again here;
 //   3. h1 and dl of the chunk's 64 rows are stored by unit in LDS, so that dW2 = sum over
-//      rows of dl h1^T is an MFMA product over the rows; each wave owns 16 output units of
-//      dW2 (and of db2, the row sums of its dl rows);
+//      rows of dl h1^T is an MFMA product over the rows (over the chunk's tiles only);
+//      each wave owns 16 output units of dW2 (and of db2, the row sums of its dl rows);
 //   4. the order's d1 summed over its rows gives the embedding columns of dW1 (outer
 //      product with E[r]) and dE[r] (W1's embedding columns times it), the latter into a
 //      per-workgroup FP64 table in global memory.
@@ -411,11 +411,13 @@ __global__ __launch_bounds__(256, 2) void k_grad(Prob P, Plan L, const float *pa
 #pragma unroll
                                 for (int v = 0; v < 4; ++v) d1[T][v] = h1[T][v] > 0.f ? acc[v] : 0.f;
                             }
+                            // row 16 wave + m of the chunk at column 16 (m % 4) + 4 wave + m / 4
+                            const int col = 16 * (m & 3) + 4 * wave + (m >> 2);
 #pragma unroll
                             for (int t = 0; t < 4; ++t)
 #pragma unroll
                                 for (int v = 0; v < 4; ++v) {
-                                    const int at = (16 * t + 4 * g + v) * RS + 16 * wave + m;
+                                    const int at = (16 * t + 4 * g + v) * RS + col;
                                     H1T[at] = h1[t][v];
                                     DLT[at] = dl[t][v];
                                 }
@@ -453,36 +455,32 @@ __global__ __launch_bounds__(256, 2) void k_grad(Prob P, Plan L, const float *pa
                             for (int v = 0; v < 4; ++v) tt[t * 4 + v] = d1[t][v] * lx;
                         sc1 += reduce_scatter16(tt);
                     };
-                    // dW2 over the chunk's rows (this wave's 16 output units), and their db2
-                    auto chunk_dw2 = [&]() {
+                    // dW2 over the rows of the chunk's q tiles (this wave's 16 output units), and
+                    // their db2: MFMA step c takes rows 4c .. 4c + 3 (lane group g: row 4c + g,
+                    // the column block g of the by-unit tensors), so tile t is steps 4t .. 4t + 3
+                    // and the steps of absent tiles (whose columns hold stale values) are skipped
+                    auto chunk_dw2 = [&](int q) {
                         const float4 *ap = (const float4 *)(DLT + (16 * wave + m) * RS + 16 * g);
-                        const float4 a0 = ap[0], a1 = ap[1], a2 = ap[2], a3 = ap[3];
-                        const float av[16] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w,
-                                              a2.x, a2.y, a2.z, a2.w, a3.x, a3.y, a3.z, a3.w};
+                        const float4 aq[4] = {ap[0], ap[1], ap[2], ap[3]};
                         float rs = 0.f;
 #pragma unroll
-                        for (int c = 0; c < 16; ++c) rs += av[c];
+                        for (int cb = 0; cb < 4; ++cb)
+                            if (cb < q) rs += ((aq[cb].x + aq[cb].y) + aq[cb].z) + aq[cb].w;
                         sb2 += rs;
 #pragma unroll
                         for (int T = 0; T < 4; ++T) {
                             const float4 *bp = (const float4 *)(H1T + (16 * T + m) * RS + 16 * g);
-                            const float4 q0 = bp[0], q1 = bp[1], q2 = bp[2], q3 = bp[3];
-                            const float bv[16] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w,
-                                                  q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w};
 #pragma unroll
-                            for (int c = 0; c < 16; ++c)
-                                aW2[T] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[c], bv[c], aW2[T], 0, 0, 0);
-                        }
-                    };
-                    auto zero_tile = [&]() { // this wave has no tile in the chunk
-#pragma unroll
-                        for (int t = 0; t < 4; ++t)
-#pragma unroll
-                            for (int v = 0; v < 4; ++v) {
-                                const int at = (16 * t + 4 * g + v) * RS + 16 * wave + m;
-                                H1T[at] = 0.f;
-                                DLT[at] = 0.f;
+                            for (int cb = 0; cb < 4; ++cb) {
+                                if (cb < q) {
+                                    const float4 bq = bp[cb];
+                                    aW2[T] = __builtin_amdgcn_mfma_f32_16x16x4f32(aq[cb].x, bq.x, aW2[T], 0, 0, 0);
+                                    aW2[T] = __builtin_amdgcn_mfma_f32_16x16x4f32(aq[cb].y, bq.y, aW2[T], 0, 0, 0);
+                                    aW2[T] = __builtin_amdgcn_mfma_f32_16x16x4f32(aq[cb].z, bq.z, aW2[T], 0, 0, 0);
+                                    aW2[T] = __builtin_amdgcn_mfma_f32_16x16x4f32(aq[cb].w, bq.w, aW2[T], 0, 0, 0);
+                                }
                             }
+                        }
                     };
                     const int nch = (nf + 63) >> 6;
 #pragma unroll
@@ -490,11 +488,9 @@ __global__ __launch_bounds__(256, 2) void k_grad(Prob P, Plan L, const float *pa
                         if (j < nch) {
                             if (wave + GW * j < ntiles)
                                 backward(k1[j], k2[j], ks[j], kw[j], kc[j], kl[j]);
-                            else if (two)
-                                zero_tile();
                             if (two) {
                                 __syncthreads();
-                                chunk_dw2();
+                                chunk_dw2(min(GW, ntiles - GW * j));
                                 if (j + 1 < nch) __syncthreads();
                             }
                         }
@@ -509,12 +505,10 @@ __global__ __launch_bounds__(256, 2) void k_grad(Prob P, Plan L, const float *pa
                             v4f h1[4], h2[4];
                             const float sc = tile_forward(W2s, Vs, two, b3, prO, cost, lx, h1, h2);
                             backward(h1, h2, sc, valid ? w : -1, cost, lx);
-                        } else if (two) {
-                            zero_tile();
                         }
                         if (two) {
                             __syncthreads();
-                            chunk_dw2();
+                            chunk_dw2(min(GW, ntiles - GW * j));
                             if (j + 1 < nch) __syncthreads();
                         }
                     }
