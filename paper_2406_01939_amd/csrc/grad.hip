@@ -261,6 +261,35 @@ __global__ __launch_bounds__(256, 2) void k_grad(Prob P, Plan L, const float *pa
         sW1E[0] = sW1E[1] = sW1E[2] = sW1E[3] = 0.f;
         pending = 0;
     };
+    // An order's d1 summed over its rows (each wave's part in red, written before a barrier
+    // that every thread has passed since): the embedding columns of dW1 and dE[r].
+    bool pend = false; // an order's part in red not yet taken up
+    int pend_r = 0, pend_slot = 0;
+    double pend_dE = 0.0; // dE[r] of that order as read when it started (wave 0, lanes < 16)
+    auto drain = [&]() {
+        auto d1o_at = [&](int u) { // fixed order over the waves
+            return ((red[u] + red[H + u]) + red[2 * H + u]) + red[3 * H + u];
+        };
+        {
+            const float d = d1o_at(threadIdx.x >> 2);
+            const float4 ev = *(const float4 *)(ErL + pend_slot * 16 + 4 * (threadIdx.x & 3));
+            sW1E[0] = fmaf(ev.x, d, sW1E[0]);
+            sW1E[1] = fmaf(ev.y, d, sW1E[1]);
+            sW1E[2] = fmaf(ev.z, d, sW1E[2]);
+            sW1E[3] = fmaf(ev.w, d, sW1E[3]);
+        }
+        if (wave == 0) { // dE[r][k] += sum_j W1[j][2 + k] d1o[j]
+            const float d = d1o_at(lane);
+            float v[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) v[k] = W1E[lane * W1ES + k] * d;
+            float t = reduce_scatter16(v);
+            t = t + __shfl_xor(t, 16, WAVE);
+            t = t + __shfl_xor(t, 32, WAVE);
+            if (lane < 16) dEw[(int64_t)pend_r * 16 + lane] = pend_dE + (double)t;
+        }
+        pend = false;
+    };
     const int n_items = L.ctl->n_sr;
     for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
         const int s = item;
@@ -285,13 +314,14 @@ __global__ __launch_bounds__(256, 2) void k_grad(Prob P, Plan L, const float *pa
             a_cur = L.s_alpha[lo];
             q_cur = L.s_qty[lo];
             A_cur = adv[L.perm[lo]];
-            stage_store(stage_load(r_cur, b), r_cur, b, lo & 1);
         }
         if (lo + 1 < hi) r_nxt = L.s_region[lo + 1];
-        __syncthreads();
+        __syncthreads(); // (the last run's pending order has been taken up)
+        if (lo < hi) stage_store(stage_load(r_cur, b), r_cur, b, lo & 1);
         build_stock_list(x, N, sl, pos, nfp);
         __syncthreads();
         for (int p = lo; p < hi; ++p) {
+            if (pend) drain();
             const int r = r_cur, a = a_cur, q = q_cur;
             const float A = A_cur;
             const bool more = p + 1 < hi;
@@ -512,31 +542,14 @@ __global__ __launch_bounds__(256, 2) void k_grad(Prob P, Plan L, const float *pa
                             if (j + 1 < nch) __syncthreads();
                         }
                     }
-                    // 4. the order's d1 over all rows: embedding columns of dW1 and dE[r]
+                    // 4. the order's d1 over all rows, taken up after the order's closing
+                    // barrier (at the next order's start or the run's end)
                     sb1 += o1;
                     red[wave * H + us] = o1;
-                    __syncthreads();
-                    auto d1o_at = [&](int u) { // fixed order over the waves
-                        return ((red[u] + red[H + u]) + red[2 * H + u]) + red[3 * H + u];
-                    };
-                    {
-                        const float d = d1o_at(threadIdx.x >> 2);
-                        const float4 ev = *(const float4 *)(ErO + 4 * (threadIdx.x & 3));
-                        sW1E[0] = fmaf(ev.x, d, sW1E[0]);
-                        sW1E[1] = fmaf(ev.y, d, sW1E[1]);
-                        sW1E[2] = fmaf(ev.z, d, sW1E[2]);
-                        sW1E[3] = fmaf(ev.w, d, sW1E[3]);
-                    }
-                    if (wave == 0) { // dE[r][k] += sum_j W1[j][2 + k] d1o[j]
-                        const float d = d1o_at(lane);
-                        float v[16];
-#pragma unroll
-                        for (int k = 0; k < 16; ++k) v[k] = W1E[lane * W1ES + k] * d;
-                        float t = reduce_scatter16(v);
-                        t = t + __shfl_xor(t, 16, WAVE);
-                        t = t + __shfl_xor(t, 32, WAVE);
-                        if (lane < 16) dEw[(int64_t)r * 16 + lane] = dEold + (double)t;
-                    }
+                    pend = true;
+                    pend_r = r;
+                    pend_slot = p & 1;
+                    pend_dE = dEold;
                 }
             } else {
                 if (more) A_n = adv[pm_n];
@@ -562,6 +575,7 @@ __global__ __launch_bounds__(256, 2) void k_grad(Prob P, Plan L, const float *pa
             A_cur = A_n;
             r_nxt = r_n2;
         }
+        if (pend) drain();
         pending += hi - lo;
         if (pending >= FLUSH) flush();
     }
