@@ -408,7 +408,7 @@ __global__ __launch_bounds__(256, 2) void k_grad(Prob P, Plan L, const float *pa
                     float o1 = 0.f; // this order's d1 summed over this wave's rows (scattered)
                     // 2.-3. backward of one tile of this wave (rows past nf: zero deltas)
                     auto backward = [&](const v4f h1[4], const v4f h2[4], float sc, int w,
-                                        float cost, float lx) {
+                                        float cost, float lx, int qc) {
                         const float ds = w >= 0 ? A * ((w == a ? 1.f : 0.f) - expf(sc - mx - lz)) : 0.f;
                         if (g == 0) sb3 += ds;
                         v4f d1[4];
@@ -441,8 +441,11 @@ __global__ __launch_bounds__(256, 2) void k_grad(Prob P, Plan L, const float *pa
 #pragma unroll
                                 for (int v = 0; v < 4; ++v) d1[T][v] = h1[T][v] > 0.f ? acc[v] : 0.f;
                             }
-                            // row 16 wave + m of the chunk at column 16 (m % 4) + 4 wave + m / 4
-                            const int col = 16 * (m & 3) + 4 * wave + (m >> 2);
+                            // row 16 wave + m of the chunk: in a chunk of qc < 4 tiles at column
+                            // 16 (m % 4) + 4 wave + m / 4 (tile t in MFMA steps 4t .. 4t + 3);
+                            // in a full chunk at column 16 wave + m (step c: rows c + 16 g),
+                            // whose stores fall on distinct banks
+                            const int col = qc < GW ? 16 * (m & 3) + 4 * wave + (m >> 2) : 16 * wave + m;
 #pragma unroll
                             for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -486,8 +489,8 @@ __global__ __launch_bounds__(256, 2) void k_grad(Prob P, Plan L, const float *pa
                         sc1 += reduce_scatter16(tt);
                     };
                     // dW2 over the rows of the chunk's q tiles (this wave's 16 output units), and
-                    // their db2: MFMA step c takes rows 4c .. 4c + 3 (lane group g: row 4c + g,
-                    // the column block g of the by-unit tensors), so tile t is steps 4t .. 4t + 3
+                    // their db2: lane group g reads column block g of the by-unit tensors; with
+                    // q < 4 MFMA step c takes rows 4c .. 4c + 3, so tile t is steps 4t .. 4t + 3
                     // and the steps of absent tiles (whose columns hold stale values) are skipped
                     auto chunk_dw2 = [&](int q) {
                         const float4 *ap = (const float4 *)(DLT + (16 * wave + m) * RS + 16 * g);
@@ -517,7 +520,7 @@ __global__ __launch_bounds__(256, 2) void k_grad(Prob P, Plan L, const float *pa
                     for (int j = 0; j < KEEP; ++j) {
                         if (j < nch) {
                             if (wave + GW * j < ntiles)
-                                backward(k1[j], k2[j], ks[j], kw[j], kc[j], kl[j]);
+                                backward(k1[j], k2[j], ks[j], kw[j], kc[j], kl[j], min(GW, ntiles - GW * j));
                             if (two) {
                                 __syncthreads();
                                 chunk_dw2(min(GW, ntiles - GW * j));
@@ -534,7 +537,7 @@ __global__ __launch_bounds__(256, 2) void k_grad(Prob P, Plan L, const float *pa
                             const float cost = valid ? cr[w] : 0.f, lx = valid ? lxs[w] : 0.f;
                             v4f h1[4], h2[4];
                             const float sc = tile_forward(W2s, Vs, two, b3, prO, cost, lx, h1, h2);
-                            backward(h1, h2, sc, valid ? w : -1, cost, lx);
+                            backward(h1, h2, sc, valid ? w : -1, cost, lx, min(GW, ntiles - GW * j));
                         }
                         if (two) {
                             __syncthreads();
