@@ -115,6 +115,8 @@ def _check(rc: int, what: str):
 
 def serial(inst, b: int = 0, greedy: bool = False) -> dict:
     """Serial rollout of trajectory b (greedy=True forces the greedy policy)."""
+    if inst.x0 is None:
+        raise ValueError("serial rollout needs the initial inventory (x0 is a generator here)")
     B = _Bound(inst, b)
     if greedy:
         B.p.params = None

@@ -105,6 +105,18 @@ def test_gradient_random_advantages_batch(api, oracle):
     _compare(oracle, inst, prob, api, acts, adv)
 
 
+def test_gradient_wide_orders(api, oracle):
+    """N = 500 warehouses (the width of the 16 x 1e7 workload), most of them in stock: up to
+    32 row tiles an order, so full and partial 64-row chunks and tiles scored again in the
+    backward pass."""
+    inst = random_tiny(420, N=500, K=3, R=7, T=160, qmax=3, inv_max=6, n_traj=2, mlp=True)
+    assert (inst.x0 > 0).mean() > 0.8
+    prob = api.DeviceProblem.from_instance(inst)
+    _say("case grad wide N=500 batch2 T=160")
+    acts, _, adv = _oracle_rollout(oracle, inst)
+    _compare(oracle, inst, prob, api, acts, adv)
+
+
 def test_gradient_is_reproducible(api):
     """Two calls on the same input give the same gradient bit for bit (the accumulation
     order is fixed)."""
